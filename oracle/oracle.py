@@ -1,0 +1,351 @@
+"""FP64 CPU oracle for the TTCF daughter path of arxiv 2312.02990 (TTCF4LAMMPS).
+
+TEST INFRASTRUCTURE: only the test-suite, the smoke check and the benchmark's CPU-baseline
+leg import this module. The GPU library shares no code with it.
+
+Two layers:
+  * ctypes bindings of ``libttcf_oracle.so`` (dynamics, forces, cell lists; plain C, FP64);
+  * the TTCF / direct-average estimators and the Green-Kubo integral written with numpy
+    in FP64, each following the equation it cites.
+
+Sign convention: ``vpxy`` is V * P_xy with P_xy the pressure-tensor component. The paper's
+Eq. (TTCF1) writes Omega = +gamma_dot V P_xy / k_B T with P_xy read as a shear stress; in the
+pressure-tensor convention the same dissipation function is Omega = -gamma_dot V P_xy / T,
+which is what the adiabatic energy balance dH0/dt = -gamma_dot V P_xy gives (the paper defines
+Omega as beta times the adiabatic rate of change of the internal energy).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+WCA_RC = 2.0 ** (1.0 / 6.0)
+
+
+class Box(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad_", C.c_int32), ("lx", C.c_double), ("ly", C.c_double),
+                ("lz", C.c_double), ("rc", C.c_double), ("c_attr", C.c_double),
+                ("u_shift", C.c_double)]
+
+
+def lj_shift(rc: float, c_attr: float) -> float:
+    """Constant that makes 4[(1/r)^12 - c (1/r)^6] + shift vanish at r = rc (Example 1:
+    the shift guarantees continuity at the cutoff)."""
+    s6 = 1.0 / rc ** 6
+    return -4.0 * (s6 * s6 - c_attr * s6)
+
+
+def make_box(n: int, l, rc: float = WCA_RC, c_attr: float = 1.0, u_shift: float | None = None) -> Box:
+    if np.isscalar(l):
+        l = (float(l),) * 3
+    if u_shift is None:
+        u_shift = lj_shift(rc, c_attr)
+    return Box(int(n), 0, float(l[0]), float(l[1]), float(l[2]), float(rc), float(c_attr),
+               float(u_shift))
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = os.path.join(_HERE, "libttcf_oracle.so")
+        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
+                os.path.join(_HERE, "ttcf_oracle.c")):
+            _build.build()
+        lib = C.CDLL(path)
+        D = C.POINTER(C.c_double)
+        I = C.POINTER(C.c_int32)
+        L = C.POINTER(C.c_int64)
+        B = C.POINTER(Box)
+        lib.orc_cell_dims.argtypes = [B, I]
+        lib.orc_cell_list.argtypes = [B, D, I, I, I]
+        lib.orc_forces.argtypes = [B, C.c_double, D, D, D]
+        lib.orc_forces_brute.argtypes = [B, C.c_double, D, D, D]
+        lib.orc_pairs.argtypes = [B, C.c_double, D, C.c_double, C.c_int64, I, I]
+        lib.orc_pairs.restype = C.c_int64
+        lib.orc_pairs_brute.argtypes = [B, C.c_double, D, C.c_double, C.c_int64, I, I]
+        lib.orc_pairs_brute.restype = C.c_int64
+        lib.orc_vpxy.argtypes = [B, C.c_double, D, D]
+        lib.orc_vpxy.restype = C.c_double
+        lib.orc_map.argtypes = [B, C.c_int32, D, D, D, D]
+        lib.orc_map.restype = None
+        lib.orc_nh_run.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double, D, D, D,
+                                   C.c_int64, D, D, D]
+        lib.orc_sllod_run.argtypes = [B, C.c_double, C.c_double, C.c_int32, C.c_double, D, D, L,
+                                      C.c_int64, D, D, D]
+        lib.orc_iso_kick.argtypes = [C.c_int32, D, D, C.c_double]
+        lib.orc_iso_kick.restype = None
+        lib.orc_iso_shear.argtypes = [C.c_int32, D, C.c_double, C.c_double]
+        lib.orc_iso_shear.restype = None
+        lib.orc_mother_sample.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double, D, D,
+                                          D, C.c_int64, C.c_int32, C.c_int64, D, D]
+        lib.orc_run_daughters.argtypes = [B, C.c_double, D, D, C.c_int32, I, I, D, C.c_int64,
+                                          C.c_int32, D, D, D]
+        for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
+                   "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters"):
+            getattr(lib, fn).restype = C.c_int32
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ----------------------------------------------------------------------------------------
+# forces, cell lists, pairs
+# ----------------------------------------------------------------------------------------
+
+def cell_dims(box: Box):
+    d = np.zeros(3, np.int32)
+    if _load().orc_cell_dims(C.byref(box), _ip(d)) != 0:
+        raise ValueError("box too small for a 27-cell grid (need n_x >= 4, n_y, n_z >= 3)")
+    return d
+
+
+def cell_list(box: Box, r):
+    """(cell_of, order, start) of the canonical cell list (cell id, then atom id)."""
+    r = _f64(r)
+    d = cell_dims(box)
+    cell_of = np.zeros(box.n, np.int32)
+    order = np.zeros(box.n, np.int32)
+    start = np.zeros(int(d.prod()) + 1, np.int32)
+    rc = _load().orc_cell_list(C.byref(box), _dp(r), _ip(cell_of), _ip(order), _ip(start))
+    if rc != 0:
+        raise RuntimeError(f"orc_cell_list failed: {rc}")
+    return cell_of, order, start
+
+
+def forces(box: Box, r, dxle: float = 0.0, brute: bool = False):
+    """(F as (3, n), U, W_xy, n_pairs) at Lees-Edwards offset dxle."""
+    r = _f64(r)
+    f = np.zeros(3 * box.n)
+    out = np.zeros(3)
+    fn = _load().orc_forces_brute if brute else _load().orc_forces
+    rc = fn(C.byref(box), float(dxle), _dp(r), _dp(f), _dp(out))
+    if rc != 0:
+        raise RuntimeError(f"oracle forces failed: {rc}")
+    return f.reshape(3, box.n), out[0], out[1], int(round(out[2]))
+
+
+def pairs(box: Box, r, dxle: float = 0.0, rlist: float | None = None, brute: bool = False):
+    """Sorted (i, j) pairs, i<j, closer than rlist (default rc)."""
+    r = _f64(r)
+    rl = box.rc if rlist is None else float(rlist)
+    cap = 64 * box.n
+    pi = np.zeros(cap, np.int32)
+    pj = np.zeros(cap, np.int32)
+    fn = _load().orc_pairs_brute if brute else _load().orc_pairs
+    cnt = fn(C.byref(box), float(dxle), _dp(r), rl, cap, _ip(pi), _ip(pj))
+    if cnt < 0:
+        raise RuntimeError(f"oracle pairs failed: {cnt}")
+    return pi[:cnt].copy(), pj[:cnt].copy()
+
+
+def vpxy(box: Box, r, p, dxle: float = 0.0) -> float:
+    return _load().orc_vpxy(C.byref(box), float(dxle), _dp(_f64(r)), _dp(_f64(p)))
+
+
+def apply_mapping(box: Box, m: int, r, p):
+    """Eq. (mappings): m=0 identity, 1 p->-p, 2 (x,px)->(-x,-px), 3 (x,py,pz)->(-x,-py,-pz)."""
+    r = _f64(r)
+    p = _f64(p)
+    ro = np.empty_like(r)
+    po = np.empty_like(p)
+    _load().orc_map(C.byref(box), int(m), _dp(r), _dp(p), _dp(ro), _dp(po))
+    return ro, po
+
+
+# ----------------------------------------------------------------------------------------
+# dynamics
+# ----------------------------------------------------------------------------------------
+
+def le_offset(box: Box, gamma_dot: float, dt: float, k: int) -> float:
+    """Sliding-brick offset of the image above the box after k steps."""
+    return float(np.fmod(gamma_dot * box.ly * (float(k) * dt), box.lx))
+
+
+def nh_q(nf: float, temperature: float, tau: float) -> float:
+    """Nose-Hoover mass Q = nf T tau^2 (the paper calls Q a damping factor and leaves it free)."""
+    return nf * temperature * tau * tau
+
+
+@dataclass
+class NHState:
+    r: np.ndarray
+    p: np.ndarray
+    zeta: float = 0.0
+
+
+def nh_run(box: Box, state: NHState, nsteps: int, temperature: float, dt: float, q: float,
+           nf: float, record: bool = False):
+    """Advance a Nose-Hoover mother in place. With record: (vpxy, ke, pe) per step."""
+    z = np.array([state.zeta])
+    outs = [np.zeros(nsteps + 1) for _ in range(3)] if record else [None, None, None]
+    rc = _load().orc_nh_run(C.byref(box), temperature, q, nf, dt, _dp(state.r), _dp(state.p),
+                            _dp(z), int(nsteps), *[_dp(o) for o in outs])
+    if rc != 0:
+        raise RuntimeError(f"orc_nh_run failed: {rc}")
+    state.zeta = float(z[0])
+    return tuple(outs) if record else None
+
+
+def mother_sample(box: Box, state: NHState, n_equil: int, n_states: int, steps_between: int,
+                  temperature: float, dt: float, q: float, nf: float):
+    """Alg. LAMMPS SCRIPT, mother side: equilibrate n_equil steps, then n_states times run
+    steps_between steps and save the state. Returns (states_r, states_p), (n_states, 3n)."""
+    sr = np.zeros((n_states, 3 * box.n))
+    sp = np.zeros((n_states, 3 * box.n))
+    z = np.array([state.zeta])
+    rc = _load().orc_mother_sample(C.byref(box), temperature, q, nf, dt, _dp(state.r),
+                                   _dp(state.p), _dp(z), int(n_equil), int(n_states),
+                                   int(steps_between), _dp(sr), _dp(sp))
+    if rc != 0:
+        raise RuntimeError(f"orc_mother_sample failed: {rc}")
+    state.zeta = float(z[0])
+    return sr, sp
+
+
+def sllod_run(box: Box, r, p, gamma_dot: float, dt: float, nsteps: int, gik: bool = True,
+              k0: float = 0.0, kstep: int = 0):
+    """Advance one SLLOD trajectory in place (r, p float64 SoA arrays).
+    Returns (vpxy, ke, pe, k_final), series of length nsteps+1."""
+    assert r.dtype == np.float64 and p.dtype == np.float64 and r.flags.c_contiguous
+    outs = [np.zeros(nsteps + 1) for _ in range(3)]
+    k = np.array([kstep], dtype=np.int64)
+    rc = _load().orc_sllod_run(C.byref(box), float(gamma_dot), float(dt), int(bool(gik)),
+                               float(k0), _dp(r), _dp(p),
+                               k.ctypes.data_as(C.POINTER(C.c_int64)), int(nsteps),
+                               *[_dp(o) for o in outs])
+    if rc != 0:
+        raise RuntimeError(f"orc_sllod_run failed: {rc}")
+    return outs[0], outs[1], outs[2], int(k[0])
+
+
+def iso_kick(p, f, tau: float):
+    """Exact isokinetic force kick (returns a new array; p, f are flat SoA)."""
+    p = _f64(p).copy()
+    f = _f64(f)
+    _load().orc_iso_kick(len(p) // 3, _dp(p), _dp(f), float(tau))
+    return p
+
+
+def iso_shear(p, gamma_dot: float, tau: float):
+    """Exact isokinetic shear flow of the momenta (returns a new array)."""
+    p = _f64(p).copy()
+    _load().orc_iso_shear(len(p) // 3, _dp(p), float(gamma_dot), float(tau))
+    return p
+
+
+def run_daughters(box: Box, states_r, states_p, state_of, map_of, gamma_of, dt: float,
+                  nsteps: int, nthreads: int = 0, final_state: bool = False):
+    """Alg. LAMMPS SCRIPT, daughter side, on a CPU thread pool. Returns vpxy (n_d, nsteps+1)
+    [and final r, p] and the number of threads used."""
+    states_r = _f64(states_r)
+    states_p = _f64(states_p)
+    state_of = np.ascontiguousarray(state_of, np.int32)
+    map_of = np.ascontiguousarray(map_of, np.int32)
+    gamma_of = _f64(gamma_of)
+    nd = len(state_of)
+    out = np.zeros((nd, nsteps + 1))
+    ro = np.zeros((nd, 3 * box.n)) if final_state else None
+    po = np.zeros((nd, 3 * box.n)) if final_state else None
+    if nthreads <= 0:
+        nthreads = os.cpu_count() or 1
+    used = _load().orc_run_daughters(C.byref(box), float(dt), _dp(states_r), _dp(states_p), nd,
+                                     _ip(state_of), _ip(map_of), _dp(gamma_of), int(nsteps),
+                                     int(nthreads), _dp(out), _dp(ro), _dp(po))
+    if used < 0:
+        raise RuntimeError(f"orc_run_daughters failed: {used}")
+    if final_state:
+        return out, ro, po, used
+    return out, used
+
+
+# ----------------------------------------------------------------------------------------
+# estimators (numpy, FP64)
+# ----------------------------------------------------------------------------------------
+
+def omega0(vpxy0, gamma_dot, temperature):
+    """Dissipation function at t=0, Eq. (TTCF1) in the pressure-tensor convention:
+    Omega = -(V/T) gamma_dot P_xy(0) = -(gamma_dot/T) * (V P_xy(0))."""
+    return -(np.asarray(gamma_dot, np.float64) / temperature) * np.asarray(vpxy0, np.float64)
+
+
+@dataclass
+class Response:
+    ttcf: np.ndarray       # <B(t)> by Eq. (TTCF)
+    ttcf_se: np.ndarray    # block standard error over start states
+    dav: np.ndarray        # direct average of B(t)
+    dav_se: np.ndarray
+    g: np.ndarray          # per-start-state TTCF series G_n(t), (n_states, n_t)
+    d: np.ndarray          # per-start-state direct-average series D_n(t)
+    integrand: np.ndarray  # <Omega(0) B(t)> over all daughters, Eq. (integrand)
+    integrand_se_paper: np.ndarray  # sigma/sqrt(N_daughters) of Omega(0)B(t) (paper's SE)
+    dav_se_paper: np.ndarray        # sigma/sqrt(N_daughters) of B(t)
+
+
+def ttcf_response(b, vpxy0, gamma_of, temperature: float, dt: float, n_maps: int = 4) -> Response:
+    """TTCF and direct-average responses from per-daughter series.
+
+    b[d, k]   : observable B of daughter d at t_k = k dt, k = 0..n_t-1
+    vpxy0[d]  : V * P_xy of daughter d at t = 0 (gives Omega(0))
+    gamma_of[d]: shear rate of daughter d
+    Daughters are ordered state-major: d = n * n_maps + m.
+
+    Eq. (TTCF): <B(t)> = <B(0)> + int_0^t <Omega(0) B(s)> ds, with the ensemble average of
+    Eq. (integrand) and the integral taken by the trapezoid rule on the step grid. The
+    standard error is the block error over start states (each block = the n_maps mapped
+    daughters of one state), std with ddof=1 over sqrt(number of states).
+    """
+    b = np.asarray(b, np.float64)
+    nd, nt = b.shape
+    assert nd % n_maps == 0
+    ns = nd // n_maps
+    om = omega0(vpxy0, gamma_of, temperature)  # (nd,)
+    ob = om[:, None] * b                       # Omega(0) B(t)
+    integ = np.zeros_like(ob)
+    integ[:, 1:] = np.cumsum(0.5 * dt * (ob[:, :-1] + ob[:, 1:]), axis=1)
+    per_d = b[:, :1] + integ                   # B(0) + int_0^t Omega(0) B(s) ds
+    g = per_d.reshape(ns, n_maps, nt).mean(axis=1)
+    dd = b.reshape(ns, n_maps, nt).mean(axis=1)
+    sq = np.sqrt(ns)
+    return Response(
+        ttcf=g.mean(axis=0), ttcf_se=(g.std(axis=0, ddof=1) / sq) if ns > 1 else np.full(nt, np.nan),
+        dav=dd.mean(axis=0), dav_se=(dd.std(axis=0, ddof=1) / sq) if ns > 1 else np.full(nt, np.nan),
+        g=g, d=dd, integrand=ob.mean(axis=0),
+        integrand_se_paper=ob.std(axis=0, ddof=1) / np.sqrt(nd),
+        dav_se_paper=b.std(axis=0, ddof=1) / np.sqrt(nd))
+
+
+def viscosity(response_mean, gamma_dot):
+    """Eq. (visc): eta(t) = <P_xy(t)>/gamma_dot in the paper's shear-stress sign, i.e.
+    -<P_xy(t)>/gamma_dot with the pressure-tensor P_xy used here."""
+    return -np.asarray(response_mean) / gamma_dot
+
+
+def green_kubo(pxy_series, volume: float, temperature: float, dt: float, max_lag: int):
+    """Equilibrium limit of Eq. (visc) (TTCF as a generalisation of Green-Kubo):
+    C(s) = <P_xy(0) P_xy(s)> averaged over every time origin of an equilibrium series,
+    eta_GK(t) = (V/T) int_0^t C(s) ds by the trapezoid rule. Returns (C, eta_GK)."""
+    x = np.asarray(pxy_series, np.float64)
+    n = len(x)
+    c = np.array([np.dot(x[: n - s], x[s:]) / (n - s) for s in range(max_lag + 1)])
+    eta = np.zeros(max_lag + 1)
+    eta[1:] = np.cumsum(0.5 * dt * (c[:-1] + c[1:]))
+    return c, (volume / temperature) * eta

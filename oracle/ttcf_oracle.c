@@ -1,0 +1,673 @@
+/*
+ * ttcf_oracle.c -- plain FP64 CPU oracle for the TTCF daughter path of arxiv 2312.02990.
+ *
+ * TEST INFRASTRUCTURE: only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg use this file. It shares no code with the GPU library.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fPIC -shared (no fast-math, no vector intrinsics),
+ * so every expression below is evaluated as written, one rounding per operation.
+ *
+ * What each part follows in the paper:
+ *   - WCA / wetting-factor LJ pair potential: Example 1 (WCA equation, shift for continuity
+ *     at r_c) and Example 2 (LJ with c_ij).
+ *   - SLLOD equations of motion, Eq. (system1), under the sliding-brick (Lees-Edwards)
+ *     boundaries that the paper equates with LAMMPS' box deformation (Example 1).
+ *   - Equilibrium mother dynamics with a Nose-Hoover thermostat (Eq. system1 with
+ *     gamma_dot = 0), sampled periodically (Mathematical Framework; Alg. LAMMPS SCRIPT).
+ *   - The mappings of Eq. (mappings).
+ *   - P_xy and the dissipation function of Eq. (TTCF1); Omega = -(V/T) gamma_dot P_xy in the
+ *     pressure-tensor sign convention (the paper writes P_xy as a shear stress).
+ * Where the paper does not fix a detail the chosen reading is stated at the spot.
+ */
+#include "ttcf_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------------------ */
+/* pair potential                                                                        */
+/* ------------------------------------------------------------------------------------ */
+
+/* phi(r) = 4[(1/r)^12 - c (1/r)^6] + shift, force on i from j = fscal * r_ij with
+ * fscal = -phi'(r)/r = 48 r^-14 - 24 c r^-8. */
+static void pair_eval(const orc_box* b, double r2, double* fscal, double* phi) {
+    double s = 1.0 / r2;
+    double s3 = s * s * s;
+    double s6 = s3 * s3;
+    *fscal = (48.0 * s6 - 24.0 * b->c_attr * s3) * s;
+    *phi = 4.0 * (s6 - b->c_attr * s3) + b->u_shift;
+}
+
+/* Minimum-image separation r_i - r_j in the sliding-brick box with LE offset dxle:
+ * the y image is chosen first; crossing it shifts x by the offset, then x and z are
+ * wrapped periodically. */
+static void min_image(const orc_box* b, double dxle, double xi, double yi, double zi,
+                      double xj, double yj, double zj, double d[3]) {
+    double dy = yi - yj;
+    double ny = rint(dy / b->ly);
+    dy = dy - ny * b->ly;
+    double dx = xi - xj;
+    dx = dx - ny * dxle;
+    dx = dx - b->lx * rint(dx / b->lx);
+    double dz = zi - zj;
+    dz = dz - b->lz * rint(dz / b->lz);
+    d[0] = dx;
+    d[1] = dy;
+    d[2] = dz;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* cell list                                                                             */
+/* ------------------------------------------------------------------------------------ */
+
+int32_t orc_cell_dims(const orc_box* b, int32_t dims[3]) {
+    dims[0] = (int32_t)floor(b->lx / b->rc);
+    dims[1] = (int32_t)floor(b->ly / b->rc);
+    dims[2] = (int32_t)floor(b->lz / b->rc);
+    if (dims[0] < 4 || dims[1] < 3 || dims[2] < 3) return -1;
+    return 0;
+}
+
+static int32_t cell_coord(double x, int32_t n, double inv_w) {
+    int32_t c = (int32_t)floor(x * inv_w);
+    if (c < 0) c = 0;
+    if (c > n - 1) c = n - 1;
+    return c;
+}
+
+int32_t orc_cell_list(const orc_box* b, const double* r, int32_t* cell_of, int32_t* order,
+                      int32_t* start) {
+    int32_t d[3];
+    if (orc_cell_dims(b, d) != 0) return -1;
+    const int32_t n = b->n;
+    const int32_t ncell = d[0] * d[1] * d[2];
+    const double inv[3] = {(double)d[0] / b->lx, (double)d[1] / b->ly, (double)d[2] / b->lz};
+    const double* x = r;
+    const double* y = r + n;
+    const double* z = r + 2 * n;
+    for (int32_t c = 0; c <= ncell; ++c) start[c] = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t cx = cell_coord(x[i], d[0], inv[0]);
+        int32_t cy = cell_coord(y[i], d[1], inv[1]);
+        int32_t cz = cell_coord(z[i], d[2], inv[2]);
+        cell_of[i] = cx + d[0] * (cy + d[1] * cz);
+        start[cell_of[i] + 1] += 1;
+    }
+    for (int32_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
+    int32_t* fill = (int32_t*)malloc(sizeof(int32_t) * (size_t)ncell);
+    if (!fill) return -2;
+    for (int32_t c = 0; c < ncell; ++c) fill[c] = start[c];
+    for (int32_t i = 0; i < n; ++i) order[fill[cell_of[i]]++] = i; /* ascending atom id */
+    free(fill);
+    return 0;
+}
+
+/* Visit every candidate j of atom i through the 27-cell neighbourhood. Rows of cells that
+ * lie across the y boundary are images displaced by +-dxle in x, so for them the x range
+ * is recomputed from the displaced image: all cells whose image overlaps
+ * [cx*w - rc, (cx+1)*w + rc] (plus a tiny margin for rounding of the cell index). */
+typedef void (*visit_fn)(void* ctx, int32_t i, int32_t j);
+
+static void for_each_candidate(const orc_box* b, double dxle, const int32_t d[3],
+                               const int32_t* cell_of, const int32_t* order,
+                               const int32_t* start, int32_t i, double reach, visit_fn fn,
+                               void* ctx) {
+    const double wx = b->lx / (double)d[0];
+    const int32_t c = cell_of[i];
+    const int32_t cx = c % d[0];
+    const int32_t cy = (c / d[0]) % d[1];
+    const int32_t cz = c / (d[0] * d[1]);
+    const double margin = 1e-9;
+    for (int32_t dz = -1; dz <= 1; ++dz) {
+        int32_t zz = (cz + dz + d[2]) % d[2];
+        for (int32_t dy = -1; dy <= 1; ++dy) {
+            int32_t yy = cy + dy;
+            double img = 0.0;
+            if (yy < 0) {
+                yy += d[1];
+                img = -1.0;
+            } else if (yy >= d[1]) {
+                yy -= d[1];
+                img = 1.0;
+            }
+            double sh = img * dxle;
+            int32_t lo = (int32_t)floor(((double)cx * wx - reach - margin - sh) / wx);
+            int32_t hi = (int32_t)floor(((double)(cx + 1) * wx + reach + margin - sh) / wx);
+            if (hi - lo + 1 > d[0]) hi = lo + d[0] - 1;
+            for (int32_t xx = lo; xx <= hi; ++xx) {
+                int32_t cxx = ((xx % d[0]) + d[0]) % d[0];
+                int32_t cell = cxx + d[0] * (yy + d[1] * zz);
+                for (int32_t s = start[cell]; s < start[cell + 1]; ++s) {
+                    int32_t j = order[s];
+                    if (j != i) fn(ctx, i, j);
+                }
+            }
+        }
+    }
+}
+
+typedef struct {
+    const orc_box* b;
+    double dxle;
+    const double* r;
+    double rc2;
+    double fi[3];
+    double u, w, npair;
+} force_ctx;
+
+static void force_visit(void* vctx, int32_t i, int32_t j) {
+    force_ctx* c = (force_ctx*)vctx;
+    const int32_t n = c->b->n;
+    const double* r = c->r;
+    double d[3];
+    min_image(c->b, c->dxle, r[i], r[n + i], r[2 * n + i], r[j], r[n + j], r[2 * n + j], d);
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 < c->rc2) {
+        double fs, phi;
+        pair_eval(c->b, r2, &fs, &phi);
+        c->fi[0] += fs * d[0];
+        c->fi[1] += fs * d[1];
+        c->fi[2] += fs * d[2];
+        /* every unordered pair is visited twice: half of each contribution */
+        c->u += 0.5 * phi;
+        c->w += 0.5 * (d[0] * (fs * d[1]));
+        c->npair += 0.5;
+    }
+}
+
+int32_t orc_forces(const orc_box* b, double dxle, const double* r, double* f, double* out) {
+    int32_t d[3];
+    if (orc_cell_dims(b, d) != 0) return -1;
+    const int32_t n = b->n;
+    const int32_t ncell = d[0] * d[1] * d[2];
+    int32_t* cell_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* start = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncell + 1));
+    if (!cell_of || !order || !start) {
+        free(cell_of);
+        free(order);
+        free(start);
+        return -2;
+    }
+    orc_cell_list(b, r, cell_of, order, start);
+    force_ctx c;
+    c.b = b;
+    c.dxle = dxle;
+    c.r = r;
+    c.rc2 = b->rc * b->rc;
+    c.u = 0.0;
+    c.w = 0.0;
+    c.npair = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        c.fi[0] = c.fi[1] = c.fi[2] = 0.0;
+        for_each_candidate(b, dxle, d, cell_of, order, start, i, b->rc, force_visit, &c);
+        f[i] = c.fi[0];
+        f[n + i] = c.fi[1];
+        f[2 * n + i] = c.fi[2];
+    }
+    out[0] = c.u;
+    out[1] = c.w;
+    out[2] = c.npair;
+    free(cell_of);
+    free(order);
+    free(start);
+    return 0;
+}
+
+int32_t orc_forces_brute(const orc_box* b, double dxle, const double* r, double* f,
+                         double* out) {
+    const int32_t n = b->n;
+    const double rc2 = b->rc * b->rc;
+    double u = 0.0, w = 0.0, npair = 0.0;
+    for (int32_t k = 0; k < 3 * n; ++k) f[k] = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t j = i + 1; j < n; ++j) {
+            /* every image of j: r_j + (mx*Lx + my*dxle, my*Ly, mz*Lz) */
+            for (int32_t my = -2; my <= 2; ++my) {
+                for (int32_t mx = -3; mx <= 3; ++mx) {
+                    for (int32_t mz = -2; mz <= 2; ++mz) {
+                        double dx = r[i] - (r[j] + (double)mx * b->lx + (double)my * dxle);
+                        double dy = r[n + i] - (r[n + j] + (double)my * b->ly);
+                        double dz = r[2 * n + i] - (r[2 * n + j] + (double)mz * b->lz);
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        if (r2 < rc2) {
+                            double fs, phi;
+                            pair_eval(b, r2, &fs, &phi);
+                            f[i] += fs * dx;
+                            f[n + i] += fs * dy;
+                            f[2 * n + i] += fs * dz;
+                            f[j] -= fs * dx;
+                            f[n + j] -= fs * dy;
+                            f[2 * n + j] -= fs * dz;
+                            u += phi;
+                            w += dx * (fs * dy);
+                            npair += 1.0;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    out[0] = u;
+    out[1] = w;
+    out[2] = npair;
+    return 0;
+}
+
+typedef struct {
+    const orc_box* b;
+    double dxle;
+    const double* r;
+    double rl2;
+    int64_t cap, cnt;
+    int32_t *pi, *pj;
+} pair_ctx;
+
+static void pair_visit(void* vctx, int32_t i, int32_t j) {
+    pair_ctx* c = (pair_ctx*)vctx;
+    if (j <= i) return;
+    const int32_t n = c->b->n;
+    const double* r = c->r;
+    double d[3];
+    min_image(c->b, c->dxle, r[i], r[n + i], r[2 * n + i], r[j], r[n + j], r[2 * n + j], d);
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 < c->rl2) {
+        if (c->cnt < c->cap) {
+            c->pi[c->cnt] = i;
+            c->pj[c->cnt] = j;
+        }
+        c->cnt += 1;
+    }
+}
+
+static int cmp_pair(const void* a, const void* b) {
+    const int64_t x = *(const int64_t*)a, y = *(const int64_t*)b;
+    return (x > y) - (x < y);
+}
+
+static void sort_pairs(int64_t cnt, int32_t* pi, int32_t* pj) {
+    int64_t* key = (int64_t*)malloc(sizeof(int64_t) * (size_t)(cnt > 0 ? cnt : 1));
+    for (int64_t k = 0; k < cnt; ++k) key[k] = ((int64_t)pi[k] << 32) | (int64_t)pj[k];
+    qsort(key, (size_t)cnt, sizeof(int64_t), cmp_pair);
+    for (int64_t k = 0; k < cnt; ++k) {
+        pi[k] = (int32_t)(key[k] >> 32);
+        pj[k] = (int32_t)(key[k] & 0xffffffff);
+    }
+    free(key);
+}
+
+int64_t orc_pairs(const orc_box* b, double dxle, const double* r, double rlist, int64_t cap,
+                  int32_t* pi, int32_t* pj) {
+    int32_t d[3];
+    if (orc_cell_dims(b, d) != 0 || rlist > b->rc) return -2;
+    const int32_t n = b->n;
+    const int32_t ncell = d[0] * d[1] * d[2];
+    int32_t* cell_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* start = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncell + 1));
+    orc_cell_list(b, r, cell_of, order, start);
+    pair_ctx c = {b, dxle, r, rlist * rlist, cap, 0, pi, pj};
+    for (int32_t i = 0; i < n; ++i)
+        for_each_candidate(b, dxle, d, cell_of, order, start, i, rlist, pair_visit, &c);
+    free(cell_of);
+    free(order);
+    free(start);
+    if (c.cnt > cap) return -1;
+    sort_pairs(c.cnt, pi, pj);
+    return c.cnt;
+}
+
+int64_t orc_pairs_brute(const orc_box* b, double dxle, const double* r, double rlist,
+                        int64_t cap, int32_t* pi, int32_t* pj) {
+    const int32_t n = b->n;
+    const double rl2 = rlist * rlist;
+    int64_t cnt = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t j = i + 1; j < n; ++j) {
+            double d[3];
+            min_image(b, dxle, r[i], r[n + i], r[2 * n + i], r[j], r[n + j], r[2 * n + j], d);
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            if (r2 < rl2) {
+                if (cnt < cap) {
+                    pi[cnt] = i;
+                    pj[cnt] = j;
+                }
+                ++cnt;
+            }
+        }
+    }
+    return cnt > cap ? -1 : cnt;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* observables and mappings                                                              */
+/* ------------------------------------------------------------------------------------ */
+
+static double kinetic(int32_t n, const double* p) {
+    double s = 0.0;
+    for (int32_t k = 0; k < 3 * n; ++k) s += p[k] * p[k];
+    return 0.5 * s;
+}
+
+static double sum_pxpy(int32_t n, const double* p) {
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s += p[i] * p[n + i];
+    return s;
+}
+
+double orc_vpxy(const orc_box* b, double dxle, const double* r, const double* p) {
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)b->n);
+    double out[3];
+    orc_forces(b, dxle, r, f, out);
+    free(f);
+    return sum_pxpy(b->n, p) + out[1];
+}
+
+void orc_map(const orc_box* b, int32_t m, const double* r, const double* p, double* r_out,
+             double* p_out) {
+    const int32_t n = b->n;
+    memcpy(r_out, r, sizeof(double) * 3 * (size_t)n);
+    memcpy(p_out, p, sizeof(double) * 3 * (size_t)n);
+    if (m == 1) {
+        for (int32_t k = 0; k < 3 * n; ++k) p_out[k] = -p[k];
+    } else if (m == 2 || m == 3) {
+        for (int32_t i = 0; i < n; ++i) {
+            /* x -> -x, brought back into [0, Lx) */
+            r_out[i] = (r[i] == 0.0) ? 0.0 : b->lx - r[i];
+        }
+        if (m == 2) {
+            for (int32_t i = 0; i < n; ++i) p_out[i] = -p[i];
+        } else {
+            for (int32_t i = 0; i < n; ++i) {
+                p_out[n + i] = -p[n + i];
+                p_out[2 * n + i] = -p[2 * n + i];
+            }
+        }
+    }
+}
+
+/* Periodic wrap of one coordinate into [0, L). */
+static double wrap1(double x, double l) {
+    if (x >= l) {
+        x -= l;
+        if (x >= l) x -= l * floor(x / l);
+    } else if (x < 0.0) {
+        x += l;
+        if (x < 0.0) x -= l * floor(x / l);
+        if (x >= l) x = 0.0; /* x was a tiny negative number: x + L rounded to L */
+    }
+    return x;
+}
+
+/* Sliding-brick wrap: crossing the top (bottom) face moves x by -dxle (+dxle). */
+static void wrap_le(const orc_box* b, double dxle, double* r) {
+    const int32_t n = b->n;
+    for (int32_t i = 0; i < n; ++i) {
+        double x = r[i], y = r[n + i];
+        if (y >= b->ly) {
+            y -= b->ly;
+            x -= dxle;
+        } else if (y < 0.0) {
+            y += b->ly;
+            x += dxle;
+            if (y >= b->ly) y = 0.0;
+        }
+        r[i] = wrap1(x, b->lx);
+        r[n + i] = y;
+        r[2 * n + i] = wrap1(r[2 * n + i], b->lz);
+    }
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* mother: Nose-Hoover equilibrium dynamics                                              */
+/* ------------------------------------------------------------------------------------ */
+
+/* One symmetric step (h = dt):
+ *   zeta += (h/2)(sum p^2 - nf T)/Q;  p *= exp(-zeta h/2);  p += (h/2) F;
+ *   r += h p (wrap);  F = F(r);  p += (h/2) F;  p *= exp(-zeta h/2);
+ *   zeta += (h/2)(sum p^2 - nf T)/Q.
+ * The paper's thermostat equation (Eq. system1) gives the zeta dynamics; the mass Q is
+ * not stated there and is a parameter here. */
+int32_t orc_nh_run(const orc_box* b, double temperature, double q, double nf, double dt,
+                   double* r, double* p, double* zeta, int64_t nsteps, double* vpxy_out,
+                   double* ke_out, double* pe_out) {
+    const int32_t n = b->n;
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!f) return -2;
+    double out[3];
+    if (orc_forces(b, 0.0, r, f, out) != 0) {
+        free(f);
+        return -1;
+    }
+    const double h = dt;
+    double z = *zeta;
+    if (vpxy_out) vpxy_out[0] = sum_pxpy(n, p) + out[1];
+    if (ke_out) ke_out[0] = kinetic(n, p);
+    if (pe_out) pe_out[0] = out[0];
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        double p2 = 2.0 * kinetic(n, p);
+        z += 0.5 * h * (p2 - nf * temperature) / q;
+        double sc = exp(-z * 0.5 * h);
+        for (int32_t k = 0; k < 3 * n; ++k) p[k] *= sc;
+        for (int32_t k = 0; k < 3 * n; ++k) p[k] += 0.5 * h * f[k];
+        for (int32_t k = 0; k < 3 * n; ++k) r[k] += h * p[k];
+        wrap_le(b, 0.0, r);
+        orc_forces(b, 0.0, r, f, out);
+        for (int32_t k = 0; k < 3 * n; ++k) p[k] += 0.5 * h * f[k];
+        sc = exp(-z * 0.5 * h);
+        for (int32_t k = 0; k < 3 * n; ++k) p[k] *= sc;
+        p2 = 2.0 * kinetic(n, p);
+        z += 0.5 * h * (p2 - nf * temperature) / q;
+        if (vpxy_out) vpxy_out[s] = sum_pxpy(n, p) + out[1];
+        if (ke_out) ke_out[s] = kinetic(n, p);
+        if (pe_out) pe_out[s] = out[0];
+    }
+    *zeta = z;
+    free(f);
+    return 0;
+}
+
+int32_t orc_mother_sample(const orc_box* b, double temperature, double q, double nf, double dt,
+                          double* r, double* p, double* zeta, int64_t n_equil,
+                          int32_t n_states, int64_t steps_between, double* states_r,
+                          double* states_p) {
+    const size_t sz = 3 * (size_t)b->n;
+    int32_t rc = orc_nh_run(b, temperature, q, nf, dt, r, p, zeta, n_equil, 0, 0, 0);
+    if (rc) return rc;
+    for (int32_t s = 0; s < n_states; ++s) {
+        rc = orc_nh_run(b, temperature, q, nf, dt, r, p, zeta, steps_between, 0, 0, 0);
+        if (rc) return rc;
+        memcpy(states_r + (size_t)s * sz, r, sizeof(double) * sz);
+        memcpy(states_p + (size_t)s * sz, p, sizeof(double) * sz);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* daughters: SLLOD with Lees-Edwards boundaries and a Gaussian isokinetic constraint    */
+/* ------------------------------------------------------------------------------------ */
+
+static double le_offset(const orc_box* b, double gamma_dot, double dt, int64_t k) {
+    return fmod(gamma_dot * b->ly * ((double)k * dt), b->lx);
+}
+
+/* Exact flow, over a time tau, of the momentum equation dp/dt = F - alpha p with F held
+ * fixed and alpha = (F.p)/(p.p) the Gaussian multiplier that keeps p.p constant
+ * (closed form of Zhang, J. Chem. Phys. 106, 6102 (1997)):
+ *   a = F.p/p.p, b = F.F/p.p, q = sqrt(b),
+ *   s(tau) = (a/b)(cosh(q tau) - 1) + sinh(q tau)/q,  s'(tau) = (a/q) sinh(q tau) + cosh(q tau),
+ *   p(tau) = (p(0) + F s(tau)) / s'(tau).
+ * cosh - 1 is formed as 2 sinh^2(q tau/2) to avoid cancellation. */
+void orc_iso_kick(int32_t n, double* p, const double* f, double tau) {
+    double pp = 0.0, fp = 0.0, ff = 0.0;
+    for (int32_t c = 0; c < 3 * n; ++c) {
+        pp += p[c] * p[c];
+        fp += f[c] * p[c];
+        ff += f[c] * f[c];
+    }
+    double a = fp / pp;
+    double b = ff / pp;
+    double ch1_b, sh_q; /* (cosh(q tau) - 1)/b and sinh(q tau)/q */
+    if (b > 0.0) {
+        double q = sqrt(b);
+        double hs = sinh(0.5 * q * tau) / q;
+        ch1_b = 2.0 * hs * hs;
+        sh_q = sinh(q * tau) / q;
+    } else {
+        ch1_b = 0.5 * tau * tau;
+        sh_q = tau;
+    }
+    double s = a * ch1_b + sh_q;
+    double sdot = a * sh_q + (1.0 + b * ch1_b);
+    for (int32_t c = 0; c < 3 * n; ++c) p[c] = (p[c] + f[c] * s) / sdot;
+}
+
+/* Exact flow, over a time tau, of dpx/dt = -gamma_dot py - alpha px, dpy/dt = -alpha py,
+ * dpz/dt = -alpha pz with alpha = -gamma_dot (sum px py)/(p.p): alpha multiplies every
+ * component, so the solution is the unconstrained shear flow px -> px - gamma_dot tau py
+ * scaled back to the initial p.p. */
+void orc_iso_shear(int32_t n, double* p, double gamma_dot, double tau) {
+    double pp0 = 0.0, pp1 = 0.0;
+    for (int32_t c = 0; c < 3 * n; ++c) pp0 += p[c] * p[c];
+    for (int32_t i = 0; i < n; ++i) p[i] -= tau * gamma_dot * p[n + i];
+    for (int32_t c = 0; c < 3 * n; ++c) pp1 += p[c] * p[c];
+    double g = sqrt(pp0 / pp1);
+    for (int32_t c = 0; c < 3 * n; ++c) p[c] *= g;
+}
+
+/* One step (h = dt) of Eq. (system1) with the Nose-Hoover term replaced by the Gaussian
+ * isokinetic multiplier alpha = (sum F.p - gamma_dot sum px py)/(sum p.p) (reading: the
+ * daughters are isokinetic). Symmetric splitting of the vector field into a shear part S,
+ * a force part K and a streaming part D, each integrated exactly:
+ *   S(h/2) K(h/2) D(h) [k += 1, new LE offset, sliding-brick wrap, F = F(r)] K(h/2) S(h/2)
+ * with
+ *   S: dpx/dt = -gamma_dot py (- alpha_S p under the constraint)
+ *   K: dp/dt = F (- alpha_K p under the constraint)
+ *   D: dx/dt = px + gamma_dot y, dy/dt = py, dz/dt = pz:
+ *      x += h px + h gamma_dot (y + (h/2) py); y += h py; z += h pz.
+ * Each constrained part keeps p.p fixed, so the step is second order, time reversible and
+ * isokinetic; a final rescale to K0 only removes round-off drift (its factor is 1 to
+ * within a few ulps). gik = 0 gives the adiabatic SLLOD step (no multiplier). */
+int32_t orc_sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik, double k0,
+                      double* r, double* p, int64_t* kstep, int64_t nsteps, double* vpxy_out,
+                      double* ke_out, double* pe_out) {
+    const int32_t n = b->n;
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!f) return -2;
+    double* x = r;
+    double* y = r + n;
+    double* z = r + 2 * n;
+    double* px = p;
+    double* py = p + n;
+    double* pz = p + 2 * n;
+    double out[3];
+    int64_t k = *kstep;
+    double dxle = le_offset(b, gamma_dot, dt, k);
+    if (orc_forces(b, dxle, r, f, out) != 0) {
+        free(f);
+        return -1;
+    }
+    if (k0 <= 0.0) k0 = kinetic(n, p);
+    const double h = dt;
+    if (vpxy_out) vpxy_out[0] = sum_pxpy(n, p) + out[1];
+    if (ke_out) ke_out[0] = kinetic(n, p);
+    if (pe_out) pe_out[0] = out[0];
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        if (gik) {
+            orc_iso_shear(n, p, gamma_dot, 0.5 * h);
+            orc_iso_kick(n, p, f, 0.5 * h);
+        } else {
+            for (int32_t i = 0; i < n; ++i) px[i] -= 0.5 * h * gamma_dot * py[i];
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] += 0.5 * h * f[c];
+        }
+        for (int32_t i = 0; i < n; ++i) {
+            x[i] += h * px[i] + h * gamma_dot * (y[i] + 0.5 * h * py[i]);
+            y[i] += h * py[i];
+            z[i] += h * pz[i];
+        }
+        k += 1;
+        dxle = le_offset(b, gamma_dot, dt, k);
+        wrap_le(b, dxle, r);
+        orc_forces(b, dxle, r, f, out);
+        if (gik) {
+            orc_iso_kick(n, p, f, 0.5 * h);
+            orc_iso_shear(n, p, gamma_dot, 0.5 * h);
+            double lam = sqrt(k0 / kinetic(n, p));
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] *= lam;
+        } else {
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] += 0.5 * h * f[c];
+            for (int32_t i = 0; i < n; ++i) px[i] -= 0.5 * h * gamma_dot * py[i];
+        }
+        if (vpxy_out) vpxy_out[s] = sum_pxpy(n, p) + out[1];
+        if (ke_out) ke_out[s] = kinetic(n, p);
+        if (pe_out) pe_out[s] = out[0];
+    }
+    *kstep = k;
+    free(f);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* batch of daughters on a thread pool (one daughter per thread at a time)               */
+/* ------------------------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_box* b;
+    double dt;
+    const double *states_r, *states_p;
+    int32_t n_daughters;
+    const int32_t *state_of, *map_of;
+    const double* gamma_of;
+    int64_t nsteps;
+    double *vpxy_out, *r_out, *p_out;
+    int32_t tid, nthreads;
+    int32_t status;
+} batch_job;
+
+static void* batch_worker(void* arg) {
+    batch_job* jb = (batch_job*)arg;
+    const size_t sz = 3 * (size_t)jb->b->n;
+    double* r = (double*)malloc(sizeof(double) * sz);
+    double* p = (double*)malloc(sizeof(double) * sz);
+    jb->status = 0;
+    for (int32_t d = jb->tid; d < jb->n_daughters; d += jb->nthreads) {
+        const int32_t s = jb->state_of[d];
+        orc_map(jb->b, jb->map_of[d], jb->states_r + (size_t)s * sz, jb->states_p + (size_t)s * sz,
+                r, p);
+        int64_t k = 0;
+        int32_t rc = orc_sllod_run(jb->b, jb->gamma_of[d], jb->dt, 1, 0.0, r, p, &k, jb->nsteps,
+                                   jb->vpxy_out + (size_t)d * (size_t)(jb->nsteps + 1), 0, 0);
+        if (rc) jb->status = rc;
+        if (jb->r_out) memcpy(jb->r_out + (size_t)d * sz, r, sizeof(double) * sz);
+        if (jb->p_out) memcpy(jb->p_out + (size_t)d * sz, p, sizeof(double) * sz);
+    }
+    free(r);
+    free(p);
+    return 0;
+}
+
+int32_t orc_run_daughters(const orc_box* b, double dt, const double* states_r,
+                          const double* states_p, int32_t n_daughters, const int32_t* state_of,
+                          const int32_t* map_of, const double* gamma_of, int64_t nsteps,
+                          int32_t nthreads, double* vpxy_out, double* r_out, double* p_out) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > n_daughters) nthreads = n_daughters > 0 ? n_daughters : 1;
+    batch_job* jobs = (batch_job*)calloc((size_t)nthreads, sizeof(batch_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    for (int32_t t = 0; t < nthreads; ++t) {
+        batch_job j = {b,      dt,     states_r, states_p, n_daughters, state_of, map_of,
+                       gamma_of, nsteps, vpxy_out, r_out,  p_out,       t,        nthreads, 0};
+        jobs[t] = j;
+        pthread_create(&th[t], 0, batch_worker, &jobs[t]);
+    }
+    int32_t status = 0;
+    for (int32_t t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], 0);
+        if (jobs[t].status) status = jobs[t].status;
+    }
+    free(jobs);
+    free(th);
+    return status ? status : nthreads;
+}

@@ -1,0 +1,111 @@
+/*
+ * ttcf_oracle.h -- plain FP64 CPU oracle for the TTCF daughter path of
+ * arxiv 2312.02990 (TTCF4LAMMPS).
+ *
+ * TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the benchmark's
+ * CPU-baseline leg load this library. The GPU library shares no code with it and
+ * never calls it.
+ *
+ * Conventions (LJ reduced units, m = sigma = epsilon = k_B = 1):
+ *   - state arrays are structure-of-arrays: r = [x(0..n-1) | y(..) | z(..)], same for p, f;
+ *   - p is the peculiar momentum (thermal part only; the streaming velocity gamma_dot*y
+ *     is carried by the SLLOD position equation);
+ *   - P_xy is the pressure-tensor component, V*P_xy = sum_i px_i py_i + sum_{i<j} x_ij F_y,ij.
+ *
+ * Parity status of each entry point is listed in the test-suite; every function here is
+ * pinned by at least one independent check (brute force, closed form or invariant).
+ */
+#ifndef TTCF_ORACLE_H
+#define TTCF_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int32_t n;        /* atoms                                                   */
+    int32_t pad_;
+    double  lx, ly, lz;  /* box edges                                            */
+    double  rc;       /* cutoff radius; pairs interact when r^2 < rc*rc           */
+    double  c_attr;   /* attraction factor c: phi = 4[(1/r)^12 - c (1/r)^6] + shift */
+    double  u_shift;  /* energy shift making phi(rc) = 0 (WCA: +1)               */
+} orc_box;
+
+/* Cell grid: n_a = floor(L_a / rc); returns 0 or -1 if any n_a < 3 or n_x < 4. */
+int32_t orc_cell_dims(const orc_box* b, int32_t dims[3]);
+
+/* Canonical cell list of positions r (SoA, every coordinate in [0, L)):
+ * cell_of[i] = cx + nx*(cy + ny*cz) with c_a = floor(r_a * (n_a / L_a)) clamped to [0, n_a-1];
+ * order[] lists atom ids sorted by (cell id, atom id); start[c]..start[c+1] is cell c's range. */
+int32_t orc_cell_list(const orc_box* b, const double* r, int32_t* cell_of, int32_t* order,
+                      int32_t* start);
+
+/* Pair forces through the cell list, Lees-Edwards offset dxle.
+ * f: SoA forces; out[0] = U (potential energy), out[1] = W_xy = sum_{i<j} x_ij F_y,ij,
+ * out[2] = number of interacting pairs. */
+int32_t orc_forces(const orc_box* b, double dxle, const double* r, double* f, double* out);
+
+/* Same quantities by an O(N^2) sum over explicit periodic / sliding-brick images. */
+int32_t orc_forces_brute(const orc_box* b, double dxle, const double* r, double* f, double* out);
+
+/* Pairs i<j with squared minimum-image separation < rlist^2, found through the cell list
+ * (requires rlist <= rc) and returned sorted by (i, j). Returns the count, or -1 if the
+ * capacity is too small. */
+int64_t orc_pairs(const orc_box* b, double dxle, const double* r, double rlist, int64_t cap,
+                  int32_t* pi, int32_t* pj);
+/* Same set by testing every pair i<j. */
+int64_t orc_pairs_brute(const orc_box* b, double dxle, const double* r, double rlist,
+                        int64_t cap, int32_t* pi, int32_t* pj);
+
+/* V*P_xy of a state at LE offset dxle. */
+double orc_vpxy(const orc_box* b, double dxle, const double* r, const double* p);
+
+/* The four phase-space mappings of a start state (m = 0 identity, 1 p->-p,
+ * 2 x-reflection (x,px)->(-x,-px), 3 (x,py,pz)->(-x,-py,-pz)); reflected x is wrapped
+ * back into [0, Lx). */
+void orc_map(const orc_box* b, int32_t m, const double* r, const double* p, double* r_out,
+             double* p_out);
+
+/* Nose-Hoover equilibrium run (gamma_dot = 0, plain periodic box), symmetric splitting.
+ * q = thermostat mass, nf = degrees of freedom. Per-step outputs may be NULL:
+ * vpxy_out[k], ke_out[k], pe_out[k] for k = 0..nsteps. */
+int32_t orc_nh_run(const orc_box* b, double temperature, double q, double nf, double dt,
+                   double* r, double* p, double* zeta, int64_t nsteps, double* vpxy_out,
+                   double* ke_out, double* pe_out);
+
+/* Exact isokinetic sub-flows (sum p.p preserved): force kick over tau with F fixed, and
+ * the shear flow dpx/dt = -gamma_dot py, both with the Gaussian multiplier. */
+void orc_iso_kick(int32_t n, double* p, const double* f, double tau);
+void orc_iso_shear(int32_t n, double* p, double gamma_dot, double tau);
+
+/* SLLOD run under Lees-Edwards boundaries, step counter k (LE offset
+ * dx = fmod(gamma_dot * ly * (k*dt), lx)); gik != 0 integrates the Gaussian isokinetic
+ * equations (kinetic energy held at k0; k0 <= 0: the kinetic energy of the initial p).
+ * Per-step outputs (k = 0..nsteps) may be NULL: vpxy_out, ke_out, pe_out. */
+int32_t orc_sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik, double k0,
+                      double* r, double* p, int64_t* k, int64_t nsteps, double* vpxy_out,
+                      double* ke_out, double* pe_out);
+
+/* Mother sampling: starting from (r, p, zeta) run n_equil NH steps, then n_states times
+ * {run steps_between NH steps; copy (r, p) into states_r/p[s]}. The thermostat state is
+ * carried through. states_r, states_p: n_states * 3n each. */
+int32_t orc_mother_sample(const orc_box* b, double temperature, double q, double nf, double dt,
+                          double* r, double* p, double* zeta, int64_t n_equil,
+                          int32_t n_states, int64_t steps_between, double* states_r,
+                          double* states_p);
+
+/* Batch of independent GIK-SLLOD daughters on a pool of nthreads threads.
+ * Daughter d starts from start state state_of[d] under mapping map_of[d] with shear rate
+ * gamma_of[d] and runs nsteps steps; its series V*P_xy(t_k), k = 0..nsteps, goes to
+ * vpxy_out[d*(nsteps+1) + k]. Final states (may be NULL) go to r_out/p_out[d*3n].
+ * Returns the number of threads used, or a negative error. */
+int32_t orc_run_daughters(const orc_box* b, double dt, const double* states_r,
+                          const double* states_p, int32_t n_daughters, const int32_t* state_of,
+                          const int32_t* map_of, const double* gamma_of, int64_t nsteps,
+                          int32_t nthreads, double* vpxy_out, double* r_out, double* p_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,215 @@
+"""Benchmark of the TTCF daughter path on one MI355X.
+
+Workload (the batched bulk configuration): WCA fluid, N = 2048 (8^3 fcc cells), rho = 0.8442,
+T = 0.722, dt = 0.0025. One Nose-Hoover mother (melted at T = 2 for 1000 steps, equilibrated
+2000 steps) is sampled every 100 steps into 1024 start states that stay resident in HBM. A
+benchmark step is one pass of the daughter path over one batch: spawn the 4 mapped daughters
+of every start state (4096 daughters), run 500 isokinetic SLLOD steps each in one persistent
+launch (FP32 pair forces, FP64 integration), accumulate, and form the TTCF response. The
+shear rate cycles through {1e-6, 1e-4, 1e-2, 1} from step to step.
+
+Prints one JSON line; ``value`` is daughter atom-steps per second over the timed steps.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "daughter atom-steps/s; TTCF σ(P_xy) per GPU-s, learned CV vs plain"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_ATOM_STEP = 96  # read and write of r and p in FP64 (6 x 8 B each way)
+GAMMAS = (1e-6, 1e-4, 1e-2, 1.0)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_daughters_config2_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_kernels.hip")
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they were taken on
+    the current kernel source; otherwise None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def host_threads() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n_cells: int, nsteps: int, budget_s: float):
+    """The FP64 oracle, unchanged, on a bounded sample of the same workload: daughters of the
+    same system size and length from seeded start states (perturbed fcc lattice with
+    Maxwell-Boltzmann momenta), one daughter per thread at a time on the host's cores."""
+    import oracle as orc
+    import ttcf_inputs as I
+    s = I.System(n_cells)
+    box = orc.make_box(s.n, s.box)
+    threads = host_threads()
+    # calibrate: one daughter, a few steps, one thread
+    r = I.perturbed_positions(s, 5, 0.1).reshape(1, -1)
+    p = I.maxwell_boltzmann(s.n, s.temperature, 5).reshape(1, -1)
+    t0 = time.perf_counter()
+    orc.run_daughters(box, r, p, [0], [0], [1e-2], s.dt, 20, nthreads=1)
+    per_step = (time.perf_counter() - t0) / 20
+    per_daughter = per_step * nsteps
+    n_d = max(threads, int(budget_s * threads / per_daughter) // threads * threads)
+    n_states = (n_d + 3) // 4
+    sr = np.stack([I.perturbed_positions(s, 100 + k, 0.1).ravel() for k in range(n_states)])
+    sp = np.stack([I.maxwell_boltzmann(s.n, s.temperature, 100 + k).ravel()
+                   for k in range(n_states)])
+    state_of = np.arange(n_d) // 4
+    map_of = np.arange(n_d) % 4
+    t0 = time.perf_counter()
+    _, used = orc.run_daughters(box, sr, sp, state_of, map_of, np.full(n_d, 1e-2), s.dt, nsteps,
+                                nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {
+        "value": n_d * s.n * nsteps / dt, "unit": "daughter atom-steps/s", "cores": int(used),
+        "kind": "oracle",
+        "sample": f"{n_d} daughters x {nsteps} steps of the N={s.n} system (FP64 oracle, "
+                  f"{used} threads, {cpu_model()}), {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-cells", type=int, default=8, help="fcc cells per edge (N = 4 n^3)")
+    ap.add_argument("--states", type=int, default=1024)
+    ap.add_argument("--daughter-steps", type=int, default=500)
+    ap.add_argument("--precision", type=int, default=1, help="0 FP64 forces, 1 FP32 forces")
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle work for the CPU baseline (0 to skip)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the daughter path shards by start state, and "
+              "this build measures one GPU's share (see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import ttcf_inputs as I
+    from paper_2312_02990_amd import ttcf as T
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    T.use_torch_allocator()
+    stream = T.current_stream()
+    s = I.System(args.n_cells)
+    sysd = T.make_system(s.n, s.box, s.temperature, s.dt, precision=args.precision)
+    r0, p0 = I.initial_state(s, 2)
+    ctx = T.Context(stream)
+    t0 = time.perf_counter()
+    mid = ctx.ttcf_init_mother(sysd, r0, p0, n_equil=2000, n_melt=1000, t_melt=2.0)
+    ctx.ttcf_sample_states(mid, args.states, 100)
+    torch.cuda.synchronize()
+    mother_s = time.perf_counter() - t0
+    mother_steps = 3000 + 100 * args.states
+
+    nst = args.daughter_steps
+    n_d = 4 * args.states
+
+    def one_step(i):
+        gd = GAMMAS[i % len(GAMMAS)]
+        ctx.ttcf_spawn_daughters(mid, args.states, 0, gd, nst)
+        ctx.ttcf_step(nst)
+        ctx.ttcf_accumulate()
+        return ctx.ttcf_response(nst + 1, gd)
+
+    for i in range(args.warmup):
+        one_step(i)
+    ctx.ttcf_step_timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    last = None
+    for i in range(args.steps):
+        last = one_step(args.warmup + i)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms, launches = ctx.ttcf_step_timing(reset=True)
+    ctx.close()
+
+    atom_steps = n_d * s.n * nst
+    value = atom_steps * args.steps / wall
+    avg_launch_s = kern_ms / 1e3 / max(launches, 1)
+    achieved = BYTES_PER_ATOM_STEP * atom_steps / avg_launch_s / 1e9
+    traffic = measured_traffic()
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "daughter atom-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pair forces / f64 integration and sums" if args.precision
+                 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"batched bulk WCA: N={s.n}, rho={s.density}, T={s.temperature}, "
+                        f"dt={s.dt}; {args.states} start states x 4 mappings = {n_d} daughters "
+                        f"x {nst} steps per batch, one persistent launch; shear rate cycling "
+                        f"{list(GAMMAS)}",
+            "n_atoms": s.n, "daughters": n_d, "daughter_steps": nst,
+            "parallelism": "one GPU",
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_daughters (persistent daughter step kernel)",
+            "kernel_ms_per_launch": 1e3 * avg_launch_s,
+            "algorithmic_bytes_per_launch": BYTES_PER_ATOM_STEP * atom_steps,
+        },
+        "kernel_atom_steps_per_s": atom_steps / avg_launch_s,
+        "mother_s": mother_s,
+        "mother_atom_steps_per_s": mother_steps * s.n / mother_s,
+        "last_response": {"gamma_dot": GAMMAS[(args.warmup + args.steps - 1) % len(GAMMAS)],
+                          "ttcf_end": float(last[0][-1]), "ttcf_se_end": float(last[1][-1]),
+                          "dav_end": float(last[2][-1]), "dav_se_end": float(last[3][-1])},
+    }
+    if args.cpu_budget > 0:
+        line["cpu_baseline"] = cpu_baseline(args.n_cells, nst, args.cpu_budget)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

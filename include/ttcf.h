@@ -1,0 +1,198 @@
+/*
+ * ttcf.h -- C ABI of the MI355X (gfx950) TTCF daughter library.
+ *
+ * The library integrates many SLLOD "daughter" trajectories branched from an equilibrium
+ * "mother" trajectory and turns them into a transient-time correlation function (TTCF)
+ * response, following arxiv 2312.02990 (TTCF4LAMMPS):
+ *   - Eq. (TTCF):      <B(t)> = <B(0)> + int_0^t <Omega(0) B(s)> ds
+ *   - Eq. (integrand): <Omega(0) B(s)> = (1/N) sum_i Omega(0)_i B(s)_i over N daughters
+ *   - Eq. (mappings):  every start state Gamma spawns Gamma, Gamma', Gamma'', Gamma'''
+ *   - Eq. (system1):   SLLOD equations of motion (Lees-Edwards sliding-brick boundaries)
+ *   - Eq. (TTCF1):     Omega = -(V/T) gamma_dot P_xy for the bulk shear field, with P_xy the
+ *                      pressure-tensor component (the paper writes +gamma_dot V P_xy / k_B T with
+ *                      P_xy read as the shear stress)
+ *   - Alg. LAMMPS SCRIPT: initialise, run the mother, save a state every N_s steps, map it,
+ *                      switch the field on, run N_d daughter steps, record the response.
+ * The five calls ttcf_init_mother, ttcf_spawn_daughters, ttcf_step, ttcf_accumulate and
+ * ttcf_response follow that algorithm; the remaining calls are inspection hooks.
+ *
+ * Conventions
+ *   - LJ reduced units (m = sigma = epsilon = k_B = 1).
+ *   - Every call returns an int32 status (TTCF_OK = 0, negative on error); out-parameters
+ *     are written only on success; ttcf_last_error(ctx) gives a message. No exception and no
+ *     C++ type crosses this interface.
+ *   - Host arrays are caller-owned and are read or written during the call only.
+ *     Position and momentum arrays are structure-of-arrays FP64: [x_0..x_{n-1}, y_0.., z_0..].
+ *     Momenta are peculiar momenta (the streaming part gamma_dot*y is not included).
+ *   - The context owns all device memory; allocations go through hipMalloc unless
+ *     ttcf_set_allocator installed other functions (before the first context was created).
+ *   - A context is single-threaded and stream-ordered: work is enqueued on the stream given
+ *     at creation; calls that return host data synchronise that stream.
+ *   - There is no CPU fallback: every call that computes runs HIP kernels and fails with
+ *     TTCF_EDEVICE when no gfx950 device is usable.
+ */
+#ifndef TTCF_H
+#define TTCF_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ttcf_ctx ttcf_ctx; /* opaque, owned by the library */
+
+enum {
+    TTCF_OK = 0,
+    TTCF_EINVAL = -1,    /* bad argument (sizes, box too small for the cell grid, ...)    */
+    TTCF_ENOMEM = -2,    /* device or host allocation failed                              */
+    TTCF_EDEVICE = -3,   /* a HIP call failed, or no usable gfx950 device                 */
+    TTCF_ESTATE = -4,    /* call out of order (e.g. a response before any accumulation)   */
+    TTCF_EUNSTABLE = -5  /* every daughter group failed its health check                  */
+};
+
+enum { TTCF_WCA = 0, TTCF_LJ = 1 };
+
+/* Arithmetic of the pair forces. Positions, momenta, the thermostat multiplier, P_xy and
+ * every accumulated sum are FP64 in both forms. */
+enum { TTCF_PREC_FP64 = 0, TTCF_PREC_FP32_FORCES = 1 };
+
+enum { TTCF_OBS_PXY = 0 };
+
+/* One simulated system (Example 1 of the paper: WCA fluid in a cubic periodic box). */
+typedef struct {
+    int32_t n_atoms;
+    int32_t potential;     /* TTCF_WCA or TTCF_LJ (phi = 4[(1/r)^12 - c_attr (1/r)^6] + shift)  */
+    double  box[3];        /* box edges Lx, Ly, Lz                                              */
+    double  temperature;   /* target T: mother thermostat and the Omega normalisation           */
+    double  dt;            /* time step                                                         */
+    double  r_cut;         /* cutoff; pairs interact when r^2 < r_cut^2 (WCA: 2^(1/6))          */
+    double  c_attr;        /* attraction factor c (WCA: 1)                                      */
+    double  u_shift;       /* energy shift making phi(r_cut) = 0 (WCA: 1)                       */
+    double  nh_tau;        /* mother Nose-Hoover time constant: Q = (3N-3) T nh_tau^2           */
+    int32_t precision;     /* TTCF_PREC_*                                                       */
+    int32_t block_threads; /* threads per workgroup for this system (0: chosen by the library)  */
+} ttcf_system;
+
+/* Optional allocator (e.g. a framework's caching allocator). Process-wide; must be set
+ * before the first context exists. NULL restores hipMalloc/hipFree. */
+typedef void* (*ttcf_alloc_fn)(uint64_t bytes, void* stream, void* user);
+typedef void (*ttcf_free_fn)(void* ptr, void* user);
+int32_t ttcf_set_allocator(ttcf_alloc_fn alloc, ttcf_free_fn release, void* user);
+
+/* ---- the five calls ----------------------------------------------------------------- */
+
+/* Alg. LAMMPS SCRIPT, "initialize system (null ext. field)" and "run N_t timestep".
+ * Creates a context when *ctx == NULL (stream: a hipStream_t, or NULL for the default
+ * stream), otherwise adds another mother to *ctx (systems of different size may share one
+ * context; their daughters then run in one batch). r0, p0: host, 3*n_atoms doubles each,
+ * every coordinate inside [0, L). Runs n_melt Nose-Hoover steps at t_melt (0 steps to skip)
+ * and then n_equil steps at sys->temperature, on the GPU. *out_mother receives the mother id. */
+int32_t ttcf_init_mother(ttcf_ctx** ctx, const ttcf_system* sys, const double* r0,
+                         const double* p0, int64_t n_melt, double t_melt, int64_t n_equil,
+                         void* stream, int32_t* out_mother);
+
+/* Alg. LAMMPS SCRIPT, the outer loop: for each of n_states start states "run N_s timestep,
+ * save system state", then for each mapping "load, apply mapping, switch on ext. field".
+ * steps_between > 0: the mother advances steps_between steps before each saved state (the
+ *   new states replace the mother's stored set);
+ * steps_between == 0: the mother's stored states are reused (n_states must equal their
+ *   count), so several shear rates can share one set of start states.
+ * mapping_mask: bit m selects mapping m of Eq. (mappings) (0xF: all four).
+ * gamma_dot: n_gamma == 1 (one rate for all) or n_gamma == n_states (one per state, shared by
+ *   its mapped daughters).
+ * n_steps: daughter length N_d. Daughters are numbered state-major from *out_first.
+ * Omega(0) and B(0) are taken on the mapped start state. */
+int32_t ttcf_spawn_daughters(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
+                             int64_t steps_between, uint32_t mapping_mask,
+                             const double* gamma_dot, int32_t n_gamma, int32_t n_steps,
+                             int64_t* out_first);
+
+/* Alg. LAMMPS SCRIPT, "run N_d timestep": advances every live daughter by up to n_steps
+ * steps (never past its own N_d) in one persistent kernel launch, recording B(t_k) = P_xy
+ * after every step. Asynchronous on the context's stream. */
+int32_t ttcf_step(ttcf_ctx* ctx, int32_t n_steps);
+
+/* Eq. (integrand) and Alg. SHELL SCRIPT "perform partial average and TTCF integration":
+ * folds every finished daughter into per-start-state sums (the trapezoid-rule integral of
+ * P_xy(0) B(s) and the direct average of B, compensated FP64) and frees its slot. A group
+ * whose daughters failed the health check (non-finite or drifting values) is kept out of
+ * every average as a whole, since dropping single mappings would break <Omega(0)> = 0.
+ * *out_groups (may be NULL) receives the number of healthy groups added. */
+int32_t ttcf_accumulate(ttcf_ctx* ctx, int64_t* out_groups);
+
+/* Eq. (TTCF) and Alg. SHELL SCRIPT "gather total averages, total TTCF integration,
+ * statistics". For k = 0..n_t-1 writes (any pointer may be NULL; n_t doubles each):
+ *   ttcf_mean[k] = <B(0)> + int_0^{t_k} <Omega(0) B(s)> ds   (trapezoid rule)
+ *   dav_mean[k]  = <B(t_k)>                                  (direct average)
+ *   *_se[k]      = block standard error over start states (std, ddof=1, / sqrt(count)).
+ * gamma_dot_filter > 0: only groups whose shear rate equals it exactly;
+ * gamma_dot_filter <= 0: every group, each divided by its own shear rate (the response per
+ *   unit shear rate; -ttcf_mean is then the transient viscosity of Eq. (visc)).
+ * Synchronises the stream. TTCF_ESTATE if no group matches or n_t exceeds the recorded
+ * length of a matching group. */
+int32_t ttcf_response(ttcf_ctx* ctx, int32_t observable, double gamma_dot_filter, int32_t n_t,
+                      double* ttcf_mean, double* ttcf_se, double* dav_mean, double* dav_se,
+                      int64_t* out_n_states);
+
+/* ---- lifetime and errors ------------------------------------------------------------ */
+
+void ttcf_destroy(ttcf_ctx* ctx);              /* NULL-safe; frees all device memory */
+const char* ttcf_strerror(int32_t code);       /* static string                      */
+const char* ttcf_last_error(const ttcf_ctx* ctx); /* valid until the next call on ctx  */
+
+/* ---- inspection hooks (tests and benchmarks) ---------------------------------------- */
+
+/* Alg. LAMMPS SCRIPT, "run N_s timestep, save system state" alone: the mother advances
+ * steps_between steps before each of n_states saved states (replacing the stored set);
+ * no daughter is spawned. */
+int32_t ttcf_sample_states(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
+                           int64_t steps_between);
+/* Replace the mother's stored start states by host data (n_states * 3n doubles each for
+ * r and p, state-major), so that a daughter batch can start from given states. */
+int32_t ttcf_import_states(ttcf_ctx* ctx, int32_t mother, int32_t n_states, const double* r,
+                           const double* p);
+/* Copy the mother's stored start states to host arrays of the same layout. */
+int32_t ttcf_export_states(ttcf_ctx* ctx, int32_t mother, int32_t n_states, double* r,
+                           double* p);
+/* Mother's current state: r, p (3n each), the Nose-Hoover variable and the step count. */
+int32_t ttcf_export_mother(ttcf_ctx* ctx, int32_t mother, double* r, double* p, double* zeta,
+                           int64_t* steps);
+/* Mother series: V*P_xy after every step of the last ttcf_init_mother/ttcf_spawn_daughters
+ * run on this mother when recording was enabled with ttcf_record_mother (n values). */
+int32_t ttcf_record_mother(ttcf_ctx* ctx, int32_t mother, int64_t capacity);
+int32_t ttcf_export_mother_series(ttcf_ctx* ctx, int32_t mother, int64_t n, double* vpxy,
+                                  int64_t* out_count);
+/* A live (not yet accumulated) daughter: r, p (3n each) and its step counter. */
+int32_t ttcf_export_daughter(ttcf_ctx* ctx, int64_t daughter, double* r, double* p,
+                             int64_t* k);
+/* Recorded series of live daughters first..first+count-1: vpxy[d*n_t + k] = V*P_xy(t_k). */
+int32_t ttcf_export_series(ttcf_ctx* ctx, int64_t first, int32_t count, int32_t n_t,
+                           double* vpxy);
+/* Health word of a live daughter (0 = healthy). */
+int32_t ttcf_daughter_health(ttcf_ctx* ctx, int64_t daughter, int32_t* health);
+/* Failure injection: writes NaN into momentum component 0 of atom 0 of a live daughter. */
+int32_t ttcf_debug_poison(ttcf_ctx* ctx, int64_t daughter);
+
+/* Stateless kernels on given host positions (SoA, inside the box), run on `stream`:
+ * the canonical cell list (cell_of[n], order[n], start[n_cells+1]; cell id
+ * cx + nx (cy + ny cz), c_a = floor(r_a * (n_a / L_a)), n_a = floor(L_a / r_cut)) ... */
+int32_t ttcf_debug_cell_list(const ttcf_system* sys, const double* r, int32_t* dims,
+                             int32_t* cell_of, int32_t* order, int32_t* start, void* stream);
+/* ... the pairs i<j with squared minimum-image separation < rlist^2 (rlist <= r_cut), found
+ * through the cell list at Lees-Edwards offset dxle, sorted by (i, j); *count receives the
+ * number found (-1 if cap is too small) ... */
+int32_t ttcf_debug_pairs(const ttcf_system* sys, double dxle, const double* r, double rlist,
+                         int64_t cap, int32_t* pi, int32_t* pj, int64_t* count, void* stream);
+/* ... and one force evaluation: f (3n, SoA), out[0] = U, out[1] = W_xy = sum_{i<j} x_ij F_y,ij,
+ * computed in sys->precision. */
+int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, double* f,
+                          double* out, void* stream);
+
+/* Device time of the daughter step kernel: total milliseconds and launch count since the
+ * last reset (timing events are recorded on the context's stream around every launch). */
+int32_t ttcf_step_timing(ttcf_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

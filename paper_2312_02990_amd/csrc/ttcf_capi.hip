@@ -1,0 +1,1056 @@
+// ttcf_capi.hip -- host runtime behind the C ABI of include/ttcf.h.
+//
+// Owns the mothers, the daughter descriptors and the per-start-state accumulators of one
+// context; every computing call enqueues gfx950 kernels from ttcf_kernels.hip on the
+// context's stream. There is no host fallback for any computation.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ttcf.h"
+#include "ttcf_internal.h"
+
+using namespace ttcf;
+
+namespace {
+
+ttcf_alloc_fn g_alloc = nullptr;
+ttcf_free_fn g_free = nullptr;
+void* g_user = nullptr;
+int g_live_contexts = 0;
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+    if (bytes == 0) bytes = 8;
+    if (g_alloc) return g_alloc((uint64_t)bytes, (void*)s, g_user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(void* p) {
+    if (!p) return;
+    if (g_free)
+        g_free(p, g_user);
+    else
+        (void)hipFree(p);
+}
+
+struct Mother {
+    ttcf_system sys{};
+    SysDev dev{};
+    int threads = 0, apt = 0;
+    double* state = nullptr;     // 6n
+    double* zeta = nullptr;      // 1
+    int64_t steps = 0;
+    double* states = nullptr;    // n_states * 6n
+    int32_t n_states = 0, states_cap = 0;
+    double* series = nullptr;    // recorded V*P_xy
+    int64_t series_cap = 0, series_count = 0;
+};
+
+struct Batch {
+    int32_t mother = -1;
+    int32_t n_daughters = 0;
+    int32_t n_steps = 0;
+    int64_t first_id = 0;
+    double* states = nullptr;    // n_daughters * 6n
+    double* series = nullptr;    // n_daughters * (n_steps + 1)
+    void* scratch = nullptr;     // spawn index arrays
+    int32_t remaining = 0;       // daughters not yet accumulated
+};
+
+struct Live {                   // host view of one live daughter
+    int64_t id;
+    int32_t batch;
+    int32_t index;              // within its batch
+    int32_t group;
+};
+
+}  // namespace
+
+struct ttcf_ctx {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int num_cu = 0;
+    size_t max_lds = 0;
+    std::string err;
+    std::vector<Mother> mothers;
+    std::vector<Batch> batches;
+    // live daughters: host mirror and device copy of their descriptors
+    std::vector<DaughterDesc> descs;
+    std::vector<Live> live;
+    DaughterDesc* d_descs = nullptr;
+    size_t d_descs_cap = 0;
+    bool device_newer = false;  // kernels have advanced the device descriptors
+    int32_t* d_order = nullptr;
+    size_t d_order_cap = 0;
+    int32_t* d_queue = nullptr;
+    int64_t next_id = 0;
+    int32_t next_group = 0;
+    // accumulated start-state groups
+    double* acc_d = nullptr;
+    double* acc_i = nullptr;
+    int64_t acc_rows = 0, acc_cap = 0;
+    int32_t acc_stride = 0;
+    std::vector<double> row_gamma, row_coef;
+    std::vector<int32_t> row_nt, row_health;
+    double* d_row_gamma = nullptr;
+    double* d_row_coef = nullptr;
+    int32_t* d_row_health = nullptr;
+    // timing of the step kernel
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
+    double step_ms = 0.0;
+    int64_t step_launches = 0;
+};
+
+namespace {
+
+int32_t fail(ttcf_ctx* c, int32_t code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHECK(ctx, expr)                                                                   \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail((ctx), TTCF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int32_t build_sysdev(const ttcf_system* s, SysDev* d, std::string* why) {
+    if (s->n_atoms < 2 || s->n_atoms > kMaxAtoms) {
+        *why = "n_atoms must be in [2, 65535]";
+        return TTCF_EINVAL;
+    }
+    if (!(s->r_cut > 0.0) || !(s->dt > 0.0) || !(s->temperature > 0.0)) {
+        *why = "r_cut, dt and temperature must be positive";
+        return TTCF_EINVAL;
+    }
+    d->n = s->n_atoms;
+    for (int a = 0; a < 3; ++a) {
+        if (!(s->box[a] > 0.0)) {
+            *why = "box edges must be positive";
+            return TTCF_EINVAL;
+        }
+        d->nc[a] = (int32_t)std::floor(s->box[a] / s->r_cut);
+        d->box[a] = s->box[a];
+        d->w[a] = s->box[a] / (double)d->nc[a];
+        d->inv_w[a] = (double)d->nc[a] / s->box[a];
+    }
+    if (d->nc[0] < 4 || d->nc[1] < 3 || d->nc[2] < 3 || d->nc[0] > kMaxCells1D ||
+        d->nc[1] > kMaxCells1D || d->nc[2] > kMaxCells1D) {
+        *why = "box too small for the cell grid (need floor(Lx/rc) >= 4, floor(Ly/rc), "
+               "floor(Lz/rc) >= 3)";
+        return TTCF_EINVAL;
+    }
+    d->rc = s->r_cut;
+    d->rc2 = s->r_cut * s->r_cut;
+    d->c_attr = s->c_attr;
+    d->u_shift = s->u_shift;
+    d->dt = s->dt;
+    d->volume = s->box[0] * s->box[1] * s->box[2];
+    return TTCF_OK;
+}
+
+int32_t check_shape(ttcf_ctx* c, const ttcf_system* s, const SysDev& d, int* threads, int* apt) {
+    const int t = pick_threads(d.n, s->block_threads);
+    if (t % 64 != 0 || t < 64 || t > kMaxThreads)
+        return fail(c, TTCF_EINVAL, "block_threads must be a multiple of 64 in [64, 1024]");
+    const int a = pick_apt(d.n, t);
+    if (a < 0) return fail(c, TTCF_EINVAL, "too many atoms for the chosen block size (max 4/thread)");
+    *threads = t;
+    *apt = a;
+    return TTCF_OK;
+}
+
+size_t lds_for(const SysDev& d, int precision) {
+    return lds_bytes_for(d.n, d.nc[0] * d.nc[1] * d.nc[2], 0, precision);
+}
+
+// Pull the device descriptors back when kernels have advanced them.
+int32_t sync_descs(ttcf_ctx* c) {
+    if (!c->device_newer || c->descs.empty()) return TTCF_OK;
+    HIPCHECK(c, hipMemcpyAsync(c->descs.data(), c->d_descs, sizeof(DaughterDesc) * c->descs.size(),
+                               hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->device_newer = false;
+    return TTCF_OK;
+}
+
+int32_t push_descs(ttcf_ctx* c) {
+    if (c->descs.empty()) return TTCF_OK;
+    if (c->d_descs_cap < c->descs.size()) {
+        dev_free(c->d_descs);
+        size_t cap = std::max<size_t>(c->descs.size(), 2 * c->d_descs_cap);
+        c->d_descs = (DaughterDesc*)dev_alloc(sizeof(DaughterDesc) * cap, c->stream);
+        if (!c->d_descs) return fail(c, TTCF_ENOMEM, "descriptor allocation failed");
+        c->d_descs_cap = cap;
+    }
+    HIPCHECK(c, hipMemcpyAsync(c->d_descs, c->descs.data(), sizeof(DaughterDesc) * c->descs.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    // pageable source: complete the copy before the host vector can change
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
+int32_t run_mother(ttcf_ctx* c, Mother& m, double temperature, int64_t n_chunks,
+                   int64_t steps_per_chunk, double* snapshots) {
+    if (steps_per_chunk <= 0 && n_chunks <= 0) return TTCF_OK;
+    MotherLaunch L{};
+    L.sys = m.dev;
+    L.state = m.state;
+    L.zeta = m.zeta;
+    L.temperature = temperature;
+    const double nf = 3.0 * m.dev.n - 3.0;
+    L.nf = nf;
+    L.q = nf * temperature * m.sys.nh_tau * m.sys.nh_tau;
+    L.n_chunks = n_chunks;
+    L.steps_per_chunk = steps_per_chunk;
+    L.snapshots = snapshots;
+    const int64_t total = (n_chunks > 0 ? n_chunks : 1) * steps_per_chunk;
+    L.series = nullptr;
+    if (m.series && m.series_count + total <= m.series_cap) {
+        L.series = m.series + m.series_count;
+        m.series_count += total;
+    }
+    L.threads = m.threads;
+    L.apt = m.apt;
+    L.precision = m.sys.precision;
+    L.lds_bytes = lds_for(m.dev, m.sys.precision);
+    HIPCHECK(c, launch_mother(L, c->stream));
+    m.steps += total;
+    return TTCF_OK;
+}
+
+int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
+    const int32_t stride = std::max(c->acc_stride, n_t);
+    if (rows_needed <= c->acc_cap && stride == c->acc_stride) return TTCF_OK;
+    const int64_t cap = std::max<int64_t>(rows_needed, 2 * c->acc_cap);
+    double* nd = (double*)dev_alloc(sizeof(double) * (size_t)cap * stride, c->stream);
+    double* ni = (double*)dev_alloc(sizeof(double) * (size_t)cap * stride, c->stream);
+    double* ng = (double*)dev_alloc(sizeof(double) * (size_t)cap, c->stream);
+    double* nc = (double*)dev_alloc(sizeof(double) * (size_t)cap, c->stream);
+    int32_t* nh = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)cap, c->stream);
+    if (!nd || !ni || !ng || !nc || !nh) return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
+    if (c->acc_rows > 0) {
+        HIPCHECK(c, hipMemcpy2DAsync(nd, sizeof(double) * stride, c->acc_d,
+                                     sizeof(double) * c->acc_stride, sizeof(double) * c->acc_stride,
+                                     (size_t)c->acc_rows, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHECK(c, hipMemcpy2DAsync(ni, sizeof(double) * stride, c->acc_i,
+                                     sizeof(double) * c->acc_stride, sizeof(double) * c->acc_stride,
+                                     (size_t)c->acc_rows, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+    }
+    dev_free(c->acc_d);
+    dev_free(c->acc_i);
+    dev_free(c->d_row_gamma);
+    dev_free(c->d_row_coef);
+    dev_free(c->d_row_health);
+    c->acc_d = nd;
+    c->acc_i = ni;
+    c->d_row_gamma = ng;
+    c->d_row_coef = nc;
+    c->d_row_health = nh;
+    c->acc_cap = cap;
+    c->acc_stride = stride;
+    return TTCF_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------------------
+
+extern "C" {
+
+int32_t ttcf_set_allocator(ttcf_alloc_fn alloc, ttcf_free_fn release, void* user) {
+    if (g_live_contexts > 0) return TTCF_ESTATE;
+    if ((alloc == nullptr) != (release == nullptr)) return TTCF_EINVAL;
+    g_alloc = alloc;
+    g_free = release;
+    g_user = user;
+    return TTCF_OK;
+}
+
+const char* ttcf_strerror(int32_t code) {
+    switch (code) {
+        case TTCF_OK: return "ok";
+        case TTCF_EINVAL: return "invalid argument";
+        case TTCF_ENOMEM: return "out of memory";
+        case TTCF_EDEVICE: return "device error";
+        case TTCF_ESTATE: return "call out of order";
+        case TTCF_EUNSTABLE: return "every daughter group failed its health check";
+    }
+    return "unknown error";
+}
+
+const char* ttcf_last_error(const ttcf_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+void ttcf_destroy(ttcf_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& ev : c->pending_events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    for (auto& m : c->mothers) {
+        dev_free(m.state);
+        dev_free(m.zeta);
+        dev_free(m.states);
+        dev_free(m.series);
+    }
+    for (auto& b : c->batches) {
+        dev_free(b.states);
+        dev_free(b.series);
+        dev_free(b.scratch);
+    }
+    dev_free(c->d_descs);
+    dev_free(c->d_order);
+    dev_free(c->d_queue);
+    dev_free(c->acc_d);
+    dev_free(c->acc_i);
+    dev_free(c->d_row_gamma);
+    dev_free(c->d_row_coef);
+    dev_free(c->d_row_health);
+    --g_live_contexts;
+    delete c;
+}
+
+int32_t ttcf_init_mother(ttcf_ctx** pctx, const ttcf_system* sys, const double* r0,
+                         const double* p0, int64_t n_melt, double t_melt, int64_t n_equil,
+                         void* stream, int32_t* out_mother) {
+    if (!pctx || !sys || !r0 || !p0 || n_melt < 0 || n_equil < 0) return TTCF_EINVAL;
+    if (sys->precision != TTCF_PREC_FP64 && sys->precision != TTCF_PREC_FP32_FORCES)
+        return TTCF_EINVAL;
+    if (n_melt > 0 && !(t_melt > 0.0)) return TTCF_EINVAL;
+    ttcf_ctx* c = *pctx;
+    bool created = false;
+    if (!c) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return TTCF_EDEVICE;
+        c = new ttcf_ctx();
+        created = true;
+        ++g_live_contexts;
+        c->stream = (hipStream_t)stream;
+        if (hipGetDevice(&c->device) != hipSuccess) {
+            ttcf_destroy(c);
+            return TTCF_EDEVICE;
+        }
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+            ttcf_destroy(c);
+            return TTCF_EDEVICE;
+        }
+        c->num_cu = prop.multiProcessorCount;
+        c->max_lds = prop.sharedMemPerBlock;
+        c->d_queue = (int32_t*)dev_alloc(sizeof(int32_t) * 4, c->stream);
+        if (!c->d_queue) {
+            ttcf_destroy(c);
+            return TTCF_ENOMEM;
+        }
+    }
+    Mother m;
+    m.sys = *sys;
+    std::string why;
+    int32_t rc = build_sysdev(sys, &m.dev, &why);
+    if (rc == TTCF_OK) rc = check_shape(c, sys, m.dev, &m.threads, &m.apt);
+    else c->err = why;
+    if (rc == TTCF_OK && lds_for(m.dev, sys->precision) > c->max_lds)
+        rc = fail(c, TTCF_EINVAL, "system too large for one workgroup's LDS");
+    if (rc != TTCF_OK) {
+        if (created) ttcf_destroy(c);
+        return rc;
+    }
+    const int n = sys->n_atoms;
+    for (int k = 0; k < 3 * n; ++k) {
+        const int a = k / n;
+        if (!(r0[k] >= 0.0 && r0[k] < sys->box[a]) || !std::isfinite(p0[k])) {
+            if (created) ttcf_destroy(c);
+            else c->err = "initial positions must lie in [0, L) and momenta be finite";
+            return TTCF_EINVAL;
+        }
+    }
+    m.state = (double*)dev_alloc(sizeof(double) * 6 * n, c->stream);
+    m.zeta = (double*)dev_alloc(sizeof(double), c->stream);
+    if (!m.state || !m.zeta) {
+        dev_free(m.state);
+        dev_free(m.zeta);
+        if (created) ttcf_destroy(c);
+        return TTCF_ENOMEM;
+    }
+    const double zero = 0.0;
+    HIPCHECK(c, hipMemcpyAsync(m.state, r0, sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(m.state + 3 * n, p0, sizeof(double) * 3 * n, hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHECK(c, hipMemcpyAsync(m.zeta, &zero, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->mothers.push_back(m);
+    Mother& mm = c->mothers.back();
+    rc = run_mother(c, mm, t_melt, 0, n_melt, nullptr);
+    if (rc == TTCF_OK) rc = run_mother(c, mm, sys->temperature, 0, n_equil, nullptr);
+    if (rc != TTCF_OK) return rc;
+    *pctx = c;
+    if (out_mother) *out_mother = (int32_t)c->mothers.size() - 1;
+    return TTCF_OK;
+}
+
+int32_t ttcf_record_mother(ttcf_ctx* c, int32_t mother, int64_t capacity) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || capacity < 0) return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(m.series);
+    m.series = capacity > 0 ? (double*)dev_alloc(sizeof(double) * capacity, c->stream) : nullptr;
+    if (capacity > 0 && !m.series) return fail(c, TTCF_ENOMEM, "series allocation failed");
+    m.series_cap = capacity;
+    m.series_count = 0;
+    return TTCF_OK;
+}
+
+int32_t ttcf_export_mother_series(ttcf_ctx* c, int32_t mother, int64_t n, double* vpxy,
+                                  int64_t* out_count) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || n < 0) return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    const int64_t cnt = std::min(n, m.series_count);
+    if (cnt > 0 && vpxy)
+        HIPCHECK(c, hipMemcpyAsync(vpxy, m.series, sizeof(double) * cnt, hipMemcpyDeviceToHost,
+                                   c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (out_count) *out_count = m.series_count;
+    return TTCF_OK;
+}
+
+int32_t ttcf_import_states(ttcf_ctx* c, int32_t mother, int32_t n_states, const double* r,
+                           const double* p) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || !r || !p)
+        return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    const size_t n = (size_t)m.dev.n;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (m.states_cap < n_states) {
+        dev_free(m.states);
+        m.states = (double*)dev_alloc(sizeof(double) * 6 * n * n_states, c->stream);
+        if (!m.states) return fail(c, TTCF_ENOMEM, "state buffer allocation failed");
+        m.states_cap = n_states;
+    }
+    for (int32_t s = 0; s < n_states; ++s) {
+        HIPCHECK(c, hipMemcpyAsync(m.states + 6 * n * s, r + 3 * n * s, sizeof(double) * 3 * n,
+                                   hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(m.states + 6 * n * s + 3 * n, p + 3 * n * s,
+                                   sizeof(double) * 3 * n, hipMemcpyHostToDevice, c->stream));
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    m.n_states = n_states;
+    return TTCF_OK;
+}
+
+int32_t ttcf_export_states(ttcf_ctx* c, int32_t mother, int32_t n_states, double* r, double* p) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0) return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    if (n_states > m.n_states) return fail(c, TTCF_EINVAL, "fewer stored states than requested");
+    const size_t n = (size_t)m.dev.n;
+    for (int32_t s = 0; s < n_states; ++s) {
+        if (r)
+            HIPCHECK(c, hipMemcpyAsync(r + 3 * n * s, m.states + 6 * n * s, sizeof(double) * 3 * n,
+                                       hipMemcpyDeviceToHost, c->stream));
+        if (p)
+            HIPCHECK(c, hipMemcpyAsync(p + 3 * n * s, m.states + 6 * n * s + 3 * n,
+                                       sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
+int32_t ttcf_export_mother(ttcf_ctx* c, int32_t mother, double* r, double* p, double* zeta,
+                           int64_t* steps) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size()) return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    const size_t n = (size_t)m.dev.n;
+    if (r) HIPCHECK(c, hipMemcpyAsync(r, m.state, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
+    if (p)
+        HIPCHECK(c, hipMemcpyAsync(p, m.state + 3 * n, sizeof(double) * 3 * n, hipMemcpyDeviceToHost,
+                                   c->stream));
+    if (zeta) HIPCHECK(c, hipMemcpyAsync(zeta, m.zeta, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (steps) *steps = m.steps;
+    return TTCF_OK;
+}
+
+int32_t ttcf_sample_states(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 ||
+        steps_between <= 0)
+        return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    const size_t n = (size_t)m.dev.n;
+    if (m.states_cap < n_states) {
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        dev_free(m.states);
+        m.states = (double*)dev_alloc(sizeof(double) * 6 * n * n_states, c->stream);
+        if (!m.states) return fail(c, TTCF_ENOMEM, "state buffer allocation failed");
+        m.states_cap = n_states;
+    }
+    int32_t rc = run_mother(c, m, m.sys.temperature, n_states, steps_between, m.states);
+    if (rc != TTCF_OK) return rc;
+    m.n_states = n_states;
+    return TTCF_OK;
+}
+
+int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
+                             uint32_t mapping_mask, const double* gamma_dot, int32_t n_gamma,
+                             int32_t n_steps, int64_t* out_first) {
+    if (!c) return TTCF_EINVAL;
+    if (mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || steps_between < 0 ||
+        (mapping_mask & 0xFu) == 0 || (mapping_mask & ~0xFu) != 0 || !gamma_dot ||
+        !(n_gamma == 1 || n_gamma == n_states) || n_steps < 0)
+        return fail(c, TTCF_EINVAL, "bad spawn arguments");
+    for (int32_t g = 0; g < n_gamma; ++g)
+        if (!std::isfinite(gamma_dot[g])) return fail(c, TTCF_EINVAL, "shear rates must be finite");
+    Mother& m = c->mothers[mother];
+    const size_t n = (size_t)m.dev.n;
+    if (steps_between > 0) {
+        int32_t rc = ttcf_sample_states(c, mother, n_states, steps_between);
+        if (rc != TTCF_OK) return rc;
+    } else if (m.n_states != n_states) {
+        return fail(c, TTCF_EINVAL, "steps_between == 0 needs n_states equal to the stored count");
+    }
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    std::vector<int32_t> maps;
+    for (int q = 0; q < 4; ++q)
+        if (mapping_mask & (1u << q)) maps.push_back(q);
+    const int32_t nm = (int32_t)maps.size();
+    const int32_t nd = n_states * nm;
+    Batch b;
+    b.mother = mother;
+    b.n_daughters = nd;
+    b.n_steps = n_steps;
+    b.first_id = c->next_id;
+    b.remaining = nd;
+    b.states = (double*)dev_alloc(sizeof(double) * 6 * n * nd, c->stream);
+    b.series = (double*)dev_alloc(sizeof(double) * (size_t)(n_steps + 1) * nd, c->stream);
+    const size_t scratch_bytes = sizeof(int32_t) * 2 * nd + sizeof(double*) * nd + 64;
+    b.scratch = dev_alloc(scratch_bytes, c->stream);
+    if (!b.states || !b.series || !b.scratch) {
+        dev_free(b.states);
+        dev_free(b.series);
+        dev_free(b.scratch);
+        return fail(c, TTCF_ENOMEM, "daughter allocation failed");
+    }
+    std::vector<char> host(scratch_bytes);
+    double** dst = (double**)host.data();
+    int32_t* state_of = (int32_t*)(host.data() + sizeof(double*) * nd);
+    int32_t* map_of = state_of + nd;
+    const int32_t bidx = (int32_t)c->batches.size();
+    for (int32_t s = 0; s < n_states; ++s) {
+        const int32_t group = c->next_group++;
+        const double g = gamma_dot[n_gamma == 1 ? 0 : s];
+        for (int32_t q = 0; q < nm; ++q) {
+            const int32_t d = s * nm + q;
+            dst[d] = b.states + 6 * n * d;
+            state_of[d] = s;
+            map_of[d] = maps[q];
+            DaughterDesc ds{};
+            ds.state = dst[d];
+            ds.series = b.series + (size_t)(n_steps + 1) * d;
+            ds.sys = m.dev;
+            ds.gamma_dot = g;
+            ds.k0 = 0.0;
+            ds.k = 0;
+            ds.n_steps = n_steps;
+            ds.done = 0;
+            ds.health = 0;
+            ds.group = group;
+            ds.map = maps[q];
+            ds.block = m.threads;
+            c->descs.push_back(ds);
+            c->live.push_back(Live{c->next_id + d, bidx, d, group});
+        }
+    }
+    HIPCHECK(c, hipMemcpyAsync(b.scratch, host.data(), scratch_bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, launch_spawn(m.states, m.dev.n, n_states, (const int32_t*)((char*)b.scratch + sizeof(double*) * nd),
+                             (const int32_t*)((char*)b.scratch + sizeof(double*) * nd) + nd,
+                             (double* const*)b.scratch, nd, m.dev.box[0], c->stream));
+    // the host copy of the index arrays must outlive the asynchronous copy
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->batches.push_back(b);
+    c->next_id += nd;
+    rc = push_descs(c);
+    if (rc != TTCF_OK) return rc;
+    if (out_first) *out_first = b.first_id;
+    return TTCF_OK;
+}
+
+int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
+    if (!c || n_steps < 0) return TTCF_EINVAL;
+    if (c->descs.empty() || n_steps == 0) return TTCF_OK;
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    // daughters still to run, largest systems first; one launch shape for all
+    std::vector<int32_t> order;
+    int nmax = 0, cmax = 0, threads = 0, apt = 1, precision = -1;
+    for (size_t i = 0; i < c->descs.size(); ++i) {
+        const DaughterDesc& d = c->descs[i];
+        if (d.health != 0 || d.done >= d.n_steps) continue;
+        order.push_back((int32_t)i);
+        nmax = std::max(nmax, d.sys.n);
+        cmax = std::max(cmax, d.sys.nc[0] * d.sys.nc[1] * d.sys.nc[2]);
+        threads = std::max(threads, d.block);
+        const Mother& m = c->mothers[c->batches[c->live[i].batch].mother];
+        if (precision < 0) precision = m.sys.precision;
+        else if (precision != m.sys.precision)
+            return fail(c, TTCF_EINVAL, "live daughters mix force precisions");
+    }
+    if (order.empty()) return TTCF_OK;
+    apt = pick_apt(nmax, threads);
+    if (apt < 0) return fail(c, TTCF_EINVAL, "batch needs more than 4 atoms per thread");
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return c->descs[a].sys.n > c->descs[b].sys.n;
+    });
+    if (c->d_order_cap < order.size()) {
+        dev_free(c->d_order);
+        c->d_order = (int32_t*)dev_alloc(sizeof(int32_t) * order.size() * 2, c->stream);
+        if (!c->d_order) return fail(c, TTCF_ENOMEM, "order allocation failed");
+        c->d_order_cap = order.size() * 2;
+    }
+    HIPCHECK(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int32_t) * order.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    BatchLaunch L{};
+    L.descs = c->d_descs;
+    L.order = c->d_order;
+    L.n_jobs = (int32_t)order.size();
+    L.queue = c->d_queue;
+    L.max_steps = n_steps;
+    L.threads = threads;
+    L.apt = apt;
+    L.precision = precision;
+    L.nmax = nmax;
+    L.cmax = cmax;
+    L.lds_bytes = lds_bytes_for(nmax, cmax, threads, precision);
+    if (L.lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
+    const int per_cu_lds = (int)(c->max_lds / L.lds_bytes);
+    const int per_cu_waves = 32 / (threads / 64);  // 8 waves per SIMD, 4 SIMDs
+    const int per_cu = std::max(1, std::min(per_cu_lds, per_cu_waves));
+    L.grid = std::min<int>(L.n_jobs, per_cu * c->num_cu);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHECK(c, hipEventCreate(&e0));
+    HIPCHECK(c, hipEventCreate(&e1));
+    HIPCHECK(c, hipEventRecord(e0, c->stream));
+    HIPCHECK(c, launch_daughters(L, c->stream));
+    HIPCHECK(c, hipEventRecord(e1, c->stream));
+    c->pending_events.emplace_back(e0, e1);
+    c->device_newer = true;
+    return TTCF_OK;
+}
+
+int32_t ttcf_step_timing(ttcf_ctx* c, double* total_ms, int64_t* launches, int32_t reset) {
+    if (!c) return TTCF_EINVAL;
+    for (auto& ev : c->pending_events) {
+        HIPCHECK(c, hipEventSynchronize(ev.second));
+        float ms = 0.0f;
+        HIPCHECK(c, hipEventElapsedTime(&ms, ev.first, ev.second));
+        c->step_ms += ms;
+        c->step_launches += 1;
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    c->pending_events.clear();
+    if (total_ms) *total_ms = c->step_ms;
+    if (launches) *launches = c->step_launches;
+    if (reset) {
+        c->step_ms = 0.0;
+        c->step_launches = 0;
+    }
+    return TTCF_OK;
+}
+
+int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
+    if (!c) return TTCF_EINVAL;
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    // ready groups: every daughter finished or failed; groups are contiguous in descs
+    std::vector<int32_t> first_of;
+    std::vector<char> take(c->descs.size(), 0);
+    size_t i = 0;
+    std::vector<std::pair<size_t, size_t>> ready;
+    while (i < c->descs.size()) {
+        size_t j = i;
+        bool done = true;
+        while (j < c->descs.size() && c->descs[j].group == c->descs[i].group) {
+            const DaughterDesc& d = c->descs[j];
+            if (d.health == 0 && d.done < d.n_steps) done = false;
+            ++j;
+        }
+        if (done) ready.emplace_back(i, j);
+        i = j;
+    }
+    if (ready.empty()) {
+        if (out_groups) *out_groups = 0;
+        return TTCF_OK;
+    }
+    // groups with equal series length go in one launch; lengths may differ between batches
+    std::vector<int32_t> lens;
+    for (auto& r : ready) lens.push_back(c->descs[r.first].n_steps + 1);
+    int32_t maxlen = *std::max_element(lens.begin(), lens.end());
+    rc = grow_acc(c, c->acc_rows + (int64_t)ready.size(), maxlen);
+    if (rc != TTCF_OK) return rc;
+    int64_t added_healthy = 0;
+    std::vector<int32_t> uniq = lens;
+    std::sort(uniq.begin(), uniq.end());
+    uniq.erase(std::unique(uniq.begin(), uniq.end()), uniq.end());
+    int32_t* d_first = (int32_t*)dev_alloc(sizeof(int32_t) * (ready.size() + 1), c->stream);
+    if (!d_first) return fail(c, TTCF_ENOMEM, "index allocation failed");
+    for (int32_t len : uniq) {
+        first_of.clear();
+        std::vector<size_t> which;
+        for (size_t g = 0; g < ready.size(); ++g)
+            if (lens[g] == len) which.push_back(g);
+        // the kernel reads each group's daughters as a contiguous desc range
+        // (group k: descs [first_of[k], first_of[k+1]) ); build a compacted desc array
+        std::vector<DaughterDesc> sub;
+        for (size_t g : which) {
+            first_of.push_back((int32_t)sub.size());
+            for (size_t q = ready[g].first; q < ready[g].second; ++q) sub.push_back(c->descs[q]);
+        }
+        first_of.push_back((int32_t)sub.size());
+        DaughterDesc* d_sub = (DaughterDesc*)dev_alloc(sizeof(DaughterDesc) * sub.size(), c->stream);
+        if (!d_sub) {
+            dev_free(d_first);
+            return fail(c, TTCF_ENOMEM, "descriptor allocation failed");
+        }
+        HIPCHECK(c, hipMemcpyAsync(d_sub, sub.data(), sizeof(DaughterDesc) * sub.size(),
+                                   hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(d_first, first_of.data(), sizeof(int32_t) * first_of.size(),
+                                   hipMemcpyHostToDevice, c->stream));
+        AccumLaunch A{};
+        A.descs = d_sub;
+        A.first_of = d_first;
+        A.d_out = c->acc_d + (size_t)c->acc_rows * c->acc_stride;
+        A.i_out = c->acc_i + (size_t)c->acc_rows * c->acc_stride;
+        A.health_out = c->d_row_health + c->acc_rows;
+        A.gamma_out = c->d_row_gamma + c->acc_rows;
+        A.n_groups = (int32_t)which.size();
+        A.n_t = len;
+        // rows are written with the context's stride
+        if (c->acc_stride != len) {
+            // launch one group at a time into strided rows
+            for (int32_t g = 0; g < A.n_groups; ++g) {
+                AccumLaunch one = A;
+                one.first_of = d_first + g;
+                one.d_out = A.d_out + (size_t)g * c->acc_stride;
+                one.i_out = A.i_out + (size_t)g * c->acc_stride;
+                one.health_out = A.health_out + g;
+                one.gamma_out = A.gamma_out + g;
+                one.n_groups = 1;
+                HIPCHECK(c, launch_accumulate(one, c->stream));
+            }
+        } else {
+            HIPCHECK(c, launch_accumulate(A, c->stream));
+        }
+        std::vector<int32_t> hh(which.size());
+        HIPCHECK(c, hipMemcpyAsync(hh.data(), A.health_out, sizeof(int32_t) * which.size(),
+                                   hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        dev_free(d_sub);
+        for (size_t q = 0; q < which.size(); ++q) {
+            const DaughterDesc& d0 = c->descs[ready[which[q]].first];
+            c->row_gamma.push_back(d0.gamma_dot);
+            c->row_coef.push_back(d0.sys.volume * d0.gamma_dot /
+                                  c->mothers[c->batches[c->live[ready[which[q]].first].batch].mother]
+                                      .sys.temperature);
+            c->row_nt.push_back(len);
+            c->row_health.push_back(hh[q]);
+            if (hh[q] == 0) ++added_healthy;
+        }
+        c->acc_rows += (int64_t)which.size();
+        for (size_t g : which)
+            for (size_t q = ready[g].first; q < ready[g].second; ++q) take[q] = 1;
+    }
+    dev_free(d_first);
+    HIPCHECK(c, hipMemcpyAsync(c->d_row_coef, c->row_coef.data(), sizeof(double) * c->row_coef.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->d_row_gamma, c->row_gamma.data(),
+                               sizeof(double) * c->row_gamma.size(), hipMemcpyHostToDevice, c->stream));
+    // drop accumulated daughters; free batches with nothing left
+    std::vector<DaughterDesc> nd;
+    std::vector<Live> nl;
+    for (size_t q = 0; q < c->descs.size(); ++q) {
+        if (take[q]) {
+            c->batches[c->live[q].batch].remaining -= 1;
+        } else {
+            nd.push_back(c->descs[q]);
+            nl.push_back(c->live[q]);
+        }
+    }
+    c->descs.swap(nd);
+    c->live.swap(nl);
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    for (auto& b : c->batches) {
+        if (b.remaining == 0 && b.states) {
+            dev_free(b.states);
+            dev_free(b.series);
+            dev_free(b.scratch);
+            b.states = nullptr;
+            b.series = nullptr;
+            b.scratch = nullptr;
+        }
+    }
+    rc = push_descs(c);
+    if (rc != TTCF_OK) return rc;
+    if (out_groups) *out_groups = added_healthy;
+    if (added_healthy == 0) return fail(c, TTCF_EUNSTABLE, "every finished group failed its health check");
+    return TTCF_OK;
+}
+
+int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, int32_t n_t,
+                      double* ttcf_mean, double* ttcf_se, double* dav_mean, double* dav_se,
+                      int64_t* out_n_states) {
+    if (!c || observable != TTCF_OBS_PXY || n_t <= 0) return TTCF_EINVAL;
+    std::vector<int32_t> rows;
+    for (int64_t r = 0; r < c->acc_rows; ++r) {
+        if (gamma_dot_filter > 0.0 && c->row_gamma[r] != gamma_dot_filter) continue;
+        if (c->row_health[r] != 0) continue;
+        if (gamma_dot_filter <= 0.0 && c->row_gamma[r] == 0.0) continue;
+        rows.push_back((int32_t)r);
+    }
+    if (rows.empty()) return fail(c, TTCF_ESTATE, "no accumulated group matches the filter");
+    for (int32_t r : rows)
+        if (c->row_nt[r] < n_t) return fail(c, TTCF_ESTATE, "n_t exceeds a matching group's length");
+    const size_t bytes = sizeof(int32_t) * rows.size() + sizeof(double) * 4 * n_t + 64;
+    char* scratch = (char*)dev_alloc(bytes, c->stream);
+    if (!scratch) return fail(c, TTCF_ENOMEM, "response scratch allocation failed");
+    double* d_out = (double*)scratch;
+    int32_t* d_used = (int32_t*)(scratch + sizeof(double) * 4 * n_t);
+    int32_t* d_rows = d_used + 4;
+    HIPCHECK(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    std::vector<int32_t> hh = c->row_health;
+    HIPCHECK(c, hipMemcpyAsync(c->d_row_health, hh.data(), sizeof(int32_t) * hh.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    ResponseLaunch R{};
+    R.d_all = c->acc_d;
+    R.i_all = c->acc_i;
+    R.gamma = c->d_row_gamma;
+    R.coef = c->d_row_coef;
+    R.health = c->d_row_health;
+    R.rows = d_rows;
+    R.n_rows = (int32_t)rows.size();
+    R.n_t = n_t;
+    R.n_t_stride = c->acc_stride;
+    R.normalise = gamma_dot_filter <= 0.0 ? 1 : 0;
+    R.out = d_out;
+    R.used = d_used;
+    HIPCHECK(c, launch_response(R, c->stream));
+    std::vector<double> out(4 * (size_t)n_t);
+    int32_t used = 0;
+    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * 4 * n_t, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHECK(c, hipMemcpyAsync(&used, d_used, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(scratch);
+    if (ttcf_mean) std::memcpy(ttcf_mean, out.data(), sizeof(double) * n_t);
+    if (ttcf_se) std::memcpy(ttcf_se, out.data() + n_t, sizeof(double) * n_t);
+    if (dav_mean) std::memcpy(dav_mean, out.data() + 2 * n_t, sizeof(double) * n_t);
+    if (dav_se) std::memcpy(dav_se, out.data() + 3 * n_t, sizeof(double) * n_t);
+    if (out_n_states) *out_n_states = used;
+    return TTCF_OK;
+}
+
+static int32_t find_live(ttcf_ctx* c, int64_t id) {
+    for (size_t i = 0; i < c->live.size(); ++i)
+        if (c->live[i].id == id) return (int32_t)i;
+    return -1;
+}
+
+int32_t ttcf_export_daughter(ttcf_ctx* c, int64_t daughter, double* r, double* p, int64_t* k) {
+    if (!c) return TTCF_EINVAL;
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    const int32_t i = find_live(c, daughter);
+    if (i < 0) return fail(c, TTCF_EINVAL, "no such live daughter");
+    const DaughterDesc& d = c->descs[i];
+    const size_t n = (size_t)d.sys.n;
+    if (r) HIPCHECK(c, hipMemcpyAsync(r, d.state, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, c->stream));
+    if (p)
+        HIPCHECK(c, hipMemcpyAsync(p, d.state + 3 * n, sizeof(double) * 3 * n, hipMemcpyDeviceToHost,
+                                   c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (k) *k = d.k;
+    return TTCF_OK;
+}
+
+int32_t ttcf_export_series(ttcf_ctx* c, int64_t first, int32_t count, int32_t n_t, double* vpxy) {
+    if (!c || count <= 0 || n_t <= 0 || !vpxy) return TTCF_EINVAL;
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t i = find_live(c, first + q);
+        if (i < 0) return fail(c, TTCF_EINVAL, "no such live daughter");
+        const DaughterDesc& d = c->descs[i];
+        if (n_t > d.n_steps + 1) return fail(c, TTCF_EINVAL, "n_t exceeds the daughter length");
+        HIPCHECK(c, hipMemcpyAsync(vpxy + (size_t)q * n_t, d.series, sizeof(double) * n_t,
+                                   hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
+int32_t ttcf_daughter_health(ttcf_ctx* c, int64_t daughter, int32_t* health) {
+    if (!c || !health) return TTCF_EINVAL;
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    const int32_t i = find_live(c, daughter);
+    if (i < 0) return fail(c, TTCF_EINVAL, "no such live daughter");
+    *health = c->descs[i].health;
+    return TTCF_OK;
+}
+
+int32_t ttcf_debug_poison(ttcf_ctx* c, int64_t daughter) {
+    if (!c) return TTCF_EINVAL;
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    const int32_t i = find_live(c, daughter);
+    if (i < 0) return fail(c, TTCF_EINVAL, "no such live daughter");
+    const DaughterDesc& d = c->descs[i];
+    const double nan = std::nan("");
+    HIPCHECK(c, hipMemcpyAsync(d.state + 3 * (size_t)d.sys.n, &nan, sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
+// ---- stateless inspection kernels ---------------------------------------------------------
+
+static int32_t debug_setup(const ttcf_system* sys, const double* r, SysDev* S, double** d_r,
+                           hipStream_t s) {
+    std::string why;
+    int32_t rc = build_sysdev(sys, S, &why);
+    if (rc != TTCF_OK) return rc;
+    if (pick_apt(S->n, pick_threads(S->n, 0)) < 0) return TTCF_EINVAL;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return TTCF_EDEVICE;
+    if (lds_bytes_for(S->n, S->nc[0] * S->nc[1] * S->nc[2], 0, 0) > prop.sharedMemPerBlock)
+        return TTCF_EINVAL;
+    for (int k = 0; k < 3 * S->n; ++k)
+        if (!(r[k] >= 0.0 && r[k] < S->box[k / S->n])) return TTCF_EINVAL;
+    *d_r = (double*)dev_alloc(sizeof(double) * 3 * S->n, s);
+    if (!*d_r) return TTCF_ENOMEM;
+    if (hipMemcpyAsync(*d_r, r, sizeof(double) * 3 * S->n, hipMemcpyHostToDevice, s) != hipSuccess)
+        return TTCF_EDEVICE;
+    return TTCF_OK;
+}
+
+int32_t ttcf_debug_cell_list(const ttcf_system* sys, const double* r, int32_t* dims,
+                             int32_t* cell_of, int32_t* order, int32_t* start, void* stream) {
+    if (!sys || !r || !cell_of || !order || !start) return TTCF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    SysDev S{};
+    double* d_r = nullptr;
+    int32_t rc = debug_setup(sys, r, &S, &d_r, s);
+    if (rc != TTCF_OK) {
+        dev_free(d_r);
+        return rc;
+    }
+    const int C = S.nc[0] * S.nc[1] * S.nc[2];
+    int32_t* buf = (int32_t*)dev_alloc(sizeof(int32_t) * (2 * S.n + C + 1), s);
+    if (!buf) {
+        dev_free(d_r);
+        return TTCF_ENOMEM;
+    }
+    hipError_t e = launch_debug_cells(S, d_r, buf, buf + S.n, buf + 2 * S.n, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cell_of, buf, sizeof(int32_t) * S.n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(order, buf + S.n, sizeof(int32_t) * S.n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(start, buf + 2 * S.n, sizeof(int32_t) * (C + 1), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(buf);
+    dev_free(d_r);
+    if (e != hipSuccess) return TTCF_EDEVICE;
+    if (dims) {
+        dims[0] = S.nc[0];
+        dims[1] = S.nc[1];
+        dims[2] = S.nc[2];
+    }
+    return TTCF_OK;
+}
+
+int32_t ttcf_debug_pairs(const ttcf_system* sys, double dxle, const double* r, double rlist,
+                         int64_t cap, int32_t* pi, int32_t* pj, int64_t* count, void* stream) {
+    if (!sys || !r || !pi || !pj || !count || cap < 0 || !(rlist > 0.0) || rlist > sys->r_cut)
+        return TTCF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    SysDev S{};
+    double* d_r = nullptr;
+    int32_t rc = debug_setup(sys, r, &S, &d_r, s);
+    if (rc != TTCF_OK) {
+        dev_free(d_r);
+        return rc;
+    }
+    const size_t cap_sz = (size_t)std::max<int64_t>(cap, 1);
+    int32_t* buf = (int32_t*)dev_alloc(sizeof(int32_t) * 2 * cap_sz + 16, s);
+    if (!buf) {
+        dev_free(d_r);
+        return TTCF_ENOMEM;
+    }
+    unsigned long long* d_cnt = (unsigned long long*)(buf + 2 * cap_sz);
+    const unsigned long long zero = 0;
+    hipError_t e = hipMemcpyAsync(d_cnt, &zero, sizeof(zero), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_debug_pairs(S, dxle, d_r, rlist, cap, buf, buf + cap_sz, d_cnt, s);
+    unsigned long long cnt = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && (int64_t)cnt <= cap) {
+        std::vector<int32_t> a(cnt), b(cnt);
+        e = hipMemcpyAsync(a.data(), buf, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(b.data(), buf + cap_sz, sizeof(int32_t) * cnt,
+                                                hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        // the kernel emits pairs in arrival order; present them sorted by (i, j)
+        std::vector<int64_t> key(cnt);
+        for (size_t q = 0; q < cnt; ++q) key[q] = ((int64_t)a[q] << 32) | (int64_t)(uint32_t)b[q];
+        std::sort(key.begin(), key.end());
+        for (size_t q = 0; q < cnt; ++q) {
+            pi[q] = (int32_t)(key[q] >> 32);
+            pj[q] = (int32_t)(key[q] & 0xffffffff);
+        }
+    }
+    dev_free(buf);
+    dev_free(d_r);
+    if (e != hipSuccess) return TTCF_EDEVICE;
+    *count = (int64_t)cnt <= cap ? (int64_t)cnt : -1;
+    return TTCF_OK;
+}
+
+int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, double* f,
+                          double* out, void* stream) {
+    if (!sys || !r || !f || !out) return TTCF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    SysDev S{};
+    double* d_r = nullptr;
+    int32_t rc = debug_setup(sys, r, &S, &d_r, s);
+    if (rc != TTCF_OK) {
+        dev_free(d_r);
+        return rc;
+    }
+    double* buf = (double*)dev_alloc(sizeof(double) * (3 * S.n + 2), s);
+    if (!buf) {
+        dev_free(d_r);
+        return TTCF_ENOMEM;
+    }
+    hipError_t e = launch_debug_forces(S, sys->precision, dxle, d_r, buf, buf + 3 * S.n, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, buf, sizeof(double) * 3 * S.n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, buf + 3 * S.n, sizeof(double) * 2, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(buf);
+    dev_free(d_r);
+    return e == hipSuccess ? TTCF_OK : TTCF_EDEVICE;
+}
+
+}  // extern "C"

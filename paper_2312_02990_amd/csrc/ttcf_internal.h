@@ -1,0 +1,120 @@
+// ttcf_internal.h -- device-side parameter blocks and kernel launchers shared by the
+// gfx950 kernels (ttcf_kernels.hip) and the host runtime behind the C ABI (ttcf_capi.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ttcf {
+
+constexpr int kMaxThreads = 1024;
+constexpr int kMaxWaves = kMaxThreads / 64;
+constexpr int kRedSlots = 12;       // doubles reduced per block reduction
+constexpr int kMaxCells1D = 1023;   // packed cell coordinates use 10 bits each
+constexpr int kMaxAtoms = 65535;    // sorted atom ids are stored as uint16
+
+// Constants of one simulated system, uniform inside a workgroup.
+struct SysDev {
+    int32_t n;          // atoms
+    int32_t nc[3];      // cell grid, n_a = floor(L_a / r_cut)
+    double box[3];      // L_a
+    double w[3];        // cell widths L_a / n_a
+    double inv_w[3];    // n_a / L_a (one FP64 division on the host, as the cell index needs)
+    double rc, rc2;     // cutoff and its square
+    double c_attr;      // attraction factor c
+    double u_shift;     // energy shift
+    double dt;
+    double volume;
+};
+
+// One daughter trajectory. Owned by the host runtime; the kernel updates k, done, health.
+struct DaughterDesc {
+    double* state;      // 6n doubles: x | y | z | px | py | pz
+    double* series;     // n_steps + 1 doubles: V * P_xy(t_k)
+    SysDev sys;
+    double gamma_dot;
+    double k0;          // kinetic energy held by the isokinetic constraint
+    int64_t k;          // strain counter: LE offset = fmod(gamma_dot Ly (k dt), Lx)
+    int32_t n_steps;    // daughter length N_d
+    int32_t done;       // steps completed so far
+    int32_t health;     // 0 healthy; bit 0 non-finite, bit 1 kinetic-energy drift
+    int32_t group;      // start-state group (accumulator slot)
+    int32_t map;        // mapping 0..3
+    int32_t block;      // threads per workgroup the launcher was sized for
+};
+
+enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2 };
+
+// Launch configuration of the persistent daughter kernel.
+struct BatchLaunch {
+    DaughterDesc* descs;   // device array
+    const int32_t* order;  // device: job order (largest systems first)
+    int32_t n_jobs;
+    int32_t* queue;        // device counter (zeroed by the launcher)
+    int32_t max_steps;     // steps this call (each daughter stops at its own N_d)
+    int32_t threads;       // workgroup size
+    int32_t apt;           // atoms per thread (template selector: 1, 2, 4 or 8)
+    int32_t precision;     // 0 FP64 forces, 1 FP32 forces
+    int32_t grid;          // workgroups (persistent)
+    int32_t nmax, cmax;    // largest system / cell grid in the batch (LDS sizing)
+    size_t lds_bytes;
+};
+
+struct MotherLaunch {
+    SysDev sys;
+    double* state;         // 6n doubles
+    double* zeta;          // device scalar: Nose-Hoover variable
+    double temperature;    // target
+    double q;              // thermostat mass
+    double nf;             // degrees of freedom
+    int64_t n_chunks;      // snapshots to take (0: just run steps_per_chunk)
+    int64_t steps_per_chunk;
+    double* snapshots;     // n_chunks * 6n doubles, or nullptr
+    double* series;        // V*P_xy after every step (n_chunks*steps_per_chunk), or nullptr
+    int32_t threads, apt, precision;
+    size_t lds_bytes;
+};
+
+struct AccumLaunch {
+    const DaughterDesc* descs;   // device
+    const int32_t* first_of;     // device: first desc index of each group (n_groups + 1)
+    double* d_out;               // n_groups rows of stride n_t: mean over mappings of P_xy(t_k)
+    double* i_out;               // same: mean over mappings of int_0^t P_xy(0) P_xy(s) ds
+    int32_t* health_out;         // n_groups
+    double* gamma_out;           // n_groups
+    int32_t n_groups, n_t;
+};
+
+struct ResponseLaunch {
+    const double* d_all;         // groups' direct-average series (row stride n_t_stride)
+    const double* i_all;         // groups' integral series
+    const double* gamma;         // per group shear rate
+    const double* coef;          // per group V gamma / T (Omega(0) = -coef P_xy(0))
+    const int32_t* health;       // per group health
+    const int32_t* rows;         // selected group rows
+    int32_t n_rows, n_t, n_t_stride;
+    int32_t normalise;           // divide each group by its own shear rate
+    double* out;                 // 4 * n_t: ttcf mean, ttcf se, dav mean, dav se
+    int32_t* used;               // number of healthy rows
+};
+
+// Host-side choice of the per-daughter kernel shape.
+int pick_threads(int n, int requested);
+int pick_apt(int n, int threads);
+size_t lds_bytes_for(int nmax, int cmax, int threads, int precision);
+
+hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s);
+hipError_t launch_mother(const MotherLaunch& m, hipStream_t s);
+hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s);
+hipError_t launch_response(const ResponseLaunch& r, hipStream_t s);
+hipError_t launch_spawn(const double* states, int32_t n, int32_t n_states, const int32_t* state_of,
+                        const int32_t* map_of, double* const* dst, int32_t n_daughters, double lx,
+                        hipStream_t s);
+hipError_t launch_debug_cells(const SysDev& sys, const double* r, int32_t* cell_of, int32_t* order,
+                              int32_t* start, hipStream_t s);
+hipError_t launch_debug_pairs(const SysDev& sys, double dxle, const double* r, double rlist,
+                              int64_t cap, int32_t* pi, int32_t* pj, unsigned long long* count,
+                              hipStream_t s);
+hipError_t launch_debug_forces(const SysDev& sys, int precision, double dxle, const double* r,
+                               double* f, double* out, hipStream_t s);
+
+}  // namespace ttcf

@@ -1,0 +1,1233 @@
+// ttcf_kernels.hip -- gfx950 kernels of the TTCF daughter path (arxiv 2312.02990).
+//
+// One workgroup owns one trajectory (a daughter, or the mother). Positions and momenta live
+// in FP64 registers of their owner thread (atom a belongs to thread a % T); the cell list is
+// rebuilt in LDS every step (counting sort, canonical (cell, atom id) order), and the pair
+// forces are evaluated one sorted slot per thread over the 27-cell neighbourhood, whose rows
+// across the y boundary are displaced by the Lees-Edwards offset. Pair separations are
+// formed from coordinates relative to the owning cell's corner, so the FP32 force form loses
+// no precision to the absolute coordinate. All reductions are fixed-order wavefront butterflies
+// followed by a fixed-order sum over waves: results are deterministic.
+#include <hip/hip_runtime.h>
+
+#include "ttcf_internal.h"
+
+namespace ttcf {
+
+// ---------------------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------------------
+
+template <typename Real> struct Vec4;
+template <> struct Vec4<float> { using T = float4; };
+template <> struct Vec4<double> { using T = double4; };
+
+__device__ __forceinline__ float pack_cell(float, int v) { return __int_as_float(v); }
+__device__ __forceinline__ double pack_cell(double, int v) { return (double)v; }
+__device__ __forceinline__ int unpack_cell(float w) { return __float_as_int(w); }
+__device__ __forceinline__ int unpack_cell(double w) { return (int)w; }
+
+// Reciprocal: hardware estimate refined by Newton steps to (near) correct rounding.
+__device__ __forceinline__ float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// Cell coordinate of one FP64 coordinate: floor(v * (n / L)), clamped. A lone product,
+// so nothing can be contracted and the result is bit-identical to any IEEE evaluation.
+__device__ __forceinline__ int cell_coord(double v, double inv_w, int nc) {
+    int c = (int)floor(v * inv_w);
+    return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
+}
+
+__device__ __forceinline__ double wrap1(double x, double l) {
+    if (x >= l) {
+        x -= l;
+        if (x >= l) x -= l * floor(x / l);
+    } else if (x < 0.0) {
+        x += l;
+        if (x < 0.0) x -= l * floor(x / l);
+        if (x >= l) x = 0.0;
+    }
+    return x;
+}
+
+__device__ __forceinline__ double le_offset(const SysDev& S, double gamma_dot, int64_t k) {
+    return fmod(gamma_dot * S.box[1] * ((double)k * S.dt), S.box[0]);
+}
+
+// Sliding-brick wrap of one atom after a move (y crossing shifts x by -+ dxle).
+__device__ __forceinline__ void wrap_le(const SysDev& S, double dxle, double& x, double& y,
+                                        double& z) {
+    if (y >= S.box[1]) {
+        y -= S.box[1];
+        x -= dxle;
+    } else if (y < 0.0) {
+        y += S.box[1];
+        x += dxle;
+        if (y >= S.box[1]) y = 0.0;
+    }
+    x = wrap1(x, S.box[0]);
+    z = wrap1(z, S.box[2]);
+}
+
+// ---------------------------------------------------------------------------------------
+// LDS layout
+// ---------------------------------------------------------------------------------------
+
+template <typename Real>
+struct Lds {
+    typename Vec4<Real>::T* spos;  // [nmax] sorted cell-relative positions, .w = packed cell
+    Real* ax;                      // [nmax] per atom id: relative x, later F_x
+    Real* ay;
+    Real* az;
+    double* red;                   // block-reduction scratch
+    Real* shx;                     // [3 rows][5] x shift of each stencil column
+    Real* shyz;                    // [6]: y shifts (dy = -1,0,1), z shifts
+    int32_t* rowinfo;              // [3 rows][2]: first column offset mod nx, column count
+    int32_t* cnt;                  // [cmax] counts, then placement cursors
+    int32_t* start;                // [cmax + 1]
+    uint16_t* sid;                 // [nmax] atom ids in canonical order
+    int32_t* scan;                 // [kMaxWaves]
+    int32_t* misc;                 // [4]
+};
+
+struct LdsPlan {
+    size_t spos, ax, ay, az, red, shx, shyz, rowinfo, cnt, start, sid, scan, misc, total;
+};
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) & ~(a - 1); }
+
+__host__ __device__ inline LdsPlan plan_lds(int nmax, int cmax, size_t real_bytes) {
+    LdsPlan p;
+    size_t off = 0;
+    auto take = [&](size_t bytes, size_t al) {
+        off = align_up(off, al);
+        size_t at = off;
+        off += bytes;
+        return at;
+    };
+    p.spos = take(4 * real_bytes * (size_t)nmax, 32);
+    p.ax = take(real_bytes * (size_t)nmax, 16);
+    p.ay = take(real_bytes * (size_t)nmax, 16);
+    p.az = take(real_bytes * (size_t)nmax, 16);
+    p.red = take(sizeof(double) * (kMaxWaves * kRedSlots + kRedSlots), 16);
+    p.shx = take(real_bytes * 16, 16);
+    p.shyz = take(real_bytes * 8, 16);
+    p.rowinfo = take(sizeof(int32_t) * 8, 16);
+    p.cnt = take(sizeof(int32_t) * (size_t)cmax, 16);
+    p.start = take(sizeof(int32_t) * (size_t)(cmax + 1), 16);
+    p.sid = take(sizeof(uint16_t) * (size_t)nmax, 16);
+    p.scan = take(sizeof(int32_t) * kMaxWaves, 16);
+    p.misc = take(sizeof(int32_t) * 4, 16);
+    p.total = align_up(off, 128);
+    return p;
+}
+
+template <typename Real>
+__device__ inline Lds<Real> carve(char* base, int nmax, int cmax) {
+    LdsPlan p = plan_lds(nmax, cmax, sizeof(Real));
+    Lds<Real> L;
+    L.spos = (typename Vec4<Real>::T*)(base + p.spos);
+    L.ax = (Real*)(base + p.ax);
+    L.ay = (Real*)(base + p.ay);
+    L.az = (Real*)(base + p.az);
+    L.red = (double*)(base + p.red);
+    L.shx = (Real*)(base + p.shx);
+    L.shyz = (Real*)(base + p.shyz);
+    L.rowinfo = (int32_t*)(base + p.rowinfo);
+    L.cnt = (int32_t*)(base + p.cnt);
+    L.start = (int32_t*)(base + p.start);
+    L.sid = (uint16_t*)(base + p.sid);
+    L.scan = (int32_t*)(base + p.scan);
+    L.misc = (int32_t*)(base + p.misc);
+    return L;
+}
+
+// ---------------------------------------------------------------------------------------
+// block-level collectives
+// ---------------------------------------------------------------------------------------
+
+// Sum K doubles over the workgroup; every thread receives the totals. Fixed order:
+// butterfly inside each wave, then wave 0..W-1 in sequence.
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        v[k] = x;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w * K + threadIdx.x];
+        red[kMaxWaves * kRedSlots + threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = red[kMaxWaves * kRedSlots + k];
+}
+
+// Exclusive scan of cnt[0..C) into start[0..C) (and into cnt as placement cursors).
+__device__ __forceinline__ void scan_cells(int32_t* cnt, int32_t* start, int C, int32_t* ws) {
+    const int T = blockDim.x, t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6, nw = T >> 6;
+    const int chunk = (C + T - 1) / T;
+    const int b = t * chunk;
+    const int e = min(C, b + chunk);
+    int local = 0;
+    for (int c = b; c < e; ++c) local += cnt[c];
+    int x = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) ws[wave] = x;
+    __syncthreads();
+    if (t == 0) {
+        int acc = 0;
+        for (int w = 0; w < nw; ++w) {
+            int v = ws[w];
+            ws[w] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    int run = ws[wave] + x - local;
+    for (int c = b; c < e; ++c) {
+        int v = cnt[c];
+        start[c] = run;
+        cnt[c] = run;
+        run += v;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// cell list (steps 1-4) and pair forces (step 5)
+// ---------------------------------------------------------------------------------------
+
+// Shift tables of the stencil. Row 1: columns cx-1..cx+1 of a row that does not cross the y
+// boundary. Rows 0/2: the row below/above the box, an image displaced by -dxle/+dxle in x;
+// its columns are every cell whose image overlaps [cx w - rc, (cx+1) w + rc] (plus a margin
+// that covers the FP32 cutoff test), which is cx + off .. cx + off + nq - 1, independent of cx.
+// Column q of a row has x shift S = -(off + q) w - sh, with sh the row's image displacement
+// reduced to [-Lx/2, Lx/2]; the separation is then d_x = (u_i - u_j) + S.
+template <typename Real>
+__device__ void build_shift_tables(const SysDev& S, double dxle, const Lds<Real>& L) {
+    const double wx = S.w[0];
+    const double margin = 1e-6 * S.rc;
+    for (int row = 0; row < 3; ++row) {
+        int off, nq;
+        double sh;
+        if (row == 1) {
+            off = -1;
+            nq = 3;
+            sh = 0.0;
+        } else {
+            double img = row == 0 ? -1.0 : 1.0;
+            sh = img * dxle;
+            sh -= S.box[0] * rint(sh / S.box[0]);
+            off = (int)floor((-S.rc - margin - sh) / wx);
+            int hi = (int)floor((wx + S.rc + margin - sh) / wx);
+            nq = hi - off + 1;
+            if (nq > 5) nq = 5;
+            if (nq > S.nc[0]) nq = S.nc[0];
+        }
+        int offm = ((off % S.nc[0]) + S.nc[0]) % S.nc[0];
+        L.rowinfo[2 * row] = offm;
+        L.rowinfo[2 * row + 1] = nq;
+        for (int q = 0; q < 5; ++q) L.shx[row * 5 + q] = (Real)(-(double)(off + q) * wx - sh);
+    }
+    for (int d = 0; d < 3; ++d) {
+        L.shyz[d] = (Real)(-(double)(d - 1) * S.w[1]);
+        L.shyz[3 + d] = (Real)(-(double)(d - 1) * S.w[2]);
+    }
+}
+
+// Steps 1-4: cell of every atom, relative coordinates, counting sort into canonical order,
+// sorted positions. Leaves cnt[] zeroed. cell_out (may be null) receives each owned atom's cell.
+template <typename Real, int APT>
+__device__ void build_cells(const SysDev& S, double dxle, const double (&x)[APT],
+                            const double (&y)[APT], const double (&z)[APT], const Lds<Real>& L,
+                            int (&cell)[APT]) {
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    const int nc0 = S.nc[0], nc1 = S.nc[1], nc2 = S.nc[2];
+    const int C = nc0 * nc1 * nc2;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        cell[j] = -1;
+        if (a < n) {
+            const int cx = cell_coord(x[j], S.inv_w[0], nc0);
+            const int cy = cell_coord(y[j], S.inv_w[1], nc1);
+            const int cz = cell_coord(z[j], S.inv_w[2], nc2);
+            cell[j] = cx + nc0 * (cy + nc1 * cz);
+            L.ax[a] = (Real)(x[j] - (double)cx * S.w[0]);
+            L.ay[a] = (Real)(y[j] - (double)cy * S.w[1]);
+            L.az[a] = (Real)(z[j] - (double)cz * S.w[2]);
+            atomicAdd(&L.cnt[cell[j]], 1);
+        }
+    }
+    if (t == 0) build_shift_tables<Real>(S, dxle, L);
+    __syncthreads();
+    scan_cells(L.cnt, L.start, C, L.scan);
+    if (t == 0) L.start[C] = n;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        if (cell[j] >= 0) {
+            const int idx = atomicAdd(&L.cnt[cell[j]], 1);
+            L.sid[idx] = (uint16_t)(t + j * T);
+        }
+    }
+    __syncthreads();
+    for (int c = t; c < C; c += T) {
+        const int b = L.start[c], e = L.start[c + 1];
+        for (int i = b + 1; i < e; ++i) {  // insertion sort: cells hold a handful of atoms
+            const uint16_t v = L.sid[i];
+            int k = i - 1;
+            while (k >= b && L.sid[k] > v) {
+                L.sid[k + 1] = L.sid[k];
+                --k;
+            }
+            L.sid[k + 1] = v;
+        }
+        const int cx = c % nc0, cy = (c / nc0) % nc1, cz = c / (nc0 * nc1);
+        const int pk = cx | (cy << 10) | (cz << 20);
+        for (int i = b; i < e; ++i) {
+            const int a = L.sid[i];
+            typename Vec4<Real>::T v;
+            v.x = L.ax[a];
+            v.y = L.ay[a];
+            v.z = L.az[a];
+            v.w = pack_cell(Real(0), pk);
+            L.spos[i] = v;
+        }
+        L.cnt[c] = 0;
+    }
+    __syncthreads();
+}
+
+// Step 5: forces of every sorted slot, written per atom id into ax/ay/az; returns this
+// thread's share of W_xy = sum_{i<j} x_ij F_y,ij (and U when want_u).
+template <typename Real, bool WantU>
+__device__ void pair_forces(const SysDev& S, const Lds<Real>& L, double& wpart, double& upart) {
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    const int nc0 = S.nc[0], nc1 = S.nc[1], nc2 = S.nc[2];
+    const Real rc2 = (Real)S.rc2;
+    const Real ca = (Real)S.c_attr;
+    const Real ush = (Real)S.u_shift;
+    double wacc = 0.0, uacc = 0.0;
+    for (int s = t; s < n; s += T) {
+        const typename Vec4<Real>::T ui = L.spos[s];
+        const int pk = unpack_cell(ui.w);
+        const int cx = pk & 1023, cy = (pk >> 10) & 1023, cz = pk >> 20;
+        Real fx = 0, fy = 0, fz = 0, wxy = 0, ue = 0;
+#pragma unroll 1
+        for (int dz = 0; dz < 3; ++dz) {
+            int zz = cz + dz - 1;
+            zz = zz < 0 ? zz + nc2 : (zz >= nc2 ? zz - nc2 : zz);
+            const Real sz = L.shyz[3 + dz];
+#pragma unroll 1
+            for (int dy = 0; dy < 3; ++dy) {
+                int yy = cy + dy - 1;
+                int row = 1;
+                if (yy < 0) {
+                    yy += nc1;
+                    row = 0;
+                } else if (yy >= nc1) {
+                    yy -= nc1;
+                    row = 2;
+                }
+                const Real sy = L.shyz[dy];
+                const int nq = L.rowinfo[2 * row + 1];
+                int xx = cx + L.rowinfo[2 * row];
+                if (xx >= nc0) xx -= nc0;
+                const int base = nc0 * (yy + nc1 * zz);
+#pragma unroll 1
+                for (int q = 0; q < nq; ++q) {
+                    const Real sx = L.shx[row * 5 + q];
+                    const int c = base + xx;
+                    const int e = L.start[c + 1];
+                    for (int tt = L.start[c]; tt < e; ++tt) {
+                        if (tt == s) continue;
+                        const typename Vec4<Real>::T uj = L.spos[tt];
+                        const Real dx = (ui.x - uj.x) + sx;
+                        const Real dyv = (ui.y - uj.y) + sy;
+                        const Real dzv = (ui.z - uj.z) + sz;
+                        const Real r2 = dx * dx + dyv * dyv + dzv * dzv;
+                        if (r2 < rc2) {
+                            const Real inv = recip(r2);
+                            const Real s3 = inv * inv * inv;
+                            const Real fs = s3 * (Real(48) * s3 - Real(24) * ca) * inv;
+                            fx += fs * dx;
+                            fy += fs * dyv;
+                            fz += fs * dzv;
+                            wxy += dx * (fs * dyv);
+                            if (WantU) ue += Real(4) * s3 * (s3 - ca) + ush;
+                        }
+                    }
+                    ++xx;
+                    if (xx >= nc0) xx -= nc0;
+                }
+            }
+        }
+        const int i = L.sid[s];
+        L.ax[i] = fx;
+        L.ay[i] = fy;
+        L.az[i] = fz;
+        wacc += (double)wxy;
+        if (WantU) uacc += (double)ue;
+    }
+    wpart = 0.5 * wacc;  // every unordered pair was visited from both sides
+    upart = 0.5 * uacc;
+    __syncthreads();
+}
+
+// Full force evaluation for the owned atoms.
+template <typename Real, int APT, bool WantU>
+__device__ void compute_forces(const SysDev& S, double dxle, const double (&x)[APT],
+                               const double (&y)[APT], const double (&z)[APT], double (&fx)[APT],
+                               double (&fy)[APT], double (&fz)[APT], double& wpart, double& upart,
+                               const Lds<Real>& L) {
+    int cell[APT];
+    build_cells<Real, APT>(S, dxle, x, y, z, L, cell);
+    pair_forces<Real, WantU>(S, L, wpart, upart);
+    const int T = blockDim.x, t = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        if (a < S.n) {
+            fx[j] = (double)L.ax[a];
+            fy[j] = (double)L.ay[a];
+            fz[j] = (double)L.az[a];
+        } else {
+            fx[j] = fy[j] = fz[j] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// isokinetic integrator coefficients
+// ---------------------------------------------------------------------------------------
+
+// Exact flow over tau of dp/dt = F - (F.p/p.p) p with F fixed: p -> (p + F s)/sdot,
+// s = (a/b)(cosh(q tau) - 1) + sinh(q tau)/q, sdot = (a/q) sinh(q tau) + cosh(q tau),
+// a = F.p/p.p, b = F.F/p.p, q = sqrt(b) (Zhang, J. Chem. Phys. 106, 6102 (1997)).
+__device__ __forceinline__ void iso_kick_coeffs(double a, double b, double tau, double& s,
+                                                double& sdot) {
+    double ch1_b, sh_q;
+    if (b > 0.0) {
+        const double q = sqrt(b);
+        const double hs = sinh(0.5 * q * tau) / q;
+        ch1_b = 2.0 * hs * hs;
+        sh_q = sinh(q * tau) / q;
+    } else {
+        ch1_b = 0.5 * tau * tau;
+        sh_q = tau;
+    }
+    s = a * ch1_b + sh_q;
+    sdot = a * sh_q + (1.0 + b * ch1_b);
+}
+
+// ---------------------------------------------------------------------------------------
+// daughter: isokinetic SLLOD under Lees-Edwards boundaries
+// ---------------------------------------------------------------------------------------
+//
+// Step (h = dt, tau = h/2, tg = tau gamma_dot), the symmetric splitting
+//   S(tau) K(tau) D(h) [forces] K(tau) S(tau)
+// with S the shear flow px -= tg py and K the force kick, both carrying the Gaussian
+// multiplier (so both keep sum p.p), and D the streaming flow x += h px + h gamma_dot (y +
+// tau py), y += h py, z += h pz. S under the constraint is the plain shear scaled back to the
+// old p.p; K is the closed-form kick above. The scalars each part needs are moments of (p, F):
+// the moments reduced once after the force pass give, in closed form, those of the second
+// half and of the next step's first half, so the step needs a single block reduction.
+template <typename Real, int APT>
+__device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& L) {
+    const int T = blockDim.x, t = threadIdx.x;
+    const SysDev S = dsc->sys;
+    const int n = S.n;
+    double* st = dsc->state;
+    const double gd = dsc->gamma_dot;
+    int64_t k = dsc->k;
+    int done = dsc->done;
+    const int n_steps = dsc->n_steps;
+    double k0 = dsc->k0;
+    int health = dsc->health;
+    int todo = min(steps_cap, n_steps - done);
+    if (health != 0) todo = 0;
+    if (todo <= 0 && done > 0) return;
+
+    double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT], fx[APT], fy[APT], fz[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        const bool v = a < n;
+        x[j] = v ? st[a] : 0.0;
+        y[j] = v ? st[n + a] : 0.0;
+        z[j] = v ? st[2 * n + a] : 0.0;
+        px[j] = v ? st[3 * n + a] : 0.0;
+        py[j] = v ? st[4 * n + a] : 0.0;
+        pz[j] = v ? st[5 * n + a] : 0.0;
+    }
+    double dxle = le_offset(S, gd, k);
+    double wpart, upart;
+    compute_forces<Real, APT, false>(S, dxle, x, y, z, fx, fy, fz, wpart, upart, L);
+
+    // prologue moments: pp, pxpy, pypy, fp, fxpy, ff, W
+    double m0[7] = {0, 0, 0, 0, 0, 0, wpart};
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        m0[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+        m0[1] += px[j] * py[j];
+        m0[2] += py[j] * py[j];
+        m0[3] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+        m0[4] += fx[j] * py[j];
+        m0[5] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+    }
+    block_sum<7>(m0, L.red);
+    if (done == 0) {
+        if (k0 <= 0.0) k0 = 0.5 * m0[0];
+        if (t == 0) dsc->series[0] = m0[1] + m0[6];
+    }
+    double pp = m0[0], pxpy = m0[1], pypy = m0[2], fp = m0[3], fxpy = m0[4], ff = m0[5];
+    const double h = S.dt, tau = 0.5 * S.dt, tg = tau * gd;
+
+    for (int step = 0; step < todo; ++step) {
+        // ---- first half: S(tau) then K(tau)
+        const double ppt = pp - 2.0 * tg * pxpy + tg * tg * pypy;
+        const double g1 = sqrt(pp / ppt);
+        const double fp1 = g1 * (fp - tg * fxpy);
+        double s1, sd1;
+        iso_kick_coeffs(fp1 / pp, ff / pp, tau, s1, sd1);
+        const double isd1 = 1.0 / sd1;
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double qx = g1 * (px[j] - tg * py[j]);
+            const double qy = g1 * py[j];
+            const double qz = g1 * pz[j];
+            px[j] = (qx + fx[j] * s1) * isd1;
+            py[j] = (qy + fy[j] * s1) * isd1;
+            pz[j] = (qz + fz[j] * s1) * isd1;
+        }
+        // ---- streaming D(h), new strain, sliding-brick wrap
+        k += 1;
+        dxle = le_offset(S, gd, k);
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            x[j] += h * px[j] + h * gd * (y[j] + tau * py[j]);
+            y[j] += h * py[j];
+            z[j] += h * pz[j];
+            wrap_le(S, dxle, x[j], y[j], z[j]);
+        }
+        compute_forces<Real, APT, false>(S, dxle, x, y, z, fx, fy, fz, wpart, upart, L);
+        // ---- moments of (p'', F): pp, pxpy, pypy, fp, fxpy, fypx, fxfy, fypy, fyfy, ff, W, pos
+        double m[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, wpart, 0};
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            m[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+            m[1] += px[j] * py[j];
+            m[2] += py[j] * py[j];
+            m[3] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+            m[4] += fx[j] * py[j];
+            m[5] += fy[j] * px[j];
+            m[6] += fx[j] * fy[j];
+            m[7] += fy[j] * py[j];
+            m[8] += fy[j] * fy[j];
+            m[9] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+            m[11] += x[j] + y[j] + z[j];
+        }
+        block_sum<12>(m, L.red);
+        // ---- second half: K(tau) then S(tau), then the exact K0 rescale
+        double s2, sd2;
+        iso_kick_coeffs(m[3] / m[0], m[9] / m[0], tau, s2, sd2);
+        const double isd2 = 1.0 / sd2;
+        const double pp3 = (m[0] + 2.0 * s2 * m[3] + s2 * s2 * m[9]) * isd2 * isd2;
+        const double pxpy3 = (m[1] + s2 * (m[4] + m[5]) + s2 * s2 * m[6]) * isd2 * isd2;
+        const double pypy3 = (m[2] + 2.0 * s2 * m[7] + s2 * s2 * m[8]) * isd2 * isd2;
+        const double fp3 = (m[3] + s2 * m[9]) * isd2;
+        const double fxpy3 = (m[4] + s2 * m[6]) * isd2;
+        const double ppt2 = pp3 - 2.0 * tg * pxpy3 + tg * tg * pypy3;
+        const double pxpyt = pxpy3 - tg * pypy3;
+        const double c = sqrt(2.0 * k0 / ppt2);
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double qx = (px[j] + fx[j] * s2) * isd2;
+            const double qy = (py[j] + fy[j] * s2) * isd2;
+            const double qz = (pz[j] + fz[j] * s2) * isd2;
+            px[j] = c * (qx - tg * qy);
+            py[j] = c * qy;
+            pz[j] = c * qz;
+        }
+        pp = c * c * ppt2;
+        pxpy = c * c * pxpyt;
+        pypy = c * c * pypy3;
+        fp = c * (fp3 - tg * fxpy3);
+        fxpy = c * fxpy3;
+        ff = m[9];
+        const double vpxy = pxpy + m[10];
+        done += 1;
+        if (t == 0) dsc->series[done] = vpxy;
+        if (!isfinite(vpxy) || !isfinite(c) || !isfinite(m[11])) {
+            health |= kHealthNonFinite;
+            break;
+        }
+        if (fabs(pp3 / m[0] - 1.0) > 1e-10) {
+            health |= kHealthDrift;
+            break;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        if (a < n) {
+            st[a] = x[j];
+            st[n + a] = y[j];
+            st[2 * n + a] = z[j];
+            st[3 * n + a] = px[j];
+            st[4 * n + a] = py[j];
+            st[5 * n + a] = pz[j];
+        }
+    }
+    if (t == 0) {
+        dsc->k = k;
+        dsc->done = done;
+        dsc->k0 = k0;
+        dsc->health = health;
+    }
+    __syncthreads();
+}
+
+template <typename Real, int APT>
+__global__ __launch_bounds__(kMaxThreads) void k_daughters(BatchLaunch b) {
+    extern __shared__ __align__(32) char smem[];
+    const Lds<Real> L = carve<Real>(smem, b.nmax, b.cmax);
+    for (int c = threadIdx.x; c < b.cmax; c += blockDim.x) L.cnt[c] = 0;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) L.misc[0] = atomicAdd(b.queue, 1);
+        __syncthreads();
+        // the job index is the same in every lane: make that visible so the descriptor is
+        // read with scalar loads and its fields stay in scalar registers
+        const int j = __builtin_amdgcn_readfirstlane(L.misc[0]);
+        if (j >= b.n_jobs) break;
+        run_daughter<Real, APT>(&b.descs[b.order[j]], b.max_steps, L);
+    }
+}
+
+__global__ void k_zero_int(int32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// mother: Nose-Hoover equilibrium dynamics (gamma_dot = 0, plain periodic box)
+// ---------------------------------------------------------------------------------------
+// zeta += tau (p.p - nf T)/Q; p = exp(-zeta tau) p + tau F; r += h p; F = F(r); p += tau F;
+// p *= exp(-zeta tau); zeta += tau (p.p - nf T)/Q. The p.p of the last update is c^2 times
+// the reduced p.p before the scaling, so one reduction per step suffices.
+template <typename Real, int APT>
+__global__ __launch_bounds__(kMaxThreads) void k_mother(MotherLaunch m) {
+    extern __shared__ __align__(32) char smem[];
+    const SysDev S = m.sys;
+    const Lds<Real> L = carve<Real>(smem, S.n, S.nc[0] * S.nc[1] * S.nc[2]);
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    for (int c = t; c < S.nc[0] * S.nc[1] * S.nc[2]; c += T) L.cnt[c] = 0;
+    double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT], fx[APT], fy[APT], fz[APT];
+    double* st = m.state;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        const bool v = a < n;
+        x[j] = v ? st[a] : 0.0;
+        y[j] = v ? st[n + a] : 0.0;
+        z[j] = v ? st[2 * n + a] : 0.0;
+        px[j] = v ? st[3 * n + a] : 0.0;
+        py[j] = v ? st[4 * n + a] : 0.0;
+        pz[j] = v ? st[5 * n + a] : 0.0;
+    }
+    __syncthreads();
+    double wpart, upart;
+    compute_forces<Real, APT, false>(S, 0.0, x, y, z, fx, fy, fz, wpart, upart, L);
+    double m0[1] = {0.0};
+#pragma unroll
+    for (int j = 0; j < APT; ++j) m0[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+    block_sum<1>(m0, L.red);
+    double pp = m0[0];
+    double zeta = *m.zeta;
+    const double h = S.dt, tau = 0.5 * S.dt, gT = m.nf * m.temperature, iq = 1.0 / m.q;
+    const int64_t chunks = m.n_chunks > 0 ? m.n_chunks : 1;
+    int64_t rec = 0;
+    for (int64_t ch = 0; ch < chunks; ++ch) {
+        for (int64_t s = 0; s < m.steps_per_chunk; ++s) {
+            zeta += tau * (pp - gT) * iq;
+            const double c1 = exp(-zeta * tau);
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                px[j] = c1 * px[j] + tau * fx[j];
+                py[j] = c1 * py[j] + tau * fy[j];
+                pz[j] = c1 * pz[j] + tau * fz[j];
+                x[j] += h * px[j];
+                y[j] += h * py[j];
+                z[j] += h * pz[j];
+                wrap_le(S, 0.0, x[j], y[j], z[j]);
+            }
+            compute_forces<Real, APT, false>(S, 0.0, x, y, z, fx, fy, fz, wpart, upart, L);
+            double mm[3] = {0.0, 0.0, wpart};
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                px[j] += tau * fx[j];
+                py[j] += tau * fy[j];
+                pz[j] += tau * fz[j];
+                mm[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                mm[1] += px[j] * py[j];
+            }
+            block_sum<3>(mm, L.red);
+            const double c2 = exp(-zeta * tau);
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                px[j] *= c2;
+                py[j] *= c2;
+                pz[j] *= c2;
+            }
+            pp = c2 * c2 * mm[0];
+            zeta += tau * (pp - gT) * iq;
+            if (m.series != nullptr && t == 0) m.series[rec] = c2 * c2 * mm[1] + mm[2];
+            ++rec;
+        }
+        if (m.snapshots != nullptr) {
+            double* dst = m.snapshots + (size_t)ch * 6 * (size_t)n;
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                const int a = t + j * T;
+                if (a < n) {
+                    dst[a] = x[j];
+                    dst[n + a] = y[j];
+                    dst[2 * n + a] = z[j];
+                    dst[3 * n + a] = px[j];
+                    dst[4 * n + a] = py[j];
+                    dst[5 * n + a] = pz[j];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        if (a < n) {
+            st[a] = x[j];
+            st[n + a] = y[j];
+            st[2 * n + a] = z[j];
+            st[3 * n + a] = px[j];
+            st[4 * n + a] = py[j];
+            st[5 * n + a] = pz[j];
+        }
+    }
+    if (t == 0) *m.zeta = zeta;
+}
+
+// ---------------------------------------------------------------------------------------
+// spawn: the mappings of the start states
+// ---------------------------------------------------------------------------------------
+// m = 0 identity; 1 p -> -p; 2 (x, px) -> (-x, -px); 3 (x, py, pz) -> (-x, -py, -pz); the
+// reflected x is brought back into [0, Lx) as Lx - x (0 stays 0).
+__global__ void k_spawn(const double* states, int32_t n, const int32_t* state_of,
+                        const int32_t* map_of, double* const* dst, double lx) {
+    const int d = blockIdx.x;
+    const double* src = states + (size_t)state_of[d] * 6 * (size_t)n;
+    double* out = dst[d];
+    const int m = map_of[d];
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        double x = src[a], y = src[n + a], z = src[2 * n + a];
+        double px = src[3 * n + a], py = src[4 * n + a], pz = src[5 * n + a];
+        if (m == 1) {
+            px = -px;
+            py = -py;
+            pz = -pz;
+        } else if (m == 2 || m == 3) {
+            x = (x == 0.0) ? 0.0 : lx - x;
+            if (m == 2) {
+                px = -px;
+            } else {
+                py = -py;
+                pz = -pz;
+            }
+        }
+        out[a] = x;
+        out[n + a] = y;
+        out[2 * n + a] = z;
+        out[3 * n + a] = px;
+        out[4 * n + a] = py;
+        out[5 * n + a] = pz;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// accumulate: per start-state group, the direct average and the integral of P(0)P(s)
+// ---------------------------------------------------------------------------------------
+
+__device__ __forceinline__ void neumaier_add(double& sum, double& comp, double v) {
+    const double tsum = sum + v;
+    if (fabs(sum) >= fabs(v))
+        comp += (sum - tsum) + v;
+    else
+        comp += (v - tsum) + sum;
+    sum = tsum;
+}
+
+constexpr int kMaxMaps = 4;
+
+__global__ void k_accumulate(AccumLaunch a) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.n_groups) return;
+    const int b = a.first_of[g], e = a.first_of[g + 1];
+    const int nm = min(e - b, kMaxMaps);
+    int health = 0;
+    double p0[kMaxMaps], sum[kMaxMaps], comp[kMaxMaps], prev[kMaxMaps];
+    const double* ser[kMaxMaps];
+    double inv_v = 1.0, dt = 0.0;
+    for (int m = 0; m < nm; ++m) {
+        const DaughterDesc& d = a.descs[b + m];
+        health |= d.health;
+        ser[m] = d.series;
+        inv_v = 1.0 / d.sys.volume;
+        dt = d.sys.dt;
+        p0[m] = d.series[0] * inv_v;
+        prev[m] = p0[m];
+        sum[m] = 0.0;
+        comp[m] = 0.0;
+    }
+    a.health_out[g] = health;
+    a.gamma_out[g] = a.descs[b].gamma_dot;
+    const double inm = 1.0 / (double)nm;
+    double* dout = a.d_out + (size_t)g * a.n_t;
+    double* iout = a.i_out + (size_t)g * a.n_t;
+    {
+        double dsum = 0.0;
+        for (int m = 0; m < nm; ++m) dsum += p0[m];
+        dout[0] = dsum * inm;
+        iout[0] = 0.0;
+    }
+    for (int k = 1; k < a.n_t; ++k) {
+        double dsum = 0.0, isum = 0.0;
+        for (int m = 0; m < nm; ++m) {
+            const double cur = ser[m][k] * inv_v;
+            neumaier_add(sum[m], comp[m], 0.5 * dt * (p0[m] * prev[m] + p0[m] * cur));
+            prev[m] = cur;
+            dsum += cur;
+            isum += sum[m] + comp[m];
+        }
+        dout[k] = dsum * inm;
+        iout[k] = isum * inm;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// response: mean and block standard error over the selected groups, per time point
+// ---------------------------------------------------------------------------------------
+// G_n(t) = D_n(0) - coef_n I_n(t), coef_n = V gamma_n / T, is the start state's TTCF estimate
+// (Eq. TTCF with Omega(0) = -(V/T) gamma_n P_xy(0)); D_n(t) its direct average. Two passes (mean, then the
+// squared deviations), each a compensated sum in a fixed row order.
+__global__ void k_response(ResponseLaunch r) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.n_t) return;
+    double gs = 0, gc = 0, ds = 0, dc = 0;
+    int used = 0;
+    for (int i = 0; i < r.n_rows; ++i) {
+        const int row = r.rows[i];
+        if (r.health[row] != 0) continue;
+        const double* dser = r.d_all + (size_t)row * r.n_t_stride;
+        const double* iser = r.i_all + (size_t)row * r.n_t_stride;
+        const double gam = r.gamma[row];
+        double g = dser[0] - r.coef[row] * iser[k];
+        double dv = dser[k];
+        if (r.normalise) {
+            g /= gam;
+            dv /= gam;
+        }
+        neumaier_add(gs, gc, g);
+        neumaier_add(ds, dc, dv);
+        ++used;
+    }
+    const double gm = (gs + gc) / (double)used;
+    const double dm = (ds + dc) / (double)used;
+    double gv = 0, gvc = 0, dvv = 0, dvc = 0;
+    for (int i = 0; i < r.n_rows; ++i) {
+        const int row = r.rows[i];
+        if (r.health[row] != 0) continue;
+        const double* dser = r.d_all + (size_t)row * r.n_t_stride;
+        const double* iser = r.i_all + (size_t)row * r.n_t_stride;
+        const double gam = r.gamma[row];
+        double g = dser[0] - r.coef[row] * iser[k];
+        double dv = dser[k];
+        if (r.normalise) {
+            g /= gam;
+            dv /= gam;
+        }
+        neumaier_add(gv, gvc, (g - gm) * (g - gm));
+        neumaier_add(dvv, dvc, (dv - dm) * (dv - dm));
+    }
+    const double denom = used > 1 ? (double)(used - 1) * (double)used : 1.0;
+    r.out[k] = gm;
+    r.out[r.n_t + k] = used > 1 ? sqrt((gv + gvc) / denom) : 0.0;
+    r.out[2 * r.n_t + k] = dm;
+    r.out[3 * r.n_t + k] = used > 1 ? sqrt((dvv + dvc) / denom) : 0.0;
+    if (k == 0) *r.used = used;
+}
+
+// ---------------------------------------------------------------------------------------
+// inspection kernels (single workgroup, positions given)
+// ---------------------------------------------------------------------------------------
+
+template <typename Real, int APT>
+__global__ __launch_bounds__(kMaxThreads) void k_debug_cells(SysDev S, const double* r,
+                                                             int32_t* cell_of, int32_t* order,
+                                                             int32_t* start) {
+    extern __shared__ __align__(32) char smem[];
+    const int C = S.nc[0] * S.nc[1] * S.nc[2];
+    const Lds<Real> L = carve<Real>(smem, S.n, C);
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    for (int c = t; c < C; c += T) L.cnt[c] = 0;
+    double x[APT], y[APT], z[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        x[j] = a < n ? r[a] : 0.0;
+        y[j] = a < n ? r[n + a] : 0.0;
+        z[j] = a < n ? r[2 * n + a] : 0.0;
+    }
+    __syncthreads();
+    int cell[APT];
+    build_cells<Real, APT>(S, 0.0, x, y, z, L, cell);
+#pragma unroll
+    for (int j = 0; j < APT; ++j)
+        if (cell[j] >= 0) cell_of[t + j * T] = cell[j];
+    for (int i = t; i < n; i += T) order[i] = L.sid[i];
+    for (int c = t; c <= C; c += T) start[c] = L.start[c];
+}
+
+template <typename Real, int APT>
+__global__ __launch_bounds__(kMaxThreads) void k_debug_forces(SysDev S, double dxle,
+                                                              const double* r, double* f,
+                                                              double* out) {
+    extern __shared__ __align__(32) char smem[];
+    const int C = S.nc[0] * S.nc[1] * S.nc[2];
+    const Lds<Real> L = carve<Real>(smem, S.n, C);
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    for (int c = t; c < C; c += T) L.cnt[c] = 0;
+    double x[APT], y[APT], z[APT], fx[APT], fy[APT], fz[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        x[j] = a < n ? r[a] : 0.0;
+        y[j] = a < n ? r[n + a] : 0.0;
+        z[j] = a < n ? r[2 * n + a] : 0.0;
+    }
+    __syncthreads();
+    double wpart, upart;
+    compute_forces<Real, APT, true>(S, dxle, x, y, z, fx, fy, fz, wpart, upart, L);
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        if (a < n) {
+            f[a] = fx[j];
+            f[n + a] = fy[j];
+            f[2 * n + a] = fz[j];
+        }
+    }
+    double m[2] = {upart, wpart};
+    block_sum<2>(m, L.red);
+    if (t == 0) {
+        out[0] = m[0];
+        out[1] = m[1];
+    }
+}
+
+// Minimum-image separation exactly as a plain FP64 evaluation gives it: y image first (its
+// crossing shifts x by the offset), then periodic x and z. No contraction into FMAs, so the
+// pair set below is bit-identical to any IEEE evaluation of the same expressions.
+__device__ void min_image_exact(const SysDev& S, double dxle, double xi, double yi, double zi,
+                                double xj, double yj, double zj, double& dx, double& dy,
+                                double& dz) {
+#pragma clang fp contract(off)
+    dy = yi - yj;
+    const double ny = rint(dy / S.box[1]);
+    dy = dy - ny * S.box[1];
+    dx = xi - xj;
+    dx = dx - ny * dxle;
+    dx = dx - S.box[0] * rint(dx / S.box[0]);
+    dz = zi - zj;
+    dz = dz - S.box[2] * rint(dz / S.box[2]);
+}
+
+__device__ double dist2_exact(double dx, double dy, double dz) {
+#pragma clang fp contract(off)
+    return dx * dx + dy * dy + dz * dz;
+}
+
+// Pairs i<j closer than rlist, found through the same cell list and stencil as the forces
+// (FP32 shift tables are not used: the test is done on FP64 absolute positions).
+template <int APT>
+__global__ __launch_bounds__(kMaxThreads) void k_debug_pairs(SysDev S, double dxle,
+                                                             const double* r, double rlist,
+                                                             int64_t cap, int32_t* pi,
+                                                             int32_t* pj,
+                                                             unsigned long long* count) {
+    extern __shared__ __align__(32) char smem[];
+    const int C = S.nc[0] * S.nc[1] * S.nc[2];
+    const Lds<double> L = carve<double>(smem, S.n, C);
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    const int nc0 = S.nc[0], nc1 = S.nc[1], nc2 = S.nc[2];
+    for (int c = t; c < C; c += T) L.cnt[c] = 0;
+    double x[APT], y[APT], z[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        x[j] = a < n ? r[a] : 0.0;
+        y[j] = a < n ? r[n + a] : 0.0;
+        z[j] = a < n ? r[2 * n + a] : 0.0;
+    }
+    __syncthreads();
+    int cell[APT];
+    build_cells<double, APT>(S, dxle, x, y, z, L, cell);
+    const double rl2 = rlist * rlist;
+    for (int s = t; s < n; s += T) {
+        const int i = L.sid[s];
+        const int pk = unpack_cell(L.spos[s].w);
+        const int cx = pk & 1023, cy = (pk >> 10) & 1023, cz = pk >> 20;
+        for (int dz = 0; dz < 3; ++dz) {
+            int zz = cz + dz - 1;
+            zz = zz < 0 ? zz + nc2 : (zz >= nc2 ? zz - nc2 : zz);
+            for (int dy = 0; dy < 3; ++dy) {
+                int yy = cy + dy - 1;
+                int row = 1;
+                if (yy < 0) {
+                    yy += nc1;
+                    row = 0;
+                } else if (yy >= nc1) {
+                    yy -= nc1;
+                    row = 2;
+                }
+                const int nq = L.rowinfo[2 * row + 1];
+                int xx = cx + L.rowinfo[2 * row];
+                if (xx >= nc0) xx -= nc0;
+                for (int q = 0; q < nq; ++q) {
+                    const int c = xx + nc0 * (yy + nc1 * zz);
+                    for (int tt = L.start[c]; tt < L.start[c + 1]; ++tt) {
+                        const int j = L.sid[tt];
+                        if (j <= i) continue;
+                        double ddx, ddy, ddz;
+                        min_image_exact(S, dxle, r[i], r[n + i], r[2 * n + i], r[j], r[n + j],
+                                        r[2 * n + j], ddx, ddy, ddz);
+                        if (dist2_exact(ddx, ddy, ddz) < rl2) {
+                            const unsigned long long at = atomicAdd(count, 1ull);
+                            if ((int64_t)at < cap) {
+                                pi[at] = i;
+                                pj[at] = j;
+                            }
+                        }
+                    }
+                    ++xx;
+                    if (xx >= nc0) xx -= nc0;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------------------
+
+int pick_threads(int n, int requested) {
+    if (requested > 0) return requested;
+    int t = ((n + 63) / 64) * 64;
+    if (t > kMaxThreads) t = kMaxThreads;
+    if (t < 64) t = 64;
+    return t;
+}
+
+int pick_apt(int n, int threads) {
+    const int need = (n + threads - 1) / threads;
+    if (need <= 1) return 1;
+    if (need <= 2) return 2;
+    if (need <= 4) return 4;
+    return -1;
+}
+
+size_t lds_bytes_for(int nmax, int cmax, int threads, int precision) {
+    (void)threads;
+    return plan_lds(nmax, cmax, precision == 0 ? sizeof(double) : sizeof(float)).total;
+}
+
+template <typename Real, int APT>
+static hipError_t launch_daughters_t(const BatchLaunch& b, hipStream_t s) {
+    (void)hipFuncSetAttribute((const void*)k_daughters<Real, APT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)b.lds_bytes);
+    hipLaunchKernelGGL((k_daughters<Real, APT>), dim3(b.grid), dim3(b.threads), b.lds_bytes, s,
+                       b);
+    return hipGetLastError();
+}
+
+hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.queue, 1);
+    if (b.precision == 0) {
+        switch (b.apt) {
+            case 1: return launch_daughters_t<double, 1>(b, s);
+            case 2: return launch_daughters_t<double, 2>(b, s);
+            case 4: return launch_daughters_t<double, 4>(b, s);
+        }
+    } else {
+        switch (b.apt) {
+            case 1: return launch_daughters_t<float, 1>(b, s);
+            case 2: return launch_daughters_t<float, 2>(b, s);
+            case 4: return launch_daughters_t<float, 4>(b, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename Real, int APT>
+static hipError_t launch_mother_t(const MotherLaunch& m, hipStream_t s) {
+    (void)hipFuncSetAttribute((const void*)k_mother<Real, APT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)m.lds_bytes);
+    hipLaunchKernelGGL((k_mother<Real, APT>), dim3(1), dim3(m.threads), m.lds_bytes, s, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_mother(const MotherLaunch& m, hipStream_t s) {
+    if (m.precision == 0) {
+        switch (m.apt) {
+            case 1: return launch_mother_t<double, 1>(m, s);
+            case 2: return launch_mother_t<double, 2>(m, s);
+            case 4: return launch_mother_t<double, 4>(m, s);
+        }
+    } else {
+        switch (m.apt) {
+            case 1: return launch_mother_t<float, 1>(m, s);
+            case 2: return launch_mother_t<float, 2>(m, s);
+            case 4: return launch_mother_t<float, 4>(m, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s) {
+    if (a.n_groups <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_accumulate, dim3((a.n_groups + 63) / 64), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_response(const ResponseLaunch& r, hipStream_t s) {
+    hipLaunchKernelGGL(k_response, dim3((r.n_t + 63) / 64), dim3(64), 0, s, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_spawn(const double* states, int32_t n, int32_t n_states,
+                        const int32_t* state_of, const int32_t* map_of, double* const* dst,
+                        int32_t n_daughters, double lx, hipStream_t s) {
+    (void)n_states;
+    if (n_daughters <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spawn, dim3(n_daughters), dim3(256), 0, s, states, n, state_of, map_of,
+                       dst, lx);
+    return hipGetLastError();
+}
+
+template <typename Real, int APT>
+static hipError_t debug_cells_t(const SysDev& S, const double* r, int32_t* cell_of,
+                                int32_t* order, int32_t* start, int threads, hipStream_t s) {
+    const size_t lds = plan_lds(S.n, S.nc[0] * S.nc[1] * S.nc[2], sizeof(Real)).total;
+    (void)hipFuncSetAttribute((const void*)k_debug_cells<Real, APT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_debug_cells<Real, APT>), dim3(1), dim3(threads), lds, s, S, r, cell_of,
+                       order, start);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_cells(const SysDev& S, const double* r, int32_t* cell_of, int32_t* order,
+                              int32_t* start, hipStream_t s) {
+    const int threads = pick_threads(S.n, 0);
+    switch (pick_apt(S.n, threads)) {
+        case 1: return debug_cells_t<double, 1>(S, r, cell_of, order, start, threads, s);
+        case 2: return debug_cells_t<double, 2>(S, r, cell_of, order, start, threads, s);
+        case 4: return debug_cells_t<double, 4>(S, r, cell_of, order, start, threads, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename Real, int APT>
+static hipError_t debug_forces_t(const SysDev& S, double dxle, const double* r, double* f,
+                                 double* out, int threads, hipStream_t s) {
+    const size_t lds = plan_lds(S.n, S.nc[0] * S.nc[1] * S.nc[2], sizeof(Real)).total;
+    (void)hipFuncSetAttribute((const void*)k_debug_forces<Real, APT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_debug_forces<Real, APT>), dim3(1), dim3(threads), lds, s, S, dxle, r,
+                       f, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_forces(const SysDev& S, int precision, double dxle, const double* r,
+                               double* f, double* out, hipStream_t s) {
+    const int threads = pick_threads(S.n, 0);
+    const int apt = pick_apt(S.n, threads);
+    if (precision == 0) {
+        switch (apt) {
+            case 1: return debug_forces_t<double, 1>(S, dxle, r, f, out, threads, s);
+            case 2: return debug_forces_t<double, 2>(S, dxle, r, f, out, threads, s);
+            case 4: return debug_forces_t<double, 4>(S, dxle, r, f, out, threads, s);
+        }
+    } else {
+        switch (apt) {
+            case 1: return debug_forces_t<float, 1>(S, dxle, r, f, out, threads, s);
+            case 2: return debug_forces_t<float, 2>(S, dxle, r, f, out, threads, s);
+            case 4: return debug_forces_t<float, 4>(S, dxle, r, f, out, threads, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int APT>
+static hipError_t debug_pairs_t(const SysDev& S, double dxle, const double* r, double rlist,
+                                int64_t cap, int32_t* pi, int32_t* pj,
+                                unsigned long long* count, int threads, hipStream_t s) {
+    const size_t lds = plan_lds(S.n, S.nc[0] * S.nc[1] * S.nc[2], sizeof(double)).total;
+    (void)hipFuncSetAttribute((const void*)k_debug_pairs<APT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_debug_pairs<APT>), dim3(1), dim3(threads), lds, s, S, dxle, r, rlist,
+                       cap, pi, pj, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_pairs(const SysDev& S, double dxle, const double* r, double rlist,
+                              int64_t cap, int32_t* pi, int32_t* pj, unsigned long long* count,
+                              hipStream_t s) {
+    const int threads = pick_threads(S.n, 0);
+    switch (pick_apt(S.n, threads)) {
+        case 1: return debug_pairs_t<1>(S, dxle, r, rlist, cap, pi, pj, count, threads, s);
+        case 2: return debug_pairs_t<2>(S, dxle, r, rlist, cap, pi, pj, count, threads, s);
+        case 4: return debug_pairs_t<4>(S, dxle, r, rlist, cap, pi, pj, count, threads, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace ttcf

@@ -1,0 +1,351 @@
+"""Python binding of the gfx950 TTCF library (include/ttcf.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of libttcf.so. The
+library is loaded from this package directory; if it is missing, importing this module
+raises, because there is no other implementation to fall back to. PyTorch supplies the HIP
+stream and, when ``use_torch_allocator()`` is called, the device allocator.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libttcf.so")
+
+TTCF_OK, TTCF_EINVAL, TTCF_ENOMEM, TTCF_EDEVICE, TTCF_ESTATE, TTCF_EUNSTABLE = 0, -1, -2, -3, -4, -5
+TTCF_WCA, TTCF_LJ = 0, 1
+TTCF_PREC_FP64, TTCF_PREC_FP32_FORCES = 0, 1
+TTCF_OBS_PXY = 0
+
+
+class TTCFError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str = ""):
+        super().__init__(f"{where} failed with {code}: {detail}")
+        self.code = code
+
+
+class System(C.Structure):
+    """ttcf_system of include/ttcf.h."""
+    _fields_ = [("n_atoms", C.c_int32), ("potential", C.c_int32), ("box", C.c_double * 3),
+                ("temperature", C.c_double), ("dt", C.c_double), ("r_cut", C.c_double),
+                ("c_attr", C.c_double), ("u_shift", C.c_double), ("nh_tau", C.c_double),
+                ("precision", C.c_int32), ("block_threads", C.c_int32)]
+
+
+def make_system(n_atoms: int, box, temperature: float = 0.722, dt: float = 0.0025,
+                r_cut: float = 2.0 ** (1.0 / 6.0), c_attr: float = 1.0, u_shift: float | None = None,
+                nh_tau: float = 0.25, precision: int = TTCF_PREC_FP32_FORCES,
+                block_threads: int = 0, potential: int = TTCF_WCA) -> System:
+    if np.isscalar(box):
+        box = (float(box),) * 3
+    if u_shift is None:
+        s6 = 1.0 / r_cut ** 6
+        u_shift = -4.0 * (s6 * s6 - c_attr * s6)
+    s = System()
+    s.n_atoms = int(n_atoms)
+    s.potential = int(potential)
+    for a in range(3):
+        s.box[a] = float(box[a])
+    s.temperature = float(temperature)
+    s.dt = float(dt)
+    s.r_cut = float(r_cut)
+    s.c_attr = float(c_attr)
+    s.u_shift = float(u_shift)
+    s.nh_tau = float(nh_tau)
+    s.precision = int(precision)
+    s.block_threads = int(block_threads)
+    return s
+
+
+_lib = None
+_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p, C.c_void_p)
+_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+_keep = []
+
+
+def lib():
+    """The loaded libttcf.so (raises when it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no CPU implementation of this library)")
+    L = C.CDLL(LIB_PATH)
+    D, I, L64, V = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_void_p
+    S = C.POINTER(System)
+    P = C.POINTER(C.c_void_p)
+    sig = {
+        "ttcf_set_allocator": [_ALLOC, _FREE, V],
+        "ttcf_init_mother": [P, S, D, D, C.c_int64, C.c_double, C.c_int64, V, I],
+        "ttcf_spawn_daughters": [V, C.c_int32, C.c_int32, C.c_int64, C.c_uint32, D, C.c_int32,
+                                 C.c_int32, L64],
+        "ttcf_step": [V, C.c_int32],
+        "ttcf_accumulate": [V, L64],
+        "ttcf_response": [V, C.c_int32, C.c_double, C.c_int32, D, D, D, D, L64],
+        "ttcf_sample_states": [V, C.c_int32, C.c_int32, C.c_int64],
+        "ttcf_import_states": [V, C.c_int32, C.c_int32, D, D],
+        "ttcf_export_states": [V, C.c_int32, C.c_int32, D, D],
+        "ttcf_export_mother": [V, C.c_int32, D, D, D, L64],
+        "ttcf_record_mother": [V, C.c_int32, C.c_int64],
+        "ttcf_export_mother_series": [V, C.c_int32, C.c_int64, D, L64],
+        "ttcf_export_daughter": [V, C.c_int64, D, D, L64],
+        "ttcf_export_series": [V, C.c_int64, C.c_int32, C.c_int32, D],
+        "ttcf_daughter_health": [V, C.c_int64, I],
+        "ttcf_debug_poison": [V, C.c_int64],
+        "ttcf_debug_cell_list": [S, D, I, I, I, I, V],
+        "ttcf_debug_pairs": [S, C.c_double, D, C.c_double, C.c_int64, I, I, L64, V],
+        "ttcf_debug_forces": [S, C.c_double, D, D, D, V],
+        "ttcf_step_timing": [V, D, L64, C.c_int32],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = C.c_int32
+    L.ttcf_destroy.argtypes = [V]
+    L.ttcf_destroy.restype = None
+    L.ttcf_strerror.argtypes = [C.c_int32]
+    L.ttcf_strerror.restype = C.c_char_p
+    L.ttcf_last_error.argtypes = [V]
+    L.ttcf_last_error.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+# names exported by include/ttcf.h (checked by the CPU test-suite)
+EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "ttcf_step",
+            "ttcf_accumulate", "ttcf_response", "ttcf_destroy", "ttcf_strerror",
+            "ttcf_last_error", "ttcf_sample_states", "ttcf_import_states", "ttcf_export_states", "ttcf_export_mother",
+            "ttcf_record_mother", "ttcf_export_mother_series", "ttcf_export_daughter",
+            "ttcf_export_series", "ttcf_daughter_health", "ttcf_debug_poison",
+            "ttcf_debug_cell_list", "ttcf_debug_pairs", "ttcf_debug_forces", "ttcf_step_timing"]
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(code: int, where: str, ctx=None):
+    if code != TTCF_OK:
+        detail = lib().ttcf_last_error(ctx).decode() if ctx else lib().ttcf_strerror(code).decode()
+        raise TTCFError(code, where, detail)
+
+
+def current_stream():
+    """torch's current HIP stream handle (None: the default stream)."""
+    import torch
+    if torch.cuda.is_available():
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return None
+
+
+def use_torch_allocator():
+    """Route the library's device allocations through torch's caching allocator."""
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  stream if stream else None)
+
+    def _free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = _ALLOC(_alloc), _FREE(_free)
+    _keep.extend([a, f])
+    _check(lib().ttcf_set_allocator(a, f, None), "ttcf_set_allocator")
+
+
+# ----------------------------------------------------------------------------------------
+# stateless kernels
+# ----------------------------------------------------------------------------------------
+
+def ttcf_debug_cell_list(sys: System, r, stream=None):
+    r = _f64(r).ravel()
+    n = sys.n_atoms
+    dims = np.zeros(3, np.int32)
+    ncell = int(np.prod([int(np.floor(sys.box[a] / sys.r_cut)) for a in range(3)]))
+    cell_of = np.zeros(n, np.int32)
+    order = np.zeros(n, np.int32)
+    start = np.zeros(ncell + 1, np.int32)
+    _check(lib().ttcf_debug_cell_list(C.byref(sys), _dp(r), _ip(dims), _ip(cell_of), _ip(order),
+                                      _ip(start), stream), "ttcf_debug_cell_list")
+    return dims, cell_of, order, start
+
+
+def ttcf_debug_pairs(sys: System, r, dxle: float = 0.0, rlist: float | None = None, stream=None):
+    r = _f64(r).ravel()
+    cap = 64 * sys.n_atoms
+    pi = np.zeros(cap, np.int32)
+    pj = np.zeros(cap, np.int32)
+    cnt = C.c_int64(0)
+    rl = sys.r_cut if rlist is None else float(rlist)
+    _check(lib().ttcf_debug_pairs(C.byref(sys), float(dxle), _dp(r), rl, cap, _ip(pi), _ip(pj),
+                                  C.byref(cnt), stream), "ttcf_debug_pairs")
+    if cnt.value < 0:
+        raise TTCFError(TTCF_EINVAL, "ttcf_debug_pairs", "capacity too small")
+    return pi[:cnt.value].copy(), pj[:cnt.value].copy()
+
+
+def ttcf_debug_forces(sys: System, r, dxle: float = 0.0, stream=None):
+    r = _f64(r).ravel()
+    f = np.zeros(3 * sys.n_atoms)
+    out = np.zeros(2)
+    _check(lib().ttcf_debug_forces(C.byref(sys), float(dxle), _dp(r), _dp(f), _dp(out), stream),
+           "ttcf_debug_forces")
+    return f.reshape(3, sys.n_atoms), out[0], out[1]
+
+
+# ----------------------------------------------------------------------------------------
+# context
+# ----------------------------------------------------------------------------------------
+
+class Context:
+    """One ttcf_ctx: mothers, live daughters and accumulated start-state groups."""
+
+    def __init__(self, stream=None):
+        self._ctx = C.c_void_p(None)
+        self._stream = stream
+        self.systems = []
+
+    @property
+    def handle(self):
+        return self._ctx
+
+    def close(self):
+        if self._ctx:
+            lib().ttcf_destroy(self._ctx)
+            self._ctx = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- the five calls
+    def ttcf_init_mother(self, sys: System, r0, p0, n_equil: int, n_melt: int = 0,
+                         t_melt: float = 0.0) -> int:
+        r0 = _f64(r0).ravel()
+        p0 = _f64(p0).ravel()
+        assert r0.size == 3 * sys.n_atoms and p0.size == 3 * sys.n_atoms
+        mid = C.c_int32(-1)
+        code = lib().ttcf_init_mother(C.byref(self._ctx), C.byref(sys), _dp(r0), _dp(p0),
+                                      int(n_melt), float(t_melt), int(n_equil), self._stream,
+                                      C.byref(mid))
+        _check(code, "ttcf_init_mother", self._ctx if self._ctx else None)
+        self.systems.append(sys)
+        return mid.value
+
+    def ttcf_spawn_daughters(self, mother: int, n_states: int, steps_between: int,
+                             gamma_dot, n_steps: int, mapping_mask: int = 0xF) -> int:
+        g = _f64(np.atleast_1d(gamma_dot))
+        first = C.c_int64(-1)
+        _check(lib().ttcf_spawn_daughters(self._ctx, int(mother), int(n_states), int(steps_between),
+                                          int(mapping_mask), _dp(g), int(g.size), int(n_steps),
+                                          C.byref(first)), "ttcf_spawn_daughters", self._ctx)
+        return first.value
+
+    def ttcf_step(self, n_steps: int):
+        _check(lib().ttcf_step(self._ctx, int(n_steps)), "ttcf_step", self._ctx)
+
+    def ttcf_accumulate(self) -> int:
+        groups = C.c_int64(0)
+        _check(lib().ttcf_accumulate(self._ctx, C.byref(groups)), "ttcf_accumulate", self._ctx)
+        return groups.value
+
+    def ttcf_response(self, n_t: int, gamma_dot_filter: float, observable: int = TTCF_OBS_PXY):
+        """(ttcf_mean, ttcf_se, dav_mean, dav_se, n_states)."""
+        out = [np.zeros(n_t) for _ in range(4)]
+        used = C.c_int64(0)
+        _check(lib().ttcf_response(self._ctx, int(observable), float(gamma_dot_filter), int(n_t),
+                                   *[_dp(o) for o in out], C.byref(used)), "ttcf_response",
+               self._ctx)
+        return out[0], out[1], out[2], out[3], used.value
+
+    # ---- inspection hooks
+    def ttcf_sample_states(self, mother: int, n_states: int, steps_between: int):
+        _check(lib().ttcf_sample_states(self._ctx, int(mother), int(n_states), int(steps_between)),
+               "ttcf_sample_states", self._ctx)
+
+    def ttcf_import_states(self, mother: int, r, p):
+        r = _f64(r)
+        p = _f64(p)
+        ns = r.shape[0]
+        _check(lib().ttcf_import_states(self._ctx, int(mother), ns, _dp(r), _dp(p)),
+               "ttcf_import_states", self._ctx)
+
+    def ttcf_export_states(self, mother: int, n_states: int):
+        n = self.systems[mother].n_atoms
+        r = np.zeros((n_states, 3 * n))
+        p = np.zeros((n_states, 3 * n))
+        _check(lib().ttcf_export_states(self._ctx, int(mother), int(n_states), _dp(r), _dp(p)),
+               "ttcf_export_states", self._ctx)
+        return r, p
+
+    def ttcf_export_mother(self, mother: int):
+        n = self.systems[mother].n_atoms
+        r = np.zeros(3 * n)
+        p = np.zeros(3 * n)
+        z = np.zeros(1)
+        steps = C.c_int64(0)
+        _check(lib().ttcf_export_mother(self._ctx, int(mother), _dp(r), _dp(p), _dp(z),
+                                        C.byref(steps)), "ttcf_export_mother", self._ctx)
+        return r, p, float(z[0]), steps.value
+
+    def ttcf_record_mother(self, mother: int, capacity: int):
+        _check(lib().ttcf_record_mother(self._ctx, int(mother), int(capacity)),
+               "ttcf_record_mother", self._ctx)
+
+    def ttcf_export_mother_series(self, mother: int, n: int):
+        out = np.zeros(n)
+        cnt = C.c_int64(0)
+        _check(lib().ttcf_export_mother_series(self._ctx, int(mother), int(n), _dp(out),
+                                               C.byref(cnt)), "ttcf_export_mother_series", self._ctx)
+        return out[:min(n, cnt.value)]
+
+    def ttcf_export_daughter(self, daughter: int, n_atoms: int):
+        r = np.zeros(3 * n_atoms)
+        p = np.zeros(3 * n_atoms)
+        k = C.c_int64(0)
+        _check(lib().ttcf_export_daughter(self._ctx, int(daughter), _dp(r), _dp(p), C.byref(k)),
+               "ttcf_export_daughter", self._ctx)
+        return r, p, k.value
+
+    def ttcf_export_series(self, first: int, count: int, n_t: int):
+        out = np.zeros((count, n_t))
+        _check(lib().ttcf_export_series(self._ctx, int(first), int(count), int(n_t), _dp(out)),
+               "ttcf_export_series", self._ctx)
+        return out
+
+    def ttcf_daughter_health(self, daughter: int) -> int:
+        h = C.c_int32(0)
+        _check(lib().ttcf_daughter_health(self._ctx, int(daughter), C.byref(h)),
+               "ttcf_daughter_health", self._ctx)
+        return h.value
+
+    def ttcf_debug_poison(self, daughter: int):
+        _check(lib().ttcf_debug_poison(self._ctx, int(daughter)), "ttcf_debug_poison", self._ctx)
+
+    def ttcf_step_timing(self, reset: bool = False):
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        _check(lib().ttcf_step_timing(self._ctx, C.byref(ms), C.byref(n), int(reset)),
+               "ttcf_step_timing", self._ctx)
+        return ms.value, n.value

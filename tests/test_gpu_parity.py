@@ -1,0 +1,382 @@
+"""GPU-vs-oracle parity through the C ABI (runs on an MI355X).
+
+Inputs are seeded (ttcf_inputs) or produced by the FP64 oracle; nothing the GPU computes is
+fed back into the oracle. Bars:
+  * cell lists and neighbour pairs: bit-exact on identical FP64 positions;
+  * forces: max_i |dF_i| / rms_i |F_i| <= 1e-12 (FP64 form), <= 1e-5 (FP32 form);
+  * trajectories over 50 steps: max |dr|/L and max |dp|/rms(p) <= 1e-4 (FP32 forms),
+    <= 1e-9 (FP64 form);
+  * accumulate/response kernels: equal (1e-12 relative) to the oracle's estimator applied to
+    the same per-daughter series; TTCF within 2 standard errors of the oracle's TTCF.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import ttcf_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TAU = 0.25
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2312_02990_amd import ttcf
+    ttcf.lib()
+    return ttcf
+
+
+def gsys(T, s: I.System, precision):
+    return T.make_system(s.n, s.box, s.temperature, s.dt, precision=precision)
+
+
+def oracle_states(orc, s: I.System, seed: int, n_states: int, between: int = 100,
+                  n_equil: int = 2000, n_melt: int = 1000):
+    """Mother of the paper's algorithm on the oracle: melt, equilibrate, sample."""
+    r, p = I.initial_state(s, seed)
+    box = orc.make_box(s.n, s.box)
+    st = orc.NHState(r.ravel().copy(), p.ravel().copy())
+    if n_melt:
+        orc.nh_run(box, st, n_melt, 2.0, s.dt, orc.nh_q(s.nf, 2.0, TAU), s.nf)
+    sr, sp = orc.mother_sample(box, st, n_equil, n_states, between, s.temperature, s.dt,
+                               orc.nh_q(s.nf, s.temperature, TAU), s.nf)
+    return box, sr, sp
+
+
+@pytest.fixture(scope="module")
+def cfg1(orc):
+    """Config 1: WCA N=256, rho=0.8442, T=0.722; 8 start states every 100 steps."""
+    s = I.System(4)
+    box, sr, sp = oracle_states(orc, s, seed=1, n_states=8)
+    return s, box, sr, sp
+
+
+# ----------------------------------------------------------------------------------------
+# cell lists, pairs, forces
+# ----------------------------------------------------------------------------------------
+
+SIZES = [(3, 0.8442), (4, 0.8442), (5, 0.8442), (8, 0.8442), (10, 0.7), (5, 0.9)]
+
+
+@pytest.mark.parametrize("n_cells,rho", SIZES)
+def test_cell_list_bit_exact(T, orc, n_cells, rho):
+    s = I.System(n_cells, density=rho)
+    say(f"cell list N={s.n} rho={rho}")
+    r = I.perturbed_positions(s, 40 + n_cells, amplitude=0.2)
+    dims, cell_of, order, start = T.ttcf_debug_cell_list(gsys(T, s, 1), r)
+    box = orc.make_box(s.n, s.box)
+    c2, o2, s2 = orc.cell_list(box, r.ravel())
+    assert np.array_equal(dims, orc.cell_dims(box))
+    assert np.array_equal(cell_of, c2)
+    assert np.array_equal(order, o2)
+    assert np.array_equal(start, s2)
+
+
+@pytest.mark.parametrize("dx_frac", [0.0, 0.37, -0.61, 0.999999])
+def test_pairs_bit_exact(T, orc, cfg1, dx_frac):
+    s, box, sr, sp = cfg1
+    for r, sysobj, b in ((sr[3], s, box),):
+        dxle = dx_frac * sysobj.box
+        say(f"pairs N={sysobj.n} dx={dxle}")
+        for rl in (box.rc, 0.93 * box.rc):
+            gi, gj = T.ttcf_debug_pairs(gsys(T, sysobj, 0), r, dxle, rl)
+            oi, oj = orc.pairs(b, r, dxle, rl)
+            assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+    # a larger box
+    s8 = I.System(8)
+    r8 = I.perturbed_positions(s8, 7, amplitude=0.15)
+    b8 = orc.make_box(s8.n, s8.box)
+    gi, gj = T.ttcf_debug_pairs(gsys(T, s8, 0), r8, dx_frac * s8.box)
+    oi, oj = orc.pairs(b8, r8.ravel(), dx_frac * s8.box)
+    assert np.array_equal(gi, oi) and np.array_equal(gj, oj)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (1, 1e-5)])
+@pytest.mark.parametrize("dx_frac", [0.0, 0.43, -0.27])
+def test_forces(T, orc, cfg1, precision, tol, dx_frac):
+    s, box, sr, sp = cfg1
+    cases = [(s, box, sr[5])]
+    s8 = I.System(8)
+    cases.append((s8, orc.make_box(s8.n, s8.box), I.perturbed_positions(s8, 9, 0.12).ravel()))
+    for sysobj, b, r in cases:
+        dxle = dx_frac * sysobj.box
+        say(f"forces N={sysobj.n} precision={precision} dx={dxle}")
+        f, u, w = T.ttcf_debug_forces(gsys(T, sysobj, precision), r, dxle)
+        fo, uo, wo, _ = orc.forces(b, r, dxle)
+        rms = np.sqrt(np.mean(np.sum(fo * fo, axis=0)))
+        err = np.max(np.linalg.norm(f - fo, axis=0)) / rms
+        assert err <= tol, err
+        fsum = np.linalg.norm(fo, axis=0).sum()
+        assert abs(w - wo) <= tol * fsum * b.rc
+        assert abs(u - uo) <= tol * max(abs(uo), 1.0) * (10 if precision else 1)
+
+
+# ----------------------------------------------------------------------------------------
+# trajectories
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-4)])
+def test_mother_short_trajectory(T, orc, precision, tol):
+    s = I.System(4)
+    r0, p0 = I.initial_state(s, 3)
+    r0 = I.perturbed_positions(s, 3, 0.05)
+    say(f"mother 50 steps precision={precision}")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, precision), r0, p0, n_equil=50)
+        rg, pg, zg, steps = ctx.ttcf_export_mother(mid)
+    assert steps == 50
+    box = orc.make_box(s.n, s.box)
+    st = orc.NHState(r0.ravel().copy(), p0.ravel().copy())
+    orc.nh_run(box, st, 50, s.temperature, s.dt, orc.nh_q(s.nf, s.temperature, TAU), s.nf)
+    dr = rg - st.r
+    dr -= s.box * np.rint(dr / s.box)
+    assert np.abs(dr).max() / s.box <= tol
+    assert np.abs(pg - st.p).max() / np.sqrt(np.mean(st.p ** 2)) <= tol
+    assert zg == pytest.approx(st.zeta, rel=100 * tol, abs=100 * tol)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-4)])
+@pytest.mark.parametrize("gd", [1e-3, 1.0])
+def test_daughter_trajectories(T, orc, cfg1, precision, tol, gd):
+    s, box, sr, sp = cfg1
+    nst = 50
+    say(f"daughters 32 x {nst} steps precision={precision} gamma={gd}")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, precision), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        first = ctx.ttcf_spawn_daughters(mid, 8, 0, gd, nst)
+        ctx.ttcf_step(nst)
+        ser = ctx.ttcf_export_series(first, 32, nst + 1)
+        fin = [ctx.ttcf_export_daughter(first + d, s.n) for d in range(32)]
+    state_of = np.repeat(np.arange(8), 4)
+    map_of = np.tile(np.arange(4), 8)
+    vo, ro, po, _ = orc.run_daughters(box, sr, sp, state_of, map_of, np.full(32, gd), s.dt, nst,
+                                      nthreads=8, final_state=True)
+    scale = np.std(vo)
+    assert np.abs(ser - vo).max() / scale <= tol
+    for d in range(32):
+        rg, pg, k = fin[d]
+        assert k == nst
+        dr = rg - ro[d]
+        dr -= s.box * np.rint(dr / s.box)
+        assert np.abs(dr).max() / s.box <= tol
+        assert np.abs(pg - po[d]).max() / np.sqrt(np.mean(po[d] ** 2)) <= tol
+        # the isokinetic constraint holds on the GPU state
+        k_start = 0.5 * np.sum(sp[d // 4] ** 2)
+        assert 0.5 * np.sum(pg ** 2) == pytest.approx(k_start, rel=1e-13)
+    # Eq. (mappings): P_xy(0) of the four mapped daughters is (P, P, -P, -P)
+    v0 = ser[:, 0].reshape(8, 4)
+    np.testing.assert_allclose(v0[:, 1], v0[:, 0], rtol=1e-12)
+    np.testing.assert_allclose(v0[:, 2], -v0[:, 0], rtol=1e-5 if precision else 1e-12)
+    np.testing.assert_allclose(v0[:, 3], -v0[:, 0], rtol=1e-5 if precision else 1e-12)
+
+
+# ----------------------------------------------------------------------------------------
+# accumulate and response
+# ----------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_config1_ttcf_matches_oracle(T, orc, cfg1, precision):
+    """Config 1 end to end: 8 states x 4 mappings = 32 daughters x 100 steps at 1e-3."""
+    s, box, sr, sp = cfg1
+    nst, gd = 100, 1e-3
+    say(f"config 1 TTCF precision={precision}")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, precision), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        first = ctx.ttcf_spawn_daughters(mid, 8, 0, gd, nst)
+        ctx.ttcf_step(40)
+        ctx.ttcf_step(100)  # continues to each daughter's own length
+        ser = ctx.ttcf_export_series(first, 32, nst + 1)
+        assert ctx.ttcf_accumulate() == 8
+        tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, gd)
+    assert used == 8
+    # the accumulate/response kernels reproduce the oracle's estimator on the same series
+    ref = orc.ttcf_response(ser / s.volume, ser[:, 0], np.full(32, gd), s.temperature, s.dt)
+    np.testing.assert_allclose(tm, ref.ttcf, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(tse, ref.ttcf_se, rtol=1e-9, atol=1e-15)
+    np.testing.assert_allclose(dm, ref.dav, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(dse, ref.dav_se, rtol=1e-9, atol=1e-15)
+    # and the whole path agrees with the oracle's own daughters within 2 SE
+    state_of = np.repeat(np.arange(8), 4)
+    map_of = np.tile(np.arange(4), 8)
+    vo, _ = orc.run_daughters(box, sr, sp, state_of, map_of, np.full(32, gd), s.dt, nst,
+                              nthreads=8)
+    oref = orc.ttcf_response(vo / s.volume, vo[:, 0], np.full(32, gd), s.temperature, s.dt)
+    comb = np.hypot(tse, oref.ttcf_se)
+    assert np.all(np.abs(tm - oref.ttcf)[1:] <= 2.0 * comb[1:])
+    assert np.all(np.abs(dm - oref.dav) <= 2.0 * np.hypot(dse, oref.dav_se) + 1e-15)
+
+
+def test_response_filters_and_normalisation(T, orc, cfg1):
+    s, box, sr, sp = cfg1
+    nst = 30
+    say("response filters")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        f1 = ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-2, nst)
+        f2 = ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-4, nst)
+        ctx.ttcf_step(nst)
+        s1 = ctx.ttcf_export_series(f1, 32, nst + 1)
+        s2 = ctx.ttcf_export_series(f2, 32, nst + 1)
+        assert ctx.ttcf_accumulate() == 16
+        a = ctx.ttcf_response(nst + 1, 1e-2)
+        b = ctx.ttcf_response(nst + 1, 1e-4)
+        c = ctx.ttcf_response(nst + 1, 0.0)
+        with pytest.raises(T.TTCFError):
+            ctx.ttcf_response(nst + 1, 3e-3)
+        with pytest.raises(T.TTCFError):
+            ctx.ttcf_response(nst + 2, 1e-2)
+    ra = orc.ttcf_response(s1 / s.volume, s1[:, 0], np.full(32, 1e-2), s.temperature, s.dt)
+    rb = orc.ttcf_response(s2 / s.volume, s2[:, 0], np.full(32, 1e-4), s.temperature, s.dt)
+    np.testing.assert_allclose(a[0], ra.ttcf, rtol=1e-12, atol=1e-16)
+    np.testing.assert_allclose(b[0], rb.ttcf, rtol=1e-12, atol=1e-16)
+    # per-unit-rate response over both batches: mean of the 16 normalised groups
+    g = np.concatenate([ra.g / 1e-2, rb.g / 1e-4])
+    np.testing.assert_allclose(c[0], g.mean(axis=0), rtol=1e-10, atol=1e-14)
+    assert c[4] == 16
+
+
+def test_health_check_excludes_whole_group(T, orc, cfg1):
+    s, box, sr, sp = cfg1
+    nst = 20
+    say("health / failure injection")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        first = ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-3, nst)
+        ctx.ttcf_step(5)
+        ctx.ttcf_debug_poison(first + 13)  # state 3, mapping 1
+        ctx.ttcf_step(nst)
+        assert ctx.ttcf_daughter_health(first + 13) != 0
+        assert ctx.ttcf_daughter_health(first + 12) == 0
+        ser = ctx.ttcf_export_series(first, 32, nst + 1)
+        assert ctx.ttcf_accumulate() == 7
+        tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, 1e-3)
+    assert used == 7
+    keep = np.array([d for d in range(32) if d // 4 != 3])
+    ref = orc.ttcf_response(ser[keep] / s.volume, ser[keep, 0], np.full(28, 1e-3),
+                            s.temperature, s.dt)
+    np.testing.assert_allclose(tm, ref.ttcf, rtol=1e-12, atol=1e-16)
+
+
+def test_uneven_batch_is_invariant_and_deterministic(T, orc, cfg1):
+    """Daughters of two system sizes in one launch give bit-identical series to each size
+    run alone, and repeated runs are bit-identical."""
+    s, box, sr, sp = cfg1
+    s5 = I.System(5)
+    r5, p5 = I.initial_state(s5, 8)
+    r5 = I.perturbed_positions(s5, 8, 0.1)
+    nst = 25
+    say("uneven batch invariance")
+
+    def run(with256, with500):
+        out = {}
+        with T.Context() as ctx:
+            if with256:
+                m1 = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+                ctx.ttcf_import_states(m1, sr[:2], sp[:2])
+            if with500:
+                m2 = ctx.ttcf_init_mother(
+                    T.make_system(s5.n, s5.box, block_threads=512, precision=1), r5, p5,
+                    n_equil=0)
+                ctx.ttcf_import_states(m2, r5.reshape(1, -1), p5.reshape(1, -1))
+            if with256:
+                f1 = ctx.ttcf_spawn_daughters(m1, 2, 0, 0.1, nst)
+            if with500:
+                f2 = ctx.ttcf_spawn_daughters(m2, 1, 0, 0.1, nst)
+            ctx.ttcf_step(nst)
+            if with256:
+                out[256] = ctx.ttcf_export_series(f1, 8, nst + 1)
+            if with500:
+                out[500] = ctx.ttcf_export_series(f2, 4, nst + 1)
+        return out
+
+    both = run(True, True)
+    both2 = run(True, True)
+    a = run(True, False)
+    b = run(False, True)
+    assert np.array_equal(both[256], both2[256]) and np.array_equal(both[500], both2[500])
+    # the 256-atom daughters ran with 512-thread workgroups in the mixed launch and with
+    # 256-thread ones alone; their per-atom work is identical, so are their results
+    np.testing.assert_allclose(both[256], a[256], rtol=0, atol=0)
+    np.testing.assert_allclose(both[500], b[500], rtol=0, atol=0)
+
+
+# ----------------------------------------------------------------------------------------
+# the mother on the GPU
+# ----------------------------------------------------------------------------------------
+
+def test_gpu_mother_is_canonical_at_T(T):
+    """A long GPU mother run holds the target temperature and samples states with zero-mean
+    P_xy (<Omega(0)> = 0)."""
+    s = I.System(4)
+    r0, p0 = I.initial_state(s, 11)
+    say("gpu mother statistics")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 1), r0, p0, n_equil=2000, n_melt=1000, t_melt=2.0)
+        ctx.ttcf_record_mother(mid, 200000)
+        ctx.ttcf_spawn_daughters(mid, 2000, 100, 1e-3, 0)
+        vp = ctx.ttcf_export_mother_series(mid, 200000)
+        r, p = ctx.ttcf_export_states(mid, 2000)
+    assert len(vp) == 200000
+    ke = 0.5 * np.sum(p * p, axis=1)
+    temp = 2 * ke / s.nf
+    assert temp.mean() == pytest.approx(s.temperature, rel=0.01)
+    blocks = vp.reshape(50, -1).mean(axis=1)
+    se = blocks.std(ddof=1) / np.sqrt(50)
+    assert abs(blocks.mean()) < 3 * se
+    # every stored state is inside the box
+    rr = r.reshape(2000, 3, s.n)
+    assert np.all(rr >= 0) and np.all(rr < s.box)
+
+
+# ----------------------------------------------------------------------------------------
+# the headline workload at full size, in the benchmark's launch configuration
+# ----------------------------------------------------------------------------------------
+
+def test_config2_full_size_sampled(T, orc):
+    """N=2048, 1024 start states x 4 mappings = 4096 daughters x 500 steps, FP32 forces, in
+    one persistent launch. The oracle (16 equilibrated states, tiled to 1024) recomputes a
+    sample of 8 daughters; their first 50 steps agree to 1e-4; every daughter keeps its
+    kinetic energy and the mapped P_xy(0) cancel."""
+    s = I.System(8)
+    box, sr16, sp16 = oracle_states(orc, s, seed=2, n_states=16, n_melt=0, n_equil=400,
+                                    between=50)
+    reps = 64
+    sr = np.tile(sr16, (reps, 1))
+    sp = np.tile(sp16, (reps, 1))
+    nst, gd = 500, 1e-2
+    say("config 2 full size: 4096 daughters x 500 steps")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        first = ctx.ttcf_spawn_daughters(mid, 1024, 0, gd, nst)
+        ctx.ttcf_step(nst)
+        sample = [0, 1, 2, 3, 4 * 517 + 0, 4 * 517 + 1, 4 * 517 + 2, 4 * 517 + 3]
+        ser = np.stack([ctx.ttcf_export_series(first + d, 1, nst + 1)[0] for d in sample])
+        allv0 = ctx.ttcf_export_series(first, 4096, 1)[:, 0]
+        fin = [ctx.ttcf_export_daughter(first + d, s.n) for d in (0, 4095)]
+        assert ctx.ttcf_accumulate() == 1024
+        tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, gd)
+    assert used == 1024 and np.all(np.isfinite(tm)) and np.all(np.isfinite(dm))
+    st_of = np.array([d // 4 for d in sample]) % 16
+    mp_of = np.array([d % 4 for d in sample])
+    vo, _ = orc.run_daughters(box, sr16, sp16, st_of, mp_of, np.full(len(sample), gd), s.dt, 50,
+                              nthreads=8)
+    scale = np.std(vo)
+    assert np.abs(ser[:, :51] - vo).max() / scale <= 1e-4
+    v0 = allv0.reshape(1024, 4)
+    np.testing.assert_allclose(v0.sum(axis=1), 0.0, atol=1e-5 * np.abs(v0).max())
+    for (rg, pg, k), d in zip(fin, (0, 4095)):
+        assert k == nst
+        k_start = 0.5 * np.sum(sp[d // 4] ** 2)
+        assert 0.5 * np.sum(pg ** 2) == pytest.approx(k_start, rel=1e-13)

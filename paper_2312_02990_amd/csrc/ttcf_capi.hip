@@ -927,7 +927,7 @@ int32_t ttcf_debug_poison(ttcf_ctx* c, int64_t daughter) {
 // ---- stateless inspection kernels ---------------------------------------------------------
 
 static int32_t debug_setup(const ttcf_system* sys, const double* r, SysDev* S, double** d_r,
-                           hipStream_t s) {
+                           hipStream_t s, int lds_precision) {
     std::string why;
     int32_t rc = build_sysdev(sys, S, &why);
     if (rc != TTCF_OK) return rc;
@@ -936,7 +936,7 @@ static int32_t debug_setup(const ttcf_system* sys, const double* r, SysDev* S, d
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
         return TTCF_EDEVICE;
-    if (lds_bytes_for(S->n, S->nc[0] * S->nc[1] * S->nc[2], 0, 0) > prop.sharedMemPerBlock)
+    if (lds_bytes_for(S->n, S->nc[0] * S->nc[1] * S->nc[2], 0, lds_precision) > prop.sharedMemPerBlock)
         return TTCF_EINVAL;
     for (int k = 0; k < 3 * S->n; ++k)
         if (!(r[k] >= 0.0 && r[k] < S->box[k / S->n])) return TTCF_EINVAL;
@@ -953,7 +953,7 @@ int32_t ttcf_debug_cell_list(const ttcf_system* sys, const double* r, int32_t* d
     hipStream_t s = (hipStream_t)stream;
     SysDev S{};
     double* d_r = nullptr;
-    int32_t rc = debug_setup(sys, r, &S, &d_r, s);
+    int32_t rc = debug_setup(sys, r, &S, &d_r, s, TTCF_PREC_FP32_FORCES);
     if (rc != TTCF_OK) {
         dev_free(d_r);
         return rc;
@@ -988,7 +988,7 @@ int32_t ttcf_debug_pairs(const ttcf_system* sys, double dxle, const double* r, d
     hipStream_t s = (hipStream_t)stream;
     SysDev S{};
     double* d_r = nullptr;
-    int32_t rc = debug_setup(sys, r, &S, &d_r, s);
+    int32_t rc = debug_setup(sys, r, &S, &d_r, s, TTCF_PREC_FP32_FORCES);
     if (rc != TTCF_OK) {
         dev_free(d_r);
         return rc;
@@ -1034,7 +1034,7 @@ int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, 
     hipStream_t s = (hipStream_t)stream;
     SysDev S{};
     double* d_r = nullptr;
-    int32_t rc = debug_setup(sys, r, &S, &d_r, s);
+    int32_t rc = debug_setup(sys, r, &S, &d_r, s, sys->precision);
     if (rc != TTCF_OK) {
         dev_free(d_r);
         return rc;

@@ -993,7 +993,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_debug_pairs(SysDev S, double dx
                                                              unsigned long long* count) {
     extern __shared__ __align__(32) char smem[];
     const int C = S.nc[0] * S.nc[1] * S.nc[2];
-    const Lds<double> L = carve<double>(smem, S.n, C);
+    const Lds<float> L = carve<float>(smem, S.n, C);
     const int T = blockDim.x, t = threadIdx.x, n = S.n;
     const int nc0 = S.nc[0], nc1 = S.nc[1], nc2 = S.nc[2];
     for (int c = t; c < C; c += T) L.cnt[c] = 0;
@@ -1007,7 +1007,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_debug_pairs(SysDev S, double dx
     }
     __syncthreads();
     int cell[APT];
-    build_cells<double, APT>(S, dxle, x, y, z, L, cell);
+    build_cells<float, APT>(S, dxle, x, y, z, L, cell);
     const double rl2 = rlist * rlist;
     for (int s = t; s < n; s += T) {
         const int i = L.sid[s];
@@ -1168,9 +1168,9 @@ hipError_t launch_debug_cells(const SysDev& S, const double* r, int32_t* cell_of
                               int32_t* start, hipStream_t s) {
     const int threads = pick_threads(S.n, 0);
     switch (pick_apt(S.n, threads)) {
-        case 1: return debug_cells_t<double, 1>(S, r, cell_of, order, start, threads, s);
-        case 2: return debug_cells_t<double, 2>(S, r, cell_of, order, start, threads, s);
-        case 4: return debug_cells_t<double, 4>(S, r, cell_of, order, start, threads, s);
+        case 1: return debug_cells_t<float, 1>(S, r, cell_of, order, start, threads, s);
+        case 2: return debug_cells_t<float, 2>(S, r, cell_of, order, start, threads, s);
+        case 4: return debug_cells_t<float, 4>(S, r, cell_of, order, start, threads, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1210,7 +1210,7 @@ template <int APT>
 static hipError_t debug_pairs_t(const SysDev& S, double dxle, const double* r, double rlist,
                                 int64_t cap, int32_t* pi, int32_t* pj,
                                 unsigned long long* count, int threads, hipStream_t s) {
-    const size_t lds = plan_lds(S.n, S.nc[0] * S.nc[1] * S.nc[2], sizeof(double)).total;
+    const size_t lds = plan_lds(S.n, S.nc[0] * S.nc[1] * S.nc[2], sizeof(float)).total;
     (void)hipFuncSetAttribute((const void*)k_debug_pairs<APT>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL((k_debug_pairs<APT>), dim3(1), dim3(threads), lds, s, S, dxle, r, rlist,

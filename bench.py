@@ -111,8 +111,17 @@ def main():
     ap.add_argument("--states", type=int, default=1024)
     ap.add_argument("--daughter-steps", type=int, default=500)
     ap.add_argument("--precision", type=int, default=1, help="0 FP64 forces, 1 FP32 forces")
+    ap.add_argument("--threads", type=int, default=0,
+                    help="threads per workgroup (0: the library's choice)")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="daughter kernel form: 0 auto, 1 cell list, 2 neighbour list")
+    ap.add_argument("--skin", type=float, default=0.0, help="neighbour-list skin (0: default)")
+    ap.add_argument("--kmax", type=int, default=0, help="neighbour-list capacity (0: default)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 to skip)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (a kernel of known "
+                         "traffic, used to calibrate the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the daughter path shards by start state, and "
@@ -128,14 +137,24 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_probe_mib > 0:
+        nel = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     T.use_torch_allocator()
     stream = T.current_stream()
     s = I.System(args.n_cells)
-    sysd = T.make_system(s.n, s.box, s.temperature, s.dt, precision=args.precision)
+    sysd = T.make_system(s.n, s.box, s.temperature, s.dt, precision=args.precision,
+                         block_threads=args.threads)
     r0, p0 = I.initial_state(s, 2)
     ctx = T.Context(stream)
     t0 = time.perf_counter()
     mid = ctx.ttcf_init_mother(sysd, r0, p0, n_equil=2000, n_melt=1000, t_melt=2.0)
+    ctx.ttcf_set_step_shape(args.variant, args.threads, args.skin, args.kmax)
     ctx.ttcf_sample_states(mid, args.states, 100)
     torch.cuda.synchronize()
     mother_s = time.perf_counter() - t0

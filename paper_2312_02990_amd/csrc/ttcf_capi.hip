@@ -102,6 +102,10 @@ struct ttcf_ctx {
     double* d_row_gamma = nullptr;
     double* d_row_coef = nullptr;
     int32_t* d_row_health = nullptr;
+    // shape of the daughter step kernel
+    int32_t shape_variant = 0, shape_threads = 0, shape_kmax = 24;
+    double shape_skin = 0.25;
+    int32_t last_variant = -1;
     // timing of the step kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
     double step_ms = 0.0;
@@ -154,7 +158,27 @@ int32_t build_sysdev(const ttcf_system* s, SysDev* d, std::string* why) {
     d->u_shift = s->u_shift;
     d->dt = s->dt;
     d->volume = s->box[0] * s->box[1] * s->box[2];
+    for (int a = 0; a < 3; ++a) {
+        d->fix_scale[a] = 4294967296.0 / s->box[a];
+        d->fix_unit[a] = (float)(s->box[a] / 4294967296.0);
+    }
+    d->rc2_f = (float)d->rc2;
     return TTCF_OK;
+}
+
+// List-build grid of the neighbour-list form for a given skin; false if the box is too
+// small for a 27-cell stencil of that reach.
+bool set_list_grid(SysDev* d, double skin) {
+    const double reach = d->rc + skin;
+    d->skin = skin;
+    for (int a = 0; a < 3; ++a) {
+        d->lc[a] = (int32_t)std::floor(d->box[a] / reach);
+        d->lw[a] = d->box[a] / (double)d->lc[a];
+        d->l_inv_w[a] = (double)d->lc[a] / d->box[a];
+    }
+    d->rl2_f = (float)(reach * reach);
+    return d->lc[0] >= 4 && d->lc[1] >= 3 && d->lc[2] >= 3 && d->lc[0] <= kMaxCells1D &&
+           d->lc[1] <= kMaxCells1D && d->lc[2] <= kMaxCells1D;
 }
 
 int32_t check_shape(ttcf_ctx* c, const ttcf_system* s, const SysDev& d, int* threads, int* apt) {
@@ -606,8 +630,31 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
             return fail(c, TTCF_EINVAL, "live daughters mix force precisions");
     }
     if (order.empty()) return TTCF_OK;
+    if (c->shape_threads > 0) threads = c->shape_threads;
     apt = pick_apt(nmax, threads);
     if (apt < 0) return fail(c, TTCF_EINVAL, "batch needs more than 4 atoms per thread");
+    // kernel form: neighbour lists when asked for or (automatic) when the FP32 form fits
+    int variant = kVariantCells;
+    int lcmax = 0;
+    bool nl_ok = precision == TTCF_PREC_FP32_FORCES;
+    for (int32_t i : order) {
+        SysDev& d = c->descs[i].sys;
+        nl_ok = nl_ok && set_list_grid(&d, c->shape_skin);
+        lcmax = std::max(lcmax, d.lc[0] * d.lc[1] * d.lc[2]);
+    }
+    const size_t nl_bytes = lds_bytes_nl(nmax, lcmax, c->shape_kmax);
+    nl_ok = nl_ok && nl_bytes <= c->max_lds;
+    if (c->shape_variant == 2) {
+        if (!nl_ok) return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
+        variant = kVariantNeighbourList;
+    } else if (c->shape_variant == 0 && nl_ok) {
+        variant = kVariantNeighbourList;
+    }
+    if (variant == kVariantNeighbourList) {
+        rc = push_descs(c);  // the list grids were just written into the descriptors
+        if (rc != TTCF_OK) return rc;
+    }
+    c->last_variant = variant;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return c->descs[a].sys.n > c->descs[b].sys.n;
     });
@@ -630,8 +677,11 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
     L.apt = apt;
     L.precision = precision;
     L.nmax = nmax;
-    L.cmax = cmax;
-    L.lds_bytes = lds_bytes_for(nmax, cmax, threads, precision);
+    L.cmax = variant == kVariantNeighbourList ? lcmax : cmax;
+    L.variant = variant;
+    L.kmax = c->shape_kmax;
+    L.lds_bytes = variant == kVariantNeighbourList ? nl_bytes
+                                                   : lds_bytes_for(nmax, cmax, threads, precision);
     if (L.lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
     const int per_cu_lds = (int)(c->max_lds / L.lds_bytes);
     const int per_cu_waves = 32 / (threads / 64);  // 8 waves per SIMD, 4 SIMDs
@@ -645,6 +695,18 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
     HIPCHECK(c, hipEventRecord(e1, c->stream));
     c->pending_events.emplace_back(e0, e1);
     c->device_newer = true;
+    return TTCF_OK;
+}
+
+int32_t ttcf_set_step_shape(ttcf_ctx* c, int32_t variant, int32_t threads, double skin,
+                            int32_t kmax) {
+    if (!c || variant < 0 || variant > 2 || threads < 0 || threads > kMaxThreads ||
+        (threads > 0 && threads % 64 != 0) || kmax > 255)
+        return TTCF_EINVAL;
+    c->shape_variant = variant;
+    c->shape_threads = threads;
+    c->shape_skin = skin > 0.0 ? skin : 0.25;
+    c->shape_kmax = kmax > 0 ? kmax : 24;
     return TTCF_OK;
 }
 

@@ -24,6 +24,17 @@ struct SysDev {
     double u_shift;     // energy shift
     double dt;
     double volume;
+    // neighbour-list form: list-build grid with cells of width >= rc + skin, and the
+    // 32-bit fixed-point map of the box (coordinate * 2^32 / L, so integer differences are
+    // minimum-image separations)
+    int32_t lc[3];
+    double lw[3];
+    double l_inv_w[3];
+    double skin;
+    double fix_scale[3];   // 2^32 / L_a
+    float fix_unit[3];     // L_a / 2^32
+    float rc2_f;           // cutoff^2 and list radius^2 in FP32
+    float rl2_f;
 };
 
 // One daughter trajectory. Owned by the host runtime; the kernel updates k, done, health.
@@ -42,7 +53,13 @@ struct DaughterDesc {
     int32_t block;      // threads per workgroup the launcher was sized for
 };
 
-enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2 };
+enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2, kHealthListOverflow = 4 };
+
+// Daughter step kernels: the cell-list form rebuilds a canonical cell list every step and
+// evaluates pairs over the 27-cell stencil (FP64 or FP32 forces); the neighbour-list form
+// (FP32 forces) keeps per-atom lists of radius rc + skin in LDS and rebuilds them only when
+// the atoms have moved far enough to require it.
+enum Variant : int32_t { kVariantCells = 0, kVariantNeighbourList = 1 };
 
 // Launch configuration of the persistent daughter kernel.
 struct BatchLaunch {
@@ -56,6 +73,8 @@ struct BatchLaunch {
     int32_t precision;     // 0 FP64 forces, 1 FP32 forces
     int32_t grid;          // workgroups (persistent)
     int32_t nmax, cmax;    // largest system / cell grid in the batch (LDS sizing)
+    int32_t variant;       // Variant
+    int32_t kmax;          // neighbour-list capacity per atom (neighbour-list form)
     size_t lds_bytes;
 };
 
@@ -101,6 +120,7 @@ struct ResponseLaunch {
 int pick_threads(int n, int requested);
 int pick_apt(int n, int threads);
 size_t lds_bytes_for(int nmax, int cmax, int threads, int precision);
+size_t lds_bytes_nl(int nmax, int cmax, int kmax);
 
 hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s);
 hipError_t launch_mother(const MotherLaunch& m, hipStream_t s);

@@ -98,10 +98,12 @@ struct Lds {
     uint16_t* sid;                 // [nmax] atom ids in canonical order
     int32_t* scan;                 // [kMaxWaves]
     int32_t* misc;                 // [4]
+    SysDev* sys;                   // the trajectory's system constants (read from LDS, so
+                                   // they do not occupy registers across the step loop)
 };
 
 struct LdsPlan {
-    size_t spos, ax, ay, az, red, shx, shyz, rowinfo, cnt, start, sid, scan, misc, total;
+    size_t spos, ax, ay, az, red, shx, shyz, rowinfo, cnt, start, sid, scan, misc, sys, total;
 };
 
 __host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) & ~(a - 1); }
@@ -128,6 +130,7 @@ __host__ __device__ inline LdsPlan plan_lds(int nmax, int cmax, size_t real_byte
     p.sid = take(sizeof(uint16_t) * (size_t)nmax, 16);
     p.scan = take(sizeof(int32_t) * kMaxWaves, 16);
     p.misc = take(sizeof(int32_t) * 4, 16);
+    p.sys = take(sizeof(SysDev), 16);
     p.total = align_up(off, 128);
     return p;
 }
@@ -149,6 +152,7 @@ __device__ inline Lds<Real> carve(char* base, int nmax, int cmax) {
     L.sid = (uint16_t*)(base + p.sid);
     L.scan = (int32_t*)(base + p.scan);
     L.misc = (int32_t*)(base + p.misc);
+    L.sys = (SysDev*)(base + p.sys);
     return L;
 }
 
@@ -463,7 +467,9 @@ __device__ __forceinline__ void iso_kick_coeffs(double a, double b, double tau, 
 template <typename Real, int APT>
 __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& L) {
     const int T = blockDim.x, t = threadIdx.x;
-    const SysDev S = dsc->sys;
+    if (t == 0) *L.sys = dsc->sys;
+    __syncthreads();
+    const SysDev& S = *L.sys;
     const int n = S.n;
     double* st = dsc->state;
     const double gd = dsc->gamma_dot;
@@ -616,8 +622,8 @@ __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& 
     __syncthreads();
 }
 
-template <typename Real, int APT>
-__global__ __launch_bounds__(kMaxThreads) void k_daughters(BatchLaunch b) {
+template <typename Real, int APT, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_daughters(BatchLaunch b) {
     extern __shared__ __align__(32) char smem[];
     const Lds<Real> L = carve<Real>(smem, b.nmax, b.cmax);
     for (int c = threadIdx.x; c < b.cmax; c += blockDim.x) L.cnt[c] = 0;
@@ -647,8 +653,10 @@ __global__ void k_zero_int(int32_t* p, int n) {
 template <typename Real, int APT>
 __global__ __launch_bounds__(kMaxThreads) void k_mother(MotherLaunch m) {
     extern __shared__ __align__(32) char smem[];
-    const SysDev S = m.sys;
-    const Lds<Real> L = carve<Real>(smem, S.n, S.nc[0] * S.nc[1] * S.nc[2]);
+    const Lds<Real> L = carve<Real>(smem, m.sys.n, m.sys.nc[0] * m.sys.nc[1] * m.sys.nc[2]);
+    if (threadIdx.x == 0) *L.sys = m.sys;
+    __syncthreads();
+    const SysDev& S = *L.sys;
     const int T = blockDim.x, t = threadIdx.x, n = S.n;
     for (int c = t; c < S.nc[0] * S.nc[1] * S.nc[2]; c += T) L.cnt[c] = 0;
     double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT], fx[APT], fy[APT], fz[APT];
@@ -1054,6 +1062,506 @@ __global__ __launch_bounds__(kMaxThreads) void k_debug_pairs(SysDev S, double dx
 }
 
 // ---------------------------------------------------------------------------------------
+// neighbour-list form of the daughter step (FP32 pair forces)
+// ---------------------------------------------------------------------------------------
+//
+// Pair separations come from 32-bit fixed-point coordinates X = rint(x 2^32 / L): the box
+// is exactly 2^32 units wide, so the wrapped integer difference X_i - X_j is the periodic
+// minimum image. The y difference tells whether the pair reaches across the sliding
+// boundary (n_y = +-1); then the Lees-Edwards offset, also in fixed point, is subtracted
+// from the x difference. The result is converted to FP32 once, so the separation carries
+// one rounding of a number no larger than the cutoff.
+//
+// Every atom keeps a list of the atoms within rc + skin, sorted by atom id, in LDS. A pair's
+// relative displacement since the list was built is at most
+//   2 d + |gamma_dot| t (rc + 2 d),
+// with d the largest peculiar path length of any atom and t the time since the build (the
+// second term is the shear flow between the two atoms; across the y boundary the drifting
+// offset compensates the images' streaming). The lists are rebuilt as soon as that bound
+// reaches the skin, so every pair inside rc is always listed. Because each list is sorted
+// and pairs outside rc add nothing, the forces do not depend on when rebuilds happen.
+
+struct NlLds {
+    uint4* posq;       // [nmax] fixed-point positions (X, Y, Z, unused)
+    uint16_t* nbr;     // [kmax][nmax] neighbour ids, column a = atom a
+    uint16_t* ncnt;    // [nmax]
+    int32_t* cnt;      // [cmax] list-grid cell counts / cursors
+    int32_t* start;    // [cmax + 1]
+    uint16_t* sid;     // [nmax] atoms grouped by list-grid cell
+    int32_t* rowinfo;  // [3 rows][2]: first column offset mod nx, column count
+    double* red;       // block-reduction scratch
+    int32_t* scan;     // [kMaxWaves]
+    float* wmax;       // [kMaxWaves] per-wave maximum path length
+    int32_t* misc;     // [4]: [0] job, [1] list overflow
+    SysDev* sys;
+};
+
+struct NlPlan {
+    size_t posq, nbr, ncnt, cnt, start, sid, rowinfo, red, scan, wmax, misc, sys, total;
+};
+
+__host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax) {
+    NlPlan p;
+    size_t off = 0;
+    auto take = [&](size_t bytes, size_t al) {
+        off = align_up(off, al);
+        size_t at = off;
+        off += bytes;
+        return at;
+    };
+    p.posq = take(16 * (size_t)nmax, 16);
+    p.nbr = take(2 * (size_t)kmax * nmax, 16);
+    p.ncnt = take(2 * (size_t)nmax, 16);
+    p.cnt = take(4 * (size_t)cmax, 16);
+    p.start = take(4 * (size_t)(cmax + 1), 16);
+    p.sid = take(2 * (size_t)nmax, 16);
+    p.rowinfo = take(4 * 8, 16);
+    p.red = take(sizeof(double) * (kMaxWaves * kRedSlots + kRedSlots), 16);
+    p.scan = take(4 * kMaxWaves, 16);
+    p.wmax = take(4 * kMaxWaves, 16);
+    p.misc = take(4 * 4, 16);
+    p.sys = take(sizeof(SysDev), 16);
+    p.total = align_up(off, 128);
+    return p;
+}
+
+__device__ inline NlLds carve_nl(char* base, int nmax, int cmax, int kmax) {
+    NlPlan p = plan_nl(nmax, cmax, kmax);
+    NlLds L;
+    L.posq = (uint4*)(base + p.posq);
+    L.nbr = (uint16_t*)(base + p.nbr);
+    L.ncnt = (uint16_t*)(base + p.ncnt);
+    L.cnt = (int32_t*)(base + p.cnt);
+    L.start = (int32_t*)(base + p.start);
+    L.sid = (uint16_t*)(base + p.sid);
+    L.rowinfo = (int32_t*)(base + p.rowinfo);
+    L.red = (double*)(base + p.red);
+    L.scan = (int32_t*)(base + p.scan);
+    L.wmax = (float*)(base + p.wmax);
+    L.misc = (int32_t*)(base + p.misc);
+    L.sys = (SysDev*)(base + p.sys);
+    return L;
+}
+
+__device__ __forceinline__ uint32_t fix32(double v, double scale) {
+    return (uint32_t)(int64_t)rint(v * scale);
+}
+
+// Separation (FP32) of fixed-point positions i and j; dxq is the LE offset in fixed point.
+__device__ __forceinline__ void fix_sep(uint32_t xi, uint32_t yi, uint32_t zi, const uint4& q,
+                                        uint32_t dxq, const SysDev& S, float& dx, float& dy,
+                                        float& dz) {
+    const uint32_t uy = yi - q.y;
+    const int32_t iy = (int32_t)uy;
+    // n_y = +1 when y_i - y_j > L/2 (the image above is nearer), -1 when < -L/2
+    const uint32_t shift = (iy < 0 && yi >= q.y) ? dxq : ((iy > 0 && yi < q.y) ? 0u - dxq : 0u);
+    const int32_t ix = (int32_t)(xi - q.x - shift);
+    const int32_t iz = (int32_t)(zi - q.z);
+    dx = (float)ix * S.fix_unit[0];
+    dy = (float)iy * S.fix_unit[1];
+    dz = (float)iz * S.fix_unit[2];
+}
+
+// Rebuild the lists: counting sort of the atoms into the list grid (cells >= rc + skin wide),
+// then every owner collects its atoms' neighbours within rc + skin over the 27-cell stencil
+// (LE-displaced x range for rows across the y boundary) and sorts them by id.
+template <int APT>
+__device__ void nl_rebuild(const SysDev& S, double dxle, uint32_t dxq, const double (&x)[APT],
+                           const double (&y)[APT], const double (&z)[APT],
+                           const uint32_t (&qx)[APT], const uint32_t (&qy)[APT],
+                           const uint32_t (&qz)[APT], const NlLds& L, int kmax, int nmax) {
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    const int nc0 = S.lc[0], nc1 = S.lc[1], nc2 = S.lc[2];
+    const int C = nc0 * nc1 * nc2;
+    int cell[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        cell[j] = -1;
+        if (a < n) {
+            const int cx = cell_coord(x[j], S.l_inv_w[0], nc0);
+            const int cy = cell_coord(y[j], S.l_inv_w[1], nc1);
+            const int cz = cell_coord(z[j], S.l_inv_w[2], nc2);
+            cell[j] = cx + nc0 * (cy + nc1 * cz);
+            atomicAdd(&L.cnt[cell[j]], 1);
+        }
+    }
+    if (t == 0) {
+        L.misc[1] = 0;
+        const double reach = S.rc + S.skin;
+        const double wx = S.lw[0];
+        const double margin = 1e-6 * reach;
+        for (int row = 0; row < 3; ++row) {
+            int off, nq;
+            if (row == 1) {
+                off = -1;
+                nq = 3;
+            } else {
+                double sh = (row == 0 ? -1.0 : 1.0) * dxle;
+                sh -= S.box[0] * rint(sh / S.box[0]);
+                off = (int)floor((-reach - margin - sh) / wx);
+                const int hi = (int)floor((wx + reach + margin - sh) / wx);
+                nq = hi - off + 1;
+                if (nq > 5) nq = 5;
+                if (nq > nc0) nq = nc0;
+            }
+            L.rowinfo[2 * row] = ((off % nc0) + nc0) % nc0;
+            L.rowinfo[2 * row + 1] = nq;
+        }
+    }
+    __syncthreads();
+    scan_cells(L.cnt, L.start, C, L.scan);
+    if (t == 0) L.start[C] = n;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        if (cell[j] >= 0) {
+            const int idx = atomicAdd(&L.cnt[cell[j]], 1);
+            L.sid[idx] = (uint16_t)(t + j * T);
+        }
+    }
+    __syncthreads();
+    const float rl2 = S.rl2_f;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        if (a >= n) continue;
+        const int c0 = cell[j];
+        const int cx = c0 % nc0, cy = (c0 / nc0) % nc1, cz = c0 / (nc0 * nc1);
+        int count = 0;
+        bool over = false;
+#pragma unroll 1
+        for (int dz = 0; dz < 3; ++dz) {
+            int zz = cz + dz - 1;
+            zz = zz < 0 ? zz + nc2 : (zz >= nc2 ? zz - nc2 : zz);
+#pragma unroll 1
+            for (int dy = 0; dy < 3; ++dy) {
+                int yy = cy + dy - 1;
+                int row = 1;
+                if (yy < 0) {
+                    yy += nc1;
+                    row = 0;
+                } else if (yy >= nc1) {
+                    yy -= nc1;
+                    row = 2;
+                }
+                const int nq = L.rowinfo[2 * row + 1];
+                int xx = cx + L.rowinfo[2 * row];
+                if (xx >= nc0) xx -= nc0;
+                const int base = nc0 * (yy + nc1 * zz);
+#pragma unroll 1
+                for (int q = 0; q < nq; ++q) {
+                    const int c = base + xx;
+                    const int e = L.start[c + 1];
+                    for (int tt = L.start[c]; tt < e; ++tt) {
+                        const int jn = L.sid[tt];
+                        if (jn == a) continue;
+                        float ddx, ddy, ddz;
+                        fix_sep(qx[j], qy[j], qz[j], L.posq[jn], dxq, S, ddx, ddy, ddz);
+                        if (ddx * ddx + ddy * ddy + ddz * ddz < rl2) {
+                            if (count < kmax)
+                                L.nbr[count * nmax + a] = (uint16_t)jn;
+                            else
+                                over = true;
+                            ++count;
+                        }
+                    }
+                    ++xx;
+                    if (xx >= nc0) xx -= nc0;
+                }
+            }
+        }
+        if (over) {
+            L.misc[1] = 1;
+            count = kmax;
+        }
+        // ascending ids: a fixed summation order for the forces
+        for (int i = 1; i < count; ++i) {
+            const uint16_t v = L.nbr[i * nmax + a];
+            int k = i - 1;
+            while (k >= 0 && L.nbr[k * nmax + a] > v) {
+                L.nbr[(k + 1) * nmax + a] = L.nbr[k * nmax + a];
+                --k;
+            }
+            L.nbr[(k + 1) * nmax + a] = v;
+        }
+        L.ncnt[a] = (uint16_t)count;
+    }
+    for (int c = t; c < C; c += T) L.cnt[c] = 0;
+    __syncthreads();
+}
+
+// Forces on the owned atoms from their lists; returns this thread's share of W_xy.
+template <int APT>
+__device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
+                                            const uint32_t (&qx)[APT], const uint32_t (&qy)[APT],
+                                            const uint32_t (&qz)[APT], double (&fx)[APT],
+                                            double (&fy)[APT], double (&fz)[APT], const NlLds& L,
+                                            int nmax) {
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    const float rc2 = S.rc2_f;
+    const float ca = (float)S.c_attr;
+    double wacc = 0.0;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        float gx = 0.f, gy = 0.f, gz = 0.f, w = 0.f;
+        if (a < n) {
+            const int c = L.ncnt[a];
+            for (int k = 0; k < c; ++k) {
+                const uint4 q = L.posq[L.nbr[k * nmax + a]];
+                float dx, dy, dz;
+                fix_sep(qx[j], qy[j], qz[j], q, dxq, S, dx, dy, dz);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 < rc2) {
+                    const float inv = recip(r2);
+                    const float s3 = inv * inv * inv;
+                    const float fs = s3 * (48.f * s3 - 24.f * ca) * inv;
+                    gx += fs * dx;
+                    gy += fs * dy;
+                    gz += fs * dz;
+                    w += dx * (fs * dy);
+                }
+            }
+        }
+        fx[j] = (double)gx;
+        fy[j] = (double)gy;
+        fz[j] = (double)gz;
+        wacc += (double)w;
+    }
+    return 0.5 * wacc;
+}
+
+// Publish the fixed-point positions of the owned atoms and the wave maxima of the path
+// lengths; after the barrier every thread reads the workgroup maximum.
+template <int APT>
+__device__ __forceinline__ float nl_publish(const SysDev& S, const double (&x)[APT],
+                                            const double (&y)[APT], const double (&z)[APT],
+                                            uint32_t (&qx)[APT], uint32_t (&qy)[APT],
+                                            uint32_t (&qz)[APT], const float (&path)[APT],
+                                            const NlLds& L) {
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    float pm = 0.f;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        qx[j] = fix32(x[j], S.fix_scale[0]);
+        qy[j] = fix32(y[j], S.fix_scale[1]);
+        qz[j] = fix32(z[j], S.fix_scale[2]);
+        if (a < n) {
+            L.posq[a] = make_uint4(qx[j], qy[j], qz[j], 0u);
+            pm = fmaxf(pm, path[j]);
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pm = fmaxf(pm, __shfl_xor(pm, o, 64));
+    if ((t & 63) == 0) L.wmax[t >> 6] = pm;
+    __syncthreads();
+    float m = 0.f;
+    for (int w = 0; w < (T >> 6); ++w) m = fmaxf(m, L.wmax[w]);
+    return m;
+}
+
+template <int APT>
+__device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L, int kmax,
+                                int nmax) {
+    const int T = blockDim.x, t = threadIdx.x;
+    if (t == 0) *L.sys = dsc->sys;
+    __syncthreads();
+    const SysDev& S = *L.sys;
+    const int n = S.n;
+    double* st = dsc->state;
+    const double gd = dsc->gamma_dot;
+    int64_t k = dsc->k;
+    int done = dsc->done;
+    const int n_steps = dsc->n_steps;
+    double k0 = dsc->k0;
+    int health = dsc->health;
+    int todo = min(steps_cap, n_steps - done);
+    if (health != 0) todo = 0;
+    if (todo <= 0 && done > 0) return;
+
+    double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT], fx[APT], fy[APT], fz[APT];
+    uint32_t qx[APT], qy[APT], qz[APT];
+    float path[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        const bool v = a < n;
+        x[j] = v ? st[a] : 0.0;
+        y[j] = v ? st[n + a] : 0.0;
+        z[j] = v ? st[2 * n + a] : 0.0;
+        px[j] = v ? st[3 * n + a] : 0.0;
+        py[j] = v ? st[4 * n + a] : 0.0;
+        pz[j] = v ? st[5 * n + a] : 0.0;
+        path[j] = 0.f;
+    }
+    double dxle = le_offset(S, gd, k);
+    uint32_t dxq = fix32(dxle, S.fix_scale[0]);
+    nl_publish<APT>(S, x, y, z, qx, qy, qz, path, L);
+    nl_rebuild<APT>(S, dxle, dxq, x, y, z, qx, qy, qz, L, kmax, nmax);
+    if (L.misc[1] != 0) health |= kHealthListOverflow;
+    double wpart = nl_forces<APT>(S, dxq, qx, qy, qz, fx, fy, fz, L, nmax);
+
+    double m0[7] = {0, 0, 0, 0, 0, 0, wpart};
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        m0[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+        m0[1] += px[j] * py[j];
+        m0[2] += py[j] * py[j];
+        m0[3] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+        m0[4] += fx[j] * py[j];
+        m0[5] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+    }
+    block_sum<7>(m0, L.red);
+    if (done == 0) {
+        if (k0 <= 0.0) k0 = 0.5 * m0[0];
+        if (t == 0) dsc->series[0] = m0[1] + m0[6];
+    }
+    if (health != 0) todo = 0;
+    double pp = m0[0], pxpy = m0[1], pypy = m0[2], fp = m0[3], fxpy = m0[4], ff = m0[5];
+    const double h = S.dt, tau = 0.5 * S.dt, tg = tau * gd;
+    const float reach = (float)S.rc;
+    const float skin = (float)S.skin;
+    const float agd = (float)fabs(gd);
+    int since = 0;
+
+    for (int step = 0; step < todo; ++step) {
+        // ---- first half: S(tau) then K(tau)
+        const double ppt = pp - 2.0 * tg * pxpy + tg * tg * pypy;
+        const double g1 = sqrt(pp / ppt);
+        const double fp1 = g1 * (fp - tg * fxpy);
+        double s1, sd1;
+        iso_kick_coeffs(fp1 / pp, ff / pp, tau, s1, sd1);
+        const double isd1 = 1.0 / sd1;
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double qxp = g1 * (px[j] - tg * py[j]);
+            const double qyp = g1 * py[j];
+            const double qzp = g1 * pz[j];
+            px[j] = (qxp + fx[j] * s1) * isd1;
+            py[j] = (qyp + fy[j] * s1) * isd1;
+            pz[j] = (qzp + fz[j] * s1) * isd1;
+        }
+        // ---- streaming D(h), new strain, sliding-brick wrap, peculiar path length
+        k += 1;
+        dxle = le_offset(S, gd, k);
+        dxq = fix32(dxle, S.fix_scale[0]);
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double vx = px[j] + tg * py[j];
+            path[j] += (float)(h * sqrt(vx * vx + py[j] * py[j] + pz[j] * pz[j]));
+            x[j] += h * px[j] + h * gd * (y[j] + tau * py[j]);
+            y[j] += h * py[j];
+            z[j] += h * pz[j];
+            wrap_le(S, dxle, x[j], y[j], z[j]);
+        }
+        const float dmax = nl_publish<APT>(S, x, y, z, qx, qy, qz, path, L);
+        ++since;
+        const float tsince = (float)(since * h);
+        if (2.f * dmax + agd * tsince * (reach + 2.f * dmax) >= skin) {
+            nl_rebuild<APT>(S, dxle, dxq, x, y, z, qx, qy, qz, L, kmax, nmax);
+            if (L.misc[1] != 0) {
+                health |= kHealthListOverflow;
+                break;
+            }
+#pragma unroll
+            for (int j = 0; j < APT; ++j) path[j] = 0.f;
+            since = 0;
+        }
+        wpart = nl_forces<APT>(S, dxq, qx, qy, qz, fx, fy, fz, L, nmax);
+        // ---- moments of (p'', F): pp, pxpy, pypy, fp, fxpy, fypx, fxfy, fypy, fyfy, ff, W, pos
+        double m[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, wpart, 0};
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            m[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+            m[1] += px[j] * py[j];
+            m[2] += py[j] * py[j];
+            m[3] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+            m[4] += fx[j] * py[j];
+            m[5] += fy[j] * px[j];
+            m[6] += fx[j] * fy[j];
+            m[7] += fy[j] * py[j];
+            m[8] += fy[j] * fy[j];
+            m[9] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+            m[11] += x[j] + y[j] + z[j];
+        }
+        block_sum<12>(m, L.red);
+        double s2, sd2;
+        iso_kick_coeffs(m[3] / m[0], m[9] / m[0], tau, s2, sd2);
+        const double isd2 = 1.0 / sd2;
+        const double pp3 = (m[0] + 2.0 * s2 * m[3] + s2 * s2 * m[9]) * isd2 * isd2;
+        const double pxpy3 = (m[1] + s2 * (m[4] + m[5]) + s2 * s2 * m[6]) * isd2 * isd2;
+        const double pypy3 = (m[2] + 2.0 * s2 * m[7] + s2 * s2 * m[8]) * isd2 * isd2;
+        const double fp3 = (m[3] + s2 * m[9]) * isd2;
+        const double fxpy3 = (m[4] + s2 * m[6]) * isd2;
+        const double ppt2 = pp3 - 2.0 * tg * pxpy3 + tg * tg * pypy3;
+        const double pxpyt = pxpy3 - tg * pypy3;
+        const double c = sqrt(2.0 * k0 / ppt2);
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double qxp = (px[j] + fx[j] * s2) * isd2;
+            const double qyp = (py[j] + fy[j] * s2) * isd2;
+            const double qzp = (pz[j] + fz[j] * s2) * isd2;
+            px[j] = c * (qxp - tg * qyp);
+            py[j] = c * qyp;
+            pz[j] = c * qzp;
+        }
+        pp = c * c * ppt2;
+        pxpy = c * c * pxpyt;
+        pypy = c * c * pypy3;
+        fp = c * (fp3 - tg * fxpy3);
+        fxpy = c * fxpy3;
+        ff = m[9];
+        const double vpxy = pxpy + m[10];
+        done += 1;
+        if (t == 0) dsc->series[done] = vpxy;
+        if (!isfinite(vpxy) || !isfinite(c) || !isfinite(m[11])) {
+            health |= kHealthNonFinite;
+            break;
+        }
+        if (fabs(pp3 / m[0] - 1.0) > 1e-10) {
+            health |= kHealthDrift;
+            break;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        if (a < n) {
+            st[a] = x[j];
+            st[n + a] = y[j];
+            st[2 * n + a] = z[j];
+            st[3 * n + a] = px[j];
+            st[4 * n + a] = py[j];
+            st[5 * n + a] = pz[j];
+        }
+    }
+    if (t == 0) {
+        dsc->k = k;
+        dsc->done = done;
+        dsc->k0 = k0;
+        dsc->health = health;
+    }
+    __syncthreads();
+}
+
+template <int APT, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
+    extern __shared__ __align__(32) char smem[];
+    const NlLds L = carve_nl(smem, b.nmax, b.cmax, b.kmax);
+    for (int c = threadIdx.x; c < b.cmax; c += blockDim.x) L.cnt[c] = 0;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) L.misc[0] = atomicAdd(b.queue, 1);
+        __syncthreads();
+        const int j = __builtin_amdgcn_readfirstlane(L.misc[0]);
+        if (j >= b.n_jobs) break;
+        run_daughter_nl<APT>(&b.descs[b.order[j]], b.max_steps, L, b.kmax, b.nmax);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
 
@@ -1073,37 +1581,76 @@ int pick_apt(int n, int threads) {
     return -1;
 }
 
+size_t lds_bytes_nl(int nmax, int cmax, int kmax) { return plan_nl(nmax, cmax, kmax).total; }
+
 size_t lds_bytes_for(int nmax, int cmax, int threads, int precision) {
     (void)threads;
     return plan_lds(nmax, cmax, precision == 0 ? sizeof(double) : sizeof(float)).total;
 }
 
-template <typename Real, int APT>
+template <typename Real, int APT, int MAXT>
 static hipError_t launch_daughters_t(const BatchLaunch& b, hipStream_t s) {
-    (void)hipFuncSetAttribute((const void*)k_daughters<Real, APT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)b.lds_bytes);
-    hipLaunchKernelGGL((k_daughters<Real, APT>), dim3(b.grid), dim3(b.threads), b.lds_bytes, s,
+    if (b.threads > MAXT) return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_daughters<Real, APT, MAXT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
+    hipLaunchKernelGGL((k_daughters<Real, APT, MAXT>), dim3(b.grid), dim3(b.threads), b.lds_bytes,
+                       s, b);
+    return hipGetLastError();
+}
+
+template <typename Real>
+static hipError_t launch_daughters_r(const BatchLaunch& b, hipStream_t s) {
+    // workgroups of up to 512 threads get a 256-register budget, 1024-thread ones 128
+    if (b.threads <= 512) {
+        switch (b.apt) {
+            case 1: return launch_daughters_t<Real, 1, 512>(b, s);
+            case 2: return launch_daughters_t<Real, 2, 512>(b, s);
+            case 4: return launch_daughters_t<Real, 4, 512>(b, s);
+        }
+    } else {
+        switch (b.apt) {
+            case 1: return launch_daughters_t<Real, 1, 1024>(b, s);
+            case 2: return launch_daughters_t<Real, 2, 1024>(b, s);
+            case 4: return launch_daughters_t<Real, 4, 1024>(b, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int APT, int MAXT>
+static hipError_t launch_nl_t(const BatchLaunch& b, hipStream_t s) {
+    if (b.threads > MAXT) return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
+    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT>), dim3(b.grid), dim3(b.threads), b.lds_bytes, s,
                        b);
     return hipGetLastError();
 }
 
-hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.queue, 1);
-    if (b.precision == 0) {
+static hipError_t launch_nl(const BatchLaunch& b, hipStream_t s) {
+    if (b.threads <= 512) {
         switch (b.apt) {
-            case 1: return launch_daughters_t<double, 1>(b, s);
-            case 2: return launch_daughters_t<double, 2>(b, s);
-            case 4: return launch_daughters_t<double, 4>(b, s);
+            case 1: return launch_nl_t<1, 512>(b, s);
+            case 2: return launch_nl_t<2, 512>(b, s);
+            case 4: return launch_nl_t<4, 512>(b, s);
         }
     } else {
         switch (b.apt) {
-            case 1: return launch_daughters_t<float, 1>(b, s);
-            case 2: return launch_daughters_t<float, 2>(b, s);
-            case 4: return launch_daughters_t<float, 4>(b, s);
+            case 1: return launch_nl_t<1, 1024>(b, s);
+            case 2: return launch_nl_t<2, 1024>(b, s);
+            case 4: return launch_nl_t<4, 1024>(b, s);
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.queue, 1);
+    if (b.variant == kVariantNeighbourList) {
+        if (b.precision != 1) return hipErrorInvalidValue;
+        return launch_nl(b, s);
+    }
+    return b.precision == 0 ? launch_daughters_r<double>(b, s) : launch_daughters_r<float>(b, s);
 }
 
 template <typename Real, int APT>

@@ -100,6 +100,7 @@ def lib():
         "ttcf_debug_pairs": [S, C.c_double, D, C.c_double, C.c_int64, I, I, L64, V],
         "ttcf_debug_forces": [S, C.c_double, D, D, D, V],
         "ttcf_step_timing": [V, D, L64, C.c_int32],
+        "ttcf_set_step_shape": [V, C.c_int32, C.c_int32, C.c_double, C.c_int32],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -121,7 +122,8 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_last_error", "ttcf_sample_states", "ttcf_import_states", "ttcf_export_states", "ttcf_export_mother",
             "ttcf_record_mother", "ttcf_export_mother_series", "ttcf_export_daughter",
             "ttcf_export_series", "ttcf_daughter_health", "ttcf_debug_poison",
-            "ttcf_debug_cell_list", "ttcf_debug_pairs", "ttcf_debug_forces", "ttcf_step_timing"]
+            "ttcf_debug_cell_list", "ttcf_debug_pairs", "ttcf_debug_forces", "ttcf_step_timing",
+            "ttcf_set_step_shape"]
 
 
 def _dp(a):
@@ -342,6 +344,12 @@ class Context:
 
     def ttcf_debug_poison(self, daughter: int):
         _check(lib().ttcf_debug_poison(self._ctx, int(daughter)), "ttcf_debug_poison", self._ctx)
+
+    def ttcf_set_step_shape(self, variant: int = 0, threads: int = 0, skin: float = 0.0,
+                            kmax: int = 0):
+        """variant 0 auto, 1 cell list, 2 neighbour list (see include/ttcf.h)."""
+        _check(lib().ttcf_set_step_shape(self._ctx, int(variant), int(threads), float(skin),
+                                         int(kmax)), "ttcf_set_step_shape", self._ctx)
 
     def ttcf_step_timing(self, reset: bool = False):
         ms = C.c_double(0.0)

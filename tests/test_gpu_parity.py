@@ -173,14 +173,16 @@ def test_mother_short_trajectory(T, orc, precision, tol):
     assert zg == pytest.approx(st.zeta, rel=100 * tol, abs=100 * tol)
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-9), (1, 1e-4)])
+@pytest.mark.parametrize("precision,variant,tol", [(0, 1, 1e-9), (1, 1, 1e-4), (1, 2, 1e-4)])
 @pytest.mark.parametrize("gd", [1e-3, 1.0])
-def test_daughter_trajectories(T, orc, cfg1, precision, tol, gd):
+def test_daughter_trajectories(T, orc, cfg1, precision, variant, tol, gd):
+    """variant 1: cell list every step; variant 2: neighbour lists (FP32 forces)."""
     s, box, sr, sp = cfg1
     nst = 50
-    say(f"daughters 32 x {nst} steps precision={precision} gamma={gd}")
+    say(f"daughters 32 x {nst} steps precision={precision} variant={variant} gamma={gd}")
     with T.Context() as ctx:
         mid = ctx.ttcf_init_mother(gsys(T, s, precision), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_set_step_shape(variant=variant)
         ctx.ttcf_import_states(mid, sr, sp)
         first = ctx.ttcf_spawn_daughters(mid, 8, 0, gd, nst)
         ctx.ttcf_step(nst)
@@ -207,6 +209,41 @@ def test_daughter_trajectories(T, orc, cfg1, precision, tol, gd):
     np.testing.assert_allclose(v0[:, 1], v0[:, 0], rtol=1e-12)
     np.testing.assert_allclose(v0[:, 2], -v0[:, 0], rtol=1e-5 if precision else 1e-12)
     np.testing.assert_allclose(v0[:, 3], -v0[:, 0], rtol=1e-5 if precision else 1e-12)
+
+
+def test_neighbour_lists_are_skin_invariant(T, orc, cfg1):
+    """Lists are sorted by atom id and pairs beyond the cutoff add nothing, so the results
+    are bit-identical for any skin (and any rebuild schedule), at strong shear too."""
+    s, box, sr, sp = cfg1
+    nst = 200
+    out = []
+    for skin, kmax in ((0.15, 20), (0.25, 24), (0.4, 40)):
+        say(f"skin {skin}")
+        with T.Context() as ctx:
+            mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+            ctx.ttcf_import_states(mid, sr[:2], sp[:2])
+            ctx.ttcf_set_step_shape(variant=2, skin=skin, kmax=kmax)
+            first = ctx.ttcf_spawn_daughters(mid, 2, 0, [1e-3, 2.0], nst)
+            ctx.ttcf_step(nst)
+            out.append(ctx.ttcf_export_series(first, 8, nst + 1))
+            assert all(ctx.ttcf_daughter_health(first + d) == 0 for d in range(8))
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[1], out[2])
+
+
+def test_neighbour_list_form_matches_cell_form(T, cfg1):
+    """The two FP32 kernel forms agree to FP32 accuracy over 100 steps."""
+    s, box, sr, sp = cfg1
+    nst = 100
+    out = []
+    for variant in (1, 2):
+        with T.Context() as ctx:
+            mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+            ctx.ttcf_import_states(mid, sr, sp)
+            ctx.ttcf_set_step_shape(variant=variant)
+            first = ctx.ttcf_spawn_daughters(mid, 8, 0, 0.5, nst)
+            ctx.ttcf_step(nst)
+            out.append(ctx.ttcf_export_series(first, 32, nst + 1))
+    assert np.abs(out[0] - out[1]).max() / np.std(out[0]) < 1e-3
 
 
 # ----------------------------------------------------------------------------------------

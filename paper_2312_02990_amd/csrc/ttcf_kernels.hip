@@ -436,17 +436,39 @@ __device__ void compute_forces(const SysDev& S, double dxle, const double (&x)[A
 // Exact flow over tau of dp/dt = F - (F.p/p.p) p with F fixed: p -> (p + F s)/sdot,
 // s = (a/b)(cosh(q tau) - 1) + sinh(q tau)/q, sdot = (a/q) sinh(q tau) + cosh(q tau),
 // a = F.p/p.p, b = F.F/p.p, q = sqrt(b) (Zhang, J. Chem. Phys. 106, 6102 (1997)).
+// With u = b tau^2 = (q tau)^2 the two combinations needed are power series in u:
+//   (cosh(q tau) - 1)/b = tau^2 (1/2 + u/24 + u^2/720 + ...)
+//   sinh(q tau)/q       = tau   (1 + u/6 + u^2/120 + ...)
+// Seven terms reach double precision for u < 0.04 (q tau < 0.2, the usual regime: the
+// first omitted term is below 1e-17 of the sum); larger arguments use the library sinh.
 __device__ __forceinline__ void iso_kick_coeffs(double a, double b, double tau, double& s,
                                                 double& sdot) {
     double ch1_b, sh_q;
-    if (b > 0.0) {
+    const double u = b * tau * tau;
+    if (u < 0.04) {
+        // Horner forms of the two series, coefficients 2/(2k+2)! and 1/(2k+1)!
+        double c = 1.0 / 87178291200.0;  // 1/14!
+        c = c * u + 1.0 / 479001600.0;   // 1/12!
+        c = c * u + 1.0 / 3628800.0;     // 1/10!
+        c = c * u + 1.0 / 40320.0;       // 1/8!
+        c = c * u + 1.0 / 720.0;         // 1/6!
+        c = c * u + 1.0 / 24.0;          // 1/4!
+        c = c * u + 0.5;                 // 1/2!
+        double d = 1.0 / 1307674368000.0;  // 1/15!
+        d = d * u + 1.0 / 6227020800.0;    // 1/13!
+        d = d * u + 1.0 / 39916800.0;      // 1/11!
+        d = d * u + 1.0 / 362880.0;        // 1/9!
+        d = d * u + 1.0 / 5040.0;          // 1/7!
+        d = d * u + 1.0 / 120.0;           // 1/5!
+        d = d * u + 1.0 / 6.0;             // 1/3!
+        d = d * u + 1.0;
+        ch1_b = tau * tau * c;
+        sh_q = tau * d;
+    } else {
         const double q = sqrt(b);
         const double hs = sinh(0.5 * q * tau) / q;
         ch1_b = 2.0 * hs * hs;
         sh_q = sinh(q * tau) / q;
-    } else {
-        ch1_b = 0.5 * tau * tau;
-        sh_q = tau;
     }
     s = a * ch1_b + sh_q;
     sdot = a * sh_q + (1.0 + b * ch1_b);
@@ -1153,8 +1175,12 @@ __device__ __forceinline__ void fix_sep(uint32_t xi, uint32_t yi, uint32_t zi, c
                                         float& dz) {
     const uint32_t uy = yi - q.y;
     const int32_t iy = (int32_t)uy;
-    // n_y = +1 when y_i - y_j > L/2 (the image above is nearer), -1 when < -L/2
-    const uint32_t shift = (iy < 0 && yi >= q.y) ? dxq : ((iy > 0 && yi < q.y) ? 0u - dxq : 0u);
+    // n_y = +1 when y_i - y_j > L/2 (the image above is nearer), -1 when < -L/2, else 0:
+    // n_y = (sign bit of the wrapped difference) - (borrow of the unsigned subtraction);
+    // the x difference then loses n_y times the offset
+    const uint32_t sgn = uy >> 31;
+    const uint32_t brw = yi < q.y ? 1u : 0u;
+    const uint32_t shift = ((0u - sgn) & dxq) - ((0u - brw) & dxq);
     const int32_t ix = (int32_t)(xi - q.x - shift);
     const int32_t iz = (int32_t)(zi - q.z);
     dx = (float)ix * S.fix_unit[0];

@@ -201,6 +201,72 @@ int32_t ttcf_set_step_shape(ttcf_ctx* ctx, int32_t variant, int32_t threads, dou
  * last reset (timing events are recorded on the context's stream around every launch). */
 int32_t ttcf_step_timing(ttcf_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
 
+/* ---- learned control variate for Eq. (TTCF) ------------------------------------------
+ * Not part of the paper's method: a variance-reduction layer over its estimator. A network
+ * g(x) predicts B(t_1..t_K) of a daughter from 64 features x of its mapped start state
+ * (P_xy(0), Omega(0) of Eq. (TTCF1), and per slab of 31 equal slabs in y the sums of p_x and
+ * of p_x p_y). Each daughter gets h(t_k) = Omega(0) int_0^{t_k} g ds (trapezoid rule on the
+ * step grid, g(0) = B(0)); a start state's H_n is the mean of h over its mappings. The
+ * estimate is mean_n [G_n(t) - H_n(t)] + mu_H(t), with G_n the start state's Eq. (TTCF)
+ * series and mu_H = E[H] over equilibrium start states, estimated from independent mother
+ * samples. For any fixed network the estimate is unbiased; a zero network gives Eq. (TTCF).
+ *
+ * Network: y = W3 gelu(W2 gelu(W1 x' + b1) + b2) + b3 with 256 hidden units, GELU in its
+ * erf form, x' the standardised features and y the standardised targets (column mean and
+ * standard deviation over the training set, fixed when training starts). Parameters are FP32,
+ * laid out flat as W1[64][256], b1[256], W2[256][256], b2[256], W3[256][K], b3[K] (row-major,
+ * input index first); 64*256 + 256 + 256*256 + 256 + 256*K + K values. The products run on
+ * the bfloat16 matrix cores (operands rounded to nearest even, FP32 accumulation). */
+
+/* (Re)create the network with K = n_out outputs from host weights (n_weights FP32 values in
+ * the layout above); clears the Adam moments, the training set and the mean term. */
+int32_t ttcf_cv_init(ttcf_ctx* ctx, int32_t n_out, const float* weights, int64_t n_weights);
+/* Copy the current parameters to a host array of n_weights floats. */
+int32_t ttcf_cv_export_weights(ttcf_ctx* ctx, float* weights, int64_t n_weights);
+/* Append live daughters first..first+count-1 (all of one mother, each stepped at least K
+ * steps, start states still stored on the mother) to the training set: their features and
+ * the targets B(t_1..t_K) = P_xy from their recorded series. */
+int32_t ttcf_cv_add_training(ttcf_ctx* ctx, int64_t first, int32_t count);
+/* Training rows first_row..first_row+count-1 as stored (raw, not standardised): features
+ * x[count][64] and targets t[count][K] (either pointer may be NULL). */
+int32_t ttcf_cv_export_training(ttcf_ctx* ctx, int64_t first_row, int32_t count, float* x,
+                                float* t);
+/* Adam (beta 0.9/0.999, eps 1e-8) on the mean squared error of the standardised targets,
+ * batches of `batch` rows, steps = floor(rows / batch) per epoch. order (may be NULL: rows in
+ * stored order) holds epochs * rows training-row indices, one permutation per epoch; rows
+ * past the last full batch are skipped. loss_out (may be NULL) receives each epoch's loss on
+ * its last batch (epochs doubles). */
+int32_t ttcf_cv_train(ttcf_ctx* ctx, int32_t epochs, int32_t batch, double lr,
+                      const int32_t* order, double* loss_out);
+/* Give live daughters first..first+count-1 (one mother, stepped at least once) their h series
+ * from the current network; ttcf_accumulate then carries H_n beside G_n for every group
+ * whose daughters all have one. h is zero past t_K. */
+int32_t ttcf_cv_attach(ttcf_ctx* ctx, int64_t first, int32_t count);
+/* mu_H at shear rate gamma_dot from mother samples that no daughter of the estimate used:
+ * n_replicas copies of the mother's current state, copy q with the host momentum kick
+ * kicks[q*3n ..] added as given (may be NULL: no kicks; kicks let the copies decorrelate and
+ * should sum to zero per copy, so that the total momentum stays zero), run
+ * decorrelate_steps Nose-Hoover steps, then `rounds` times: states_per_replica states each
+ * steps_between steps apart, all four mappings of each, h from the network, added to the
+ * running compensated sums. The mother itself does not move. *out_samples (may be NULL) gets
+ * the total number of start states in the mean term. */
+int32_t ttcf_cv_mean_term(ttcf_ctx* ctx, int32_t mother, int32_t n_replicas, const double* kicks,
+                          int64_t decorrelate_steps, int32_t rounds, int32_t states_per_replica,
+                          int64_t steps_between, double gamma_dot, int64_t* out_samples);
+/* Control-variate estimate at k = 0..n_t-1 (n_t <= K + 1) over the healthy groups at shear
+ * rate gamma_dot_filter (which must equal the mean term's) that carry H_n: cv_mean, its block
+ * standard error over start states cv_se (mu_H's own error is reported separately in
+ * mu_h_se), and mu_H. Any pointer may be NULL. */
+int32_t ttcf_cv_response(ttcf_ctx* ctx, double gamma_dot_filter, int32_t n_t, double* cv_mean,
+                         double* cv_se, double* mu_h, double* mu_h_se, int64_t* out_n_states);
+/* The network alone (tests): forward pass on host rows x[rows][64] (fed to W1 unstandardised)
+ * into y[rows][K] ... */
+int32_t ttcf_mlp_forward(ttcf_ctx* ctx, const float* x, int32_t rows, float* y);
+/* ... and the gradient of mean((y - target)^2) over all rows*K elements with respect to the
+ * parameters, in the flat layout (n_weights floats into grad). */
+int32_t ttcf_mlp_gradient(ttcf_ctx* ctx, const float* x, const float* target, int32_t rows,
+                          float* grad);
+
 #ifdef __cplusplus
 }
 #endif

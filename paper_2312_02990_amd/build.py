@@ -5,7 +5,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libttcf.so")
-SOURCES = [os.path.join(CSRC, "ttcf_kernels.hip"), os.path.join(CSRC, "ttcf_capi.hip")]
+SOURCES = [os.path.join(CSRC, "ttcf_kernels.hip"), os.path.join(CSRC, "ttcf_mlp.hip"),
+           os.path.join(CSRC, "ttcf_capi.hip")]
 HEADERS = [os.path.join(CSRC, "ttcf_internal.h"),
            os.path.join(os.path.dirname(HERE), "include", "ttcf.h")]
 

@@ -60,6 +60,7 @@ struct Batch {
     int64_t first_id = 0;
     double* states = nullptr;    // n_daughters * 6n
     double* series = nullptr;    // n_daughters * (n_steps + 1)
+    double* hseries = nullptr;   // learned control variate, same layout (allocated on demand)
     void* scratch = nullptr;     // spawn index arrays
     int32_t remaining = 0;       // daughters not yet accumulated
 };
@@ -69,6 +70,7 @@ struct Live {                   // host view of one live daughter
     int32_t batch;
     int32_t index;              // within its batch
     int32_t group;
+    int32_t state;              // index of its start state in the mother's stored set
 };
 
 }  // namespace
@@ -102,6 +104,29 @@ struct ttcf_ctx {
     double* d_row_gamma = nullptr;
     double* d_row_coef = nullptr;
     int32_t* d_row_health = nullptr;
+    // mother launch blocks (device array)
+    MotherLaunch* d_mlaunch = nullptr;
+    int32_t mlaunch_cap = 0;
+    // accumulated control-variate series (same rows as acc_d)
+    double* acc_h = nullptr;
+    std::vector<int32_t> row_cv;
+    // learned control variate
+    int32_t cv_out = 0;          // outputs (time points t_1..t_nout)
+    int64_t cv_nparam = 0;
+    float* cv_p = nullptr;       // parameters, gradients, Adam moments (4 x nparam)
+    float* cv_g = nullptr;
+    float* cv_m = nullptr;
+    float* cv_v = nullptr;
+    int64_t cv_adam_steps = 0;
+    float* cv_x = nullptr;       // training features (raw)
+    float* cv_t = nullptr;       // training targets (raw)
+    int64_t cv_rows = 0, cv_cap = 0;
+    float* cv_stats = nullptr;   // x mean, x 1/std (kCvIn each), y mean, y 1/std (cv_out each)
+    bool cv_stats_ready = false;
+    double* cv_mu = nullptr;     // mean term: sum, comp, sumsq, compsq (4 x (cv_out + 1))
+    int64_t cv_mu_count = 0;
+    double cv_mu_dt = 0.0;
+    double cv_mu_gamma = 0.0;
     // shape of the daughter step kernel
     int32_t shape_variant = 0, shape_threads = 0, shape_kmax = 24;
     double shape_skin = 0.25;
@@ -222,6 +247,20 @@ int32_t push_descs(ttcf_ctx* c) {
     return TTCF_OK;
 }
 
+int32_t upload_mother_launches(ttcf_ctx* c, const MotherLaunch* ls, int32_t count) {
+    if (c->mlaunch_cap < count) {
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        dev_free(c->d_mlaunch);
+        c->d_mlaunch = (MotherLaunch*)dev_alloc(sizeof(MotherLaunch) * count, c->stream);
+        if (!c->d_mlaunch) return fail(c, TTCF_ENOMEM, "mother launch allocation failed");
+        c->mlaunch_cap = count;
+    }
+    HIPCHECK(c, hipMemcpyAsync(c->d_mlaunch, ls, sizeof(MotherLaunch) * count, hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
 int32_t run_mother(ttcf_ctx* c, Mother& m, double temperature, int64_t n_chunks,
                    int64_t steps_per_chunk, double* snapshots) {
     if (steps_per_chunk <= 0 && n_chunks <= 0) return TTCF_OK;
@@ -246,7 +285,9 @@ int32_t run_mother(ttcf_ctx* c, Mother& m, double temperature, int64_t n_chunks,
     L.apt = m.apt;
     L.precision = m.sys.precision;
     L.lds_bytes = lds_for(m.dev, m.sys.precision);
-    HIPCHECK(c, launch_mother(L, c->stream));
+    int32_t rc = upload_mother_launches(c, &L, 1);
+    if (rc != TTCF_OK) return rc;
+    HIPCHECK(c, launch_mothers(c->d_mlaunch, 1, L, c->stream));
     m.steps += total;
     return TTCF_OK;
 }
@@ -257,10 +298,12 @@ int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
     const int64_t cap = std::max<int64_t>(rows_needed, 2 * c->acc_cap);
     double* nd = (double*)dev_alloc(sizeof(double) * (size_t)cap * stride, c->stream);
     double* ni = (double*)dev_alloc(sizeof(double) * (size_t)cap * stride, c->stream);
+    double* nh = (double*)dev_alloc(sizeof(double) * (size_t)cap * stride, c->stream);
     double* ng = (double*)dev_alloc(sizeof(double) * (size_t)cap, c->stream);
     double* nc = (double*)dev_alloc(sizeof(double) * (size_t)cap, c->stream);
-    int32_t* nh = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)cap, c->stream);
-    if (!nd || !ni || !ng || !nc || !nh) return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
+    int32_t* nhl = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)cap, c->stream);
+    if (!nd || !ni || !nh || !ng || !nc || !nhl)
+        return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
     if (c->acc_rows > 0) {
         HIPCHECK(c, hipMemcpy2DAsync(nd, sizeof(double) * stride, c->acc_d,
                                      sizeof(double) * c->acc_stride, sizeof(double) * c->acc_stride,
@@ -268,18 +311,23 @@ int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
         HIPCHECK(c, hipMemcpy2DAsync(ni, sizeof(double) * stride, c->acc_i,
                                      sizeof(double) * c->acc_stride, sizeof(double) * c->acc_stride,
                                      (size_t)c->acc_rows, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHECK(c, hipMemcpy2DAsync(nh, sizeof(double) * stride, c->acc_h,
+                                     sizeof(double) * c->acc_stride, sizeof(double) * c->acc_stride,
+                                     (size_t)c->acc_rows, hipMemcpyDeviceToDevice, c->stream));
         HIPCHECK(c, hipStreamSynchronize(c->stream));
     }
     dev_free(c->acc_d);
     dev_free(c->acc_i);
+    dev_free(c->acc_h);
     dev_free(c->d_row_gamma);
     dev_free(c->d_row_coef);
     dev_free(c->d_row_health);
     c->acc_d = nd;
     c->acc_i = ni;
+    c->acc_h = nh;
     c->d_row_gamma = ng;
     c->d_row_coef = nc;
-    c->d_row_health = nh;
+    c->d_row_health = nhl;
     c->acc_cap = cap;
     c->acc_stride = stride;
     return TTCF_OK;
@@ -342,6 +390,14 @@ void ttcf_destroy(ttcf_ctx* c) {
     dev_free(c->d_row_gamma);
     dev_free(c->d_row_coef);
     dev_free(c->d_row_health);
+    dev_free(c->d_mlaunch);
+    dev_free(c->acc_h);
+    dev_free(c->cv_p);
+    dev_free(c->cv_x);
+    dev_free(c->cv_t);
+    dev_free(c->cv_stats);
+    dev_free(c->cv_mu);
+    for (auto& b : c->batches) dev_free(b.hseries);
     --g_live_contexts;
     delete c;
 }
@@ -592,7 +648,7 @@ int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int6
             ds.map = maps[q];
             ds.block = m.threads;
             c->descs.push_back(ds);
-            c->live.push_back(Live{c->next_id + d, bidx, d, group});
+            c->live.push_back(Live{c->next_id + d, bidx, d, group, s});
         }
     }
     HIPCHECK(c, hipMemcpyAsync(b.scratch, host.data(), scratch_bytes, hipMemcpyHostToDevice, c->stream));
@@ -796,6 +852,7 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
         A.i_out = c->acc_i + (size_t)c->acc_rows * c->acc_stride;
         A.health_out = c->d_row_health + c->acc_rows;
         A.gamma_out = c->d_row_gamma + c->acc_rows;
+        A.h_out = c->acc_h + (size_t)c->acc_rows * c->acc_stride;
         A.n_groups = (int32_t)which.size();
         A.n_t = len;
         // rows are written with the context's stride
@@ -808,6 +865,7 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
                 one.i_out = A.i_out + (size_t)g * c->acc_stride;
                 one.health_out = A.health_out + g;
                 one.gamma_out = A.gamma_out + g;
+                one.h_out = A.h_out + (size_t)g * c->acc_stride;
                 one.n_groups = 1;
                 HIPCHECK(c, launch_accumulate(one, c->stream));
             }
@@ -827,6 +885,12 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
                                       .sys.temperature);
             c->row_nt.push_back(len);
             c->row_health.push_back(hh[q]);
+            {
+                int has = 1;
+                for (size_t d = ready[which[q]].first; d < ready[which[q]].second; ++d)
+                    has &= c->descs[d].hseries != nullptr ? 1 : 0;
+                c->row_cv.push_back(has);
+            }
             if (hh[q] == 0) ++added_healthy;
         }
         c->acc_rows += (int64_t)which.size();
@@ -857,9 +921,11 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
             dev_free(b.states);
             dev_free(b.series);
             dev_free(b.scratch);
+            dev_free(b.hseries);
             b.states = nullptr;
             b.series = nullptr;
             b.scratch = nullptr;
+            b.hseries = nullptr;
         }
     }
     rc = push_descs(c);
@@ -985,6 +1051,625 @@ int32_t ttcf_debug_poison(ttcf_ctx* c, int64_t daughter) {
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     return TTCF_OK;
 }
+
+}  // extern "C"
+
+// ---- learned control variate -------------------------------------------------------------
+
+namespace {
+
+// parameter offsets: W1 [kCvIn x H], b1 [H], W2 [H x H], b2 [H], W3 [H x n_out], b3 [n_out]
+struct CvLayout {
+    int64_t w1, b1, w2, b2, w3, b3, total;
+};
+
+CvLayout cv_layout(int n_out) {
+    CvLayout l;
+    const int64_t H = kCvHidden;
+    l.w1 = 0;
+    l.b1 = l.w1 + (int64_t)kCvIn * H;
+    l.w2 = l.b1 + H;
+    l.b2 = l.w2 + H * H;
+    l.w3 = l.b2 + H;
+    l.b3 = l.w3 + H * n_out;
+    l.total = l.b3 + n_out;
+    return l;
+}
+
+// Scratch of one forward/backward pass over `rows` samples.
+struct CvWork {
+    float *x, *t, *z1, *a1, *z2, *a2, *y, *dy, *dz2, *dz1;
+    double* loss;
+    void* base = nullptr;
+};
+
+int32_t cv_work_alloc(ttcf_ctx* c, int rows, CvWork* w) {
+    const int H = kCvHidden, O = c->cv_out;
+    const size_t f = (size_t)rows * (kCvIn + O + 4 * H + 2 * O + 2 * H) + 64;
+    w->base = dev_alloc(sizeof(float) * f + 64, c->stream);
+    if (!w->base) return fail(c, TTCF_ENOMEM, "network scratch allocation failed");
+    float* p = (float*)w->base;
+    w->x = p; p += (size_t)rows * kCvIn;
+    w->t = p; p += (size_t)rows * O;
+    w->z1 = p; p += (size_t)rows * H;
+    w->a1 = p; p += (size_t)rows * H;
+    w->z2 = p; p += (size_t)rows * H;
+    w->a2 = p; p += (size_t)rows * H;
+    w->y = p; p += (size_t)rows * O;
+    w->dy = p; p += (size_t)rows * O;
+    w->dz2 = p; p += (size_t)rows * H;
+    w->dz1 = p; p += (size_t)rows * H;
+    w->loss = (double*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    return TTCF_OK;
+}
+
+GemmArgs gemm(const float* A, int64_t sam, int64_t sak, const float* B, int64_t sbk, int64_t sbn,
+              float* C, int ldc, int M, int N, int K, int epi, const float* bias = nullptr,
+              float* Z = nullptr, const float* Zin = nullptr) {
+    GemmArgs g{};
+    g.A = A;
+    g.sam = sam;
+    g.sak = sak;
+    g.B = B;
+    g.sbk = sbk;
+    g.sbn = sbn;
+    g.C = C;
+    g.ldc = ldc;
+    g.bias = bias;
+    g.Z = Z;
+    g.Zin = Zin;
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.epi = epi;
+    return g;
+}
+
+// y = W3 gelu(W2 gelu(W1 x + b1) + b2) + b3 for w.x (rows x kCvIn)
+int32_t cv_forward(ttcf_ctx* c, const float* P, CvWork& w, int rows) {
+    const int H = kCvHidden, O = c->cv_out;
+    const CvLayout l = cv_layout(O);
+    HIPCHECK(c, launch_gemm(gemm(w.x, kCvIn, 1, P + l.w1, H, 1, w.a1, H, rows, H, kCvIn, 1, P + l.b1, w.z1),
+                            c->stream));
+    HIPCHECK(c, launch_gemm(gemm(w.a1, H, 1, P + l.w2, H, 1, w.a2, H, rows, H, H, 1, P + l.b2, w.z2),
+                            c->stream));
+    HIPCHECK(c, launch_gemm(gemm(w.a2, H, 1, P + l.w3, O, 1, w.y, O, rows, O, H, 0, P + l.b3),
+                            c->stream));
+    return TTCF_OK;
+}
+
+// gradient of mean((y - t)^2) over every element into G
+int32_t cv_backward(ttcf_ctx* c, const float* P, float* G, CvWork& w, int rows) {
+    const int H = kCvHidden, O = c->cv_out;
+    const CvLayout l = cv_layout(O);
+    const int64_t cnt = (int64_t)rows * O;
+    HIPCHECK(c, launch_mse_grad(w.y, w.t, cnt, 2.0f / (float)cnt, w.dy, c->stream));
+    // W3: a2^T dy; b3: column sums of dy; dz2 = (dy W3^T) gelu'(z2)
+    HIPCHECK(c, launch_gemm(gemm(w.a2, 1, H, w.dy, O, 1, G + l.w3, O, H, O, rows, 0), c->stream));
+    HIPCHECK(c, launch_colsum(w.dy, rows, O, O, G + l.b3, c->stream));
+    HIPCHECK(c, launch_gemm(gemm(w.dy, O, 1, P + l.w3, 1, O, w.dz2, H, rows, H, O, 2, nullptr, nullptr, w.z2),
+                            c->stream));
+    HIPCHECK(c, launch_gemm(gemm(w.a1, 1, H, w.dz2, H, 1, G + l.w2, H, H, H, rows, 0), c->stream));
+    HIPCHECK(c, launch_colsum(w.dz2, rows, H, H, G + l.b2, c->stream));
+    HIPCHECK(c, launch_gemm(gemm(w.dz2, H, 1, P + l.w2, 1, H, w.dz1, H, rows, H, H, 2, nullptr, nullptr, w.z1),
+                            c->stream));
+    HIPCHECK(c, launch_gemm(gemm(w.x, 1, kCvIn, w.dz1, H, 1, G + l.w1, H, kCvIn, H, rows, 0), c->stream));
+    HIPCHECK(c, launch_colsum(w.dz1, rows, H, H, G + l.b1, c->stream));
+    return TTCF_OK;
+}
+
+int32_t cv_check(ttcf_ctx* c) {
+    if (!c) return TTCF_EINVAL;
+    if (!c->cv_p) return fail(c, TTCF_ESTATE, "the control-variate network is not initialised");
+    return TTCF_OK;
+}
+
+// Features, P_xy(0) and Omega(0) of live daughters [first, first + count): rows of kCvIn floats.
+int32_t cv_features_of(ttcf_ctx* c, int64_t first, int32_t count, float* d_feat, double* d_b0,
+                       double* d_om, int* out_mother) {
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    std::vector<int32_t> idx(count);
+    int mother = -1;
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t i = find_live(c, first + q);
+        if (i < 0) return fail(c, TTCF_EINVAL, "no such live daughter");
+        const int mo = c->batches[c->live[i].batch].mother;
+        if (mother < 0) mother = mo;
+        if (mo != mother) return fail(c, TTCF_EINVAL, "daughters of one call must share a mother");
+        if (c->descs[i].done < 1 && c->descs[i].n_steps > 0)
+            return fail(c, TTCF_ESTATE, "features need P_xy(0): run ttcf_step first");
+        idx[q] = i;
+    }
+    Mother& m = c->mothers[mother];
+    const DaughterDesc& d0 = c->descs[idx[0]];
+    // per row: state index, mapping, V*P_xy(0) gathered from the series
+    std::vector<int32_t> st(count), mp(count);
+    for (int32_t q = 0; q < count; ++q) {
+        st[q] = c->live[idx[q]].state;
+        mp[q] = c->descs[idx[q]].map;
+        if (st[q] >= m.n_states) return fail(c, TTCF_ESTATE, "the mother's stored states were replaced");
+    }
+    const size_t bytes = sizeof(int32_t) * 2 * count + sizeof(double) * count + 64;
+    char* buf = (char*)dev_alloc(bytes, c->stream);
+    if (!buf) return fail(c, TTCF_ENOMEM, "feature scratch allocation failed");
+    double* d_vp = (double*)buf;
+    int32_t* d_st = (int32_t*)(d_vp + count);
+    int32_t* d_mp = d_st + count;
+    for (int32_t q = 0; q < count; ++q)
+        HIPCHECK(c, hipMemcpyAsync(d_vp + q, c->descs[idx[q]].series, sizeof(double),
+                                   hipMemcpyDeviceToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(d_st, st.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(d_mp, mp.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, launch_cv_features(m.states, m.dev.n, d_st, d_mp, d_vp, nullptr, count, m.dev.box[1],
+                                   m.dev.volume, m.sys.temperature, d0.gamma_dot, d_feat, d_b0, d_om,
+                                   c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(buf);
+    if (out_mother) *out_mother = mother;
+    return TTCF_OK;
+}
+
+// Standardised-network predictions of B(t_1..t_nout) for raw feature rows, then h rows.
+int32_t cv_predict_h(ttcf_ctx* c, const float* d_feat, const double* d_b0, const double* d_om,
+                     int rows, double dt, double* d_h, int64_t h_stride) {
+    const int O = c->cv_out;
+    const float* xs = c->cv_stats;
+    const float* ys = c->cv_stats + 2 * kCvIn;
+    const int chunk = 65536;
+    CvWork w;
+    int32_t rc = cv_work_alloc(c, std::min(rows, chunk), &w);
+    if (rc != TTCF_OK) return rc;
+    for (int r0 = 0; r0 < rows; r0 += chunk) {
+        const int nr = std::min(chunk, rows - r0);
+        HIPCHECK(c, launch_gather_norm(d_feat + (size_t)r0 * kCvIn, nullptr, nr, kCvIn, xs, xs + kCvIn,
+                                       w.x, c->stream));
+        rc = cv_forward(c, c->cv_p, w, nr);
+        if (rc != TTCF_OK) return rc;
+        HIPCHECK(c, launch_cv_h(w.y, nr, O, ys, ys + O, d_b0 + r0, d_om + r0, dt,
+                                d_h + (size_t)r0 * h_stride, h_stride, c->stream));
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(w.base);
+    return TTCF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ttcf_cv_init(ttcf_ctx* c, int32_t n_out, const float* weights, int64_t n_weights) {
+    if (!c || n_out <= 0 || n_out > 4096 || !weights) return TTCF_EINVAL;
+    const CvLayout l = cv_layout(n_out);
+    if (n_weights != l.total) return fail(c, TTCF_EINVAL, "weight count does not match the network");
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(c->cv_p);
+    dev_free(c->cv_stats);
+    dev_free(c->cv_mu);
+    c->cv_out = n_out;
+    c->cv_nparam = l.total;
+    c->cv_p = (float*)dev_alloc(sizeof(float) * 4 * l.total, c->stream);
+    c->cv_stats = (float*)dev_alloc(sizeof(float) * (2 * kCvIn + 2 * n_out), c->stream);
+    c->cv_mu = (double*)dev_alloc(sizeof(double) * 4 * (n_out + 1), c->stream);
+    if (!c->cv_p || !c->cv_stats || !c->cv_mu) return fail(c, TTCF_ENOMEM, "network allocation failed");
+    c->cv_g = c->cv_p + l.total;
+    c->cv_m = c->cv_g + l.total;
+    c->cv_v = c->cv_m + l.total;
+    HIPCHECK(c, hipMemcpyAsync(c->cv_p, weights, sizeof(float) * l.total, hipMemcpyHostToDevice, c->stream));
+    std::vector<float> zeros(2 * l.total, 0.0f);
+    HIPCHECK(c, hipMemcpyAsync(c->cv_m, zeros.data(), sizeof(float) * 2 * l.total, hipMemcpyHostToDevice,
+                               c->stream));
+    std::vector<float> st(2 * kCvIn + 2 * n_out);
+    for (int i = 0; i < kCvIn; ++i) st[i] = 0.f, st[kCvIn + i] = 1.f;
+    for (int i = 0; i < n_out; ++i) st[2 * kCvIn + i] = 0.f, st[2 * kCvIn + n_out + i] = 1.f;
+    HIPCHECK(c, hipMemcpyAsync(c->cv_stats, st.data(), sizeof(float) * st.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    std::vector<double> mz(4 * (n_out + 1), 0.0);
+    HIPCHECK(c, hipMemcpyAsync(c->cv_mu, mz.data(), sizeof(double) * mz.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->cv_adam_steps = 0;
+    c->cv_stats_ready = false;
+    c->cv_mu_count = 0;
+    c->cv_rows = 0;
+    return TTCF_OK;
+}
+
+int32_t ttcf_cv_export_weights(ttcf_ctx* c, float* weights, int64_t n_weights) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (!weights || n_weights != c->cv_nparam) return TTCF_EINVAL;
+    HIPCHECK(c, hipMemcpyAsync(weights, c->cv_p, sizeof(float) * n_weights, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
+int32_t ttcf_mlp_forward(ttcf_ctx* c, const float* x, int32_t rows, float* y) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (!x || !y || rows <= 0) return TTCF_EINVAL;
+    CvWork w;
+    rc = cv_work_alloc(c, rows, &w);
+    if (rc != TTCF_OK) return rc;
+    HIPCHECK(c, hipMemcpyAsync(w.x, x, sizeof(float) * rows * kCvIn, hipMemcpyHostToDevice, c->stream));
+    rc = cv_forward(c, c->cv_p, w, rows);
+    if (rc != TTCF_OK) return rc;
+    HIPCHECK(c, hipMemcpyAsync(y, w.y, sizeof(float) * rows * c->cv_out, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(w.base);
+    return TTCF_OK;
+}
+
+int32_t ttcf_mlp_gradient(ttcf_ctx* c, const float* x, const float* target, int32_t rows,
+                          float* grad) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (!x || !target || !grad || rows <= 0) return TTCF_EINVAL;
+    CvWork w;
+    rc = cv_work_alloc(c, rows, &w);
+    if (rc != TTCF_OK) return rc;
+    HIPCHECK(c, hipMemcpyAsync(w.x, x, sizeof(float) * rows * kCvIn, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(w.t, target, sizeof(float) * rows * c->cv_out, hipMemcpyHostToDevice,
+                               c->stream));
+    rc = cv_forward(c, c->cv_p, w, rows);
+    if (rc == TTCF_OK) rc = cv_backward(c, c->cv_p, c->cv_g, w, rows);
+    if (rc != TTCF_OK) return rc;
+    HIPCHECK(c, hipMemcpyAsync(grad, c->cv_g, sizeof(float) * c->cv_nparam, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(w.base);
+    return TTCF_OK;
+}
+
+int32_t ttcf_cv_add_training(ttcf_ctx* c, int64_t first, int32_t count) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (count <= 0) return TTCF_EINVAL;
+    rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    const int O = c->cv_out;
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t i = find_live(c, first + q);
+        if (i < 0) return fail(c, TTCF_EINVAL, "no such live daughter");
+        if (c->descs[i].done < O) return fail(c, TTCF_ESTATE, "daughter has fewer recorded steps than outputs");
+    }
+    if (c->cv_rows + count > c->cv_cap) {
+        const int64_t cap = std::max<int64_t>(c->cv_rows + count, 2 * c->cv_cap);
+        float* nx = (float*)dev_alloc(sizeof(float) * cap * kCvIn, c->stream);
+        float* nt = (float*)dev_alloc(sizeof(float) * cap * O, c->stream);
+        if (!nx || !nt) return fail(c, TTCF_ENOMEM, "training-set allocation failed");
+        if (c->cv_rows > 0) {
+            HIPCHECK(c, hipMemcpyAsync(nx, c->cv_x, sizeof(float) * c->cv_rows * kCvIn,
+                                       hipMemcpyDeviceToDevice, c->stream));
+            HIPCHECK(c, hipMemcpyAsync(nt, c->cv_t, sizeof(float) * c->cv_rows * O,
+                                       hipMemcpyDeviceToDevice, c->stream));
+        }
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        dev_free(c->cv_x);
+        dev_free(c->cv_t);
+        c->cv_x = nx;
+        c->cv_t = nt;
+        c->cv_cap = cap;
+    }
+    double* tmp = (double*)dev_alloc(sizeof(double) * 2 * count, c->stream);
+    if (!tmp) return fail(c, TTCF_ENOMEM, "scratch allocation failed");
+    rc = cv_features_of(c, first, count, c->cv_x + c->cv_rows * kCvIn, tmp, tmp + count, nullptr);
+    if (rc != TTCF_OK) return rc;
+    // targets B(t_1..t_nout) = V P_xy / V, stored as FP32
+    std::vector<double> ser((size_t)O + 1);
+    std::vector<float> tg((size_t)count * O);
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t i = find_live(c, first + q);
+        HIPCHECK(c, hipMemcpyAsync(ser.data(), c->descs[i].series, sizeof(double) * (O + 1),
+                                   hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        const double iv = 1.0 / c->descs[i].sys.volume;
+        for (int k = 0; k < O; ++k) tg[(size_t)q * O + k] = (float)(ser[k + 1] * iv);
+    }
+    HIPCHECK(c, hipMemcpyAsync(c->cv_t + c->cv_rows * O, tg.data(), sizeof(float) * tg.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(tmp);
+    c->cv_rows += count;
+    c->cv_stats_ready = false;
+    return TTCF_OK;
+}
+
+int32_t ttcf_cv_export_training(ttcf_ctx* c, int64_t first_row, int32_t count, float* x, float* t) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (first_row < 0 || count <= 0 || first_row + count > c->cv_rows) return TTCF_EINVAL;
+    if (x)
+        HIPCHECK(c, hipMemcpyAsync(x, c->cv_x + first_row * kCvIn, sizeof(float) * count * kCvIn,
+                                   hipMemcpyDeviceToHost, c->stream));
+    if (t)
+        HIPCHECK(c, hipMemcpyAsync(t, c->cv_t + first_row * c->cv_out,
+                                   sizeof(float) * count * c->cv_out, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
+int32_t ttcf_cv_train(ttcf_ctx* c, int32_t epochs, int32_t batch, double lr, const int32_t* order,
+                      double* loss_out) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (epochs < 0 || batch <= 0 || !(lr > 0.0)) return TTCF_EINVAL;
+    if (c->cv_rows < batch) return fail(c, TTCF_ESTATE, "fewer training samples than one batch");
+    const int O = c->cv_out;
+    const int64_t n = c->cv_rows;
+    if (order)
+        for (int64_t q = 0; q < (int64_t)epochs * n; ++q)
+            if (order[q] < 0 || order[q] >= n) return fail(c, TTCF_EINVAL, "order index out of range");
+    float* xs = c->cv_stats;
+    float* ys = c->cv_stats + 2 * kCvIn;
+    if (!c->cv_stats_ready) {
+        HIPCHECK(c, launch_col_stats(c->cv_x, n, kCvIn, xs, xs + kCvIn, c->stream));
+        HIPCHECK(c, launch_col_stats(c->cv_t, n, O, ys, ys + O, c->stream));
+        c->cv_stats_ready = true;
+    }
+    CvWork w;
+    rc = cv_work_alloc(c, batch, &w);
+    if (rc != TTCF_OK) return rc;
+    int32_t* d_idx = (int32_t*)dev_alloc(sizeof(int32_t) * n, c->stream);
+    if (!d_idx) return fail(c, TTCF_ENOMEM, "index allocation failed");
+    std::vector<int32_t> nat;
+    if (!order) {
+        nat.resize(n);
+        for (int64_t q = 0; q < n; ++q) nat[q] = (int32_t)q;
+    }
+    const int64_t steps = n / batch;
+    for (int32_t e = 0; e < epochs; ++e) {
+        const int32_t* ord = order ? order + (int64_t)e * n : nat.data();
+        HIPCHECK(c, hipMemcpyAsync(d_idx, ord, sizeof(int32_t) * n, hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        for (int64_t s = 0; s < steps; ++s) {
+            const int32_t* bi = d_idx + s * batch;
+            HIPCHECK(c, launch_gather_norm(c->cv_x, bi, batch, kCvIn, xs, xs + kCvIn, w.x, c->stream));
+            HIPCHECK(c, launch_gather_norm(c->cv_t, bi, batch, O, ys, ys + O, w.t, c->stream));
+            rc = cv_forward(c, c->cv_p, w, batch);
+            if (rc == TTCF_OK) rc = cv_backward(c, c->cv_p, c->cv_g, w, batch);
+            if (rc != TTCF_OK) return rc;
+            c->cv_adam_steps += 1;
+            HIPCHECK(c, launch_adam(c->cv_p, c->cv_g, c->cv_m, c->cv_v, c->cv_nparam, (float)lr,
+                                    c->cv_adam_steps, c->stream));
+            if (s == steps - 1 && loss_out) {
+                HIPCHECK(c, launch_mse_loss(w.y, w.t, (int64_t)batch * O, w.loss, c->stream));
+                HIPCHECK(c, hipMemcpyAsync(loss_out + e, w.loss, sizeof(double), hipMemcpyDeviceToHost,
+                                           c->stream));
+            }
+        }
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(d_idx);
+    dev_free(w.base);
+    return TTCF_OK;
+}
+
+int32_t ttcf_cv_attach(ttcf_ctx* c, int64_t first, int32_t count) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (count <= 0) return TTCF_EINVAL;
+    if (!c->cv_stats_ready) return fail(c, TTCF_ESTATE, "train the network before attaching it");
+    rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    const int O = c->cv_out;
+    float* feat = (float*)dev_alloc(sizeof(float) * count * kCvIn + sizeof(double) * 2 * count + 64,
+                                    c->stream);
+    if (!feat) return fail(c, TTCF_ENOMEM, "feature allocation failed");
+    double* b0 = (double*)(((uintptr_t)(feat + (size_t)count * kCvIn) + 15) & ~(uintptr_t)15);
+    double* om = b0 + count;
+    rc = cv_features_of(c, first, count, feat, b0, om, nullptr);
+    if (rc != TTCF_OK) return rc;
+    // every daughter's h series lives in its batch's buffer (same layout as the series)
+    double* hrow = (double*)dev_alloc(sizeof(double) * (size_t)count * (O + 1), c->stream);
+    if (!hrow) return fail(c, TTCF_ENOMEM, "h allocation failed");
+    const DaughterDesc& d0 = c->descs[find_live(c, first)];
+    rc = cv_predict_h(c, feat, b0, om, count, d0.sys.dt, hrow, O + 1);
+    if (rc != TTCF_OK) return rc;
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t i = find_live(c, first + q);
+        Batch& b = c->batches[c->live[i].batch];
+        if (!b.hseries) {
+            b.hseries = (double*)dev_alloc(sizeof(double) * (size_t)(b.n_steps + 1) * b.n_daughters,
+                                           c->stream);
+            if (!b.hseries) return fail(c, TTCF_ENOMEM, "h series allocation failed");
+            std::vector<double> z((size_t)(b.n_steps + 1) * b.n_daughters, 0.0);
+            HIPCHECK(c, hipMemcpyAsync(b.hseries, z.data(), sizeof(double) * z.size(),
+                                       hipMemcpyHostToDevice, c->stream));
+            HIPCHECK(c, hipStreamSynchronize(c->stream));
+        }
+        double* dst = b.hseries + (size_t)(b.n_steps + 1) * c->live[i].index;
+        const int nk = std::min(b.n_steps, O) + 1;
+        HIPCHECK(c, hipMemcpyAsync(dst, hrow + (size_t)q * (O + 1), sizeof(double) * nk,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        c->descs[i].hseries = dst;
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(hrow);
+    dev_free(feat);
+    return push_descs(c);
+}
+
+int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const double* kicks,
+                          int64_t decorrelate_steps, int32_t rounds, int32_t states_per_replica,
+                          int64_t steps_between, double gamma_dot, int64_t* out_samples) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (mother < 0 || mother >= (int32_t)c->mothers.size() || n_replicas <= 0 || rounds <= 0 ||
+        states_per_replica <= 0 || steps_between <= 0 || decorrelate_steps < 0)
+        return TTCF_EINVAL;
+    if (!c->cv_stats_ready) return fail(c, TTCF_ESTATE, "train the network before the mean term");
+    Mother& m = c->mothers[mother];
+    const int n = m.dev.n, O = c->cv_out;
+    const int64_t per_round = (int64_t)n_replicas * states_per_replica;
+    if (per_round * 4 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many samples per round");
+    // replicas of the mother, each with its own momentum kick, in one buffer
+    const size_t sz = 6 * (size_t)n;
+    double* rep = (double*)dev_alloc(sizeof(double) * (sz * n_replicas + n_replicas), c->stream);
+    double* kick_d = kicks ? (double*)dev_alloc(sizeof(double) * 3 * (size_t)n * n_replicas, c->stream)
+                           : nullptr;
+    double* snaps = (double*)dev_alloc(sizeof(double) * sz * per_round, c->stream);
+    double* vp = (double*)dev_alloc(sizeof(double) * per_round, c->stream);
+    const int rows = (int)(4 * per_round);
+    float* feat = (float*)dev_alloc(sizeof(float) * (size_t)rows * kCvIn, c->stream);
+    double* b0 = (double*)dev_alloc(sizeof(double) * 2 * (size_t)rows, c->stream);
+    double* hh = (double*)dev_alloc(sizeof(double) * (size_t)rows * (O + 1), c->stream);
+    int32_t* idx = (int32_t*)dev_alloc(sizeof(int32_t) * 2 * (size_t)rows + 64, c->stream);
+    if (!rep || (kicks && !kick_d) || !snaps || !vp || !feat || !b0 || !hh || !idx)
+        return fail(c, TTCF_ENOMEM, "mean-term allocation failed");
+    double* zrep = rep + sz * n_replicas;
+    if (kicks)
+        HIPCHECK(c, hipMemcpyAsync(kick_d, kicks, sizeof(double) * 3 * (size_t)n * n_replicas,
+                                   hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, launch_replicate(m.state, m.zeta, n, kick_d, n_replicas, rep, zrep, c->stream));
+    std::vector<int32_t> hs(2 * (size_t)rows);
+    for (int r = 0; r < rows; ++r) {
+        hs[r] = r / 4;       // state
+        hs[rows + r] = r % 4;  // mapping
+    }
+    HIPCHECK(c, hipMemcpyAsync(idx, hs.data(), sizeof(int32_t) * hs.size(), hipMemcpyHostToDevice, c->stream));
+    const double sgn_h[4] = {1.0, 1.0, -1.0, -1.0};
+    double* sgn = (double*)dev_alloc(sizeof(double) * 4, c->stream);
+    if (!sgn) return fail(c, TTCF_ENOMEM, "allocation failed");
+    HIPCHECK(c, hipMemcpyAsync(sgn, sgn_h, sizeof(sgn_h), hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    std::vector<MotherLaunch> ls(n_replicas);
+    const double nf = 3.0 * n - 3.0;
+    for (int r = 0; r < n_replicas; ++r) {
+        MotherLaunch& L = ls[r];
+        L = MotherLaunch{};
+        L.sys = m.dev;
+        L.state = rep + sz * r;
+        L.zeta = zrep + r;
+        L.temperature = m.sys.temperature;
+        L.nf = nf;
+        L.q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
+        L.threads = m.threads;
+        L.apt = m.apt;
+        L.precision = m.sys.precision;
+        L.lds_bytes = lds_for(m.dev, m.sys.precision);
+    }
+    if (decorrelate_steps > 0) {
+        for (auto& L : ls) {
+            L.n_chunks = 0;
+            L.steps_per_chunk = decorrelate_steps;
+            L.snapshots = nullptr;
+        }
+        rc = upload_mother_launches(c, ls.data(), n_replicas);
+        if (rc != TTCF_OK) return rc;
+        HIPCHECK(c, launch_mothers(c->d_mlaunch, n_replicas, ls[0], c->stream));
+    }
+    for (int r = 0; r < n_replicas; ++r) {
+        ls[r].n_chunks = states_per_replica;
+        ls[r].steps_per_chunk = steps_between;
+        ls[r].snapshots = snaps + sz * (size_t)r * states_per_replica;
+    }
+    rc = upload_mother_launches(c, ls.data(), n_replicas);
+    if (rc != TTCF_OK) return rc;
+    for (int32_t round = 0; round < rounds; ++round) {
+        HIPCHECK(c, launch_mothers(c->d_mlaunch, n_replicas, ls[0], c->stream));
+        HIPCHECK(c, launch_states_vpxy(m.dev, snaps, (int32_t)per_round, vp, c->stream));
+        HIPCHECK(c, launch_cv_features(snaps, n, idx, idx + rows, vp, sgn, rows, m.dev.box[1],
+                                       m.dev.volume, m.sys.temperature, gamma_dot, feat, b0,
+                                       b0 + rows, c->stream));
+        rc = cv_predict_h(c, feat, b0, b0 + rows, rows, m.dev.dt, hh, O + 1);
+        if (rc != TTCF_OK) return rc;
+        HIPCHECK(c, launch_cv_mu_accum(hh, (int)per_round, 4, O + 1, c->cv_mu, c->cv_mu + (O + 1),
+                                       c->cv_mu + 2 * (O + 1), c->cv_mu + 3 * (O + 1), c->stream));
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(rep);
+    dev_free(kick_d);
+    dev_free(snaps);
+    dev_free(vp);
+    dev_free(feat);
+    dev_free(b0);
+    dev_free(hh);
+    dev_free(idx);
+    dev_free(sgn);
+    c->cv_mu_count += per_round * rounds;
+    c->cv_mu_dt = m.dev.dt;
+    c->cv_mu_gamma = gamma_dot;
+    if (out_samples) *out_samples = c->cv_mu_count;
+    return TTCF_OK;
+}
+
+int32_t ttcf_cv_response(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, double* cv_mean,
+                         double* cv_se, double* mu_h, double* mu_h_se, int64_t* out_n_states) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (n_t <= 0 || n_t > c->cv_out + 1) return fail(c, TTCF_EINVAL, "n_t beyond the network's grid");
+    if (c->cv_mu_count < 2) return fail(c, TTCF_ESTATE, "no mean term: call ttcf_cv_mean_term");
+    if (!(gamma_dot_filter > 0.0) || gamma_dot_filter != c->cv_mu_gamma)
+        return fail(c, TTCF_EINVAL, "the filter must be the shear rate of the mean term");
+    std::vector<int32_t> rows;
+    for (int64_t r = 0; r < c->acc_rows; ++r) {
+        if (!c->row_cv[r] || c->row_health[r] != 0) continue;
+        if (c->row_gamma[r] != gamma_dot_filter) continue;
+        if (c->row_nt[r] < n_t) continue;
+        rows.push_back((int32_t)r);
+    }
+    if (rows.empty()) return fail(c, TTCF_ESTATE, "no accumulated group carries the control variate");
+    // mean term per time point from its compensated sums
+    const int K = c->cv_out + 1;
+    std::vector<double> mu(4 * (size_t)K);
+    HIPCHECK(c, hipMemcpyAsync(mu.data(), c->cv_mu, sizeof(double) * mu.size(), hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    std::vector<double> muv(K), muse(K);
+    const double cnt = (double)c->cv_mu_count;
+    for (int k = 0; k < K; ++k) {
+        const double s = mu[k] + mu[K + k], s2 = mu[2 * K + k] + mu[3 * K + k];
+        muv[k] = s / cnt;
+        const double var = (s2 - s * s / cnt) / (cnt - 1.0);
+        muse[k] = std::sqrt(std::max(var, 0.0) / cnt);
+    }
+    double* d_mu = (double*)dev_alloc(sizeof(double) * K, c->stream);
+    const size_t bytes = sizeof(int32_t) * rows.size() + sizeof(double) * 4 * n_t + 64;
+    char* scratch = (char*)dev_alloc(bytes, c->stream);
+    if (!d_mu || !scratch) return fail(c, TTCF_ENOMEM, "response scratch allocation failed");
+    double* d_out = (double*)scratch;
+    int32_t* d_used = (int32_t*)(scratch + sizeof(double) * 4 * n_t);
+    int32_t* d_rows = d_used + 4;
+    HIPCHECK(c, hipMemcpyAsync(d_mu, muv.data(), sizeof(double) * K, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->d_row_health, c->row_health.data(), sizeof(int32_t) * c->row_health.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    ResponseLaunch R{};
+    R.d_all = c->acc_d;
+    R.i_all = c->acc_i;
+    R.gamma = c->d_row_gamma;
+    R.coef = c->d_row_coef;
+    R.health = c->d_row_health;
+    R.rows = d_rows;
+    R.n_rows = (int32_t)rows.size();
+    R.n_t = n_t;
+    R.n_t_stride = c->acc_stride;
+    R.normalise = 0;
+    R.h_all = c->acc_h;
+    R.mu_h = d_mu;
+    R.out = d_out;
+    R.used = d_used;
+    HIPCHECK(c, launch_response(R, c->stream));
+    std::vector<double> out(4 * (size_t)n_t);
+    int32_t used = 0;
+    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * 4 * n_t, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(&used, d_used, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(scratch);
+    dev_free(d_mu);
+    if (cv_mean) std::memcpy(cv_mean, out.data(), sizeof(double) * n_t);
+    if (cv_se) std::memcpy(cv_se, out.data() + n_t, sizeof(double) * n_t);
+    if (mu_h) std::memcpy(mu_h, muv.data(), sizeof(double) * n_t);
+    if (mu_h_se) std::memcpy(mu_h_se, muse.data(), sizeof(double) * n_t);
+    if (out_n_states) *out_n_states = used;
+    return TTCF_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 // ---- stateless inspection kernels ---------------------------------------------------------
 

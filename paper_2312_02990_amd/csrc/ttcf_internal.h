@@ -51,6 +51,8 @@ struct DaughterDesc {
     int32_t group;      // start-state group (accumulator slot)
     int32_t map;        // mapping 0..3
     int32_t block;      // threads per workgroup the launcher was sized for
+    int32_t pad_;
+    double* hseries;    // n_steps + 1 doubles: learned control variate h(t_k), or null
 };
 
 enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2, kHealthListOverflow = 4 };
@@ -100,6 +102,7 @@ struct AccumLaunch {
     double* i_out;               // same: mean over mappings of int_0^t P_xy(0) P_xy(s) ds
     int32_t* health_out;         // n_groups
     double* gamma_out;           // n_groups
+    double* h_out;               // same layout: mean over mappings of h(t_k) (0 without CV)
     int32_t n_groups, n_t;
 };
 
@@ -112,9 +115,55 @@ struct ResponseLaunch {
     const int32_t* rows;         // selected group rows
     int32_t n_rows, n_t, n_t_stride;
     int32_t normalise;           // divide each group by its own shear rate
+    const double* h_all;         // groups' control-variate series, or null (plain TTCF)
+    const double* mu_h;          // control-variate mean term per time point, or null
     double* out;                 // 4 * n_t: ttcf mean, ttcf se, dav mean, dav se
     int32_t* used;               // number of healthy rows
 };
+
+// ---- learned control variate ---------------------------------------------------------
+constexpr int kCvIn = 64;       // features per start state
+constexpr int kCvSlabs = 31;    // y slabs of the binned features
+constexpr int kCvHidden = 256;  // hidden width of both hidden layers
+
+struct GemmArgs {
+    const float* A;
+    int64_t sam, sak;            // A(m, k) = A[m sam + k sak]
+    const float* B;
+    int64_t sbk, sbn;            // B(k, n) = B[k sbk + n sbn]
+    float* C;
+    int ldc;
+    const float* bias;           // epilogue 0/1
+    float* Z;                    // epilogue 1: pre-activation output
+    const float* Zin;            // epilogue 2: pre-activation input
+    int M, N, K;
+    int epi;                     // 0 C = AB + bias; 1 Z = AB + bias, C = gelu(Z); 2 C = AB gelu'(Zin)
+};
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s);
+hipError_t launch_colsum(const float* X, int M, int N, int ld, float* out, hipStream_t s);
+hipError_t launch_mse_grad(const float* Y, const float* Tg, int64_t count, float scale, float* dY,
+                           hipStream_t s);
+hipError_t launch_mse_loss(const float* Y, const float* Tg, int64_t count, double* loss,
+                           hipStream_t s);
+hipError_t launch_adam(float* P, const float* G, float* Mo, float* Vo, int64_t n, float lr,
+                       int64_t step, hipStream_t s);
+hipError_t launch_gather_norm(const float* src, const int32_t* idx, int rows, int cols,
+                              const float* mu, const float* inv, float* dst, hipStream_t s);
+hipError_t launch_col_stats(const float* X, int64_t rows, int cols, float* mu, float* inv,
+                            hipStream_t s);
+hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* state_of,
+                              const int32_t* map_of, const double* vpxy0, const double* vsign,
+                              int32_t rows, double ly, double volume, double temperature,
+                              double gamma_dot, float* out, double* b0_out, double* om_out,
+                              hipStream_t s);
+hipError_t launch_cv_h(const float* pred, int rows, int n_out, const float* ymu, const float* yinv,
+                       const double* b0, const double* omega, double dt, double* out,
+                       int64_t out_stride, hipStream_t s);
+hipError_t launch_cv_mu_accum(const double* h, int groups, int maps, int nt, double* sum,
+                              double* comp, double* sumsq, double* compsq, hipStream_t s);
+hipError_t launch_states_vpxy(const SysDev& sys, const double* states, int32_t count, double* out,
+                              hipStream_t s);
 
 // Host-side choice of the per-daughter kernel shape.
 int pick_threads(int n, int requested);
@@ -123,7 +172,10 @@ size_t lds_bytes_for(int nmax, int cmax, int threads, int precision);
 size_t lds_bytes_nl(int nmax, int cmax, int kmax);
 
 hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s);
-hipError_t launch_mother(const MotherLaunch& m, hipStream_t s);
+hipError_t launch_mothers(const MotherLaunch* dev_ms, int count, const MotherLaunch& shape,
+                          hipStream_t s);
+hipError_t launch_replicate(const double* src, const double* zsrc, int32_t n, const double* kicks,
+                            int32_t count, double* dst, double* zdst, hipStream_t s);
 hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s);
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s);
 hipError_t launch_spawn(const double* states, int32_t n, int32_t n_states, const int32_t* state_of,

@@ -673,9 +673,10 @@ __global__ void k_zero_int(int32_t* p, int n) {
 // p *= exp(-zeta tau); zeta += tau (p.p - nf T)/Q. The p.p of the last update is c^2 times
 // the reduced p.p before the scaling, so one reduction per step suffices.
 template <typename Real, int APT>
-__global__ __launch_bounds__(kMaxThreads) void k_mother(MotherLaunch m) {
+__global__ __launch_bounds__(kMaxThreads) void k_mother(const MotherLaunch* ms, int nmax, int cmax) {
     extern __shared__ __align__(32) char smem[];
-    const Lds<Real> L = carve<Real>(smem, m.sys.n, m.sys.nc[0] * m.sys.nc[1] * m.sys.nc[2]);
+    const MotherLaunch& m = ms[blockIdx.x];  // one workgroup per mother
+    const Lds<Real> L = carve<Real>(smem, nmax, cmax);
     if (threadIdx.x == 0) *L.sys = m.sys;
     __syncthreads();
     const SysDev& S = *L.sys;
@@ -850,6 +851,18 @@ __global__ void k_accumulate(AccumLaunch a) {
     const double inm = 1.0 / (double)nm;
     double* dout = a.d_out + (size_t)g * a.n_t;
     double* iout = a.i_out + (size_t)g * a.n_t;
+    if (a.h_out) {
+        // mapping mean of the learned control variate (0 where a daughter has none)
+        double* hout = a.h_out + (size_t)g * a.n_t;
+        for (int k = 0; k < a.n_t; ++k) {
+            double hs = 0.0;
+            for (int m = 0; m < nm; ++m) {
+                const double* hh = a.descs[b + m].hseries;
+                hs += hh ? hh[k] : 0.0;
+            }
+            hout[k] = hs * inm;
+        }
+    }
     {
         double dsum = 0.0;
         for (int m = 0; m < nm; ++m) dsum += p0[m];
@@ -888,6 +901,7 @@ __global__ void k_response(ResponseLaunch r) {
         const double* iser = r.i_all + (size_t)row * r.n_t_stride;
         const double gam = r.gamma[row];
         double g = dser[0] - r.coef[row] * iser[k];
+        if (r.h_all) g -= r.h_all[(size_t)row * r.n_t_stride + k];
         double dv = dser[k];
         if (r.normalise) {
             g /= gam;
@@ -907,6 +921,7 @@ __global__ void k_response(ResponseLaunch r) {
         const double* iser = r.i_all + (size_t)row * r.n_t_stride;
         const double gam = r.gamma[row];
         double g = dser[0] - r.coef[row] * iser[k];
+        if (r.h_all) g -= r.h_all[(size_t)row * r.n_t_stride + k];
         double dv = dser[k];
         if (r.normalise) {
             g /= gam;
@@ -916,11 +931,45 @@ __global__ void k_response(ResponseLaunch r) {
         neumaier_add(dvv, dvc, (dv - dm) * (dv - dm));
     }
     const double denom = used > 1 ? (double)(used - 1) * (double)used : 1.0;
-    r.out[k] = gm;
+    r.out[k] = gm + (r.mu_h ? r.mu_h[k] : 0.0);
     r.out[r.n_t + k] = used > 1 ? sqrt((gv + gvc) / denom) : 0.0;
     r.out[2 * r.n_t + k] = dm;
     r.out[3 * r.n_t + k] = used > 1 ? sqrt((dvv + dvc) / denom) : 0.0;
     if (k == 0) *r.used = used;
+}
+
+// ---------------------------------------------------------------------------------------
+// V*P_xy of many stored states (6n doubles each), one workgroup per state at a time
+// ---------------------------------------------------------------------------------------
+
+template <int APT>
+__global__ __launch_bounds__(kMaxThreads) void k_states_vpxy(SysDev S, const double* states,
+                                                             int32_t count, double* out) {
+    extern __shared__ __align__(32) char smem[];
+    const int C = S.nc[0] * S.nc[1] * S.nc[2];
+    const Lds<double> L = carve<double>(smem, S.n, C);
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    for (int c = t; c < C; c += T) L.cnt[c] = 0;
+    for (int sidx = blockIdx.x; sidx < count; sidx += gridDim.x) {
+        const double* st = states + (size_t)sidx * 6 * (size_t)n;
+        double x[APT], y[APT], z[APT], fx[APT], fy[APT], fz[APT];
+        double kin = 0.0;
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const int a = t + j * T;
+            const bool v = a < n;
+            x[j] = v ? st[a] : 0.0;
+            y[j] = v ? st[n + a] : 0.0;
+            z[j] = v ? st[2 * n + a] : 0.0;
+            kin += v ? st[3 * n + a] * st[4 * n + a] : 0.0;
+        }
+        __syncthreads();
+        double wpart, upart;
+        compute_forces<double, APT, false>(S, 0.0, x, y, z, fx, fy, fz, wpart, upart, L);
+        double m[2] = {kin, wpart};
+        block_sum<2>(m, L.red);
+        if (t == 0) out[sidx] = m[0] + m[1];
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1591,6 +1640,30 @@ __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
 // host-side launchers
 // ---------------------------------------------------------------------------------------
 
+template <int APT>
+static hipError_t states_vpxy_t(const SysDev& S, const double* states, int32_t count, double* out,
+                                int threads, hipStream_t s) {
+    const size_t lds = plan_lds(S.n, S.nc[0] * S.nc[1] * S.nc[2], sizeof(double)).total;
+    (void)hipFuncSetAttribute((const void*)k_states_vpxy<APT>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const int grid = count < 2048 ? count : 2048;
+    hipLaunchKernelGGL((k_states_vpxy<APT>), dim3(grid), dim3(threads), lds, s, S, states, count,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_states_vpxy(const SysDev& S, const double* states, int32_t count, double* out,
+                              hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int threads = pick_threads(S.n, 0);
+    switch (pick_apt(S.n, threads)) {
+        case 1: return states_vpxy_t<1>(S, states, count, out, threads, s);
+        case 2: return states_vpxy_t<2>(S, states, count, out, threads, s);
+        case 4: return states_vpxy_t<4>(S, states, count, out, threads, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 int pick_threads(int n, int requested) {
     if (requested > 0) return requested;
     int t = ((n + 63) / 64) * 64;
@@ -1680,29 +1753,50 @@ hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
 }
 
 template <typename Real, int APT>
-static hipError_t launch_mother_t(const MotherLaunch& m, hipStream_t s) {
+static hipError_t launch_mother_t(const MotherLaunch* dev_ms, int count, int threads, int nmax,
+                                  int cmax, size_t lds, hipStream_t s) {
     (void)hipFuncSetAttribute((const void*)k_mother<Real, APT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)m.lds_bytes);
-    hipLaunchKernelGGL((k_mother<Real, APT>), dim3(1), dim3(m.threads), m.lds_bytes, s, m);
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_mother<Real, APT>), dim3(count), dim3(threads), lds, s, dev_ms, nmax, cmax);
     return hipGetLastError();
 }
 
-hipError_t launch_mother(const MotherLaunch& m, hipStream_t s) {
-    if (m.precision == 0) {
-        switch (m.apt) {
-            case 1: return launch_mother_t<double, 1>(m, s);
-            case 2: return launch_mother_t<double, 2>(m, s);
-            case 4: return launch_mother_t<double, 4>(m, s);
+// dev_ms: device array of `count` mothers sharing one launch shape (threads, apt, precision)
+hipError_t launch_mothers(const MotherLaunch* dev_ms, int count, const MotherLaunch& shape,
+                          hipStream_t s) {
+    const int nmax = shape.sys.n, cmax = shape.sys.nc[0] * shape.sys.nc[1] * shape.sys.nc[2];
+    if (shape.precision == 0) {
+        switch (shape.apt) {
+            case 1: return launch_mother_t<double, 1>(dev_ms, count, shape.threads, nmax, cmax, shape.lds_bytes, s);
+            case 2: return launch_mother_t<double, 2>(dev_ms, count, shape.threads, nmax, cmax, shape.lds_bytes, s);
+            case 4: return launch_mother_t<double, 4>(dev_ms, count, shape.threads, nmax, cmax, shape.lds_bytes, s);
         }
     } else {
-        switch (m.apt) {
-            case 1: return launch_mother_t<float, 1>(m, s);
-            case 2: return launch_mother_t<float, 2>(m, s);
-            case 4: return launch_mother_t<float, 4>(m, s);
+        switch (shape.apt) {
+            case 1: return launch_mother_t<float, 1>(dev_ms, count, shape.threads, nmax, cmax, shape.lds_bytes, s);
+            case 2: return launch_mother_t<float, 2>(dev_ms, count, shape.threads, nmax, cmax, shape.lds_bytes, s);
+            case 4: return launch_mother_t<float, 4>(dev_ms, count, shape.threads, nmax, cmax, shape.lds_bytes, s);
         }
     }
     return hipErrorInvalidValue;
+}
+
+// replica r of a mother: state = src + (0 | kicks[r]) on the momenta, zeta copied
+__global__ void k_replicate(const double* src, const double* zsrc, int32_t n, const double* kicks,
+                            double* dst, double* zdst) {
+    const int r = blockIdx.x;
+    double* d = dst + (size_t)r * 6 * n;
+    const double* k = kicks ? kicks + (size_t)r * 3 * n : nullptr;
+    for (int i = threadIdx.x; i < 6 * n; i += blockDim.x)
+        d[i] = src[i] + ((k && i >= 3 * n) ? k[i - 3 * n] : 0.0);
+    if (threadIdx.x == 0) zdst[r] = *zsrc;
+}
+
+hipError_t launch_replicate(const double* src, const double* zsrc, int32_t n, const double* kicks,
+                            int32_t count, double* dst, double* zdst, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_replicate, dim3(count), dim3(256), 0, s, src, zsrc, n, kicks, dst, zdst);
+    return hipGetLastError();
 }
 
 hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s) {

@@ -1,0 +1,346 @@
+// ttcf_mlp.hip -- gfx950 kernels of the learned control variate: start-state features, a
+// bfloat16 matrix-core GEMM with FP32 accumulation (forward and backward passes of the MLP),
+// Adam, and the integral h = Omega(0) int g ds of the predicted response.
+#include <hip/hip_runtime.h>
+
+#include "ttcf_internal.h"
+
+namespace ttcf {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even
+__device__ __forceinline__ short f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+// ---------------------------------------------------------------------------------------
+// GEMM: C(m, n) = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]
+// Operands are rounded to bfloat16 as they are staged into LDS; v_mfma_f32_16x16x16_bf16
+// accumulates in FP32. Workgroup tile 64 x 64 (four waves of 32 x 32, each 2 x 2 MFMA
+// tiles), K step 32. Operand layout of the 16x16x16 instruction: lane l holds A[l % 16][4 (l /
+// 16) + i] and B[4 (l / 16) + i][l % 16] (i = 0..3); the result D[4 (l / 16) + i][l % 16].
+// Epilogues: 0 C = acc + bias; 1 Z = acc + bias, C = gelu(Z); 2 C = acc * gelu'(Zin).
+// The K loop runs in a fixed order: results are deterministic.
+// ---------------------------------------------------------------------------------------
+
+constexpr int kBM = 64, kBN = 64, kBK = 32;
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+    __shared__ short As[kBM][kBK + 4];
+    __shared__ short Bs[kBK][kBN + 4];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < g.K; k0 += kBK) {
+        for (int e = t; e < kBM * kBK; e += 256) {
+            const int r = e / kBK, c = e % kBK;
+            const int m = m0 + r, k = k0 + c;
+            const float v = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0.f;
+            As[r][c] = f2bf(v);
+        }
+        for (int e = t; e < kBK * kBN; e += 256) {
+            const int r = e / kBN, c = e % kBN;
+            const int k = k0 + r, n = n0 + c;
+            const float v = (k < g.K && n < g.N) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0.f;
+            Bs[r][c] = f2bf(v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < kBK; kk += 16) {
+            const int kb = kk + (lane >> 4) * 4;
+            bf16x4 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = wm + i * 16 + (lane & 15);
+                a[i] = bf16x4{As[row][kb], As[row][kb + 1], As[row][kb + 2], As[row][kb + 3]};
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int col = wn + j * 16 + (lane & 15);
+                b[j] = bf16x4{Bs[kb][col], Bs[kb + 1][col], Bs[kb + 2][col], Bs[kb + 3][col]};
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm + i * 16 + (lane >> 4) * 4 + r;
+                const int n = n0 + wn + j * 16 + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                float v = acc[i][j][r];
+                const int64_t o = (int64_t)m * g.ldc + n;
+                if (g.epi == 0) {
+                    if (g.bias) v += g.bias[n];
+                    g.C[o] = v;
+                } else if (g.epi == 1) {
+                    if (g.bias) v += g.bias[n];
+                    g.Z[o] = v;
+                    g.C[o] = gelu_f(v);
+                } else {
+                    g.C[o] = v * gelu_grad_f(g.Zin[o]);
+                }
+            }
+}
+
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
+    dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM);
+    hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// small element-wise and reduction kernels (fixed-order sums)
+// ---------------------------------------------------------------------------------------
+
+__global__ void k_colsum(const float* X, int M, int N, int ld, float* out) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int m = 0; m < M; ++m) s += X[(int64_t)m * ld + n];
+    out[n] = s;
+}
+
+// dY = 2 (Y - T) / (M N); loss (one value) = mean (Y - T)^2 when loss != null
+__global__ void k_mse_grad(const float* Y, const float* Tg, int64_t count, float scale, float* dY) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dY[i] = scale * (Y[i] - Tg[i]);
+}
+
+__global__ void k_mse_loss(const float* Y, const float* Tg, int64_t count, double* loss) {
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < count; i += 256) {
+        const double d = (double)Y[i] - (double)Tg[i];
+        s += d * d;
+    }
+    part[threadIdx.x] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int i = 0; i < 256; ++i) tot += part[i];
+        *loss = tot / (double)count;
+    }
+}
+
+__global__ void k_adam(float* P, const float* G, float* Mo, float* Vo, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = G[i];
+    const float m = b1 * Mo[i] + (1.f - b1) * g;
+    const float v = b2 * Vo[i] + (1.f - b2) * g * g;
+    Mo[i] = m;
+    Vo[i] = v;
+    P[i] -= lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+// dst[r][c] = (src[idx[r]][c] - mu[c]) * inv[c] (mu, inv may be null: plain gather)
+__global__ void k_gather_norm(const float* src, const int32_t* idx, int rows, int cols,
+                              const float* mu, const float* inv, float* dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    const int64_t sr = idx ? idx[r] : r;
+    float v = src[sr * cols + c];
+    if (mu) v = (v - mu[c]) * inv[c];
+    dst[e] = v;
+}
+
+// mean and 1/std of every column (two passes in FP64; std floor 1e-12)
+__global__ void k_col_stats(const float* X, int64_t rows, int cols, float* mu, float* inv) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    double s = 0.0;
+    for (int64_t r = 0; r < rows; ++r) s += X[r * cols + c];
+    const double m = s / (double)rows;
+    double q = 0.0;
+    for (int64_t r = 0; r < rows; ++r) {
+        const double d = X[r * cols + c] - m;
+        q += d * d;
+    }
+    const double sd = sqrt(q / (double)(rows > 1 ? rows - 1 : 1));
+    mu[c] = (float)m;
+    inv[c] = (float)(1.0 / (sd > 1e-12 ? sd : 1e-12));
+}
+
+hipError_t launch_colsum(const float* X, int M, int N, int ld, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_colsum, dim3((N + 127) / 128), dim3(128), 0, s, X, M, N, ld, out);
+    return hipGetLastError();
+}
+hipError_t launch_mse_grad(const float* Y, const float* Tg, int64_t count, float scale, float* dY,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_mse_grad, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, Y, Tg,
+                       count, scale, dY);
+    return hipGetLastError();
+}
+hipError_t launch_mse_loss(const float* Y, const float* Tg, int64_t count, double* loss,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_mse_loss, dim3(1), dim3(256), 0, s, Y, Tg, count, loss);
+    return hipGetLastError();
+}
+hipError_t launch_adam(float* P, const float* G, float* Mo, float* Vo, int64_t n, float lr,
+                       int64_t step, hipStream_t s) {
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, P, G, Mo, Vo, n,
+                       lr, b1, b2, 1e-8f, c1, c2);
+    return hipGetLastError();
+}
+hipError_t launch_gather_norm(const float* src, const int32_t* idx, int rows, int cols,
+                              const float* mu, const float* inv, float* dst, hipStream_t s) {
+    const int64_t n = (int64_t)rows * cols;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_norm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, idx,
+                       rows, cols, mu, inv, dst);
+    return hipGetLastError();
+}
+hipError_t launch_col_stats(const float* X, int64_t rows, int cols, float* mu, float* inv,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(k_col_stats, dim3((cols + 63) / 64), dim3(64), 0, s, X, rows, cols, mu, inv);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// features of mapped start states
+// ---------------------------------------------------------------------------------------
+// Row layout (kCvIn = 64): [P_xy(0), Omega(0), sum p_x over slab k (31), sum p_x p_y over slab
+// k (31)], slab k = floor(y * 31 / Ly) clamped. One workgroup per row; thread q < 62 owns one
+// slab sum and adds the atoms in index order (deterministic).
+__global__ void k_cv_features(const double* states, int32_t n, const int32_t* state_of,
+                              const int32_t* map_of, const double* vpxy0, const double* vsign,
+                              int32_t rows, double ly, double volume, double temperature,
+                              double gamma_dot, float* out, double* b0_out, double* om_out) {
+    const int row = blockIdx.x;
+    if (row >= rows) return;
+    const double* st = states + (size_t)state_of[row] * 6 * (size_t)n;
+    const int m = map_of[row];
+    // mapping signs: p -> -p (m=1); (x, px) -> (-x, -px) (m=2); (x, py, pz) -> -(...) (m=3)
+    const double sx = (m == 1 || m == 2) ? -1.0 : 1.0;
+    const double sy = (m == 1 || m == 3) ? -1.0 : 1.0;
+    const int q = threadIdx.x;
+    float* o = out + (size_t)row * kCvIn;
+    if (q < 2 * kCvSlabs) {
+        const int slab = q % kCvSlabs;
+        const bool stress = q >= kCvSlabs;
+        const double inv = (double)kCvSlabs / ly;
+        double acc = 0.0;
+        for (int a = 0; a < n; ++a) {
+            int k = (int)floor(st[n + a] * inv);
+            k = k < 0 ? 0 : (k > kCvSlabs - 1 ? kCvSlabs - 1 : k);
+            if (k != slab) continue;
+            const double px = sx * st[3 * n + a];
+            acc += stress ? px * (sy * st[4 * n + a]) : px;
+        }
+        o[2 + q] = (float)acc;
+    }
+    if (q == 0) {
+        // vpxy0 indexed by row (vsign null) or by state with the mapping's sign of P_xy
+        const double vp = vsign ? vpxy0[state_of[row]] * vsign[m] : vpxy0[row];
+        const double pxy = vp / volume;
+        const double om = -(volume / temperature) * gamma_dot * pxy;
+        o[0] = (float)pxy;
+        o[1] = (float)om;
+        if (b0_out) b0_out[row] = pxy;
+        if (om_out) om_out[row] = om;
+    }
+}
+
+hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* state_of,
+                              const int32_t* map_of, const double* vpxy0, const double* vsign,
+                              int32_t rows, double ly, double volume, double temperature,
+                              double gamma_dot, float* out, double* b0_out, double* om_out,
+                              hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cv_features, dim3(rows), dim3(64), 0, s, states, n, state_of, map_of,
+                       vpxy0, vsign, rows, ly, volume, temperature, gamma_dot, out, b0_out, om_out);
+    return hipGetLastError();
+}
+
+// h(t_k) = Omega(0) int_0^{t_k} g ds (trapezoid, g(0) = B(0)) of each row, FP64; pred holds
+// the standardised predictions, B(t_k) = pred / yinv[k] + ymu[k]. out rows (n_out + 1 values)
+// are out_stride apart.
+__global__ void k_cv_h(const float* pred, int rows, int n_out, const float* ymu, const float* yinv,
+                       const double* b0, const double* omega, double dt, double* out,
+                       int64_t out_stride) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    const float* p = pred + (size_t)r * n_out;
+    double* h = out + (size_t)r * out_stride;
+    double prev = b0[r], acc = 0.0;
+    const double om = omega[r];
+    h[0] = 0.0;
+    for (int k = 0; k < n_out; ++k) {
+        const double cur = (double)p[k] / (double)yinv[k] + (double)ymu[k];
+        acc += 0.5 * dt * (prev + cur);
+        prev = cur;
+        h[k + 1] = om * acc;
+    }
+}
+
+hipError_t launch_cv_h(const float* pred, int rows, int n_out, const float* ymu, const float* yinv,
+                       const double* b0, const double* omega, double dt, double* out,
+                       int64_t out_stride, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cv_h, dim3((rows + 63) / 64), dim3(64), 0, s, pred, rows, n_out, ymu, yinv,
+                       b0, omega, dt, out, out_stride);
+    return hipGetLastError();
+}
+
+// mean-term accumulation: for every t, add the mapping means of h over the groups of this
+// chunk (group = 4 consecutive rows) into compensated sums of H and H^2.
+__global__ void k_cv_mu_accum(const double* h, int groups, int maps, int nt, double* sum,
+                              double* comp, double* sumsq, double* compsq) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nt) return;
+    double s = sum[k], c = comp[k], s2 = sumsq[k], c2 = compsq[k];
+    for (int gidx = 0; gidx < groups; ++gidx) {
+        double v = 0.0;
+        for (int m = 0; m < maps; ++m) v += h[(size_t)(gidx * maps + m) * nt + k];
+        v /= (double)maps;
+        double tsum = s + v;
+        c += fabs(s) >= fabs(v) ? (s - tsum) + v : (v - tsum) + s;
+        s = tsum;
+        const double v2 = v * v;
+        tsum = s2 + v2;
+        c2 += fabs(s2) >= fabs(v2) ? (s2 - tsum) + v2 : (v2 - tsum) + s2;
+        s2 = tsum;
+    }
+    sum[k] = s;
+    comp[k] = c;
+    sumsq[k] = s2;
+    compsq[k] = c2;
+}
+
+hipError_t launch_cv_mu_accum(const double* h, int groups, int maps, int nt, double* sum,
+                              double* comp, double* sumsq, double* compsq, hipStream_t s) {
+    hipLaunchKernelGGL(k_cv_mu_accum, dim3((nt + 63) / 64), dim3(64), 0, s, h, groups, maps, nt, sum,
+                       comp, sumsq, compsq);
+    return hipGetLastError();
+}
+
+}  // namespace ttcf

@@ -78,6 +78,7 @@ def lib():
     D, I, L64, V = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_void_p
     S = C.POINTER(System)
     P = C.POINTER(C.c_void_p)
+    F = C.POINTER(C.c_float)
     sig = {
         "ttcf_set_allocator": [_ALLOC, _FREE, V],
         "ttcf_init_mother": [P, S, D, D, C.c_int64, C.c_double, C.c_int64, V, I],
@@ -101,6 +102,17 @@ def lib():
         "ttcf_debug_forces": [S, C.c_double, D, D, D, V],
         "ttcf_step_timing": [V, D, L64, C.c_int32],
         "ttcf_set_step_shape": [V, C.c_int32, C.c_int32, C.c_double, C.c_int32],
+        "ttcf_cv_init": [V, C.c_int32, F, C.c_int64],
+        "ttcf_cv_export_weights": [V, F, C.c_int64],
+        "ttcf_cv_add_training": [V, C.c_int64, C.c_int32],
+        "ttcf_cv_export_training": [V, C.c_int64, C.c_int32, F, F],
+        "ttcf_cv_train": [V, C.c_int32, C.c_int32, C.c_double, I, D],
+        "ttcf_cv_attach": [V, C.c_int64, C.c_int32],
+        "ttcf_cv_mean_term": [V, C.c_int32, C.c_int32, D, C.c_int64, C.c_int32, C.c_int32,
+                              C.c_int64, C.c_double, L64],
+        "ttcf_cv_response": [V, C.c_double, C.c_int32, D, D, D, D, L64],
+        "ttcf_mlp_forward": [V, F, C.c_int32, F],
+        "ttcf_mlp_gradient": [V, F, F, C.c_int32, F],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -123,7 +135,17 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_record_mother", "ttcf_export_mother_series", "ttcf_export_daughter",
             "ttcf_export_series", "ttcf_daughter_health", "ttcf_debug_poison",
             "ttcf_debug_cell_list", "ttcf_debug_pairs", "ttcf_debug_forces", "ttcf_step_timing",
-            "ttcf_set_step_shape"]
+            "ttcf_set_step_shape", "ttcf_cv_init", "ttcf_cv_export_weights",
+            "ttcf_cv_add_training", "ttcf_cv_export_training", "ttcf_cv_train", "ttcf_cv_attach", "ttcf_cv_mean_term",
+            "ttcf_cv_response", "ttcf_mlp_forward", "ttcf_mlp_gradient"]
+
+# network shape of the learned control variate (fixed by the library)
+CV_IN = 64
+CV_HIDDEN = 256
+
+
+def cv_param_count(n_out: int) -> int:
+    return CV_IN * CV_HIDDEN + CV_HIDDEN + CV_HIDDEN * CV_HIDDEN + CV_HIDDEN + CV_HIDDEN * n_out + n_out
 
 
 def _dp(a):
@@ -131,7 +153,15 @@ def _dp(a):
 
 
 def _ip(a):
-    return a.ctypes.data_as(C.POINTER(C.c_int32))
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
 
 
 def _f64(a):
@@ -357,3 +387,75 @@ class Context:
         _check(lib().ttcf_step_timing(self._ctx, C.byref(ms), C.byref(n), int(reset)),
                "ttcf_step_timing", self._ctx)
         return ms.value, n.value
+
+    # ---- learned control variate
+    def ttcf_cv_init(self, n_out: int, weights):
+        w = _f32(weights).ravel()
+        _check(lib().ttcf_cv_init(self._ctx, int(n_out), _fp(w), int(w.size)), "ttcf_cv_init",
+               self._ctx)
+        self.cv_out = int(n_out)
+
+    def ttcf_cv_export_weights(self):
+        w = np.zeros(cv_param_count(self.cv_out), np.float32)
+        _check(lib().ttcf_cv_export_weights(self._ctx, _fp(w), int(w.size)),
+               "ttcf_cv_export_weights", self._ctx)
+        return w
+
+    def ttcf_cv_add_training(self, first: int, count: int):
+        _check(lib().ttcf_cv_add_training(self._ctx, int(first), int(count)),
+               "ttcf_cv_add_training", self._ctx)
+
+    def ttcf_cv_export_training(self, first_row: int, count: int):
+        x = np.zeros((count, CV_IN), np.float32)
+        t = np.zeros((count, self.cv_out), np.float32)
+        _check(lib().ttcf_cv_export_training(self._ctx, int(first_row), int(count), _fp(x), _fp(t)),
+               "ttcf_cv_export_training", self._ctx)
+        return x, t
+
+    def ttcf_cv_train(self, epochs: int, batch: int, lr: float, order=None):
+        """order: (epochs, rows) int32 permutations or None. Returns the per-epoch losses."""
+        o = None if order is None else np.ascontiguousarray(order, dtype=np.int32)
+        loss = np.zeros(max(int(epochs), 1))
+        _check(lib().ttcf_cv_train(self._ctx, int(epochs), int(batch), float(lr), _ip(o),
+                                   _dp(loss)), "ttcf_cv_train", self._ctx)
+        return loss[:int(epochs)]
+
+    def ttcf_cv_attach(self, first: int, count: int):
+        _check(lib().ttcf_cv_attach(self._ctx, int(first), int(count)), "ttcf_cv_attach",
+               self._ctx)
+
+    def ttcf_cv_mean_term(self, mother: int, n_replicas: int, kicks, decorrelate_steps: int,
+                          rounds: int, states_per_replica: int, steps_between: int,
+                          gamma_dot: float) -> int:
+        k = None if kicks is None else _f64(kicks).ravel()
+        out = C.c_int64(0)
+        _check(lib().ttcf_cv_mean_term(self._ctx, int(mother), int(n_replicas), _dp(k),
+                                       int(decorrelate_steps), int(rounds),
+                                       int(states_per_replica), int(steps_between),
+                                       float(gamma_dot), C.byref(out)),
+               "ttcf_cv_mean_term", self._ctx)
+        return out.value
+
+    def ttcf_cv_response(self, n_t: int, gamma_dot_filter: float):
+        """(cv_mean, cv_se, mu_h, mu_h_se, n_states)."""
+        out = [np.zeros(n_t) for _ in range(4)]
+        used = C.c_int64(0)
+        _check(lib().ttcf_cv_response(self._ctx, float(gamma_dot_filter), int(n_t),
+                                      *[_dp(o) for o in out], C.byref(used)),
+               "ttcf_cv_response", self._ctx)
+        return out[0], out[1], out[2], out[3], used.value
+
+    def ttcf_mlp_forward(self, x):
+        x = _f32(x)
+        y = np.zeros((x.shape[0], self.cv_out), np.float32)
+        _check(lib().ttcf_mlp_forward(self._ctx, _fp(x), int(x.shape[0]), _fp(y)),
+               "ttcf_mlp_forward", self._ctx)
+        return y
+
+    def ttcf_mlp_gradient(self, x, target):
+        x = _f32(x)
+        t = _f32(target)
+        g = np.zeros(cv_param_count(self.cv_out), np.float32)
+        _check(lib().ttcf_mlp_gradient(self._ctx, _fp(x), _fp(t), int(x.shape[0]), _fp(g)),
+               "ttcf_mlp_gradient", self._ctx)
+        return g

@@ -1,13 +1,14 @@
 """GPU-vs-oracle parity through the C ABI (runs on an MI355X).
 
 Inputs are seeded (ttcf_inputs) or produced by the FP64 oracle; nothing the GPU computes is
-fed back into the oracle. Bars:
+fed into the oracle. Bars:
   * cell lists and neighbour pairs: bit-exact on identical FP64 positions;
   * forces: max_i |dF_i| / rms_i |F_i| <= 1e-12 (FP64 form), <= 1e-5 (FP32 form);
   * trajectories over 50 steps: max |dr|/L and max |dp|/rms(p) <= 1e-4 (FP32 forms),
     <= 1e-9 (FP64 form);
-  * accumulate/response kernels: equal (1e-12 relative) to the oracle's estimator applied to
-    the same per-daughter series; TTCF within 2 standard errors of the oracle's TTCF.
+  * accumulate/response kernels with FP64 forces: the oracle's own daughters through its own
+    estimator agree to 1e-7 of the per-state series' scale (the trajectories agree to ~1e-9);
+    with FP32 forces, TTCF and direct average within 2 combined standard errors.
 """
 import sys
 
@@ -262,25 +263,43 @@ def test_config1_ttcf_matches_oracle(T, orc, cfg1, precision):
         first = ctx.ttcf_spawn_daughters(mid, 8, 0, gd, nst)
         ctx.ttcf_step(40)
         ctx.ttcf_step(100)  # continues to each daughter's own length
-        ser = ctx.ttcf_export_series(first, 32, nst + 1)
         assert ctx.ttcf_accumulate() == 8
         tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, gd)
     assert used == 8
-    # the accumulate/response kernels reproduce the oracle's estimator on the same series
-    ref = orc.ttcf_response(ser / s.volume, ser[:, 0], np.full(32, gd), s.temperature, s.dt)
-    np.testing.assert_allclose(tm, ref.ttcf, rtol=1e-12, atol=1e-15)
-    np.testing.assert_allclose(tse, ref.ttcf_se, rtol=1e-9, atol=1e-15)
-    np.testing.assert_allclose(dm, ref.dav, rtol=1e-12, atol=1e-15)
-    np.testing.assert_allclose(dse, ref.dav_se, rtol=1e-9, atol=1e-15)
-    # and the whole path agrees with the oracle's own daughters within 2 SE
+    # the oracle's own daughters from the same start states, through its own estimator
     state_of = np.repeat(np.arange(8), 4)
     map_of = np.tile(np.arange(4), 8)
     vo, _ = orc.run_daughters(box, sr, sp, state_of, map_of, np.full(32, gd), s.dt, nst,
                               nthreads=8)
     oref = orc.ttcf_response(vo / s.volume, vo[:, 0], np.full(32, gd), s.temperature, s.dt)
+    if precision == 0:
+        # FP64 forces: the trajectories agree to ~1e-9 of their spread over 100 steps, so the
+        # estimates agree to that accuracy (relative to the spread of the per-state series)
+        for got, ref, per in ((tm, oref.ttcf, oref.g), (dm, oref.dav, oref.d)):
+            assert np.abs(got - ref).max() <= 1e-7 * np.abs(per).max()
+        np.testing.assert_allclose(tse, oref.ttcf_se, rtol=1e-6, atol=1e-7 * np.abs(oref.g).max())
+        np.testing.assert_allclose(dse, oref.dav_se, rtol=1e-6, atol=1e-7 * np.abs(oref.d).max())
+    # both forms: within 2 combined standard errors at every time point
     comb = np.hypot(tse, oref.ttcf_se)
     assert np.all(np.abs(tm - oref.ttcf)[1:] <= 2.0 * comb[1:])
     assert np.all(np.abs(dm - oref.dav) <= 2.0 * np.hypot(dse, oref.dav_se) + 1e-15)
+
+
+def oracle_group_response(orc, s, box, sr, sp, states, gd, nst):
+    """The oracle's own four mapped daughters of each listed start state, through its
+    estimator."""
+    states = np.asarray(states)
+    state_of = np.repeat(states, 4)
+    map_of = np.tile(np.arange(4), len(states))
+    vo, _ = orc.run_daughters(box, sr, sp, state_of, map_of, np.full(len(state_of), gd), s.dt,
+                              nst, nthreads=8)
+    return orc.ttcf_response(vo / s.volume, vo[:, 0], np.full(len(state_of), gd),
+                             s.temperature, s.dt)
+
+
+def close_to(got, ref, per, rel=1e-7):
+    """FP64 forces against the oracle: agreement to rel of the per-state series' scale."""
+    assert np.abs(got - ref).max() <= rel * np.abs(per).max()
 
 
 def test_response_filters_and_normalisation(T, orc, cfg1):
@@ -288,13 +307,11 @@ def test_response_filters_and_normalisation(T, orc, cfg1):
     nst = 30
     say("response filters")
     with T.Context() as ctx:
-        mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+        mid = ctx.ttcf_init_mother(gsys(T, s, 0), sr[0], sp[0], n_equil=0)
         ctx.ttcf_import_states(mid, sr, sp)
-        f1 = ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-2, nst)
-        f2 = ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-4, nst)
+        ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-2, nst)
+        ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-4, nst)
         ctx.ttcf_step(nst)
-        s1 = ctx.ttcf_export_series(f1, 32, nst + 1)
-        s2 = ctx.ttcf_export_series(f2, 32, nst + 1)
         assert ctx.ttcf_accumulate() == 16
         a = ctx.ttcf_response(nst + 1, 1e-2)
         b = ctx.ttcf_response(nst + 1, 1e-4)
@@ -303,14 +320,14 @@ def test_response_filters_and_normalisation(T, orc, cfg1):
             ctx.ttcf_response(nst + 1, 3e-3)
         with pytest.raises(T.TTCFError):
             ctx.ttcf_response(nst + 2, 1e-2)
-    ra = orc.ttcf_response(s1 / s.volume, s1[:, 0], np.full(32, 1e-2), s.temperature, s.dt)
-    rb = orc.ttcf_response(s2 / s.volume, s2[:, 0], np.full(32, 1e-4), s.temperature, s.dt)
-    np.testing.assert_allclose(a[0], ra.ttcf, rtol=1e-12, atol=1e-16)
-    np.testing.assert_allclose(b[0], rb.ttcf, rtol=1e-12, atol=1e-16)
+    ra = oracle_group_response(orc, s, box, sr, sp, range(8), 1e-2, nst)
+    rb = oracle_group_response(orc, s, box, sr, sp, range(8), 1e-4, nst)
+    close_to(a[0], ra.ttcf, ra.g)
+    close_to(b[0], rb.ttcf, rb.g)
+    assert a[4] == 8 and b[4] == 8
     # per-unit-rate response over both batches: mean of the 16 normalised groups
     g = np.concatenate([ra.g / 1e-2, rb.g / 1e-4])
-    # t = 0 is a cancellation residue (the four mapped P_xy(0) sum to ~0): absolute bar there
-    np.testing.assert_allclose(c[0], g.mean(axis=0), rtol=1e-10, atol=1e-12 * np.abs(g).max())
+    close_to(c[0], g.mean(axis=0), g)
     assert c[4] == 16
 
 
@@ -319,7 +336,7 @@ def test_health_check_excludes_whole_group(T, orc, cfg1):
     nst = 20
     say("health / failure injection")
     with T.Context() as ctx:
-        mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+        mid = ctx.ttcf_init_mother(gsys(T, s, 0), sr[0], sp[0], n_equil=0)
         ctx.ttcf_import_states(mid, sr, sp)
         first = ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-3, nst)
         ctx.ttcf_step(5)
@@ -327,14 +344,12 @@ def test_health_check_excludes_whole_group(T, orc, cfg1):
         ctx.ttcf_step(nst)
         assert ctx.ttcf_daughter_health(first + 13) != 0
         assert ctx.ttcf_daughter_health(first + 12) == 0
-        ser = ctx.ttcf_export_series(first, 32, nst + 1)
         assert ctx.ttcf_accumulate() == 7
         tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, 1e-3)
     assert used == 7
-    keep = np.array([d for d in range(32) if d // 4 != 3])
-    ref = orc.ttcf_response(ser[keep] / s.volume, ser[keep, 0], np.full(28, 1e-3),
-                            s.temperature, s.dt)
-    np.testing.assert_allclose(tm, ref.ttcf, rtol=1e-12, atol=1e-16)
+    ref = oracle_group_response(orc, s, box, sr, sp, [0, 1, 2, 4, 5, 6, 7], 1e-3, nst)
+    close_to(tm, ref.ttcf, ref.g)
+    close_to(dm, ref.dav, ref.d)
 
 
 def test_uneven_batch_is_invariant_and_deterministic(T, orc, cfg1):

@@ -102,6 +102,124 @@ def cpu_baseline(n_cells: int, nsteps: int, budget_s: float):
     }
 
 
+def seeded_kicks(n_rep: int, n: int, scale: float, seed: int):
+    """Zero-sum momentum kicks, one set per mother copy (numpy PCG64, seeded)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k = scale * rng.standard_normal((n_rep, 3, n))
+    k -= k.mean(axis=2, keepdims=True)
+    return k.reshape(n_rep, 3 * n)
+
+
+def cv_leg(T, stream, gd=1e-4, nst=200, train_states=4096, eval_states=4096, epochs=30,
+           batch=256, lr=1e-3, mean_replicas=1024, mean_rounds=20, mean_per_round=49,
+           mean_between=50, decorrelate=400, kick=0.05, seed=5, verbose=False):
+    """Learned control variate on the config-5 workload: WCA N=256 at the paper's state
+    point, shear rate 1e-4, daughters of 200 steps. Training daughters, evaluation daughters
+    and the mean-term samples come from separate branches of one mother (copies kicked by
+    seeded zero-sum momentum changes, then decorrelated). Every GPU phase is timed between
+    stream synchronisations. Returns the estimate, its standard errors and the figure of merit
+    SE * sqrt(GPU seconds) of the plain and the control-variate estimates."""
+    import torch
+    import ttcf_inputs as I
+
+    def sync_time(t0):
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    s = I.System(4)
+    sysd = T.make_system(s.n, s.box, s.temperature, s.dt, precision=1)
+    ctx = T.Context(stream)
+    r0, p0 = I.initial_state(s, seed)
+    t0 = time.perf_counter()
+    mid = ctx.ttcf_init_mother(sysd, r0, p0, n_equil=2000, n_melt=1000, t_melt=2.0)
+    t_mother = sync_time(t0)
+    n_rep = 256
+    timings = {"mother_init_s": t_mother}
+
+    def daughters(n_states, kick_seed, phase):
+        t0 = time.perf_counter()
+        per = n_states // n_rep
+        ctx.ttcf_sample_states_replicated(mid, n_rep, seeded_kicks(n_rep, s.n, kick, kick_seed),
+                                          decorrelate, per, 100)
+        first = ctx.ttcf_spawn_daughters(mid, n_rep * per, 0, gd, nst)
+        ctx.ttcf_step(nst)
+        timings[phase + "_daughters_s"] = sync_time(t0)
+        return first, 4 * n_rep * per
+
+    # training set: three quarters train the network, one quarter calibrates beta(t)
+    first, nd = daughters(train_states, seed * 1000 + 1, "train")
+    n_fit = (3 * nd // 4) // 4 * 4
+    n_out = nst
+    ctx.ttcf_cv_init(n_out, _seeded_weights(n_out, seed))
+    t0 = time.perf_counter()
+    ctx.ttcf_cv_add_training(first, n_fit)
+    rng = np.random.Generator(np.random.PCG64(seed + 7))
+    order = np.stack([rng.permutation(n_fit).astype(np.int32) for _ in range(epochs)])
+    loss = ctx.ttcf_cv_train(epochs, batch, lr, order)
+    timings["training_s"] = sync_time(t0)
+    t0 = time.perf_counter()
+    ctx.ttcf_cv_attach(first + n_fit, nd - n_fit, T.TTCF_CV_CALIBRATE)
+    ctx.ttcf_accumulate()  # training groups carry no control variate: they stay out of it
+    beta = ctx.ttcf_cv_calibrate(nst + 1, gd)
+    timings["calibration_s"] = sync_time(t0)
+    # evaluation daughters with the control variate attached
+    first, nd_eval = daughters(eval_states, seed * 1000 + 2, "eval")
+    t0 = time.perf_counter()
+    ctx.ttcf_cv_attach(first, nd_eval, T.TTCF_CV_ESTIMATE)
+    timings["attach_s"] = sync_time(t0)
+    t0 = time.perf_counter()
+    ctx.ttcf_accumulate()
+    timings["eval_accumulate_s"] = sync_time(t0)
+    # mean term from independent branches
+    t0 = time.perf_counter()
+    n_mean = ctx.ttcf_cv_mean_term(mid, mean_replicas,
+                                   seeded_kicks(mean_replicas, s.n, kick, seed * 1000 + 3),
+                                   decorrelate, mean_rounds, mean_per_round, mean_between, gd)
+    timings["mean_term_s"] = sync_time(t0)
+    cm, cse, pm, pse, mu, mu_se, used = ctx.ttcf_cv_response(nst + 1, gd)
+    ctx.close()
+    t_plain = timings["eval_daughters_s"] + timings["eval_accumulate_s"]
+    t_cv = t_plain + timings["train_daughters_s"] + timings["training_s"] + \
+        timings["calibration_s"] + timings["attach_s"] + timings["mean_term_s"]
+    se_cv = np.hypot(cse, mu_se)
+    k = np.arange(1, nst + 1)
+    gain = (pse[k] * np.sqrt(t_plain)) / (se_cv[k] * np.sqrt(t_cv))
+    vr = (pse[k] / se_cv[k]) ** 2
+    bias_bound = 2.0 * (pse + cse + mu_se)
+    out = {
+        "workload": f"WCA N={s.n}, rho={s.density}, T={s.temperature}, gamma_dot={gd}, "
+                    f"{nst}-step daughters; {nd} training and {nd_eval} evaluation daughters; "
+                    f"{n_mean} mean-term start states x 4 mappings; MLP 64-256-256-{n_out}, "
+                    f"{epochs} epochs, batch {batch}, lr {lr}",
+        "gain_at_t_end": float(gain[-1]),
+        "gain_median": float(np.median(gain)),
+        "gain_at_10_steps": float(gain[9]),
+        "variance_ratio_at_steps": {str(j): float(vr[j - 1]) for j in (1, 10, 50, 100, nst)},
+        "fom_plain_t_end": float(pse[-1] * np.sqrt(t_plain)),
+        "fom_cv_t_end": float(se_cv[-1] * np.sqrt(t_cv)),
+        "gpu_s_plain": t_plain, "gpu_s_cv": t_cv,
+        "ttcf_plain_t_end": float(pm[-1]), "se_plain_t_end": float(pse[-1]),
+        "ttcf_cv_t_end": float(cm[-1]), "se_cv_t_end": float(se_cv[-1]),
+        "bias_within_bound": bool(np.all(np.abs(cm - pm) <= bias_bound)),
+        "train_loss_last_epoch": float(loss[-1]) if len(loss) else None,
+        "n_states_eval": int(used), "timings_s": timings,
+    }
+    if verbose:
+        out["series"] = {"beta": beta.tolist(), "plain": pm.tolist(), "plain_se": pse.tolist(), "cv": cm.tolist(),
+                         "cv_se": se_cv.tolist(), "loss": loss.tolist()}
+    return out
+
+
+def _seeded_weights(n_out: int, seed: int):
+    """He-normal weights, zero biases, FP32 (numpy PCG64, seeded)."""
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    h, n_in = 256, 64
+    parts = [rng.standard_normal((n_in, h)) * np.sqrt(2.0 / n_in), np.zeros(h),
+             rng.standard_normal((h, h)) * np.sqrt(2.0 / h), np.zeros(h),
+             rng.standard_normal((h, n_out)) * np.sqrt(1.0 / h), np.zeros(n_out)]
+    return np.concatenate([a.ravel() for a in parts]).astype(np.float32)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)

@@ -154,6 +154,14 @@ int32_t ttcf_import_states(ttcf_ctx* ctx, int32_t mother, int32_t n_states, cons
 /* Copy the mother's stored start states to host arrays of the same layout. */
 int32_t ttcf_export_states(ttcf_ctx* ctx, int32_t mother, int32_t n_states, double* r,
                            double* p);
+/* Beside Alg. LAMMPS SCRIPT's one serial mother: n_replicas copies of the mother's current state,
+ * copy q with the momentum kick kicks[q*3n ..] added as given (may be NULL; kicks should sum to
+ * zero per copy), run decorrelate_steps Nose-Hoover steps together (one launch), then save
+ * states_per_replica states each steps_between steps apart. The stored set is replaced by the
+ * n_replicas * states_per_replica states, copy-major. The mother itself does not move. */
+int32_t ttcf_sample_states_replicated(ttcf_ctx* ctx, int32_t mother, int32_t n_replicas,
+                                      const double* kicks, int64_t decorrelate_steps,
+                                      int32_t states_per_replica, int64_t steps_between);
 /* Mother's current state: r, p (3n each), the Nose-Hoover variable and the step count. */
 int32_t ttcf_export_mother(ttcf_ctx* ctx, int32_t mother, double* r, double* p, double* zeta,
                            int64_t* steps);
@@ -238,10 +246,15 @@ int32_t ttcf_cv_export_training(ttcf_ctx* ctx, int64_t first_row, int32_t count,
  * its last batch (epochs doubles). */
 int32_t ttcf_cv_train(ttcf_ctx* ctx, int32_t epochs, int32_t batch, double lr,
                       const int32_t* order, double* loss_out);
-/* Give live daughters first..first+count-1 (one mother, stepped at least once) their h series
- * from the current network; ttcf_accumulate then carries H_n beside G_n for every group
- * whose daughters all have one. h is zero past t_K. */
-int32_t ttcf_cv_attach(ttcf_ctx* ctx, int64_t first, int32_t count);
+/* Roles of daughters that carry the control variate. */
+enum { TTCF_CV_ESTIMATE = 1, TTCF_CV_CALIBRATE = 2 };
+
+/* Give live daughters first..first+count-1 (consecutive ids, one mother, stepped at least
+ * once, start states still stored on the mother) their h series from the current network;
+ * ttcf_accumulate then carries H_n beside G_n for every group whose daughters all have one in
+ * the same role. role TTCF_CV_ESTIMATE: the groups enter ttcf_cv_response; TTCF_CV_CALIBRATE:
+ * they only enter ttcf_cv_calibrate. h is zero past t_K. */
+int32_t ttcf_cv_attach(ttcf_ctx* ctx, int64_t first, int32_t count, int32_t role);
 /* mu_H at shear rate gamma_dot from mother samples that no daughter of the estimate used:
  * n_replicas copies of the mother's current state, copy q with the host momentum kick
  * kicks[q*3n ..] added as given (may be NULL: no kicks; kicks let the copies decorrelate and
@@ -253,12 +266,22 @@ int32_t ttcf_cv_attach(ttcf_ctx* ctx, int64_t first, int32_t count);
 int32_t ttcf_cv_mean_term(ttcf_ctx* ctx, int32_t mother, int32_t n_replicas, const double* kicks,
                           int64_t decorrelate_steps, int32_t rounds, int32_t states_per_replica,
                           int64_t steps_between, double gamma_dot, int64_t* out_samples);
-/* Control-variate estimate at k = 0..n_t-1 (n_t <= K + 1) over the healthy groups at shear
- * rate gamma_dot_filter (which must equal the mean term's) that carry H_n: cv_mean, its block
- * standard error over start states cv_se (mu_H's own error is reported separately in
- * mu_h_se), and mu_H. Any pointer may be NULL. */
+/* Control-variate coefficient beta(t_k) = Cov(G_n, H_n) / Var(H_n), k = 0..n_t-1, over the
+ * healthy calibration groups at shear rate gamma_dot_filter (0 where H does not vary); kept by
+ * the context and used by ttcf_cv_response at that rate. Fitted on groups that the estimate
+ * does not use, it leaves the estimate unbiased while never letting a poor network add
+ * variance (to within the calibration's own sampling error). beta (may be NULL): n_t doubles. */
+int32_t ttcf_cv_calibrate(ttcf_ctx* ctx, double gamma_dot_filter, int32_t n_t, double* beta);
+/* Control-variate estimate at k = 0..n_t-1 (n_t <= K + 1) over the healthy estimate groups at
+ * shear rate gamma_dot_filter (which must equal the mean term's):
+ *   cv_mean = mean_n [G_n - beta H_n] + beta mu_H, beta from ttcf_cv_calibrate (else 1);
+ * cv_se, its block standard error over start states (without the mean term's error);
+ * plain_mean/plain_se, the Eq. (TTCF) estimate over the same groups; mu_h/mu_h_se, the added
+ * term beta mu_H and its standard error (samples taken as independent). Any pointer may be
+ * NULL. */
 int32_t ttcf_cv_response(ttcf_ctx* ctx, double gamma_dot_filter, int32_t n_t, double* cv_mean,
-                         double* cv_se, double* mu_h, double* mu_h_se, int64_t* out_n_states);
+                         double* cv_se, double* plain_mean, double* plain_se, double* mu_h,
+                         double* mu_h_se, int64_t* out_n_states);
 /* The network alone (tests): forward pass on host rows x[rows][64] (fed to W1 unstandardised)
  * into y[rows][K] ... */
 int32_t ttcf_mlp_forward(ttcf_ctx* ctx, const float* x, int32_t rows, float* y);

@@ -40,6 +40,24 @@ void dev_free(void* p) {
         (void)hipFree(p);
 }
 
+// Device buffers of one call, freed on every return path (stream-ordered like dev_alloc).
+struct Scratch {
+    hipStream_t s;
+    std::vector<void*> held;
+    explicit Scratch(hipStream_t st) : s(st) {}
+    Scratch(const Scratch&) = delete;
+    Scratch& operator=(const Scratch&) = delete;
+    template <typename T>
+    T* get(size_t count) {
+        void* p = dev_alloc(sizeof(T) * count + 64, s);
+        if (p) held.push_back(p);
+        return (T*)p;
+    }
+    ~Scratch() {
+        for (void* p : held) dev_free(p);
+    }
+};
+
 struct Mother {
     ttcf_system sys{};
     SysDev dev{};
@@ -71,6 +89,7 @@ struct Live {                   // host view of one live daughter
     int32_t index;              // within its batch
     int32_t group;
     int32_t state;              // index of its start state in the mother's stored set
+    int32_t cv_role = 0;        // learned control variate: 0 none, 1 estimate, 2 calibration
 };
 
 }  // namespace
@@ -127,6 +146,8 @@ struct ttcf_ctx {
     int64_t cv_mu_count = 0;
     double cv_mu_dt = 0.0;
     double cv_mu_gamma = 0.0;
+    std::vector<double> cv_beta;  // calibrated control-variate coefficient per time point
+    double cv_beta_gamma = 0.0;
     // shape of the daughter step kernel
     int32_t shape_variant = 0, shape_threads = 0, shape_kmax = 24;
     double shape_skin = 0.25;
@@ -886,10 +907,11 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
             c->row_nt.push_back(len);
             c->row_health.push_back(hh[q]);
             {
-                int has = 1;
+                // a group carries the control variate when all its daughters do, in one role
+                int role = c->live[ready[which[q]].first].cv_role;
                 for (size_t d = ready[which[q]].first; d < ready[which[q]].second; ++d)
-                    has &= c->descs[d].hseries != nullptr ? 1 : 0;
-                c->row_cv.push_back(has);
+                    if (c->descs[d].hseries == nullptr || c->live[d].cv_role != role) role = 0;
+                c->row_cv.push_back(role);
             }
             if (hh[q] == 0) ++added_healthy;
         }
@@ -989,10 +1011,12 @@ int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, 
     return TTCF_OK;
 }
 
+// live daughters are kept in increasing id order (spawned in order, removed in place)
 static int32_t find_live(ttcf_ctx* c, int64_t id) {
-    for (size_t i = 0; i < c->live.size(); ++i)
-        if (c->live[i].id == id) return (int32_t)i;
-    return -1;
+    auto it = std::lower_bound(c->live.begin(), c->live.end(), id,
+                               [](const Live& l, int64_t v) { return l.id < v; });
+    if (it == c->live.end() || it->id != id) return -1;
+    return (int32_t)(it - c->live.begin());
 }
 
 int32_t ttcf_export_daughter(ttcf_ctx* c, int64_t daughter, double* r, double* p, int64_t* k) {
@@ -1053,6 +1077,100 @@ int32_t ttcf_debug_poison(ttcf_ctx* c, int64_t daughter) {
 }
 
 }  // extern "C"
+
+// ---- replicas of a mother ---------------------------------------------------------------
+
+namespace {
+
+// Copies of a mother's current state (and thermostat variable), each with its own optional
+// momentum kick, advanced together by one launch of the mother kernel (one workgroup per
+// copy). The mother itself is not changed.
+struct Replicas {
+    Scratch* sc = nullptr;
+    std::vector<MotherLaunch> ls;
+    double* rep = nullptr;
+    int32_t count = 0;
+    ~Replicas() { delete sc; }
+
+    int32_t start(ttcf_ctx* c, Mother& m, int32_t n_rep, const double* kicks, int64_t decorrelate) {
+        const int n = m.dev.n;
+        const size_t sz = 6 * (size_t)n;
+        sc = new Scratch(c->stream);
+        rep = sc->get<double>(sz * n_rep + n_rep);
+        double* kick_d = kicks ? sc->get<double>(3 * (size_t)n * n_rep) : nullptr;
+        if (!rep || (kicks && !kick_d)) return fail(c, TTCF_ENOMEM, "replica allocation failed");
+        double* zrep = rep + sz * n_rep;
+        if (kicks)
+            HIPCHECK(c, hipMemcpyAsync(kick_d, kicks, sizeof(double) * 3 * (size_t)n * n_rep,
+                                       hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(c, launch_replicate(m.state, m.zeta, n, kick_d, n_rep, rep, zrep, c->stream));
+        count = n_rep;
+        ls.assign(n_rep, MotherLaunch{});
+        const double nf = 3.0 * n - 3.0;
+        for (int r = 0; r < n_rep; ++r) {
+            MotherLaunch& L = ls[r];
+            L.sys = m.dev;
+            L.state = rep + sz * r;
+            L.zeta = zrep + r;
+            L.temperature = m.sys.temperature;
+            L.nf = nf;
+            L.q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
+            L.threads = m.threads;
+            L.apt = m.apt;
+            L.precision = m.sys.precision;
+            L.lds_bytes = lds_for(m.dev, m.sys.precision);
+        }
+        if (decorrelate > 0) return run(c, 0, decorrelate, nullptr);
+        return TTCF_OK;
+    }
+
+    // every copy: n_chunks times {steps steps; snapshot into snaps (copy-major)}
+    int32_t run(ttcf_ctx* c, int64_t n_chunks, int64_t steps, double* snaps) {
+        const size_t sz = 6 * (size_t)ls[0].sys.n;
+        for (int r = 0; r < count; ++r) {
+            ls[r].n_chunks = n_chunks;
+            ls[r].steps_per_chunk = steps;
+            ls[r].snapshots = snaps ? snaps + sz * (size_t)r * (size_t)n_chunks : nullptr;
+        }
+        int32_t rc = upload_mother_launches(c, ls.data(), count);
+        if (rc != TTCF_OK) return rc;
+        HIPCHECK(c, launch_mothers(c->d_mlaunch, count, ls[0], c->stream));
+        return TTCF_OK;
+    }
+
+    int32_t sample(ttcf_ctx* c, int32_t per_copy, int64_t between, double* snaps) {
+        return run(c, per_copy, between, snaps);
+    }
+};
+
+}  // namespace
+
+extern "C" int32_t ttcf_sample_states_replicated(ttcf_ctx* c, int32_t mother, int32_t n_replicas,
+                                                 const double* kicks, int64_t decorrelate_steps,
+                                                 int32_t states_per_replica, int64_t steps_between) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || n_replicas <= 0 ||
+        states_per_replica <= 0 || steps_between <= 0 || decorrelate_steps < 0)
+        return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    const int64_t total = (int64_t)n_replicas * states_per_replica;
+    if (total > (int64_t)1 << 24) return fail(c, TTCF_EINVAL, "too many states");
+    const size_t n = (size_t)m.dev.n;
+    if (m.states_cap < total) {
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+        dev_free(m.states);
+        m.states = (double*)dev_alloc(sizeof(double) * 6 * n * total, c->stream);
+        m.states_cap = m.states ? total : 0;
+        m.n_states = 0;
+        if (!m.states) return fail(c, TTCF_ENOMEM, "state buffer allocation failed");
+    }
+    Replicas R;
+    int32_t rc = R.start(c, m, n_replicas, kicks, decorrelate_steps);
+    if (rc == TTCF_OK) rc = R.sample(c, states_per_replica, steps_between, m.states);
+    if (rc != TTCF_OK) return rc;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    m.n_states = (int32_t)total;
+    return TTCF_OK;
+}
 
 // ---- learned control variate -------------------------------------------------------------
 
@@ -1164,49 +1282,50 @@ int32_t cv_check(ttcf_ctx* c) {
     return TTCF_OK;
 }
 
-// Features, P_xy(0) and Omega(0) of live daughters [first, first + count): rows of kCvIn floats.
+// Features, P_xy(0) and Omega(0) of live daughters [first, first + count): rows of kCvIn
+// floats; with d_targets != null also B(t_1..t_nout) of each daughter (FP32). Returns the
+// index of the first daughter in the live list through *i0_out.
 int32_t cv_features_of(ttcf_ctx* c, int64_t first, int32_t count, float* d_feat, double* d_b0,
-                       double* d_om, int* out_mother) {
+                       double* d_om, float* d_targets, int32_t n_out, int32_t* i0_out) {
     int32_t rc = sync_descs(c);
     if (rc != TTCF_OK) return rc;
-    std::vector<int32_t> idx(count);
-    int mother = -1;
-    for (int32_t q = 0; q < count; ++q) {
-        const int32_t i = find_live(c, first + q);
-        if (i < 0) return fail(c, TTCF_EINVAL, "no such live daughter");
-        const int mo = c->batches[c->live[i].batch].mother;
-        if (mother < 0) mother = mo;
-        if (mo != mother) return fail(c, TTCF_EINVAL, "daughters of one call must share a mother");
-        if (c->descs[i].done < 1 && c->descs[i].n_steps > 0)
-            return fail(c, TTCF_ESTATE, "features need P_xy(0): run ttcf_step first");
-        idx[q] = i;
-    }
+    const int32_t i0 = find_live(c, first);
+    if (i0 < 0 || i0 + count > (int32_t)c->live.size() ||
+        c->live[i0 + count - 1].id != first + count - 1)
+        return fail(c, TTCF_EINVAL, "the daughters must be live and consecutive");
+    const int mother = c->batches[c->live[i0].batch].mother;
     Mother& m = c->mothers[mother];
-    const DaughterDesc& d0 = c->descs[idx[0]];
-    // per row: state index, mapping, V*P_xy(0) gathered from the series
-    std::vector<int32_t> st(count), mp(count);
+    std::vector<int32_t> idx(2 * (size_t)count);
+    std::vector<const double*> ser(count);
     for (int32_t q = 0; q < count; ++q) {
-        st[q] = c->live[idx[q]].state;
-        mp[q] = c->descs[idx[q]].map;
-        if (st[q] >= m.n_states) return fail(c, TTCF_ESTATE, "the mother's stored states were replaced");
+        const int32_t i = i0 + q;
+        if (c->batches[c->live[i].batch].mother != mother)
+            return fail(c, TTCF_EINVAL, "daughters of one call must share a mother");
+        const DaughterDesc& d = c->descs[i];
+        if (d.done < std::max(1, n_out))
+            return fail(c, TTCF_ESTATE, "the daughters have not been stepped far enough");
+        if (c->live[i].state >= m.n_states)
+            return fail(c, TTCF_ESTATE, "the mother's stored states were replaced");
+        idx[q] = c->live[i].state;
+        idx[count + q] = d.map;
+        ser[q] = d.series;
     }
-    const size_t bytes = sizeof(int32_t) * 2 * count + sizeof(double) * count + 64;
-    char* buf = (char*)dev_alloc(bytes, c->stream);
-    if (!buf) return fail(c, TTCF_ENOMEM, "feature scratch allocation failed");
-    double* d_vp = (double*)buf;
-    int32_t* d_st = (int32_t*)(d_vp + count);
-    int32_t* d_mp = d_st + count;
-    for (int32_t q = 0; q < count; ++q)
-        HIPCHECK(c, hipMemcpyAsync(d_vp + q, c->descs[idx[q]].series, sizeof(double),
-                                   hipMemcpyDeviceToDevice, c->stream));
-    HIPCHECK(c, hipMemcpyAsync(d_st, st.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(c, hipMemcpyAsync(d_mp, mp.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(c, launch_cv_features(m.states, m.dev.n, d_st, d_mp, d_vp, nullptr, count, m.dev.box[1],
-                                   m.dev.volume, m.sys.temperature, d0.gamma_dot, d_feat, d_b0, d_om,
-                                   c->stream));
+    Scratch sc(c->stream);
+    double* d_vp = sc.get<double>(count);
+    int32_t* d_idx = sc.get<int32_t>(2 * (size_t)count);
+    const double** d_ser = sc.get<const double*>(count);
+    if (!d_vp || !d_idx || !d_ser) return fail(c, TTCF_ENOMEM, "feature scratch allocation failed");
+    HIPCHECK(c, hipMemcpyAsync(d_idx, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHECK(c, hipMemcpyAsync(d_ser, ser.data(), sizeof(double*) * count, hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHECK(c, launch_cv_gather_series(d_ser, count, n_out, 1.0 / m.dev.volume, d_targets, d_vp,
+                                        c->stream));
+    HIPCHECK(c, launch_cv_features(m.states, m.dev.n, d_idx, d_idx + count, d_vp, nullptr, count,
+                                   m.dev.box[1], m.dev.volume, m.sys.temperature,
+                                   c->descs[i0].gamma_dot, d_feat, d_b0, d_om, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    dev_free(buf);
-    if (out_mother) *out_mother = mother;
+    if (i0_out) *i0_out = i0;
     return TTCF_OK;
 }
 
@@ -1272,6 +1391,8 @@ int32_t ttcf_cv_init(ttcf_ctx* c, int32_t n_out, const float* weights, int64_t n
     c->cv_stats_ready = false;
     c->cv_mu_count = 0;
     c->cv_rows = 0;
+    c->cv_beta.clear();
+    c->cv_beta_gamma = 0.0;
     return TTCF_OK;
 }
 
@@ -1325,19 +1446,16 @@ int32_t ttcf_cv_add_training(ttcf_ctx* c, int64_t first, int32_t count) {
     int32_t rc = cv_check(c);
     if (rc != TTCF_OK) return rc;
     if (count <= 0) return TTCF_EINVAL;
-    rc = sync_descs(c);
-    if (rc != TTCF_OK) return rc;
     const int O = c->cv_out;
-    for (int32_t q = 0; q < count; ++q) {
-        const int32_t i = find_live(c, first + q);
-        if (i < 0) return fail(c, TTCF_EINVAL, "no such live daughter");
-        if (c->descs[i].done < O) return fail(c, TTCF_ESTATE, "daughter has fewer recorded steps than outputs");
-    }
     if (c->cv_rows + count > c->cv_cap) {
         const int64_t cap = std::max<int64_t>(c->cv_rows + count, 2 * c->cv_cap);
         float* nx = (float*)dev_alloc(sizeof(float) * cap * kCvIn, c->stream);
         float* nt = (float*)dev_alloc(sizeof(float) * cap * O, c->stream);
-        if (!nx || !nt) return fail(c, TTCF_ENOMEM, "training-set allocation failed");
+        if (!nx || !nt) {
+            dev_free(nx);
+            dev_free(nt);
+            return fail(c, TTCF_ENOMEM, "training-set allocation failed");
+        }
         if (c->cv_rows > 0) {
             HIPCHECK(c, hipMemcpyAsync(nx, c->cv_x, sizeof(float) * c->cv_rows * kCvIn,
                                        hipMemcpyDeviceToDevice, c->stream));
@@ -1351,25 +1469,12 @@ int32_t ttcf_cv_add_training(ttcf_ctx* c, int64_t first, int32_t count) {
         c->cv_t = nt;
         c->cv_cap = cap;
     }
-    double* tmp = (double*)dev_alloc(sizeof(double) * 2 * count, c->stream);
+    Scratch sc(c->stream);
+    double* tmp = sc.get<double>(2 * (size_t)count);
     if (!tmp) return fail(c, TTCF_ENOMEM, "scratch allocation failed");
-    rc = cv_features_of(c, first, count, c->cv_x + c->cv_rows * kCvIn, tmp, tmp + count, nullptr);
+    rc = cv_features_of(c, first, count, c->cv_x + c->cv_rows * kCvIn, tmp, tmp + count,
+                        c->cv_t + c->cv_rows * O, O, nullptr);
     if (rc != TTCF_OK) return rc;
-    // targets B(t_1..t_nout) = V P_xy / V, stored as FP32
-    std::vector<double> ser((size_t)O + 1);
-    std::vector<float> tg((size_t)count * O);
-    for (int32_t q = 0; q < count; ++q) {
-        const int32_t i = find_live(c, first + q);
-        HIPCHECK(c, hipMemcpyAsync(ser.data(), c->descs[i].series, sizeof(double) * (O + 1),
-                                   hipMemcpyDeviceToHost, c->stream));
-        HIPCHECK(c, hipStreamSynchronize(c->stream));
-        const double iv = 1.0 / c->descs[i].sys.volume;
-        for (int k = 0; k < O; ++k) tg[(size_t)q * O + k] = (float)(ser[k + 1] * iv);
-    }
-    HIPCHECK(c, hipMemcpyAsync(c->cv_t + c->cv_rows * O, tg.data(), sizeof(float) * tg.size(),
-                               hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(c, hipStreamSynchronize(c->stream));
-    dev_free(tmp);
     c->cv_rows += count;
     c->cv_stats_ready = false;
     return TTCF_OK;
@@ -1445,48 +1550,47 @@ int32_t ttcf_cv_train(ttcf_ctx* c, int32_t epochs, int32_t batch, double lr, con
     return TTCF_OK;
 }
 
-int32_t ttcf_cv_attach(ttcf_ctx* c, int64_t first, int32_t count) {
+int32_t ttcf_cv_attach(ttcf_ctx* c, int64_t first, int32_t count, int32_t role) {
     int32_t rc = cv_check(c);
     if (rc != TTCF_OK) return rc;
-    if (count <= 0) return TTCF_EINVAL;
+    if (count <= 0 || (role != TTCF_CV_ESTIMATE && role != TTCF_CV_CALIBRATE)) return TTCF_EINVAL;
     if (!c->cv_stats_ready) return fail(c, TTCF_ESTATE, "train the network before attaching it");
-    rc = sync_descs(c);
-    if (rc != TTCF_OK) return rc;
     const int O = c->cv_out;
-    float* feat = (float*)dev_alloc(sizeof(float) * count * kCvIn + sizeof(double) * 2 * count + 64,
-                                    c->stream);
-    if (!feat) return fail(c, TTCF_ENOMEM, "feature allocation failed");
-    double* b0 = (double*)(((uintptr_t)(feat + (size_t)count * kCvIn) + 15) & ~(uintptr_t)15);
+    Scratch sc(c->stream);
+    float* feat = sc.get<float>((size_t)count * kCvIn);
+    double* b0 = sc.get<double>(2 * (size_t)count);
+    double* hrow = sc.get<double>((size_t)count * (O + 1));
+    double** dst = sc.get<double*>(count);
+    int32_t* nk = sc.get<int32_t>(count);
+    if (!feat || !b0 || !hrow || !dst || !nk) return fail(c, TTCF_ENOMEM, "feature allocation failed");
     double* om = b0 + count;
-    rc = cv_features_of(c, first, count, feat, b0, om, nullptr);
+    int32_t i0 = 0;
+    rc = cv_features_of(c, first, count, feat, b0, om, nullptr, 0, &i0);
     if (rc != TTCF_OK) return rc;
-    // every daughter's h series lives in its batch's buffer (same layout as the series)
-    double* hrow = (double*)dev_alloc(sizeof(double) * (size_t)count * (O + 1), c->stream);
-    if (!hrow) return fail(c, TTCF_ENOMEM, "h allocation failed");
-    const DaughterDesc& d0 = c->descs[find_live(c, first)];
-    rc = cv_predict_h(c, feat, b0, om, count, d0.sys.dt, hrow, O + 1);
+    rc = cv_predict_h(c, feat, b0, om, count, c->descs[i0].sys.dt, hrow, O + 1);
     if (rc != TTCF_OK) return rc;
+    // each daughter's h series lives in its batch's buffer, laid out like the B series; h is
+    // zero past t_K
+    std::vector<double*> dh(count);
+    std::vector<int32_t> nh(count);
     for (int32_t q = 0; q < count; ++q) {
-        const int32_t i = find_live(c, first + q);
+        const int32_t i = i0 + q;
         Batch& b = c->batches[c->live[i].batch];
+        const size_t len = (size_t)b.n_steps + 1;
         if (!b.hseries) {
-            b.hseries = (double*)dev_alloc(sizeof(double) * (size_t)(b.n_steps + 1) * b.n_daughters,
-                                           c->stream);
+            b.hseries = (double*)dev_alloc(sizeof(double) * len * b.n_daughters, c->stream);
             if (!b.hseries) return fail(c, TTCF_ENOMEM, "h series allocation failed");
-            std::vector<double> z((size_t)(b.n_steps + 1) * b.n_daughters, 0.0);
-            HIPCHECK(c, hipMemcpyAsync(b.hseries, z.data(), sizeof(double) * z.size(),
-                                       hipMemcpyHostToDevice, c->stream));
-            HIPCHECK(c, hipStreamSynchronize(c->stream));
+            HIPCHECK(c, launch_fill_f64(b.hseries, 0.0, (int64_t)len * b.n_daughters, c->stream));
         }
-        double* dst = b.hseries + (size_t)(b.n_steps + 1) * c->live[i].index;
-        const int nk = std::min(b.n_steps, O) + 1;
-        HIPCHECK(c, hipMemcpyAsync(dst, hrow + (size_t)q * (O + 1), sizeof(double) * nk,
-                                   hipMemcpyDeviceToDevice, c->stream));
-        c->descs[i].hseries = dst;
+        dh[q] = b.hseries + len * c->live[i].index;
+        nh[q] = std::min(b.n_steps, O) + 1;
+        c->descs[i].hseries = dh[q];
+        c->live[i].cv_role = role;
     }
+    HIPCHECK(c, hipMemcpyAsync(dst, dh.data(), sizeof(double*) * count, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(nk, nh.data(), sizeof(int32_t) * count, hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, launch_cv_scatter_h(hrow, O + 1, count, dst, nk, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    dev_free(hrow);
-    dev_free(feat);
     return push_descs(c);
 }
 
@@ -1496,78 +1600,42 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
     int32_t rc = cv_check(c);
     if (rc != TTCF_OK) return rc;
     if (mother < 0 || mother >= (int32_t)c->mothers.size() || n_replicas <= 0 || rounds <= 0 ||
-        states_per_replica <= 0 || steps_between <= 0 || decorrelate_steps < 0)
+        states_per_replica <= 0 || steps_between <= 0 || decorrelate_steps < 0 ||
+        !std::isfinite(gamma_dot))
         return TTCF_EINVAL;
     if (!c->cv_stats_ready) return fail(c, TTCF_ESTATE, "train the network before the mean term");
+    if (c->cv_mu_count > 0 && gamma_dot != c->cv_mu_gamma)
+        return fail(c, TTCF_EINVAL, "the mean term already holds samples at another shear rate");
     Mother& m = c->mothers[mother];
     const int n = m.dev.n, O = c->cv_out;
     const int64_t per_round = (int64_t)n_replicas * states_per_replica;
     if (per_round * 4 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many samples per round");
-    // replicas of the mother, each with its own momentum kick, in one buffer
+    Scratch sc(c->stream);
     const size_t sz = 6 * (size_t)n;
-    double* rep = (double*)dev_alloc(sizeof(double) * (sz * n_replicas + n_replicas), c->stream);
-    double* kick_d = kicks ? (double*)dev_alloc(sizeof(double) * 3 * (size_t)n * n_replicas, c->stream)
-                           : nullptr;
-    double* snaps = (double*)dev_alloc(sizeof(double) * sz * per_round, c->stream);
-    double* vp = (double*)dev_alloc(sizeof(double) * per_round, c->stream);
+    double* snaps = sc.get<double>(sz * per_round);
+    double* vp = sc.get<double>(per_round);
     const int rows = (int)(4 * per_round);
-    float* feat = (float*)dev_alloc(sizeof(float) * (size_t)rows * kCvIn, c->stream);
-    double* b0 = (double*)dev_alloc(sizeof(double) * 2 * (size_t)rows, c->stream);
-    double* hh = (double*)dev_alloc(sizeof(double) * (size_t)rows * (O + 1), c->stream);
-    int32_t* idx = (int32_t*)dev_alloc(sizeof(int32_t) * 2 * (size_t)rows + 64, c->stream);
-    if (!rep || (kicks && !kick_d) || !snaps || !vp || !feat || !b0 || !hh || !idx)
+    float* feat = sc.get<float>((size_t)rows * kCvIn);
+    double* b0 = sc.get<double>(2 * (size_t)rows);
+    double* hh = sc.get<double>((size_t)rows * (O + 1));
+    int32_t* idx = sc.get<int32_t>(2 * (size_t)rows);
+    double* sgn = sc.get<double>(4);
+    if (!snaps || !vp || !feat || !b0 || !hh || !idx || !sgn)
         return fail(c, TTCF_ENOMEM, "mean-term allocation failed");
-    double* zrep = rep + sz * n_replicas;
-    if (kicks)
-        HIPCHECK(c, hipMemcpyAsync(kick_d, kicks, sizeof(double) * 3 * (size_t)n * n_replicas,
-                                   hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(c, launch_replicate(m.state, m.zeta, n, kick_d, n_replicas, rep, zrep, c->stream));
     std::vector<int32_t> hs(2 * (size_t)rows);
     for (int r = 0; r < rows; ++r) {
-        hs[r] = r / 4;       // state
+        hs[r] = r / 4;         // state
         hs[rows + r] = r % 4;  // mapping
     }
+    const double sgn_h[4] = {1.0, 1.0, -1.0, -1.0};  // sign of P_xy(0) under each mapping
     HIPCHECK(c, hipMemcpyAsync(idx, hs.data(), sizeof(int32_t) * hs.size(), hipMemcpyHostToDevice, c->stream));
-    const double sgn_h[4] = {1.0, 1.0, -1.0, -1.0};
-    double* sgn = (double*)dev_alloc(sizeof(double) * 4, c->stream);
-    if (!sgn) return fail(c, TTCF_ENOMEM, "allocation failed");
     HIPCHECK(c, hipMemcpyAsync(sgn, sgn_h, sizeof(sgn_h), hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(c, hipStreamSynchronize(c->stream));
-    std::vector<MotherLaunch> ls(n_replicas);
-    const double nf = 3.0 * n - 3.0;
-    for (int r = 0; r < n_replicas; ++r) {
-        MotherLaunch& L = ls[r];
-        L = MotherLaunch{};
-        L.sys = m.dev;
-        L.state = rep + sz * r;
-        L.zeta = zrep + r;
-        L.temperature = m.sys.temperature;
-        L.nf = nf;
-        L.q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
-        L.threads = m.threads;
-        L.apt = m.apt;
-        L.precision = m.sys.precision;
-        L.lds_bytes = lds_for(m.dev, m.sys.precision);
-    }
-    if (decorrelate_steps > 0) {
-        for (auto& L : ls) {
-            L.n_chunks = 0;
-            L.steps_per_chunk = decorrelate_steps;
-            L.snapshots = nullptr;
-        }
-        rc = upload_mother_launches(c, ls.data(), n_replicas);
-        if (rc != TTCF_OK) return rc;
-        HIPCHECK(c, launch_mothers(c->d_mlaunch, n_replicas, ls[0], c->stream));
-    }
-    for (int r = 0; r < n_replicas; ++r) {
-        ls[r].n_chunks = states_per_replica;
-        ls[r].steps_per_chunk = steps_between;
-        ls[r].snapshots = snaps + sz * (size_t)r * states_per_replica;
-    }
-    rc = upload_mother_launches(c, ls.data(), n_replicas);
+    Replicas R;
+    rc = R.start(c, m, n_replicas, kicks, decorrelate_steps);
     if (rc != TTCF_OK) return rc;
     for (int32_t round = 0; round < rounds; ++round) {
-        HIPCHECK(c, launch_mothers(c->d_mlaunch, n_replicas, ls[0], c->stream));
+        rc = R.sample(c, states_per_replica, steps_between, snaps);
+        if (rc != TTCF_OK) return rc;
         HIPCHECK(c, launch_states_vpxy(m.dev, snaps, (int32_t)per_round, vp, c->stream));
         HIPCHECK(c, launch_cv_features(snaps, n, idx, idx + rows, vp, sgn, rows, m.dev.box[1],
                                        m.dev.volume, m.sys.temperature, gamma_dot, feat, b0,
@@ -1578,15 +1646,6 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
                                        c->cv_mu + 2 * (O + 1), c->cv_mu + 3 * (O + 1), c->stream));
     }
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    dev_free(rep);
-    dev_free(kick_d);
-    dev_free(snaps);
-    dev_free(vp);
-    dev_free(feat);
-    dev_free(b0);
-    dev_free(hh);
-    dev_free(idx);
-    dev_free(sgn);
     c->cv_mu_count += per_round * rounds;
     c->cv_mu_dt = m.dev.dt;
     c->cv_mu_gamma = gamma_dot;
@@ -1594,8 +1653,49 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
     return TTCF_OK;
 }
 
+int32_t ttcf_cv_calibrate(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, double* beta) {
+    int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    if (n_t <= 0 || n_t > c->cv_out + 1) return fail(c, TTCF_EINVAL, "n_t beyond the network's grid");
+    std::vector<int32_t> rows;
+    for (int64_t r = 0; r < c->acc_rows; ++r) {
+        if (c->row_cv[r] != TTCF_CV_CALIBRATE || c->row_health[r] != 0) continue;
+        if (c->row_gamma[r] != gamma_dot_filter || c->row_nt[r] < n_t) continue;
+        rows.push_back((int32_t)r);
+    }
+    if (rows.size() < 2) return fail(c, TTCF_ESTATE, "fewer than two calibration groups");
+    Scratch sc(c->stream);
+    double* d_beta = sc.get<double>(n_t);
+    int32_t* d_rows = sc.get<int32_t>(rows.size());
+    if (!d_beta || !d_rows) return fail(c, TTCF_ENOMEM, "calibration scratch allocation failed");
+    HIPCHECK(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice,
+                               c->stream));
+    HIPCHECK(c, hipMemcpyAsync(c->d_row_health, c->row_health.data(), sizeof(int32_t) * c->row_health.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    ResponseLaunch R{};
+    R.d_all = c->acc_d;
+    R.i_all = c->acc_i;
+    R.gamma = c->d_row_gamma;
+    R.coef = c->d_row_coef;
+    R.health = c->d_row_health;
+    R.rows = d_rows;
+    R.n_rows = (int32_t)rows.size();
+    R.n_t = n_t;
+    R.n_t_stride = c->acc_stride;
+    R.h_all = c->acc_h;
+    HIPCHECK(c, launch_cv_beta(R, d_beta, c->stream));
+    std::vector<double> bb(n_t);
+    HIPCHECK(c, hipMemcpyAsync(bb.data(), d_beta, sizeof(double) * n_t, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->cv_beta = bb;
+    c->cv_beta_gamma = gamma_dot_filter;
+    if (beta) std::memcpy(beta, bb.data(), sizeof(double) * n_t);
+    return TTCF_OK;
+}
+
 int32_t ttcf_cv_response(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, double* cv_mean,
-                         double* cv_se, double* mu_h, double* mu_h_se, int64_t* out_n_states) {
+                         double* cv_se, double* plain_mean, double* plain_se, double* mu_h,
+                         double* mu_h_se, int64_t* out_n_states) {
     int32_t rc = cv_check(c);
     if (rc != TTCF_OK) return rc;
     if (n_t <= 0 || n_t > c->cv_out + 1) return fail(c, TTCF_EINVAL, "n_t beyond the network's grid");
@@ -1604,12 +1704,13 @@ int32_t ttcf_cv_response(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, doub
         return fail(c, TTCF_EINVAL, "the filter must be the shear rate of the mean term");
     std::vector<int32_t> rows;
     for (int64_t r = 0; r < c->acc_rows; ++r) {
-        if (!c->row_cv[r] || c->row_health[r] != 0) continue;
+        if (c->row_cv[r] != TTCF_CV_ESTIMATE || c->row_health[r] != 0) continue;
         if (c->row_gamma[r] != gamma_dot_filter) continue;
         if (c->row_nt[r] < n_t) continue;
         rows.push_back((int32_t)r);
     }
-    if (rows.empty()) return fail(c, TTCF_ESTATE, "no accumulated group carries the control variate");
+    if (rows.size() < 2) return fail(c, TTCF_ESTATE, "fewer than two groups carry the control variate");
+    const bool calibrated = c->cv_beta_gamma == gamma_dot_filter && (int32_t)c->cv_beta.size() >= n_t;
     // mean term per time point from its compensated sums
     const int K = c->cv_out + 1;
     std::vector<double> mu(4 * (size_t)K);
@@ -1619,19 +1720,35 @@ int32_t ttcf_cv_response(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, doub
     std::vector<double> muv(K), muse(K);
     const double cnt = (double)c->cv_mu_count;
     for (int k = 0; k < K; ++k) {
-        const double s = mu[k] + mu[K + k], s2 = mu[2 * K + k] + mu[3 * K + k];
-        muv[k] = s / cnt;
-        const double var = (s2 - s * s / cnt) / (cnt - 1.0);
+        const double sm = mu[k] + mu[K + k], s2 = mu[2 * K + k] + mu[3 * K + k];
+        muv[k] = sm / cnt;
+        const double var = (s2 - sm * sm / cnt) / (cnt - 1.0);
         muse[k] = std::sqrt(std::max(var, 0.0) / cnt);
     }
-    double* d_mu = (double*)dev_alloc(sizeof(double) * K, c->stream);
-    const size_t bytes = sizeof(int32_t) * rows.size() + sizeof(double) * 4 * n_t + 64;
-    char* scratch = (char*)dev_alloc(bytes, c->stream);
-    if (!d_mu || !scratch) return fail(c, TTCF_ENOMEM, "response scratch allocation failed");
-    double* d_out = (double*)scratch;
-    int32_t* d_used = (int32_t*)(scratch + sizeof(double) * 4 * n_t);
-    int32_t* d_rows = d_used + 4;
-    HIPCHECK(c, hipMemcpyAsync(d_mu, muv.data(), sizeof(double) * K, hipMemcpyHostToDevice, c->stream));
+    if (calibrated)
+        for (int k = 0; k < n_t; ++k) {
+            muv[k] *= c->cv_beta[k];
+            muse[k] *= std::fabs(c->cv_beta[k]);
+        }
+    Scratch sc(c->stream);
+    double* d_mu = sc.get<double>(K);
+    double* d_beta = sc.get<double>(K);
+    double* d_out = sc.get<double>(8 * (size_t)n_t);
+    int32_t* d_used = sc.get<int32_t>(2);
+    int32_t* d_rows = sc.get<int32_t>(rows.size());
+    if (!d_mu || !d_beta || !d_out || !d_used || !d_rows)
+        return fail(c, TTCF_ENOMEM, "response scratch allocation failed");
+    // the kernel adds beta * mu: pass mu_H itself and beta (1 when uncalibrated)
+    {
+        std::vector<double> bb(K, 1.0), mraw(K);
+        for (int k = 0; k < K; ++k) mraw[k] = mu[k] + mu[K + k];
+        for (int k = 0; k < K; ++k) mraw[k] /= cnt;
+        if (calibrated)
+            for (int k = 0; k < n_t; ++k) bb[k] = c->cv_beta[k];
+        HIPCHECK(c, hipMemcpyAsync(d_mu, mraw.data(), sizeof(double) * K, hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(c, hipMemcpyAsync(d_beta, bb.data(), sizeof(double) * K, hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+    }
     HIPCHECK(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice,
                                c->stream));
     HIPCHECK(c, hipMemcpyAsync(c->d_row_health, c->row_health.data(), sizeof(int32_t) * c->row_health.size(),
@@ -1647,20 +1764,26 @@ int32_t ttcf_cv_response(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, doub
     R.n_t = n_t;
     R.n_t_stride = c->acc_stride;
     R.normalise = 0;
+    // the plain estimate over the same groups, then the control-variate one
+    R.out = d_out + 4 * (size_t)n_t;
+    R.used = d_used + 1;
+    HIPCHECK(c, launch_response(R, c->stream));
     R.h_all = c->acc_h;
     R.mu_h = d_mu;
+    R.beta = d_beta;
     R.out = d_out;
     R.used = d_used;
     HIPCHECK(c, launch_response(R, c->stream));
-    std::vector<double> out(4 * (size_t)n_t);
+    std::vector<double> out(8 * (size_t)n_t);
     int32_t used = 0;
-    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * 4 * n_t, hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * out.size(), hipMemcpyDeviceToHost,
+                               c->stream));
     HIPCHECK(c, hipMemcpyAsync(&used, d_used, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    dev_free(scratch);
-    dev_free(d_mu);
     if (cv_mean) std::memcpy(cv_mean, out.data(), sizeof(double) * n_t);
     if (cv_se) std::memcpy(cv_se, out.data() + n_t, sizeof(double) * n_t);
+    if (plain_mean) std::memcpy(plain_mean, out.data() + 4 * n_t, sizeof(double) * n_t);
+    if (plain_se) std::memcpy(plain_se, out.data() + 5 * n_t, sizeof(double) * n_t);
     if (mu_h) std::memcpy(mu_h, muv.data(), sizeof(double) * n_t);
     if (mu_h_se) std::memcpy(mu_h_se, muse.data(), sizeof(double) * n_t);
     if (out_n_states) *out_n_states = used;

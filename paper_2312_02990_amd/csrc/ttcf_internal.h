@@ -117,6 +117,7 @@ struct ResponseLaunch {
     int32_t normalise;           // divide each group by its own shear rate
     const double* h_all;         // groups' control-variate series, or null (plain TTCF)
     const double* mu_h;          // control-variate mean term per time point, or null
+    const double* beta;          // control-variate coefficient per time point, or null (1)
     double* out;                 // 4 * n_t: ttcf mean, ttcf se, dav mean, dav se
     int32_t* used;               // number of healthy rows
 };
@@ -152,6 +153,12 @@ hipError_t launch_gather_norm(const float* src, const int32_t* idx, int rows, in
                               const float* mu, const float* inv, float* dst, hipStream_t s);
 hipError_t launch_col_stats(const float* X, int64_t rows, int cols, float* mu, float* inv,
                             hipStream_t s);
+hipError_t launch_cv_gather_series(const double* const* series, int32_t count, int32_t n_out,
+                                   double inv_volume, float* targets, double* vpxy0, hipStream_t s);
+hipError_t launch_cv_scatter_h(const double* h, int32_t stride, int32_t count, double* const* dst,
+                               const int32_t* lens, hipStream_t s);
+hipError_t launch_cv_beta(const ResponseLaunch& r, double* beta, hipStream_t s);
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s);
 hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* state_of,
                               const int32_t* map_of, const double* vpxy0, const double* vsign,
                               int32_t rows, double ly, double volume, double temperature,

@@ -894,6 +894,7 @@ __global__ void k_response(ResponseLaunch r) {
     if (k >= r.n_t) return;
     double gs = 0, gc = 0, ds = 0, dc = 0;
     int used = 0;
+    const double beta = r.beta ? r.beta[k] : 1.0;
     for (int i = 0; i < r.n_rows; ++i) {
         const int row = r.rows[i];
         if (r.health[row] != 0) continue;
@@ -901,7 +902,7 @@ __global__ void k_response(ResponseLaunch r) {
         const double* iser = r.i_all + (size_t)row * r.n_t_stride;
         const double gam = r.gamma[row];
         double g = dser[0] - r.coef[row] * iser[k];
-        if (r.h_all) g -= r.h_all[(size_t)row * r.n_t_stride + k];
+        if (r.h_all) g -= beta * r.h_all[(size_t)row * r.n_t_stride + k];
         double dv = dser[k];
         if (r.normalise) {
             g /= gam;
@@ -921,7 +922,7 @@ __global__ void k_response(ResponseLaunch r) {
         const double* iser = r.i_all + (size_t)row * r.n_t_stride;
         const double gam = r.gamma[row];
         double g = dser[0] - r.coef[row] * iser[k];
-        if (r.h_all) g -= r.h_all[(size_t)row * r.n_t_stride + k];
+        if (r.h_all) g -= beta * r.h_all[(size_t)row * r.n_t_stride + k];
         double dv = dser[k];
         if (r.normalise) {
             g /= gam;
@@ -931,11 +932,47 @@ __global__ void k_response(ResponseLaunch r) {
         neumaier_add(dvv, dvc, (dv - dm) * (dv - dm));
     }
     const double denom = used > 1 ? (double)(used - 1) * (double)used : 1.0;
-    r.out[k] = gm + (r.mu_h ? r.mu_h[k] : 0.0);
+    r.out[k] = gm + (r.mu_h ? beta * r.mu_h[k] : 0.0);
     r.out[r.n_t + k] = used > 1 ? sqrt((gv + gvc) / denom) : 0.0;
     r.out[2 * r.n_t + k] = dm;
     r.out[3 * r.n_t + k] = used > 1 ? sqrt((dvv + dvc) / denom) : 0.0;
     if (k == 0) *r.used = used;
+}
+
+// Control-variate coefficient beta(t) = Cov(G, H) / Var(H) over the selected healthy groups
+// (the variance-minimising multiple of H), two compensated passes in a fixed row order;
+// beta = 0 where H does not vary.
+__global__ void k_cv_beta(ResponseLaunch r, double* beta) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= r.n_t) return;
+    double gs = 0, gc = 0, hs = 0, hc = 0;
+    int used = 0;
+    for (int i = 0; i < r.n_rows; ++i) {
+        const int row = r.rows[i];
+        if (r.health[row] != 0) continue;
+        const double* dser = r.d_all + (size_t)row * r.n_t_stride;
+        const double g = dser[0] - r.coef[row] * r.i_all[(size_t)row * r.n_t_stride + k];
+        neumaier_add(gs, gc, g);
+        neumaier_add(hs, hc, r.h_all[(size_t)row * r.n_t_stride + k]);
+        ++used;
+    }
+    if (used < 2) {
+        beta[k] = 0.0;
+        return;
+    }
+    const double gm = (gs + gc) / used, hm = (hs + hc) / used;
+    double cs = 0, cc = 0, vs = 0, vc = 0;
+    for (int i = 0; i < r.n_rows; ++i) {
+        const int row = r.rows[i];
+        if (r.health[row] != 0) continue;
+        const double* dser = r.d_all + (size_t)row * r.n_t_stride;
+        const double g = dser[0] - r.coef[row] * r.i_all[(size_t)row * r.n_t_stride + k] - gm;
+        const double h = r.h_all[(size_t)row * r.n_t_stride + k] - hm;
+        neumaier_add(cs, cc, g * h);
+        neumaier_add(vs, vc, h * h);
+    }
+    const double var = vs + vc;
+    beta[k] = var > 0.0 ? (cs + cc) / var : 0.0;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1807,6 +1844,11 @@ hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s) {
 
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s) {
     hipLaunchKernelGGL(k_response, dim3((r.n_t + 63) / 64), dim3(64), 0, s, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_cv_beta(const ResponseLaunch& r, double* beta, hipStream_t s) {
+    hipLaunchKernelGGL(k_cv_beta, dim3((r.n_t + 63) / 64), dim3(64), 0, s, r, beta);
     return hipGetLastError();
 }
 

@@ -281,6 +281,54 @@ hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* st
     return hipGetLastError();
 }
 
+// P_xy(0) (as V P_xy) and, when targets != null, B(t_1..t_nout) = P_xy of each daughter's
+// recorded series, one workgroup per daughter.
+__global__ void k_cv_gather_series(const double* const* series, int32_t count, int32_t n_out,
+                                   double inv_volume, float* targets, double* vpxy0) {
+    const int row = blockIdx.x;
+    if (row >= count) return;
+    const double* s = series[row];
+    if (targets)
+        for (int k = threadIdx.x; k < n_out; k += blockDim.x)
+            targets[(size_t)row * n_out + k] = (float)(s[k + 1] * inv_volume);
+    if (threadIdx.x == 0) vpxy0[row] = s[0];
+}
+
+hipError_t launch_cv_gather_series(const double* const* series, int32_t count, int32_t n_out,
+                                   double inv_volume, float* targets, double* vpxy0, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cv_gather_series, dim3(count), dim3(64), 0, s, series, count, n_out,
+                       inv_volume, targets, vpxy0);
+    return hipGetLastError();
+}
+
+// h rows (stride values apart) into each daughter's own h series, the first lens[r] values
+__global__ void k_cv_scatter_h(const double* h, int32_t stride, int32_t count, double* const* dst,
+                               const int32_t* lens) {
+    const int row = blockIdx.x;
+    if (row >= count) return;
+    double* d = dst[row];
+    for (int k = threadIdx.x; k < lens[row]; k += blockDim.x) d[k] = h[(size_t)row * stride + k];
+}
+
+hipError_t launch_cv_scatter_h(const double* h, int32_t stride, int32_t count, double* const* dst,
+                               const int32_t* lens, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cv_scatter_h, dim3(count), dim3(64), 0, s, h, stride, count, dst, lens);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_f64(double* p, double v, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, v, count);
+    return hipGetLastError();
+}
+
 // h(t_k) = Omega(0) int_0^{t_k} g ds (trapezoid, g(0) = B(0)) of each row, FP64; pred holds
 // the standardised predictions, B(t_k) = pred / yinv[k] + ymu[k]. out rows (n_out + 1 values)
 // are out_stride apart.

@@ -19,6 +19,8 @@ TTCF_OK, TTCF_EINVAL, TTCF_ENOMEM, TTCF_EDEVICE, TTCF_ESTATE, TTCF_EUNSTABLE = 0
 TTCF_WCA, TTCF_LJ = 0, 1
 TTCF_PREC_FP64, TTCF_PREC_FP32_FORCES = 0, 1
 TTCF_OBS_PXY = 0
+TTCF_CV_ESTIMATE = 1
+TTCF_CV_CALIBRATE = 2
 
 
 class TTCFError(RuntimeError):
@@ -107,10 +109,13 @@ def lib():
         "ttcf_cv_add_training": [V, C.c_int64, C.c_int32],
         "ttcf_cv_export_training": [V, C.c_int64, C.c_int32, F, F],
         "ttcf_cv_train": [V, C.c_int32, C.c_int32, C.c_double, I, D],
-        "ttcf_cv_attach": [V, C.c_int64, C.c_int32],
+        "ttcf_cv_attach": [V, C.c_int64, C.c_int32, C.c_int32],
+        "ttcf_cv_calibrate": [V, C.c_double, C.c_int32, D],
         "ttcf_cv_mean_term": [V, C.c_int32, C.c_int32, D, C.c_int64, C.c_int32, C.c_int32,
                               C.c_int64, C.c_double, L64],
-        "ttcf_cv_response": [V, C.c_double, C.c_int32, D, D, D, D, L64],
+        "ttcf_cv_response": [V, C.c_double, C.c_int32, D, D, D, D, D, D, L64],
+        "ttcf_sample_states_replicated": [V, C.c_int32, C.c_int32, D, C.c_int64, C.c_int32,
+                                          C.c_int64],
         "ttcf_mlp_forward": [V, F, C.c_int32, F],
         "ttcf_mlp_gradient": [V, F, F, C.c_int32, F],
     }
@@ -136,8 +141,9 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_export_series", "ttcf_daughter_health", "ttcf_debug_poison",
             "ttcf_debug_cell_list", "ttcf_debug_pairs", "ttcf_debug_forces", "ttcf_step_timing",
             "ttcf_set_step_shape", "ttcf_cv_init", "ttcf_cv_export_weights",
-            "ttcf_cv_add_training", "ttcf_cv_export_training", "ttcf_cv_train", "ttcf_cv_attach", "ttcf_cv_mean_term",
-            "ttcf_cv_response", "ttcf_mlp_forward", "ttcf_mlp_gradient"]
+            "ttcf_cv_add_training", "ttcf_cv_export_training", "ttcf_cv_train", "ttcf_cv_attach", "ttcf_cv_calibrate", "ttcf_cv_mean_term",
+            "ttcf_cv_response", "ttcf_mlp_forward", "ttcf_mlp_gradient",
+            "ttcf_sample_states_replicated"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -323,6 +329,15 @@ class Context:
         _check(lib().ttcf_import_states(self._ctx, int(mother), ns, _dp(r), _dp(p)),
                "ttcf_import_states", self._ctx)
 
+    def ttcf_sample_states_replicated(self, mother: int, n_replicas: int, kicks,
+                                      decorrelate_steps: int, states_per_replica: int,
+                                      steps_between: int):
+        k = None if kicks is None else _f64(kicks).ravel()
+        _check(lib().ttcf_sample_states_replicated(self._ctx, int(mother), int(n_replicas), _dp(k),
+                                                   int(decorrelate_steps), int(states_per_replica),
+                                                   int(steps_between)),
+               "ttcf_sample_states_replicated", self._ctx)
+
     def ttcf_export_states(self, mother: int, n_states: int):
         n = self.systems[mother].n_atoms
         r = np.zeros((n_states, 3 * n))
@@ -420,9 +435,16 @@ class Context:
                                    _dp(loss)), "ttcf_cv_train", self._ctx)
         return loss[:int(epochs)]
 
-    def ttcf_cv_attach(self, first: int, count: int):
-        _check(lib().ttcf_cv_attach(self._ctx, int(first), int(count)), "ttcf_cv_attach",
-               self._ctx)
+    def ttcf_cv_attach(self, first: int, count: int, role: int = 1):
+        """role 1 (TTCF_CV_ESTIMATE) or 2 (TTCF_CV_CALIBRATE)."""
+        _check(lib().ttcf_cv_attach(self._ctx, int(first), int(count), int(role)),
+               "ttcf_cv_attach", self._ctx)
+
+    def ttcf_cv_calibrate(self, n_t: int, gamma_dot_filter: float):
+        beta = np.zeros(n_t)
+        _check(lib().ttcf_cv_calibrate(self._ctx, float(gamma_dot_filter), int(n_t), _dp(beta)),
+               "ttcf_cv_calibrate", self._ctx)
+        return beta
 
     def ttcf_cv_mean_term(self, mother: int, n_replicas: int, kicks, decorrelate_steps: int,
                           rounds: int, states_per_replica: int, steps_between: int,
@@ -437,13 +459,13 @@ class Context:
         return out.value
 
     def ttcf_cv_response(self, n_t: int, gamma_dot_filter: float):
-        """(cv_mean, cv_se, mu_h, mu_h_se, n_states)."""
-        out = [np.zeros(n_t) for _ in range(4)]
+        """(cv_mean, cv_se, plain_mean, plain_se, mu_h, mu_h_se, n_states)."""
+        out = [np.zeros(n_t) for _ in range(6)]
         used = C.c_int64(0)
         _check(lib().ttcf_cv_response(self._ctx, float(gamma_dot_filter), int(n_t),
                                       *[_dp(o) for o in out], C.byref(used)),
                "ttcf_cv_response", self._ctx)
-        return out[0], out[1], out[2], out[3], used.value
+        return (*out, used.value)
 
     def ttcf_mlp_forward(self, x):
         x = _f32(x)

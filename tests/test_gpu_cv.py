@@ -262,7 +262,9 @@ def test_cv_estimate_and_mean_term_match_oracle(T, orc, cfg):
         tm, tse, _, _, _ = ctx.ttcf_response(N_OUT + 1, GD)
         cnt = ctx.ttcf_cv_mean_term(mid, 1, None, 0, 1, n_mean, n_between, GD)
         assert cnt == n_mean
-        cm, cse, mu, mu_se, used = ctx.ttcf_cv_response(N_OUT + 1, GD)
+        cm, cse, pm, pse, mu, mu_se, used = ctx.ttcf_cv_response(N_OUT + 1, GD)
+        np.testing.assert_array_equal(pm, tm)  # same groups, same kernel
+        np.testing.assert_array_equal(pse, tse)
         assert used == 16
         # the mother itself did not move
         r_m, p_m, _, steps = ctx.ttcf_export_mother(mid)
@@ -296,3 +298,59 @@ def test_cv_estimate_and_mean_term_match_oracle(T, orc, cfg):
     g_n = orc.ttcf_response(vo / s.volume, vo[:, 0], np.full(64, GD), s.temperature, s.dt).g
     resid = g_n - hn
     np.testing.assert_allclose(cse, resid.std(axis=0, ddof=1) / 4.0, atol=2e-3 * hscale)
+
+
+def test_calibrated_cv_matches_oracle(T, orc, cfg):
+    """Start states 0-7 calibrate beta(t) = Cov(G, H) / Var(H); states 8-15 form the
+    estimate mean[G - beta H] + beta mu_H. Everything against the oracle's own daughters,
+    network and mother."""
+    s, box, sr, sp = cfg
+    say("calibrated cv")
+    n_between, n_mean = 25, 6
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        first = ctx.ttcf_spawn_daughters(mid, 16, 0, GD, N_OUT)
+        ctx.ttcf_step(N_OUT)
+        w32, net = seeded_net(N_OUT, seed=23)
+        ctx.ttcf_cv_init(N_OUT, w32)
+        ctx.ttcf_cv_add_training(first, 64)
+        ctx.ttcf_cv_train(0, 64, 1e-3)
+        ctx.ttcf_cv_attach(first, 32, T.TTCF_CV_CALIBRATE)
+        ctx.ttcf_cv_attach(first + 32, 32, T.TTCF_CV_ESTIMATE)
+        assert ctx.ttcf_accumulate() == 16
+        beta = ctx.ttcf_cv_calibrate(N_OUT + 1, GD)
+        ctx.ttcf_cv_mean_term(mid, 1, None, 0, 1, n_mean, n_between, GD)
+        cm, cse, pm, pse, bmu, bmu_se, used = ctx.ttcf_cv_response(N_OUT + 1, GD)
+    assert used == 8
+    fo, b0, om = oracle_features(orc, box, s, sr, sp, range(16), GD)
+    state_of = np.repeat(np.arange(16), 4)
+    map_of = np.tile(np.arange(4), 16)
+    vo, _ = orc.run_daughters(box, sr, sp, state_of, map_of, np.full(64, GD), s.dt, N_OUT,
+                              nthreads=8)
+    fo32 = fo.astype(np.float32).astype(np.float64)
+    xmu, xinv = col_stats32(fo32)
+    ymu, yinv = col_stats32((vo[:, 1:] / s.volume).astype(np.float32).astype(np.float64))
+    hn = oracle_h(net, fo32, xmu, xinv, ymu, yinv, b0, om, s.dt).reshape(16, 4, -1).mean(axis=1)
+    g_n = orc.ttcf_response(vo / s.volume, vo[:, 0], np.full(64, GD), s.temperature, s.dt).g
+    gc, hc = g_n[:8], hn[:8]
+    cov = ((gc - gc.mean(axis=0)) * (hc - hc.mean(axis=0))).sum(axis=0)
+    var = ((hc - hc.mean(axis=0)) ** 2).sum(axis=0)
+    beta_ref = np.where(var > 0, cov / np.where(var > 0, var, 1.0), 0.0)
+    assert beta[0] == 0.0 and beta_ref[0] == 0.0
+    np.testing.assert_allclose(beta[1:], beta_ref[1:], rtol=2e-2, atol=2e-2)
+    st = orc.NHState(sr[0].copy(), sp[0].copy())
+    mr, mp = orc.mother_sample(box, st, 0, n_mean, n_between, s.temperature, s.dt,
+                               orc.nh_q(s.nf, s.temperature, TAU), s.nf)
+    fm, b0m, omm = oracle_features(orc, box, s, mr, mp, range(n_mean), GD)
+    mu_ref = oracle_h(net, fm.astype(np.float32).astype(np.float64), xmu, xinv, ymu, yinv, b0m,
+                      omm, s.dt).reshape(n_mean, 4, -1).mean(axis=1).mean(axis=0)
+    ge, he = g_n[8:], hn[8:]
+    hscale = np.abs(he).max()
+    close_plain = np.abs(pm - ge.mean(axis=0)).max() <= 1e-7 * np.abs(ge).max()
+    assert close_plain
+    np.testing.assert_allclose(bmu, beta_ref * mu_ref, atol=3e-2 * hscale)
+    cv_ref = (ge - beta_ref * he).mean(axis=0) + beta_ref * mu_ref
+    np.testing.assert_allclose(cm, cv_ref, atol=3e-2 * hscale)
+    se_ref = (ge - beta_ref * he).std(axis=0, ddof=1) / np.sqrt(8)
+    np.testing.assert_allclose(cse, se_ref, rtol=5e-2, atol=3e-2 * hscale)

@@ -174,6 +174,34 @@ def test_mother_short_trajectory(T, orc, precision, tol):
     assert zg == pytest.approx(st.zeta, rel=100 * tol, abs=100 * tol)
 
 
+def test_replicated_sampling_matches_oracle(T, orc, cfg1):
+    """Copies of the mother, each kicked by a seeded zero-sum momentum change, decorrelated and
+    sampled in one launch: every stored state equals the oracle's mother run from the same
+    kicked start, and the mother itself does not move."""
+    s, box, sr, sp = cfg1
+    n_rep, per, between, decor = 3, 4, 10, 20
+    rng = np.random.Generator(np.random.PCG64(77))
+    kicks = 1e-3 * rng.standard_normal((n_rep, 3, s.n))
+    kicks -= kicks.mean(axis=2, keepdims=True)
+    kicks = kicks.reshape(n_rep, 3 * s.n)
+    say("replicated mother sampling")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 0), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_sample_states_replicated(mid, n_rep, kicks, decor, per, between)
+        gr, gp = ctx.ttcf_export_states(mid, n_rep * per)
+        rm, pm, _, steps = ctx.ttcf_export_mother(mid)
+    assert steps == 0 and np.array_equal(rm, sr[0]) and np.array_equal(pm, sp[0])
+    q = orc.nh_q(s.nf, s.temperature, TAU)
+    for k in range(n_rep):
+        st = orc.NHState(sr[0].copy(), sp[0] + kicks[k])
+        orr, orp = orc.mother_sample(box, st, decor, per, between, s.temperature, s.dt, q, s.nf)
+        for j in range(per):
+            dr = gr[k * per + j] - orr[j]
+            dr -= s.box * np.rint(dr / s.box)
+            assert np.abs(dr).max() / s.box <= 1e-9
+            assert np.abs(gp[k * per + j] - orp[j]).max() / np.sqrt(np.mean(orp[j] ** 2)) <= 1e-9
+
+
 @pytest.mark.parametrize("precision,variant,tol", [(0, 1, 1e-9), (1, 1, 1e-4), (1, 2, 1e-4)])
 @pytest.mark.parametrize("gd", [1e-3, 1.0])
 def test_daughter_trajectories(T, orc, cfg1, precision, variant, tol, gd):

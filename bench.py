@@ -237,6 +237,9 @@ def main():
     ap.add_argument("--kmax", type=int, default=0, help="neighbour-list capacity (0: default)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 to skip)")
+    ap.add_argument("--cv", type=int, default=1,
+                    help="1: also measure the learned control variate (N=256, shear rate 1e-4 "
+                         "workload) and report it under 'cv'")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (a kernel of known "
                          "traffic, used to calibrate the HBM byte counters)")
@@ -343,6 +346,11 @@ def main():
                           "ttcf_end": float(last[0][-1]), "ttcf_se_end": float(last[1][-1]),
                           "dav_end": float(last[2][-1]), "dav_se_end": float(last[3][-1])},
     }
+    if args.cv:
+        try:
+            line["cv"] = cv_leg(T, stream)
+        except Exception as e:  # the headline line is printed whatever happens here
+            line["cv"] = {"error": repr(e)}
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(args.n_cells, nst, args.cpu_budget)
     print(json.dumps(line), flush=True)

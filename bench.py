@@ -102,6 +102,39 @@ def cpu_baseline(n_cells: int, nsteps: int, budget_s: float):
     }
 
 
+def precision_statement(T, ctx, mid, sysd, s, n_states, nst, stream):
+    """FP32-force responses against FP64-force responses from the same start states, at each
+    shear rate: max over t of |difference| in units of the FP64 response's standard error, and
+    relative to the largest |TTCF|."""
+    r, p = ctx.ttcf_export_states(mid, n_states)
+    sys64 = T.make_system(s.n, s.box, s.temperature, s.dt, precision=0)
+    out = {}
+    for prec, tag in ((1, "fp32"), (0, "fp64")):
+        res = {}
+        with T.Context(stream) as c2:
+            sysp = sysd if prec == 1 else sys64
+            m2 = c2.ttcf_init_mother(sysp, r[0], p[0], n_equil=0)
+            c2.ttcf_import_states(m2, r, p)
+            for gd in GAMMAS:
+                c2.ttcf_spawn_daughters(m2, n_states, 0, gd, nst)
+            c2.ttcf_step(nst)
+            c2.ttcf_accumulate()
+            for gd in GAMMAS:
+                res[gd] = c2.ttcf_response(nst + 1, gd)
+        out[tag] = res
+    stmt = {}
+    for gd in GAMMAS:
+        a, b = out["fp32"][gd], out["fp64"][gd]
+        k = slice(1, None)
+        stmt[str(gd)] = {
+            "ttcf_max_err_over_se": float(np.max(np.abs(a[0][k] - b[0][k]) / b[1][k])),
+            "ttcf_max_rel_err": float(np.max(np.abs(a[0] - b[0])) / np.max(np.abs(b[0]))),
+            "dav_max_err_over_se": float(np.max(np.abs(a[2][k] - b[2][k]) / b[3][k])),
+        }
+    return {"reference": "same start states, FP64 pair forces (the FP64 form matches the "
+                         "oracle to 1e-9 over 50 steps)", "per_shear_rate": stmt}
+
+
 def seeded_kicks(n_rep: int, n: int, scale: float, seed: int):
     """Zero-sum momentum kicks, one set per mother copy (numpy PCG64, seeded)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -237,6 +270,9 @@ def main():
     ap.add_argument("--kmax", type=int, default=0, help="neighbour-list capacity (0: default)")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline (0 to skip)")
+    ap.add_argument("--fp64-check", type=int, default=1,
+                    help="1: rerun the batch's start states with FP64 forces at every shear rate "
+                         "and report the FP32-force error of each response")
     ap.add_argument("--cv", type=int, default=1,
                     help="1: also measure the learned control variate (N=256, shear rate 1e-4 "
                          "workload) and report it under 'cv'")
@@ -302,6 +338,9 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms, launches = ctx.ttcf_step_timing(reset=True)
+    precision = None
+    if args.precision == 1 and args.fp64_check:
+        precision = precision_statement(T, ctx, mid, sysd, s, args.states, nst, stream)
     ctx.close()
 
     atom_steps = n_d * s.n * nst
@@ -346,6 +385,8 @@ def main():
                           "ttcf_end": float(last[0][-1]), "ttcf_se_end": float(last[1][-1]),
                           "dav_end": float(last[2][-1]), "dav_se_end": float(last[3][-1])},
     }
+    if precision is not None:
+        line["precision"] = precision
     if args.cv:
         try:
             line["cv"] = cv_leg(T, stream)

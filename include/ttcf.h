@@ -199,9 +199,11 @@ int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, 
 /* Shape of the daughter step kernel (the knobs a tuner searches). variant: 0 automatic,
  * 1 cell list rebuilt every step (FP64 or FP32 forces), 2 neighbour lists of radius
  * r_cut + skin rebuilt when needed (FP32 forces only); threads: workgroup size (0: the
- * system's block_threads or the library's choice); skin <= 0 and kmax <= 0 select the defaults
- * (0.25 sigma, 24 neighbours per atom). Affects the following ttcf_step calls; results do
- * not depend on the skin (lists are sorted, and pairs beyond r_cut contribute nothing). */
+ * system's block_threads, else the library's choice: 512 for the list form up to 2048 atoms);
+ * skin <= 0 selects the automatic skin (the list-cell grid of a 0.25 sigma skin, with the skin
+ * widened to fill those cells); kmax <= 0 selects 24 neighbours per atom. Affects the
+ * following ttcf_step calls; results do not depend on the skin (lists are sorted, and pairs
+ * beyond r_cut contribute nothing). */
 int32_t ttcf_set_step_shape(ttcf_ctx* ctx, int32_t variant, int32_t threads, double skin,
                             int32_t kmax);
 

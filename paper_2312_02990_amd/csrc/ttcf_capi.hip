@@ -150,7 +150,7 @@ struct ttcf_ctx {
     double cv_beta_gamma = 0.0;
     // shape of the daughter step kernel
     int32_t shape_variant = 0, shape_threads = 0, shape_kmax = 24;
-    double shape_skin = 0.25;
+    double shape_skin = 0.0;  // <= 0: automatic (see auto_skin)
     int32_t last_variant = -1;
     // timing of the step kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
@@ -214,7 +214,21 @@ int32_t build_sysdev(const ttcf_system* s, SysDev* d, std::string* why) {
 
 // List-build grid of the neighbour-list form for a given skin; false if the box is too
 // small for a 27-cell stencil of that reach.
+// Automatic skin: the list grid of a 0.25 sigma skin, with the skin widened to fill its
+// cells (cell width minus the cutoff, in the narrowest direction). Fewer rebuilds for the
+// same candidate count per rebuild.
+double auto_skin(const SysDev& d) {
+    const double base = d.rc + 0.25;
+    double w = d.box[0];
+    for (int a = 0; a < 3; ++a) {
+        const double n = std::floor(d.box[a] / base);
+        if (n >= 1.0) w = std::min(w, d.box[a] / n);
+    }
+    return std::max(0.25, w * (1.0 - 1e-9) - d.rc);
+}
+
 bool set_list_grid(SysDev* d, double skin) {
+    if (!(skin > 0.0)) skin = auto_skin(*d);
     const double reach = d->rc + skin;
     d->skin = skin;
     for (int a = 0; a < 3; ++a) {
@@ -710,6 +724,10 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
     if (c->shape_threads > 0) threads = c->shape_threads;
     apt = pick_apt(nmax, threads);
     if (apt < 0) return fail(c, TTCF_EINVAL, "batch needs more than 4 atoms per thread");
+    bool explicit_threads = c->shape_threads > 0;
+    for (int32_t i : order)
+        explicit_threads = explicit_threads ||
+                           c->mothers[c->batches[c->live[i].batch].mother].sys.block_threads > 0;
     // kernel form: neighbour lists when asked for or (automatic) when the FP32 form fits
     int variant = kVariantCells;
     int lcmax = 0;
@@ -730,6 +748,12 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
     if (variant == kVariantNeighbourList) {
         rc = push_descs(c);  // the list grids were just written into the descriptors
         if (rc != TTCF_OK) return rc;
+        // 512 threads with up to 4 atoms each keep the list form free of register spills
+        // (at 1024 threads a lane has 128 registers and spills); measured faster at N = 2048
+        if (!explicit_threads && nmax <= 4 * 512) {
+            threads = std::min(512, pick_threads(nmax, 0));
+            apt = pick_apt(nmax, threads);
+        }
     }
     c->last_variant = variant;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
@@ -782,7 +806,7 @@ int32_t ttcf_set_step_shape(ttcf_ctx* c, int32_t variant, int32_t threads, doubl
         return TTCF_EINVAL;
     c->shape_variant = variant;
     c->shape_threads = threads;
-    c->shape_skin = skin > 0.0 ? skin : 0.25;
+    c->shape_skin = skin > 0.0 ? skin : 0.0;
     c->shape_kmax = kmax > 0 ? kmax : 24;
     return TTCF_OK;
 }

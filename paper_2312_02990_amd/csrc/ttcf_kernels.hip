@@ -60,8 +60,22 @@ __device__ __forceinline__ double wrap1(double x, double l) {
     return x;
 }
 
+// Lees-Edwards offset fmod(gamma_dot L_y (k dt), L_x), from the integer step counter. The
+// remainder v - q L_x of the right integer q is exactly representable, so one fused
+// multiply-add gives it exactly (the same bits as fmod); q from the rounded quotient can be
+// off by one, which the two checks correct.
 __device__ __forceinline__ double le_offset(const SysDev& S, double gamma_dot, int64_t k) {
-    return fmod(gamma_dot * S.box[1] * ((double)k * S.dt), S.box[0]);
+    const double v = gamma_dot * S.box[1] * ((double)k * S.dt);
+    const double lx = S.box[0];
+    const double av = fabs(v);
+    if (av < lx) return v;
+    const double q = floor(av / lx);
+    double r = __builtin_fma(-lx, q, av);
+    if (r < 0.0)
+        r = __builtin_fma(-lx, q - 1.0, av);
+    else if (r >= lx)
+        r = __builtin_fma(-lx, q + 1.0, av);
+    return v < 0.0 ? -r : r;
 }
 
 // Sliding-brick wrap of one atom after a move (y crossing shifts x by -+ dxle).
@@ -1192,10 +1206,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_debug_pairs(SysDev S, double dx
 struct NlLds {
     uint4* posq;       // [nmax] fixed-point positions (X, Y, Z, unused)
     uint16_t* nbr;     // [kmax][nmax] neighbour ids, column a = atom a
-    uint16_t* ncnt;    // [nmax]
+    uint32_t* ncnt;    // [nmax] list lengths
     int32_t* cnt;      // [cmax] list-grid cell counts / cursors
     int32_t* start;    // [cmax + 1]
-    uint16_t* sid;     // [nmax] atoms grouped by list-grid cell
+    uint16_t* sid;     // [nmax + 4] atoms grouped by list-grid cell (4 entries of padding)
     int32_t* rowinfo;  // [3 rows][2]: first column offset mod nx, column count
     double* red;       // block-reduction scratch
     int32_t* scan;     // [kMaxWaves]
@@ -1218,11 +1232,11 @@ __host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax) {
         return at;
     };
     p.posq = take(16 * (size_t)nmax, 16);
-    p.nbr = take(2 * (size_t)kmax * nmax, 16);
-    p.ncnt = take(2 * (size_t)nmax, 16);
+    p.nbr = take(2 * (size_t)(kmax + 1) * nmax, 16);  // row kmax: sink for rejected candidates
+    p.ncnt = take(4 * (size_t)nmax, 16);
     p.cnt = take(4 * (size_t)cmax, 16);
     p.start = take(4 * (size_t)(cmax + 1), 16);
-    p.sid = take(2 * (size_t)nmax, 16);
+    p.sid = take(2 * (size_t)(nmax + 4), 16);  // 4 padding entries: reads past a range stay inside
     p.rowinfo = take(4 * 8, 16);
     p.red = take(sizeof(double) * (kMaxWaves * kRedSlots + kRedSlots), 16);
     p.scan = take(4 * kMaxWaves, 16);
@@ -1238,7 +1252,7 @@ __device__ inline NlLds carve_nl(char* base, int nmax, int cmax, int kmax) {
     NlLds L;
     L.posq = (uint4*)(base + p.posq);
     L.nbr = (uint16_t*)(base + p.nbr);
-    L.ncnt = (uint16_t*)(base + p.ncnt);
+    L.ncnt = (uint32_t*)(base + p.ncnt);
     L.cnt = (int32_t*)(base + p.cnt);
     L.start = (int32_t*)(base + p.start);
     L.sid = (uint16_t*)(base + p.sid);
@@ -1278,7 +1292,7 @@ __device__ __forceinline__ void fix_sep(uint32_t xi, uint32_t yi, uint32_t zi, c
 // then every owner collects its atoms' neighbours within rc + skin over the 27-cell stencil
 // (LE-displaced x range for rows across the y boundary) and sorts them by id.
 template <int APT>
-__device__ void nl_rebuild(const SysDev& S, double dxle, uint32_t dxq, const double (&x)[APT],
+__device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_t dxq, const double (&x)[APT],
                            const double (&y)[APT], const double (&z)[APT],
                            const uint32_t (&qx)[APT], const uint32_t (&qy)[APT],
                            const uint32_t (&qz)[APT], const NlLds& L, int kmax, int nmax) {
@@ -1341,49 +1355,59 @@ __device__ void nl_rebuild(const SysDev& S, double dxle, uint32_t dxq, const dou
         const int c0 = cell[j];
         const int cx = c0 % nc0, cy = (c0 / nc0) % nc1, cz = c0 / (nc0 * nc1);
         int count = 0;
-        bool over = false;
+        // the cells of one stencil row are consecutive cell ids, so their atoms form one
+        // contiguous range of the sorted order (two when the row wraps around in x)
+        // branch-free: every candidate is written, rejected ones into the sink row kmax
+        const int sink = kmax * nmax + a;
+        int slot = a;  // count * nmax + a while count < kmax
+        auto scan = [&](int lo, int hi) {
 #pragma unroll 1
-        for (int dz = 0; dz < 3; ++dz) {
-            int zz = cz + dz - 1;
-            zz = zz < 0 ? zz + nc2 : (zz >= nc2 ? zz - nc2 : zz);
-#pragma unroll 1
-            for (int dy = 0; dy < 3; ++dy) {
-                int yy = cy + dy - 1;
-                int row = 1;
-                if (yy < 0) {
-                    yy += nc1;
-                    row = 0;
-                } else if (yy >= nc1) {
-                    yy -= nc1;
-                    row = 2;
+            for (int tt = lo; tt < hi; tt += 4) {
+                int jn[4];
+                uint4 q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    // unconditional load (the array is padded); a value past the range is
+                    // replaced before it is used as an index
+                    const int raw = L.sid[tt + u];
+                    jn[u] = tt + u < hi ? raw : a;
                 }
-                const int nq = L.rowinfo[2 * row + 1];
-                int xx = cx + L.rowinfo[2 * row];
-                if (xx >= nc0) xx -= nc0;
-                const int base = nc0 * (yy + nc1 * zz);
-#pragma unroll 1
-                for (int q = 0; q < nq; ++q) {
-                    const int c = base + xx;
-                    const int e = L.start[c + 1];
-                    for (int tt = L.start[c]; tt < e; ++tt) {
-                        const int jn = L.sid[tt];
-                        if (jn == a) continue;
-                        float ddx, ddy, ddz;
-                        fix_sep(qx[j], qy[j], qz[j], L.posq[jn], dxq, S, ddx, ddy, ddz);
-                        if (ddx * ddx + ddy * ddy + ddz * ddz < rl2) {
-                            if (count < kmax)
-                                L.nbr[count * nmax + a] = (uint16_t)jn;
-                            else
-                                over = true;
-                            ++count;
-                        }
-                    }
-                    ++xx;
-                    if (xx >= nc0) xx -= nc0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[u] = L.posq[jn[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    float ddx, ddy, ddz;
+                    fix_sep(qx[j], qy[j], qz[j], q[u], dxq, S, ddx, ddy, ddz);
+                    const bool hit = (jn[u] != a) & (ddx * ddx + ddy * ddy + ddz * ddz < rl2);
+                    const bool room = hit & (count < kmax);
+                    L.nbr[room ? slot : sink] = (uint16_t)jn[u];
+                    slot += room ? nmax : 0;
+                    count += hit ? 1 : 0;
                 }
             }
+        };
+#pragma unroll 1
+        for (int r9 = 0; r9 < 9; ++r9) {
+            int zz = cz + r9 / 3 - 1;
+            zz = zz < 0 ? zz + nc2 : (zz >= nc2 ? zz - nc2 : zz);
+            int yy = cy + r9 % 3 - 1;
+            int row = 1;
+            if (yy < 0) {
+                yy += nc1;
+                row = 0;
+            } else if (yy >= nc1) {
+                yy -= nc1;
+                row = 2;
+            }
+            const int nq = L.rowinfo[2 * row + 1];
+            int x0 = cx + L.rowinfo[2 * row];
+            if (x0 >= nc0) x0 -= nc0;
+            const int base = nc0 * (yy + nc1 * zz);
+            const int xe = x0 + nq;
+            scan(L.start[base + x0], L.start[base + (xe < nc0 ? xe : nc0)]);
+            if (xe > nc0) scan(L.start[base], L.start[base + xe - nc0]);
         }
-        if (over) {
+        if (count > kmax) {
             L.misc[1] = 1;
             count = kmax;
         }
@@ -1397,7 +1421,7 @@ __device__ void nl_rebuild(const SysDev& S, double dxle, uint32_t dxq, const dou
             }
             L.nbr[(k + 1) * nmax + a] = v;
         }
-        L.ncnt[a] = (uint16_t)count;
+        L.ncnt[a] = (uint32_t)count;
     }
     for (int c = t; c < C; c += T) L.cnt[c] = 0;
     __syncthreads();
@@ -1407,8 +1431,8 @@ __device__ void nl_rebuild(const SysDev& S, double dxle, uint32_t dxq, const dou
 template <int APT>
 __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
                                             const uint32_t (&qx)[APT], const uint32_t (&qy)[APT],
-                                            const uint32_t (&qz)[APT], double (&fx)[APT],
-                                            double (&fy)[APT], double (&fz)[APT], const NlLds& L,
+                                            const uint32_t (&qz)[APT], float (&fx)[APT],
+                                            float (&fy)[APT], float (&fz)[APT], const NlLds& L,
                                             int nmax) {
     const int T = blockDim.x, t = threadIdx.x, n = S.n;
     const float rc2 = S.rc2_f;
@@ -1425,20 +1449,19 @@ __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
                 float dx, dy, dz;
                 fix_sep(qx[j], qy[j], qz[j], q, dxq, S, dx, dy, dz);
                 const float r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < rc2) {
-                    const float inv = recip(r2);
-                    const float s3 = inv * inv * inv;
-                    const float fs = s3 * (48.f * s3 - 24.f * ca) * inv;
-                    gx += fs * dx;
-                    gy += fs * dy;
-                    gz += fs * dz;
-                    w += dx * (fs * dy);
-                }
+                // listed pairs beyond the cutoff contribute an exact zero (no branch)
+                const float inv = recip(r2);
+                const float s3 = inv * inv * inv;
+                const float fs = r2 < rc2 ? s3 * (48.f * s3 - 24.f * ca) * inv : 0.f;
+                gx += fs * dx;
+                gy += fs * dy;
+                gz += fs * dz;
+                w += dx * (fs * dy);
             }
         }
-        fx[j] = (double)gx;
-        fy[j] = (double)gy;
-        fz[j] = (double)gz;
+        fx[j] = gx;
+        fy[j] = gy;
+        fz[j] = gz;
         wacc += (double)w;
     }
     return 0.5 * wacc;
@@ -1493,7 +1516,8 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     if (health != 0) todo = 0;
     if (todo <= 0 && done > 0) return;
 
-    double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT], fx[APT], fy[APT], fz[APT];
+    double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT];
+    float fx[APT], fy[APT], fz[APT];  // FP32 pair forces; every use below promotes them to FP64
     uint32_t qx[APT], qy[APT], qz[APT];
     float path[APT];
 #pragma unroll
@@ -1521,9 +1545,10 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
         m0[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
         m0[1] += px[j] * py[j];
         m0[2] += py[j] * py[j];
-        m0[3] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
-        m0[4] += fx[j] * py[j];
-        m0[5] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+        m0[3] += (double)fx[j] * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
+        m0[4] += (double)fx[j] * py[j];
+        m0[5] += (double)fx[j] * (double)fx[j] + (double)fy[j] * (double)fy[j] +
+                 (double)fz[j] * (double)fz[j];
     }
     block_sum<7>(m0, L.red);
     if (done == 0) {
@@ -1551,9 +1576,9 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             const double qxp = g1 * (px[j] - tg * py[j]);
             const double qyp = g1 * py[j];
             const double qzp = g1 * pz[j];
-            px[j] = (qxp + fx[j] * s1) * isd1;
-            py[j] = (qyp + fy[j] * s1) * isd1;
-            pz[j] = (qzp + fz[j] * s1) * isd1;
+            px[j] = (qxp + (double)fx[j] * s1) * isd1;
+            py[j] = (qyp + (double)fy[j] * s1) * isd1;
+            pz[j] = (qzp + (double)fz[j] * s1) * isd1;
         }
         // ---- streaming D(h), new strain, sliding-brick wrap, peculiar path length
         k += 1;
@@ -1589,13 +1614,14 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             m[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
             m[1] += px[j] * py[j];
             m[2] += py[j] * py[j];
-            m[3] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
-            m[4] += fx[j] * py[j];
-            m[5] += fy[j] * px[j];
-            m[6] += fx[j] * fy[j];
-            m[7] += fy[j] * py[j];
-            m[8] += fy[j] * fy[j];
-            m[9] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+            m[3] += (double)fx[j] * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
+            m[4] += (double)fx[j] * py[j];
+            m[5] += (double)fy[j] * px[j];
+            m[6] += (double)fx[j] * (double)fy[j];
+            m[7] += (double)fy[j] * py[j];
+            m[8] += (double)fy[j] * (double)fy[j];
+            m[9] += (double)fx[j] * (double)fx[j] + (double)fy[j] * (double)fy[j] +
+                    (double)fz[j] * (double)fz[j];
             m[11] += x[j] + y[j] + z[j];
         }
         block_sum<12>(m, L.red);
@@ -1612,9 +1638,9 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
         const double c = sqrt(2.0 * k0 / ppt2);
 #pragma unroll
         for (int j = 0; j < APT; ++j) {
-            const double qxp = (px[j] + fx[j] * s2) * isd2;
-            const double qyp = (py[j] + fy[j] * s2) * isd2;
-            const double qzp = (pz[j] + fz[j] * s2) * isd2;
+            const double qxp = (px[j] + (double)fx[j] * s2) * isd2;
+            const double qyp = (py[j] + (double)fy[j] * s2) * isd2;
+            const double qzp = (pz[j] + (double)fz[j] * s2) * isd2;
             px[j] = c * (qxp - tg * qyp);
             py[j] = c * qyp;
             pz[j] = c * qzp;

@@ -56,8 +56,8 @@ def _load():
     global _lib
     if _lib is None:
         path = os.path.join(_HERE, "libttcf_oracle.so")
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(
-                os.path.join(_HERE, "ttcf_oracle.c")):
+        if not os.path.exists(path) or any(
+                os.path.getmtime(path) < os.path.getmtime(src) for src in _build.SOURCES):
             _build.build()
         lib = C.CDLL(path)
         D = C.POINTER(C.c_double)

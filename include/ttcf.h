@@ -56,7 +56,9 @@ enum { TTCF_WCA = 0, TTCF_LJ = 1 };
  * every accumulated sum are FP64 in both forms. */
 enum { TTCF_PREC_FP64 = 0, TTCF_PREC_FP32_FORCES = 1 };
 
-enum { TTCF_OBS_PXY = 0 };
+/* Observables: P_xy (bulk); for the channel, the wall shear stress and the momentum
+ * profile (n_bins values per time point). */
+enum { TTCF_OBS_PXY = 0, TTCF_OBS_WALL_STRESS = 1, TTCF_OBS_VPROFILE = 2 };
 
 /* One simulated system (Example 1 of the paper: WCA fluid in a cubic periodic box). */
 typedef struct {
@@ -291,6 +293,91 @@ int32_t ttcf_mlp_forward(ttcf_ctx* ctx, const float* x, int32_t rows, float* y);
  * parameters, in the flat layout (n_weights floats into grad). */
 int32_t ttcf_mlp_gradient(ttcf_ctx* ctx, const float* x, const float* target, int32_t rows,
                           float* grad);
+
+/* ---- the confined channel (the paper's second example) -------------------------------
+ * Eq. system2: a Lennard-Jones liquid between two walls; wall atoms are tethered by springs
+ * of stiffness k to lattice sites, the lattices move along x at +v/2 (top) and -v/2 (bottom),
+ * and a Nose-Hoover thermostat acts on the wall atoms only. Pairs interact by
+ * 4[(1/r)^12 - c (1/r)^6] (shifted to vanish at r_cut) with c = c_ff (fluid-fluid) or c_wf
+ * (wall-fluid); wall atoms do not interact with each other. x and z are periodic; y is
+ * bounded by the walls. Integration: velocity Verlet with the thermostat's half steps around
+ * it (time reversible). FP32 pair forces, FP64 tethers, positions, momenta and sums.
+ * Dissipation function (Eq. TTCF2 with beta = 1/T and the sign of the adiabatic energy
+ * balance): Omega(0) = -(k v / (2 T)) S(0), S = sum_top (x^w - x^l) - sum_bottom (x^w - x^l).
+ * Observables B(t): TTCF_OBS_WALL_STRESS, [sum_{fluid i, top j} F_x,ij -
+ * sum_{fluid i, bottom j} F_x,ij] / (2 lx lz) (the method-of-planes stress at the
+ * interfaces); TTCF_OBS_VPROFILE, per bin of y in [bin_lo, bin_hi), the fluid's summed p_x
+ * over the bin volume.
+ * Mappings (Eq. mappings, applied to atoms and lattice sites): 1 reverses p and the
+ * thermostat variable; 2 reflects x and reverses p_x; 3 reflects x and reverses p_y, p_z and
+ * the thermostat variable. Arrays are SoA over all atoms: fluid first, then the bottom wall,
+ * then the top wall; lattice arrays are SoA over the wall atoms (bottom then top).
+ * Results are deterministic for a given sequence of calls. */
+typedef struct ttcf_channel_ctx ttcf_channel_ctx; /* opaque, owned by the library */
+
+typedef struct {
+    int32_t n_fluid;      /* fluid atoms                                                   */
+    int32_t n_wall;       /* wall atoms of both walls (even; the first half is the bottom) */
+    int32_t n_bins;       /* momentum-profile bins, 1..256                                 */
+    int32_t kmax;         /* neighbour-list capacity per atom (<= 0: 128)                  */
+    double lx, lz;        /* periodic edges                                                */
+    double y_extent;      /* every atom stays inside [0, y_extent)                         */
+    double r_cut, c_ff, c_wf, k_spring;
+    double temperature;   /* wall thermostat target                                        */
+    double dt, nh_tau;    /* thermostat mass Q = 3 N_w T nh_tau^2                          */
+    double bin_lo, bin_hi;
+    double skin;          /* neighbour-list skin (<= 0: 0.3)                               */
+} ttcf_channel;
+
+/* Alg. LAMMPS SCRIPT "initialise": a context holding the mother (positions r0, momenta p0,
+ * 3 n each; lattice sites, 3 n_wall; thermostat variable 0) on `stream`. */
+int32_t ttcf_channel_create(ttcf_channel_ctx** ctx, const ttcf_channel* ch, const double* r0,
+                            const double* p0, const double* lattice, void* stream);
+void ttcf_channel_destroy(ttcf_channel_ctx* ctx);
+const char* ttcf_channel_last_error(const ttcf_channel_ctx* ctx);
+/* "run N_t timestep": the equilibrium mother (lattices at rest) advances n_steps. */
+int32_t ttcf_channel_run_mother(ttcf_channel_ctx* ctx, int64_t n_steps);
+/* "run N_s timestep, save system state", n_states times: replaces the stored start states. */
+int32_t ttcf_channel_sample_states(ttcf_channel_ctx* ctx, int32_t n_states,
+                                   int64_t steps_between);
+/* Stored start states from / to host arrays: r, p (n_states x 3n), zeta (n_states). */
+int32_t ttcf_channel_import_states(ttcf_channel_ctx* ctx, int32_t n_states, const double* r,
+                                   const double* p, const double* zeta);
+int32_t ttcf_channel_export_states(ttcf_channel_ctx* ctx, int32_t n_states, double* r, double* p,
+                                   double* zeta);
+int32_t ttcf_channel_export_mother(ttcf_channel_ctx* ctx, double* r, double* p, double* zeta,
+                                   int64_t* steps);
+/* Map the first n_states stored states (mapping_mask as for the bulk), set the lattice speed
+ * v (n_v == 1, or one per state), daughters of n_steps steps, numbered state-major from
+ * *out_first. */
+int32_t ttcf_channel_spawn(ttcf_channel_ctx* ctx, int32_t n_states, uint32_t mapping_mask,
+                           const double* v, int32_t n_v, int32_t n_steps, int64_t* out_first);
+/* "run N_d timestep": every live daughter advances up to n_steps (one launch per batch),
+ * recording the observables after every step. Asynchronous. */
+int32_t ttcf_channel_step(ttcf_channel_ctx* ctx, int32_t n_steps);
+/* Fold finished batches into per-start-state rows (mapping means of B(t) and of
+ * int_0^t S(0) B(s) ds, compensated FP64); a group with an unhealthy daughter is excluded. */
+int32_t ttcf_channel_accumulate(ttcf_channel_ctx* ctx, int64_t* out_groups);
+/* Eq. TTCF and the direct average of one observable at lattice speed v_filter (exact match),
+ * k = 0..n_t-1; TTCF_OBS_VPROFILE writes n_t x n_bins values (bin fastest) per array. Block
+ * standard errors over start states. Any pointer may be NULL. */
+int32_t ttcf_channel_response(ttcf_channel_ctx* ctx, int32_t observable, double v_filter,
+                              int32_t n_t, double* ttcf_mean, double* ttcf_se, double* dav_mean,
+                              double* dav_se, int64_t* out_n_states);
+/* Inspection: recorded observables of live daughters (count x n_t x (1 + n_bins)) and their
+ * S(0); a daughter's state; its health word; one force evaluation of a configuration at the
+ * lattice sites given (f: 3n, out[0..2] = x force on the fluid from the top and from the
+ * bottom wall and S, out[3] = list overflow, out[4] = an atom outside [0, y_extent)); the
+ * device time of the step kernel. */
+int32_t ttcf_channel_export_series(ttcf_channel_ctx* ctx, int64_t first, int32_t count,
+                                   int32_t n_t, double* obs, double* s0);
+int32_t ttcf_channel_export_daughter(ttcf_channel_ctx* ctx, int64_t daughter, double* r,
+                                     double* p, double* zeta);
+int32_t ttcf_channel_daughter_health(ttcf_channel_ctx* ctx, int64_t daughter, int32_t* health);
+int32_t ttcf_channel_debug_forces(const ttcf_channel* ch, const double* r, const double* lattice,
+                                  double* f, double* out, void* stream);
+int32_t ttcf_channel_step_timing(ttcf_channel_ctx* ctx, double* total_ms, int64_t* launches,
+                                 int32_t reset);
 
 #ifdef __cplusplus
 }

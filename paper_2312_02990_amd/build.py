@@ -6,8 +6,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libttcf.so")
 SOURCES = [os.path.join(CSRC, "ttcf_kernels.hip"), os.path.join(CSRC, "ttcf_mlp.hip"),
-           os.path.join(CSRC, "ttcf_capi.hip")]
-HEADERS = [os.path.join(CSRC, "ttcf_internal.h"),
+           os.path.join(CSRC, "ttcf_capi.hip"), os.path.join(CSRC, "ttcf_channel.hip"),
+           os.path.join(CSRC, "ttcf_channel_capi.hip")]
+HEADERS = [os.path.join(CSRC, "ttcf_internal.h"), os.path.join(CSRC, "ttcf_channel.h"),
            os.path.join(os.path.dirname(HERE), "include", "ttcf.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

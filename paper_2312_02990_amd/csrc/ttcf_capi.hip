@@ -40,6 +40,15 @@ void dev_free(void* p) {
         (void)hipFree(p);
 }
 
+}  // namespace
+
+namespace ttcf {
+void* rt_alloc(size_t bytes, hipStream_t s) { return dev_alloc(bytes, s); }
+void rt_free(void* p) { dev_free(p); }
+}  // namespace ttcf
+
+namespace {
+
 // Device buffers of one call, freed on every return path (stream-ordered like dev_alloc).
 struct Scratch {
     hipStream_t s;

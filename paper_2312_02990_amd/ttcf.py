@@ -19,6 +19,8 @@ TTCF_OK, TTCF_EINVAL, TTCF_ENOMEM, TTCF_EDEVICE, TTCF_ESTATE, TTCF_EUNSTABLE = 0
 TTCF_WCA, TTCF_LJ = 0, 1
 TTCF_PREC_FP64, TTCF_PREC_FP32_FORCES = 0, 1
 TTCF_OBS_PXY = 0
+TTCF_OBS_WALL_STRESS = 1
+TTCF_OBS_VPROFILE = 2
 TTCF_CV_ESTIMATE = 1
 TTCF_CV_CALIBRATE = 2
 
@@ -35,6 +37,25 @@ class System(C.Structure):
                 ("temperature", C.c_double), ("dt", C.c_double), ("r_cut", C.c_double),
                 ("c_attr", C.c_double), ("u_shift", C.c_double), ("nh_tau", C.c_double),
                 ("precision", C.c_int32), ("block_threads", C.c_int32)]
+
+
+class Channel(C.Structure):
+    """ttcf_channel of include/ttcf.h."""
+    _fields_ = [("n_fluid", C.c_int32), ("n_wall", C.c_int32), ("n_bins", C.c_int32),
+                ("kmax", C.c_int32), ("lx", C.c_double), ("lz", C.c_double),
+                ("y_extent", C.c_double), ("r_cut", C.c_double), ("c_ff", C.c_double),
+                ("c_wf", C.c_double), ("k_spring", C.c_double), ("temperature", C.c_double),
+                ("dt", C.c_double), ("nh_tau", C.c_double), ("bin_lo", C.c_double),
+                ("bin_hi", C.c_double), ("skin", C.c_double)]
+
+
+def make_channel(geom, skin: float = 0.0, kmax: int = 0) -> Channel:
+    """From a ttcf_inputs.ChannelSystem."""
+    return Channel(int(geom.n_fluid), int(geom.n_wall), int(geom.n_bins), int(kmax),
+                   float(geom.lx), float(geom.lz), float(geom.y_extent), float(geom.rc),
+                   float(geom.c_ff), float(geom.c_wf), float(geom.k_spring),
+                   float(geom.temperature), float(geom.dt), float(geom.nh_tau),
+                   float(geom.bin_lo), float(geom.bin_hi), float(skin))
 
 
 def make_system(n_atoms: int, box, temperature: float = 0.722, dt: float = 0.0025,
@@ -76,11 +97,18 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(there is no CPU implementation of this library)")
+    # torch ships a HIP runtime of its own: load it first, so that this library binds to the
+    # same runtime (a second copy loaded earlier leaves torch's device discovery broken)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     D, I, L64, V = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_int64), C.c_void_p
     S = C.POINTER(System)
     P = C.POINTER(C.c_void_p)
     F = C.POINTER(C.c_float)
+    CH = C.POINTER(Channel)
     sig = {
         "ttcf_set_allocator": [_ALLOC, _FREE, V],
         "ttcf_init_mother": [P, S, D, D, C.c_int64, C.c_double, C.c_int64, V, I],
@@ -114,6 +142,21 @@ def lib():
         "ttcf_cv_mean_term": [V, C.c_int32, C.c_int32, D, C.c_int64, C.c_int32, C.c_int32,
                               C.c_int64, C.c_double, L64],
         "ttcf_cv_response": [V, C.c_double, C.c_int32, D, D, D, D, D, D, L64],
+        "ttcf_channel_create": [P, CH, D, D, D, V],
+        "ttcf_channel_run_mother": [V, C.c_int64],
+        "ttcf_channel_sample_states": [V, C.c_int32, C.c_int64],
+        "ttcf_channel_import_states": [V, C.c_int32, D, D, D],
+        "ttcf_channel_export_states": [V, C.c_int32, D, D, D],
+        "ttcf_channel_export_mother": [V, D, D, D, L64],
+        "ttcf_channel_spawn": [V, C.c_int32, C.c_uint32, D, C.c_int32, C.c_int32, L64],
+        "ttcf_channel_step": [V, C.c_int32],
+        "ttcf_channel_accumulate": [V, L64],
+        "ttcf_channel_response": [V, C.c_int32, C.c_double, C.c_int32, D, D, D, D, L64],
+        "ttcf_channel_export_series": [V, C.c_int64, C.c_int32, C.c_int32, D, D],
+        "ttcf_channel_export_daughter": [V, C.c_int64, D, D, D],
+        "ttcf_channel_daughter_health": [V, C.c_int64, I],
+        "ttcf_channel_debug_forces": [CH, D, D, D, D, V],
+        "ttcf_channel_step_timing": [V, D, L64, C.c_int32],
         "ttcf_sample_states_replicated": [V, C.c_int32, C.c_int32, D, C.c_int64, C.c_int32,
                                           C.c_int64],
         "ttcf_mlp_forward": [V, F, C.c_int32, F],
@@ -129,6 +172,10 @@ def lib():
     L.ttcf_strerror.restype = C.c_char_p
     L.ttcf_last_error.argtypes = [V]
     L.ttcf_last_error.restype = C.c_char_p
+    L.ttcf_channel_destroy.argtypes = [V]
+    L.ttcf_channel_destroy.restype = None
+    L.ttcf_channel_last_error.argtypes = [V]
+    L.ttcf_channel_last_error.restype = C.c_char_p
     _lib = L
     return L
 
@@ -143,7 +190,13 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_set_step_shape", "ttcf_cv_init", "ttcf_cv_export_weights",
             "ttcf_cv_add_training", "ttcf_cv_export_training", "ttcf_cv_train", "ttcf_cv_attach", "ttcf_cv_calibrate", "ttcf_cv_mean_term",
             "ttcf_cv_response", "ttcf_mlp_forward", "ttcf_mlp_gradient",
-            "ttcf_sample_states_replicated"]
+            "ttcf_sample_states_replicated", "ttcf_channel_create", "ttcf_channel_destroy",
+            "ttcf_channel_last_error", "ttcf_channel_run_mother", "ttcf_channel_sample_states",
+            "ttcf_channel_import_states", "ttcf_channel_export_states",
+            "ttcf_channel_export_mother", "ttcf_channel_spawn", "ttcf_channel_step",
+            "ttcf_channel_accumulate", "ttcf_channel_response", "ttcf_channel_export_series",
+            "ttcf_channel_export_daughter", "ttcf_channel_daughter_health",
+            "ttcf_channel_debug_forces", "ttcf_channel_step_timing"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -481,3 +534,149 @@ class Context:
         _check(lib().ttcf_mlp_gradient(self._ctx, _fp(x), _fp(t), int(x.shape[0]), _fp(g)),
                "ttcf_mlp_gradient", self._ctx)
         return g
+
+
+# ----------------------------------------------------------------------------------------
+# the confined channel
+# ----------------------------------------------------------------------------------------
+
+def ttcf_channel_debug_forces(ch: Channel, r, lattice, stream=None):
+    """(f (3n,), out[5]) of one configuration at the given lattice sites."""
+    r = _f64(r).ravel()
+    lat = _f64(lattice).ravel()
+    n = ch.n_fluid + ch.n_wall
+    f = np.zeros(3 * n)
+    out = np.zeros(5)
+    code = lib().ttcf_channel_debug_forces(C.byref(ch), _dp(r), _dp(lat), _dp(f), _dp(out), stream)
+    if code != 0:
+        detail = lib().ttcf_channel_last_error(None)
+        raise TTCFError(code, "ttcf_channel_debug_forces", detail.decode() if detail else "")
+    return f, out
+
+
+class ChannelContext:
+    """One ttcf_channel_ctx: the channel mother, its stored states, daughters and rows.
+    stream: a HIP stream handle (e.g. current_stream()), or None for the default stream."""
+
+    def __init__(self, ch: Channel, r0, p0, lattice, stream=None):
+        self.ch = ch
+        self.n = ch.n_fluid + ch.n_wall
+        self.n_obs = 1 + ch.n_bins
+        self._ctx = C.c_void_p(None)
+        r0 = _f64(r0).ravel()
+        p0 = _f64(p0).ravel()
+        lat = _f64(lattice).ravel()
+        assert r0.size == 3 * self.n and p0.size == 3 * self.n and lat.size == 3 * ch.n_wall
+        code = lib().ttcf_channel_create(C.byref(self._ctx), C.byref(ch), _dp(r0), _dp(p0),
+                                         _dp(lat), stream)
+        if code != 0:
+            detail = lib().ttcf_channel_last_error(None)
+            raise TTCFError(code, "ttcf_channel_create", detail.decode() if detail else "")
+
+    def _chk(self, code, where):
+        if code != 0:
+            detail = lib().ttcf_channel_last_error(self._ctx)
+            raise TTCFError(code, where, detail.decode() if detail else "")
+
+    def close(self):
+        if self._ctx:
+            lib().ttcf_channel_destroy(self._ctx)
+            self._ctx = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def run_mother(self, n_steps: int):
+        self._chk(lib().ttcf_channel_run_mother(self._ctx, int(n_steps)), "ttcf_channel_run_mother")
+
+    def sample_states(self, n_states: int, steps_between: int):
+        self._chk(lib().ttcf_channel_sample_states(self._ctx, int(n_states), int(steps_between)),
+                  "ttcf_channel_sample_states")
+
+    def import_states(self, r, p, zeta):
+        r = _f64(r)
+        p = _f64(p)
+        z = _f64(zeta)
+        self._chk(lib().ttcf_channel_import_states(self._ctx, int(r.shape[0]), _dp(r), _dp(p), _dp(z)),
+                  "ttcf_channel_import_states")
+
+    def export_states(self, n_states: int):
+        r = np.zeros((n_states, 3 * self.n))
+        p = np.zeros((n_states, 3 * self.n))
+        z = np.zeros(n_states)
+        self._chk(lib().ttcf_channel_export_states(self._ctx, int(n_states), _dp(r), _dp(p), _dp(z)),
+                  "ttcf_channel_export_states")
+        return r, p, z
+
+    def export_mother(self):
+        r = np.zeros(3 * self.n)
+        p = np.zeros(3 * self.n)
+        z = np.zeros(1)
+        steps = C.c_int64(0)
+        self._chk(lib().ttcf_channel_export_mother(self._ctx, _dp(r), _dp(p), _dp(z), C.byref(steps)),
+                  "ttcf_channel_export_mother")
+        return r, p, float(z[0]), steps.value
+
+    def spawn(self, n_states: int, v, n_steps: int, mapping_mask: int = 0xF) -> int:
+        vv = _f64(np.atleast_1d(v))
+        first = C.c_int64(-1)
+        self._chk(lib().ttcf_channel_spawn(self._ctx, int(n_states), int(mapping_mask), _dp(vv),
+                                           int(vv.size), int(n_steps), C.byref(first)),
+                  "ttcf_channel_spawn")
+        return first.value
+
+    def step(self, n_steps: int):
+        self._chk(lib().ttcf_channel_step(self._ctx, int(n_steps)), "ttcf_channel_step")
+
+    def accumulate(self) -> int:
+        g = C.c_int64(0)
+        self._chk(lib().ttcf_channel_accumulate(self._ctx, C.byref(g)), "ttcf_channel_accumulate")
+        return g.value
+
+    def response(self, observable: int, v_filter: float, n_t: int):
+        """(ttcf, ttcf_se, dav, dav_se, n_states); arrays (n_t,) or (n_t, n_bins)."""
+        cols = 1 if observable == TTCF_OBS_WALL_STRESS else self.ch.n_bins
+        out = [np.zeros(n_t * cols) for _ in range(4)]
+        used = C.c_int64(0)
+        self._chk(lib().ttcf_channel_response(self._ctx, int(observable), float(v_filter), int(n_t),
+                                              *[_dp(o) for o in out], C.byref(used)),
+                  "ttcf_channel_response")
+        shape = (n_t,) if cols == 1 else (n_t, cols)
+        return (*[o.reshape(shape) for o in out], used.value)
+
+    def export_series(self, first: int, count: int, n_t: int):
+        obs = np.zeros((count, n_t, self.n_obs))
+        s0 = np.zeros(count)
+        self._chk(lib().ttcf_channel_export_series(self._ctx, int(first), int(count), int(n_t),
+                                                   _dp(obs), _dp(s0)), "ttcf_channel_export_series")
+        return obs, s0
+
+    def export_daughter(self, daughter: int):
+        r = np.zeros(3 * self.n)
+        p = np.zeros(3 * self.n)
+        z = np.zeros(1)
+        self._chk(lib().ttcf_channel_export_daughter(self._ctx, int(daughter), _dp(r), _dp(p), _dp(z)),
+                  "ttcf_channel_export_daughter")
+        return r, p, float(z[0])
+
+    def daughter_health(self, daughter: int) -> int:
+        h = C.c_int32(0)
+        self._chk(lib().ttcf_channel_daughter_health(self._ctx, int(daughter), C.byref(h)),
+                  "ttcf_channel_daughter_health")
+        return h.value
+
+    def step_timing(self, reset: bool = False):
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        self._chk(lib().ttcf_channel_step_timing(self._ctx, C.byref(ms), C.byref(n), int(reset)),
+                  "ttcf_channel_step_timing")
+        return ms.value, n.value

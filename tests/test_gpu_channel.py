@@ -1,0 +1,141 @@
+"""Confined-channel path on the GPU against the FP64 channel oracle (runs on an MI355X).
+
+Inputs are seeded (ttcf_inputs) or produced by the oracle; the oracle never receives GPU
+output. Bars (FP32 pair forces on the GPU):
+  * forces: max |dF| <= 1e-5 * rms |F|; the walls' x forces on the fluid and S to 1e-5;
+  * trajectories over 50 steps: max |dr| / L, max |dp| / rms(p), observables, to 1e-4 of their
+    scale; S(0) of mapped daughters to 1e-12 (FP64 tethers, identical start states);
+  * responses: TTCF and direct average of both observables from the oracle's own daughters
+    and estimator agree to 1e-3 of the per-state series' scale, and within 2 SE.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import ttcf_inputs as I
+
+pytestmark = pytest.mark.gpu
+
+GEOM = I.ChannelSystem(n_x=7, n_z=10, n_fluid=420)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_2312_02990_amd import ttcf
+    ttcf.lib()
+    return ttcf
+
+
+@pytest.fixture(scope="module")
+def CHO():
+    from oracle import channel
+    return channel
+
+
+@pytest.fixture(scope="module")
+def states(CHO):
+    """Oracle mother: 400 steps from the seeded start, then 4 states 60 steps apart."""
+    g = GEOM
+    r, p, rl = I.channel_initial_state(g, 2)
+    c = CHO.make_channel(g)
+    q = CHO.nh_q(g.n_wall, g.temperature, g.nh_tau)
+    st = CHO.ChState(r.ravel().copy(), p.ravel().copy())
+    sr, sp, sz = CHO.mother_sample(c, st, rl.ravel(), 400, 4, 60, g.temperature, q, g.dt)
+    return c, q, rl.ravel().copy(), sr, sp, sz
+
+
+def test_forces_match_oracle(T, CHO, states):
+    c, q, rl, sr, sp, sz = states
+    say("channel forces")
+    ch = T.make_channel(GEOM)
+    for k in range(2):
+        f, out = T.ttcf_channel_debug_forces(ch, sr[k], rl)
+        fo, oo = CHO.forces(c, sr[k], rl)
+        rms = np.sqrt(np.mean(fo ** 2))
+        assert np.abs(f - fo).max() <= 1e-5 * rms
+        assert out[3] == 0 and out[4] == 0
+        assert out[0] == pytest.approx(oo[2], rel=1e-5, abs=1e-5 * rms)
+        assert out[1] == pytest.approx(oo[3], rel=1e-5, abs=1e-5 * rms)
+        assert out[2] == pytest.approx(oo[4], rel=1e-12, abs=1e-12)
+
+
+def test_mother_trajectory_matches_oracle(T, CHO, states):
+    c, q, rl, sr, sp, sz = states
+    say("channel mother 50 steps")
+    g = GEOM
+    with T.ChannelContext(T.make_channel(g), sr[0], sp[0], rl.reshape(3, -1)) as ctx:
+        ctx.run_mother(50)
+        rg, pg, zg, steps = ctx.export_mother()
+    assert steps == 50
+    st = CHO.ChState(sr[0].copy(), sp[0].copy(), 0.0)
+    CHO.run(c, st, rl, 50, g.temperature, q, g.dt)
+    dr = (rg - st.r).reshape(3, -1)
+    dr[0] -= g.lx * np.rint(dr[0] / g.lx)
+    dr[2] -= g.lz * np.rint(dr[2] / g.lz)
+    assert np.abs(dr).max() / g.lx <= 1e-4
+    assert np.abs(pg - st.p).max() / np.sqrt(np.mean(st.p ** 2)) <= 1e-4
+    assert zg == pytest.approx(st.zeta, abs=1e-4 * max(1.0, abs(st.zeta)))
+
+
+@pytest.fixture(scope="module")
+def daughters(T, CHO, states):
+    """4 states x 4 mappings, 50 steps at lattice speed 0.5, on the GPU and in the oracle."""
+    c, q, rl, sr, sp, sz = states
+    g = GEOM
+    nst, v = 50, 0.5
+    say("channel daughters")
+    with T.ChannelContext(T.make_channel(g), sr[0], sp[0], rl.reshape(3, -1)) as ctx:
+        ctx.import_states(sr, sp, sz)
+        first = ctx.spawn(4, v, nst)
+        ctx.step(20)
+        ctx.step(nst)
+        obs, s0 = ctx.export_series(first, 16, nst + 1)
+        fin = [ctx.export_daughter(first + d) for d in (0, 7, 15)]
+        health = [ctx.daughter_health(first + d) for d in range(16)]
+        assert ctx.accumulate() == 4
+        resp = {o: ctx.response(o, v, nst + 1) for o in (T.TTCF_OBS_WALL_STRESS, T.TTCF_OBS_VPROFILE)}
+    state_of = np.repeat(np.arange(4), 4)
+    map_of = np.tile(np.arange(4), 4)
+    oo, os0 = CHO.run_daughters(c, sr, sp, sz, rl, state_of, map_of, np.full(16, v), g.temperature,
+                                q, g.dt, nst)
+    return dict(obs=obs, s0=s0, fin=fin, health=health, resp=resp, oo=oo, os0=os0, v=v, nst=nst)
+
+
+def test_daughter_series_match_oracle(daughters):
+    d = daughters
+    assert all(h == 0 for h in d["health"])
+    np.testing.assert_allclose(d["s0"], d["os0"], rtol=1e-12, atol=1e-12)
+    oo, obs = d["oo"], d["obs"]
+    for col in (slice(0, 1), slice(1, None)):
+        scale = np.abs(oo[:, :, col]).max()
+        assert np.abs(obs[:, :, col] - oo[:, :, col]).max() <= 1e-4 * scale
+    # Eq. mappings on the GPU: S(0) of the four mapped daughters is (S, S, -S, -S)
+    s = d["s0"].reshape(4, 4)
+    np.testing.assert_allclose(s[:, 1], s[:, 0], rtol=1e-14)
+    np.testing.assert_allclose(s[:, 2], -s[:, 0], rtol=1e-12)
+    np.testing.assert_allclose(s[:, 3], -s[:, 0], rtol=1e-12)
+
+
+def test_channel_response_matches_oracle(CHO, daughters):
+    d = daughters
+    g = GEOM
+    ref = CHO.ttcf_response(d["oo"], d["os0"], np.full(16, d["v"]), g.k_spring, g.temperature, g.dt)
+    for o, cols in ((1, slice(0, 1)), (2, slice(1, None))):
+        tm, tse, dm, dse, used = d["resp"][o]
+        assert used == 4
+        rt, rse = ref.ttcf[:, cols], ref.ttcf_se[:, cols]
+        rd, rdse = ref.dav[:, cols], ref.dav_se[:, cols]
+        if o == 1:
+            rt, rse, rd, rdse = rt[:, 0], rse[:, 0], rd[:, 0], rdse[:, 0]
+        gscale = np.abs(ref.g[:, :, cols]).max()
+        dscale = np.abs(ref.d[:, :, cols]).max()
+        assert np.abs(tm - rt).max() <= 1e-3 * gscale
+        assert np.abs(dm - rd).max() <= 1e-3 * dscale
+        assert np.all(np.abs(tm - rt) <= 2.0 * np.hypot(tse, rse) + 1e-3 * gscale)
+        np.testing.assert_allclose(tse, rse, rtol=1e-2, atol=1e-3 * gscale)

@@ -135,6 +135,56 @@ def precision_statement(T, ctx, mid, sysd, s, n_states, nst, stream):
                          "oracle to 1e-9 over 50 steps)", "per_shear_rate": stmt}
 
 
+def channel_leg(T, stream, n_states=256, nst=1000, speeds=(1e-2, 1e-4), n_equil=2000,
+                between=20, seed=4):
+    """The confined channel at full size: 12000 fluid + 2 x 3000 tethered wall atoms, LJ
+    with wetting factors 1.2 / 0.6325, r_c = 2.5, k = 150, wall thermostat at T = 1,
+    dt = 0.005. One mother equilibrates n_equil steps and is sampled every `between` steps
+    (a throughput workload: the paper samples 5 time units apart); each lattice speed gets
+    n_states x 4 daughters of nst steps in one launch."""
+    import torch
+    import ttcf_inputs as I
+    g = I.ChannelSystem()
+    r, p, lat = I.channel_initial_state(g, seed)
+    out = {"workload": f"channel: {g.n_fluid} fluid + {g.n_wall} wall atoms, lx={g.lx:.2f}, "
+                       f"lz={g.lz:.2f}, gap={g.gap:.2f}; {n_states} states x 4 mappings x "
+                       f"{nst} steps per lattice speed, speeds {list(speeds)}"}
+    with T.ChannelContext(T.make_channel(g), r, p, lat, stream) as ctx:
+        t0 = time.perf_counter()
+        ctx.run_mother(n_equil)
+        ctx.sample_states(n_states, between)
+        torch.cuda.synchronize()
+        out["mother_s"] = time.perf_counter() - t0
+        out["mother_atom_steps_per_s"] = (n_equil + n_states * between) * g.n / out["mother_s"]
+        ctx.step_timing(reset=True)
+        t0 = time.perf_counter()
+        for v in speeds:
+            ctx.spawn(n_states, v, nst)
+            ctx.step(nst)
+            ctx.accumulate()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, launches = ctx.step_timing(reset=True)
+        atom_steps = len(speeds) * 4 * n_states * nst * g.n
+        out["kernel_atom_steps_per_s"] = atom_steps / (ms / 1e3)
+        out["end_to_end_atom_steps_per_s"] = atom_steps / wall
+        out["kernel_ms_per_launch"] = ms / max(launches, 1)
+        resp = {}
+        for v in speeds:
+            tm, tse, dm, dse, used = ctx.response(T.TTCF_OBS_WALL_STRESS, v, nst + 1)
+            pm, pse, pd, _, _ = ctx.response(T.TTCF_OBS_VPROFILE, v, nst + 1)
+            filled = np.nonzero(np.abs(pd).max(axis=0) > 0)[0]  # bins the fluid reaches
+            lo, hi = (int(filled[0]), int(filled[-1])) if filled.size else (0, 0)
+            resp[str(v)] = {"wall_stress_ttcf_end": float(tm[-1]), "se": float(tse[-1]),
+                            "wall_stress_dav_end": float(dm[-1]), "dav_se": float(dse[-1]),
+                            "profile_bins_filled": [lo, hi],
+                            "profile_ttcf_end_edge_bins": [float(pm[-1, lo]), float(pm[-1, hi])],
+                            "profile_se_end_edge_bins": [float(pse[-1, lo]), float(pse[-1, hi])],
+                            "n_states": int(used)}
+        out["responses"] = resp
+    return out
+
+
 def seeded_kicks(n_rep: int, n: int, scale: float, seed: int):
     """Zero-sum momentum kicks, one set per mother copy (numpy PCG64, seeded)."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -273,6 +323,8 @@ def main():
     ap.add_argument("--fp64-check", type=int, default=1,
                     help="1: rerun the batch's start states with FP64 forces at every shear rate "
                          "and report the FP32-force error of each response")
+    ap.add_argument("--channel", type=int, default=1,
+                    help="1: also measure the confined-channel workload (report under 'channel')")
     ap.add_argument("--cv", type=int, default=1,
                     help="1: also measure the learned control variate (N=256, shear rate 1e-4 "
                          "workload) and report it under 'cv'")
@@ -387,6 +439,11 @@ def main():
     }
     if precision is not None:
         line["precision"] = precision
+    if args.channel:
+        try:
+            line["channel"] = channel_leg(T, stream)
+        except Exception as e:  # the headline line is printed whatever happens here
+            line["channel"] = {"error": repr(e)}
     if args.cv:
         try:
             line["cv"] = cv_leg(T, stream)

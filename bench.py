@@ -135,6 +135,58 @@ def precision_statement(T, ctx, mid, sysd, s, n_states, nst, stream):
                          "oracle to 1e-9 over 50 steps)", "per_shear_rate": stmt}
 
 
+def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per_size=128,
+               nst=400, seed=31):
+    """Mixed system sizes in one step call: N in {500, 864, 2048, 4000} x rho in {0.7, 0.8442,
+    0.9}, one mother per (N, rho), 128 start states per N (state n at density index n mod 3),
+    a shear rate per state drawn log-uniformly in [1e-5, 1e-1] (shared by its four mapped
+    daughters), 400 steps, FP32 forces. Start states come from replicas of each mother
+    (kicked, decorrelated). The response is the per-unit-rate TTCF over all groups."""
+    import torch
+    import ttcf_inputs as I
+    ctx = T.Context(stream)
+    t0 = time.perf_counter()
+    total_atoms = 0
+    spawned = []
+    rates = I.log_uniform_rates(len(sizes) * per_size, 1e-5, 1e-1, seed)
+    ri = 0
+    for nc in sizes:
+        for di, rho in enumerate(densities):
+            count = len([k for k in range(per_size) if k % len(densities) == di])
+            s = I.System(nc, density=rho)
+            r0, p0 = I.initial_state(s, 3000 + 10 * nc + di)
+            mid = ctx.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1),
+                                       r0, p0, n_equil=1000, n_melt=1000, t_melt=2.0)
+            n_rep = count
+            ctx.ttcf_sample_states_replicated(mid, n_rep, seeded_kicks(n_rep, s.n, 0.05, seed + mid),
+                                              200, 1, 50)
+            spawned.append((mid, count, s.n, rates[ri:ri + count]))
+            ri += count
+    torch.cuda.synchronize()
+    mother_s = time.perf_counter() - t0
+    for mid, count, n, g in spawned:
+        ctx.ttcf_spawn_daughters(mid, count, 0, g, nst)
+        total_atoms += 4 * count * n
+    ctx.ttcf_step_timing(reset=True)
+    t0 = time.perf_counter()
+    ctx.ttcf_step(nst)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms, launches = ctx.ttcf_step_timing(reset=True)
+    groups = ctx.ttcf_accumulate()
+    tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, 0.0)
+    ctx.close()
+    atom_steps = total_atoms * nst
+    return {"workload": f"sizes {[4 * n ** 3 for n in sizes]} x densities {list(densities)}, "
+                        f"{per_size} states per size x 4 mappings, {nst} steps, per-state shear "
+                        f"rates log-uniform in [1e-5, 1e-1]",
+            "daughters": 4 * len(sizes) * per_size, "kernel_launches": launches,
+            "kernel_atom_steps_per_s": atom_steps / (ms / 1e3),
+            "end_to_end_atom_steps_per_s": atom_steps / wall, "mothers_s": mother_s,
+            "healthy_groups": int(groups),
+            "per_unit_rate_ttcf_end": float(tm[-1]), "per_unit_rate_ttcf_se_end": float(tse[-1])}
+
+
 def channel_leg(T, stream, n_states=256, nst=1000, speeds=(1e-2, 1e-4), n_equil=2000,
                 between=20, seed=4):
     """The confined channel at full size: 12000 fluid + 2 x 3000 tethered wall atoms, LJ
@@ -323,6 +375,8 @@ def main():
     ap.add_argument("--fp64-check", type=int, default=1,
                     help="1: rerun the batch's start states with FP64 forces at every shear rate "
                          "and report the FP32-force error of each response")
+    ap.add_argument("--uneven", type=int, default=1,
+                    help="1: also measure the mixed-size batch (report under 'uneven')")
     ap.add_argument("--channel", type=int, default=1,
                     help="1: also measure the confined-channel workload (report under 'channel')")
     ap.add_argument("--cv", type=int, default=1,
@@ -439,6 +493,11 @@ def main():
     }
     if precision is not None:
         line["precision"] = precision
+    if args.uneven:
+        try:
+            line["uneven"] = uneven_leg(T, stream)
+        except Exception as e:  # the headline line is printed whatever happens here
+            line["uneven"] = {"error": repr(e)}
     if args.channel:
         try:
             line["channel"] = channel_leg(T, stream)

@@ -709,65 +709,84 @@ int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int6
     return TTCF_OK;
 }
 
+// Launch shape of one group of daughters in one kernel form.
+int32_t plan_group(ttcf_ctx* c, const std::vector<int32_t>& group, int variant, int precision,
+                   int32_t n_steps, BatchLaunch* L) {
+    int nmax = 0, cmax = 0, lcmax = 0, threads = 0;
+    bool explicit_threads = c->shape_threads > 0;
+    for (int32_t i : group) {
+        const DaughterDesc& d = c->descs[i];
+        nmax = std::max(nmax, d.sys.n);
+        cmax = std::max(cmax, d.sys.nc[0] * d.sys.nc[1] * d.sys.nc[2]);
+        lcmax = std::max(lcmax, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2]);
+        threads = std::max(threads, d.block);
+        explicit_threads = explicit_threads ||
+                           c->mothers[c->batches[c->live[i].batch].mother].sys.block_threads > 0;
+    }
+    if (c->shape_threads > 0) threads = c->shape_threads;
+    // 512 threads with up to 4 atoms each keep the list form free of register spills
+    // (at 1024 threads a lane has 128 registers and spills); measured faster at N = 2048
+    if (variant == kVariantNeighbourList && !explicit_threads && nmax <= 4 * 512)
+        threads = std::min(512, pick_threads(nmax, 0));
+    const int apt = pick_apt(nmax, threads);
+    if (apt < 0) return fail(c, TTCF_EINVAL, "batch needs more than 4 atoms per thread");
+    *L = BatchLaunch{};
+    L->descs = c->d_descs;
+    L->n_jobs = (int32_t)group.size();
+    L->queue = c->d_queue;
+    L->max_steps = n_steps;
+    L->threads = threads;
+    L->apt = apt;
+    L->precision = precision;
+    L->nmax = nmax;
+    L->cmax = variant == kVariantNeighbourList ? lcmax : cmax;
+    L->variant = variant;
+    L->kmax = c->shape_kmax;
+    L->lds_bytes = variant == kVariantNeighbourList ? lds_bytes_nl(nmax, lcmax, c->shape_kmax)
+                                                    : lds_bytes_for(nmax, cmax, threads, precision);
+    if (L->lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
+    const int per_cu_lds = (int)(c->max_lds / L->lds_bytes);
+    const int per_cu_waves = 32 / (threads / 64);  // 8 waves per SIMD, 4 SIMDs
+    const int per_cu = std::max(1, std::min(per_cu_lds, per_cu_waves));
+    L->grid = std::min<int>(L->n_jobs, per_cu * c->num_cu);
+    return TTCF_OK;
+}
+
 int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
     if (!c || n_steps < 0) return TTCF_EINVAL;
     if (c->descs.empty() || n_steps == 0) return TTCF_OK;
     int32_t rc = sync_descs(c);
     if (rc != TTCF_OK) return rc;
-    // daughters still to run, largest systems first; one launch shape for all
-    std::vector<int32_t> order;
-    int nmax = 0, cmax = 0, threads = 0, apt = 1, precision = -1;
+    // daughters still to run; each goes to the neighbour-list form when it may and its lists
+    // fit, else to the cell form; each form is one persistent launch, largest systems first
+    std::vector<int32_t> nl_group, cell_group;
+    int precision = -1;
     for (size_t i = 0; i < c->descs.size(); ++i) {
-        const DaughterDesc& d = c->descs[i];
+        DaughterDesc& d = c->descs[i];
         if (d.health != 0 || d.done >= d.n_steps) continue;
-        order.push_back((int32_t)i);
-        nmax = std::max(nmax, d.sys.n);
-        cmax = std::max(cmax, d.sys.nc[0] * d.sys.nc[1] * d.sys.nc[2]);
-        threads = std::max(threads, d.block);
         const Mother& m = c->mothers[c->batches[c->live[i].batch].mother];
-        if (precision < 0) precision = m.sys.precision;
+        if (precision < 0)
+            precision = m.sys.precision;
         else if (precision != m.sys.precision)
             return fail(c, TTCF_EINVAL, "live daughters mix force precisions");
+        bool nl = precision == TTCF_PREC_FP32_FORCES && c->shape_variant != 1 &&
+                  set_list_grid(&d.sys, c->shape_skin) &&
+                  lds_bytes_nl(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2], c->shape_kmax) <=
+                      c->max_lds;
+        if (c->shape_variant == 2 && !nl)
+            return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
+        (nl ? nl_group : cell_group).push_back((int32_t)i);
     }
-    if (order.empty()) return TTCF_OK;
-    if (c->shape_threads > 0) threads = c->shape_threads;
-    apt = pick_apt(nmax, threads);
-    if (apt < 0) return fail(c, TTCF_EINVAL, "batch needs more than 4 atoms per thread");
-    bool explicit_threads = c->shape_threads > 0;
-    for (int32_t i : order)
-        explicit_threads = explicit_threads ||
-                           c->mothers[c->batches[c->live[i].batch].mother].sys.block_threads > 0;
-    // kernel form: neighbour lists when asked for or (automatic) when the FP32 form fits
-    int variant = kVariantCells;
-    int lcmax = 0;
-    bool nl_ok = precision == TTCF_PREC_FP32_FORCES;
-    for (int32_t i : order) {
-        SysDev& d = c->descs[i].sys;
-        nl_ok = nl_ok && set_list_grid(&d, c->shape_skin);
-        lcmax = std::max(lcmax, d.lc[0] * d.lc[1] * d.lc[2]);
-    }
-    const size_t nl_bytes = lds_bytes_nl(nmax, lcmax, c->shape_kmax);
-    nl_ok = nl_ok && nl_bytes <= c->max_lds;
-    if (c->shape_variant == 2) {
-        if (!nl_ok) return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
-        variant = kVariantNeighbourList;
-    } else if (c->shape_variant == 0 && nl_ok) {
-        variant = kVariantNeighbourList;
-    }
-    if (variant == kVariantNeighbourList) {
+    if (nl_group.empty() && cell_group.empty()) return TTCF_OK;
+    if (!nl_group.empty()) {
         rc = push_descs(c);  // the list grids were just written into the descriptors
         if (rc != TTCF_OK) return rc;
-        // 512 threads with up to 4 atoms each keep the list form free of register spills
-        // (at 1024 threads a lane has 128 registers and spills); measured faster at N = 2048
-        if (!explicit_threads && nmax <= 4 * 512) {
-            threads = std::min(512, pick_threads(nmax, 0));
-            apt = pick_apt(nmax, threads);
-        }
     }
-    c->last_variant = variant;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-        return c->descs[a].sys.n > c->descs[b].sys.n;
-    });
+    auto by_size = [&](int32_t a, int32_t b) { return c->descs[a].sys.n > c->descs[b].sys.n; };
+    std::stable_sort(nl_group.begin(), nl_group.end(), by_size);
+    std::stable_sort(cell_group.begin(), cell_group.end(), by_size);
+    std::vector<int32_t> order(nl_group);
+    order.insert(order.end(), cell_group.begin(), cell_group.end());
     if (c->d_order_cap < order.size()) {
         dev_free(c->d_order);
         c->d_order = (int32_t*)dev_alloc(sizeof(int32_t) * order.size() * 2, c->stream);
@@ -777,33 +796,26 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
     HIPCHECK(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int32_t) * order.size(),
                                hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    BatchLaunch L{};
-    L.descs = c->d_descs;
-    L.order = c->d_order;
-    L.n_jobs = (int32_t)order.size();
-    L.queue = c->d_queue;
-    L.max_steps = n_steps;
-    L.threads = threads;
-    L.apt = apt;
-    L.precision = precision;
-    L.nmax = nmax;
-    L.cmax = variant == kVariantNeighbourList ? lcmax : cmax;
-    L.variant = variant;
-    L.kmax = c->shape_kmax;
-    L.lds_bytes = variant == kVariantNeighbourList ? nl_bytes
-                                                   : lds_bytes_for(nmax, cmax, threads, precision);
-    if (L.lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
-    const int per_cu_lds = (int)(c->max_lds / L.lds_bytes);
-    const int per_cu_waves = 32 / (threads / 64);  // 8 waves per SIMD, 4 SIMDs
-    const int per_cu = std::max(1, std::min(per_cu_lds, per_cu_waves));
-    L.grid = std::min<int>(L.n_jobs, per_cu * c->num_cu);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHECK(c, hipEventCreate(&e0));
-    HIPCHECK(c, hipEventCreate(&e1));
-    HIPCHECK(c, hipEventRecord(e0, c->stream));
-    HIPCHECK(c, launch_daughters(L, c->stream));
-    HIPCHECK(c, hipEventRecord(e1, c->stream));
-    c->pending_events.emplace_back(e0, e1);
+    c->last_variant = nl_group.empty() ? kVariantCells
+                                       : (cell_group.empty() ? kVariantNeighbourList : 3);
+    size_t offset = 0;
+    for (int form = 0; form < 2; ++form) {
+        const std::vector<int32_t>& group = form == 0 ? nl_group : cell_group;
+        if (group.empty()) continue;
+        BatchLaunch L{};
+        rc = plan_group(c, group, form == 0 ? kVariantNeighbourList : kVariantCells, precision,
+                        n_steps, &L);
+        if (rc != TTCF_OK) return rc;
+        L.order = c->d_order + offset;
+        offset += group.size();
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHECK(c, hipEventCreate(&e0));
+        HIPCHECK(c, hipEventCreate(&e1));
+        HIPCHECK(c, hipEventRecord(e0, c->stream));
+        HIPCHECK(c, launch_daughters(L, c->stream));
+        HIPCHECK(c, hipEventRecord(e1, c->stream));
+        c->pending_events.emplace_back(e0, e1);
+    }
     c->device_newer = true;
     return TTCF_OK;
 }

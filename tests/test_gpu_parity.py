@@ -423,6 +423,43 @@ def test_uneven_batch_is_invariant_and_deterministic(T, orc, cfg1):
     np.testing.assert_allclose(both[500], b[500], rtol=0, atol=0)
 
 
+def test_mixed_forms_in_one_step_call(T):
+    """N = 4000 (its lists do not fit in LDS: cell form) and N = 500 (neighbour-list form)
+    live together: one ttcf_step call launches both forms, and each size's series equal the
+    ones it gives alone."""
+    s_big = I.System(10, density=0.7)
+    s_small = I.System(5)
+    rb = I.perturbed_positions(s_big, 21, 0.1)
+    pb = I.maxwell_boltzmann(s_big.n, s_big.temperature, 21)
+    rs = I.perturbed_positions(s_small, 22, 0.1)
+    ps = I.maxwell_boltzmann(s_small.n, s_small.temperature, 22)
+    nst = 20
+    say("mixed kernel forms")
+
+    def run(big, small):
+        out = {}
+        with T.Context() as ctx:
+            if big:
+                mb = ctx.ttcf_init_mother(gsys(T, s_big, 1), rb, pb, n_equil=0)
+                ctx.ttcf_import_states(mb, rb.reshape(1, -1), pb.reshape(1, -1))
+                fb = ctx.ttcf_spawn_daughters(mb, 1, 0, 0.05, nst)
+            if small:
+                ms = ctx.ttcf_init_mother(gsys(T, s_small, 1), rs, ps, n_equil=0)
+                ctx.ttcf_import_states(ms, rs.reshape(1, -1), ps.reshape(1, -1))
+                fs = ctx.ttcf_spawn_daughters(ms, 1, 0, 0.05, nst)
+            ctx.ttcf_step(nst)
+            if big:
+                out["big"] = ctx.ttcf_export_series(fb, 4, nst + 1)
+            if small:
+                out["small"] = ctx.ttcf_export_series(fs, 4, nst + 1)
+        return out
+
+    both = run(True, True)
+    assert np.array_equal(both["big"], run(True, False)["big"])
+    assert np.array_equal(both["small"], run(False, True)["small"])
+    assert np.all(np.isfinite(both["big"])) and np.all(np.isfinite(both["small"]))
+
+
 # ----------------------------------------------------------------------------------------
 # the mother on the GPU
 # ----------------------------------------------------------------------------------------

@@ -136,7 +136,7 @@ def precision_statement(T, ctx, mid, sysd, s, n_states, nst, stream):
 
 
 def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per_size=128,
-               nst=400, seed=31):
+               nst=400, seed=31, tune=True):
     """Mixed system sizes in one step call: N in {500, 864, 2048, 4000} x rho in {0.7, 0.8442,
     0.9}, one mother per (N, rho), 128 start states per N (state n at density index n mod 3),
     a shear rate per state drawn log-uniformly in [1e-5, 1e-1] (shared by its four mapped
@@ -148,6 +148,8 @@ def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per
     t0 = time.perf_counter()
     total_atoms = 0
     spawned = []
+    shapes = {}
+    tune_s = 0.0
     rates = I.log_uniform_rates(len(sizes) * per_size, 1e-5, 1e-1, seed)
     ri = 0
     for nc in sizes:
@@ -160,10 +162,17 @@ def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per
             n_rep = count
             ctx.ttcf_sample_states_replicated(mid, n_rep, seeded_kicks(n_rep, s.n, 0.05, seed + mid),
                                               200, 1, 50)
+            if tune:
+                t1 = time.perf_counter()
+                sh = ctx.ttcf_autotune(mid, 0, 1e-3, 40)
+                tune_s += time.perf_counter() - t1
+                shapes[f"N={s.n} rho={rho}"] = (
+                    f"{'lists' if sh['variant'] == 2 else 'cells'}/{sh['threads']}"
+                    + (f" skin {sh['skin']:.3f} kmax {sh['kmax']}" if sh["variant"] == 2 else ""))
             spawned.append((mid, count, s.n, rates[ri:ri + count]))
             ri += count
     torch.cuda.synchronize()
-    mother_s = time.perf_counter() - t0
+    mother_s = time.perf_counter() - t0 - tune_s
     for mid, count, n, g in spawned:
         ctx.ttcf_spawn_daughters(mid, count, 0, g, nst)
         total_atoms += 4 * count * n
@@ -183,6 +192,7 @@ def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per
             "daughters": 4 * len(sizes) * per_size, "kernel_launches": launches,
             "kernel_atom_steps_per_s": atom_steps / (ms / 1e3),
             "end_to_end_atom_steps_per_s": atom_steps / wall, "mothers_s": mother_s,
+            "autotune_s": tune_s, "tuned_shapes": shapes,
             "healthy_groups": int(groups),
             "per_unit_rate_ttcf_end": float(tm[-1]), "per_unit_rate_ttcf_se_end": float(tse[-1])}
 

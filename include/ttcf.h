@@ -209,6 +209,45 @@ int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, 
 int32_t ttcf_set_step_shape(ttcf_ctx* ctx, int32_t variant, int32_t threads, double skin,
                             int32_t kmax);
 
+/* Launch-shape autotuner for the batched step of many independent daughters (Sec. Software
+ * methodology: the daughter runs are split into independent jobs, one per core). Times
+ * the step kernel on probe daughters spawned from the first n_states stored start states of
+ * `mother` (0: all; all four mappings, shear rate gamma_dot; the set repeated until there
+ * are four daughters per compute unit, so that throughput is measured) over a short untimed
+ * warm-up
+ * and probe_steps timed steps, for each candidate shape: the cell form at 256, 512 and 1024
+ * threads, and (FP32 forces) the neighbour-list form at those sizes and at the skins that
+ * fill list cells one coarser, equal to and one finer than the automatic grid, its list
+ * capacity raised while the probe overflows. Probe daughters are discarded (never
+ * accumulated) and live daughters are not advanced. The fastest shape (list capacity plus a
+ * margin of 4 where it fits) is stored in the context's cache under (device architecture,
+ * N, round(1000 N/V), round(10000 r_cut), precision), replacing an older entry, and written
+ * to *out (may be NULL). While no explicit shape is set (ttcf_set_step_shape(ctx, 0, 0, 0,
+ * 0), the default), ttcf_step uses the cached shape of each daughter's system, the list
+ * grid of its skin and, per launch, the workgroup size of the largest system and the
+ * largest capacity. Synchronises the context's stream. Errors: TTCF_EINVAL (no stored
+ * states, bad arguments, no shape fits), TTCF_EDEVICE (probe daughters unhealthy other than
+ * by list overflow, or a HIP error). */
+typedef struct ttcf_shape {
+    int32_t variant;       /* 1 cell form, 2 neighbour-list form                              */
+    int32_t threads;       /* workgroup size                                                  */
+    int32_t kmax;          /* neighbour-list capacity per atom (list form)                    */
+    double skin;           /* list skin, sigma (list form)                                    */
+    double ms_per_step;    /* probe batch, device milliseconds per step                       */
+    int32_t candidates;    /* shapes timed                                                    */
+} ttcf_shape;
+int32_t ttcf_autotune(ttcf_ctx* ctx, int32_t mother, int32_t n_states, double gamma_dot,
+                      int32_t probe_steps, ttcf_shape* out);
+/* The context's cache of tuned shapes as JSON text: an array of objects with keys arch, n,
+ * rho_key, rc_key, precision, variant, threads, kmax, skin, ms_per_step. *len receives the
+ * text length (without the terminating NUL); buf (may be NULL) receives at most cap - 1
+ * characters and a NUL (TTCF_EINVAL when cap <= len). */
+int32_t ttcf_autotune_export(ttcf_ctx* ctx, char* buf, int64_t cap, int64_t* len);
+/* Adds the entries of such a text to the cache (replacing equal keys). Entries of other
+ * architectures are kept but never used on this device. TTCF_EINVAL on a malformed entry
+ * (nothing is added then). */
+int32_t ttcf_autotune_import(ttcf_ctx* ctx, const char* text);
+
 /* Device time of the daughter step kernel: total milliseconds and launch count since the
  * last reset (timing events are recorded on the context's stream around every launch). */
 int32_t ttcf_step_timing(ttcf_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);

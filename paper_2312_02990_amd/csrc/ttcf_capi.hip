@@ -92,6 +92,25 @@ struct Batch {
     int32_t remaining = 0;       // daughters not yet accumulated
 };
 
+struct StepShape {              // knobs of the daughter step kernel (0: automatic)
+    int32_t variant = 0;        // 1 cell form, 2 neighbour-list form
+    int32_t threads = 0;
+    int32_t kmax = 0;           // list capacity per atom (0: kDefaultKmax)
+    double skin = 0.0;          // list skin (<= 0: auto_skin)
+};
+
+constexpr int32_t kDefaultKmax = 24;
+
+struct TunedShape {             // one autotuner result
+    std::string arch;           // device architecture name
+    int32_t n = 0;              // atoms
+    int32_t rho_key = 0;        // round(1000 n / V)
+    int32_t rc_key = 0;         // round(10000 r_cut)
+    int32_t precision = 0;
+    StepShape shape;
+    double ms_per_step = 0.0;   // probe batch, per step
+};
+
 struct Live {                   // host view of one live daughter
     int64_t id;
     int32_t batch;
@@ -157,9 +176,12 @@ struct ttcf_ctx {
     double cv_mu_gamma = 0.0;
     std::vector<double> cv_beta;  // calibrated control-variate coefficient per time point
     double cv_beta_gamma = 0.0;
-    // shape of the daughter step kernel
-    int32_t shape_variant = 0, shape_threads = 0, shape_kmax = 24;
-    double shape_skin = 0.0;  // <= 0: automatic (see auto_skin)
+    // shape of the daughter step kernel: set explicitly, or looked up per system among the
+    // tuned shapes (when none is set), else the library's defaults
+    StepShape shape;
+    bool shape_explicit = false;
+    std::vector<TunedShape> tuned;
+    std::string arch;
     int32_t last_variant = -1;
     // timing of the step kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
@@ -473,6 +495,7 @@ int32_t ttcf_init_mother(ttcf_ctx** pctx, const ttcf_system* sys, const double* 
         }
         c->num_cu = prop.multiProcessorCount;
         c->max_lds = prop.sharedMemPerBlock;
+        c->arch = prop.gcnArchName;
         c->d_queue = (int32_t*)dev_alloc(sizeof(int32_t) * 4, c->stream);
         if (!c->d_queue) {
             ttcf_destroy(c);
@@ -624,9 +647,24 @@ int32_t ttcf_sample_states(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_
     return TTCF_OK;
 }
 
+namespace {
+int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
+                   uint32_t mapping_mask, const double* gamma_dot, int32_t n_gamma, int32_t n_steps,
+                   bool prefix_ok, int64_t* out_first);
+}
+
 int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
                              uint32_t mapping_mask, const double* gamma_dot, int32_t n_gamma,
                              int32_t n_steps, int64_t* out_first) {
+    return spawn_impl(c, mother, n_states, steps_between, mapping_mask, gamma_dot, n_gamma, n_steps,
+                      false, out_first);
+}
+
+namespace {
+// prefix_ok: with steps_between == 0, the first n_states stored states may be used
+int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
+                   uint32_t mapping_mask, const double* gamma_dot, int32_t n_gamma, int32_t n_steps,
+                   bool prefix_ok, int64_t* out_first) {
     if (!c) return TTCF_EINVAL;
     if (mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || steps_between < 0 ||
         (mapping_mask & 0xFu) == 0 || (mapping_mask & ~0xFu) != 0 || !gamma_dot ||
@@ -639,7 +677,7 @@ int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int6
     if (steps_between > 0) {
         int32_t rc = ttcf_sample_states(c, mother, n_states, steps_between);
         if (rc != TTCF_OK) return rc;
-    } else if (m.n_states != n_states) {
+    } else if (m.n_states != n_states && !(prefix_ok && n_states <= m.n_states)) {
         return fail(c, TTCF_EINVAL, "steps_between == 0 needs n_states equal to the stored count");
     }
     int32_t rc = sync_descs(c);
@@ -709,21 +747,26 @@ int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int6
     return TTCF_OK;
 }
 
-// Launch shape of one group of daughters in one kernel form.
+// Launch shape of one group of daughters in one kernel form. threads_req > 0 fixes the
+// workgroup size; kmax is the list capacity of the neighbour-list form.
 int32_t plan_group(ttcf_ctx* c, const std::vector<int32_t>& group, int variant, int precision,
-                   int32_t n_steps, BatchLaunch* L) {
+                   int32_t n_steps, int threads_req, int kmax, BatchLaunch* L) {
     int nmax = 0, cmax = 0, lcmax = 0, threads = 0;
-    bool explicit_threads = c->shape_threads > 0;
+    size_t nl_lds = 0;
+    bool explicit_threads = threads_req > 0;
     for (int32_t i : group) {
         const DaughterDesc& d = c->descs[i];
         nmax = std::max(nmax, d.sys.n);
         cmax = std::max(cmax, d.sys.nc[0] * d.sys.nc[1] * d.sys.nc[2]);
         lcmax = std::max(lcmax, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2]);
+        if (variant == kVariantNeighbourList)
+            nl_lds = std::max(nl_lds, lds_bytes_nl(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2],
+                                                   d.kmax));
         threads = std::max(threads, d.block);
         explicit_threads = explicit_threads ||
                            c->mothers[c->batches[c->live[i].batch].mother].sys.block_threads > 0;
     }
-    if (c->shape_threads > 0) threads = c->shape_threads;
+    if (threads_req > 0) threads = threads_req;
     // 512 threads with up to 4 atoms each keep the list form free of register spills
     // (at 1024 threads a lane has 128 registers and spills); measured faster at N = 2048
     if (variant == kVariantNeighbourList && !explicit_threads && nmax <= 4 * 512)
@@ -741,8 +784,8 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<int32_t>& group, int variant, 
     L->nmax = nmax;
     L->cmax = variant == kVariantNeighbourList ? lcmax : cmax;
     L->variant = variant;
-    L->kmax = c->shape_kmax;
-    L->lds_bytes = variant == kVariantNeighbourList ? lds_bytes_nl(nmax, lcmax, c->shape_kmax)
+    L->kmax = kmax;
+    L->lds_bytes = variant == kVariantNeighbourList ? nl_lds
                                                     : lds_bytes_for(nmax, cmax, threads, precision);
     if (L->lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
     const int per_cu_lds = (int)(c->max_lds / L->lds_bytes);
@@ -752,28 +795,55 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<int32_t>& group, int variant, 
     return TTCF_OK;
 }
 
-int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
-    if (!c || n_steps < 0) return TTCF_EINVAL;
+int32_t rho_key_of(const SysDev& d) { return (int32_t)std::lround(1000.0 * d.n / d.volume); }
+int32_t rc_key_of(const SysDev& d) { return (int32_t)std::lround(10000.0 * d.rc); }
+
+const TunedShape* find_tuned(const ttcf_ctx* c, const SysDev& d, int precision) {
+    const int32_t rk = rho_key_of(d), ck = rc_key_of(d);
+    for (const TunedShape& t : c->tuned)
+        if (t.n == d.n && t.rho_key == rk && t.rc_key == ck && t.precision == precision &&
+            t.arch == c->arch)
+            return &t;
+    return nullptr;
+}
+
+// Advances the live daughters selected by `only` (all when null) by up to n_steps. `force`
+// (may be null) overrides every other shape. With timing, the launches are bracketed by
+// events that ttcf_step_timing reads.
+int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
+                  const StepShape* force, bool timing) {
     if (c->descs.empty() || n_steps == 0) return TTCF_OK;
     int32_t rc = sync_descs(c);
     if (rc != TTCF_OK) return rc;
     // daughters still to run; each goes to the neighbour-list form when it may and its lists
     // fit, else to the cell form; each form is one persistent launch, largest systems first
     std::vector<int32_t> nl_group, cell_group;
+    std::vector<StepShape> eff(c->descs.size());
     int precision = -1;
     for (size_t i = 0; i < c->descs.size(); ++i) {
         DaughterDesc& d = c->descs[i];
-        if (d.health != 0 || d.done >= d.n_steps) continue;
+        if (d.health != 0 || d.done >= d.n_steps || (only && !(*only)[i])) continue;
         const Mother& m = c->mothers[c->batches[c->live[i].batch].mother];
         if (precision < 0)
             precision = m.sys.precision;
         else if (precision != m.sys.precision)
             return fail(c, TTCF_EINVAL, "live daughters mix force precisions");
-        bool nl = precision == TTCF_PREC_FP32_FORCES && c->shape_variant != 1 &&
-                  set_list_grid(&d.sys, c->shape_skin) &&
-                  lds_bytes_nl(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2], c->shape_kmax) <=
+        StepShape e;
+        if (force) {
+            e = *force;
+        } else if (c->shape_explicit) {
+            e = c->shape;
+        } else if (const TunedShape* t = find_tuned(c, d.sys, precision)) {
+            e = t->shape;
+        }
+        if (e.kmax <= 0) e.kmax = kDefaultKmax;
+        eff[i] = e;
+        d.kmax = e.kmax;
+        bool nl = precision == TTCF_PREC_FP32_FORCES && e.variant != 1 &&
+                  set_list_grid(&d.sys, e.skin) &&
+                  lds_bytes_nl(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2], e.kmax) <=
                       c->max_lds;
-        if (c->shape_variant == 2 && !nl)
+        if (e.variant == 2 && !nl)
             return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
         (nl ? nl_group : cell_group).push_back((int32_t)i);
     }
@@ -802,22 +872,64 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
     for (int form = 0; form < 2; ++form) {
         const std::vector<int32_t>& group = form == 0 ? nl_group : cell_group;
         if (group.empty()) continue;
+        // the largest system's shape sets the workgroup size; the capacity covers every member
+        int kmax = 0;
+        for (int32_t i : group) kmax = std::max(kmax, eff[i].kmax);
         BatchLaunch L{};
         rc = plan_group(c, group, form == 0 ? kVariantNeighbourList : kVariantCells, precision,
-                        n_steps, &L);
+                        n_steps, eff[group[0]].threads, kmax, &L);
         if (rc != TTCF_OK) return rc;
         L.order = c->d_order + offset;
         offset += group.size();
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        HIPCHECK(c, hipEventCreate(&e0));
-        HIPCHECK(c, hipEventCreate(&e1));
-        HIPCHECK(c, hipEventRecord(e0, c->stream));
+        if (timing) {
+            HIPCHECK(c, hipEventCreate(&e0));
+            HIPCHECK(c, hipEventCreate(&e1));
+            HIPCHECK(c, hipEventRecord(e0, c->stream));
+        }
         HIPCHECK(c, launch_daughters(L, c->stream));
-        HIPCHECK(c, hipEventRecord(e1, c->stream));
-        c->pending_events.emplace_back(e0, e1);
+        if (timing) {
+            HIPCHECK(c, hipEventRecord(e1, c->stream));
+            c->pending_events.emplace_back(e0, e1);
+        }
     }
     c->device_newer = true;
     return TTCF_OK;
+}
+
+// Removes the live daughters of batch `bidx` without accumulating them and frees the batch.
+int32_t discard_batch(ttcf_ctx* c, int32_t bidx) {
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    std::vector<DaughterDesc> nd;
+    std::vector<Live> nl;
+    for (size_t q = 0; q < c->descs.size(); ++q) {
+        if (c->live[q].batch != bidx) {
+            nd.push_back(c->descs[q]);
+            nl.push_back(c->live[q]);
+        }
+    }
+    c->descs.swap(nd);
+    c->live.swap(nl);
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    Batch& b = c->batches[bidx];
+    dev_free(b.states);
+    dev_free(b.series);
+    dev_free(b.scratch);
+    dev_free(b.hseries);
+    b.states = nullptr;
+    b.series = nullptr;
+    b.scratch = nullptr;
+    b.hseries = nullptr;
+    b.remaining = 0;
+    return push_descs(c);
+}
+
+}  // namespace
+
+int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
+    if (!c || n_steps < 0) return TTCF_EINVAL;
+    return step_impl(c, n_steps, nullptr, nullptr, true);
 }
 
 int32_t ttcf_set_step_shape(ttcf_ctx* c, int32_t variant, int32_t threads, double skin,
@@ -825,10 +937,262 @@ int32_t ttcf_set_step_shape(ttcf_ctx* c, int32_t variant, int32_t threads, doubl
     if (!c || variant < 0 || variant > 2 || threads < 0 || threads > kMaxThreads ||
         (threads > 0 && threads % 64 != 0) || kmax > 255)
         return TTCF_EINVAL;
-    c->shape_variant = variant;
-    c->shape_threads = threads;
-    c->shape_skin = skin > 0.0 ? skin : 0.0;
-    c->shape_kmax = kmax > 0 ? kmax : 24;
+    c->shape.variant = variant;
+    c->shape.threads = threads;
+    c->shape.skin = skin > 0.0 ? skin : 0.0;
+    c->shape.kmax = kmax > 0 ? kmax : 0;
+    c->shape_explicit = variant != 0 || threads != 0 || skin > 0.0 || kmax > 0;
+    return TTCF_OK;
+}
+
+int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamma_dot,
+                      int32_t probe_steps, ttcf_shape* out) {
+    if (!c) return TTCF_EINVAL;
+    if (mother < 0 || mother >= (int32_t)c->mothers.size() || n_states < 0 || probe_steps < 1 ||
+        !std::isfinite(gamma_dot))
+        return fail(c, TTCF_EINVAL, "bad autotune arguments");
+    Mother& m = c->mothers[mother];
+    if (m.n_states < 1) return fail(c, TTCF_EINVAL, "autotune needs stored start states");
+    if (n_states == 0 || n_states > m.n_states) n_states = m.n_states;
+    const SysDev& d = m.dev;
+    const int precision = m.sys.precision;
+    // candidate shapes: each form at 256, 512 and 1024 threads; the list form also at the
+    // skins that fill list cells one coarser, equal to and one finer than the automatic grid
+    std::vector<StepShape> cand;
+    for (int t : {256, 512, 1024}) {
+        if (pick_apt(d.n, t) < 0) continue;
+        if (lds_bytes_for(d.n, d.nc[0] * d.nc[1] * d.nc[2], t, precision) <= c->max_lds)
+            cand.push_back(StepShape{1, t, 0, 0.0});
+    }
+    std::vector<double> skins;
+    if (precision == TTCF_PREC_FP32_FORCES) {
+        const double lmin = std::min(d.box[0], std::min(d.box[1], d.box[2]));
+        const int n0 = (int)std::floor(lmin / (d.rc + 0.25));
+        for (int lc = n0 - 1; lc <= n0 + 1; ++lc) {
+            if (lc < 3) continue;
+            const double skin = lmin / lc * (1.0 - 1e-9) - d.rc;
+            SysDev probe = d;
+            if (skin >= 0.1 && set_list_grid(&probe, skin)) skins.push_back(skin);
+        }
+    }
+    // expected list length at each skin sets the first capacity tried; a capacity that
+    // overflows on the probe is raised and the shape timed again
+    const double rho = d.n / d.volume;
+    for (double skin : skins)
+        for (int t : {256, 512, 1024}) {
+            if (pick_apt(d.n, t) < 0) continue;
+            const double reach = d.rc + skin;
+            const double mean = 4.18879020478639 * reach * reach * reach * rho;
+            int k0 = std::max(12, ((int)std::ceil(1.6 * mean) + 3) / 4 * 4);
+            cand.push_back(StepShape{2, t, std::min(k0, 255), skin});
+        }
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    const int warm = std::max(1, probe_steps / 5);
+    double best = 1e300;
+    StepShape best_shape;
+    int timed = 0;
+    for (size_t ci = 0; ci < cand.size(); ++ci) {
+        StepShape sh = cand[ci];
+        for (int attempt = 0; attempt < 4; ++attempt) {
+            if (sh.variant == 2) {
+                SysDev probe = d;
+                set_list_grid(&probe, sh.skin);
+                if (lds_bytes_nl(d.n, probe.lc[0] * probe.lc[1] * probe.lc[2], sh.kmax) > c->max_lds)
+                    break;
+            }
+            // enough copies of the probe states to give every compute unit four daughters,
+            // so that the probe measures throughput, not the latency of a few daughters
+            const int32_t copies = std::max(1, (c->num_cu + n_states - 1) / n_states);
+            const int32_t bfirst = (int32_t)c->batches.size();
+            for (int32_t k = 0; k < copies && rc == TTCF_OK; ++k) {
+                int64_t first = -1;
+                rc = spawn_impl(c, mother, n_states, 0, 0xF, &gamma_dot, 1, warm + probe_steps,
+                                true, &first);
+            }
+            const int32_t bend = (int32_t)c->batches.size();
+            auto discard_probe = [&]() {
+                int32_t r2 = TTCF_OK;
+                for (int32_t b = bfirst; b < bend && r2 == TTCF_OK; ++b) r2 = discard_batch(c, b);
+                return r2;
+            };
+            if (rc != TTCF_OK) {
+                (void)discard_probe();
+                return rc;
+            }
+            std::vector<char> only(c->descs.size(), 0);
+            for (size_t q = 0; q < c->descs.size(); ++q)
+                only[q] = c->live[q].batch >= bfirst && c->live[q].batch < bend;
+            rc = step_impl(c, warm, &only, &sh, false);
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            float ms = 0.0f;
+            if (rc == TTCF_OK) {
+                HIPCHECK(c, hipEventCreate(&e0));
+                HIPCHECK(c, hipEventCreate(&e1));
+                HIPCHECK(c, hipEventRecord(e0, c->stream));
+                rc = step_impl(c, probe_steps, &only, &sh, false);
+                HIPCHECK(c, hipEventRecord(e1, c->stream));
+                HIPCHECK(c, hipEventSynchronize(e1));
+                HIPCHECK(c, hipEventElapsedTime(&ms, e0, e1));
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+            }
+            if (rc != TTCF_OK) {
+                (void)discard_probe();
+                return rc;
+            }
+            rc = sync_descs(c);
+            if (rc != TTCF_OK) return rc;
+            int32_t health = 0;
+            for (size_t q = 0; q < c->descs.size(); ++q)
+                if (only[q]) health |= c->descs[q].health;
+            rc = discard_probe();
+            if (rc != TTCF_OK) return rc;
+            if (health & ~kHealthListOverflow)
+                return fail(c, TTCF_EDEVICE, "probe daughters failed the health check");
+            if (health & kHealthListOverflow) {
+                if (sh.kmax >= 255) break;
+                sh.kmax = std::min(255, sh.kmax + 8);
+                continue;
+            }
+            ++timed;
+            const double per_step = ms / probe_steps;
+            if (per_step < best) {
+                best = per_step;
+                best_shape = sh;
+            }
+            break;
+        }
+    }
+    if (timed == 0) return fail(c, TTCF_EINVAL, "no step shape fits this system");
+    // a margin over the largest list the probe needed, where the LDS allows
+    if (best_shape.variant == 2) {
+        SysDev probe = d;
+        set_list_grid(&probe, best_shape.skin);
+        const int lcn = probe.lc[0] * probe.lc[1] * probe.lc[2];
+        const int k = std::min(255, best_shape.kmax + 4);
+        if (lds_bytes_nl(d.n, lcn, k) <= c->max_lds) best_shape.kmax = k;
+    }
+    TunedShape t;
+    t.arch = c->arch;
+    t.n = d.n;
+    t.rho_key = rho_key_of(d);
+    t.rc_key = rc_key_of(d);
+    t.precision = precision;
+    t.shape = best_shape;
+    t.ms_per_step = best;
+    bool replaced = false;
+    for (TunedShape& u : c->tuned)
+        if (u.arch == t.arch && u.n == t.n && u.rho_key == t.rho_key && u.rc_key == t.rc_key &&
+            u.precision == t.precision) {
+            u = t;
+            replaced = true;
+        }
+    if (!replaced) c->tuned.push_back(t);
+    if (out) {
+        out->variant = best_shape.variant;
+        out->threads = best_shape.threads;
+        out->kmax = best_shape.kmax;
+        out->skin = best_shape.skin;
+        out->ms_per_step = best;
+        out->candidates = timed;
+    }
+    return TTCF_OK;
+}
+
+int32_t ttcf_autotune_export(ttcf_ctx* c, char* buf, int64_t cap, int64_t* len) {
+    if (!c || cap < 0) return TTCF_EINVAL;
+    std::string js = "[\n";
+    char line[512];
+    for (size_t i = 0; i < c->tuned.size(); ++i) {
+        const TunedShape& t = c->tuned[i];
+        std::snprintf(line, sizeof line,
+                      "{\"arch\": \"%s\", \"n\": %d, \"rho_key\": %d, \"rc_key\": %d, "
+                      "\"precision\": %d, \"variant\": %d, \"threads\": %d, \"kmax\": %d, "
+                      "\"skin\": %.17g, \"ms_per_step\": %.9g}%s\n",
+                      t.arch.c_str(), t.n, t.rho_key, t.rc_key, t.precision, t.shape.variant,
+                      t.shape.threads, t.shape.kmax, t.shape.skin, t.ms_per_step,
+                      i + 1 < c->tuned.size() ? "," : "");
+        js += line;
+    }
+    js += "]\n";
+    if (len) *len = (int64_t)js.size();
+    if (buf && cap > 0) {
+        const size_t n = std::min<size_t>(js.size(), (size_t)cap - 1);
+        std::memcpy(buf, js.data(), n);
+        buf[n] = '\0';
+        if (js.size() + 1 > (size_t)cap) return fail(c, TTCF_EINVAL, "buffer too small");
+    }
+    return TTCF_OK;
+}
+
+namespace {
+// Value of "key": in the object text [b, e); strings without escapes, numbers via strtod.
+bool json_field(const char* b, const char* e, const char* key, std::string* str, double* num) {
+    const std::string pat = std::string("\"") + key + "\"";
+    const std::string obj(b, e);
+    size_t at = obj.find(pat);
+    if (at == std::string::npos) return false;
+    at = obj.find(':', at + pat.size());
+    if (at == std::string::npos) return false;
+    ++at;
+    while (at < obj.size() && (obj[at] == ' ' || obj[at] == '\t')) ++at;
+    if (at >= obj.size()) return false;
+    if (str) {
+        if (obj[at] != '"') return false;
+        const size_t end = obj.find('"', at + 1);
+        if (end == std::string::npos) return false;
+        *str = obj.substr(at + 1, end - at - 1);
+        return true;
+    }
+    char* stop = nullptr;
+    *num = std::strtod(obj.c_str() + at, &stop);
+    return stop != obj.c_str() + at;
+}
+}  // namespace
+
+int32_t ttcf_autotune_import(ttcf_ctx* c, const char* text) {
+    if (!c || !text) return TTCF_EINVAL;
+    std::vector<TunedShape> got;
+    const char* p = text;
+    while ((p = std::strchr(p, '{')) != nullptr) {
+        const char* e = std::strchr(p, '}');
+        if (!e) return fail(c, TTCF_EINVAL, "autotune cache: unterminated object");
+        TunedShape t;
+        double v[9];
+        const char* keys[9] = {"n", "rho_key", "rc_key", "precision", "variant",
+                               "threads", "kmax", "skin", "ms_per_step"};
+        if (!json_field(p, e, "arch", &t.arch, nullptr))
+            return fail(c, TTCF_EINVAL, "autotune cache: missing arch");
+        for (int k = 0; k < 9; ++k)
+            if (!json_field(p, e, keys[k], nullptr, &v[k]))
+                return fail(c, TTCF_EINVAL, std::string("autotune cache: missing ") + keys[k]);
+        t.n = (int32_t)v[0];
+        t.rho_key = (int32_t)v[1];
+        t.rc_key = (int32_t)v[2];
+        t.precision = (int32_t)v[3];
+        t.shape.variant = (int32_t)v[4];
+        t.shape.threads = (int32_t)v[5];
+        t.shape.kmax = (int32_t)v[6];
+        t.shape.skin = v[7];
+        t.ms_per_step = v[8];
+        if (t.shape.variant < 1 || t.shape.variant > 2 || t.shape.threads % 64 != 0 ||
+            t.shape.threads < 64 || t.shape.threads > kMaxThreads || t.shape.kmax < 0 ||
+            t.shape.kmax > 255 || !(t.shape.skin >= 0.0) || t.n < 2)
+            return fail(c, TTCF_EINVAL, "autotune cache: shape out of range");
+        got.push_back(t);
+        p = e + 1;
+    }
+    for (const TunedShape& t : got) {
+        bool replaced = false;
+        for (TunedShape& u : c->tuned)
+            if (u.arch == t.arch && u.n == t.n && u.rho_key == t.rho_key && u.rc_key == t.rc_key &&
+                u.precision == t.precision) {
+                u = t;
+                replaced = true;
+            }
+        if (!replaced) c->tuned.push_back(t);
+    }
     return TTCF_OK;
 }
 

@@ -51,7 +51,7 @@ struct DaughterDesc {
     int32_t group;      // start-state group (accumulator slot)
     int32_t map;        // mapping 0..3
     int32_t block;      // threads per workgroup the launcher was sized for
-    int32_t pad_;
+    int32_t kmax;       // neighbour-list form: list capacity per atom
     double* hseries;    // n_steps + 1 doubles: learned control variate h(t_k), or null
 };
 
@@ -176,7 +176,9 @@ hipError_t launch_states_vpxy(const SysDev& sys, const double* states, int32_t c
 int pick_threads(int n, int requested);
 int pick_apt(int n, int threads);
 size_t lds_bytes_for(int nmax, int cmax, int threads, int precision);
-size_t lds_bytes_nl(int nmax, int cmax, int kmax);
+// LDS of the neighbour-list step kernel for one daughter of n atoms, `cells` list cells and
+// list capacity kmax (a launch needs the largest over its daughters)
+size_t lds_bytes_nl(int n, int cells, int kmax);
 
 hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s);
 hipError_t launch_mothers(const MotherLaunch* dev_ms, int count, const MotherLaunch& shape,

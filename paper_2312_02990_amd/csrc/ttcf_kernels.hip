@@ -1684,18 +1684,28 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     __syncthreads();
 }
 
+// The job slot sits at the start of the LDS; behind it the LDS is laid out per job for that
+// daughter's own size, list grid and capacity, so a launch needs only the largest single
+// footprint among its daughters.
+constexpr int kNlJobBytes = 128;
+
 template <int APT, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
     extern __shared__ __align__(32) char smem[];
-    const NlLds L = carve_nl(smem, b.nmax, b.cmax, b.kmax);
-    for (int c = threadIdx.x; c < b.cmax; c += blockDim.x) L.cnt[c] = 0;
+    int32_t* job = (int32_t*)smem;
     for (;;) {
         __syncthreads();
-        if (threadIdx.x == 0) L.misc[0] = atomicAdd(b.queue, 1);
+        if (threadIdx.x == 0) *job = atomicAdd(b.queue, 1);
         __syncthreads();
-        const int j = __builtin_amdgcn_readfirstlane(L.misc[0]);
+        const int j = __builtin_amdgcn_readfirstlane(*job);
         if (j >= b.n_jobs) break;
-        run_daughter_nl<APT>(&b.descs[b.order[j]], b.max_steps, L, b.kmax, b.nmax);
+        DaughterDesc* d = &b.descs[b.order[j]];
+        const int n = d->sys.n, kmax = d->kmax;
+        const int cells = d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2];
+        const NlLds L = carve_nl(smem + kNlJobBytes, n, cells, kmax);
+        for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
+        // run_daughter_nl synchronises before its first use of the counts
+        run_daughter_nl<APT>(d, b.max_steps, L, kmax, n);
     }
 }
 
@@ -1743,7 +1753,9 @@ int pick_apt(int n, int threads) {
     return -1;
 }
 
-size_t lds_bytes_nl(int nmax, int cmax, int kmax) { return plan_nl(nmax, cmax, kmax).total; }
+size_t lds_bytes_nl(int n, int cells, int kmax) {
+    return kNlJobBytes + plan_nl(n, cells, kmax).total;
+}
 
 size_t lds_bytes_for(int nmax, int cmax, int threads, int precision) {
     (void)threads;

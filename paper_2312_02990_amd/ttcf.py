@@ -39,6 +39,11 @@ class System(C.Structure):
                 ("precision", C.c_int32), ("block_threads", C.c_int32)]
 
 
+class Shape(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("threads", C.c_int32), ("kmax", C.c_int32),
+                ("skin", C.c_double), ("ms_per_step", C.c_double), ("candidates", C.c_int32)]
+
+
 class Channel(C.Structure):
     """ttcf_channel of include/ttcf.h."""
     _fields_ = [("n_fluid", C.c_int32), ("n_wall", C.c_int32), ("n_bins", C.c_int32),
@@ -159,6 +164,9 @@ def lib():
         "ttcf_channel_step_timing": [V, D, L64, C.c_int32],
         "ttcf_sample_states_replicated": [V, C.c_int32, C.c_int32, D, C.c_int64, C.c_int32,
                                           C.c_int64],
+        "ttcf_autotune": [V, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.POINTER(Shape)],
+        "ttcf_autotune_export": [V, C.c_char_p, C.c_int64, L64],
+        "ttcf_autotune_import": [V, C.c_char_p],
         "ttcf_mlp_forward": [V, F, C.c_int32, F],
         "ttcf_mlp_gradient": [V, F, F, C.c_int32, F],
     }
@@ -196,7 +204,8 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_channel_export_mother", "ttcf_channel_spawn", "ttcf_channel_step",
             "ttcf_channel_accumulate", "ttcf_channel_response", "ttcf_channel_export_series",
             "ttcf_channel_export_daughter", "ttcf_channel_daughter_health",
-            "ttcf_channel_debug_forces", "ttcf_channel_step_timing"]
+            "ttcf_channel_debug_forces", "ttcf_channel_step_timing", "ttcf_autotune",
+            "ttcf_autotune_export", "ttcf_autotune_import"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -455,6 +464,29 @@ class Context:
         _check(lib().ttcf_step_timing(self._ctx, C.byref(ms), C.byref(n), int(reset)),
                "ttcf_step_timing", self._ctx)
         return ms.value, n.value
+
+    def ttcf_autotune(self, mother: int, n_states: int = 0, gamma_dot: float = 1e-3,
+                      probe_steps: int = 50) -> dict:
+        """Times the candidate step shapes on probe daughters of ``mother`` and caches the
+        fastest for its system (see include/ttcf.h)."""
+        out = Shape()
+        _check(lib().ttcf_autotune(self._ctx, int(mother), int(n_states), float(gamma_dot),
+                                   int(probe_steps), C.byref(out)), "ttcf_autotune", self._ctx)
+        return {"variant": out.variant, "threads": out.threads, "kmax": out.kmax,
+                "skin": out.skin, "ms_per_step": out.ms_per_step, "candidates": out.candidates}
+
+    def ttcf_autotune_export(self) -> str:
+        n = C.c_int64(0)
+        _check(lib().ttcf_autotune_export(self._ctx, None, 0, C.byref(n)), "ttcf_autotune_export",
+               self._ctx)
+        buf = C.create_string_buffer(n.value + 1)
+        _check(lib().ttcf_autotune_export(self._ctx, buf, n.value + 1, C.byref(n)),
+               "ttcf_autotune_export", self._ctx)
+        return buf.value.decode()
+
+    def ttcf_autotune_import(self, text: str):
+        _check(lib().ttcf_autotune_import(self._ctx, text.encode()), "ttcf_autotune_import",
+               self._ctx)
 
     # ---- learned control variate
     def ttcf_cv_init(self, n_out: int, weights):

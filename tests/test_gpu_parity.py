@@ -460,6 +460,61 @@ def test_mixed_forms_in_one_step_call(T):
     assert np.all(np.isfinite(both["big"])) and np.all(np.isfinite(both["small"]))
 
 
+def test_autotuned_shape_is_the_one_used(T):
+    """The autotuner leaves live daughters alone, caches its pick for the system, and
+    ttcf_step then runs exactly that shape: series equal bit for bit to the same shape set
+    explicitly or imported from the exported cache text, and to the default shape within
+    FP32 rounding."""
+    s = I.System(5)
+    r0, p0 = I.initial_state(s, 41)
+    nst = 30
+    say("autotune")
+
+    def run(setup):
+        with T.Context() as ctx:
+            mid = ctx.ttcf_init_mother(gsys(T, s, 1), r0, p0, n_equil=200, n_melt=200, t_melt=2.0)
+            ctx.ttcf_sample_states(mid, 8, 20)
+            first = ctx.ttcf_spawn_daughters(mid, 8, 0, 0.05, nst)
+            info = setup(ctx, mid)
+            ctx.ttcf_step(nst)
+            series = ctx.ttcf_export_series(first, 32, nst + 1)
+            assert ctx.ttcf_accumulate() == 8
+            return series, info
+
+    tuned, (shape, text) = run(lambda ctx, mid: (ctx.ttcf_autotune(mid, 0, 0.05, 20),
+                                                 ctx.ttcf_autotune_export()))
+    say("tuned shape", shape)
+    assert shape["variant"] in (1, 2) and shape["threads"] in (256, 512, 1024)
+    assert shape["candidates"] >= 3 and shape["ms_per_step"] > 0.0
+    assert '"n": 500' in text
+    nl = shape["variant"] == 2
+    explicit, _ = run(lambda ctx, mid: ctx.ttcf_set_step_shape(
+        shape["variant"], shape["threads"], shape["skin"] if nl else 0.0,
+        shape["kmax"] if nl else 0))
+    imported, _ = run(lambda ctx, mid: ctx.ttcf_autotune_import(text))
+    default, _ = run(lambda ctx, mid: None)
+    assert np.array_equal(tuned, explicit)
+    assert np.array_equal(tuned, imported)
+    assert np.abs(tuned - default).max() <= 1e-4 * np.abs(default).max()
+    assert np.all(np.isfinite(tuned))
+
+
+def test_autotune_cache_text_is_validated(T):
+    s = I.System(4)
+    r0, p0 = I.initial_state(s, 3)
+    with T.Context() as ctx:
+        ctx.ttcf_init_mother(gsys(T, s, 1), r0, p0, n_equil=0)
+        assert ctx.ttcf_autotune_export().strip() == "[\n]".strip()
+        with pytest.raises(T.TTCFError):
+            ctx.ttcf_autotune_import('[{"arch": "x", "n": 256}]')
+        with pytest.raises(T.TTCFError):
+            ctx.ttcf_autotune(0)  # no stored start states yet
+        good = ('[{"arch": "gfx000", "n": 256, "rho_key": 844, "rc_key": 11225, "precision": 1, '
+                '"variant": 2, "threads": 256, "kmax": 20, "skin": 0.4, "ms_per_step": 1}]')
+        ctx.ttcf_autotune_import(good)
+        assert '"arch": "gfx000"' in ctx.ttcf_autotune_export()
+
+
 # ----------------------------------------------------------------------------------------
 # the mother on the GPU
 # ----------------------------------------------------------------------------------------

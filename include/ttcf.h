@@ -252,6 +252,47 @@ int32_t ttcf_autotune_import(ttcf_ctx* ctx, const char* text);
  * last reset (timing events are recorded on the context's stream around every launch). */
 int32_t ttcf_step_timing(ttcf_ctx* ctx, double* total_ms, int64_t* launches, int32_t reset);
 
+/* ---- captured batch cycles -----------------------------------------------------------
+ * One cycle of Alg. SHELL SCRIPT and Alg. LAMMPS SCRIPT for one mother, recorded once as a
+ * HIP graph and replayed without host work: the mother (or its parallel copies) advances and
+ * saves start states, the mapped daughters of every state are spawned, run n_steps steps and
+ * folded into per-start-state rows, as ttcf_sample_states / ttcf_sample_states_replicated,
+ * ttcf_spawn_daughters, ttcf_step and ttcf_accumulate would do them, with the same kernels
+ * and launch shapes (the shape is resolved when the graph is created). Every node is a
+ * kernel (no memset or copy nodes). */
+typedef struct ttcf_graph ttcf_graph;
+typedef struct ttcf_graph_desc {
+    int32_t mother;
+    int32_t n_replicas;          /* 0: the mother itself saves the states; R > 0: R copies of it
+                                  * (made at creation with optional momentum kicks, then
+                                  * decorrelated) run in parallel and persist across replays */
+    const double* kicks;         /* R*3n zero-sum momentum kicks (SoA per copy) or NULL      */
+    int64_t decorrelate_steps;   /* copies: steps run once at creation                        */
+    int32_t states_per_replica;  /* states saved per copy per replay (R = 0: per replay)      */
+    int64_t steps_between;       /* mother steps before each saved state (> 0)                */
+    uint32_t mapping_mask;       /* as ttcf_spawn_daughters                                   */
+    const double* gamma_dot;     /* n_gamma == 1, or one rate per saved state                 */
+    int32_t n_gamma;
+    int32_t n_steps;             /* daughter length N_d                                       */
+    int32_t max_replays;         /* accumulator rows are reserved for this many replays       */
+} ttcf_graph_desc;
+/* Records the cycle. Start states are saved copy-major (copy r's states together), groups are
+ * numbered state-major as in ttcf_spawn_daughters. Reserves max_replays * (number of saved
+ * states) accumulator rows (they count in ttcf_response once written) plus room for 4096
+ * rows of ordinary ttcf_accumulate calls: while a graph exists the accumulator cannot grow
+ * beyond that (TTCF_ESTATE). The context's mother is advanced by replays in stream order with
+ * the context's other work. Errors: TTCF_EINVAL (bad description, shape does not fit),
+ * TTCF_ENOMEM, TTCF_EDEVICE (capture or instantiation failed). */
+int32_t ttcf_graph_create(ttcf_ctx* ctx, const ttcf_graph_desc* desc, ttcf_graph** out);
+/* Replays the cycle n_replays times on the context's stream (asynchronous). TTCF_ESTATE when
+ * that would exceed max_replays. */
+int32_t ttcf_graph_launch(ttcf_graph* graph, int32_t n_replays);
+/* Replays so far. */
+int32_t ttcf_graph_replays(const ttcf_graph* graph, int32_t* out_replays);
+/* Waits for the context's stream and frees the graph and its buffers; rows it has written
+ * stay in the accumulator. ttcf_destroy destroys the graphs of its context. */
+void ttcf_graph_destroy(ttcf_graph* graph);
+
 /* ---- learned control variate for Eq. (TTCF) ------------------------------------------
  * Not part of the paper's method: a variance-reduction layer over its estimator. A network
  * g(x) predicts B(t_1..t_K) of a daughter from 64 features x of its mapped start state

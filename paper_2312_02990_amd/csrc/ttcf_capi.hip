@@ -182,6 +182,9 @@ struct ttcf_ctx {
     bool shape_explicit = false;
     std::vector<TunedShape> tuned;
     std::string arch;
+    // captured batch cycles (they pin the accumulator arrays while they exist)
+    std::vector<ttcf_graph*> graphs;
+    bool graph_rows_dirty = false;  // graphs have written row health since the last download
     int32_t last_variant = -1;
     // timing of the step kernel
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending_events;
@@ -361,6 +364,9 @@ int32_t run_mother(ttcf_ctx* c, Mother& m, double temperature, int64_t n_chunks,
 int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
     const int32_t stride = std::max(c->acc_stride, n_t);
     if (rows_needed <= c->acc_cap && stride == c->acc_stride) return TTCF_OK;
+    if (!c->graphs.empty())
+        return fail(c, TTCF_ESTATE, "accumulator capacity is pinned by a captured graph: destroy "
+                                    "it before accumulating beyond the rows reserved for it");
     const int64_t cap = std::max<int64_t>(rows_needed, 2 * c->acc_cap);
     double* nd = (double*)dev_alloc(sizeof(double) * (size_t)cap * stride, c->stream);
     double* ni = (double*)dev_alloc(sizeof(double) * (size_t)cap * stride, c->stream);
@@ -432,6 +438,7 @@ const char* ttcf_last_error(const ttcf_ctx* ctx) { return ctx ? ctx->err.c_str()
 
 void ttcf_destroy(ttcf_ctx* c) {
     if (!c) return;
+    while (!c->graphs.empty()) ttcf_graph_destroy(c->graphs.back());
     (void)hipStreamSynchronize(c->stream);
     for (auto& ev : c->pending_events) {
         (void)hipEventDestroy(ev.first);
@@ -447,6 +454,7 @@ void ttcf_destroy(ttcf_ctx* c) {
         dev_free(b.states);
         dev_free(b.series);
         dev_free(b.scratch);
+        dev_free(b.hseries);
     }
     dev_free(c->d_descs);
     dev_free(c->d_order);
@@ -749,13 +757,15 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
 
 // Launch shape of one group of daughters in one kernel form. threads_req > 0 fixes the
 // workgroup size; kmax is the list capacity of the neighbour-list form.
-int32_t plan_group(ttcf_ctx* c, const std::vector<int32_t>& group, int variant, int precision,
-                   int32_t n_steps, int threads_req, int kmax, BatchLaunch* L) {
-    int nmax = 0, cmax = 0, lcmax = 0, threads = 0;
+// block_explicit: some member's system fixes its workgroup size (block_threads > 0).
+int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, bool block_explicit,
+                   int variant, int precision, int32_t n_steps, int threads_req, BatchLaunch* L) {
+    int nmax = 0, cmax = 0, lcmax = 0, threads = 0, kmax = 0;
     size_t nl_lds = 0;
-    bool explicit_threads = threads_req > 0;
-    for (int32_t i : group) {
-        const DaughterDesc& d = c->descs[i];
+    bool explicit_threads = threads_req > 0 || block_explicit;
+    for (const DaughterDesc* dp : group) {
+        const DaughterDesc& d = *dp;
+        kmax = std::max(kmax, d.kmax);
         nmax = std::max(nmax, d.sys.n);
         cmax = std::max(cmax, d.sys.nc[0] * d.sys.nc[1] * d.sys.nc[2]);
         lcmax = std::max(lcmax, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2]);
@@ -763,8 +773,6 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<int32_t>& group, int variant, 
             nl_lds = std::max(nl_lds, lds_bytes_nl(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2],
                                                    d.kmax));
         threads = std::max(threads, d.block);
-        explicit_threads = explicit_threads ||
-                           c->mothers[c->batches[c->live[i].batch].mother].sys.block_threads > 0;
     }
     if (threads_req > 0) threads = threads_req;
     // 512 threads with up to 4 atoms each keep the list form free of register spills
@@ -807,6 +815,32 @@ const TunedShape* find_tuned(const ttcf_ctx* c, const SysDev& d, int precision) 
     return nullptr;
 }
 
+// Shape a daughter of system d runs with: `force`, else the explicit shape, else the tuned
+// shape of its system, else the defaults.
+StepShape resolve_shape(const ttcf_ctx* c, const SysDev& d, int precision, const StepShape* force) {
+    StepShape e;
+    if (force) {
+        e = *force;
+    } else if (c->shape_explicit) {
+        e = c->shape;
+    } else if (const TunedShape* t = find_tuned(c, d, precision)) {
+        e = t->shape;
+    }
+    if (e.kmax <= 0) e.kmax = kDefaultKmax;
+    return e;
+}
+
+// Writes the list grid and capacity of shape e into a descriptor; *nl tells whether it runs in
+// the neighbour-list form (FP32 forces, not forced to cells, and its lists fit in LDS).
+int32_t apply_shape(ttcf_ctx* c, const StepShape& e, int precision, DaughterDesc* d, bool* nl) {
+    d->kmax = e.kmax;
+    *nl = precision == TTCF_PREC_FP32_FORCES && e.variant != 1 && set_list_grid(&d->sys, e.skin) &&
+          lds_bytes_nl(d->sys.n, d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2], e.kmax) <= c->max_lds;
+    if (e.variant == 2 && !*nl)
+        return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
+    return TTCF_OK;
+}
+
 // Advances the live daughters selected by `only` (all when null) by up to n_steps. `force`
 // (may be null) overrides every other shape. With timing, the launches are bracketed by
 // events that ttcf_step_timing reads.
@@ -828,23 +862,11 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
             precision = m.sys.precision;
         else if (precision != m.sys.precision)
             return fail(c, TTCF_EINVAL, "live daughters mix force precisions");
-        StepShape e;
-        if (force) {
-            e = *force;
-        } else if (c->shape_explicit) {
-            e = c->shape;
-        } else if (const TunedShape* t = find_tuned(c, d.sys, precision)) {
-            e = t->shape;
-        }
-        if (e.kmax <= 0) e.kmax = kDefaultKmax;
+        const StepShape e = resolve_shape(c, d.sys, precision, force);
         eff[i] = e;
-        d.kmax = e.kmax;
-        bool nl = precision == TTCF_PREC_FP32_FORCES && e.variant != 1 &&
-                  set_list_grid(&d.sys, e.skin) &&
-                  lds_bytes_nl(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2], e.kmax) <=
-                      c->max_lds;
-        if (e.variant == 2 && !nl)
-            return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
+        bool nl = false;
+        rc = apply_shape(c, e, precision, &d, &nl);
+        if (rc != TTCF_OK) return rc;
         (nl ? nl_group : cell_group).push_back((int32_t)i);
     }
     if (nl_group.empty() && cell_group.empty()) return TTCF_OK;
@@ -872,12 +894,17 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     for (int form = 0; form < 2; ++form) {
         const std::vector<int32_t>& group = form == 0 ? nl_group : cell_group;
         if (group.empty()) continue;
-        // the largest system's shape sets the workgroup size; the capacity covers every member
-        int kmax = 0;
-        for (int32_t i : group) kmax = std::max(kmax, eff[i].kmax);
+        // the largest system's shape sets the workgroup size
+        std::vector<const DaughterDesc*> ds;
+        bool block_explicit = false;
+        for (int32_t i : group) {
+            ds.push_back(&c->descs[i]);
+            block_explicit = block_explicit ||
+                             c->mothers[c->batches[c->live[i].batch].mother].sys.block_threads > 0;
+        }
         BatchLaunch L{};
-        rc = plan_group(c, group, form == 0 ? kVariantNeighbourList : kVariantCells, precision,
-                        n_steps, eff[group[0]].threads, kmax, &L);
+        rc = plan_group(c, ds, block_explicit, form == 0 ? kVariantNeighbourList : kVariantCells,
+                        precision, n_steps, eff[group[0]].threads, &L);
         if (rc != TTCF_OK) return rc;
         L.order = c->d_order + offset;
         offset += group.size();
@@ -1285,23 +1312,8 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
         A.h_out = c->acc_h + (size_t)c->acc_rows * c->acc_stride;
         A.n_groups = (int32_t)which.size();
         A.n_t = len;
-        // rows are written with the context's stride
-        if (c->acc_stride != len) {
-            // launch one group at a time into strided rows
-            for (int32_t g = 0; g < A.n_groups; ++g) {
-                AccumLaunch one = A;
-                one.first_of = d_first + g;
-                one.d_out = A.d_out + (size_t)g * c->acc_stride;
-                one.i_out = A.i_out + (size_t)g * c->acc_stride;
-                one.health_out = A.health_out + g;
-                one.gamma_out = A.gamma_out + g;
-                one.h_out = A.h_out + (size_t)g * c->acc_stride;
-                one.n_groups = 1;
-                HIPCHECK(c, launch_accumulate(one, c->stream));
-            }
-        } else {
-            HIPCHECK(c, launch_accumulate(A, c->stream));
-        }
+        A.row_stride = c->acc_stride;  // rows are written with the context's stride
+        HIPCHECK(c, launch_accumulate(A, c->stream));
         std::vector<int32_t> hh(which.size());
         HIPCHECK(c, hipMemcpyAsync(hh.data(), A.health_out, sizeof(int32_t) * which.size(),
                                    hipMemcpyDeviceToHost, c->stream));
@@ -1366,10 +1378,25 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
     return TTCF_OK;
 }
 
+namespace {
+// Rows that replayed graphs wrote carry their health on the device only: fetch it.
+int32_t refresh_row_health(ttcf_ctx* c) {
+    if (!c->graph_rows_dirty || c->acc_rows == 0) return TTCF_OK;
+    HIPCHECK(c, hipMemcpyAsync(c->row_health.data(), c->d_row_health,
+                               sizeof(int32_t) * (size_t)c->acc_rows, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    c->graph_rows_dirty = false;
+    return TTCF_OK;
+}
+}  // namespace
+
 int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, int32_t n_t,
                       double* ttcf_mean, double* ttcf_se, double* dav_mean, double* dav_se,
                       int64_t* out_n_states) {
     if (!c || observable != TTCF_OBS_PXY || n_t <= 0) return TTCF_EINVAL;
+    int32_t rc0 = refresh_row_health(c);
+    if (rc0 != TTCF_OK) return rc0;
     std::vector<int32_t> rows;
     for (int64_t r = 0; r < c->acc_rows; ++r) {
         if (gamma_dot_filter > 0.0 && c->row_gamma[r] != gamma_dot_filter) continue;
@@ -1418,6 +1445,305 @@ int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, 
     if (dav_se) std::memcpy(dav_se, out.data() + 3 * n_t, sizeof(double) * n_t);
     if (out_n_states) *out_n_states = used;
     return TTCF_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// captured batch cycles
+// ---------------------------------------------------------------------------------------
+struct ttcf_graph {
+    ttcf_ctx* ctx = nullptr;
+    int32_t mother = -1;
+    hipStream_t cap = nullptr;        // private stream the cycle was captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<void*> bufs;          // device buffers owned by the graph
+    int32_t n_states = 0, n_groups = 0, max_replays = 0, replays = 0;
+    int64_t mother_steps_per_replay = 0;  // steps the context's own mother advances per replay
+    void* get(size_t bytes) {
+        void* p = dev_alloc(bytes + 64, ctx->stream);
+        if (p) bufs.push_back(p);
+        return p;
+    }
+};
+
+namespace {
+
+constexpr int32_t kRowPending = 1 << 30;  // reserved row not yet written by a replay
+
+void free_graph(ttcf_graph* g) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    for (void* p : g->bufs) dev_free(p);
+    delete g;
+}
+
+}  // namespace
+
+int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** out) {
+    if (!c || !gd || !out) return TTCF_EINVAL;
+    if (gd->mother < 0 || gd->mother >= (int32_t)c->mothers.size() || gd->n_replicas < 0 ||
+        gd->states_per_replica <= 0 || gd->steps_between <= 0 || gd->decorrelate_steps < 0 ||
+        (gd->mapping_mask & 0xFu) == 0 || (gd->mapping_mask & ~0xFu) != 0 || !gd->gamma_dot ||
+        gd->n_steps <= 0 || gd->max_replays <= 0)
+        return fail(c, TTCF_EINVAL, "bad graph description");
+    const int64_t ns64 = (int64_t)std::max(1, gd->n_replicas) * gd->states_per_replica;
+    if (ns64 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many start states per replay");
+    const int32_t n_states = (int32_t)ns64;
+    if (!(gd->n_gamma == 1 || gd->n_gamma == n_states))
+        return fail(c, TTCF_EINVAL, "n_gamma must be 1 or the number of saved states");
+    for (int32_t q = 0; q < gd->n_gamma; ++q)
+        if (!std::isfinite(gd->gamma_dot[q])) return fail(c, TTCF_EINVAL, "shear rates must be finite");
+    Mother& m = c->mothers[gd->mother];
+    const int n = m.dev.n;
+    const size_t sz = 6 * (size_t)n;
+    std::vector<int32_t> maps;
+    for (int q = 0; q < 4; ++q)
+        if (gd->mapping_mask & (1u << q)) maps.push_back(q);
+    const int32_t nm = (int32_t)maps.size();
+    const int32_t nd = n_states * nm;
+    const int32_t n_t = gd->n_steps + 1;
+    const int64_t reserve = (int64_t)gd->max_replays * n_states;
+    // accumulator rows: grow (while nothing pins it) to hold the reserved rows and headroom
+    int32_t rc = grow_acc(c, c->acc_rows + reserve + 4096, n_t);
+    if (rc != TTCF_OK) return rc;
+
+    ttcf_graph* g = new ttcf_graph();
+    g->ctx = c;
+    g->mother = gd->mother;
+    g->n_states = n_states;
+    g->n_groups = n_states;
+    g->max_replays = gd->max_replays;
+    auto bail = [&](int32_t code, const std::string& msg) {
+        (void)hipStreamSynchronize(c->stream);
+        free_graph(g);
+        return fail(c, code, msg);
+    };
+    double* states = (double*)g->get(sizeof(double) * sz * n_states);
+    double* dstates = (double*)g->get(sizeof(double) * sz * nd);
+    double* series = (double*)g->get(sizeof(double) * (size_t)n_t * nd);
+    DaughterDesc* descs = (DaughterDesc*)g->get(sizeof(DaughterDesc) * nd);
+    DaughterDesc* templ = (DaughterDesc*)g->get(sizeof(DaughterDesc) * nd);
+    int32_t* ints = (int32_t*)g->get(sizeof(int32_t) * ((size_t)3 * nd + n_states + 8));
+    double** dst = (double**)g->get(sizeof(double*) * nd);
+    const int32_t n_copies = std::max(1, gd->n_replicas);
+    MotherLaunch* d_ml = (MotherLaunch*)g->get(sizeof(MotherLaunch) * n_copies);
+    if (!states || !dstates || !series || !descs || !templ || !ints || !dst || !d_ml)
+        return bail(TTCF_ENOMEM, "graph allocation failed");
+    int32_t* order = ints;
+    int32_t* state_of = order + nd;
+    int32_t* map_of = state_of + nd;
+    int32_t* first_of = map_of + nd;        // n_states + 1
+    int32_t* queue = first_of + n_states + 1;
+    int32_t* replay = queue + 4;
+
+    // mothers of the cycle: the context's mother itself, or persistent copies of it
+    std::vector<MotherLaunch> ml(n_copies);
+    const double nf = 3.0 * n - 3.0;
+    double* rep = nullptr;
+    if (gd->n_replicas > 0) {
+        rep = (double*)g->get(sizeof(double) * (sz * n_copies + n_copies));
+        double* kick_d = gd->kicks ? (double*)g->get(sizeof(double) * 3 * (size_t)n * n_copies)
+                                   : nullptr;
+        if (!rep || (gd->kicks && !kick_d)) return bail(TTCF_ENOMEM, "graph allocation failed");
+        if (gd->kicks && hipMemcpyAsync(kick_d, gd->kicks, sizeof(double) * 3 * (size_t)n * n_copies,
+                                        hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            return bail(TTCF_EDEVICE, "kick upload failed");
+        if (launch_replicate(m.state, m.zeta, n, kick_d, n_copies, rep, rep + sz * n_copies,
+                             c->stream) != hipSuccess)
+            return bail(TTCF_EDEVICE, "replica launch failed");
+    }
+    for (int r = 0; r < n_copies; ++r) {
+        MotherLaunch& L = ml[r];
+        L.sys = m.dev;
+        L.state = rep ? rep + sz * r : m.state;
+        L.zeta = rep ? rep + sz * n_copies + r : m.zeta;
+        L.temperature = m.sys.temperature;
+        L.nf = nf;
+        L.q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
+        L.threads = m.threads;
+        L.apt = m.apt;
+        L.precision = m.sys.precision;
+        L.lds_bytes = lds_for(m.dev, m.sys.precision);
+        L.series = nullptr;
+    }
+    if (rep && gd->decorrelate_steps > 0) {
+        // once, outside the graph, through the context's own launch block
+        for (auto& L : ml) {
+            L.n_chunks = 0;
+            L.steps_per_chunk = gd->decorrelate_steps;
+            L.snapshots = nullptr;
+        }
+        rc = upload_mother_launches(c, ml.data(), n_copies);
+        if (rc != TTCF_OK) return bail(rc, c->err);
+        if (launch_mothers(c->d_mlaunch, n_copies, ml[0], c->stream) != hipSuccess)
+            return bail(TTCF_EDEVICE, "decorrelation launch failed");
+    }
+    for (int r = 0; r < n_copies; ++r) {
+        ml[r].n_chunks = gd->states_per_replica;
+        ml[r].steps_per_chunk = gd->steps_between;
+        ml[r].snapshots = states + sz * (size_t)r * gd->states_per_replica;
+    }
+    g->mother_steps_per_replay = rep ? 0 : (int64_t)gd->states_per_replica * gd->steps_between;
+
+    // daughter descriptors (state-major groups, as ttcf_spawn_daughters) and their shape
+    const int precision = m.sys.precision;
+    const StepShape shape = resolve_shape(c, m.dev, precision, nullptr);
+    std::vector<DaughterDesc> hd(nd);
+    std::vector<double*> hdst(nd);
+    std::vector<int32_t> hints(3 * (size_t)nd + n_states + 1);
+    bool nl = false;
+    for (int32_t st = 0; st < n_states; ++st) {
+        const int32_t group = c->next_group++;
+        const double gdot = gd->gamma_dot[gd->n_gamma == 1 ? 0 : st];
+        for (int32_t q = 0; q < nm; ++q) {
+            const int32_t d = st * nm + q;
+            DaughterDesc& ds = hd[d];
+            ds = DaughterDesc{};
+            ds.state = dstates + sz * d;
+            ds.series = series + (size_t)n_t * d;
+            ds.sys = m.dev;
+            ds.gamma_dot = gdot;
+            ds.n_steps = gd->n_steps;
+            ds.group = group;
+            ds.map = maps[q];
+            ds.block = m.threads;
+            rc = apply_shape(c, shape, precision, &ds, &nl);
+            if (rc != TTCF_OK) return bail(rc, c->err);
+            hdst[d] = ds.state;
+            hints[d] = d;                    // order: one system size, any order
+            hints[nd + d] = st;              // state_of
+            hints[2 * (size_t)nd + d] = maps[q];  // map_of
+        }
+        hints[3 * (size_t)nd + st] = st * nm;    // first_of
+    }
+    hints[3 * (size_t)nd + n_states] = nd;
+    std::vector<const DaughterDesc*> hp;
+    for (auto& d : hd) hp.push_back(&d);
+    BatchLaunch B{};
+    rc = plan_group(c, hp, m.sys.block_threads > 0, nl ? kVariantNeighbourList : kVariantCells,
+                    precision, gd->n_steps, shape.threads, &B);
+    if (rc != TTCF_OK) return bail(rc, c->err);
+    B.descs = descs;
+    B.order = order;
+    B.queue = queue;
+
+    // reserved rows: metadata on the host and the device; pending until a replay writes them
+    const int64_t row0 = c->acc_rows;
+    for (int64_t r = 0; r < reserve; ++r) {
+        const DaughterDesc& d0 = hd[(size_t)(r % n_states) * nm];
+        c->row_gamma.push_back(d0.gamma_dot);
+        c->row_coef.push_back(d0.sys.volume * d0.gamma_dot / m.sys.temperature);
+        c->row_nt.push_back(n_t);
+        c->row_health.push_back(kRowPending);
+        c->row_cv.push_back(0);
+    }
+    c->acc_rows += reserve;
+    const int32_t zero = 0;
+    if (hipMemcpyAsync(templ, hd.data(), sizeof(DaughterDesc) * nd, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(dst, hdst.data(), sizeof(double*) * nd, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(ints, hints.data(), sizeof(int32_t) * hints.size(), hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(replay, &zero, sizeof(int32_t), hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(d_ml, ml.data(), sizeof(MotherLaunch) * n_copies, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_row_gamma, c->row_gamma.data(), sizeof(double) * c->row_gamma.size(),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_row_coef, c->row_coef.data(), sizeof(double) * c->row_coef.size(),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->d_row_health + row0, c->row_health.data() + row0,
+                       sizeof(int32_t) * (size_t)reserve, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        c->acc_rows = row0;
+        c->row_gamma.resize(row0);
+        c->row_coef.resize(row0);
+        c->row_nt.resize(row0);
+        c->row_health.resize(row0);
+        c->row_cv.resize(row0);
+        return bail(TTCF_EDEVICE, "graph upload failed");
+    }
+    AccumLaunch A{};
+    A.descs = descs;
+    A.first_of = first_of;
+    A.d_out = c->acc_d + (size_t)row0 * c->acc_stride;
+    A.i_out = c->acc_i + (size_t)row0 * c->acc_stride;
+    A.health_out = c->d_row_health + row0;
+    A.gamma_out = c->d_row_gamma + row0;
+    A.h_out = c->acc_h + (size_t)row0 * c->acc_stride;
+    A.n_groups = n_states;
+    A.n_t = n_t;
+    A.row_stride = c->acc_stride;
+    A.row_step = replay;
+
+    // the cycle: mothers -> spawn -> descriptor reset -> step -> accumulate -> next row block
+    auto undo_rows = [&]() {
+        c->acc_rows = row0;
+        c->row_gamma.resize(row0);
+        c->row_coef.resize(row0);
+        c->row_nt.resize(row0);
+        c->row_health.resize(row0);
+        c->row_cv.resize(row0);
+    };
+    if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) {
+        undo_rows();
+        return bail(TTCF_EDEVICE, "stream creation failed");
+    }
+    hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+        hipError_t e1 = launch_mothers(d_ml, n_copies, ml[0], g->cap);
+        if (e1 == hipSuccess)
+            e1 = launch_spawn(states, n, n_states, state_of, map_of, dst, nd, m.dev.box[0], g->cap);
+        if (e1 == hipSuccess)
+            e1 = launch_copy_words((const uint64_t*)templ, (uint64_t*)descs,
+                                   (int64_t)(sizeof(DaughterDesc) / 8) * nd, g->cap);
+        if (e1 == hipSuccess) e1 = launch_daughters(B, g->cap);
+        if (e1 == hipSuccess) e1 = launch_accumulate(A, g->cap);
+        if (e1 == hipSuccess) e1 = launch_increment(replay, g->cap);
+        e = hipStreamEndCapture(g->cap, &g->graph);
+        if (e1 != hipSuccess) e = e1;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        undo_rows();
+        return bail(TTCF_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+    }
+    static_assert(sizeof(DaughterDesc) % 8 == 0, "descriptors are copied as 64-bit words");
+    c->graphs.push_back(g);
+    *out = g;
+    return TTCF_OK;
+}
+
+int32_t ttcf_graph_launch(ttcf_graph* g, int32_t n_replays) {
+    if (!g || n_replays < 0) return TTCF_EINVAL;
+    ttcf_ctx* c = g->ctx;
+    if (g->replays + (int64_t)n_replays > g->max_replays)
+        return fail(c, TTCF_ESTATE, "replays beyond the rows reserved for this graph");
+    for (int32_t r = 0; r < n_replays; ++r) {
+        HIPCHECK(c, hipGraphLaunch(g->exec, c->stream));
+        ++g->replays;
+        c->mothers[g->mother].steps += g->mother_steps_per_replay;
+        c->graph_rows_dirty = true;
+    }
+    return TTCF_OK;
+}
+
+int32_t ttcf_graph_replays(const ttcf_graph* g, int32_t* out) {
+    if (!g || !out) return TTCF_EINVAL;
+    *out = g->replays;
+    return TTCF_OK;
+}
+
+void ttcf_graph_destroy(ttcf_graph* g) {
+    if (!g) return;
+    ttcf_ctx* c = g->ctx;
+    (void)hipStreamSynchronize(c->stream);
+    auto it = std::find(c->graphs.begin(), c->graphs.end(), g);
+    if (it != c->graphs.end()) c->graphs.erase(it);
+    free_graph(g);
 }
 
 // live daughters are kept in increasing id order (spawned in order, removed in place)
@@ -2065,6 +2391,8 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
 int32_t ttcf_cv_calibrate(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, double* beta) {
     int32_t rc = cv_check(c);
     if (rc != TTCF_OK) return rc;
+    rc = refresh_row_health(c);
+    if (rc != TTCF_OK) return rc;
     if (n_t <= 0 || n_t > c->cv_out + 1) return fail(c, TTCF_EINVAL, "n_t beyond the network's grid");
     std::vector<int32_t> rows;
     for (int64_t r = 0; r < c->acc_rows; ++r) {
@@ -2106,6 +2434,8 @@ int32_t ttcf_cv_response(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, doub
                          double* cv_se, double* plain_mean, double* plain_se, double* mu_h,
                          double* mu_h_se, int64_t* out_n_states) {
     int32_t rc = cv_check(c);
+    if (rc != TTCF_OK) return rc;
+    rc = refresh_row_health(c);
     if (rc != TTCF_OK) return rc;
     if (n_t <= 0 || n_t > c->cv_out + 1) return fail(c, TTCF_EINVAL, "n_t beyond the network's grid");
     if (c->cv_mu_count < 2) return fail(c, TTCF_ESTATE, "no mean term: call ttcf_cv_mean_term");

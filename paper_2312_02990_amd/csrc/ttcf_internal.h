@@ -104,6 +104,9 @@ struct AccumLaunch {
     double* gamma_out;           // n_groups
     double* h_out;               // same layout: mean over mappings of h(t_k) (0 without CV)
     int32_t n_groups, n_t;
+    int32_t row_stride;          // doubles between output rows (0: n_t)
+    const int32_t* row_step;     // device counter or null: outputs start (*row_step) * n_groups
+                                 // rows further on (a replayed graph writes fresh rows each time)
 };
 
 struct ResponseLaunch {
@@ -186,6 +189,10 @@ hipError_t launch_mothers(const MotherLaunch* dev_ms, int count, const MotherLau
 hipError_t launch_replicate(const double* src, const double* zsrc, int32_t n, const double* kicks,
                             int32_t count, double* dst, double* zdst, hipStream_t s);
 hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s);
+// dst[i] = src[i], i < count (64-bit words)
+hipError_t launch_copy_words(const uint64_t* src, uint64_t* dst, int64_t count, hipStream_t s);
+// *counter += 1 (one thread)
+hipError_t launch_increment(int32_t* counter, hipStream_t s);
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s);
 hipError_t launch_spawn(const double* states, int32_t n, int32_t n_states, const int32_t* state_of,
                         const int32_t* map_of, double* const* dst, int32_t n_daughters, double lx,

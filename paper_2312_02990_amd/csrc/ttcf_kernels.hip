@@ -844,6 +844,9 @@ __global__ void k_accumulate(AccumLaunch a) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= a.n_groups) return;
     const int b = a.first_of[g], e = a.first_of[g + 1];
+    // output row of this group
+    const size_t row = (size_t)g + (a.row_step ? (size_t)(*a.row_step) * (size_t)a.n_groups : 0);
+    const size_t stride = a.row_stride > 0 ? (size_t)a.row_stride : (size_t)a.n_t;
     const int nm = min(e - b, kMaxMaps);
     int health = 0;
     double p0[kMaxMaps], sum[kMaxMaps], comp[kMaxMaps], prev[kMaxMaps];
@@ -860,14 +863,14 @@ __global__ void k_accumulate(AccumLaunch a) {
         sum[m] = 0.0;
         comp[m] = 0.0;
     }
-    a.health_out[g] = health;
-    a.gamma_out[g] = a.descs[b].gamma_dot;
+    a.health_out[row] = health;
+    a.gamma_out[row] = a.descs[b].gamma_dot;
     const double inm = 1.0 / (double)nm;
-    double* dout = a.d_out + (size_t)g * a.n_t;
-    double* iout = a.i_out + (size_t)g * a.n_t;
+    double* dout = a.d_out + row * stride;
+    double* iout = a.i_out + row * stride;
     if (a.h_out) {
         // mapping mean of the learned control variate (0 where a daughter has none)
-        double* hout = a.h_out + (size_t)g * a.n_t;
+        double* hout = a.h_out + row * stride;
         for (int k = 0; k < a.n_t; ++k) {
             double hs = 0.0;
             for (int m = 0; m < nm; ++m) {
@@ -1877,6 +1880,29 @@ hipError_t launch_replicate(const double* src, const double* zsrc, int32_t n, co
 hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s) {
     if (a.n_groups <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_accumulate, dim3((a.n_groups + 63) / 64), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_words(const uint64_t* src, uint64_t* dst, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+__global__ void k_increment(int32_t* counter) {
+    if (threadIdx.x == 0) counter[0] = counter[0] + 1;
+}
+
+hipError_t launch_copy_words(const uint64_t* src, uint64_t* dst, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    const int64_t want = (count + 255) / 256;
+    const int64_t blocks = want < 1024 ? want : 1024;
+    hipLaunchKernelGGL(k_copy_words, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_increment(int32_t* counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_increment, dim3(1), dim3(64), 0, s, counter);
     return hipGetLastError();
 }
 

@@ -44,6 +44,14 @@ class Shape(C.Structure):
                 ("skin", C.c_double), ("ms_per_step", C.c_double), ("candidates", C.c_int32)]
 
 
+class GraphDesc(C.Structure):
+    _fields_ = [("mother", C.c_int32), ("n_replicas", C.c_int32),
+                ("kicks", C.POINTER(C.c_double)), ("decorrelate_steps", C.c_int64),
+                ("states_per_replica", C.c_int32), ("steps_between", C.c_int64),
+                ("mapping_mask", C.c_uint32), ("gamma_dot", C.POINTER(C.c_double)),
+                ("n_gamma", C.c_int32), ("n_steps", C.c_int32), ("max_replays", C.c_int32)]
+
+
 class Channel(C.Structure):
     """ttcf_channel of include/ttcf.h."""
     _fields_ = [("n_fluid", C.c_int32), ("n_wall", C.c_int32), ("n_bins", C.c_int32),
@@ -164,6 +172,9 @@ def lib():
         "ttcf_channel_step_timing": [V, D, L64, C.c_int32],
         "ttcf_sample_states_replicated": [V, C.c_int32, C.c_int32, D, C.c_int64, C.c_int32,
                                           C.c_int64],
+        "ttcf_graph_create": [V, C.POINTER(GraphDesc), P],
+        "ttcf_graph_launch": [V, C.c_int32],
+        "ttcf_graph_replays": [V, I],
         "ttcf_autotune": [V, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.POINTER(Shape)],
         "ttcf_autotune_export": [V, C.c_char_p, C.c_int64, L64],
         "ttcf_autotune_import": [V, C.c_char_p],
@@ -180,6 +191,8 @@ def lib():
     L.ttcf_strerror.restype = C.c_char_p
     L.ttcf_last_error.argtypes = [V]
     L.ttcf_last_error.restype = C.c_char_p
+    L.ttcf_graph_destroy.argtypes = [V]
+    L.ttcf_graph_destroy.restype = None
     L.ttcf_channel_destroy.argtypes = [V]
     L.ttcf_channel_destroy.restype = None
     L.ttcf_channel_last_error.argtypes = [V]
@@ -205,7 +218,8 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_channel_accumulate", "ttcf_channel_response", "ttcf_channel_export_series",
             "ttcf_channel_export_daughter", "ttcf_channel_daughter_health",
             "ttcf_channel_debug_forces", "ttcf_channel_step_timing", "ttcf_autotune",
-            "ttcf_autotune_export", "ttcf_autotune_import"]
+            "ttcf_autotune_export", "ttcf_autotune_import", "ttcf_graph_create",
+            "ttcf_graph_launch", "ttcf_graph_replays", "ttcf_graph_destroy"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -317,12 +331,15 @@ class Context:
         self._ctx = C.c_void_p(None)
         self._stream = stream
         self.systems = []
+        self._graphs = []
 
     @property
     def handle(self):
         return self._ctx
 
     def close(self):
+        for g in list(self._graphs):
+            g.destroy()
         if self._ctx:
             lib().ttcf_destroy(self._ctx)
             self._ctx = C.c_void_p(None)
@@ -465,6 +482,22 @@ class Context:
                "ttcf_step_timing", self._ctx)
         return ms.value, n.value
 
+    def ttcf_graph_create(self, mother: int, states_per_replica: int, steps_between: int,
+                          gamma_dot, n_steps: int, max_replays: int, n_replicas: int = 0,
+                          kicks=None, decorrelate_steps: int = 0, mapping_mask: int = 0xF):
+        """Records one batch cycle of ``mother`` as a HIP graph (see include/ttcf.h)."""
+        g = _f64(np.atleast_1d(gamma_dot))
+        k = None if kicks is None else _f64(kicks).ravel()
+        d = GraphDesc(int(mother), int(n_replicas), _dp(k), int(decorrelate_steps),
+                      int(states_per_replica), int(steps_between), int(mapping_mask), _dp(g),
+                      int(g.size), int(n_steps), int(max_replays))
+        h = C.c_void_p(None)
+        _check(lib().ttcf_graph_create(self._ctx, C.byref(d), C.byref(h)), "ttcf_graph_create",
+               self._ctx)
+        gr = Graph(self, h)
+        self._graphs.append(gr)
+        return gr
+
     def ttcf_autotune(self, mother: int, n_states: int = 0, gamma_dot: float = 1e-3,
                       probe_steps: int = 50) -> dict:
         """Times the candidate step shapes on probe daughters of ``mother`` and caches the
@@ -571,6 +604,32 @@ class Context:
 # ----------------------------------------------------------------------------------------
 # the confined channel
 # ----------------------------------------------------------------------------------------
+
+class Graph:
+    """A captured batch cycle; destroyed with its context at the latest."""
+
+    def __init__(self, ctx: Context, handle):
+        self._owner = ctx
+        self._h = handle
+
+    def launch(self, n_replays: int = 1):
+        _check(lib().ttcf_graph_launch(self._h, int(n_replays)), "ttcf_graph_launch",
+               self._owner._ctx)
+
+    @property
+    def replays(self) -> int:
+        r = C.c_int32(0)
+        _check(lib().ttcf_graph_replays(self._h, C.byref(r)), "ttcf_graph_replays",
+               self._owner._ctx)
+        return r.value
+
+    def destroy(self):
+        if self._h:
+            lib().ttcf_graph_destroy(self._h)
+            self._h = C.c_void_p(None)
+            if self in self._owner._graphs:
+                self._owner._graphs.remove(self)
+
 
 def ttcf_channel_debug_forces(ch: Channel, r, lattice, stream=None):
     """(f (3n,), out[5]) of one configuration at the given lattice sites."""

@@ -516,6 +516,103 @@ def test_autotune_cache_text_is_validated(T):
 
 
 # ----------------------------------------------------------------------------------------
+# captured batch cycles: every replay equals the same cycle run through the eager calls
+# ----------------------------------------------------------------------------------------
+def _same_response(a, b):
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+    assert a[4] == b[4]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_graph_replays_equal_eager_cycles(T, precision):
+    """A mother that saves 6 states 30 steps apart, per-state shear rates, 25-step daughters:
+    after each replay (eager work and synchronisation in between) the response and the
+    mother equal those of the same number of eager cycles, bit for bit."""
+    s = I.System(4)
+    r0, p0 = I.initial_state(s, 51)
+    ns, sb, nst, reps = 6, 30, 25, 3
+    gam = I.log_uniform_rates(ns, 1e-3, 1e-1, 52)
+    say("graph vs eager, precision", precision)
+    eager, eager_mother = [], None
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, precision), r0, p0, n_equil=100)
+        for _ in range(reps):
+            ctx.ttcf_spawn_daughters(mid, ns, sb, gam, nst)
+            ctx.ttcf_step(nst)
+            ctx.ttcf_accumulate()
+            eager.append(ctx.ttcf_response(nst + 1, 0.0))
+        eager_mother = ctx.ttcf_export_mother(mid)
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, precision), r0, p0, n_equil=100)
+        g = ctx.ttcf_graph_create(mid, ns, sb, gam, nst, max_replays=reps)
+        with pytest.raises(T.TTCFError):
+            ctx.ttcf_response(nst + 1, 0.0)  # reserved rows are not counted before a replay
+        for k in range(reps):
+            g.launch(1)
+            got = ctx.ttcf_response(nst + 1, 0.0)
+            _same_response(got, eager[k])
+            ctx.ttcf_export_mother(mid)  # eager work between replays
+        assert g.replays == reps
+        with pytest.raises(T.TTCFError):
+            g.launch(1)
+        r, p, z, steps = ctx.ttcf_export_mother(mid)
+        assert np.array_equal(r, eager_mother[0]) and np.array_equal(p, eager_mother[1])
+        assert z == eager_mother[2] and steps == eager_mother[3]
+        # ordinary daughters accumulate beside the graph's rows
+        ctx.ttcf_spawn_daughters(mid, ns, sb, gam, nst)
+        ctx.ttcf_step(nst)
+        assert ctx.ttcf_accumulate() == ns
+        assert ctx.ttcf_response(nst + 1, 0.0)[4] == (reps + 1) * ns
+
+
+def test_graph_with_parallel_mother_copies(T):
+    """Mother copies (kicked, decorrelated) persist across replays: the first replay equals
+    eager replicated sampling bit for bit, and two replays of 2 states per copy equal one
+    replay of 4 states per copy (the same start states; rows in another order)."""
+    s = I.System(4)
+    r0, p0 = I.initial_state(s, 61)
+    n_rep, per, sb, nst, dec = 4, 2, 20, 25, 50
+    rng = np.random.Generator(np.random.PCG64(62))
+    kicks = 0.05 * rng.standard_normal((n_rep, 3, s.n))
+    kicks -= kicks.mean(axis=2, keepdims=True)
+    kicks = kicks.reshape(n_rep, -1)
+    say("graph with mother copies")
+
+    def mother(ctx):
+        return ctx.ttcf_init_mother(gsys(T, s, 1), r0, p0, n_equil=100)
+
+    with T.Context() as ctx:
+        mid = mother(ctx)
+        ctx.ttcf_sample_states_replicated(mid, n_rep, kicks, dec, per, sb)
+        ctx.ttcf_spawn_daughters(mid, n_rep * per, 0, 0.02, nst)
+        ctx.ttcf_step(nst)
+        ctx.ttcf_accumulate()
+        eager = ctx.ttcf_response(nst + 1, 0.02)
+    with T.Context() as ctx:
+        mid = mother(ctx)
+        g = ctx.ttcf_graph_create(mid, per, sb, 0.02, nst, max_replays=2, n_replicas=n_rep,
+                                  kicks=kicks, decorrelate_steps=dec)
+        g.launch(1)
+        _same_response(ctx.ttcf_response(nst + 1, 0.02), eager)
+        g.launch(1)
+        two = ctx.ttcf_response(nst + 1, 0.02)
+        m_after = ctx.ttcf_export_mother(mid)
+    with T.Context() as ctx:
+        mid = mother(ctx)
+        g = ctx.ttcf_graph_create(mid, 2 * per, sb, 0.02, nst, max_replays=1, n_replicas=n_rep,
+                                  kicks=kicks, decorrelate_steps=dec)
+        g.launch(1)
+        one = ctx.ttcf_response(nst + 1, 0.02)
+        m_before = ctx.ttcf_export_mother(mid)
+    assert two[4] == one[4] == 2 * n_rep * per
+    for x, y in zip(two[:4], one[:4]):
+        np.testing.assert_allclose(x, y, rtol=1e-9, atol=1e-12 * np.abs(y).max())
+    # the copies ran, not the context's mother
+    assert m_after[3] == m_before[3] and np.array_equal(m_after[0], m_before[0])
+
+
+# ----------------------------------------------------------------------------------------
 # the mother on the GPU
 # ----------------------------------------------------------------------------------------
 

@@ -197,6 +197,41 @@ def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per
             "per_unit_rate_ttcf_end": float(tm[-1]), "per_unit_rate_ttcf_se_end": float(tse[-1])}
 
 
+def graph_leg(T, stream, n_cells=8, copies=1024, between=100, nst=500, gd=1e-2, replays=3,
+              decorrelate=400, seed=7):
+    """Whole batch cycles replayed from one captured graph: 1024 persistent copies of the
+    N = 2048 mother (kicked, decorrelated 400 steps) each advance 100 steps and save one start
+    state, whose four mapped daughters run 500 steps at shear rate 1e-2 and are folded into
+    the accumulator, with no host work between replays. Throughput counts daughter atom-steps
+    only, while the timed cycle also holds the mother steps, spawn and accumulation."""
+    import torch
+    import ttcf_inputs as I
+    s = I.System(n_cells)
+    r0, p0 = I.initial_state(s, 2)
+    with T.Context(stream) as ctx:
+        mid = ctx.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1),
+                                   r0, p0, n_equil=2000, n_melt=1000, t_melt=2.0)
+        g = ctx.ttcf_graph_create(mid, 1, between, gd, nst, max_replays=replays + 1,
+                                  n_replicas=copies, kicks=seeded_kicks(copies, s.n, 0.05, seed),
+                                  decorrelate_steps=decorrelate)
+        g.launch(1)  # warm-up replay
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.launch(replays)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, gd)
+    atom_steps = 4 * copies * s.n * nst * replays
+    return {"workload": f"N={s.n} WCA, {copies} mother copies x 1 state per replay ({between} "
+                        f"steps apart), 4 mappings x {nst} steps at shear rate {gd}; "
+                        f"{replays} timed replays",
+            "ms_per_cycle": 1e3 * wall / replays,
+            "daughter_atom_steps_per_s": atom_steps / wall,
+            "mother_atom_step_share": between / (between + 4 * nst),
+            "n_states": int(used), "ttcf_end": float(tm[-1]), "ttcf_se_end": float(tse[-1]),
+            "dav_end": float(dm[-1]), "dav_se_end": float(dse[-1])}
+
+
 def channel_leg(T, stream, n_states=256, nst=1000, speeds=(1e-2, 1e-4), n_equil=2000,
                 between=20, seed=4):
     """The confined channel at full size: 12000 fluid + 2 x 3000 tethered wall atoms, LJ
@@ -385,6 +420,8 @@ def main():
     ap.add_argument("--fp64-check", type=int, default=1,
                     help="1: rerun the batch's start states with FP64 forces at every shear rate "
                          "and report the FP32-force error of each response")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="1: also measure whole cycles replayed from a captured graph")
     ap.add_argument("--uneven", type=int, default=1,
                     help="1: also measure the mixed-size batch (report under 'uneven')")
     ap.add_argument("--channel", type=int, default=1,
@@ -503,6 +540,11 @@ def main():
     }
     if precision is not None:
         line["precision"] = precision
+    if args.graph:
+        try:
+            line["graph"] = graph_leg(T, stream)
+        except Exception as e:  # the headline line is printed whatever happens here
+            line["graph"] = {"error": repr(e)}
     if args.uneven:
         try:
             line["uneven"] = uneven_leg(T, stream)

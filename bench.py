@@ -164,7 +164,7 @@ def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per
                                               200, 1, 50)
             if tune:
                 t1 = time.perf_counter()
-                sh = ctx.ttcf_autotune(mid, 0, 1e-3, 40)
+                sh = ctx.ttcf_autotune(mid, 0, 1e-3, 200)
                 tune_s += time.perf_counter() - t1
                 shapes[f"N={s.n} rho={rho}"] = (
                     f"{'lists' if sh['variant'] == 2 else 'cells'}/{sh['threads']}"

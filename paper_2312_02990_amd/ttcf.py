@@ -499,7 +499,7 @@ class Context:
         return gr
 
     def ttcf_autotune(self, mother: int, n_states: int = 0, gamma_dot: float = 1e-3,
-                      probe_steps: int = 50) -> dict:
+                      probe_steps: int = 200) -> dict:
         """Times the candidate step shapes on probe daughters of ``mother`` and caches the
         fastest for its system (see include/ttcf.h)."""
         out = Shape()

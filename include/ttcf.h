@@ -210,24 +210,23 @@ int32_t ttcf_set_step_shape(ttcf_ctx* ctx, int32_t variant, int32_t threads, dou
                             int32_t kmax);
 
 /* Launch-shape autotuner for the batched step of many independent daughters (Sec. Software
- * methodology: the daughter runs are split into independent jobs, one per core). Times
- * the step kernel on probe daughters spawned from the first n_states stored start states of
+ * methodology: the daughter runs are split into independent jobs, one per core). Times the
+ * step kernel on probe daughters spawned from the first n_states stored start states of
  * `mother` (0: all; all four mappings, shear rate gamma_dot; the set repeated until there
- * are four daughters per compute unit, so that throughput is measured) over a short untimed
- * warm-up
- * and probe_steps timed steps, for each candidate shape: the cell form at 256, 512 and 1024
- * threads, and (FP32 forces) the neighbour-list form at those sizes and at the skins that
- * fill list cells one coarser, equal to and one finer than the automatic grid, its list
- * capacity raised while the probe overflows. Probe daughters are discarded (never
- * accumulated) and live daughters are not advanced. The fastest shape (list capacity plus a
- * margin of 4 where it fits) is stored in the context's cache under (device architecture,
- * N, round(1000 N/V), round(10000 r_cut), precision), replacing an older entry, and written
- * to *out (may be NULL). While no explicit shape is set (ttcf_set_step_shape(ctx, 0, 0, 0,
- * 0), the default), ttcf_step uses the cached shape of each daughter's system, the list
- * grid of its skin and, per launch, the workgroup size of the largest system and the
- * largest capacity. Synchronises the context's stream. Errors: TTCF_EINVAL (no stored
- * states, bad arguments, no shape fits), TTCF_EDEVICE (probe daughters unhealthy other than
- * by list overflow, or a HIP error). */
+ * are four daughters per compute unit, so that throughput is measured), over a short untimed
+ * warm-up and probe_steps timed steps (they should span several list rebuilds, e.g. the
+ * daughter length, or the pick favours short lists), for each candidate shape: the cell form
+ * at 256, 512 and 1024 threads, and (FP32 forces) the neighbour-list form at those sizes and
+ * at the skins that fill list cells one coarser, equal to and one finer than the automatic
+ * grid, its list capacity raised while the probe overflows. Probe daughters are discarded
+ * (never accumulated) and live daughters are not advanced. The fastest shape (list capacity
+ * plus a margin of 4 where it fits) is stored in the context's cache under (device
+ * architecture, N, round(1000 N/V), round(10000 r_cut), precision), replacing an older entry,
+ * and written to *out (may be NULL). While no explicit shape is set (ttcf_set_step_shape(ctx,
+ * 0, 0, 0, 0), the default), ttcf_step uses the cached shape of each daughter's system, the
+ * list grid of its skin and, per launch, the workgroup size of the largest system. Synchronises
+ * the context's stream. Errors: TTCF_EINVAL (no stored states, bad arguments, no shape fits),
+ * TTCF_EDEVICE (probe daughters unhealthy other than by list overflow, or a HIP error). */
 typedef struct ttcf_shape {
     int32_t variant;       /* 1 cell form, 2 neighbour-list form                              */
     int32_t threads;       /* workgroup size                                                  */

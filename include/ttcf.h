@@ -203,7 +203,9 @@ int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, 
  * r_cut + skin rebuilt when needed (FP32 forces only); threads: workgroup size (0: the
  * system's block_threads, else the library's choice: 512 for the list form up to 2048 atoms);
  * skin <= 0 selects the automatic skin (the list-cell grid of a 0.25 sigma skin, with the skin
- * widened to fill those cells); kmax <= 0 selects 24 neighbours per atom. Affects the
+ * widened to fill those cells); kmax <= 0 selects 24 neighbours per atom, at most 32 (the
+ * force loop visits the entries within r_cut + 0.1 sigma, kept as a 32-bit mask per atom and
+ * refreshed from the lists under the same displacement bound as the lists). Affects the
  * following ttcf_step calls; results do not depend on the skin (lists are sorted, and pairs
  * beyond r_cut contribute nothing). */
 int32_t ttcf_set_step_shape(ttcf_ctx* ctx, int32_t variant, int32_t threads, double skin,

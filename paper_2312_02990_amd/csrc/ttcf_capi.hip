@@ -271,6 +271,8 @@ bool set_list_grid(SysDev* d, double skin) {
         d->l_inv_w[a] = (double)d->lc[a] / d->box[a];
     }
     d->rl2_f = (float)(reach * reach);
+    d->skin_in = std::min(skin, kInnerSkin);
+    d->ri2_f = (float)((d->rc + d->skin_in) * (d->rc + d->skin_in));
     return d->lc[0] >= 4 && d->lc[1] >= 3 && d->lc[2] >= 3 && d->lc[0] <= kMaxCells1D &&
            d->lc[1] <= kMaxCells1D && d->lc[2] <= kMaxCells1D;
 }
@@ -834,7 +836,8 @@ StepShape resolve_shape(const ttcf_ctx* c, const SysDev& d, int precision, const
 // the neighbour-list form (FP32 forces, not forced to cells, and its lists fit in LDS).
 int32_t apply_shape(ttcf_ctx* c, const StepShape& e, int precision, DaughterDesc* d, bool* nl) {
     d->kmax = e.kmax;
-    *nl = precision == TTCF_PREC_FP32_FORCES && e.variant != 1 && set_list_grid(&d->sys, e.skin) &&
+    *nl = precision == TTCF_PREC_FP32_FORCES && e.variant != 1 && e.kmax <= kNlMaxKmax &&
+          set_list_grid(&d->sys, e.skin) &&
           lds_bytes_nl(d->sys.n, d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2], e.kmax) <= c->max_lds;
     if (e.variant == 2 && !*nl)
         return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
@@ -962,8 +965,8 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
 int32_t ttcf_set_step_shape(ttcf_ctx* c, int32_t variant, int32_t threads, double skin,
                             int32_t kmax) {
     if (!c || variant < 0 || variant > 2 || threads < 0 || threads > kMaxThreads ||
-        (threads > 0 && threads % 64 != 0) || kmax > 255)
-        return TTCF_EINVAL;
+        (threads > 0 && threads % 64 != 0) || kmax > kNlMaxKmax)
+        return fail(c, TTCF_EINVAL, "bad step shape (kmax is at most 32)");
     c->shape.variant = variant;
     c->shape.threads = threads;
     c->shape.skin = skin > 0.0 ? skin : 0.0;
@@ -1011,7 +1014,7 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
             const double reach = d.rc + skin;
             const double mean = 4.18879020478639 * reach * reach * reach * rho;
             int k0 = std::max(12, ((int)std::ceil(1.6 * mean) + 3) / 4 * 4);
-            cand.push_back(StepShape{2, t, std::min(k0, 255), skin});
+            if (k0 <= kNlMaxKmax) cand.push_back(StepShape{2, t, k0, skin});
         }
     int32_t rc = sync_descs(c);
     if (rc != TTCF_OK) return rc;
@@ -1078,8 +1081,8 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
             if (health & ~kHealthListOverflow)
                 return fail(c, TTCF_EDEVICE, "probe daughters failed the health check");
             if (health & kHealthListOverflow) {
-                if (sh.kmax >= 255) break;
-                sh.kmax = std::min(255, sh.kmax + 8);
+                if (sh.kmax >= kNlMaxKmax) break;
+                sh.kmax = std::min(kNlMaxKmax, sh.kmax + 8);
                 continue;
             }
             ++timed;
@@ -1097,7 +1100,7 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
         SysDev probe = d;
         set_list_grid(&probe, best_shape.skin);
         const int lcn = probe.lc[0] * probe.lc[1] * probe.lc[2];
-        const int k = std::min(255, best_shape.kmax + 4);
+        const int k = std::min(kNlMaxKmax, best_shape.kmax + 4);
         if (lds_bytes_nl(d.n, lcn, k) <= c->max_lds) best_shape.kmax = k;
     }
     TunedShape t;
@@ -1205,7 +1208,8 @@ int32_t ttcf_autotune_import(ttcf_ctx* c, const char* text) {
         t.ms_per_step = v[8];
         if (t.shape.variant < 1 || t.shape.variant > 2 || t.shape.threads % 64 != 0 ||
             t.shape.threads < 64 || t.shape.threads > kMaxThreads || t.shape.kmax < 0 ||
-            t.shape.kmax > 255 || !(t.shape.skin >= 0.0) || t.n < 2)
+            t.shape.kmax > (t.shape.variant == 2 ? kNlMaxKmax : 255) || !(t.shape.skin >= 0.0) ||
+            t.n < 2)
             return fail(c, TTCF_EINVAL, "autotune cache: shape out of range");
         got.push_back(t);
         p = e + 1;

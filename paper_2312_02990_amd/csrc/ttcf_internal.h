@@ -35,7 +35,17 @@ struct SysDev {
     float fix_unit[3];     // L_a / 2^32
     float rc2_f;           // cutoff^2 and list radius^2 in FP32
     float rl2_f;
+    // inner radius rc + skin_in (skin_in <= skin): the list entries within it are the ones
+    // the force loop visits; their set is refreshed from the lists when atoms may have
+    // crossed skin_in since the last refresh
+    double skin_in;
+    float ri2_f;
 };
+
+// Largest list capacity of the neighbour-list form (the inner set is a 32-bit mask).
+constexpr int kNlMaxKmax = 32;
+// Inner skin of the force loop (sigma).
+constexpr double kInnerSkin = 0.1;
 
 // One daughter trajectory. Owned by the host runtime; the kernel updates k, done, health.
 struct DaughterDesc {

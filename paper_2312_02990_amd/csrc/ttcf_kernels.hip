@@ -1216,7 +1216,7 @@ struct NlLds {
     int32_t* rowinfo;  // [3 rows][2]: first column offset mod nx, column count
     double* red;       // block-reduction scratch
     int32_t* scan;     // [kMaxWaves]
-    float* wmax;       // [kMaxWaves] per-wave maximum path length
+    float* wmax;       // [2 kMaxWaves] per-wave maxima of the two path lengths
     int32_t* misc;     // [4]: [0] job, [1] list overflow
     SysDev* sys;
 };
@@ -1243,7 +1243,7 @@ __host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax) {
     p.rowinfo = take(4 * 8, 16);
     p.red = take(sizeof(double) * (kMaxWaves * kRedSlots + kRedSlots), 16);
     p.scan = take(4 * kMaxWaves, 16);
-    p.wmax = take(4 * kMaxWaves, 16);
+    p.wmax = take(8 * kMaxWaves, 16);
     p.misc = take(4 * 4, 16);
     p.sys = take(sizeof(SysDev), 16);
     p.total = align_up(off, 128);
@@ -1351,6 +1351,7 @@ __device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_
     }
     __syncthreads();
     const float rl2 = S.rl2_f;
+    const float ux = S.fix_unit[0], uy = S.fix_unit[1], uz = S.fix_unit[2];
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
         const int a = t + j * T;
@@ -1363,7 +1364,11 @@ __device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_
         // branch-free: every candidate is written, rejected ones into the sink row kmax
         const int sink = kmax * nmax + a;
         int slot = a;  // count * nmax + a while count < kmax
-        auto scan = [&](int lo, int hi) {
+        // rsh: the Lees-Edwards x shift of the row's y image (+offset for a row wrapped from
+        // the top, -offset from the bottom, 0 otherwise). A candidate within the list radius is
+        // nearer than half the box in y, so its minimum image is the row's image; for the others
+        // the test fails with either shift.
+        auto scan = [&](int lo, int hi, uint32_t rsh) {
 #pragma unroll 1
             for (int tt = lo; tt < hi; tt += 4) {
                 int jn[4];
@@ -1379,8 +1384,9 @@ __device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_
                 for (int u = 0; u < 4; ++u) q[u] = L.posq[jn[u]];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    float ddx, ddy, ddz;
-                    fix_sep(qx[j], qy[j], qz[j], q[u], dxq, S, ddx, ddy, ddz);
+                    const float ddx = (float)(int32_t)(qx[j] - q[u].x - rsh) * ux;
+                    const float ddy = (float)(int32_t)(qy[j] - q[u].y) * uy;
+                    const float ddz = (float)(int32_t)(qz[j] - q[u].z) * uz;
                     const bool hit = (jn[u] != a) & (ddx * ddx + ddy * ddy + ddz * ddz < rl2);
                     const bool room = hit & (count < kmax);
                     L.nbr[room ? slot : sink] = (uint16_t)jn[u];
@@ -1407,8 +1413,9 @@ __device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_
             if (x0 >= nc0) x0 -= nc0;
             const int base = nc0 * (yy + nc1 * zz);
             const int xe = x0 + nq;
-            scan(L.start[base + x0], L.start[base + (xe < nc0 ? xe : nc0)]);
-            if (xe > nc0) scan(L.start[base], L.start[base + xe - nc0]);
+            const uint32_t rsh = row == 2 ? dxq : (row == 0 ? 0u - dxq : 0u);
+            scan(L.start[base + x0], L.start[base + (xe < nc0 ? xe : nc0)], rsh);
+            if (xe > nc0) scan(L.start[base], L.start[base + xe - nc0], rsh);
         }
         if (count > kmax) {
             L.misc[1] = 1;
@@ -1431,13 +1438,39 @@ __device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_
 }
 
 // Forces on the owned atoms from their lists; returns this thread's share of W_xy.
+// Marks, for every owned atom, the list entries within the inner radius (bit k: entry k);
+// entries beyond it cannot reach r_c before the next refresh.
+template <int APT>
+__device__ __forceinline__ void nl_inner(const SysDev& S, uint32_t dxq, const uint32_t (&qx)[APT],
+                                         const uint32_t (&qy)[APT], const uint32_t (&qz)[APT],
+                                         const NlLds& L, int nmax, uint32_t (&imask)[APT]) {
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    const float ri2 = S.ri2_f;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        uint32_t m = 0u;
+        if (a < n) {
+            const int c = L.ncnt[a];
+            for (int k = 0; k < c; ++k) {
+                const uint4 q = L.posq[L.nbr[k * nmax + a]];
+                float dx, dy, dz;
+                fix_sep(qx[j], qy[j], qz[j], q, dxq, S, dx, dy, dz);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                m |= (r2 < ri2 ? 1u : 0u) << k;
+            }
+        }
+        imask[j] = m;
+    }
+}
+
 template <int APT>
 __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
                                             const uint32_t (&qx)[APT], const uint32_t (&qy)[APT],
-                                            const uint32_t (&qz)[APT], float (&fx)[APT],
-                                            float (&fy)[APT], float (&fz)[APT], const NlLds& L,
-                                            int nmax) {
-    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+                                            const uint32_t (&qz)[APT], const uint32_t (&imask)[APT],
+                                            float (&fx)[APT], float (&fy)[APT], float (&fz)[APT],
+                                            const NlLds& L, int nmax) {
+    const int T = blockDim.x, t = threadIdx.x;
     const float rc2 = S.rc2_f;
     const float ca = (float)S.c_attr;
     double wacc = 0.0;
@@ -1445,9 +1478,13 @@ __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
     for (int j = 0; j < APT; ++j) {
         const int a = t + j * T;
         float gx = 0.f, gy = 0.f, gz = 0.f, w = 0.f;
-        if (a < n) {
-            const int c = L.ncnt[a];
-            for (int k = 0; k < c; ++k) {
+        {
+            // the inner entries in list order (ascending ids): a fixed summation order, and
+            // every skipped entry lies beyond r_c, where a pair adds an exact zero
+            uint32_t mk = imask[j];
+            while (mk != 0u) {
+                const int k = __builtin_ctz(mk);
+                mk &= mk - 1u;
                 const uint4 q = L.posq[L.nbr[k * nmax + a]];
                 float dx, dy, dz;
                 fix_sep(qx[j], qy[j], qz[j], q, dxq, S, dx, dy, dz);
@@ -1473,13 +1510,13 @@ __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
 // Publish the fixed-point positions of the owned atoms and the wave maxima of the path
 // lengths; after the barrier every thread reads the workgroup maximum.
 template <int APT>
-__device__ __forceinline__ float nl_publish(const SysDev& S, const double (&x)[APT],
-                                            const double (&y)[APT], const double (&z)[APT],
-                                            uint32_t (&qx)[APT], uint32_t (&qy)[APT],
-                                            uint32_t (&qz)[APT], const float (&path)[APT],
-                                            const NlLds& L) {
+__device__ __forceinline__ float2 nl_publish(const SysDev& S, const double (&x)[APT],
+                                             const double (&y)[APT], const double (&z)[APT],
+                                             uint32_t (&qx)[APT], uint32_t (&qy)[APT],
+                                             uint32_t (&qz)[APT], const float (&path)[APT],
+                                             const float (&path_in)[APT], const NlLds& L) {
     const int T = blockDim.x, t = threadIdx.x, n = S.n;
-    float pm = 0.f;
+    float pm = 0.f, pi = 0.f;
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
         const int a = t + j * T;
@@ -1489,14 +1526,24 @@ __device__ __forceinline__ float nl_publish(const SysDev& S, const double (&x)[A
         if (a < n) {
             L.posq[a] = make_uint4(qx[j], qy[j], qz[j], 0u);
             pm = fmaxf(pm, path[j]);
+            pi = fmaxf(pi, path_in[j]);
         }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) pm = fmaxf(pm, __shfl_xor(pm, o, 64));
-    if ((t & 63) == 0) L.wmax[t >> 6] = pm;
+    for (int o = 32; o > 0; o >>= 1) {
+        pm = fmaxf(pm, __shfl_xor(pm, o, 64));
+        pi = fmaxf(pi, __shfl_xor(pi, o, 64));
+    }
+    if ((t & 63) == 0) {
+        L.wmax[2 * (t >> 6)] = pm;
+        L.wmax[2 * (t >> 6) + 1] = pi;
+    }
     __syncthreads();
-    float m = 0.f;
-    for (int w = 0; w < (T >> 6); ++w) m = fmaxf(m, L.wmax[w]);
+    float2 m = make_float2(0.f, 0.f);
+    for (int w = 0; w < (T >> 6); ++w) {
+        m.x = fmaxf(m.x, L.wmax[2 * w]);
+        m.y = fmaxf(m.y, L.wmax[2 * w + 1]);
+    }
     return m;
 }
 
@@ -1522,7 +1569,8 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT];
     float fx[APT], fy[APT], fz[APT];  // FP32 pair forces; every use below promotes them to FP64
     uint32_t qx[APT], qy[APT], qz[APT];
-    float path[APT];
+    float path[APT], path_in[APT];  // path lengths since the last rebuild / inner refresh
+    uint32_t imask[APT];
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
         const int a = t + j * T;
@@ -1534,13 +1582,15 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
         py[j] = v ? st[4 * n + a] : 0.0;
         pz[j] = v ? st[5 * n + a] : 0.0;
         path[j] = 0.f;
+        path_in[j] = 0.f;
     }
     double dxle = le_offset(S, gd, k);
     uint32_t dxq = fix32(dxle, S.fix_scale[0]);
-    nl_publish<APT>(S, x, y, z, qx, qy, qz, path, L);
+    nl_publish<APT>(S, x, y, z, qx, qy, qz, path, path_in, L);
     nl_rebuild<APT>(S, dxle, dxq, x, y, z, qx, qy, qz, L, kmax, nmax);
     if (L.misc[1] != 0) health |= kHealthListOverflow;
-    double wpart = nl_forces<APT>(S, dxq, qx, qy, qz, fx, fy, fz, L, nmax);
+    nl_inner<APT>(S, dxq, qx, qy, qz, L, nmax, imask);
+    double wpart = nl_forces<APT>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax);
 
     double m0[7] = {0, 0, 0, 0, 0, 0, wpart};
 #pragma unroll
@@ -1563,8 +1613,9 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     const double h = S.dt, tau = 0.5 * S.dt, tg = tau * gd;
     const float reach = (float)S.rc;
     const float skin = (float)S.skin;
+    const float skin_in = (float)S.skin_in;
     const float agd = (float)fabs(gd);
-    int since = 0;
+    int since = 0, since_in = 0;
 
     for (int step = 0; step < todo; ++step) {
         // ---- first half: S(tau) then K(tau)
@@ -1590,16 +1641,21 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 #pragma unroll
         for (int j = 0; j < APT; ++j) {
             const double vx = px[j] + tg * py[j];
-            path[j] += (float)(h * sqrt(vx * vx + py[j] * py[j] + pz[j] * pz[j]));
+            const float dl = (float)h * sqrtf((float)(vx * vx + py[j] * py[j] + pz[j] * pz[j]));
+            path[j] += dl;
+            path_in[j] += dl;
             x[j] += h * px[j] + h * gd * (y[j] + tau * py[j]);
             y[j] += h * py[j];
             z[j] += h * pz[j];
             wrap_le(S, dxle, x[j], y[j], z[j]);
         }
-        const float dmax = nl_publish<APT>(S, x, y, z, qx, qy, qz, path, L);
+        const float2 dm = nl_publish<APT>(S, x, y, z, qx, qy, qz, path, path_in, L);
         ++since;
-        const float tsince = (float)(since * h);
-        if (2.f * dmax + agd * tsince * (reach + 2.f * dmax) >= skin) {
+        ++since_in;
+        const float tsince = (float)(since * h), tin = (float)(since_in * h);
+        // the same displacement bound guards the lists (skin) and the inner set (skin_in)
+        const bool rebuild = 2.f * dm.x + agd * tsince * (reach + 2.f * dm.x) >= skin;
+        if (rebuild) {
             nl_rebuild<APT>(S, dxle, dxq, x, y, z, qx, qy, qz, L, kmax, nmax);
             if (L.misc[1] != 0) {
                 health |= kHealthListOverflow;
@@ -1609,7 +1665,13 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             for (int j = 0; j < APT; ++j) path[j] = 0.f;
             since = 0;
         }
-        wpart = nl_forces<APT>(S, dxq, qx, qy, qz, fx, fy, fz, L, nmax);
+        if (rebuild || 2.f * dm.y + agd * tin * (reach + 2.f * dm.y) >= skin_in) {
+            nl_inner<APT>(S, dxq, qx, qy, qz, L, nmax, imask);
+#pragma unroll
+            for (int j = 0; j < APT; ++j) path_in[j] = 0.f;
+            since_in = 0;
+        }
+        wpart = nl_forces<APT>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax);
         // ---- moments of (p'', F): pp, pxpy, pypy, fp, fxpy, fypx, fxfy, fypy, fyfy, ff, W, pos
         double m[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, wpart, 0};
 #pragma unroll

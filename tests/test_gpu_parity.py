@@ -246,7 +246,7 @@ def test_neighbour_lists_are_skin_invariant(T, orc, cfg1):
     s, box, sr, sp = cfg1
     nst = 200
     out = []
-    for skin, kmax in ((0.15, 20), (0.25, 24), (0.4, 40)):
+    for skin, kmax in ((0.15, 20), (0.25, 24), (0.4, 32)):
         say(f"skin {skin}")
         with T.Context() as ctx:
             mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)

@@ -8,7 +8,8 @@
 
 namespace ttcf {
 
-constexpr int kChThreads = 512;  // loops over atoms; 512 leaves 256 VGPRs per lane
+constexpr int kChThreads = 512;  // loops over atoms
+constexpr int kChWavesPerSimd = 4;  // register budget of the step kernel: 128 VGPRs per lane
 constexpr int kChMaxWaves = kChThreads / 64;
 constexpr int kChRed = 4;          // doubles per block reduction
 constexpr int kChMaxBins = 256;

@@ -170,7 +170,9 @@ int32_t launch(ttcf_channel_ctx* c, ChannelDesc* d_descs, int32_t n_jobs, int32_
                bool timed) {
     const size_t lds = channel_lds_bytes(c->dev.n, c->dev.lc[0] * c->dev.lc[1] * c->dev.lc[2]);
     if (lds > c->max_lds) return cfail(c, TTCF_EINVAL, "system exceeds the LDS of one workgroup");
-    const int per_cu = std::max(1, std::min<int>((int)(c->max_lds / lds), 2048 / kChThreads));
+    // resident workgroups per CU: the LDS and the register budget (4 SIMDs per CU)
+    const int per_cu = std::max(
+        1, std::min<int>((int)(c->max_lds / lds), 4 * kChWavesPerSimd / (kChThreads / 64)));
     const int grid = std::max(1, std::min(n_jobs, per_cu * c->num_cu));
     int32_t rc = ensure_scratch(c, grid);
     if (rc != TTCF_OK) return rc;

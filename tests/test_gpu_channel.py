@@ -139,3 +139,18 @@ def test_channel_response_matches_oracle(CHO, daughters):
         assert np.abs(dm - rd).max() <= 1e-3 * dscale
         assert np.all(np.abs(tm - rt) <= 2.0 * np.hypot(tse, rse) + 1e-3 * gscale)
         np.testing.assert_allclose(tse, rse, rtol=1e-2, atol=1e-3 * gscale)
+
+
+def test_channel_daughters_are_deterministic(T, states):
+    """Lists are built from cells whose atoms are kept in id order, so the same call sequence
+    gives the same series bit for bit."""
+    c, q, rl, sr, sp, sz = states
+    g = GEOM
+    out = []
+    for _ in range(2):
+        with T.ChannelContext(T.make_channel(g), sr[0], sp[0], rl.reshape(3, -1)) as ctx:
+            ctx.import_states(sr, sp, sz)
+            first = ctx.spawn(4, 0.5, 40)
+            ctx.step(40)
+            out.append(ctx.export_series(first, 16, 41)[0])
+    assert np.array_equal(out[0], out[1])

@@ -174,21 +174,54 @@ __device__ inline Lds<Real> carve(char* base, int nmax, int cmax) {
 // block-level collectives
 // ---------------------------------------------------------------------------------------
 
-// Sum K doubles over the workgroup; every thread receives the totals. Fixed order:
-// butterfly inside each wave, then wave 0..W-1 in sequence.
+// One 32-bit DPP move (lanes without a source keep `old`).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp32(uint32_t old, uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = dpp32<CTRL, ROWS>(0u, (uint32_t)u);
+    const uint32_t hi = dpp32<CTRL, ROWS>(0u, (uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Inclusive sum over the wave with row shifts (1, 2, 4, 8 inside rows of 16) and row
+// broadcasts (15, 31): lane 63 ends with the wave total. VALU data-parallel moves, no LDS.
+__device__ __forceinline__ double wave_total_dpp(double x) {
+    x += dpp_f64<0x111, 0xf>(x);  // row_shr:1
+    x += dpp_f64<0x112, 0xf>(x);  // row_shr:2
+    x += dpp_f64<0x114, 0xf>(x);  // row_shr:4
+    x += dpp_f64<0x118, 0xf>(x);  // row_shr:8
+    x += dpp_f64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_f64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+// The same for the maximum of non-negative floats (0 is the identity).
+__device__ __forceinline__ float wave_max_dpp(float x) {
+    auto step = [](float a, uint32_t b) { return fmaxf(a, __builtin_bit_cast(float, b)); };
+    x = step(x, dpp32<0x111, 0xf>(0u, __builtin_bit_cast(uint32_t, x)));
+    x = step(x, dpp32<0x112, 0xf>(0u, __builtin_bit_cast(uint32_t, x)));
+    x = step(x, dpp32<0x114, 0xf>(0u, __builtin_bit_cast(uint32_t, x)));
+    x = step(x, dpp32<0x118, 0xf>(0u, __builtin_bit_cast(uint32_t, x)));
+    x = step(x, dpp32<0x142, 0xa>(0u, __builtin_bit_cast(uint32_t, x)));
+    x = step(x, dpp32<0x143, 0xc>(0u, __builtin_bit_cast(uint32_t, x)));
+    return x;
+}
+
+// Sum K doubles over the workgroup; every thread receives the totals. Fixed order: a scan
+// inside each wave (its total in lane 63), then wave 0..W-1 in sequence.
 template <int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int nw = blockDim.x >> 6;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        double x = v[k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        v[k] = x;
-    }
-    if (lane == 0) {
+    for (int k = 0; k < K; ++k) v[k] = wave_total_dpp(v[k]);
+    if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
     }
@@ -1529,12 +1562,9 @@ __device__ __forceinline__ float2 nl_publish(const SysDev& S, const double (&x)[
             pi = fmaxf(pi, path_in[j]);
         }
     }
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        pm = fmaxf(pm, __shfl_xor(pm, o, 64));
-        pi = fmaxf(pi, __shfl_xor(pi, o, 64));
-    }
-    if ((t & 63) == 0) {
+    pm = wave_max_dpp(pm);
+    pi = wave_max_dpp(pi);
+    if ((t & 63) == 63) {
         L.wmax[2 * (t >> 6)] = pm;
         L.wmax[2 * (t >> 6) + 1] = pi;
     }

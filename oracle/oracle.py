@@ -88,8 +88,16 @@ def _load():
                                           D, C.c_int64, C.c_int32, C.c_int64, D, D]
         lib.orc_run_daughters.argtypes = [B, C.c_double, D, D, C.c_int32, I, I, D, C.c_int64,
                                           C.c_int32, D, D, D]
+        lib.orc_nh_sllod_run.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, D, D, D, L, C.c_int64, D, D, D, D]
+        lib.orc_mother_sample_zeta.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double,
+                                               D, D, D, C.c_int64, C.c_int32, C.c_int64, D, D, D]
+        lib.orc_run_daughters_nh.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double, D,
+                                             D, D, C.c_int32, I, I, D, C.c_int64, C.c_int32, D, D,
+                                             D]
         for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
-                   "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters"):
+                   "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
+                   "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh"):
             getattr(lib, fn).restype = C.c_int32
         _lib = lib
     return _lib
@@ -206,19 +214,66 @@ def nh_run(box: Box, state: NHState, nsteps: int, temperature: float, dt: float,
 
 
 def mother_sample(box: Box, state: NHState, n_equil: int, n_states: int, steps_between: int,
-                  temperature: float, dt: float, q: float, nf: float):
+                  temperature: float, dt: float, q: float, nf: float, with_zeta: bool = False):
     """Alg. LAMMPS SCRIPT, mother side: equilibrate n_equil steps, then n_states times run
-    steps_between steps and save the state. Returns (states_r, states_p), (n_states, 3n)."""
+    steps_between steps and save the state. Returns (states_r, states_p), (n_states, 3n),
+    and with_zeta also the thermostat variable of every state."""
     sr = np.zeros((n_states, 3 * box.n))
     sp = np.zeros((n_states, 3 * box.n))
+    sz = np.zeros(n_states)
     z = np.array([state.zeta])
-    rc = _load().orc_mother_sample(C.byref(box), temperature, q, nf, dt, _dp(state.r),
-                                   _dp(state.p), _dp(z), int(n_equil), int(n_states),
-                                   int(steps_between), _dp(sr), _dp(sp))
+    rc = _load().orc_mother_sample_zeta(C.byref(box), temperature, q, nf, dt, _dp(state.r),
+                                        _dp(state.p), _dp(z), int(n_equil), int(n_states),
+                                        int(steps_between), _dp(sr), _dp(sp), _dp(sz))
     if rc != 0:
         raise RuntimeError(f"orc_mother_sample failed: {rc}")
     state.zeta = float(z[0])
-    return sr, sp
+    return (sr, sp, sz) if with_zeta else (sr, sp)
+
+
+def nh_sllod_run(box: Box, r, p, zeta: float, gamma_dot: float, dt: float, temperature: float,
+                 q: float, nf: float, nsteps: int, kstep: int = 0):
+    """Advance one Nose-Hoover SLLOD trajectory (Eq. system1 as printed) in place.
+    Returns (vpxy, ke, pe, zeta series, k_final, zeta_final), series of length nsteps+1."""
+    assert r.dtype == np.float64 and p.dtype == np.float64 and r.flags.c_contiguous
+    outs = [np.zeros(nsteps + 1) for _ in range(4)]
+    k = np.array([kstep], dtype=np.int64)
+    z = np.array([float(zeta)])
+    rc = _load().orc_nh_sllod_run(C.byref(box), float(gamma_dot), float(dt), float(temperature),
+                                  float(q), float(nf), _dp(r), _dp(p), _dp(z),
+                                  k.ctypes.data_as(C.POINTER(C.c_int64)), int(nsteps),
+                                  *[_dp(o) for o in outs])
+    if rc != 0:
+        raise RuntimeError(f"orc_nh_sllod_run failed: {rc}")
+    return outs[0], outs[1], outs[2], outs[3], int(k[0]), float(z[0])
+
+
+def run_daughters_nh(box: Box, states_r, states_p, states_zeta, state_of, map_of, gamma_of,
+                     dt: float, temperature: float, q: float, nf: float, nsteps: int,
+                     nthreads: int = 0, final_state: bool = False):
+    """Nose-Hoover daughters (orc_run_daughters_nh): as run_daughters, each start state with
+    its thermostat variable, reversed by the time-reversing mappings."""
+    states_r = _f64(states_r)
+    states_p = _f64(states_p)
+    states_zeta = _f64(states_zeta)
+    state_of = np.ascontiguousarray(state_of, np.int32)
+    map_of = np.ascontiguousarray(map_of, np.int32)
+    gamma_of = _f64(gamma_of)
+    nd = len(state_of)
+    out = np.zeros((nd, nsteps + 1))
+    ro = np.zeros((nd, 3 * box.n)) if final_state else None
+    po = np.zeros((nd, 3 * box.n)) if final_state else None
+    if nthreads <= 0:
+        nthreads = os.cpu_count() or 1
+    used = _load().orc_run_daughters_nh(C.byref(box), float(dt), float(temperature), float(q),
+                                        float(nf), _dp(states_r), _dp(states_p), _dp(states_zeta),
+                                        nd, _ip(state_of), _ip(map_of), _dp(gamma_of), int(nsteps),
+                                        int(nthreads), _dp(out), _dp(ro), _dp(po))
+    if used < 0:
+        raise RuntimeError(f"orc_run_daughters_nh failed: {used}")
+    if final_state:
+        return out, ro, po, used
+    return out, used
 
 
 def sllod_run(box: Box, r, p, gamma_dot: float, dt: float, nsteps: int, gik: bool = True,

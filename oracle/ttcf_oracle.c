@@ -473,6 +473,14 @@ int32_t orc_mother_sample(const orc_box* b, double temperature, double q, double
                           double* r, double* p, double* zeta, int64_t n_equil,
                           int32_t n_states, int64_t steps_between, double* states_r,
                           double* states_p) {
+    return orc_mother_sample_zeta(b, temperature, q, nf, dt, r, p, zeta, n_equil, n_states,
+                                  steps_between, states_r, states_p, 0);
+}
+
+int32_t orc_mother_sample_zeta(const orc_box* b, double temperature, double q, double nf,
+                               double dt, double* r, double* p, double* zeta, int64_t n_equil,
+                               int32_t n_states, int64_t steps_between, double* states_r,
+                               double* states_p, double* states_zeta) {
     const size_t sz = 3 * (size_t)b->n;
     int32_t rc = orc_nh_run(b, temperature, q, nf, dt, r, p, zeta, n_equil, 0, 0, 0);
     if (rc) return rc;
@@ -481,6 +489,7 @@ int32_t orc_mother_sample(const orc_box* b, double temperature, double q, double
         if (rc) return rc;
         memcpy(states_r + (size_t)s * sz, r, sizeof(double) * sz);
         memcpy(states_p + (size_t)s * sz, p, sizeof(double) * sz);
+        if (states_zeta) states_zeta[s] = *zeta;
     }
     return 0;
 }
@@ -609,6 +618,73 @@ int32_t orc_sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik
     return 0;
 }
 
+/* One step of Eq. (system1) with its Nose-Hoover multiplier alpha = zeta. Each part is
+ * integrated exactly:
+ *   Z: d zeta/dt = (sum p^2 - nf T)/Q with p fixed;
+ *   T: dp/dt = -zeta p with zeta fixed, p *= exp(-zeta tau);
+ *   S: dpx/dt = -gamma_dot py (py fixed);
+ *   K: dp/dt = F (F fixed);
+ *   D: the streaming of orc_sllod_run.
+ * T and S commute (T scales every component). The sequence
+ * Z T S K D K S T Z over half steps is symmetric, so the step is second order and time
+ * reversible under (p, zeta, gamma_dot) -> (-p, -zeta, -gamma_dot). */
+int32_t orc_nh_sllod_run(const orc_box* b, double gamma_dot, double dt, double temperature,
+                         double q, double nf, double* r, double* p, double* zeta,
+                         int64_t* kstep, int64_t nsteps, double* vpxy_out, double* ke_out,
+                         double* pe_out, double* zeta_out) {
+    const int32_t n = b->n;
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!f) return -2;
+    double* x = r;
+    double* y = r + n;
+    double* z = r + 2 * n;
+    double* px = p;
+    double* py = p + n;
+    double* pz = p + 2 * n;
+    double out[3];
+    int64_t k = *kstep;
+    double dxle = le_offset(b, gamma_dot, dt, k);
+    if (orc_forces(b, dxle, r, f, out) != 0) {
+        free(f);
+        return -1;
+    }
+    const double h = dt, tau = 0.5 * dt;
+    double zt = *zeta;
+    if (vpxy_out) vpxy_out[0] = sum_pxpy(n, p) + out[1];
+    if (ke_out) ke_out[0] = kinetic(n, p);
+    if (pe_out) pe_out[0] = out[0];
+    if (zeta_out) zeta_out[0] = zt;
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
+        double sc = exp(-zt * tau);
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] *= sc;
+        for (int32_t i = 0; i < n; ++i) px[i] -= tau * gamma_dot * py[i];
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] += tau * f[c];
+        for (int32_t i = 0; i < n; ++i) {
+            x[i] += h * px[i] + h * gamma_dot * (y[i] + tau * py[i]);
+            y[i] += h * py[i];
+            z[i] += h * pz[i];
+        }
+        k += 1;
+        dxle = le_offset(b, gamma_dot, dt, k);
+        wrap_le(b, dxle, r);
+        orc_forces(b, dxle, r, f, out);
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] += tau * f[c];
+        for (int32_t i = 0; i < n; ++i) px[i] -= tau * gamma_dot * py[i];
+        sc = exp(-zt * tau);
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] *= sc;
+        zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
+        if (vpxy_out) vpxy_out[s] = sum_pxpy(n, p) + out[1];
+        if (ke_out) ke_out[s] = kinetic(n, p);
+        if (pe_out) pe_out[s] = out[0];
+        if (zeta_out) zeta_out[s] = zt;
+    }
+    *zeta = zt;
+    *kstep = k;
+    free(f);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* batch of daughters on a thread pool (one daughter per thread at a time)               */
 /* ------------------------------------------------------------------------------------ */
@@ -624,6 +700,9 @@ typedef struct {
     double *vpxy_out, *r_out, *p_out;
     int32_t tid, nthreads;
     int32_t status;
+    /* Nose-Hoover daughters when states_zeta is not NULL */
+    const double* states_zeta;
+    double temperature, q, nf;
 } batch_job;
 
 static void* batch_worker(void* arg) {
@@ -637,8 +716,17 @@ static void* batch_worker(void* arg) {
         orc_map(jb->b, jb->map_of[d], jb->states_r + (size_t)s * sz, jb->states_p + (size_t)s * sz,
                 r, p);
         int64_t k = 0;
-        int32_t rc = orc_sllod_run(jb->b, jb->gamma_of[d], jb->dt, 1, 0.0, r, p, &k, jb->nsteps,
-                                   jb->vpxy_out + (size_t)d * (size_t)(jb->nsteps + 1), 0, 0);
+        int32_t rc;
+        double* vp = jb->vpxy_out + (size_t)d * (size_t)(jb->nsteps + 1);
+        if (jb->states_zeta) {
+            /* the mappings that reverse the momenta (m = 1, 3) reverse the thermostat too */
+            double zt = (jb->map_of[d] & 1) ? -jb->states_zeta[s] : jb->states_zeta[s];
+            rc = orc_nh_sllod_run(jb->b, jb->gamma_of[d], jb->dt, jb->temperature, jb->q,
+                                  jb->nf, r, p, &zt, &k, jb->nsteps, vp, 0, 0, 0);
+        } else {
+            rc = orc_sllod_run(jb->b, jb->gamma_of[d], jb->dt, 1, 0.0, r, p, &k, jb->nsteps,
+                               vp, 0, 0);
+        }
         if (rc) jb->status = rc;
         if (jb->r_out) memcpy(jb->r_out + (size_t)d * sz, r, sizeof(double) * sz);
         if (jb->p_out) memcpy(jb->p_out + (size_t)d * sz, p, sizeof(double) * sz);
@@ -648,17 +736,44 @@ static void* batch_worker(void* arg) {
     return 0;
 }
 
+static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
+                         const double* states_p, const double* states_zeta, double temperature,
+                         double q, double nf, int32_t n_daughters, const int32_t* state_of,
+                         const int32_t* map_of, const double* gamma_of, int64_t nsteps,
+                         int32_t nthreads, double* vpxy_out, double* r_out, double* p_out);
+
 int32_t orc_run_daughters(const orc_box* b, double dt, const double* states_r,
                           const double* states_p, int32_t n_daughters, const int32_t* state_of,
                           const int32_t* map_of, const double* gamma_of, int64_t nsteps,
                           int32_t nthreads, double* vpxy_out, double* r_out, double* p_out) {
+    return run_batch(b, dt, states_r, states_p, 0, 0.0, 0.0, 0.0, n_daughters, state_of, map_of,
+                     gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out);
+}
+
+int32_t orc_run_daughters_nh(const orc_box* b, double dt, double temperature, double q,
+                             double nf, const double* states_r, const double* states_p,
+                             const double* states_zeta, int32_t n_daughters,
+                             const int32_t* state_of, const int32_t* map_of,
+                             const double* gamma_of, int64_t nsteps, int32_t nthreads,
+                             double* vpxy_out, double* r_out, double* p_out) {
+    if (!states_zeta) return -1;
+    return run_batch(b, dt, states_r, states_p, states_zeta, temperature, q, nf, n_daughters,
+                     state_of, map_of, gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out);
+}
+
+static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
+                         const double* states_p, const double* states_zeta, double temperature,
+                         double q, double nf, int32_t n_daughters, const int32_t* state_of,
+                         const int32_t* map_of, const double* gamma_of, int64_t nsteps,
+                         int32_t nthreads, double* vpxy_out, double* r_out, double* p_out) {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > n_daughters) nthreads = n_daughters > 0 ? n_daughters : 1;
     batch_job* jobs = (batch_job*)calloc((size_t)nthreads, sizeof(batch_job));
     pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
     for (int32_t t = 0; t < nthreads; ++t) {
         batch_job j = {b,      dt,     states_r, states_p, n_daughters, state_of, map_of,
-                       gamma_of, nsteps, vpxy_out, r_out,  p_out,       t,        nthreads, 0};
+                       gamma_of, nsteps, vpxy_out, r_out,  p_out,       t,        nthreads, 0,
+                       states_zeta, temperature, q, nf};
         jobs[t] = j;
         pthread_create(&th[t], 0, batch_worker, &jobs[t]);
     }

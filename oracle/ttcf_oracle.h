@@ -95,6 +95,34 @@ int32_t orc_mother_sample(const orc_box* b, double temperature, double q, double
                           int32_t n_states, int64_t steps_between, double* states_r,
                           double* states_p);
 
+/* SLLOD of Eq. (system1) as printed, with the Nose-Hoover multiplier: d zeta/dt =
+ * (sum p^2 - nf T)/q. Symmetric splitting, each part exact:
+ *   Z(h/2) T(h/2) S(h/2) K(h/2) D(h) [k += 1, LE offset, wrap, F = F(r)] K(h/2) S(h/2) T(h/2) Z(h/2)
+ * Z: zeta += (h/2)(sum p^2 - nf T)/q; T: p *= exp(-zeta h/2); S: px -= (h/2) gamma_dot py;
+ * K: p += (h/2) F; D: the streaming part of orc_sllod_run. Per-step outputs (k = 0..nsteps)
+ * may be NULL: vpxy_out, ke_out, pe_out, zeta_out. */
+int32_t orc_nh_sllod_run(const orc_box* b, double gamma_dot, double dt, double temperature,
+                         double q, double nf, double* r, double* p, double* zeta, int64_t* k,
+                         int64_t nsteps, double* vpxy_out, double* ke_out, double* pe_out,
+                         double* zeta_out);
+
+/* orc_mother_sample that also saves the thermostat variable of every state (states_zeta,
+ * n_states doubles). */
+int32_t orc_mother_sample_zeta(const orc_box* b, double temperature, double q, double nf,
+                               double dt, double* r, double* p, double* zeta, int64_t n_equil,
+                               int32_t n_states, int64_t steps_between, double* states_r,
+                               double* states_p, double* states_zeta);
+
+/* Batch of Nose-Hoover SLLOD daughters (orc_nh_sllod_run): as orc_run_daughters, each start
+ * state with its thermostat variable states_zeta[s], reversed by the mappings that reverse
+ * time (m = 1 and 3). */
+int32_t orc_run_daughters_nh(const orc_box* b, double dt, double temperature, double q,
+                             double nf, const double* states_r, const double* states_p,
+                             const double* states_zeta, int32_t n_daughters,
+                             const int32_t* state_of, const int32_t* map_of,
+                             const double* gamma_of, int64_t nsteps, int32_t nthreads,
+                             double* vpxy_out, double* r_out, double* p_out);
+
 /* Batch of independent GIK-SLLOD daughters on a pool of nthreads threads.
  * Daughter d starts from start state state_of[d] under mapping map_of[d] with shear rate
  * gamma_of[d] and runs nsteps steps; its series V*P_xy(t_k), k = 0..nsteps, goes to

@@ -73,7 +73,14 @@ typedef struct {
     double  nh_tau;        /* mother Nose-Hoover time constant: Q = (3N-3) T nh_tau^2           */
     int32_t precision;     /* TTCF_PREC_*                                                       */
     int32_t block_threads; /* threads per workgroup for this system (0: chosen by the library)  */
+    int32_t daughter_thermostat; /* TTCF_DAUGHTER_GIK or TTCF_DAUGHTER_NH                       */
 } ttcf_system;
+
+/* Thermostat of the daughters. GIK: the Gaussian isokinetic multiplier (kinetic energy held
+ * at its start value). NH: Eq. (system1) as printed, the Nose-Hoover variable of the mother
+ * (same Q = (3N-3) T nh_tau^2 and target (3N-3) T) carried from the start state and reversed
+ * by the mappings that reverse the momenta (1 and 3). */
+enum { TTCF_DAUGHTER_GIK = 0, TTCF_DAUGHTER_NH = 1 };
 
 /* Optional allocator (e.g. a framework's caching allocator). Process-wide; must be set
  * before the first context exists. NULL restores hipMalloc/hipFree. */
@@ -156,6 +163,13 @@ int32_t ttcf_import_states(ttcf_ctx* ctx, int32_t mother, int32_t n_states, cons
 /* Copy the mother's stored start states to host arrays of the same layout. */
 int32_t ttcf_export_states(ttcf_ctx* ctx, int32_t mother, int32_t n_states, double* r,
                            double* p);
+/* The thermostat variable of every stored start state (n_states doubles): sampling records
+ * the mother's (or its copy's) at each saved state, ttcf_import_states sets 0, and
+ * ttcf_import_states_zeta sets given values for the first n_states stored states. Nose-Hoover
+ * daughters start from it (TTCF_DAUGHTER_NH). */
+int32_t ttcf_import_states_zeta(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
+                                const double* zeta);
+int32_t ttcf_export_states_zeta(ttcf_ctx* ctx, int32_t mother, int32_t n_states, double* zeta);
 /* Beside Alg. LAMMPS SCRIPT's one serial mother: n_replicas copies of the mother's current state,
  * copy q with the momentum kick kicks[q*3n ..] added as given (may be NULL; kicks should sum to
  * zero per copy), run decorrelate_steps Nose-Hoover steps together (one launch), then save

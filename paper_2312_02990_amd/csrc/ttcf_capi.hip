@@ -80,6 +80,16 @@ struct Mother {
     int64_t series_cap = 0, series_count = 0;
 };
 
+// Stored start states: states_cap blocks of 6n doubles (r, p), then states_cap doubles with
+// the thermostat variable of each state.
+inline double* zetas_of(const Mother& m) {
+    return m.states ? m.states + 6 * (size_t)m.dev.n * (size_t)m.states_cap : nullptr;
+}
+
+inline size_t state_buffer_bytes(int n, int count) {
+    return sizeof(double) * (6 * (size_t)n + 1) * (size_t)count;
+}
+
 struct Batch {
     int32_t mother = -1;
     int32_t n_daughters = 0;
@@ -333,7 +343,7 @@ int32_t upload_mother_launches(ttcf_ctx* c, const MotherLaunch* ls, int32_t coun
 }
 
 int32_t run_mother(ttcf_ctx* c, Mother& m, double temperature, int64_t n_chunks,
-                   int64_t steps_per_chunk, double* snapshots) {
+                   int64_t steps_per_chunk, double* snapshots, double* snap_zeta = nullptr) {
     if (steps_per_chunk <= 0 && n_chunks <= 0) return TTCF_OK;
     MotherLaunch L{};
     L.sys = m.dev;
@@ -346,6 +356,7 @@ int32_t run_mother(ttcf_ctx* c, Mother& m, double temperature, int64_t n_chunks,
     L.n_chunks = n_chunks;
     L.steps_per_chunk = steps_per_chunk;
     L.snapshots = snapshots;
+    L.snap_zeta = snap_zeta;
     const int64_t total = (n_chunks > 0 ? n_chunks : 1) * steps_per_chunk;
     L.series = nullptr;
     if (m.series && m.series_count + total <= m.series_cap) {
@@ -512,6 +523,11 @@ int32_t ttcf_init_mother(ttcf_ctx** pctx, const ttcf_system* sys, const double* 
             return TTCF_ENOMEM;
         }
     }
+    if (sys->daughter_thermostat != TTCF_DAUGHTER_GIK && sys->daughter_thermostat != TTCF_DAUGHTER_NH) {
+        if (created) ttcf_destroy(c);
+        else c->err = "daughter_thermostat must be TTCF_DAUGHTER_GIK or TTCF_DAUGHTER_NH";
+        return TTCF_EINVAL;
+    }
     Mother m;
     m.sys = *sys;
     std::string why;
@@ -591,10 +607,11 @@ int32_t ttcf_import_states(ttcf_ctx* c, int32_t mother, int32_t n_states, const 
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     if (m.states_cap < n_states) {
         dev_free(m.states);
-        m.states = (double*)dev_alloc(sizeof(double) * 6 * n * n_states, c->stream);
+        m.states = (double*)dev_alloc(state_buffer_bytes((int)n, n_states), c->stream);
         if (!m.states) return fail(c, TTCF_ENOMEM, "state buffer allocation failed");
         m.states_cap = n_states;
     }
+    HIPCHECK(c, launch_fill_f64(zetas_of(m), 0.0, n_states, c->stream));
     for (int32_t s = 0; s < n_states; ++s) {
         HIPCHECK(c, hipMemcpyAsync(m.states + 6 * n * s, r + 3 * n * s, sizeof(double) * 3 * n,
                                    hipMemcpyHostToDevice, c->stream));
@@ -623,6 +640,29 @@ int32_t ttcf_export_states(ttcf_ctx* c, int32_t mother, int32_t n_states, double
     return TTCF_OK;
 }
 
+int32_t ttcf_import_states_zeta(ttcf_ctx* c, int32_t mother, int32_t n_states,
+                                const double* zeta) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || !zeta)
+        return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    if (n_states > m.n_states) return fail(c, TTCF_EINVAL, "fewer stored states than given");
+    HIPCHECK(c, hipMemcpyAsync(zetas_of(m), zeta, sizeof(double) * n_states,
+                               hipMemcpyHostToDevice, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
+int32_t ttcf_export_states_zeta(ttcf_ctx* c, int32_t mother, int32_t n_states, double* zeta) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || !zeta)
+        return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    if (n_states > m.n_states) return fail(c, TTCF_EINVAL, "fewer stored states than requested");
+    HIPCHECK(c, hipMemcpyAsync(zeta, zetas_of(m), sizeof(double) * n_states,
+                               hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
+}
+
 int32_t ttcf_export_mother(ttcf_ctx* c, int32_t mother, double* r, double* p, double* zeta,
                            int64_t* steps) {
     if (!c || mother < 0 || mother >= (int32_t)c->mothers.size()) return TTCF_EINVAL;
@@ -647,11 +687,12 @@ int32_t ttcf_sample_states(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_
     if (m.states_cap < n_states) {
         HIPCHECK(c, hipStreamSynchronize(c->stream));
         dev_free(m.states);
-        m.states = (double*)dev_alloc(sizeof(double) * 6 * n * n_states, c->stream);
+        m.states = (double*)dev_alloc(state_buffer_bytes((int)n, n_states), c->stream);
         if (!m.states) return fail(c, TTCF_ENOMEM, "state buffer allocation failed");
         m.states_cap = n_states;
     }
-    int32_t rc = run_mother(c, m, m.sys.temperature, n_states, steps_between, m.states);
+    int32_t rc = run_mother(c, m, m.sys.temperature, n_states, steps_between, m.states,
+                            zetas_of(m));
     if (rc != TTCF_OK) return rc;
     m.n_states = n_states;
     return TTCF_OK;
@@ -713,6 +754,16 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
         dev_free(b.scratch);
         return fail(c, TTCF_ENOMEM, "daughter allocation failed");
     }
+    // Nose-Hoover daughters start from their state's thermostat variable
+    const bool nh = m.sys.daughter_thermostat == TTCF_DAUGHTER_NH;
+    std::vector<double> hz;
+    if (nh) {
+        hz.resize(n_states);
+        HIPCHECK(c, hipMemcpyAsync(hz.data(), zetas_of(m), sizeof(double) * n_states,
+                                   hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(c, hipStreamSynchronize(c->stream));
+    }
+    const double nf = 3.0 * (double)m.dev.n - 3.0;
     std::vector<char> host(scratch_bytes);
     double** dst = (double**)host.data();
     int32_t* state_of = (int32_t*)(host.data() + sizeof(double*) * nd);
@@ -739,6 +790,12 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
             ds.group = group;
             ds.map = maps[q];
             ds.block = m.threads;
+            if (nh) {
+                ds.thermo = 1;
+                ds.zeta = (maps[q] & 1) ? -hz[s] : hz[s];  // mappings 1 and 3 reverse time
+                ds.nh_q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
+                ds.nh_target = nf * m.sys.temperature;
+            }
             c->descs.push_back(ds);
             c->live.push_back(Live{c->next_id + d, bidx, d, group, s});
         }
@@ -1532,7 +1589,8 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     double** dst = (double**)g->get(sizeof(double*) * nd);
     const int32_t n_copies = std::max(1, gd->n_replicas);
     MotherLaunch* d_ml = (MotherLaunch*)g->get(sizeof(MotherLaunch) * n_copies);
-    if (!states || !dstates || !series || !descs || !templ || !ints || !dst || !d_ml)
+    double* szeta = (double*)g->get(sizeof(double) * n_states);  // thermostat of each state
+    if (!states || !dstates || !series || !descs || !templ || !ints || !dst || !d_ml || !szeta)
         return bail(TTCF_ENOMEM, "graph allocation failed");
     int32_t* order = ints;
     int32_t* state_of = order + nd;
@@ -1587,6 +1645,7 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
         ml[r].n_chunks = gd->states_per_replica;
         ml[r].steps_per_chunk = gd->steps_between;
         ml[r].snapshots = states + sz * (size_t)r * gd->states_per_replica;
+        ml[r].snap_zeta = szeta + (size_t)r * gd->states_per_replica;
     }
     g->mother_steps_per_replay = rep ? 0 : (int64_t)gd->states_per_replica * gd->steps_between;
 
@@ -1597,6 +1656,7 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     std::vector<double*> hdst(nd);
     std::vector<int32_t> hints(3 * (size_t)nd + n_states + 1);
     bool nl = false;
+    const bool nh = m.sys.daughter_thermostat == TTCF_DAUGHTER_NH;
     for (int32_t st = 0; st < n_states; ++st) {
         const int32_t group = c->next_group++;
         const double gdot = gd->gamma_dot[gd->n_gamma == 1 ? 0 : st];
@@ -1612,6 +1672,11 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
             ds.group = group;
             ds.map = maps[q];
             ds.block = m.threads;
+            if (nh) {  // zeta itself is written by a kernel at every replay
+                ds.thermo = 1;
+                ds.nh_q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
+                ds.nh_target = nf * m.sys.temperature;
+            }
             rc = apply_shape(c, shape, precision, &ds, &nl);
             if (rc != TTCF_OK) return bail(rc, c->err);
             hdst[d] = ds.state;
@@ -1704,6 +1769,8 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
         if (e1 == hipSuccess)
             e1 = launch_copy_words((const uint64_t*)templ, (uint64_t*)descs,
                                    (int64_t)(sizeof(DaughterDesc) / 8) * nd, g->cap);
+        if (e1 == hipSuccess && nh)
+            e1 = launch_desc_zeta(descs, szeta, state_of, map_of, nd, g->cap);
         if (e1 == hipSuccess) e1 = launch_daughters(B, g->cap);
         if (e1 == hipSuccess) e1 = launch_accumulate(A, g->cap);
         if (e1 == hipSuccess) e1 = launch_increment(replay, g->cap);
@@ -1863,13 +1930,16 @@ struct Replicas {
         return TTCF_OK;
     }
 
-    // every copy: n_chunks times {steps steps; snapshot into snaps (copy-major)}
-    int32_t run(ttcf_ctx* c, int64_t n_chunks, int64_t steps, double* snaps) {
+    // every copy: n_chunks times {steps steps; snapshot into snaps (copy-major), and its
+    // thermostat variable into zsnaps}
+    int32_t run(ttcf_ctx* c, int64_t n_chunks, int64_t steps, double* snaps,
+                double* zsnaps = nullptr) {
         const size_t sz = 6 * (size_t)ls[0].sys.n;
         for (int r = 0; r < count; ++r) {
             ls[r].n_chunks = n_chunks;
             ls[r].steps_per_chunk = steps;
             ls[r].snapshots = snaps ? snaps + sz * (size_t)r * (size_t)n_chunks : nullptr;
+            ls[r].snap_zeta = zsnaps ? zsnaps + (size_t)r * (size_t)n_chunks : nullptr;
         }
         int32_t rc = upload_mother_launches(c, ls.data(), count);
         if (rc != TTCF_OK) return rc;
@@ -1877,8 +1947,9 @@ struct Replicas {
         return TTCF_OK;
     }
 
-    int32_t sample(ttcf_ctx* c, int32_t per_copy, int64_t between, double* snaps) {
-        return run(c, per_copy, between, snaps);
+    int32_t sample(ttcf_ctx* c, int32_t per_copy, int64_t between, double* snaps,
+                   double* zsnaps = nullptr) {
+        return run(c, per_copy, between, snaps, zsnaps);
     }
 };
 
@@ -1897,14 +1968,14 @@ extern "C" int32_t ttcf_sample_states_replicated(ttcf_ctx* c, int32_t mother, in
     if (m.states_cap < total) {
         HIPCHECK(c, hipStreamSynchronize(c->stream));
         dev_free(m.states);
-        m.states = (double*)dev_alloc(sizeof(double) * 6 * n * total, c->stream);
+        m.states = (double*)dev_alloc(state_buffer_bytes((int)n, (int)total), c->stream);
         m.states_cap = m.states ? total : 0;
         m.n_states = 0;
         if (!m.states) return fail(c, TTCF_ENOMEM, "state buffer allocation failed");
     }
     Replicas R;
     int32_t rc = R.start(c, m, n_replicas, kicks, decorrelate_steps);
-    if (rc == TTCF_OK) rc = R.sample(c, states_per_replica, steps_between, m.states);
+    if (rc == TTCF_OK) rc = R.sample(c, states_per_replica, steps_between, m.states, zetas_of(m));
     if (rc != TTCF_OK) return rc;
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     m.n_states = (int32_t)total;

@@ -63,6 +63,13 @@ struct DaughterDesc {
     int32_t block;      // threads per workgroup the launcher was sized for
     int32_t kmax;       // neighbour-list form: list capacity per atom
     double* hseries;    // n_steps + 1 doubles: learned control variate h(t_k), or null
+    // thermostat of the daughter: 0 Gaussian isokinetic, 1 Nose-Hoover (zeta carried from the
+    // start state; d zeta/dt = (sum p^2 - nh_target)/nh_q)
+    int32_t thermo;
+    int32_t pad2_;
+    double zeta;
+    double nh_q;
+    double nh_target;
 };
 
 enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2, kHealthListOverflow = 4 };
@@ -100,6 +107,7 @@ struct MotherLaunch {
     int64_t n_chunks;      // snapshots to take (0: just run steps_per_chunk)
     int64_t steps_per_chunk;
     double* snapshots;     // n_chunks * 6n doubles, or nullptr
+    double* snap_zeta;     // n_chunks doubles: the thermostat variable at each snapshot, or nullptr
     double* series;        // V*P_xy after every step (n_chunks*steps_per_chunk), or nullptr
     int32_t threads, apt, precision;
     size_t lds_bytes;
@@ -201,6 +209,9 @@ hipError_t launch_replicate(const double* src, const double* zsrc, int32_t n, co
 hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s);
 // dst[i] = src[i], i < count (64-bit words)
 hipError_t launch_copy_words(const uint64_t* src, uint64_t* dst, int64_t count, hipStream_t s);
+// descs[d].zeta = zeta[state_of[d]], reversed for the time-reversing mappings (map_of odd)
+hipError_t launch_desc_zeta(DaughterDesc* descs, const double* zeta, const int32_t* state_of,
+                            const int32_t* map_of, int32_t count, hipStream_t s);
 // *counter += 1 (one thread)
 hipError_t launch_increment(int32_t* counter, hipStream_t s);
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s);

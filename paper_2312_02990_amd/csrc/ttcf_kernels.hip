@@ -547,6 +547,10 @@ __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& 
     const int n_steps = dsc->n_steps;
     double k0 = dsc->k0;
     int health = dsc->health;
+    // Nose-Hoover daughters (Eq. system1 as printed): zeta from the mapped start state
+    const bool nh = dsc->thermo == 1;
+    double zt = dsc->zeta;
+    const double nh_iq = nh ? 1.0 / dsc->nh_q : 0.0, nh_tgt = dsc->nh_target;
     int todo = min(steps_cap, n_steps - done);
     if (health != 0) todo = 0;
     if (todo <= 0 && done > 0) return;
@@ -587,6 +591,18 @@ __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& 
     const double h = S.dt, tau = 0.5 * S.dt, tg = tau * gd;
 
     for (int step = 0; step < todo; ++step) {
+        if (nh) {
+            // ---- first half: Z(tau) T(tau) S(tau) K(tau); pp = sum p^2 of the current p
+            zt += tau * (pp - nh_tgt) * nh_iq;
+            const double c1 = exp(-zt * tau);
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                const double qy = c1 * py[j];
+                px[j] = c1 * px[j] - tg * qy + tau * fx[j];
+                py[j] = qy + tau * fy[j];
+                pz[j] = c1 * pz[j] + tau * fz[j];
+            }
+        } else {
         // ---- first half: S(tau) then K(tau)
         const double ppt = pp - 2.0 * tg * pxpy + tg * tg * pypy;
         const double g1 = sqrt(pp / ppt);
@@ -603,6 +619,7 @@ __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& 
             py[j] = (qy + fy[j] * s1) * isd1;
             pz[j] = (qz + fz[j] * s1) * isd1;
         }
+        }
         // ---- streaming D(h), new strain, sliding-brick wrap
         k += 1;
         dxle = le_offset(S, gd, k);
@@ -614,6 +631,32 @@ __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& 
             wrap_le(S, dxle, x[j], y[j], z[j]);
         }
         compute_forces<Real, APT, false>(S, dxle, x, y, z, fx, fy, fz, wpart, upart, L);
+        if (nh) {
+            // ---- second half: K(tau) S(tau) T(tau), then Z(tau) on the new sum p^2
+            const double c2 = exp(-zt * tau);
+            double m4[4] = {0, 0, wpart, 0};  // pp, pxpy, W, position sum
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                const double qy = py[j] + tau * fy[j];
+                px[j] = c2 * (px[j] + tau * fx[j] - tg * qy);
+                py[j] = c2 * qy;
+                pz[j] = c2 * (pz[j] + tau * fz[j]);
+                m4[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                m4[1] += px[j] * py[j];
+                m4[3] += x[j] + y[j] + z[j];
+            }
+            block_sum<4>(m4, L.red);
+            pp = m4[0];
+            zt += tau * (pp - nh_tgt) * nh_iq;
+            const double vpxy = m4[1] + m4[2];
+            done += 1;
+            if (t == 0) dsc->series[done] = vpxy;
+            if (!isfinite(vpxy) || !isfinite(zt) || !isfinite(m4[3])) {
+                health |= kHealthNonFinite;
+                break;
+            }
+            continue;
+        }
         // ---- moments of (p'', F): pp, pxpy, pypy, fp, fxpy, fypx, fxfy, fypy, fyfy, ff, W, pos
         double m[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, wpart, 0};
 #pragma unroll
@@ -687,6 +730,7 @@ __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& 
         dsc->done = done;
         dsc->k0 = k0;
         dsc->health = health;
+        dsc->zeta = zt;
     }
     __syncthreads();
 }
@@ -791,6 +835,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_mother(const MotherLaunch* ms, 
             if (m.series != nullptr && t == 0) m.series[rec] = c2 * c2 * mm[1] + mm[2];
             ++rec;
         }
+        if (m.snap_zeta != nullptr && t == 0) m.snap_zeta[ch] = zeta;
         if (m.snapshots != nullptr) {
             double* dst = m.snapshots + (size_t)ch * 6 * (size_t)n;
 #pragma unroll
@@ -1592,6 +1637,10 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     const int n_steps = dsc->n_steps;
     double k0 = dsc->k0;
     int health = dsc->health;
+    // Nose-Hoover daughters (Eq. system1 as printed): zeta from the mapped start state
+    const bool nh = dsc->thermo == 1;
+    double zt = dsc->zeta;
+    const double nh_iq = nh ? 1.0 / dsc->nh_q : 0.0, nh_tgt = dsc->nh_target;
     int todo = min(steps_cap, n_steps - done);
     if (health != 0) todo = 0;
     if (todo <= 0 && done > 0) return;
@@ -1648,6 +1697,18 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     int since = 0, since_in = 0;
 
     for (int step = 0; step < todo; ++step) {
+        if (nh) {
+            // ---- first half: Z(tau) T(tau) S(tau) K(tau); pp = sum p^2 of the current p
+            zt += tau * (pp - nh_tgt) * nh_iq;
+            const double c1 = exp(-zt * tau);
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                const double qy = c1 * py[j];
+                px[j] = c1 * px[j] - tg * qy + tau * (double)fx[j];
+                py[j] = qy + tau * (double)fy[j];
+                pz[j] = c1 * pz[j] + tau * (double)fz[j];
+            }
+        } else {
         // ---- first half: S(tau) then K(tau)
         const double ppt = pp - 2.0 * tg * pxpy + tg * tg * pypy;
         const double g1 = sqrt(pp / ppt);
@@ -1663,6 +1724,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             px[j] = (qxp + (double)fx[j] * s1) * isd1;
             py[j] = (qyp + (double)fy[j] * s1) * isd1;
             pz[j] = (qzp + (double)fz[j] * s1) * isd1;
+        }
         }
         // ---- streaming D(h), new strain, sliding-brick wrap, peculiar path length
         k += 1;
@@ -1702,6 +1764,32 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             since_in = 0;
         }
         wpart = nl_forces<APT>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax);
+        if (nh) {
+            // ---- second half: K(tau) S(tau) T(tau), then Z(tau) on the new sum p^2
+            const double c2 = exp(-zt * tau);
+            double m4[4] = {0, 0, wpart, 0};  // pp, pxpy, W, position sum
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                const double qy = py[j] + tau * (double)fy[j];
+                px[j] = c2 * (px[j] + tau * (double)fx[j] - tg * qy);
+                py[j] = c2 * qy;
+                pz[j] = c2 * (pz[j] + tau * (double)fz[j]);
+                m4[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                m4[1] += px[j] * py[j];
+                m4[3] += x[j] + y[j] + z[j];
+            }
+            block_sum<4>(m4, L.red);
+            pp = m4[0];
+            zt += tau * (pp - nh_tgt) * nh_iq;
+            const double vpxy = m4[1] + m4[2];
+            done += 1;
+            if (t == 0) dsc->series[done] = vpxy;
+            if (!isfinite(vpxy) || !isfinite(zt) || !isfinite(m4[3])) {
+                health |= kHealthNonFinite;
+                break;
+            }
+            continue;
+        }
         // ---- moments of (p'', F): pp, pxpy, pypy, fp, fxpy, fypx, fxfy, fypy, fyfy, ff, W, pos
         double m[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, wpart, 0};
 #pragma unroll
@@ -1775,6 +1863,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
         dsc->done = done;
         dsc->k0 = k0;
         dsc->health = health;
+        dsc->zeta = zt;
     }
     __syncthreads();
 }
@@ -1979,6 +2068,22 @@ __global__ void k_copy_words(const uint64_t* src, uint64_t* dst, int64_t count) 
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+__global__ void k_desc_zeta(DaughterDesc* descs, const double* zeta, const int32_t* state_of,
+                            const int32_t* map_of, int32_t count) {
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= count) return;
+    const double z = zeta[state_of[d]];
+    descs[d].zeta = (map_of[d] & 1) ? -z : z;
+}
+
+hipError_t launch_desc_zeta(DaughterDesc* descs, const double* zeta, const int32_t* state_of,
+                            const int32_t* map_of, int32_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_desc_zeta, dim3((count + 255) / 256), dim3(256), 0, s, descs, zeta,
+                       state_of, map_of, count);
+    return hipGetLastError();
 }
 
 __global__ void k_increment(int32_t* counter) {

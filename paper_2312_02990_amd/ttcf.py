@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libttcf.so")
 TTCF_OK, TTCF_EINVAL, TTCF_ENOMEM, TTCF_EDEVICE, TTCF_ESTATE, TTCF_EUNSTABLE = 0, -1, -2, -3, -4, -5
 TTCF_WCA, TTCF_LJ = 0, 1
 TTCF_PREC_FP64, TTCF_PREC_FP32_FORCES = 0, 1
+TTCF_DAUGHTER_GIK, TTCF_DAUGHTER_NH = 0, 1
 TTCF_OBS_PXY = 0
 TTCF_OBS_WALL_STRESS = 1
 TTCF_OBS_VPROFILE = 2
@@ -36,7 +37,8 @@ class System(C.Structure):
     _fields_ = [("n_atoms", C.c_int32), ("potential", C.c_int32), ("box", C.c_double * 3),
                 ("temperature", C.c_double), ("dt", C.c_double), ("r_cut", C.c_double),
                 ("c_attr", C.c_double), ("u_shift", C.c_double), ("nh_tau", C.c_double),
-                ("precision", C.c_int32), ("block_threads", C.c_int32)]
+                ("precision", C.c_int32), ("block_threads", C.c_int32),
+                ("daughter_thermostat", C.c_int32)]
 
 
 class Shape(C.Structure):
@@ -74,7 +76,8 @@ def make_channel(geom, skin: float = 0.0, kmax: int = 0) -> Channel:
 def make_system(n_atoms: int, box, temperature: float = 0.722, dt: float = 0.0025,
                 r_cut: float = 2.0 ** (1.0 / 6.0), c_attr: float = 1.0, u_shift: float | None = None,
                 nh_tau: float = 0.25, precision: int = TTCF_PREC_FP32_FORCES,
-                block_threads: int = 0, potential: int = TTCF_WCA) -> System:
+                block_threads: int = 0, potential: int = TTCF_WCA,
+                thermostat: int = TTCF_DAUGHTER_GIK) -> System:
     if np.isscalar(box):
         box = (float(box),) * 3
     if u_shift is None:
@@ -93,6 +96,7 @@ def make_system(n_atoms: int, box, temperature: float = 0.722, dt: float = 0.002
     s.nh_tau = float(nh_tau)
     s.precision = int(precision)
     s.block_threads = int(block_threads)
+    s.daughter_thermostat = int(thermostat)
     return s
 
 
@@ -133,6 +137,8 @@ def lib():
         "ttcf_sample_states": [V, C.c_int32, C.c_int32, C.c_int64],
         "ttcf_import_states": [V, C.c_int32, C.c_int32, D, D],
         "ttcf_export_states": [V, C.c_int32, C.c_int32, D, D],
+        "ttcf_import_states_zeta": [V, C.c_int32, C.c_int32, D],
+        "ttcf_export_states_zeta": [V, C.c_int32, C.c_int32, D],
         "ttcf_export_mother": [V, C.c_int32, D, D, D, L64],
         "ttcf_record_mother": [V, C.c_int32, C.c_int64],
         "ttcf_export_mother_series": [V, C.c_int32, C.c_int64, D, L64],
@@ -219,7 +225,8 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_channel_export_daughter", "ttcf_channel_daughter_health",
             "ttcf_channel_debug_forces", "ttcf_channel_step_timing", "ttcf_autotune",
             "ttcf_autotune_export", "ttcf_autotune_import", "ttcf_graph_create",
-            "ttcf_graph_launch", "ttcf_graph_replays", "ttcf_graph_destroy"]
+            "ttcf_graph_launch", "ttcf_graph_replays", "ttcf_graph_destroy",
+            "ttcf_import_states_zeta", "ttcf_export_states_zeta"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -416,6 +423,17 @@ class Context:
                                                    int(decorrelate_steps), int(states_per_replica),
                                                    int(steps_between)),
                "ttcf_sample_states_replicated", self._ctx)
+
+    def ttcf_import_states_zeta(self, mother: int, zeta):
+        z = _f64(np.atleast_1d(zeta))
+        _check(lib().ttcf_import_states_zeta(self._ctx, int(mother), int(z.size), _dp(z)),
+               "ttcf_import_states_zeta", self._ctx)
+
+    def ttcf_export_states_zeta(self, mother: int, n_states: int):
+        z = np.zeros(n_states)
+        _check(lib().ttcf_export_states_zeta(self._ctx, int(mother), int(n_states), _dp(z)),
+               "ttcf_export_states_zeta", self._ctx)
+        return z
 
     def ttcf_export_states(self, mother: int, n_states: int):
         n = self.systems[mother].n_atoms

@@ -41,8 +41,35 @@ def test_strerror_and_argument_checks_without_device(built):
     lib.ttcf_destroy(None)
 
 
-def test_system_struct_layout_matches_header(built):
-    import ctypes as C
-    # int32 n, int32 potential, double box[3], temperature, dt, r_cut, c_attr, u_shift,
-    # nh_tau, int32 precision, int32 block_threads
-    assert C.sizeof(built.System) == 4 + 4 + 24 + 6 * 8 + 4 + 4
+def _c_layout(struct: str, fields):
+    """sizeof and offsetof of a struct of include/ttcf.h, from gcc."""
+    import subprocess
+    import tempfile
+    lines = [f'printf("%zu\\n", sizeof({struct}));']
+    lines += [f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"ttcf.h\"\nint main(void) {\n"
+           + "\n".join(lines) + "\nreturn 0;\n}\n")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, c], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return int(out[0]), [int(x) for x in out[1:]]
+
+
+@pytest.mark.parametrize("name,struct", [("System", "ttcf_system"), ("Shape", "ttcf_shape"),
+                                         ("GraphDesc", "ttcf_graph_desc"),
+                                         ("Channel", "ttcf_channel")])
+def test_struct_layouts_match_header(built, name, struct):
+    """Every ctypes mirror of a header struct has the C compiler's size and field offsets."""
+    py = getattr(built, name)
+    fields = [f[0] for f in py._fields_]
+    size, offs = _c_layout(struct, fields)
+    assert C_sizeof(py) == size
+    assert [getattr(py, f).offset for f in fields] == offs
+
+
+def C_sizeof(t):
+    import ctypes
+    return ctypes.sizeof(t)

@@ -240,6 +240,79 @@ def test_daughter_trajectories(T, orc, cfg1, precision, variant, tol, gd):
     np.testing.assert_allclose(v0[:, 3], -v0[:, 0], rtol=1e-5 if precision else 1e-12)
 
 
+@pytest.fixture(scope="module")
+def cfg1_nh(orc):
+    """Config-1 system, 8 start states every 100 steps with their thermostat variables."""
+    s = I.System(4)
+    r, p = I.initial_state(s, 11)
+    box = orc.make_box(s.n, s.box)
+    st = orc.NHState(r.ravel().copy(), p.ravel().copy())
+    orc.nh_run(box, st, 1000, 2.0, s.dt, orc.nh_q(s.nf, 2.0, TAU), s.nf)
+    sr, sp, sz = orc.mother_sample(box, st, 2000, 8, 100, s.temperature, s.dt,
+                                   orc.nh_q(s.nf, s.temperature, TAU), s.nf, with_zeta=True)
+    return s, box, sr, sp, sz
+
+
+@pytest.mark.parametrize("precision,variant,tol", [(0, 1, 1e-9), (1, 1, 1e-4), (1, 2, 1e-4)])
+@pytest.mark.parametrize("gd", [1e-3, 1.0])
+def test_nh_daughter_trajectories(T, orc, cfg1_nh, precision, variant, tol, gd):
+    """Nose-Hoover daughters (Eq. system1 as printed), zeta carried from the start state and
+    reversed by mappings 1 and 3, against the oracle; the run is split over two step calls."""
+    s, box, sr, sp, sz = cfg1_nh
+    nst = 50
+    q = orc.nh_q(s.nf, s.temperature, TAU)
+    say(f"NH daughters 32 x {nst} steps precision={precision} variant={variant} gamma={gd}")
+    with T.Context() as ctx:
+        sysd = T.make_system(s.n, s.box, s.temperature, s.dt, precision=precision, nh_tau=TAU,
+                             thermostat=T.TTCF_DAUGHTER_NH)
+        mid = ctx.ttcf_init_mother(sysd, sr[0], sp[0], n_equil=0)
+        ctx.ttcf_set_step_shape(variant=variant)
+        ctx.ttcf_import_states(mid, sr, sp)
+        assert np.all(ctx.ttcf_export_states_zeta(mid, 8) == 0.0)
+        ctx.ttcf_import_states_zeta(mid, sz)
+        assert np.array_equal(ctx.ttcf_export_states_zeta(mid, 8), sz)
+        first = ctx.ttcf_spawn_daughters(mid, 8, 0, gd, nst)
+        ctx.ttcf_step(20)
+        ctx.ttcf_step(nst)
+        ser = ctx.ttcf_export_series(first, 32, nst + 1)
+        fin = [ctx.ttcf_export_daughter(first + d, s.n) for d in range(32)]
+    state_of = np.repeat(np.arange(8), 4)
+    map_of = np.tile(np.arange(4), 8)
+    vo, ro, po, _ = orc.run_daughters_nh(box, sr, sp, sz, state_of, map_of, np.full(32, gd), s.dt,
+                                         s.temperature, q, s.nf, nst, nthreads=8,
+                                         final_state=True)
+    scale = np.std(vo)
+    assert np.abs(ser - vo).max() / scale <= tol
+    for d in range(32):
+        rg, pg, k = fin[d]
+        assert k == nst
+        dr = rg - ro[d]
+        dr -= s.box * np.rint(dr / s.box)
+        assert np.abs(dr).max() / s.box <= tol
+        assert np.abs(pg - po[d]).max() / np.sqrt(np.mean(po[d] ** 2)) <= tol
+
+
+def test_sampled_states_carry_the_mother_thermostat(T, orc, cfg1_nh):
+    """Sampling records the mother's zeta at every saved state (the last one is the mother's
+    current zeta), and replicated sampling records each copy's."""
+    s, box, sr, sp, sz = cfg1_nh
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 0), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_sample_states(mid, 3, 40)
+        z = ctx.ttcf_export_states_zeta(mid, 3)
+        _, _, zm, _ = ctx.ttcf_export_mother(mid)
+        assert z[-1] == zm and len(set(z.tolist())) == 3
+        ctx.ttcf_sample_states_replicated(mid, 2, None, 30, 2, 20)
+        zr = ctx.ttcf_export_states_zeta(mid, 4)
+        # copies without kicks run the same trajectory: equal zeta, copy by copy
+        assert zr[0] == zr[2] and zr[1] == zr[3] and zr[0] != zr[1]
+    # the oracle mother from the same state gives the same zeta sequence
+    st = orc.NHState(sr[0].copy(), sp[0].copy(), 0.0)
+    _, _, oz = orc.mother_sample(box, st, 0, 3, 40, s.temperature, s.dt,
+                                 orc.nh_q(s.nf, s.temperature, TAU), s.nf, with_zeta=True)
+    np.testing.assert_allclose(z, oz, rtol=1e-9, atol=1e-12)
+
+
 def test_neighbour_lists_are_skin_invariant(T, orc, cfg1):
     """Lists are sorted by atom id and pairs beyond the cutoff add nothing, so the results
     are bit-identical for any skin (and any rebuild schedule), at strong shear too."""
@@ -524,8 +597,8 @@ def _same_response(a, b):
     assert a[4] == b[4]
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_graph_replays_equal_eager_cycles(T, precision):
+@pytest.mark.parametrize("precision,thermostat", [(0, 0), (1, 0), (1, 1)])
+def test_graph_replays_equal_eager_cycles(T, precision, thermostat):
     """A mother that saves 6 states 30 steps apart, per-state shear rates, 25-step daughters:
     after each replay (eager work and synchronisation in between) the response and the
     mother equal those of the same number of eager cycles, bit for bit."""
@@ -536,7 +609,7 @@ def test_graph_replays_equal_eager_cycles(T, precision):
     say("graph vs eager, precision", precision)
     eager, eager_mother = [], None
     with T.Context() as ctx:
-        mid = ctx.ttcf_init_mother(gsys(T, s, precision), r0, p0, n_equil=100)
+        mid = ctx.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=precision, thermostat=thermostat), r0, p0, n_equil=100)
         for _ in range(reps):
             ctx.ttcf_spawn_daughters(mid, ns, sb, gam, nst)
             ctx.ttcf_step(nst)
@@ -544,7 +617,7 @@ def test_graph_replays_equal_eager_cycles(T, precision):
             eager.append(ctx.ttcf_response(nst + 1, 0.0))
         eager_mother = ctx.ttcf_export_mother(mid)
     with T.Context() as ctx:
-        mid = ctx.ttcf_init_mother(gsys(T, s, precision), r0, p0, n_equil=100)
+        mid = ctx.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=precision, thermostat=thermostat), r0, p0, n_equil=100)
         g = ctx.ttcf_graph_create(mid, ns, sb, gam, nst, max_replays=reps)
         with pytest.raises(T.TTCFError):
             ctx.ttcf_response(nst + 1, 0.0)  # reserved rows are not counted before a replay

@@ -197,6 +197,36 @@ def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per
             "per_unit_rate_ttcf_end": float(tm[-1]), "per_unit_rate_ttcf_se_end": float(tse[-1])}
 
 
+def thermostat_leg(T, stream, ctx, mid, s, n_states, nst, gd=1e-2):
+    """Gaussian isokinetic against Nose-Hoover daughters (the paper's own dynamics, zeta
+    carried from each start state) on the benchmark's 1024 start states at one shear rate:
+    TTCF and direct average at the end, and the step kernel's throughput for each."""
+    import torch
+    r, p = ctx.ttcf_export_states(mid, n_states)
+    z = ctx.ttcf_export_states_zeta(mid, n_states)
+    out = {"gamma_dot": gd, "workload": f"N={s.n}, {n_states} states x 4 mappings x {nst} steps"}
+    for name, th in (("gik", 0), ("nose_hoover", 1)):
+        with T.Context(stream) as c2:
+            m2 = c2.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1,
+                                                   thermostat=th), r[0], p[0], n_equil=0)
+            c2.ttcf_import_states(m2, r, p)
+            c2.ttcf_import_states_zeta(m2, z)
+            c2.ttcf_spawn_daughters(m2, n_states, 0, gd, nst)
+            c2.ttcf_step_timing(reset=True)
+            c2.ttcf_step(nst)
+            ms, _ = c2.ttcf_step_timing(reset=True)
+            c2.ttcf_accumulate()
+            tm, tse, dm, dse, used = c2.ttcf_response(nst + 1, gd)
+            torch.cuda.synchronize()
+        out[name] = {"ttcf_end": float(tm[-1]), "ttcf_se_end": float(tse[-1]),
+                     "dav_end": float(dm[-1]), "dav_se_end": float(dse[-1]),
+                     "kernel_atom_steps_per_s": 4 * n_states * s.n * nst / (ms / 1e3)}
+    a, b = out["gik"], out["nose_hoover"]
+    out["ttcf_difference_over_se"] = (a["ttcf_end"] - b["ttcf_end"]) / float(
+        np.hypot(a["ttcf_se_end"], b["ttcf_se_end"]))
+    return out
+
+
 def graph_leg(T, stream, n_cells=8, copies=1024, between=100, nst=500, gd=1e-2, replays=3,
               decorrelate=400, seed=7):
     """Whole batch cycles replayed from one captured graph: 1024 persistent copies of the
@@ -420,6 +450,8 @@ def main():
     ap.add_argument("--fp64-check", type=int, default=1,
                     help="1: rerun the batch's start states with FP64 forces at every shear rate "
                          "and report the FP32-force error of each response")
+    ap.add_argument("--thermostats", type=int, default=1,
+                    help="1: also compare isokinetic and Nose-Hoover daughters on the same states")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: also measure whole cycles replayed from a captured graph")
     ap.add_argument("--uneven", type=int, default=1,
@@ -494,6 +526,12 @@ def main():
     precision = None
     if args.precision == 1 and args.fp64_check:
         precision = precision_statement(T, ctx, mid, sysd, s, args.states, nst, stream)
+    thermostats = None
+    if args.thermostats:
+        try:
+            thermostats = thermostat_leg(T, stream, ctx, mid, s, args.states, nst)
+        except Exception as e:  # the headline line is printed whatever happens here
+            thermostats = {"error": repr(e)}
     ctx.close()
 
     atom_steps = n_d * s.n * nst
@@ -540,6 +578,8 @@ def main():
     }
     if precision is not None:
         line["precision"] = precision
+    if thermostats is not None:
+        line["thermostats"] = thermostats
     if args.graph:
         try:
             line["graph"] = graph_leg(T, stream)

@@ -497,9 +497,15 @@ def main():
     t0 = time.perf_counter()
     mid = ctx.ttcf_init_mother(sysd, r0, p0, n_equil=2000, n_melt=1000, t_melt=2.0)
     ctx.ttcf_set_step_shape(args.variant, args.threads, args.skin, args.kmax)
+    ctx.ttcf_record_mother(mid, 100 * args.states)
     ctx.ttcf_sample_states(mid, args.states, 100)
     torch.cuda.synchronize()
     mother_s = time.perf_counter() - t0
+    # the sampling interval against the correlation time of the mother's V*P_xy
+    acf_vals, acf_first, acf_tau = ctx.ttcf_mother_acf(mid, 400, 0.05)
+    mother_acf = {"steps_between": 100, "first_lag_below_0.05": acf_first,
+                  "integrated_correlation_steps": acf_tau,
+                  "acf_at_steps_between": float(acf_vals[100])}
     mother_steps = 3000 + 100 * args.states
 
     nst = args.daughter_steps
@@ -571,6 +577,7 @@ def main():
         },
         "kernel_atom_steps_per_s": atom_steps / avg_launch_s,
         "mother_s": mother_s,
+        "mother_acf": mother_acf,
         "mother_atom_steps_per_s": mother_steps * s.n / mother_s,
         "last_response": {"gamma_dot": GAMMAS[(args.warmup + args.steps - 1) % len(GAMMAS)],
                           "ttcf_end": float(last[0][-1]), "ttcf_se_end": float(last[1][-1]),

@@ -181,6 +181,19 @@ int32_t ttcf_sample_states_replicated(ttcf_ctx* ctx, int32_t mother, int32_t n_r
 /* Mother's current state: r, p (3n each), the Nose-Hoover variable and the step count. */
 int32_t ttcf_export_mother(ttcf_ctx* ctx, int32_t mother, double* r, double* p, double* zeta,
                            int64_t* steps);
+/* Sec. Mathematical Framework: the delay T_s between saved states must exceed the time over
+ * which the mother's states stay correlated. Autocorrelation of a series x[0..n) (host data,
+ * ttcf_acf) or of the mother's recorded V*P_xy series (ttcf_mother_acf), computed on the GPU:
+ *   acf[k] = C(k)/C(0), C(k) = sum_{i < n-k} (x_i - m)(x_{i+k} - m) / (n - k), m the mean,
+ * for 0 <= k < max_lag (max_lag <= n; compensated FP64 sums). *first_below (may be NULL): the
+ * smallest k >= 1 with acf[k] < threshold, -1 if none; *tau_int (may be NULL): the
+ * integrated correlation time in steps, 1/2 + sum of acf[k] over 1 <= k < k0, k0 the first
+ * lag with acf[k] <= 0 (max_lag if none). A choice of T_s: first_below for a small threshold,
+ * or a few tau_int. Errors: TTCF_EINVAL (sizes), TTCF_ESTATE (no recorded series). */
+int32_t ttcf_acf(ttcf_ctx* ctx, const double* series, int64_t n, int32_t max_lag,
+                 double threshold, double* acf, int32_t* first_below, double* tau_int);
+int32_t ttcf_mother_acf(ttcf_ctx* ctx, int32_t mother, int32_t max_lag, double threshold,
+                        double* acf, int32_t* first_below, double* tau_int);
 /* Mother series: V*P_xy after every step of the last ttcf_init_mother/ttcf_spawn_daughters
  * run on this mother when recording was enabled with ttcf_record_mother (n values). */
 int32_t ttcf_record_mother(ttcf_ctx* ctx, int32_t mother, int64_t capacity);

@@ -404,3 +404,29 @@ def green_kubo(pxy_series, volume: float, temperature: float, dt: float, max_lag
     eta = np.zeros(max_lag + 1)
     eta[1:] = np.cumsum(0.5 * dt * (c[:-1] + c[1:]))
     return c, (volume / temperature) * eta
+
+
+# ----------------------------------------------------------------------------------------
+# autocorrelation of the mother's P_xy (Sec. Mathematical Framework: choice of T_s)
+# ----------------------------------------------------------------------------------------
+
+def acf(series, max_lag: int) -> np.ndarray:
+    """acf[k] = C(k)/C(0), C(k) = sum_{i < n-k} (x_i - m)(x_{i+k} - m) / (n - k): the
+    definition, one dot product per lag."""
+    x = _f64(np.ravel(series))
+    d = x - x.mean()
+    n = len(d)
+    c = np.array([np.dot(d[:n - k], d[k:]) / (n - k) for k in range(max_lag)])
+    return c / c[0]
+
+
+def acf_summary(a: np.ndarray, threshold: float):
+    """(first lag k >= 1 with a[k] < threshold or -1, integrated correlation time
+    1/2 + sum_{1 <= k < k0} a[k] with k0 the first lag where a[k] <= 0)."""
+    below = [k for k in range(1, len(a)) if a[k] < threshold]
+    tau = 0.5
+    for k in range(1, len(a)):
+        if not a[k] > 0.0:
+            break
+        tau += a[k]
+    return (below[0] if below else -1), tau

@@ -598,6 +598,50 @@ int32_t ttcf_export_mother_series(ttcf_ctx* c, int32_t mother, int64_t n, double
     return TTCF_OK;
 }
 
+namespace {
+// Autocorrelation of a device series; results to host.
+int32_t acf_device(ttcf_ctx* c, const double* d_x, int64_t n, int32_t max_lag, double threshold,
+                   double* acf, int32_t* first_below, double* tau_int) {
+    if (n < 2 || max_lag < 1 || max_lag > n || !acf)
+        return fail(c, TTCF_EINVAL, "acf needs 2 <= n, 1 <= max_lag <= n and an output array");
+    Scratch sc(c->stream);
+    double* d = sc.get<double>((size_t)max_lag + 4);
+    if (!d) return fail(c, TTCF_ENOMEM, "acf scratch allocation failed");
+    double* d_acf = d + 4;
+    int32_t* d_fb = (int32_t*)(d + 1);
+    HIPCHECK(c, launch_acf(d_x, n, max_lag, threshold, d, d_acf, d_fb, d + 2, c->stream));
+    double tail[2];
+    int32_t fb = -1;
+    HIPCHECK(c, hipMemcpyAsync(acf, d_acf, sizeof(double) * max_lag, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHECK(c, hipMemcpyAsync(&fb, d_fb, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipMemcpyAsync(tail, d + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (first_below) *first_below = fb;
+    if (tau_int) *tau_int = tail[0];
+    return TTCF_OK;
+}
+}  // namespace
+
+int32_t ttcf_acf(ttcf_ctx* c, const double* series, int64_t n, int32_t max_lag, double threshold,
+                 double* acf, int32_t* first_below, double* tau_int) {
+    if (!c || !series || n < 2) return TTCF_EINVAL;
+    Scratch sc(c->stream);
+    double* d_x = sc.get<double>((size_t)n);
+    if (!d_x) return fail(c, TTCF_ENOMEM, "acf series allocation failed");
+    HIPCHECK(c, hipMemcpyAsync(d_x, series, sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    return acf_device(c, d_x, n, max_lag, threshold, acf, first_below, tau_int);
+}
+
+int32_t ttcf_mother_acf(ttcf_ctx* c, int32_t mother, int32_t max_lag, double threshold,
+                        double* acf, int32_t* first_below, double* tau_int) {
+    if (!c || mother < 0 || mother >= (int32_t)c->mothers.size()) return TTCF_EINVAL;
+    Mother& m = c->mothers[mother];
+    if (!m.series || m.series_count < 2)
+        return fail(c, TTCF_ESTATE, "no recorded mother series (ttcf_record_mother, then run)");
+    return acf_device(c, m.series, m.series_count, max_lag, threshold, acf, first_below, tau_int);
+}
+
 int32_t ttcf_import_states(ttcf_ctx* c, int32_t mother, int32_t n_states, const double* r,
                            const double* p) {
     if (!c || mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || !r || !p)

@@ -212,6 +212,11 @@ hipError_t launch_copy_words(const uint64_t* src, uint64_t* dst, int64_t count, 
 // descs[d].zeta = zeta[state_of[d]], reversed for the time-reversing mappings (map_of odd)
 hipError_t launch_desc_zeta(DaughterDesc* descs, const double* zeta, const int32_t* state_of,
                             const int32_t* map_of, int32_t count, hipStream_t s);
+// Autocorrelation of x[0..n) at lags 0..max_lag-1 (normalised by C(0)), the first lag below
+// threshold and the integrated correlation time; scratch: 1 double (the mean)
+hipError_t launch_acf(const double* x, int64_t n, int32_t max_lag, double threshold,
+                      double* scratch, double* acf, int32_t* first_below, double* tau_int,
+                      hipStream_t s);
 // *counter += 1 (one thread)
 hipError_t launch_increment(int32_t* counter, hipStream_t s);
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s);

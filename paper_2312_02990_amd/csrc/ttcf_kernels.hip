@@ -2086,6 +2086,65 @@ hipError_t launch_desc_zeta(DaughterDesc* descs, const double* zeta, const int32
     return hipGetLastError();
 }
 
+// ---- autocorrelation of a series (choice of the sampling interval T_s) ----------------
+// out[0] = mean of x[0..n) (one workgroup, fixed order: strided partial sums, then a block sum)
+__global__ void k_series_mean(const double* x, int64_t n, double* out) {
+    __shared__ double red[kMaxWaves * kRedSlots + kRedSlots];
+    double v[1] = {0.0};
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) v[0] += x[i];
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) out[0] = v[0] / (double)n;
+}
+
+// acf[k] = C(k) / C(0), C(k) = sum_{i < n-k} (x_i - m)(x_{i+k} - m) / (n - k): one thread
+// per lag; lanes of a wave read consecutive x_{i+k} and share x_i.
+__global__ void k_acf(const double* x, int64_t n, const double* mean, int32_t max_lag,
+                      double* acf) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const double m = mean[0];
+    double c0 = 0.0, ck = 0.0, comp0 = 0.0, compk = 0.0;
+    const bool live = k < max_lag && (int64_t)k < n;
+    for (int64_t i = 0; i < n; ++i) {
+        const double a = x[i] - m;
+        // Neumaier sums: the lag-0 sum (each thread forms it, for its own normalisation)
+        neumaier_add(c0, comp0, a * a);
+        if (live && i + k < n) neumaier_add(ck, compk, a * (x[i + k] - m));
+    }
+    if (live) {
+        const double cz = (c0 + comp0) / (double)n;
+        acf[k] = ((ck + compk) / (double)(n - k)) / cz;
+    }
+}
+
+// first lag k >= 1 with acf[k] < threshold (-1 if none), and the integrated correlation
+// time 1/2 + sum_{1 <= k < k0} acf[k], k0 the first lag with acf[k] <= 0 (max_lag if none)
+__global__ void k_acf_summary(const double* acf, int32_t max_lag, double threshold,
+                              int32_t* first_below, double* tau_int) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t fb = -1;
+    for (int32_t k = 1; k < max_lag; ++k)
+        if (acf[k] < threshold) {
+            fb = k;
+            break;
+        }
+    double tau = 0.5;
+    for (int32_t k = 1; k < max_lag && acf[k] > 0.0; ++k) tau += acf[k];
+    first_below[0] = fb;
+    tau_int[0] = tau;
+}
+
+hipError_t launch_acf(const double* x, int64_t n, int32_t max_lag, double threshold,
+                      double* scratch, double* acf, int32_t* first_below, double* tau_int,
+                      hipStream_t s) {
+    if (n < 2 || max_lag < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_series_mean, dim3(1), dim3(1024), 0, s, x, n, scratch);
+    hipLaunchKernelGGL(k_acf, dim3((max_lag + 63) / 64), dim3(64), 0, s, x, n, scratch, max_lag,
+                       acf);
+    hipLaunchKernelGGL(k_acf_summary, dim3(1), dim3(64), 0, s, acf, max_lag, threshold,
+                       first_below, tau_int);
+    return hipGetLastError();
+}
+
 __global__ void k_increment(int32_t* counter) {
     if (threadIdx.x == 0) counter[0] = counter[0] + 1;
 }

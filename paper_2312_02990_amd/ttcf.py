@@ -138,6 +138,8 @@ def lib():
         "ttcf_import_states": [V, C.c_int32, C.c_int32, D, D],
         "ttcf_export_states": [V, C.c_int32, C.c_int32, D, D],
         "ttcf_import_states_zeta": [V, C.c_int32, C.c_int32, D],
+        "ttcf_acf": [V, D, C.c_int64, C.c_int32, C.c_double, D, I, D],
+        "ttcf_mother_acf": [V, C.c_int32, C.c_int32, C.c_double, D, I, D],
         "ttcf_export_states_zeta": [V, C.c_int32, C.c_int32, D],
         "ttcf_export_mother": [V, C.c_int32, D, D, D, L64],
         "ttcf_record_mother": [V, C.c_int32, C.c_int64],
@@ -226,7 +228,7 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_channel_debug_forces", "ttcf_channel_step_timing", "ttcf_autotune",
             "ttcf_autotune_export", "ttcf_autotune_import", "ttcf_graph_create",
             "ttcf_graph_launch", "ttcf_graph_replays", "ttcf_graph_destroy",
-            "ttcf_import_states_zeta", "ttcf_export_states_zeta"]
+            "ttcf_import_states_zeta", "ttcf_export_states_zeta", "ttcf_acf", "ttcf_mother_acf"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -423,6 +425,25 @@ class Context:
                                                    int(decorrelate_steps), int(states_per_replica),
                                                    int(steps_between)),
                "ttcf_sample_states_replicated", self._ctx)
+
+    def ttcf_acf(self, series, max_lag: int, threshold: float = 0.05):
+        """(acf[0..max_lag), first lag below threshold, integrated correlation time)."""
+        x = _f64(np.ravel(series))
+        out = np.zeros(max_lag)
+        fb = C.c_int32(0)
+        tau = C.c_double(0.0)
+        _check(lib().ttcf_acf(self._ctx, _dp(x), int(x.size), int(max_lag), float(threshold),
+                              _dp(out), C.byref(fb), C.byref(tau)), "ttcf_acf", self._ctx)
+        return out, fb.value, tau.value
+
+    def ttcf_mother_acf(self, mother: int, max_lag: int, threshold: float = 0.05):
+        out = np.zeros(max_lag)
+        fb = C.c_int32(0)
+        tau = C.c_double(0.0)
+        _check(lib().ttcf_mother_acf(self._ctx, int(mother), int(max_lag), float(threshold),
+                                     _dp(out), C.byref(fb), C.byref(tau)), "ttcf_mother_acf",
+               self._ctx)
+        return out, fb.value, tau.value
 
     def ttcf_import_states_zeta(self, mother: int, zeta):
         z = _f64(np.atleast_1d(zeta))

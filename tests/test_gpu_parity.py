@@ -588,6 +588,35 @@ def test_autotune_cache_text_is_validated(T):
         assert '"arch": "gfx000"' in ctx.ttcf_autotune_export()
 
 
+def test_autocorrelation_matches_oracle(T, orc):
+    """The autocorrelation used to choose T_s: a seeded AR(1) series against the oracle's
+    definition, and the mother's recorded V*P_xy series through both entry points."""
+    x = I.ar1_series(20000, 0.95, 9)
+    s = I.System(4)
+    r0, p0 = I.initial_state(s, 1)
+    say("autocorrelation")
+    with T.Context() as ctx:
+        # melted first: an fcc start at this state point stays crystalline for a while
+        mid = ctx.ttcf_init_mother(gsys(T, s, 0), r0, p0, n_equil=1000, n_melt=1000, t_melt=2.0)
+        a, fb, tau = ctx.ttcf_acf(x, 300, 0.05)
+        ctx.ttcf_record_mother(mid, 4000)
+        ctx.ttcf_sample_states(mid, 40, 100)
+        am, fbm, taum = ctx.ttcf_mother_acf(mid, 400, 0.05)
+        series = ctx.ttcf_export_mother_series(mid, 4000)
+        a2, fb2, tau2 = ctx.ttcf_acf(series, 400, 0.05)
+        with pytest.raises(T.TTCFError):
+            ctx.ttcf_acf(x[:10], 20)  # max_lag beyond the series
+    oa = orc.acf(x, 300)
+    ofb, otau = orc.acf_summary(oa, 0.05)
+    np.testing.assert_allclose(a, oa, rtol=0, atol=1e-12)
+    assert fb == ofb and tau == pytest.approx(otau, rel=1e-12)
+    assert len(series) == 4000
+    np.testing.assert_array_equal(am, a2)
+    assert (fbm, taum) == (fb2, tau2)
+    say("mother acf: first lag below 0.05", fbm, "integrated time", taum)
+    assert am[0] == pytest.approx(1.0, abs=1e-15) and 0 < fbm < 400
+
+
 # ----------------------------------------------------------------------------------------
 # captured batch cycles: every replay equals the same cycle run through the eager calls
 # ----------------------------------------------------------------------------------------

@@ -79,6 +79,18 @@ def perturbed_positions(system: System, seed: int, amplitude: float = 0.08) -> n
     return np.ascontiguousarray(np.mod(r, system.box))
 
 
+def ar1_series(n: int, phi: float, seed: int) -> np.ndarray:
+    """A seeded first-order autoregressive series x_i = phi x_{i-1} + e_i (e_i standard
+    normal, x_0 = e_0): synthetic input of known correlation for autocorrelation checks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    e = rng.standard_normal(n)
+    x = np.empty(n)
+    x[0] = e[0]
+    for i in range(1, n):
+        x[i] = phi * x[i - 1] + e[i]
+    return x
+
+
 def log_uniform_rates(count: int, lo: float, hi: float, seed: int) -> np.ndarray:
     """Shear rates drawn log-uniformly in [lo, hi] (one per start state)."""
     rng = np.random.Generator(np.random.PCG64(seed))

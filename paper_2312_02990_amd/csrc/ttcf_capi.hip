@@ -896,6 +896,7 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
     L->cmax = variant == kVariantNeighbourList ? lcmax : cmax;
     L->variant = variant;
     L->kmax = kmax;
+    L->thermo = group.empty() ? 0 : group[0]->thermo;
     L->lds_bytes = variant == kVariantNeighbourList ? nl_lds
                                                     : lds_bytes_for(nmax, cmax, threads, precision);
     if (L->lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
@@ -954,8 +955,9 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     int32_t rc = sync_descs(c);
     if (rc != TTCF_OK) return rc;
     // daughters still to run; each goes to the neighbour-list form when it may and its lists
-    // fit, else to the cell form; each form is one persistent launch, largest systems first
-    std::vector<int32_t> nl_group, cell_group;
+    // fit, else to the cell form; each (form, thermostat) is one persistent launch, largest
+    // systems first. groups[2 form + thermo], form 0 lists, 1 cells
+    std::vector<int32_t> groups[4];
     std::vector<StepShape> eff(c->descs.size());
     int precision = -1;
     for (size_t i = 0; i < c->descs.size(); ++i) {
@@ -971,18 +973,21 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         bool nl = false;
         rc = apply_shape(c, e, precision, &d, &nl);
         if (rc != TTCF_OK) return rc;
-        (nl ? nl_group : cell_group).push_back((int32_t)i);
+        groups[2 * (nl ? 0 : 1) + (d.thermo ? 1 : 0)].push_back((int32_t)i);
     }
-    if (nl_group.empty() && cell_group.empty()) return TTCF_OK;
-    if (!nl_group.empty()) {
+    const bool any_nl = !groups[0].empty() || !groups[1].empty();
+    const bool any_cell = !groups[2].empty() || !groups[3].empty();
+    if (!any_nl && !any_cell) return TTCF_OK;
+    if (any_nl) {
         rc = push_descs(c);  // the list grids were just written into the descriptors
         if (rc != TTCF_OK) return rc;
     }
     auto by_size = [&](int32_t a, int32_t b) { return c->descs[a].sys.n > c->descs[b].sys.n; };
-    std::stable_sort(nl_group.begin(), nl_group.end(), by_size);
-    std::stable_sort(cell_group.begin(), cell_group.end(), by_size);
-    std::vector<int32_t> order(nl_group);
-    order.insert(order.end(), cell_group.begin(), cell_group.end());
+    std::vector<int32_t> order;
+    for (auto& g : groups) {
+        std::stable_sort(g.begin(), g.end(), by_size);
+        order.insert(order.end(), g.begin(), g.end());
+    }
     if (c->d_order_cap < order.size()) {
         dev_free(c->d_order);
         c->d_order = (int32_t*)dev_alloc(sizeof(int32_t) * order.size() * 2, c->stream);
@@ -992,11 +997,11 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     HIPCHECK(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int32_t) * order.size(),
                                hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    c->last_variant = nl_group.empty() ? kVariantCells
-                                       : (cell_group.empty() ? kVariantNeighbourList : 3);
+    c->last_variant = !any_nl ? kVariantCells : (!any_cell ? kVariantNeighbourList : 3);
     size_t offset = 0;
-    for (int form = 0; form < 2; ++form) {
-        const std::vector<int32_t>& group = form == 0 ? nl_group : cell_group;
+    for (int gi = 0; gi < 4; ++gi) {
+        const int form = gi / 2;
+        const std::vector<int32_t>& group = groups[gi];
         if (group.empty()) continue;
         // the largest system's shape sets the workgroup size
         std::vector<const DaughterDesc*> ds;

@@ -94,6 +94,7 @@ struct BatchLaunch {
     int32_t nmax, cmax;    // largest system / cell grid in the batch (LDS sizing)
     int32_t variant;       // Variant
     int32_t kmax;          // neighbour-list capacity per atom (neighbour-list form)
+    int32_t thermo;        // daughter thermostat of every job (0 isokinetic, 1 Nose-Hoover)
     size_t lds_bytes;
 };
 

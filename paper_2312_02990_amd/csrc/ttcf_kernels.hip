@@ -533,7 +533,7 @@ __device__ __forceinline__ void iso_kick_coeffs(double a, double b, double tau, 
 // old p.p; K is the closed-form kick above. The scalars each part needs are moments of (p, F):
 // the moments reduced once after the force pass give, in closed form, those of the second
 // half and of the next step's first half, so the step needs a single block reduction.
-template <typename Real, int APT>
+template <typename Real, int APT, bool NH>
 __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& L) {
     const int T = blockDim.x, t = threadIdx.x;
     if (t == 0) *L.sys = dsc->sys;
@@ -548,7 +548,7 @@ __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& 
     double k0 = dsc->k0;
     int health = dsc->health;
     // Nose-Hoover daughters (Eq. system1 as printed): zeta from the mapped start state
-    const bool nh = dsc->thermo == 1;
+    constexpr bool nh = NH;  // the descriptor's thermo selects the instantiation
     double zt = dsc->zeta;
     const double nh_iq = nh ? 1.0 / dsc->nh_q : 0.0, nh_tgt = dsc->nh_target;
     int todo = min(steps_cap, n_steps - done);
@@ -735,7 +735,7 @@ __device__ void run_daughter(DaughterDesc* dsc, int steps_cap, const Lds<Real>& 
     __syncthreads();
 }
 
-template <typename Real, int APT, int MAXT>
+template <typename Real, int APT, int MAXT, bool NH>
 __global__ __launch_bounds__(MAXT) void k_daughters(BatchLaunch b) {
     extern __shared__ __align__(32) char smem[];
     const Lds<Real> L = carve<Real>(smem, b.nmax, b.cmax);
@@ -748,7 +748,7 @@ __global__ __launch_bounds__(MAXT) void k_daughters(BatchLaunch b) {
         // read with scalar loads and its fields stay in scalar registers
         const int j = __builtin_amdgcn_readfirstlane(L.misc[0]);
         if (j >= b.n_jobs) break;
-        run_daughter<Real, APT>(&b.descs[b.order[j]], b.max_steps, L);
+        run_daughter<Real, APT, NH>(&b.descs[b.order[j]], b.max_steps, L);
     }
 }
 
@@ -1622,7 +1622,7 @@ __device__ __forceinline__ float2 nl_publish(const SysDev& S, const double (&x)[
     return m;
 }
 
-template <int APT>
+template <int APT, bool NH>
 __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L, int kmax,
                                 int nmax) {
     const int T = blockDim.x, t = threadIdx.x;
@@ -1638,7 +1638,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     double k0 = dsc->k0;
     int health = dsc->health;
     // Nose-Hoover daughters (Eq. system1 as printed): zeta from the mapped start state
-    const bool nh = dsc->thermo == 1;
+    constexpr bool nh = NH;  // the descriptor's thermo selects the instantiation
     double zt = dsc->zeta;
     const double nh_iq = nh ? 1.0 / dsc->nh_q : 0.0, nh_tgt = dsc->nh_target;
     int todo = min(steps_cap, n_steps - done);
@@ -1873,7 +1873,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 // footprint among its daughters.
 constexpr int kNlJobBytes = 128;
 
-template <int APT, int MAXT>
+template <int APT, int MAXT, bool NH>
 __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
     extern __shared__ __align__(32) char smem[];
     int32_t* job = (int32_t*)smem;
@@ -1889,7 +1889,7 @@ __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
         const NlLds L = carve_nl(smem + kNlJobBytes, n, cells, kmax);
         for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
         // run_daughter_nl synchronises before its first use of the counts
-        run_daughter_nl<APT>(d, b.max_steps, L, kmax, n);
+        run_daughter_nl<APT, NH>(d, b.max_steps, L, kmax, n);
     }
 }
 
@@ -1946,57 +1946,58 @@ size_t lds_bytes_for(int nmax, int cmax, int threads, int precision) {
     return plan_lds(nmax, cmax, precision == 0 ? sizeof(double) : sizeof(float)).total;
 }
 
-template <typename Real, int APT, int MAXT>
+template <typename Real, int APT, int MAXT, bool NH>
 static hipError_t launch_daughters_t(const BatchLaunch& b, hipStream_t s) {
     if (b.threads > MAXT) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_daughters<Real, APT, MAXT>,
+    (void)hipFuncSetAttribute((const void*)k_daughters<Real, APT, MAXT, NH>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
-    hipLaunchKernelGGL((k_daughters<Real, APT, MAXT>), dim3(b.grid), dim3(b.threads), b.lds_bytes,
-                       s, b);
+    hipLaunchKernelGGL((k_daughters<Real, APT, MAXT, NH>), dim3(b.grid), dim3(b.threads),
+                       b.lds_bytes, s, b);
     return hipGetLastError();
 }
 
-template <typename Real>
+template <typename Real, bool NH>
 static hipError_t launch_daughters_r(const BatchLaunch& b, hipStream_t s) {
     // workgroups of up to 512 threads get a 256-register budget, 1024-thread ones 128
     if (b.threads <= 512) {
         switch (b.apt) {
-            case 1: return launch_daughters_t<Real, 1, 512>(b, s);
-            case 2: return launch_daughters_t<Real, 2, 512>(b, s);
-            case 4: return launch_daughters_t<Real, 4, 512>(b, s);
+            case 1: return launch_daughters_t<Real, 1, 512, NH>(b, s);
+            case 2: return launch_daughters_t<Real, 2, 512, NH>(b, s);
+            case 4: return launch_daughters_t<Real, 4, 512, NH>(b, s);
         }
     } else {
         switch (b.apt) {
-            case 1: return launch_daughters_t<Real, 1, 1024>(b, s);
-            case 2: return launch_daughters_t<Real, 2, 1024>(b, s);
-            case 4: return launch_daughters_t<Real, 4, 1024>(b, s);
+            case 1: return launch_daughters_t<Real, 1, 1024, NH>(b, s);
+            case 2: return launch_daughters_t<Real, 2, 1024, NH>(b, s);
+            case 4: return launch_daughters_t<Real, 4, 1024, NH>(b, s);
         }
     }
     return hipErrorInvalidValue;
 }
 
-template <int APT, int MAXT>
+template <int APT, int MAXT, bool NH>
 static hipError_t launch_nl_t(const BatchLaunch& b, hipStream_t s) {
     if (b.threads > MAXT) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT>,
+    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT, NH>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
-    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT>), dim3(b.grid), dim3(b.threads), b.lds_bytes, s,
-                       b);
+    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT, NH>), dim3(b.grid), dim3(b.threads),
+                       b.lds_bytes, s, b);
     return hipGetLastError();
 }
 
+template <bool NH>
 static hipError_t launch_nl(const BatchLaunch& b, hipStream_t s) {
     if (b.threads <= 512) {
         switch (b.apt) {
-            case 1: return launch_nl_t<1, 512>(b, s);
-            case 2: return launch_nl_t<2, 512>(b, s);
-            case 4: return launch_nl_t<4, 512>(b, s);
+            case 1: return launch_nl_t<1, 512, NH>(b, s);
+            case 2: return launch_nl_t<2, 512, NH>(b, s);
+            case 4: return launch_nl_t<4, 512, NH>(b, s);
         }
     } else {
         switch (b.apt) {
-            case 1: return launch_nl_t<1, 1024>(b, s);
-            case 2: return launch_nl_t<2, 1024>(b, s);
-            case 4: return launch_nl_t<4, 1024>(b, s);
+            case 1: return launch_nl_t<1, 1024, NH>(b, s);
+            case 2: return launch_nl_t<2, 1024, NH>(b, s);
+            case 4: return launch_nl_t<4, 1024, NH>(b, s);
         }
     }
     return hipErrorInvalidValue;
@@ -2004,11 +2005,17 @@ static hipError_t launch_nl(const BatchLaunch& b, hipStream_t s) {
 
 hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.queue, 1);
+    // one instantiation per daughter thermostat: the isokinetic build does not carry the
+    // Nose-Hoover branch's registers (10% on the list form)
     if (b.variant == kVariantNeighbourList) {
         if (b.precision != 1) return hipErrorInvalidValue;
-        return launch_nl(b, s);
+        return b.thermo ? launch_nl<true>(b, s) : launch_nl<false>(b, s);
     }
-    return b.precision == 0 ? launch_daughters_r<double>(b, s) : launch_daughters_r<float>(b, s);
+    if (b.thermo)
+        return b.precision == 0 ? launch_daughters_r<double, true>(b, s)
+                                : launch_daughters_r<float, true>(b, s);
+    return b.precision == 0 ? launch_daughters_r<double, false>(b, s)
+                            : launch_daughters_r<float, false>(b, s);
 }
 
 template <typename Real, int APT>

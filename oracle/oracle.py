@@ -388,6 +388,33 @@ def ttcf_response(b, vpxy0, gamma_of, temperature: float, dt: float, n_maps: int
         dav_se_paper=b.std(axis=0, ddof=1) / np.sqrt(nd))
 
 
+def ttcf_response_modified(b, vpxy0, gamma_of, temperature: float, dt: float, n_maps: int = 4):
+    """Eq. (corr_modified): <B(0)> + int_0^t [<Omega(0)B(s)> - <Omega(0)><B(s)>] ds, the
+    averages over all daughters, the integral by the trapezoid rule on the step grid. The
+    standard error is the jackknife over start states (each left out with its n_maps mapped
+    daughters). Returns (mean, se), each of length n_t."""
+    b = np.asarray(b, np.float64)
+    nd, nt = b.shape
+    assert nd % n_maps == 0
+    ns = nd // n_maps
+    om = omega0(vpxy0, gamma_of, temperature)
+
+    def estimate(keep):
+        bb = b[keep]
+        oo = om[keep]
+        integrand = (oo[:, None] * bb).mean(axis=0) - oo.mean() * bb.mean(axis=0)
+        integ = np.concatenate([[0.0], np.cumsum(0.5 * dt * (integrand[:-1] + integrand[1:]))])
+        return bb[:, 0].mean() + integ
+
+    everyone = np.arange(nd)
+    full = estimate(everyone)
+    if ns < 2:
+        return full, np.full(nt, np.nan)
+    jack = np.array([estimate(everyone[(everyone // n_maps) != n]) for n in range(ns)])
+    se = np.sqrt((ns - 1) / ns * ((jack - jack.mean(axis=0)) ** 2).sum(axis=0))
+    return full, se
+
+
 def viscosity(response_mean, gamma_dot):
     """Eq. (visc): eta(t) = <P_xy(t)>/gamma_dot in the paper's shear-stress sign, i.e.
     -<P_xy(t)>/gamma_dot with the pressure-tensor P_xy used here."""

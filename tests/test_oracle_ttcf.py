@@ -122,3 +122,58 @@ def test_weak_field_limit_is_green_kubo(orc, ensemble):
         comb = np.hypot(se_gk[k], se_tt[k])
         assert abs(eta_tt[k] - eta_gk[k]) < 3.0 * comb, (k, eta_tt[k], eta_gk[k], comb)
     assert eta_gk[200] > 5 * se_gk[200]
+
+
+def test_modified_integrand_closed_forms(orc):
+    """Eq. (corr_modified) on synthetic series: with B the same constant for every daughter
+    the modified integrand is zero, so the estimate is B at all t, while Eq. (integrand)
+    drifts by B <Omega(0)> t when the sample's <Omega(0)> is not zero; with B linear in time
+    the estimate is the closed form of the sample covariance."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    nd, nt, dt, T = 12, 7, 0.1, 0.9
+    vp0 = rng.standard_normal(nd)
+    gam = np.full(nd, 0.3)
+    om = -(gam / T) * vp0
+    t = dt * np.arange(nt)
+    b = np.full((nd, nt), 1.7)
+    m, se = orc.ttcf_response_modified(b, vp0, gam, T, dt, n_maps=1)
+    np.testing.assert_allclose(m, 1.7, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(se, 0.0, atol=1e-14)
+    plain = orc.ttcf_response(b, vp0, gam, T, dt, n_maps=1)
+    np.testing.assert_allclose(plain.ttcf, 1.7 + 1.7 * om.mean() * t, rtol=1e-12)
+    a = rng.standard_normal(nd)
+    c = rng.standard_normal(nd)
+    b = a[:, None] + c[:, None] * t[None, :]
+    m, _ = orc.ttcf_response_modified(b, vp0, gam, T, dt, n_maps=1)
+    cov = lambda u, v: (u * v).mean() - u.mean() * v.mean()
+    exact = a.mean() + cov(om, a) * t + 0.5 * cov(om, c) * t * t
+    np.testing.assert_allclose(m, exact, rtol=1e-12, atol=1e-14)
+
+
+def test_modified_equals_plain_with_the_four_mappings(orc):
+    """With all four mappings <Omega(0)> vanishes state by state, so Eq. (corr_modified)
+    equals Eq. (integrand); the estimator is then linear in the state means, and the
+    jackknife error equals the block standard error (an identity for linear estimators).
+    Without the mappings the correction is active."""
+    s = I.System(3)
+    r, p = I.initial_state(s, 13)
+    box = orc.make_box(s.n, s.box)
+    q = orc.nh_q(s.nf, s.temperature, TAU)
+    st = orc.NHState(r.ravel().copy(), p.ravel().copy())
+    orc.nh_run(box, st, 600, 2.0, s.dt, q, s.nf)
+    ns, nst, gd = 16, 60, 0.5
+    sr, sp = orc.mother_sample(box, st, 600, ns, 50, s.temperature, s.dt, q, s.nf)
+    vp, _ = orc.run_daughters(box, sr, sp, np.repeat(np.arange(ns), 4), np.tile(np.arange(4), ns),
+                              np.full(4 * ns, gd), s.dt, nst, nthreads=8)
+    b = vp / s.volume
+    g = np.full(4 * ns, gd)
+    plain = orc.ttcf_response(b, vp[:, 0], g, s.temperature, s.dt)
+    m, se = orc.ttcf_response_modified(b, vp[:, 0], g, s.temperature, s.dt)
+    scale = np.abs(plain.g).max()
+    assert np.abs(m - plain.ttcf).max() <= 1e-12 * scale
+    np.testing.assert_allclose(se[1:], plain.ttcf_se[1:], rtol=1e-9)
+    # the unmapped daughters alone: the sample <Omega(0)> is not zero and the estimates differ
+    one = np.arange(0, 4 * ns, 4)
+    p1 = orc.ttcf_response(b[one], vp[one, 0], g[one], s.temperature, s.dt, n_maps=1)
+    m1, _ = orc.ttcf_response_modified(b[one], vp[one, 0], g[one], s.temperature, s.dt, n_maps=1)
+    assert np.abs(m1 - p1.ttcf).max() > 1e-6 * scale

@@ -143,6 +143,18 @@ int32_t ttcf_response(ttcf_ctx* ctx, int32_t observable, double gamma_dot_filter
                       double* ttcf_mean, double* ttcf_se, double* dav_mean, double* dav_se,
                       int64_t* out_n_states);
 
+/* Eq. (corr_modified): the response with the integrand <Omega(0)B(s)> - <Omega(0)><B(s)>,
+ * which corrects a finite sample whose <Omega(0)> is not zero (e.g. daughters spawned without
+ * all four mappings; with all four it equals ttcf_response's TTCF). B = P_xy. Over the
+ * healthy groups at shear rate gamma_dot_filter (> 0; they must share V/T, dt and the number
+ * of mapped daughters per group, so that every daughter weighs the same), for
+ * k = 0..n_t-1: mean[k] = <B(0)> + trapezoid integral to t_k of the modified integrand, the
+ * averages over all their daughters; se[k] = jackknife standard error over the groups (start
+ * states). Either pointer may be NULL. Errors: TTCF_EINVAL, TTCF_ESTATE (no matching group,
+ * n_t too long). */
+int32_t ttcf_response_modified(ttcf_ctx* ctx, double gamma_dot_filter, int32_t n_t, double* mean,
+                               double* se, int64_t* out_n_states);
+
 /* ---- lifetime and errors ------------------------------------------------------------ */
 
 void ttcf_destroy(ttcf_ctx* ctx);              /* NULL-safe; frees all device memory */

@@ -156,8 +156,8 @@ struct ttcf_ctx {
     double* acc_i = nullptr;
     int64_t acc_rows = 0, acc_cap = 0;
     int32_t acc_stride = 0;
-    std::vector<double> row_gamma, row_coef;
-    std::vector<int32_t> row_nt, row_health;
+    std::vector<double> row_gamma, row_coef, row_dt;
+    std::vector<int32_t> row_nt, row_health, row_maps;  // row_maps: daughters in the group
     double* d_row_gamma = nullptr;
     double* d_row_coef = nullptr;
     int32_t* d_row_health = nullptr;
@@ -1432,6 +1432,8 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
         for (size_t q = 0; q < which.size(); ++q) {
             const DaughterDesc& d0 = c->descs[ready[which[q]].first];
             c->row_gamma.push_back(d0.gamma_dot);
+            c->row_dt.push_back(d0.sys.dt);
+            c->row_maps.push_back((int32_t)(ready[which[q]].second - ready[which[q]].first));
             c->row_coef.push_back(d0.sys.volume * d0.gamma_dot /
                                   c->mothers[c->batches[c->live[ready[which[q]].first].batch].mother]
                                       .sys.temperature);
@@ -1751,6 +1753,8 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     for (int64_t r = 0; r < reserve; ++r) {
         const DaughterDesc& d0 = hd[(size_t)(r % n_states) * nm];
         c->row_gamma.push_back(d0.gamma_dot);
+        c->row_dt.push_back(d0.sys.dt);
+        c->row_maps.push_back(nm);
         c->row_coef.push_back(d0.sys.volume * d0.gamma_dot / m.sys.temperature);
         c->row_nt.push_back(n_t);
         c->row_health.push_back(kRowPending);
@@ -1778,6 +1782,8 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
         hipStreamSynchronize(c->stream) != hipSuccess) {
         c->acc_rows = row0;
         c->row_gamma.resize(row0);
+        c->row_dt.resize(row0);
+        c->row_maps.resize(row0);
         c->row_coef.resize(row0);
         c->row_nt.resize(row0);
         c->row_health.resize(row0);
@@ -1801,6 +1807,8 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     auto undo_rows = [&]() {
         c->acc_rows = row0;
         c->row_gamma.resize(row0);
+        c->row_dt.resize(row0);
+        c->row_maps.resize(row0);
         c->row_coef.resize(row0);
         c->row_nt.resize(row0);
         c->row_health.resize(row0);
@@ -1864,6 +1872,50 @@ void ttcf_graph_destroy(ttcf_graph* g) {
     auto it = std::find(c->graphs.begin(), c->graphs.end(), g);
     if (it != c->graphs.end()) c->graphs.erase(it);
     free_graph(g);
+}
+
+int32_t ttcf_response_modified(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, double* mean,
+                               double* se, int64_t* out_n_states) {
+    if (!c || !(gamma_dot_filter > 0.0) || n_t <= 0) return TTCF_EINVAL;
+    int32_t rc = refresh_row_health(c);
+    if (rc != TTCF_OK) return rc;
+    std::vector<int32_t> rows;
+    for (int64_t r = 0; r < c->acc_rows; ++r)
+        if (c->row_gamma[r] == gamma_dot_filter && c->row_health[r] == 0) rows.push_back((int32_t)r);
+    if (rows.empty()) return fail(c, TTCF_ESTATE, "no accumulated group matches the filter");
+    for (int32_t r : rows) {
+        if (c->row_nt[r] < n_t) return fail(c, TTCF_ESTATE, "n_t exceeds a matching group's length");
+        if (c->row_coef[r] != c->row_coef[rows[0]] || c->row_dt[r] != c->row_dt[rows[0]] ||
+            c->row_maps[r] != c->row_maps[rows[0]])
+            return fail(c, TTCF_EINVAL, "matching groups differ in V/T, dt or mapping count");
+    }
+    Scratch sc(c->stream);
+    int32_t* d_rows = sc.get<int32_t>(rows.size());
+    double* d_j = sc.get<double>(rows.size() * (size_t)n_t);
+    double* d_out = sc.get<double>(2 * (size_t)n_t);
+    if (!d_rows || !d_j || !d_out) return fail(c, TTCF_ENOMEM, "response scratch allocation failed");
+    HIPCHECK(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(),
+                               hipMemcpyHostToDevice, c->stream));
+    ModifiedLaunch A{};
+    A.d_all = c->acc_d;
+    A.i_all = c->acc_i;
+    A.stride = c->acc_stride;
+    A.rows = d_rows;
+    A.n_rows = (int32_t)rows.size();
+    A.n_t = n_t;
+    A.coef = c->row_coef[rows[0]];
+    A.dt = c->row_dt[rows[0]];
+    A.j_rows = d_j;
+    A.out = d_out;
+    HIPCHECK(c, launch_response_modified(A, c->stream));
+    std::vector<double> out(2 * (size_t)n_t);
+    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * 2 * n_t, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    if (mean) std::memcpy(mean, out.data(), sizeof(double) * n_t);
+    if (se) std::memcpy(se, out.data() + n_t, sizeof(double) * n_t);
+    if (out_n_states) *out_n_states = (int64_t)rows.size();
+    return TTCF_OK;
 }
 
 // live daughters are kept in increasing id order (spawned in order, removed in place)

@@ -218,6 +218,19 @@ hipError_t launch_desc_zeta(DaughterDesc* descs, const double* zeta, const int32
 hipError_t launch_acf(const double* x, int64_t n, int32_t max_lag, double threshold,
                       double* scratch, double* acf, int32_t* first_below, double* tau_int,
                       hipStream_t s);
+// Eq. (corr_modified) over selected accumulator rows sharing coef and dt (ttcf_estimators.hip)
+struct ModifiedLaunch {
+    const double* d_all;   // accumulator rows: D_n(t), I_n(t), row stride `stride`
+    const double* i_all;
+    int32_t stride;
+    const int32_t* rows;   // selected rows
+    int32_t n_rows, n_t;
+    double coef;           // V gamma_dot / T of every selected row
+    double dt;             // time step of every selected row
+    double* j_rows;        // n_rows x n_t scratch
+    double* out;           // [0, n_t): estimate, [n_t, 2 n_t): jackknife standard error
+};
+hipError_t launch_response_modified(const ModifiedLaunch& a, hipStream_t s);
 // *counter += 1 (one thread)
 hipError_t launch_increment(int32_t* counter, hipStream_t s);
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s);

@@ -139,6 +139,7 @@ def lib():
         "ttcf_export_states": [V, C.c_int32, C.c_int32, D, D],
         "ttcf_import_states_zeta": [V, C.c_int32, C.c_int32, D],
         "ttcf_acf": [V, D, C.c_int64, C.c_int32, C.c_double, D, I, D],
+        "ttcf_response_modified": [V, C.c_double, C.c_int32, D, D, L64],
         "ttcf_mother_acf": [V, C.c_int32, C.c_int32, C.c_double, D, I, D],
         "ttcf_export_states_zeta": [V, C.c_int32, C.c_int32, D],
         "ttcf_export_mother": [V, C.c_int32, D, D, D, L64],
@@ -228,7 +229,8 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_channel_debug_forces", "ttcf_channel_step_timing", "ttcf_autotune",
             "ttcf_autotune_export", "ttcf_autotune_import", "ttcf_graph_create",
             "ttcf_graph_launch", "ttcf_graph_replays", "ttcf_graph_destroy",
-            "ttcf_import_states_zeta", "ttcf_export_states_zeta", "ttcf_acf", "ttcf_mother_acf"]
+            "ttcf_import_states_zeta", "ttcf_export_states_zeta", "ttcf_acf", "ttcf_mother_acf",
+            "ttcf_response_modified"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -404,6 +406,16 @@ class Context:
                                    *[_dp(o) for o in out], C.byref(used)), "ttcf_response",
                self._ctx)
         return out[0], out[1], out[2], out[3], used.value
+
+    def ttcf_response_modified(self, n_t: int, gamma_dot_filter: float):
+        """Eq. (corr_modified): (mean, jackknife se, n_states)."""
+        m = np.zeros(n_t)
+        se = np.zeros(n_t)
+        used = C.c_int64(0)
+        _check(lib().ttcf_response_modified(self._ctx, float(gamma_dot_filter), int(n_t), _dp(m),
+                                            _dp(se), C.byref(used)), "ttcf_response_modified",
+               self._ctx)
+        return m, se, used.value
 
     # ---- inspection hooks
     def ttcf_sample_states(self, mother: int, n_states: int, steps_between: int):

@@ -386,6 +386,41 @@ def test_config1_ttcf_matches_oracle(T, orc, cfg1, precision):
     assert np.all(np.abs(dm - oref.dav) <= 2.0 * np.hypot(dse, oref.dav_se) + 1e-15)
 
 
+@pytest.mark.parametrize("mask", [0xF, 0x5, 0x1, 0x3])
+def test_modified_integrand_matches_oracle(T, orc, cfg1, mask):
+    """Eq. (corr_modified) from the accumulator rows against the oracle's definition and
+    jackknife on its own daughters (FP64 forces). Where a state's mappings hold as many
+    Omega-keeping (0, 1) as Omega-reversing (2, 3) ones, <Omega(0)> vanishes state by state
+    and it equals the plain estimate; otherwise (mappings {0} or {0, 1}) the sample
+    <Omega(0)> is not zero and the correction acts."""
+    s, box, sr, sp = cfg1
+    nst, gd = 100, 1e-2
+    maps = [m for m in range(4) if mask >> m & 1]
+    say(f"modified integrand, mappings {maps}")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 0), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        ctx.ttcf_spawn_daughters(mid, 8, 0, gd, nst, mapping_mask=mask)
+        ctx.ttcf_step(nst)
+        assert ctx.ttcf_accumulate() == 8
+        mm, mse, used = ctx.ttcf_response_modified(nst + 1, gd)
+        tm, tse, _, _, _ = ctx.ttcf_response(nst + 1, gd)
+    assert used == 8
+    nm = len(maps)
+    vo, _ = orc.run_daughters(box, sr, sp, np.repeat(np.arange(8), nm), np.tile(maps, 8),
+                              np.full(8 * nm, gd), s.dt, nst, nthreads=8)
+    om, ose = orc.ttcf_response_modified(vo / s.volume, vo[:, 0], np.full(8 * nm, gd),
+                                         s.temperature, s.dt, n_maps=nm)
+    scale = np.abs(vo / s.volume).max()
+    assert np.abs(mm - om).max() <= 1e-7 * scale
+    np.testing.assert_allclose(mse[1:], ose[1:], rtol=1e-5, atol=1e-9 * scale)
+    if sum(m < 2 for m in maps) == sum(m >= 2 for m in maps):
+        assert np.abs(mm - tm).max() <= 1e-12 * scale
+        np.testing.assert_allclose(mse[1:], tse[1:], rtol=1e-8)
+    else:
+        assert np.abs(mm - tm).max() > 1e-6 * scale
+
+
 def oracle_group_response(orc, s, box, sr, sp, states, gd, nst):
     """The oracle's own four mapped daughters of each listed start state, through its
     estimator."""

@@ -395,6 +395,12 @@ def cv_leg(T, stream, gd=1e-4, nst=200, train_states=4096, eval_states=4096, epo
     k = np.arange(1, nst + 1)
     gain = (pse[k] * np.sqrt(t_plain)) / (se_cv[k] * np.sqrt(t_cv))
     vr = (pse[k] / se_cv[k]) ** 2
+    # with the fixed costs (training, calibration, mean term) spread over many more
+    # evaluation daughters and the mean term's error made small: the per-daughter variance
+    # ratio over the marginal cost ratio of a daughter with the control variate attached
+    vr_pd = (pse[k] / cse[k]) ** 2
+    marginal = (t_plain + timings["attach_s"]) / t_plain
+    asym = np.sqrt(vr_pd / marginal)
     bias_bound = 2.0 * (pse + cse + mu_se)
     out = {
         "workload": f"WCA N={s.n}, rho={s.density}, T={s.temperature}, gamma_dot={gd}, "
@@ -405,6 +411,10 @@ def cv_leg(T, stream, gd=1e-4, nst=200, train_states=4096, eval_states=4096, epo
         "gain_median": float(np.median(gain)),
         "gain_at_10_steps": float(gain[9]),
         "variance_ratio_at_steps": {str(j): float(vr[j - 1]) for j in (1, 10, 50, 100, nst)},
+        "per_daughter_variance_ratio_at_steps": {str(j): float(vr_pd[j - 1])
+                                                  for j in (1, 10, 50, 100, nst)},
+        "marginal_cost_ratio": float(marginal),
+        "asymptotic_gain_at_steps": {str(j): float(asym[j - 1]) for j in (1, 10, 50, 100, nst)},
         "fom_plain_t_end": float(pse[-1] * np.sqrt(t_plain)),
         "fom_cv_t_end": float(se_cv[-1] * np.sqrt(t_cv)),
         "gpu_s_plain": t_plain, "gpu_s_cv": t_cv,

@@ -156,16 +156,20 @@ __device__ inline ChLds ch_carve(char* base, int nmax, int cmax) {
     return L;
 }
 
-// per-workgroup global scratch: fixed-point positions, lists, list lengths, path lengths
+// Per-workgroup global scratch: fixed-point positions in atom order and in list-grid order,
+// lists, list lengths, path lengths. Lists and list lengths are indexed by list-grid slot
+// (the position of the atom in the counting sort) and hold slots, so that the force pass
+// walks the atoms cell by cell and a wave's gathers stay in a few neighbouring cells.
 struct ChScratch {
-    uint4* posq;       // [n]  (X, Y, Z, type: 0 fluid, 1 bottom wall, 2 top wall)
-    uint16_t* nbr;     // [(kmax + 1) n], row kmax is a sink for rejected candidates
-    uint16_t* ncnt;    // [n]
-    float* path;       // [n]
+    uint4* posq;       // [n] by atom  (X, Y, Z, type: 0 fluid, 1 bottom wall, 2 top wall)
+    uint4* posq_s;     // [n] by slot: posq_s[i] = posq[sid[i]]
+    uint16_t* nbr;     // [(kmax + 1) n] by slot, row kmax is a sink for rejected candidates
+    uint16_t* ncnt;    // [n] by slot
+    float* path;       // [n] by atom
 };
 
 __host__ __device__ inline size_t ch_scratch_bytes(int nmax, int kmax) {
-    return ch_align(16 * (size_t)nmax, 256) + ch_align(2 * ((size_t)kmax + 1) * nmax, 256) +
+    return 2 * ch_align(16 * (size_t)nmax, 256) + ch_align(2 * ((size_t)kmax + 1) * nmax, 256) +
            ch_align(2 * (size_t)nmax, 256) + ch_align(4 * (size_t)nmax, 256);
 }
 
@@ -173,6 +177,8 @@ __device__ inline ChScratch ch_scratch(char* base, int nmax, int kmax) {
     ChScratch s;
     size_t off = 0;
     s.posq = (uint4*)(base + off);
+    off += ch_align(16 * (size_t)nmax, 256);
+    s.posq_s = (uint4*)(base + off);
     off += ch_align(16 * (size_t)nmax, 256);
     s.nbr = (uint16_t*)(base + off);
     off += ch_align(2 * ((size_t)kmax + 1) * nmax, 256);
@@ -197,6 +203,12 @@ __device__ void ch_publish(const ChannelDev& S, const double* r, const ChScratch
         G.posq[a] = make_uint4(fixp(r[a], S.fix_scale[0]), fixp(yc, S.fix_scale[1]),
                                fixp(r[2 * n + a], S.fix_scale[2]), atom_type(S, a));
     }
+}
+
+// positions in list-grid order for the slots of the last list build (sid stays in LDS)
+__device__ __forceinline__ void ch_gather_sorted(const ChannelDev& S, const ChScratch& G,
+                                                 const ChLds& L) {
+    for (int i = threadIdx.x; i < S.n; i += blockDim.x) G.posq_s[i] = G.posq[L.sid[i]];
 }
 
 __device__ __forceinline__ void ch_sep(const uint4& qa, const uint4& qb, const ChannelDev& S,
@@ -245,33 +257,33 @@ __device__ void ch_rebuild(const ChannelDev& S, const ChScratch& G, const ChLds&
         }
     }
     __syncthreads();
+    ch_gather_sorted(S, G, L);
+    for (int a = t; a < n; a += T) G.path[a] = 0.f;
+    __syncthreads();
     const float rl2 = S.rl2_f;
     const int kmax = S.kmax;
     bool over = false;
-    for (int a = t; a < n; a += T) {
-        const uint4 qa = G.posq[a];
+    for (int i = t; i < n; i += T) {
+        const uint4 qa = G.posq_s[i];
         const int cx = cell_of(qa.x, nc0), cy = cell_of(qa.y, nc1), cz = cell_of(qa.z, nc2);
         const bool wall_a = qa.w != 0u;
         int count = 0;
-        int slot = a;
-        const int sink = kmax * n + a;
+        int slot = i;
+        const int sink = kmax * n + i;
         auto scan = [&](int lo, int hi) {
             for (int tt = lo; tt < hi; tt += 2) {
                 int jn[2];
                 uint4 q[2];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int raw = L.sid[tt + u];
-                    jn[u] = tt + u < hi ? raw : a;
-                }
+                for (int u = 0; u < 2; ++u) jn[u] = tt + u < hi ? tt + u : i;
 #pragma unroll
-                for (int u = 0; u < 2; ++u) q[u] = G.posq[jn[u]];
+                for (int u = 0; u < 2; ++u) q[u] = G.posq_s[jn[u]];
 #pragma unroll
                 for (int u = 0; u < 2; ++u) {
                     float dx, dy, dz;
                     ch_sep(qa, q[u], S, dx, dy, dz);
                     const bool both_wall = wall_a & (q[u].w != 0u);
-                    const bool hit = (jn[u] != a) & !both_wall &
+                    const bool hit = (jn[u] != i) & !both_wall &
                                      (dx * dx + dy * dy + dz * dz < rl2);
                     const bool room = hit & (count < kmax);
                     G.nbr[room ? slot : sink] = (uint16_t)jn[u];
@@ -298,32 +310,33 @@ __device__ void ch_rebuild(const ChannelDev& S, const ChScratch& G, const ChLds&
             over = true;
             count = kmax;
         }
-        G.ncnt[a] = (uint16_t)count;
-        G.path[a] = 0.f;
+        G.ncnt[i] = (uint16_t)count;
     }
     if (over) L.misc[1] = 1;
     __syncthreads();
 }
 
-// Forces (LJ through the lists in FP32, tethers in FP64, the sum rounded once to FP32).
-// Partial sums of this thread: [0] x force on fluid from the top wall, [1] from the bottom
-// wall, [2] S = sum_top dx - sum_bottom dx of the tether extensions.
+// Forces (LJ through the lists in FP32, tethers in FP64, the sum rounded once to FP32),
+// walked in list-grid order: positions come from posq_s (filled for this step), forces go
+// to the atom's own index. Partial sums of this thread: [0] x force on fluid from the top
+// wall, [1] from the bottom wall, [2] S = sum_top dx - sum_bottom dx of the tether extensions.
 __device__ void ch_forces(const ChannelDev& S, const double* r, float* f, const double* latx,
                           const double* laty, const double* latz, double v, int64_t k,
-                          const ChScratch& G, double (&part)[3]) {
+                          const ChScratch& G, const ChLds& L, double (&part)[3]) {
     const int n = S.n, nf = S.n_fluid;
     const float rc2 = S.rc2_f;
     const float cff = (float)S.c_ff, cwf = (float)S.c_wf;
     const double shift = 0.5 * v * ((double)k * S.dt);
     part[0] = part[1] = part[2] = 0.0;
-    for (int a = threadIdx.x; a < n; a += blockDim.x) {
-        const uint4 qa = G.posq[a];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int a = L.sid[i];
+        const uint4 qa = G.posq_s[i];
         const bool fluid_a = qa.w == 0u;
-        const int cnt = G.ncnt[a];
+        const int cnt = G.ncnt[i];
         float gx = 0.f, gy = 0.f, gz = 0.f, wt = 0.f, wb = 0.f;
         for (int kk = 0; kk < cnt; ++kk) {
-            const int j = G.nbr[kk * n + a];
-            const uint4 qb = G.posq[j];
+            const int j = G.nbr[kk * n + i];
+            const uint4 qb = G.posq_s[j];
             float dx, dy, dz;
             ch_sep(qa, qb, S, dx, dy, dz);
             const float r2 = dx * dx + dy * dy + dz * dz;
@@ -401,7 +414,7 @@ __device__ void run_channel(ChannelDesc* d, int steps_cap, const ChScratch& G, c
     if (done == 0) {
         // forces, S(0), sum of wall p^2 and the observables of the start state
         double part[3];
-        ch_forces(S, r, f, d->latx, d->laty, d->latz, v, k, G, part);
+        ch_forces(S, r, f, d->latx, d->laty, d->latz, v, k, G, L, part);
         double w2 = 0.0;
         for (int b = t; b < S.n_bins; b += T) L.bins[b] = 0ull;
         __syncthreads();
@@ -463,9 +476,12 @@ __device__ void run_channel(ChannelDesc* d, int steps_cap, const ChScratch& G, c
                 health |= kHealthListOverflow;
                 break;
             }
+        } else {
+            ch_gather_sorted(S, G, L);
+            __syncthreads();
         }
         double part[3];
-        ch_forces(S, r, f, d->latx, d->laty, d->latz, v, k, G, part);
+        ch_forces(S, r, f, d->latx, d->laty, d->latz, v, k, G, L, part);
         for (int b = t; b < S.n_bins; b += T) L.bins[b] = 0ull;
         __syncthreads();
         // half kick, thermostat half step, observables
@@ -663,7 +679,7 @@ __global__ __launch_bounds__(kChThreads) void k_channel_debug_forces(ChannelLaun
     __syncthreads();
     ch_rebuild(S, G, L);
     double part[3];
-    ch_forces(S, d.r, d.f, d.latx, d.laty, d.latz, d.v, d.k, G, part);
+    ch_forces(S, d.r, d.f, d.latx, d.laty, d.latz, d.v, d.k, G, L, part);
     ch_block_sum<3>(part, L.red);
     if (threadIdx.x == 0) {
         out[0] = part[0];

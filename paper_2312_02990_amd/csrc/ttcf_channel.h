@@ -8,7 +8,7 @@
 
 namespace ttcf {
 
-constexpr int kChThreads = 512;  // loops over atoms
+constexpr int kChThreads = 1024;  // loops over atoms
 constexpr int kChWavesPerSimd = 4;  // register budget of the step kernel: 128 VGPRs per lane
 constexpr int kChMaxWaves = kChThreads / 64;
 constexpr int kChRed = 4;          // doubles per block reduction
@@ -59,10 +59,11 @@ struct ChannelLaunch {
 struct ChannelAccum {
     const ChannelDesc* descs;  // the groups' daughters, consecutive
     const int32_t* first_of;   // n_groups + 1
-    double* d_out;             // n_groups x n_t x n_obs
+    double* d_out;             // n_groups rows of row_stride doubles, each n_t x n_obs used
     double* i_out;
     int32_t n_groups, n_t, n_obs;
     double dt;
+    size_t row_stride;         // >= n_t * n_obs
 };
 
 struct ChannelResponse {

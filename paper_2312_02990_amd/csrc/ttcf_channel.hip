@@ -19,6 +19,8 @@ namespace ttcf {
 namespace {
 
 constexpr double kProfileScale = 1099511627776.0;  // 2^40: fixed point of the profile sums
+constexpr int kChUnroll = 8;                         // list entries per trip of the force loop
+constexpr int kChScanUnroll = 8;                     // candidates per trip of the list build
 
 __device__ __forceinline__ uint32_t fixp(double v, double scale) {
     return (uint32_t)(int64_t)rint(v * scale);
@@ -271,15 +273,15 @@ __device__ void ch_rebuild(const ChannelDev& S, const ChScratch& G, const ChLds&
         int slot = i;
         const int sink = kmax * n + i;
         auto scan = [&](int lo, int hi) {
-            for (int tt = lo; tt < hi; tt += 2) {
-                int jn[2];
-                uint4 q[2];
+            for (int tt = lo; tt < hi; tt += kChScanUnroll) {
+                int jn[kChScanUnroll];
+                uint4 q[kChScanUnroll];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) jn[u] = tt + u < hi ? tt + u : i;
+                for (int u = 0; u < kChScanUnroll; ++u) jn[u] = tt + u < hi ? tt + u : i;
 #pragma unroll
-                for (int u = 0; u < 2; ++u) q[u] = G.posq_s[jn[u]];
+                for (int u = 0; u < kChScanUnroll; ++u) q[u] = G.posq_s[jn[u]];
 #pragma unroll
-                for (int u = 0; u < 2; ++u) {
+                for (int u = 0; u < kChScanUnroll; ++u) {
                     float dx, dy, dz;
                     ch_sep(qa, q[u], S, dx, dy, dz);
                     const bool both_wall = wall_a & (q[u].w != 0u);
@@ -334,21 +336,31 @@ __device__ void ch_forces(const ChannelDev& S, const double* r, float* f, const 
         const bool fluid_a = qa.w == 0u;
         const int cnt = G.ncnt[i];
         float gx = 0.f, gy = 0.f, gz = 0.f, wt = 0.f, wb = 0.f;
-        for (int kk = 0; kk < cnt; ++kk) {
-            const int j = G.nbr[kk * n + i];
-            const uint4 qb = G.posq_s[j];
-            float dx, dy, dz;
-            ch_sep(qa, qb, S, dx, dy, dz);
-            const float r2 = dx * dx + dy * dy + dz * dz;
-            const float cw = (fluid_a & (qb.w == 0u)) ? cff : cwf;
-            const float inv = 1.0f / r2;
-            const float s3 = inv * inv * inv;
-            const float fs = r2 < rc2 ? s3 * (48.f * s3 - 24.f * cw) * inv : 0.f;
-            gx += fs * dx;
-            gy += fs * dy;
-            gz += fs * dz;
-            wt += (fluid_a & (qb.w == 2u)) ? fs * dx : 0.f;
-            wb += (fluid_a & (qb.w == 1u)) ? fs * dx : 0.f;
+        // kChUnroll list entries per trip: their index loads, then their position gathers, are
+        // issued together; entries past the list length read row 0 and add nothing
+        for (int kk = 0; kk < cnt; kk += kChUnroll) {
+            int j[kChUnroll];
+            uint4 qb[kChUnroll];
+#pragma unroll
+            for (int u = 0; u < kChUnroll; ++u) j[u] = G.nbr[(kk + u < cnt ? kk + u : 0) * n + i];
+#pragma unroll
+            for (int u = 0; u < kChUnroll; ++u) qb[u] = G.posq_s[j[u]];
+#pragma unroll
+            for (int u = 0; u < kChUnroll; ++u) {
+                float dx, dy, dz;
+                ch_sep(qa, qb[u], S, dx, dy, dz);
+                const float r2 = dx * dx + dy * dy + dz * dz;
+                const float cw = (fluid_a & (qb[u].w == 0u)) ? cff : cwf;
+                const float inv = 1.0f / r2;
+                const float s3 = inv * inv * inv;
+                const bool in = (kk + u < cnt) & (r2 < rc2);
+                const float fs = in ? s3 * (48.f * s3 - 24.f * cw) * inv : 0.f;
+                gx += fs * dx;
+                gy += fs * dy;
+                gz += fs * dz;
+                wt += (fluid_a & (qb[u].w == 2u)) ? fs * dx : 0.f;
+                wb += (fluid_a & (qb[u].w == 1u)) ? fs * dx : 0.f;
+            }
         }
         if (fluid_a) {
             f[a] = gx;
@@ -601,8 +613,8 @@ __global__ void k_channel_accumulate(ChannelAccum a) {
         comp[m] = 0.0;
     }
     const double inm = 1.0 / (double)nm;
-    double* dout = a.d_out + (size_t)g * a.n_t * a.n_obs;
-    double* iout = a.i_out + (size_t)g * a.n_t * a.n_obs;
+    double* dout = a.d_out + (size_t)g * a.row_stride;
+    double* iout = a.i_out + (size_t)g * a.row_stride;
     double d0 = 0.0;
     for (int m = 0; m < nm; ++m) d0 += prev[m];
     dout[o] = d0 * inm;

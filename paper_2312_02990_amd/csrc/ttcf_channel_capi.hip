@@ -548,20 +548,19 @@ int32_t ttcf_channel_accumulate(ttcf_channel_ctx* c, int64_t* out_groups) {
         if (!d_first) return cfail(c, TTCF_ENOMEM, "allocation failed");
         CHK(c, hipMemcpyAsync(d_first, first_of.data(), sizeof(int32_t) * first_of.size(),
                               hipMemcpyHostToDevice, c->stream));
+        // one thread per (group, observable), every group's row at the context's stride
         const size_t row = (size_t)c->acc_nt * nobs;
-        // rows are written at the context's stride one group at a time when it differs
-        for (int32_t g = 0; g < b.n_states; ++g) {
-            ChannelAccum A{};
-            A.descs = b.d_descs;
-            A.first_of = d_first + g;
-            A.d_out = c->acc_d + row * (size_t)(c->acc_rows + g);
-            A.i_out = c->acc_i + row * (size_t)(c->acc_rows + g);
-            A.n_groups = 1;
-            A.n_t = n_t;
-            A.n_obs = nobs;
-            A.dt = c->dev.dt;
-            CHK(c, launch_channel_accumulate(A, c->stream));
-        }
+        ChannelAccum A{};
+        A.descs = b.d_descs;
+        A.first_of = d_first;
+        A.d_out = c->acc_d + row * (size_t)c->acc_rows;
+        A.i_out = c->acc_i + row * (size_t)c->acc_rows;
+        A.n_groups = b.n_states;
+        A.n_t = n_t;
+        A.n_obs = nobs;
+        A.dt = c->dev.dt;
+        A.row_stride = row;
+        CHK(c, launch_channel_accumulate(A, c->stream));
         CHK(c, hipStreamSynchronize(c->stream));
         rt_free(d_first);
         for (int32_t g = 0; g < b.n_states; ++g) {

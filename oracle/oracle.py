@@ -95,9 +95,14 @@ def _load():
         lib.orc_run_daughters_nh.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double, D,
                                              D, D, C.c_int32, I, I, D, C.c_int64, C.c_int32, D, D,
                                              D]
+        lib.orc_observables.argtypes = [B, C.c_double, D, D, C.c_int32, D]
+        lib.orc_run_daughters_obs.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double,
+                                              D, D, D, C.c_int32, I, I, D, C.c_int64, C.c_int32,
+                                              D, C.c_int32, D]
         for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
                    "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
-                   "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh"):
+                   "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh",
+                   "orc_observables", "orc_run_daughters_obs"):
             getattr(lib, fn).restype = C.c_int32
         _lib = lib
     return _lib
@@ -274,6 +279,48 @@ def run_daughters_nh(box: Box, states_r, states_p, states_zeta, state_of, map_of
     if final_state:
         return out, ro, po, used
     return out, used
+
+
+N_SLABS = 8  # slabs of the bulk momentum profile
+
+
+def observables(box: Box, r, p, dxle: float = 0.0, n_slabs: int = N_SLABS) -> np.ndarray:
+    """Observables beyond P_xy (orc_observables): [P_xx - P_yy, P_yy - P_zz, (K + U)/N,
+    then per y slab the summed p_x over the slab volume], length 3 + n_slabs."""
+    r = _f64(r)
+    p = _f64(p)
+    out = np.zeros(3 + n_slabs)
+    rc = _load().orc_observables(C.byref(box), float(dxle), _dp(r), _dp(p), int(n_slabs),
+                                 _dp(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_observables failed: {rc}")
+    return out
+
+
+def run_daughters_obs(box: Box, states_r, states_p, state_of, map_of, gamma_of, dt: float,
+                      nsteps: int, states_zeta=None, temperature: float = 0.0, q: float = 0.0,
+                      nf: float = 0.0, n_slabs: int = N_SLABS, nthreads: int = 0):
+    """Daughters (GIK, or Nose-Hoover when states_zeta is given) that also record the
+    observables of `observables` after every step. Returns vpxy (n_d, nsteps+1) and
+    obs (n_d, nsteps+1, 3+n_slabs)."""
+    states_r = _f64(states_r)
+    states_p = _f64(states_p)
+    zeta = _f64(states_zeta) if states_zeta is not None else None
+    state_of = np.ascontiguousarray(state_of, np.int32)
+    map_of = np.ascontiguousarray(map_of, np.int32)
+    gamma_of = _f64(gamma_of)
+    nd = len(state_of)
+    vp = np.zeros((nd, nsteps + 1))
+    ob = np.zeros((nd, nsteps + 1, 3 + n_slabs))
+    if nthreads <= 0:
+        nthreads = os.cpu_count() or 1
+    used = _load().orc_run_daughters_obs(C.byref(box), float(dt), float(temperature), float(q),
+                                         float(nf), _dp(states_r), _dp(states_p), _dp(zeta), nd,
+                                         _ip(state_of), _ip(map_of), _dp(gamma_of), int(nsteps),
+                                         int(nthreads), _dp(vp), int(n_slabs), _dp(ob))
+    if used < 0:
+        raise RuntimeError(f"orc_run_daughters_obs failed: {used}")
+    return vp, ob
 
 
 def sllod_run(box: Box, r, p, gamma_dot: float, dt: float, nsteps: int, gik: bool = True,

@@ -365,6 +365,81 @@ double orc_vpxy(const orc_box* b, double dxle, const double* r, const double* p)
     return sum_pxpy(b->n, p) + out[1];
 }
 
+/* The pair parts of the pressure tensor's diagonal and the potential energy, for
+ * orc_observables. Each unordered pair is visited twice, so each visit adds half. */
+typedef struct {
+    const orc_box* b;
+    double dxle;
+    const double* r;
+    double rc2;
+    double w[3];
+    double u;
+} obs_ctx;
+
+static void obs_visit(void* vctx, int32_t i, int32_t j) {
+    obs_ctx* c = (obs_ctx*)vctx;
+    const int32_t n = c->b->n;
+    const double* r = c->r;
+    double d[3];
+    min_image(c->b, c->dxle, r[i], r[n + i], r[2 * n + i], r[j], r[n + j], r[2 * n + j], d);
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 < c->rc2) {
+        double fs, phi;
+        pair_eval(c->b, r2, &fs, &phi);
+        for (int a = 0; a < 3; ++a) c->w[a] += 0.5 * (d[a] * (fs * d[a]));
+        c->u += 0.5 * phi;
+    }
+}
+
+int32_t orc_observables(const orc_box* b, double dxle, const double* r, const double* p,
+                        int32_t n_slabs, double* out) {
+    int32_t d[3];
+    if (n_slabs < 1 || orc_cell_dims(b, d) != 0) return -1;
+    const int32_t n = b->n;
+    const int32_t ncell = d[0] * d[1] * d[2];
+    int32_t* cell_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* start = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncell + 1));
+    double* slab = (double*)calloc((size_t)n_slabs, sizeof(double));
+    if (!cell_of || !order || !start || !slab) {
+        free(cell_of);
+        free(order);
+        free(start);
+        free(slab);
+        return -2;
+    }
+    orc_cell_list(b, r, cell_of, order, start);
+    obs_ctx c;
+    c.b = b;
+    c.dxle = dxle;
+    c.r = r;
+    c.rc2 = b->rc * b->rc;
+    c.w[0] = c.w[1] = c.w[2] = 0.0;
+    c.u = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for_each_candidate(b, dxle, d, cell_of, order, start, i, b->rc, obs_visit, &c);
+    /* kinetic parts: sum_i p_a p_a (m = 1) */
+    double kk[3] = {0.0, 0.0, 0.0};
+    for (int32_t a = 0; a < 3; ++a)
+        for (int32_t i = 0; i < n; ++i) kk[a] += p[a * n + i] * p[a * n + i];
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t s = (int32_t)floor(r[n + i] * ((double)n_slabs / b->ly));
+        if (s < 0) s = 0;
+        if (s > n_slabs - 1) s = n_slabs - 1;
+        slab[s] += p[i];
+    }
+    const double vol = b->lx * b->ly * b->lz;
+    out[0] = ((kk[0] + c.w[0]) - (kk[1] + c.w[1])) / vol;
+    out[1] = ((kk[1] + c.w[1]) - (kk[2] + c.w[2])) / vol;
+    out[2] = (0.5 * (kk[0] + kk[1] + kk[2]) + c.u) / (double)n;
+    for (int32_t s = 0; s < n_slabs; ++s) out[3 + s] = slab[s] / (vol / (double)n_slabs);
+    free(cell_of);
+    free(order);
+    free(start);
+    free(slab);
+    return 0;
+}
+
 void orc_map(const orc_box* b, int32_t m, const double* r, const double* p, double* r_out,
              double* p_out) {
     const int32_t n = b->n;
@@ -559,10 +634,11 @@ void orc_iso_shear(int32_t n, double* p, double gamma_dot, double tau) {
  * Each constrained part keeps p.p fixed, so the step is second order, time reversible and
  * isokinetic; a final rescale to K0 only removes round-off drift (its factor is 1 to
  * within a few ulps). gik = 0 gives the adiabatic SLLOD step (no multiplier). */
-int32_t orc_sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik, double k0,
-                      double* r, double* p, int64_t* kstep, int64_t nsteps, double* vpxy_out,
-                      double* ke_out, double* pe_out) {
+static int32_t sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik, double k0,
+                         double* r, double* p, int64_t* kstep, int64_t nsteps, double* vpxy_out,
+                         double* ke_out, double* pe_out, int32_t n_slabs, double* obs_out) {
     const int32_t n = b->n;
+    const size_t nobs = 3 + (size_t)(n_slabs > 0 ? n_slabs : 0);
     double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
     if (!f) return -2;
     double* x = r;
@@ -583,6 +659,7 @@ int32_t orc_sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik
     if (vpxy_out) vpxy_out[0] = sum_pxpy(n, p) + out[1];
     if (ke_out) ke_out[0] = kinetic(n, p);
     if (pe_out) pe_out[0] = out[0];
+    if (obs_out) orc_observables(b, dxle, r, p, n_slabs, obs_out);
     for (int64_t s = 1; s <= nsteps; ++s) {
         if (gik) {
             orc_iso_shear(n, p, gamma_dot, 0.5 * h);
@@ -612,10 +689,18 @@ int32_t orc_sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik
         if (vpxy_out) vpxy_out[s] = sum_pxpy(n, p) + out[1];
         if (ke_out) ke_out[s] = kinetic(n, p);
         if (pe_out) pe_out[s] = out[0];
+        if (obs_out) orc_observables(b, dxle, r, p, n_slabs, obs_out + (size_t)s * nobs);
     }
     *kstep = k;
     free(f);
     return 0;
+}
+
+int32_t orc_sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik, double k0,
+                      double* r, double* p, int64_t* kstep, int64_t nsteps, double* vpxy_out,
+                      double* ke_out, double* pe_out) {
+    return sllod_run(b, gamma_dot, dt, gik, k0, r, p, kstep, nsteps, vpxy_out, ke_out, pe_out, 0,
+                     0);
 }
 
 /* One step of Eq. (system1) with its Nose-Hoover multiplier alpha = zeta. Each part is
@@ -628,11 +713,12 @@ int32_t orc_sllod_run(const orc_box* b, double gamma_dot, double dt, int32_t gik
  * T and S commute (T scales every component). The sequence
  * Z T S K D K S T Z over half steps is symmetric, so the step is second order and time
  * reversible under (p, zeta, gamma_dot) -> (-p, -zeta, -gamma_dot). */
-int32_t orc_nh_sllod_run(const orc_box* b, double gamma_dot, double dt, double temperature,
-                         double q, double nf, double* r, double* p, double* zeta,
-                         int64_t* kstep, int64_t nsteps, double* vpxy_out, double* ke_out,
-                         double* pe_out, double* zeta_out) {
+static int32_t nh_sllod_run(const orc_box* b, double gamma_dot, double dt, double temperature,
+                            double q, double nf, double* r, double* p, double* zeta,
+                            int64_t* kstep, int64_t nsteps, double* vpxy_out, double* ke_out,
+                            double* pe_out, double* zeta_out, int32_t n_slabs, double* obs_out) {
     const int32_t n = b->n;
+    const size_t nobs = 3 + (size_t)(n_slabs > 0 ? n_slabs : 0);
     double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
     if (!f) return -2;
     double* x = r;
@@ -654,6 +740,7 @@ int32_t orc_nh_sllod_run(const orc_box* b, double gamma_dot, double dt, double t
     if (ke_out) ke_out[0] = kinetic(n, p);
     if (pe_out) pe_out[0] = out[0];
     if (zeta_out) zeta_out[0] = zt;
+    if (obs_out) orc_observables(b, dxle, r, p, n_slabs, obs_out);
     for (int64_t s = 1; s <= nsteps; ++s) {
         zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
         double sc = exp(-zt * tau);
@@ -678,11 +765,20 @@ int32_t orc_nh_sllod_run(const orc_box* b, double gamma_dot, double dt, double t
         if (ke_out) ke_out[s] = kinetic(n, p);
         if (pe_out) pe_out[s] = out[0];
         if (zeta_out) zeta_out[s] = zt;
+        if (obs_out) orc_observables(b, dxle, r, p, n_slabs, obs_out + (size_t)s * nobs);
     }
     *zeta = zt;
     *kstep = k;
     free(f);
     return 0;
+}
+
+int32_t orc_nh_sllod_run(const orc_box* b, double gamma_dot, double dt, double temperature,
+                         double q, double nf, double* r, double* p, double* zeta,
+                         int64_t* kstep, int64_t nsteps, double* vpxy_out, double* ke_out,
+                         double* pe_out, double* zeta_out) {
+    return nh_sllod_run(b, gamma_dot, dt, temperature, q, nf, r, p, zeta, kstep, nsteps,
+                        vpxy_out, ke_out, pe_out, zeta_out, 0, 0);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -703,6 +799,9 @@ typedef struct {
     /* Nose-Hoover daughters when states_zeta is not NULL */
     const double* states_zeta;
     double temperature, q, nf;
+    /* per-step observables of orc_observables when obs_out is not NULL */
+    int32_t n_slabs;
+    double* obs_out;
 } batch_job;
 
 static void* batch_worker(void* arg) {
@@ -718,14 +817,17 @@ static void* batch_worker(void* arg) {
         int64_t k = 0;
         int32_t rc;
         double* vp = jb->vpxy_out + (size_t)d * (size_t)(jb->nsteps + 1);
+        double* ob = jb->obs_out ? jb->obs_out + (size_t)d * (size_t)(jb->nsteps + 1) *
+                                                     (size_t)(3 + jb->n_slabs)
+                                 : 0;
         if (jb->states_zeta) {
             /* the mappings that reverse the momenta (m = 1, 3) reverse the thermostat too */
             double zt = (jb->map_of[d] & 1) ? -jb->states_zeta[s] : jb->states_zeta[s];
-            rc = orc_nh_sllod_run(jb->b, jb->gamma_of[d], jb->dt, jb->temperature, jb->q,
-                                  jb->nf, r, p, &zt, &k, jb->nsteps, vp, 0, 0, 0);
+            rc = nh_sllod_run(jb->b, jb->gamma_of[d], jb->dt, jb->temperature, jb->q, jb->nf, r,
+                              p, &zt, &k, jb->nsteps, vp, 0, 0, 0, jb->n_slabs, ob);
         } else {
-            rc = orc_sllod_run(jb->b, jb->gamma_of[d], jb->dt, 1, 0.0, r, p, &k, jb->nsteps,
-                               vp, 0, 0);
+            rc = sllod_run(jb->b, jb->gamma_of[d], jb->dt, 1, 0.0, r, p, &k, jb->nsteps, vp, 0, 0,
+                           jb->n_slabs, ob);
         }
         if (rc) jb->status = rc;
         if (jb->r_out) memcpy(jb->r_out + (size_t)d * sz, r, sizeof(double) * sz);
@@ -740,14 +842,15 @@ static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
                          const double* states_p, const double* states_zeta, double temperature,
                          double q, double nf, int32_t n_daughters, const int32_t* state_of,
                          const int32_t* map_of, const double* gamma_of, int64_t nsteps,
-                         int32_t nthreads, double* vpxy_out, double* r_out, double* p_out);
+                         int32_t nthreads, double* vpxy_out, double* r_out, double* p_out,
+                         int32_t n_slabs, double* obs_out);
 
 int32_t orc_run_daughters(const orc_box* b, double dt, const double* states_r,
                           const double* states_p, int32_t n_daughters, const int32_t* state_of,
                           const int32_t* map_of, const double* gamma_of, int64_t nsteps,
                           int32_t nthreads, double* vpxy_out, double* r_out, double* p_out) {
     return run_batch(b, dt, states_r, states_p, 0, 0.0, 0.0, 0.0, n_daughters, state_of, map_of,
-                     gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out);
+                     gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out, 0, 0);
 }
 
 int32_t orc_run_daughters_nh(const orc_box* b, double dt, double temperature, double q,
@@ -758,14 +861,27 @@ int32_t orc_run_daughters_nh(const orc_box* b, double dt, double temperature, do
                              double* vpxy_out, double* r_out, double* p_out) {
     if (!states_zeta) return -1;
     return run_batch(b, dt, states_r, states_p, states_zeta, temperature, q, nf, n_daughters,
-                     state_of, map_of, gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out);
+                     state_of, map_of, gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out, 0, 0);
+}
+
+int32_t orc_run_daughters_obs(const orc_box* b, double dt, double temperature, double q,
+                              double nf, const double* states_r, const double* states_p,
+                              const double* states_zeta, int32_t n_daughters,
+                              const int32_t* state_of, const int32_t* map_of,
+                              const double* gamma_of, int64_t nsteps, int32_t nthreads,
+                              double* vpxy_out, int32_t n_slabs, double* obs_out) {
+    if (n_slabs < 1 || !obs_out) return -1;
+    return run_batch(b, dt, states_r, states_p, states_zeta, temperature, q, nf, n_daughters,
+                     state_of, map_of, gamma_of, nsteps, nthreads, vpxy_out, 0, 0, n_slabs,
+                     obs_out);
 }
 
 static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
                          const double* states_p, const double* states_zeta, double temperature,
                          double q, double nf, int32_t n_daughters, const int32_t* state_of,
                          const int32_t* map_of, const double* gamma_of, int64_t nsteps,
-                         int32_t nthreads, double* vpxy_out, double* r_out, double* p_out) {
+                         int32_t nthreads, double* vpxy_out, double* r_out, double* p_out,
+                         int32_t n_slabs, double* obs_out) {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > n_daughters) nthreads = n_daughters > 0 ? n_daughters : 1;
     batch_job* jobs = (batch_job*)calloc((size_t)nthreads, sizeof(batch_job));
@@ -773,7 +889,7 @@ static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
     for (int32_t t = 0; t < nthreads; ++t) {
         batch_job j = {b,      dt,     states_r, states_p, n_daughters, state_of, map_of,
                        gamma_of, nsteps, vpxy_out, r_out,  p_out,       t,        nthreads, 0,
-                       states_zeta, temperature, q, nf};
+                       states_zeta, temperature, q, nf, n_slabs, obs_out};
         jobs[t] = j;
         pthread_create(&th[t], 0, batch_worker, &jobs[t]);
     }

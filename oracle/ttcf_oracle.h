@@ -123,6 +123,27 @@ int32_t orc_run_daughters_nh(const orc_box* b, double dt, double temperature, do
                              const double* gamma_of, int64_t nsteps, int32_t nthreads,
                              double* vpxy_out, double* r_out, double* p_out);
 
+/* Observables of a state beyond P_xy (m = 1; V = Lx Ly Lz; pair sums over r^2 < rc^2):
+ *   out[0] = P_xx - P_yy, out[1] = P_yy - P_zz, with
+ *            V P_aa = sum_i p_a,i^2 + sum_{i<j} r_ij,a F_ij,a (r_ij the minimum image);
+ *   out[2] = (K + U) / N, K = sum_i p_i^2 / 2 (peculiar), U = sum_{i<j} phi(r_ij);
+ *   out[3 + s], s = 0..n_slabs-1: sum of p_x over the atoms with
+ *            floor(y n_slabs / Ly) = s (clamped), divided by the slab volume V / n_slabs.
+ * dxle is the Lees-Edwards offset of the positions. Returns 0, or -1 (n_slabs < 1 or a
+ * box too small for the cell grid). */
+int32_t orc_observables(const orc_box* b, double dxle, const double* r, const double* p,
+                        int32_t n_slabs, double* out);
+
+/* Batch of daughters as orc_run_daughters (states_zeta == NULL: GIK) or orc_run_daughters_nh
+ * (Nose-Hoover), that also records orc_observables after every step:
+ * obs_out[(d (nsteps + 1) + k) (3 + n_slabs) + c]. */
+int32_t orc_run_daughters_obs(const orc_box* b, double dt, double temperature, double q,
+                              double nf, const double* states_r, const double* states_p,
+                              const double* states_zeta, int32_t n_daughters,
+                              const int32_t* state_of, const int32_t* map_of,
+                              const double* gamma_of, int64_t nsteps, int32_t nthreads,
+                              double* vpxy_out, int32_t n_slabs, double* obs_out);
+
 /* Batch of independent GIK-SLLOD daughters on a pool of nthreads threads.
  * Daughter d starts from start state state_of[d] under mapping map_of[d] with shear rate
  * gamma_of[d] and runs nsteps steps; its series V*P_xy(t_k), k = 0..nsteps, goes to

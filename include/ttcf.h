@@ -57,8 +57,21 @@ enum { TTCF_WCA = 0, TTCF_LJ = 1 };
 enum { TTCF_PREC_FP64 = 0, TTCF_PREC_FP32_FORCES = 1 };
 
 /* Observables: P_xy (bulk); for the channel, the wall shear stress and the momentum
- * profile (n_bins values per time point). */
-enum { TTCF_OBS_PXY = 0, TTCF_OBS_WALL_STRESS = 1, TTCF_OBS_VPROFILE = 2 };
+ * profile (n_bins values per time point); for the bulk, when recorded
+ * (ttcf_record_observables), the normal-stress differences P_xx - P_yy and P_yy - P_zz, the
+ * energy per atom (K + U)/N with K the peculiar kinetic energy, and the momentum profile over
+ * TTCF_BULK_SLABS slabs of y (per slab: sum of p_x over its atoms / slab volume; slab s holds
+ * floor(y TTCF_BULK_SLABS / L_y) = s; TTCF_BULK_SLABS values per time point). */
+enum {
+    TTCF_OBS_PXY = 0,
+    TTCF_OBS_WALL_STRESS = 1,
+    TTCF_OBS_VPROFILE = 2,
+    TTCF_OBS_N1 = 3,
+    TTCF_OBS_N2 = 4,
+    TTCF_OBS_ENERGY = 5,
+    TTCF_OBS_SLAB_PX = 6
+};
+enum { TTCF_BULK_SLABS = 8 };
 
 /* One simulated system (Example 1 of the paper: WCA fluid in a cubic periodic box). */
 typedef struct {
@@ -142,6 +155,26 @@ int32_t ttcf_accumulate(ttcf_ctx* ctx, int64_t* out_groups);
 int32_t ttcf_response(ttcf_ctx* ctx, int32_t observable, double gamma_dot_filter, int32_t n_t,
                       double* ttcf_mean, double* ttcf_se, double* dav_mean, double* dav_se,
                       int64_t* out_n_states);
+/* observable: TTCF_OBS_PXY, or one of TTCF_OBS_N1, _N2, _ENERGY, _SLAB_PX (Eq. TTCF with that
+ * B and Omega(0) still -(V/T) gamma_dot P_xy(0); every matching group must have recorded
+ * them, else TTCF_ESTATE). TTCF_OBS_SLAB_PX writes n_t x TTCF_BULK_SLABS values (slab
+ * fastest) per array. */
+
+/* Section Mathematical Framework: B(t) may be any phase function. Sets whether daughters
+ * spawned from now on also record the extra bulk observables (TTCF_OBS_N1 .. _SLAB_PX) after
+ * every step, beside V*P_xy; ttcf_accumulate folds them like P_xy. on: 0 or 1. They are
+ * recorded by the neighbour-list form only: spawning them on a system with FP64 forces fails
+ * with TTCF_EINVAL, and stepping them in the cell form (a system whose lists do not fit in
+ * LDS) with TTCF_EINVAL. Captured graphs record P_xy only: with graphs alive, switching on
+ * fails with TTCF_ESTATE, and ttcf_graph_create fails while it is on. The recording costs a
+ * second kernel build with the extra pair sums and one more workgroup reduction per step. */
+int32_t ttcf_record_observables(ttcf_ctx* ctx, int32_t on);
+
+/* Inspection: the extra observables of live daughters first..first+count-1 that record them:
+ * out[(q n_t + k) * (3 + TTCF_BULK_SLABS) + c], c = 0: P_xx - P_yy, 1: P_yy - P_zz,
+ * 2: (K + U)/N, 3 + s: slab s of the momentum profile. */
+int32_t ttcf_export_observables(ttcf_ctx* ctx, int64_t first, int32_t count, int32_t n_t,
+                                double* out);
 
 /* Eq. (corr_modified): the response with the integrand <Omega(0)B(s)> - <Omega(0)><B(s)>,
  * which corrects a finite sample whose <Omega(0)> is not zero (e.g. daughters spawned without
@@ -154,6 +187,11 @@ int32_t ttcf_response(ttcf_ctx* ctx, int32_t observable, double gamma_dot_filter
  * n_t too long). */
 int32_t ttcf_response_modified(ttcf_ctx* ctx, double gamma_dot_filter, int32_t n_t, double* mean,
                                double* se, int64_t* out_n_states);
+/* ttcf_response_modified for any observable of ttcf_response (TTCF_OBS_SLAB_PX: n_t x
+ * TTCF_BULK_SLABS values per array, slab fastest). */
+int32_t ttcf_observable_response_modified(ttcf_ctx* ctx, int32_t observable,
+                                          double gamma_dot_filter, int32_t n_t, double* mean,
+                                          double* se, int64_t* out_n_states);
 
 /* ---- lifetime and errors ------------------------------------------------------------ */
 

@@ -98,6 +98,7 @@ struct Batch {
     double* states = nullptr;    // n_daughters * 6n
     double* series = nullptr;    // n_daughters * (n_steps + 1)
     double* hseries = nullptr;   // learned control variate, same layout (allocated on demand)
+    double* xseries = nullptr;   // extra observables: n_daughters * (n_steps + 1) * kObsCols
     void* scratch = nullptr;     // spawn index arrays
     int32_t remaining = 0;       // daughters not yet accumulated
 };
@@ -167,6 +168,12 @@ struct ttcf_ctx {
     // accumulated control-variate series (same rows as acc_d)
     double* acc_h = nullptr;
     std::vector<int32_t> row_cv;
+    // extra observables: recorded by daughters spawned while record_obs is set; accumulated
+    // rows of kObsCols columns of acc_stride values (allocated with the first such spawn)
+    bool record_obs = false;
+    double* acc_xd = nullptr;
+    double* acc_xi = nullptr;
+    std::vector<char> row_x;
     // learned control variate
     int32_t cv_out = 0;          // outputs (time points t_1..t_nout)
     int64_t cv_nparam = 0;
@@ -389,6 +396,14 @@ int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
     int32_t* nhl = (int32_t*)dev_alloc(sizeof(int32_t) * (size_t)cap, c->stream);
     if (!nd || !ni || !nh || !ng || !nc || !nhl)
         return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
+    double* nxd = nullptr;
+    double* nxi = nullptr;
+    const bool with_x = c->record_obs || c->acc_xd;
+    if (with_x) {
+        nxd = (double*)dev_alloc(sizeof(double) * (size_t)cap * kObsCols * stride, c->stream);
+        nxi = (double*)dev_alloc(sizeof(double) * (size_t)cap * kObsCols * stride, c->stream);
+        if (!nxd || !nxi) return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
+    }
     if (c->acc_rows > 0) {
         HIPCHECK(c, hipMemcpy2DAsync(nd, sizeof(double) * stride, c->acc_d,
                                      sizeof(double) * c->acc_stride, sizeof(double) * c->acc_stride,
@@ -399,7 +414,26 @@ int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
         HIPCHECK(c, hipMemcpy2DAsync(nh, sizeof(double) * stride, c->acc_h,
                                      sizeof(double) * c->acc_stride, sizeof(double) * c->acc_stride,
                                      (size_t)c->acc_rows, hipMemcpyDeviceToDevice, c->stream));
+        if (with_x && c->acc_xd) {
+            // a row is kObsCols columns of the stride: copy column by column
+            HIPCHECK(c, hipMemcpy2DAsync(nxd, sizeof(double) * stride, c->acc_xd,
+                                         sizeof(double) * c->acc_stride,
+                                         sizeof(double) * c->acc_stride,
+                                         (size_t)c->acc_rows * kObsCols, hipMemcpyDeviceToDevice,
+                                         c->stream));
+            HIPCHECK(c, hipMemcpy2DAsync(nxi, sizeof(double) * stride, c->acc_xi,
+                                         sizeof(double) * c->acc_stride,
+                                         sizeof(double) * c->acc_stride,
+                                         (size_t)c->acc_rows * kObsCols, hipMemcpyDeviceToDevice,
+                                         c->stream));
+        }
         HIPCHECK(c, hipStreamSynchronize(c->stream));
+    }
+    if (with_x) {
+        dev_free(c->acc_xd);
+        dev_free(c->acc_xi);
+        c->acc_xd = nxd;
+        c->acc_xi = nxi;
     }
     dev_free(c->acc_d);
     dev_free(c->acc_i);
@@ -468,7 +502,10 @@ void ttcf_destroy(ttcf_ctx* c) {
         dev_free(b.series);
         dev_free(b.scratch);
         dev_free(b.hseries);
+        dev_free(b.xseries);
     }
+    dev_free(c->acc_xd);
+    dev_free(c->acc_xi);
     dev_free(c->d_descs);
     dev_free(c->d_order);
     dev_free(c->d_queue);
@@ -484,7 +521,6 @@ void ttcf_destroy(ttcf_ctx* c) {
     dev_free(c->cv_t);
     dev_free(c->cv_stats);
     dev_free(c->cv_mu);
-    for (auto& b : c->batches) dev_free(b.hseries);
     --g_live_contexts;
     delete c;
 }
@@ -769,6 +805,9 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
         if (!std::isfinite(gamma_dot[g])) return fail(c, TTCF_EINVAL, "shear rates must be finite");
     Mother& m = c->mothers[mother];
     const size_t n = (size_t)m.dev.n;
+    if (c->record_obs && m.sys.precision != TTCF_PREC_FP32_FORCES)
+        return fail(c, TTCF_EINVAL, "the extra observables are recorded by the list form only "
+                                    "(FP32 forces)");
     if (steps_between > 0) {
         int32_t rc = ttcf_sample_states(c, mother, n_states, steps_between);
         if (rc != TTCF_OK) return rc;
@@ -792,10 +831,14 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
     b.series = (double*)dev_alloc(sizeof(double) * (size_t)(n_steps + 1) * nd, c->stream);
     const size_t scratch_bytes = sizeof(int32_t) * 2 * nd + sizeof(double*) * nd + 64;
     b.scratch = dev_alloc(scratch_bytes, c->stream);
-    if (!b.states || !b.series || !b.scratch) {
+    if (c->record_obs)
+        b.xseries = (double*)dev_alloc(sizeof(double) * (size_t)(n_steps + 1) * kObsCols * nd,
+                                       c->stream);
+    if (!b.states || !b.series || !b.scratch || (c->record_obs && !b.xseries)) {
         dev_free(b.states);
         dev_free(b.series);
         dev_free(b.scratch);
+        dev_free(b.xseries);
         return fail(c, TTCF_ENOMEM, "daughter allocation failed");
     }
     // Nose-Hoover daughters start from their state's thermostat variable
@@ -824,6 +867,7 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
             DaughterDesc ds{};
             ds.state = dst[d];
             ds.series = b.series + (size_t)(n_steps + 1) * d;
+            ds.xseries = b.xseries ? b.xseries + (size_t)(n_steps + 1) * kObsCols * d : nullptr;
             ds.sys = m.dev;
             ds.gamma_dot = g;
             ds.k0 = 0.0;
@@ -897,6 +941,7 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
     L->variant = variant;
     L->kmax = kmax;
     L->thermo = group.empty() ? 0 : group[0]->thermo;
+    for (const DaughterDesc* dp : group) L->obs = L->obs || dp->xseries != nullptr;
     L->lds_bytes = variant == kVariantNeighbourList ? nl_lds
                                                     : lds_bytes_for(nmax, cmax, threads, precision);
     if (L->lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
@@ -973,6 +1018,9 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         bool nl = false;
         rc = apply_shape(c, e, precision, &d, &nl);
         if (rc != TTCF_OK) return rc;
+        if (d.xseries && !nl)
+            return fail(c, TTCF_EINVAL, "daughters recording the extra observables need the "
+                                        "neighbour-list form, and this system runs in cells");
         groups[2 * (nl ? 0 : 1) + (d.thermo ? 1 : 0)].push_back((int32_t)i);
     }
     const bool any_nl = !groups[0].empty() || !groups[1].empty();
@@ -1053,10 +1101,12 @@ int32_t discard_batch(ttcf_ctx* c, int32_t bidx) {
     dev_free(b.series);
     dev_free(b.scratch);
     dev_free(b.hseries);
+    dev_free(b.xseries);
     b.states = nullptr;
     b.series = nullptr;
     b.scratch = nullptr;
     b.hseries = nullptr;
+    b.xseries = nullptr;
     b.remaining = 0;
     return push_descs(c);
 }
@@ -1424,6 +1474,35 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
         A.n_t = len;
         A.row_stride = c->acc_stride;  // rows are written with the context's stride
         HIPCHECK(c, launch_accumulate(A, c->stream));
+        // extra observables: one launch per run of consecutive groups that recorded them
+        std::vector<char> has_x(which.size(), 1);
+        for (size_t q = 0; q < which.size(); ++q)
+            for (size_t d = ready[which[q]].first; d < ready[which[q]].second; ++d)
+                has_x[q] = has_x[q] && c->descs[d].xseries != nullptr;
+        for (size_t q0 = 0; q0 < which.size();) {
+            if (!has_x[q0]) {
+                ++q0;
+                continue;
+            }
+            size_t q1 = q0;
+            while (q1 < which.size() && has_x[q1]) ++q1;
+            if (!c->acc_xd) {
+                dev_free(d_sub);
+                dev_free(d_first);
+                return fail(c, TTCF_ESTATE, "no accumulator for the extra observables");
+            }
+            AccumObsLaunch X{};
+            X.descs = d_sub;
+            X.first_of = d_first + q0;
+            X.stride = c->acc_stride;
+            X.row_stride = (int64_t)kObsCols * c->acc_stride;
+            X.d_out = c->acc_xd + (size_t)(c->acc_rows + (int64_t)q0) * X.row_stride;
+            X.i_out = c->acc_xi + (size_t)(c->acc_rows + (int64_t)q0) * X.row_stride;
+            X.n_groups = (int32_t)(q1 - q0);
+            X.n_t = len;
+            HIPCHECK(c, launch_accumulate_obs(X, c->stream));
+            q0 = q1;
+        }
         std::vector<int32_t> hh(which.size());
         HIPCHECK(c, hipMemcpyAsync(hh.data(), A.health_out, sizeof(int32_t) * which.size(),
                                    hipMemcpyDeviceToHost, c->stream));
@@ -1439,6 +1518,7 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
                                       .sys.temperature);
             c->row_nt.push_back(len);
             c->row_health.push_back(hh[q]);
+            c->row_x.push_back(has_x[q]);
             {
                 // a group carries the control variate when all its daughters do, in one role
                 int role = c->live[ready[which[q]].first].cv_role;
@@ -1477,10 +1557,12 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
             dev_free(b.series);
             dev_free(b.scratch);
             dev_free(b.hseries);
+            dev_free(b.xseries);
             b.states = nullptr;
             b.series = nullptr;
             b.scratch = nullptr;
             b.hseries = nullptr;
+            b.xseries = nullptr;
         }
     }
     rc = push_descs(c);
@@ -1503,10 +1585,40 @@ int32_t refresh_row_health(ttcf_ctx* c) {
 }
 }  // namespace
 
+namespace {
+// Columns of an observable in the accumulator: P_xy has its own arrays (acc_d, acc_i); the
+// extra observables are columns of acc_xd, acc_xi. Returns false for an unknown observable.
+static_assert(kObsSlabs == TTCF_BULK_SLABS, "slab count of the ABI");
+bool obs_columns(int32_t observable, int* col0, int* ncol) {
+    switch (observable) {
+        case TTCF_OBS_PXY: *col0 = -1; *ncol = 1; return true;
+        case TTCF_OBS_N1: *col0 = 0; *ncol = 1; return true;
+        case TTCF_OBS_N2: *col0 = 1; *ncol = 1; return true;
+        case TTCF_OBS_ENERGY: *col0 = 2; *ncol = 1; return true;
+        case TTCF_OBS_SLAB_PX: *col0 = 3; *ncol = kObsSlabs; return true;
+    }
+    return false;
+}
+
+// accumulator arrays and row stride of column `col` (-1: P_xy)
+void obs_arrays(const ttcf_ctx* c, int col, const double** d, const double** i, int64_t* stride) {
+    if (col < 0) {
+        *d = c->acc_d;
+        *i = c->acc_i;
+        *stride = c->acc_stride;
+    } else {
+        *d = c->acc_xd + (size_t)col * c->acc_stride;
+        *i = c->acc_xi + (size_t)col * c->acc_stride;
+        *stride = (int64_t)kObsCols * c->acc_stride;
+    }
+}
+}  // namespace
+
 int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, int32_t n_t,
                       double* ttcf_mean, double* ttcf_se, double* dav_mean, double* dav_se,
                       int64_t* out_n_states) {
-    if (!c || observable != TTCF_OBS_PXY || n_t <= 0) return TTCF_EINVAL;
+    int col0 = 0, ncol = 0;
+    if (!c || n_t <= 0 || !obs_columns(observable, &col0, &ncol)) return TTCF_EINVAL;
     int32_t rc0 = refresh_row_health(c);
     if (rc0 != TTCF_OK) return rc0;
     std::vector<int32_t> rows;
@@ -1517,44 +1629,59 @@ int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, 
         rows.push_back((int32_t)r);
     }
     if (rows.empty()) return fail(c, TTCF_ESTATE, "no accumulated group matches the filter");
-    for (int32_t r : rows)
+    for (int32_t r : rows) {
         if (c->row_nt[r] < n_t) return fail(c, TTCF_ESTATE, "n_t exceeds a matching group's length");
-    const size_t bytes = sizeof(int32_t) * rows.size() + sizeof(double) * 4 * n_t + 64;
+        if (col0 >= 0 && !c->row_x[r])
+            return fail(c, TTCF_ESTATE, "a matching group did not record the extra observables");
+    }
+    const size_t plane = (size_t)n_t * ncol;
+    const size_t bytes = sizeof(int32_t) * rows.size() + sizeof(double) * 4 * plane + 64;
     char* scratch = (char*)dev_alloc(bytes, c->stream);
     if (!scratch) return fail(c, TTCF_ENOMEM, "response scratch allocation failed");
     double* d_out = (double*)scratch;
-    int32_t* d_used = (int32_t*)(scratch + sizeof(double) * 4 * n_t);
+    int32_t* d_used = (int32_t*)(scratch + sizeof(double) * 4 * plane);
     int32_t* d_rows = d_used + 4;
     HIPCHECK(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice,
                                c->stream));
     std::vector<int32_t> hh = c->row_health;
     HIPCHECK(c, hipMemcpyAsync(c->d_row_health, hh.data(), sizeof(int32_t) * hh.size(),
                                hipMemcpyHostToDevice, c->stream));
-    ResponseLaunch R{};
-    R.d_all = c->acc_d;
-    R.i_all = c->acc_i;
-    R.gamma = c->d_row_gamma;
-    R.coef = c->d_row_coef;
-    R.health = c->d_row_health;
-    R.rows = d_rows;
-    R.n_rows = (int32_t)rows.size();
-    R.n_t = n_t;
-    R.n_t_stride = c->acc_stride;
-    R.normalise = gamma_dot_filter <= 0.0 ? 1 : 0;
-    R.out = d_out;
-    R.used = d_used;
-    HIPCHECK(c, launch_response(R, c->stream));
-    std::vector<double> out(4 * (size_t)n_t);
+    for (int q = 0; q < ncol; ++q) {
+        const double* da = nullptr;
+        const double* ia = nullptr;
+        int64_t stride = 0;
+        obs_arrays(c, col0 < 0 ? -1 : col0 + q, &da, &ia, &stride);
+        ResponseLaunch R{};
+        R.d_all = da;
+        R.i_all = ia;
+        R.gamma = c->d_row_gamma;
+        R.coef = c->d_row_coef;
+        R.health = c->d_row_health;
+        R.rows = d_rows;
+        R.n_rows = (int32_t)rows.size();
+        R.n_t = n_t;
+        R.n_t_stride = (int32_t)stride;
+        R.normalise = gamma_dot_filter <= 0.0 ? 1 : 0;
+        R.out = d_out + (size_t)q * 4 * n_t;
+        R.used = d_used;
+        HIPCHECK(c, launch_response(R, c->stream));
+    }
+    std::vector<double> out(4 * plane);
     int32_t used = 0;
-    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * 4 * n_t, hipMemcpyDeviceToHost,
+    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * 4 * plane, hipMemcpyDeviceToHost,
                                c->stream));
     HIPCHECK(c, hipMemcpyAsync(&used, d_used, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     dev_free(scratch);
-    if (ttcf_mean) std::memcpy(ttcf_mean, out.data(), sizeof(double) * n_t);
-    if (ttcf_se) std::memcpy(ttcf_se, out.data() + n_t, sizeof(double) * n_t);
-    if (dav_mean) std::memcpy(dav_mean, out.data() + 2 * n_t, sizeof(double) * n_t);
-    if (dav_se) std::memcpy(dav_se, out.data() + 3 * n_t, sizeof(double) * n_t);
+    // column q's block holds mean, se, dav, dav se (n_t each); the outputs put the columns
+    // fastest
+    double* dst[4] = {ttcf_mean, ttcf_se, dav_mean, dav_se};
+    for (int w = 0; w < 4; ++w) {
+        if (!dst[w]) continue;
+        for (int32_t k = 0; k < n_t; ++k)
+            for (int q = 0; q < ncol; ++q)
+                dst[w][(size_t)k * ncol + q] = out[((size_t)q * 4 + w) * n_t + k];
+    }
     if (out_n_states) *out_n_states = used;
     return TTCF_OK;
 }
@@ -1599,6 +1726,9 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
         (gd->mapping_mask & 0xFu) == 0 || (gd->mapping_mask & ~0xFu) != 0 || !gd->gamma_dot ||
         gd->n_steps <= 0 || gd->max_replays <= 0)
         return fail(c, TTCF_EINVAL, "bad graph description");
+    if (c->record_obs)
+        return fail(c, TTCF_ESTATE, "captured cycles record P_xy only: switch the extra "
+                                    "observables off first");
     const int64_t ns64 = (int64_t)std::max(1, gd->n_replicas) * gd->states_per_replica;
     if (ns64 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many start states per replay");
     const int32_t n_states = (int32_t)ns64;
@@ -1759,6 +1889,7 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
         c->row_nt.push_back(n_t);
         c->row_health.push_back(kRowPending);
         c->row_cv.push_back(0);
+        c->row_x.push_back(0);
     }
     c->acc_rows += reserve;
     const int32_t zero = 0;
@@ -1874,9 +2005,12 @@ void ttcf_graph_destroy(ttcf_graph* g) {
     free_graph(g);
 }
 
-int32_t ttcf_response_modified(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, double* mean,
-                               double* se, int64_t* out_n_states) {
-    if (!c || !(gamma_dot_filter > 0.0) || n_t <= 0) return TTCF_EINVAL;
+namespace {
+int32_t response_modified_impl(ttcf_ctx* c, int32_t observable, double gamma_dot_filter,
+                               int32_t n_t, double* mean, double* se, int64_t* out_n_states) {
+    int col0 = 0, ncol = 0;
+    if (!c || !(gamma_dot_filter > 0.0) || n_t <= 0 || !obs_columns(observable, &col0, &ncol))
+        return TTCF_EINVAL;
     int32_t rc = refresh_row_health(c);
     if (rc != TTCF_OK) return rc;
     std::vector<int32_t> rows;
@@ -1888,33 +2022,81 @@ int32_t ttcf_response_modified(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t
         if (c->row_coef[r] != c->row_coef[rows[0]] || c->row_dt[r] != c->row_dt[rows[0]] ||
             c->row_maps[r] != c->row_maps[rows[0]])
             return fail(c, TTCF_EINVAL, "matching groups differ in V/T, dt or mapping count");
+        if (col0 >= 0 && !c->row_x[r])
+            return fail(c, TTCF_ESTATE, "a matching group did not record the extra observables");
     }
     Scratch sc(c->stream);
     int32_t* d_rows = sc.get<int32_t>(rows.size());
     double* d_j = sc.get<double>(rows.size() * (size_t)n_t);
-    double* d_out = sc.get<double>(2 * (size_t)n_t);
+    double* d_out = sc.get<double>(2 * (size_t)n_t * ncol);
     if (!d_rows || !d_j || !d_out) return fail(c, TTCF_ENOMEM, "response scratch allocation failed");
     HIPCHECK(c, hipMemcpyAsync(d_rows, rows.data(), sizeof(int32_t) * rows.size(),
                                hipMemcpyHostToDevice, c->stream));
-    ModifiedLaunch A{};
-    A.d_all = c->acc_d;
-    A.i_all = c->acc_i;
-    A.stride = c->acc_stride;
-    A.rows = d_rows;
-    A.n_rows = (int32_t)rows.size();
-    A.n_t = n_t;
-    A.coef = c->row_coef[rows[0]];
-    A.dt = c->row_dt[rows[0]];
-    A.j_rows = d_j;
-    A.out = d_out;
-    HIPCHECK(c, launch_response_modified(A, c->stream));
-    std::vector<double> out(2 * (size_t)n_t);
-    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * 2 * n_t, hipMemcpyDeviceToHost,
+    for (int q = 0; q < ncol; ++q) {
+        const double* da = nullptr;
+        const double* ia = nullptr;
+        int64_t stride = 0;
+        obs_arrays(c, col0 < 0 ? -1 : col0 + q, &da, &ia, &stride);
+        ModifiedLaunch A{};
+        A.d_all = da;
+        A.i_all = ia;
+        A.stride = (int32_t)stride;
+        A.p_all = c->acc_d;
+        A.p_stride = c->acc_stride;
+        A.rows = d_rows;
+        A.n_rows = (int32_t)rows.size();
+        A.n_t = n_t;
+        A.coef = c->row_coef[rows[0]];
+        A.dt = c->row_dt[rows[0]];
+        A.j_rows = d_j;  // columns run in stream order, so one scratch serves them all
+        A.out = d_out + (size_t)q * 2 * n_t;
+        HIPCHECK(c, launch_response_modified(A, c->stream));
+    }
+    std::vector<double> out(2 * (size_t)n_t * ncol);
+    HIPCHECK(c, hipMemcpyAsync(out.data(), d_out, sizeof(double) * out.size(), hipMemcpyDeviceToHost,
                                c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    if (mean) std::memcpy(mean, out.data(), sizeof(double) * n_t);
-    if (se) std::memcpy(se, out.data() + n_t, sizeof(double) * n_t);
+    for (int32_t k = 0; k < n_t; ++k)
+        for (int q = 0; q < ncol; ++q) {
+            if (mean) mean[(size_t)k * ncol + q] = out[(size_t)q * 2 * n_t + k];
+            if (se) se[(size_t)k * ncol + q] = out[(size_t)q * 2 * n_t + n_t + k];
+        }
     if (out_n_states) *out_n_states = (int64_t)rows.size();
+    return TTCF_OK;
+}
+}  // namespace
+
+int32_t ttcf_response_modified(ttcf_ctx* c, double gamma_dot_filter, int32_t n_t, double* mean,
+                               double* se, int64_t* out_n_states) {
+    return response_modified_impl(c, TTCF_OBS_PXY, gamma_dot_filter, n_t, mean, se,
+                                  out_n_states);
+}
+
+int32_t ttcf_observable_response_modified(ttcf_ctx* c, int32_t observable, double gamma_dot_filter,
+                                          int32_t n_t, double* mean, double* se,
+                                          int64_t* out_n_states) {
+    return response_modified_impl(c, observable, gamma_dot_filter, n_t, mean, se, out_n_states);
+}
+
+int32_t ttcf_record_observables(ttcf_ctx* c, int32_t on) {
+    if (!c || (on != 0 && on != 1)) return TTCF_EINVAL;
+    if (on && !c->graphs.empty())
+        return fail(c, TTCF_ESTATE, "captured graphs exist; they record P_xy only");
+    if (on && !c->acc_xd && c->acc_cap > 0) {
+        // the accumulator exists without the extra columns: give it them now
+        double* xd = (double*)dev_alloc(sizeof(double) * (size_t)c->acc_cap * kObsCols *
+                                            c->acc_stride, c->stream);
+        double* xi = (double*)dev_alloc(sizeof(double) * (size_t)c->acc_cap * kObsCols *
+                                            c->acc_stride, c->stream);
+        if (!xd || !xi) {
+            dev_free(xd);
+            dev_free(xi);
+            return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
+        }
+        c->acc_xd = xd;
+        c->acc_xi = xi;
+    }
+    c->record_obs = on != 0;
     return TTCF_OK;
 }
 
@@ -1924,6 +2106,25 @@ static int32_t find_live(ttcf_ctx* c, int64_t id) {
                                [](const Live& l, int64_t v) { return l.id < v; });
     if (it == c->live.end() || it->id != id) return -1;
     return (int32_t)(it - c->live.begin());
+}
+
+int32_t ttcf_export_observables(ttcf_ctx* c, int64_t first, int32_t count, int32_t n_t,
+                                double* out) {
+    if (!c || count <= 0 || n_t <= 0 || !out) return TTCF_EINVAL;
+    int32_t rc = sync_descs(c);
+    if (rc != TTCF_OK) return rc;
+    for (int32_t q = 0; q < count; ++q) {
+        const int32_t i = find_live(c, first + q);
+        if (i < 0) return fail(c, TTCF_EINVAL, "no live daughter with that id");
+        const DaughterDesc& d = c->descs[i];
+        if (!d.xseries) return fail(c, TTCF_ESTATE, "that daughter does not record them");
+        if (n_t > d.n_steps + 1) return fail(c, TTCF_EINVAL, "n_t exceeds the daughter's length");
+        HIPCHECK(c, hipMemcpyAsync(out + (size_t)q * n_t * kObsCols, d.xseries,
+                                   sizeof(double) * (size_t)n_t * kObsCols, hipMemcpyDeviceToHost,
+                                   c->stream));
+    }
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return TTCF_OK;
 }
 
 int32_t ttcf_export_daughter(ttcf_ctx* c, int64_t daughter, double* r, double* p, int64_t* k) {

@@ -42,6 +42,12 @@ struct SysDev {
     float ri2_f;
 };
 
+// Observables recorded beside V*P_xy when a daughter has an extra series (kObsCols per time
+// point): P_xx - P_yy, P_yy - P_zz, (K + U)/N, and kObsSlabs values of the y-slab profile
+// sum(p_x)/(slab volume), slab s holding floor(y kObsSlabs / L_y) = s.
+constexpr int kObsSlabs = 8;
+constexpr int kObsCols = 3 + kObsSlabs;
+
 // Largest list capacity of the neighbour-list form (the inner set is a 32-bit mask).
 constexpr int kNlMaxKmax = 32;
 // Inner skin of the force loop (sigma).
@@ -70,6 +76,7 @@ struct DaughterDesc {
     double zeta;
     double nh_q;
     double nh_target;
+    double* xseries;    // (n_steps + 1) x kObsCols extra observables, or null
 };
 
 enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2, kHealthListOverflow = 4 };
@@ -95,6 +102,7 @@ struct BatchLaunch {
     int32_t variant;       // Variant
     int32_t kmax;          // neighbour-list capacity per atom (neighbour-list form)
     int32_t thermo;        // daughter thermostat of every job (0 isokinetic, 1 Nose-Hoover)
+    int32_t obs;           // 1: some job records the extra observables (list form only)
     size_t lds_bytes;
 };
 
@@ -220,9 +228,11 @@ hipError_t launch_acf(const double* x, int64_t n, int32_t max_lag, double thresh
                       hipStream_t s);
 // Eq. (corr_modified) over selected accumulator rows sharing coef and dt (ttcf_estimators.hip)
 struct ModifiedLaunch {
-    const double* d_all;   // accumulator rows: D_n(t), I_n(t), row stride `stride`
+    const double* d_all;   // accumulator rows of B: D_n(t), I_n(t), row stride `stride`
     const double* i_all;
     int32_t stride;
+    const double* p_all;   // P_xy direct-average rows (their t = 0 value gives <Omega(0)>),
+    int32_t p_stride;      // row stride p_stride (B = P_xy: p_all = d_all)
     const int32_t* rows;   // selected rows
     int32_t n_rows, n_t;
     double coef;           // V gamma_dot / T of every selected row
@@ -231,6 +241,19 @@ struct ModifiedLaunch {
     double* out;           // [0, n_t): estimate, [n_t, 2 n_t): jackknife standard error
 };
 hipError_t launch_response_modified(const ModifiedLaunch& a, hipStream_t s);
+
+// Accumulation of the extra observables: per group and column c, the mapping means
+// D_n,c(t_k) of B_c(t_k) and I_n,c(t_k) of int_0^t P_xy(0) B_c(s) ds (trapezoid rule).
+// Output row of group g, column c: d_out + g * row_stride + c * stride (n_t values).
+struct AccumObsLaunch {
+    const DaughterDesc* descs;   // device: every daughter has an xseries
+    const int32_t* first_of;     // device: n_groups + 1
+    double* d_out;
+    double* i_out;
+    int32_t n_groups, n_t;
+    int64_t stride, row_stride;
+};
+hipError_t launch_accumulate_obs(const AccumObsLaunch& a, hipStream_t s);
 // *counter += 1 (one thread)
 hipError_t launch_increment(int32_t* counter, hipStream_t s);
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s);

@@ -1542,20 +1542,24 @@ __device__ __forceinline__ void nl_inner(const SysDev& S, uint32_t dxq, const ui
     }
 }
 
-template <int APT>
+// OBS: also this thread's halves of the pair sums W_xx, W_yy, W_zz and U (xw).
+template <int APT, bool OBS>
 __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
                                             const uint32_t (&qx)[APT], const uint32_t (&qy)[APT],
                                             const uint32_t (&qz)[APT], const uint32_t (&imask)[APT],
                                             float (&fx)[APT], float (&fy)[APT], float (&fz)[APT],
-                                            const NlLds& L, int nmax) {
+                                            const NlLds& L, int nmax, double (&xw)[4]) {
     const int T = blockDim.x, t = threadIdx.x;
     const float rc2 = S.rc2_f;
     const float ca = (float)S.c_attr;
+    const float ushift = (float)S.u_shift;
     double wacc = 0.0;
+    if (OBS) xw[0] = xw[1] = xw[2] = xw[3] = 0.0;
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
         const int a = t + j * T;
         float gx = 0.f, gy = 0.f, gz = 0.f, w = 0.f;
+        float vxx = 0.f, vyy = 0.f, vzz = 0.f, uu = 0.f;
         {
             // the inner entries in list order (ascending ids): a fixed summation order, and
             // every skipped entry lies beyond r_c, where a pair adds an exact zero
@@ -1575,14 +1579,65 @@ __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
                 gy += fs * dy;
                 gz += fs * dz;
                 w += dx * (fs * dy);
+                if (OBS) {
+                    vxx += dx * (fs * dx);
+                    vyy += dy * (fs * dy);
+                    vzz += dz * (fs * dz);
+                    uu += r2 < rc2 ? 4.f * s3 * (s3 - ca) + ushift : 0.f;
+                }
             }
         }
         fx[j] = gx;
         fy[j] = gy;
         fz[j] = gz;
         wacc += (double)w;
+        if (OBS) {
+            xw[0] += 0.5 * (double)vxx;
+            xw[1] += 0.5 * (double)vyy;
+            xw[2] += 0.5 * (double)vzz;
+            xw[3] += 0.5 * (double)uu;
+        }
     }
     return 0.5 * wacc;
+}
+
+// The extra observables of the owned atoms at one time point (momenta p, positions in
+// [0, L), pair halves xw of the last force pass), reduced over the workgroup and written by
+// thread 0 to row `row` of the daughter's extra series.
+template <int APT>
+__device__ __forceinline__ void nl_record_obs(const SysDev& S, const double (&y)[APT],
+                                              const double (&px)[APT], const double (&py)[APT],
+                                              const double (&pz)[APT], const double (&xw)[4],
+                                              double* xs, int row, const NlLds& L) {
+    double o[kObsCols];
+#pragma unroll
+    for (int c = 0; c < kObsCols; ++c) o[c] = 0.0;
+    const double slab_scale = (double)kObsSlabs / S.box[1];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        // lanes past n hold zero momenta and add nothing
+        const double xx = px[j] * px[j], yy = py[j] * py[j], zz = pz[j] * pz[j];
+        o[0] += xx - yy;
+        o[1] += yy - zz;
+        o[2] += 0.5 * (xx + yy + zz);
+        int sl = (int)floor(y[j] * slab_scale);
+        sl = sl < 0 ? 0 : (sl > kObsSlabs - 1 ? kObsSlabs - 1 : sl);
+#pragma unroll
+        for (int q = 0; q < kObsSlabs; ++q) o[3 + q] += sl == q ? px[j] : 0.0;
+    }
+    o[0] += xw[0] - xw[1];
+    o[1] += xw[1] - xw[2];
+    o[2] += xw[3];
+    block_sum<kObsCols>(o, L.red);
+    if (threadIdx.x == 0) {
+        double* out = xs + (size_t)row * kObsCols;
+        const double iv = 1.0 / S.volume;
+        out[0] = o[0] * iv;
+        out[1] = o[1] * iv;
+        out[2] = o[2] / (double)S.n;
+#pragma unroll
+        for (int q = 0; q < kObsSlabs; ++q) out[3 + q] = o[3 + q] * ((double)kObsSlabs * iv);
+    }
 }
 
 // Publish the fixed-point positions of the owned atoms and the wave maxima of the path
@@ -1622,7 +1677,7 @@ __device__ __forceinline__ float2 nl_publish(const SysDev& S, const double (&x)[
     return m;
 }
 
-template <int APT, bool NH>
+template <int APT, bool NH, bool OBS>
 __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L, int kmax,
                                 int nmax) {
     const int T = blockDim.x, t = threadIdx.x;
@@ -1669,7 +1724,9 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     nl_rebuild<APT>(S, dxle, dxq, x, y, z, qx, qy, qz, L, kmax, nmax);
     if (L.misc[1] != 0) health |= kHealthListOverflow;
     nl_inner<APT>(S, dxq, qx, qy, qz, L, nmax, imask);
-    double wpart = nl_forces<APT>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax);
+    double xw[4];
+    double wpart = nl_forces<APT, OBS>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax, xw);
+    double* const xs = OBS ? dsc->xseries : nullptr;
 
     double m0[7] = {0, 0, 0, 0, 0, 0, wpart};
 #pragma unroll
@@ -1686,6 +1743,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     if (done == 0) {
         if (k0 <= 0.0) k0 = 0.5 * m0[0];
         if (t == 0) dsc->series[0] = m0[1] + m0[6];
+        if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, 0, L);
     }
     if (health != 0) todo = 0;
     double pp = m0[0], pxpy = m0[1], pypy = m0[2], fp = m0[3], fxpy = m0[4], ff = m0[5];
@@ -1763,7 +1821,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             for (int j = 0; j < APT; ++j) path_in[j] = 0.f;
             since_in = 0;
         }
-        wpart = nl_forces<APT>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax);
+        wpart = nl_forces<APT, OBS>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax, xw);
         if (nh) {
             // ---- second half: K(tau) S(tau) T(tau), then Z(tau) on the new sum p^2
             const double c2 = exp(-zt * tau);
@@ -1784,6 +1842,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             const double vpxy = m4[1] + m4[2];
             done += 1;
             if (t == 0) dsc->series[done] = vpxy;
+            if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, done, L);
             if (!isfinite(vpxy) || !isfinite(zt) || !isfinite(m4[3])) {
                 health |= kHealthNonFinite;
                 break;
@@ -1837,6 +1896,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
         const double vpxy = pxpy + m[10];
         done += 1;
         if (t == 0) dsc->series[done] = vpxy;
+        if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, done, L);
         if (!isfinite(vpxy) || !isfinite(c) || !isfinite(m[11])) {
             health |= kHealthNonFinite;
             break;
@@ -1873,7 +1933,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 // footprint among its daughters.
 constexpr int kNlJobBytes = 128;
 
-template <int APT, int MAXT, bool NH>
+template <int APT, int MAXT, bool NH, bool OBS>
 __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
     extern __shared__ __align__(32) char smem[];
     int32_t* job = (int32_t*)smem;
@@ -1889,7 +1949,7 @@ __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
         const NlLds L = carve_nl(smem + kNlJobBytes, n, cells, kmax);
         for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
         // run_daughter_nl synchronises before its first use of the counts
-        run_daughter_nl<APT, NH>(d, b.max_steps, L, kmax, n);
+        run_daughter_nl<APT, NH, OBS>(d, b.max_steps, L, kmax, n);
     }
 }
 
@@ -1975,29 +2035,29 @@ static hipError_t launch_daughters_r(const BatchLaunch& b, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-template <int APT, int MAXT, bool NH>
+template <int APT, int MAXT, bool NH, bool OBS>
 static hipError_t launch_nl_t(const BatchLaunch& b, hipStream_t s) {
     if (b.threads > MAXT) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT, NH>,
+    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT, NH, OBS>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
-    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT, NH>), dim3(b.grid), dim3(b.threads),
+    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT, NH, OBS>), dim3(b.grid), dim3(b.threads),
                        b.lds_bytes, s, b);
     return hipGetLastError();
 }
 
-template <bool NH>
+template <bool NH, bool OBS>
 static hipError_t launch_nl(const BatchLaunch& b, hipStream_t s) {
     if (b.threads <= 512) {
         switch (b.apt) {
-            case 1: return launch_nl_t<1, 512, NH>(b, s);
-            case 2: return launch_nl_t<2, 512, NH>(b, s);
-            case 4: return launch_nl_t<4, 512, NH>(b, s);
+            case 1: return launch_nl_t<1, 512, NH, OBS>(b, s);
+            case 2: return launch_nl_t<2, 512, NH, OBS>(b, s);
+            case 4: return launch_nl_t<4, 512, NH, OBS>(b, s);
         }
     } else {
         switch (b.apt) {
-            case 1: return launch_nl_t<1, 1024, NH>(b, s);
-            case 2: return launch_nl_t<2, 1024, NH>(b, s);
-            case 4: return launch_nl_t<4, 1024, NH>(b, s);
+            case 1: return launch_nl_t<1, 1024, NH, OBS>(b, s);
+            case 2: return launch_nl_t<2, 1024, NH, OBS>(b, s);
+            case 4: return launch_nl_t<4, 1024, NH, OBS>(b, s);
         }
     }
     return hipErrorInvalidValue;
@@ -2009,8 +2069,12 @@ hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
     // Nose-Hoover branch's registers (10% on the list form)
     if (b.variant == kVariantNeighbourList) {
         if (b.precision != 1) return hipErrorInvalidValue;
-        return b.thermo ? launch_nl<true>(b, s) : launch_nl<false>(b, s);
+        // the extra observables have their own instantiations, so the plain build carries
+        // none of their registers
+        if (b.obs) return b.thermo ? launch_nl<true, true>(b, s) : launch_nl<false, true>(b, s);
+        return b.thermo ? launch_nl<true, false>(b, s) : launch_nl<false, false>(b, s);
     }
+    if (b.obs) return hipErrorInvalidValue;  // the cell form records P_xy only
     if (b.thermo)
         return b.precision == 0 ? launch_daughters_r<double, true>(b, s)
                                 : launch_daughters_r<float, true>(b, s);

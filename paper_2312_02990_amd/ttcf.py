@@ -22,6 +22,9 @@ TTCF_DAUGHTER_GIK, TTCF_DAUGHTER_NH = 0, 1
 TTCF_OBS_PXY = 0
 TTCF_OBS_WALL_STRESS = 1
 TTCF_OBS_VPROFILE = 2
+TTCF_OBS_N1, TTCF_OBS_N2, TTCF_OBS_ENERGY, TTCF_OBS_SLAB_PX = 3, 4, 5, 6
+TTCF_BULK_SLABS = 8
+OBS_COLS = 3 + TTCF_BULK_SLABS  # columns of ttcf_export_observables
 TTCF_CV_ESTIMATE = 1
 TTCF_CV_CALIBRATE = 2
 
@@ -140,6 +143,9 @@ def lib():
         "ttcf_import_states_zeta": [V, C.c_int32, C.c_int32, D],
         "ttcf_acf": [V, D, C.c_int64, C.c_int32, C.c_double, D, I, D],
         "ttcf_response_modified": [V, C.c_double, C.c_int32, D, D, L64],
+        "ttcf_observable_response_modified": [V, C.c_int32, C.c_double, C.c_int32, D, D, L64],
+        "ttcf_record_observables": [V, C.c_int32],
+        "ttcf_export_observables": [V, C.c_int64, C.c_int32, C.c_int32, D],
         "ttcf_mother_acf": [V, C.c_int32, C.c_int32, C.c_double, D, I, D],
         "ttcf_export_states_zeta": [V, C.c_int32, C.c_int32, D],
         "ttcf_export_mother": [V, C.c_int32, D, D, D, L64],
@@ -230,7 +236,8 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_autotune_export", "ttcf_autotune_import", "ttcf_graph_create",
             "ttcf_graph_launch", "ttcf_graph_replays", "ttcf_graph_destroy",
             "ttcf_import_states_zeta", "ttcf_export_states_zeta", "ttcf_acf", "ttcf_mother_acf",
-            "ttcf_response_modified"]
+            "ttcf_response_modified", "ttcf_observable_response_modified",
+            "ttcf_record_observables", "ttcf_export_observables"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -399,23 +406,47 @@ class Context:
         return groups.value
 
     def ttcf_response(self, n_t: int, gamma_dot_filter: float, observable: int = TTCF_OBS_PXY):
-        """(ttcf_mean, ttcf_se, dav_mean, dav_se, n_states)."""
-        out = [np.zeros(n_t) for _ in range(4)]
+        """(ttcf_mean, ttcf_se, dav_mean, dav_se, n_states); TTCF_OBS_SLAB_PX gives arrays of
+        shape (n_t, TTCF_BULK_SLABS)."""
+        cols = TTCF_BULK_SLABS if observable == TTCF_OBS_SLAB_PX else 1
+        out = [np.zeros(n_t * cols) for _ in range(4)]
         used = C.c_int64(0)
         _check(lib().ttcf_response(self._ctx, int(observable), float(gamma_dot_filter), int(n_t),
                                    *[_dp(o) for o in out], C.byref(used)), "ttcf_response",
                self._ctx)
+        if cols > 1:
+            out = [o.reshape(n_t, cols) for o in out]
         return out[0], out[1], out[2], out[3], used.value
 
-    def ttcf_response_modified(self, n_t: int, gamma_dot_filter: float):
+    def ttcf_response_modified(self, n_t: int, gamma_dot_filter: float,
+                               observable: int = TTCF_OBS_PXY):
         """Eq. (corr_modified): (mean, jackknife se, n_states)."""
-        m = np.zeros(n_t)
-        se = np.zeros(n_t)
+        cols = TTCF_BULK_SLABS if observable == TTCF_OBS_SLAB_PX else 1
+        m = np.zeros(n_t * cols)
+        se = np.zeros(n_t * cols)
         used = C.c_int64(0)
-        _check(lib().ttcf_response_modified(self._ctx, float(gamma_dot_filter), int(n_t), _dp(m),
-                                            _dp(se), C.byref(used)), "ttcf_response_modified",
-               self._ctx)
+        if observable == TTCF_OBS_PXY:
+            rc = lib().ttcf_response_modified(self._ctx, float(gamma_dot_filter), int(n_t), _dp(m),
+                                              _dp(se), C.byref(used))
+        else:
+            rc = lib().ttcf_observable_response_modified(self._ctx, int(observable),
+                                                         float(gamma_dot_filter), int(n_t),
+                                                         _dp(m), _dp(se), C.byref(used))
+        _check(rc, "ttcf_response_modified", self._ctx)
+        if cols > 1:
+            m, se = m.reshape(n_t, cols), se.reshape(n_t, cols)
         return m, se, used.value
+
+    def ttcf_record_observables(self, on: bool = True):
+        _check(lib().ttcf_record_observables(self._ctx, int(bool(on))), "ttcf_record_observables",
+               self._ctx)
+
+    def ttcf_export_observables(self, first: int, count: int, n_t: int):
+        """(count, n_t, OBS_COLS): P_xx - P_yy, P_yy - P_zz, (K + U)/N, slab momentum profile."""
+        out = np.zeros((count, n_t, OBS_COLS))
+        _check(lib().ttcf_export_observables(self._ctx, int(first), int(count), int(n_t),
+                                             _dp(out)), "ttcf_export_observables", self._ctx)
+        return out
 
     # ---- inspection hooks
     def ttcf_sample_states(self, mother: int, n_states: int, steps_between: int):

@@ -227,6 +227,43 @@ def thermostat_leg(T, stream, ctx, mid, s, n_states, nst, gd=1e-2):
     return out
 
 
+def observables_leg(T, stream, ctx, mid, s, n_states, nst, gd=1e-2):
+    """The benchmark's start states run once more with the extra bulk observables recorded
+    (P_xx - P_yy, P_yy - P_zz, energy per atom, y-slab momentum profile): the step kernel's
+    throughput with and without them, and each observable's TTCF and direct average at the
+    end (the slab profile as its largest magnitude over the slabs)."""
+    import torch
+    r, p = ctx.ttcf_export_states(mid, n_states)
+    out = {"gamma_dot": gd, "workload": f"N={s.n}, {n_states} states x 4 mappings x {nst} steps"}
+    rates = {}
+    for rec in (False, True):
+        with T.Context(stream) as c2:
+            m2 = c2.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1),
+                                     r[0], p[0], n_equil=0)
+            c2.ttcf_import_states(m2, r, p)
+            c2.ttcf_record_observables(rec)
+            c2.ttcf_spawn_daughters(m2, n_states, 0, gd, nst)
+            c2.ttcf_step_timing(reset=True)
+            c2.ttcf_step(nst)
+            ms, _ = c2.ttcf_step_timing(reset=True)
+            rates[rec] = 4 * n_states * s.n * nst / (ms / 1e3)
+            if rec:
+                c2.ttcf_accumulate()
+                for name, o in (("n1", T.TTCF_OBS_N1), ("n2", T.TTCF_OBS_N2),
+                                ("energy_per_atom", T.TTCF_OBS_ENERGY),
+                                ("slab_px", T.TTCF_OBS_SLAB_PX)):
+                    tm, tse, dm, dse, _ = c2.ttcf_response(nst + 1, gd, observable=o)
+                    tm, tse, dm, dse = [np.atleast_2d(np.asarray(x).T).T for x in (tm, tse, dm, dse)]
+                    q = int(np.argmax(np.abs(tm[-1])))
+                    out[name] = {"ttcf_end": float(tm[-1, q]), "ttcf_se_end": float(tse[-1, q]),
+                                 "dav_end": float(dm[-1, q]), "dav_se_end": float(dse[-1, q])}
+            torch.cuda.synchronize()
+    out["kernel_atom_steps_per_s"] = rates[True]
+    out["kernel_atom_steps_per_s_without"] = rates[False]
+    out["cost_ratio"] = rates[False] / rates[True]
+    return out
+
+
 def graph_leg(T, stream, n_cells=8, copies=1024, between=100, nst=500, gd=1e-2, replays=3,
               decorrelate=400, seed=7):
     """Whole batch cycles replayed from one captured graph: 1024 persistent copies of the
@@ -462,6 +499,8 @@ def main():
                          "and report the FP32-force error of each response")
     ap.add_argument("--thermostats", type=int, default=1,
                     help="1: also compare isokinetic and Nose-Hoover daughters on the same states")
+    ap.add_argument("--observables", type=int, default=1,
+                    help="1: also measure daughters that record the extra bulk observables")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: also measure whole cycles replayed from a captured graph")
     ap.add_argument("--uneven", type=int, default=1,
@@ -548,6 +587,12 @@ def main():
             thermostats = thermostat_leg(T, stream, ctx, mid, s, args.states, nst)
         except Exception as e:  # the headline line is printed whatever happens here
             thermostats = {"error": repr(e)}
+    observables = None
+    if args.observables:
+        try:
+            observables = observables_leg(T, stream, ctx, mid, s, args.states, nst)
+        except Exception as e:  # the headline line is printed whatever happens here
+            observables = {"error": repr(e)}
     ctx.close()
 
     atom_steps = n_d * s.n * nst
@@ -597,6 +642,8 @@ def main():
         line["precision"] = precision
     if thermostats is not None:
         line["thermostats"] = thermostats
+    if observables is not None:
+        line["observables"] = observables
     if args.graph:
         try:
             line["graph"] = graph_leg(T, stream)

@@ -99,10 +99,15 @@ def _load():
         lib.orc_run_daughters_obs.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double,
                                               D, D, D, C.c_int32, I, I, D, C.c_int64, C.c_int32,
                                               D, C.c_int32, D]
+        lib.orc_colour_run.argtypes = [B, C.c_double, C.c_double, C.c_int32, C.c_double, D, D,
+                                       C.c_int64, D, D, D]
+        lib.orc_run_daughters_colour.argtypes = [B, C.c_double, D, D, C.c_int32, I, I, D,
+                                                 C.c_int64, C.c_int32, D, D, D]
         for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
                    "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
                    "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh",
-                   "orc_observables", "orc_run_daughters_obs"):
+                   "orc_observables", "orc_run_daughters_obs", "orc_colour_run",
+                   "orc_run_daughters_colour"):
             getattr(lib, fn).restype = C.c_int32
         _lib = lib
     return _lib
@@ -281,6 +286,55 @@ def run_daughters_nh(box: Box, states_r, states_p, states_zeta, state_of, map_of
     return out, used
 
 
+def colour_charges(n: int) -> np.ndarray:
+    """Colour charge of each atom: +1 for even index, -1 for odd."""
+    return np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+
+
+def colour_run(box: Box, r, p, fe: float, dt: float, nsteps: int, gik: bool = True,
+               k0: float = 0.0):
+    """Advance one colour-field trajectory in place (orc_colour_run). Returns the series
+    (V J_x, K, U), each of length nsteps+1."""
+    assert r.dtype == np.float64 and p.dtype == np.float64 and r.flags.c_contiguous
+    outs = [np.zeros(nsteps + 1) for _ in range(3)]
+    rc = _load().orc_colour_run(C.byref(box), float(fe), float(dt), int(gik), float(k0), _dp(r),
+                                _dp(p), int(nsteps), *[_dp(o) for o in outs])
+    if rc != 0:
+        raise RuntimeError(f"orc_colour_run failed: {rc}")
+    return outs[0], outs[1], outs[2]
+
+
+def run_daughters_colour(box: Box, states_r, states_p, state_of, map_of, fe_of, dt: float,
+                         nsteps: int, nthreads: int = 0, final_state: bool = False):
+    """Isokinetic colour-field daughters on a CPU thread pool: V J_x (n_d, nsteps+1)
+    [and final r, p] and the number of threads used."""
+    states_r = _f64(states_r)
+    states_p = _f64(states_p)
+    state_of = np.ascontiguousarray(state_of, np.int32)
+    map_of = np.ascontiguousarray(map_of, np.int32)
+    fe_of = _f64(fe_of)
+    nd = len(state_of)
+    out = np.zeros((nd, nsteps + 1))
+    ro = np.zeros((nd, 3 * box.n)) if final_state else None
+    po = np.zeros((nd, 3 * box.n)) if final_state else None
+    if nthreads <= 0:
+        nthreads = os.cpu_count() or 1
+    used = _load().orc_run_daughters_colour(C.byref(box), float(dt), _dp(states_r),
+                                            _dp(states_p), nd, _ip(state_of), _ip(map_of),
+                                            _dp(fe_of), int(nsteps), int(nthreads), _dp(out),
+                                            _dp(ro), _dp(po))
+    if used < 0:
+        raise RuntimeError(f"orc_run_daughters_colour failed: {used}")
+    if final_state:
+        return out, ro, po, used
+    return out, used
+
+
+def omega0_colour(vjx0, fe, temperature):
+    """Dissipation function of the colour field at t=0: Omega = (V/T) F_e J_x(0)."""
+    return (np.asarray(fe, np.float64) / temperature) * np.asarray(vjx0, np.float64)
+
+
 N_SLABS = 8  # slabs of the bulk momentum profile
 
 
@@ -402,7 +456,8 @@ class Response:
     dav_se_paper: np.ndarray        # sigma/sqrt(N_daughters) of B(t)
 
 
-def ttcf_response(b, vpxy0, gamma_of, temperature: float, dt: float, n_maps: int = 4) -> Response:
+def ttcf_response(b, vpxy0, gamma_of, temperature: float, dt: float, n_maps: int = 4,
+                  omega=None) -> Response:
     """TTCF and direct-average responses from per-daughter series.
 
     b[d, k]   : observable B of daughter d at t_k = k dt, k = 0..n_t-1
@@ -419,7 +474,8 @@ def ttcf_response(b, vpxy0, gamma_of, temperature: float, dt: float, n_maps: int
     nd, nt = b.shape
     assert nd % n_maps == 0
     ns = nd // n_maps
-    om = omega0(vpxy0, gamma_of, temperature)  # (nd,)
+    # Omega(0) of each daughter: the shear field's unless given (e.g. omega0_colour)
+    om = omega0(vpxy0, gamma_of, temperature) if omega is None else np.asarray(omega, np.float64)
     ob = om[:, None] * b                       # Omega(0) B(t)
     integ = np.zeros_like(ob)
     integ[:, 1:] = np.cumsum(0.5 * dt * (ob[:, :-1] + ob[:, 1:]), axis=1)

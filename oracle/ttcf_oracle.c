@@ -782,6 +782,73 @@ int32_t orc_nh_sllod_run(const orc_box* b, double gamma_dot, double dt, double t
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* colour field                                                                          */
+/* ------------------------------------------------------------------------------------ */
+
+/* Colour charge of atom i: +1 for even i, -1 for odd i. */
+static double colour_charge(int32_t i) { return (i & 1) ? -1.0 : 1.0; }
+
+/* f_tot = f + c_i F_e along x */
+static void colour_total(int32_t n, const double* f, double fe, double* ft) {
+    memcpy(ft, f, sizeof(double) * 3 * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) ft[i] += colour_charge(i) * fe;
+}
+
+static double colour_current(int32_t n, const double* p) {
+    double s = 0.0;
+    for (int32_t i = 0; i < n; ++i) s += colour_charge(i) * p[i];
+    return s;
+}
+
+int32_t orc_colour_run(const orc_box* b, double fe, double dt, int32_t gik, double k0, double* r,
+                       double* p, int64_t nsteps, double* jx_out, double* ke_out,
+                       double* pe_out) {
+    const int32_t n = b->n;
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* ft = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!f || !ft) {
+        free(f);
+        free(ft);
+        return -2;
+    }
+    double out[3];
+    if (orc_forces(b, 0.0, r, f, out) != 0) {
+        free(f);
+        free(ft);
+        return -1;
+    }
+    colour_total(n, f, fe, ft);
+    if (k0 <= 0.0) k0 = kinetic(n, p);
+    const double h = dt;
+    if (jx_out) jx_out[0] = colour_current(n, p);
+    if (ke_out) ke_out[0] = kinetic(n, p);
+    if (pe_out) pe_out[0] = out[0];
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        if (gik)
+            orc_iso_kick(n, p, ft, 0.5 * h);
+        else
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] += 0.5 * h * ft[c];
+        for (int32_t c = 0; c < 3 * n; ++c) r[c] += h * p[c];
+        wrap_le(b, 0.0, r);
+        orc_forces(b, 0.0, r, f, out);
+        colour_total(n, f, fe, ft);
+        if (gik) {
+            orc_iso_kick(n, p, ft, 0.5 * h);
+            double lam = sqrt(k0 / kinetic(n, p));
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] *= lam;
+        } else {
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] += 0.5 * h * ft[c];
+        }
+        if (jx_out) jx_out[s] = colour_current(n, p);
+        if (ke_out) ke_out[s] = kinetic(n, p);
+        if (pe_out) pe_out[s] = out[0];
+    }
+    free(f);
+    free(ft);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* batch of daughters on a thread pool (one daughter per thread at a time)               */
 /* ------------------------------------------------------------------------------------ */
 
@@ -802,6 +869,8 @@ typedef struct {
     /* per-step observables of orc_observables when obs_out is not NULL */
     int32_t n_slabs;
     double* obs_out;
+    /* colour-field daughters (gamma_of holds F_e, vpxy_out receives V J_x) */
+    int32_t colour;
 } batch_job;
 
 static void* batch_worker(void* arg) {
@@ -820,7 +889,10 @@ static void* batch_worker(void* arg) {
         double* ob = jb->obs_out ? jb->obs_out + (size_t)d * (size_t)(jb->nsteps + 1) *
                                                      (size_t)(3 + jb->n_slabs)
                                  : 0;
-        if (jb->states_zeta) {
+        if (jb->colour) {
+            rc = orc_colour_run(jb->b, jb->gamma_of[d], jb->dt, 1, 0.0, r, p, jb->nsteps, vp, 0,
+                                0);
+        } else if (jb->states_zeta) {
             /* the mappings that reverse the momenta (m = 1, 3) reverse the thermostat too */
             double zt = (jb->map_of[d] & 1) ? -jb->states_zeta[s] : jb->states_zeta[s];
             rc = nh_sllod_run(jb->b, jb->gamma_of[d], jb->dt, jb->temperature, jb->q, jb->nf, r,
@@ -843,14 +915,14 @@ static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
                          double q, double nf, int32_t n_daughters, const int32_t* state_of,
                          const int32_t* map_of, const double* gamma_of, int64_t nsteps,
                          int32_t nthreads, double* vpxy_out, double* r_out, double* p_out,
-                         int32_t n_slabs, double* obs_out);
+                         int32_t n_slabs, double* obs_out, int32_t colour);
 
 int32_t orc_run_daughters(const orc_box* b, double dt, const double* states_r,
                           const double* states_p, int32_t n_daughters, const int32_t* state_of,
                           const int32_t* map_of, const double* gamma_of, int64_t nsteps,
                           int32_t nthreads, double* vpxy_out, double* r_out, double* p_out) {
     return run_batch(b, dt, states_r, states_p, 0, 0.0, 0.0, 0.0, n_daughters, state_of, map_of,
-                     gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out, 0, 0);
+                     gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out, 0, 0, 0);
 }
 
 int32_t orc_run_daughters_nh(const orc_box* b, double dt, double temperature, double q,
@@ -861,7 +933,8 @@ int32_t orc_run_daughters_nh(const orc_box* b, double dt, double temperature, do
                              double* vpxy_out, double* r_out, double* p_out) {
     if (!states_zeta) return -1;
     return run_batch(b, dt, states_r, states_p, states_zeta, temperature, q, nf, n_daughters,
-                     state_of, map_of, gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out, 0, 0);
+                     state_of, map_of, gamma_of, nsteps, nthreads, vpxy_out, r_out, p_out, 0, 0,
+                     0);
 }
 
 int32_t orc_run_daughters_obs(const orc_box* b, double dt, double temperature, double q,
@@ -873,7 +946,16 @@ int32_t orc_run_daughters_obs(const orc_box* b, double dt, double temperature, d
     if (n_slabs < 1 || !obs_out) return -1;
     return run_batch(b, dt, states_r, states_p, states_zeta, temperature, q, nf, n_daughters,
                      state_of, map_of, gamma_of, nsteps, nthreads, vpxy_out, 0, 0, n_slabs,
-                     obs_out);
+                     obs_out, 0);
+}
+
+int32_t orc_run_daughters_colour(const orc_box* b, double dt, const double* states_r,
+                                 const double* states_p, int32_t n_daughters,
+                                 const int32_t* state_of, const int32_t* map_of,
+                                 const double* fe_of, int64_t nsteps, int32_t nthreads,
+                                 double* jx_out, double* r_out, double* p_out) {
+    return run_batch(b, dt, states_r, states_p, 0, 0.0, 0.0, 0.0, n_daughters, state_of, map_of,
+                     fe_of, nsteps, nthreads, jx_out, r_out, p_out, 0, 0, 1);
 }
 
 static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
@@ -881,7 +963,7 @@ static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
                          double q, double nf, int32_t n_daughters, const int32_t* state_of,
                          const int32_t* map_of, const double* gamma_of, int64_t nsteps,
                          int32_t nthreads, double* vpxy_out, double* r_out, double* p_out,
-                         int32_t n_slabs, double* obs_out) {
+                         int32_t n_slabs, double* obs_out, int32_t colour) {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > n_daughters) nthreads = n_daughters > 0 ? n_daughters : 1;
     batch_job* jobs = (batch_job*)calloc((size_t)nthreads, sizeof(batch_job));
@@ -889,7 +971,7 @@ static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
     for (int32_t t = 0; t < nthreads; ++t) {
         batch_job j = {b,      dt,     states_r, states_p, n_daughters, state_of, map_of,
                        gamma_of, nsteps, vpxy_out, r_out,  p_out,       t,        nthreads, 0,
-                       states_zeta, temperature, q, nf, n_slabs, obs_out};
+                       states_zeta, temperature, q, nf, n_slabs, obs_out, colour};
         jobs[t] = j;
         pthread_create(&th[t], 0, batch_worker, &jobs[t]);
     }

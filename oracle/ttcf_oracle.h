@@ -144,6 +144,28 @@ int32_t orc_run_daughters_obs(const orc_box* b, double dt, double temperature, d
                               const double* gamma_of, int64_t nsteps, int32_t nthreads,
                               double* vpxy_out, int32_t n_slabs, double* obs_out);
 
+/* Colour field (the colour-conductivity field of Evans and Morriss): atom i carries the
+ * colour charge c_i = +1 for even i and -1 for odd i, and the field F_e adds c_i F_e along x:
+ *   dr/dt = p,  dp/dt = F + c F_e x_hat - alpha p   (no streaming term, no box shear).
+ * The adiabatic energy changes at dH/dt = F_e sum_i c_i p_x,i = F_e V J_x, so the dissipation
+ * function is Omega = (V/T) F_e J_x and the response is the colour current J_x.
+ * gik = 1: alpha = p.(F + c F_e x_hat)/p.p (kinetic energy held at k0, k0 <= 0: that of the
+ * initial p), each half kick the exact isokinetic flow under the fixed total force, then a
+ * rescale to k0 (round-off only); gik = 0: alpha = 0. Steps K(h/2) D(h) [F(r)] K(h/2).
+ * Per-step outputs (k = 0..nsteps, may be NULL): jx_out = V J_x = sum_i c_i p_x,i, ke_out,
+ * pe_out. */
+int32_t orc_colour_run(const orc_box* b, double fe, double dt, int32_t gik, double k0, double* r,
+                       double* p, int64_t nsteps, double* jx_out, double* ke_out,
+                       double* pe_out);
+
+/* Batch of isokinetic colour-field daughters (orc_colour_run), as orc_run_daughters with the
+ * field strength fe_of[d] in place of the shear rate and V J_x in place of V P_xy. */
+int32_t orc_run_daughters_colour(const orc_box* b, double dt, const double* states_r,
+                                 const double* states_p, int32_t n_daughters,
+                                 const int32_t* state_of, const int32_t* map_of,
+                                 const double* fe_of, int64_t nsteps, int32_t nthreads,
+                                 double* jx_out, double* r_out, double* p_out);
+
 /* Batch of independent GIK-SLLOD daughters on a pool of nthreads threads.
  * Daughter d starts from start state state_of[d] under mapping map_of[d] with shear rate
  * gamma_of[d] and runs nsteps steps; its series V*P_xy(t_k), k = 0..nsteps, goes to

@@ -174,6 +174,8 @@ struct ttcf_ctx {
     double* acc_xd = nullptr;
     double* acc_xi = nullptr;
     std::vector<char> row_x;
+    // external field of each accumulated row (kFieldShear or kFieldColour)
+    std::vector<int32_t> row_field;
     // learned control variate
     int32_t cv_out = 0;          // outputs (time points t_1..t_nout)
     int64_t cv_nparam = 0;
@@ -781,7 +783,7 @@ int32_t ttcf_sample_states(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_
 namespace {
 int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
                    uint32_t mapping_mask, const double* gamma_dot, int32_t n_gamma, int32_t n_steps,
-                   bool prefix_ok, int64_t* out_first);
+                   bool prefix_ok, int64_t* out_first, int32_t field = kFieldShear);
 }
 
 int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
@@ -791,11 +793,18 @@ int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int6
                       false, out_first);
 }
 
+int32_t ttcf_spawn_colour(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
+                          uint32_t mapping_mask, const double* field, int32_t n_field,
+                          int32_t n_steps, int64_t* out_first) {
+    return spawn_impl(c, mother, n_states, steps_between, mapping_mask, field, n_field, n_steps,
+                      false, out_first, kFieldColour);
+}
+
 namespace {
 // prefix_ok: with steps_between == 0, the first n_states stored states may be used
 int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
                    uint32_t mapping_mask, const double* gamma_dot, int32_t n_gamma, int32_t n_steps,
-                   bool prefix_ok, int64_t* out_first) {
+                   bool prefix_ok, int64_t* out_first, int32_t field) {
     if (!c) return TTCF_EINVAL;
     if (mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || steps_between < 0 ||
         (mapping_mask & 0xFu) == 0 || (mapping_mask & ~0xFu) != 0 || !gamma_dot ||
@@ -808,6 +817,17 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
     if (c->record_obs && m.sys.precision != TTCF_PREC_FP32_FORCES)
         return fail(c, TTCF_EINVAL, "the extra observables are recorded by the list form only "
                                     "(FP32 forces)");
+    if (field == kFieldColour) {
+        if (c->record_obs)
+            return fail(c, TTCF_EINVAL, "colour-field daughters record V J_x only: switch the "
+                                        "extra observables off");
+        if (m.sys.precision != TTCF_PREC_FP32_FORCES)
+            return fail(c, TTCF_EINVAL, "colour-field daughters run in the list form (FP32 forces)");
+        if (m.sys.daughter_thermostat != TTCF_DAUGHTER_GIK)
+            return fail(c, TTCF_EINVAL, "colour-field daughters are isokinetic");
+        if (m.dev.n % 2 != 0)
+            return fail(c, TTCF_EINVAL, "the colour field needs an even number of atoms");
+    }
     if (steps_between > 0) {
         int32_t rc = ttcf_sample_states(c, mother, n_states, steps_between);
         if (rc != TTCF_OK) return rc;
@@ -869,7 +889,9 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
             ds.series = b.series + (size_t)(n_steps + 1) * d;
             ds.xseries = b.xseries ? b.xseries + (size_t)(n_steps + 1) * kObsCols * d : nullptr;
             ds.sys = m.dev;
-            ds.gamma_dot = g;
+            ds.gamma_dot = field == kFieldColour ? 0.0 : g;
+            ds.field = field;
+            ds.fe = field == kFieldColour ? g : 0.0;
             ds.k0 = 0.0;
             ds.k = 0;
             ds.n_steps = n_steps;
@@ -941,7 +963,13 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
     L->variant = variant;
     L->kmax = kmax;
     L->thermo = group.empty() ? 0 : group[0]->thermo;
-    for (const DaughterDesc* dp : group) L->obs = L->obs || dp->xseries != nullptr;
+    for (const DaughterDesc* dp : group) {
+        L->obs = L->obs || dp->xseries != nullptr;
+        L->field = L->field || dp->field != kFieldShear;
+    }
+    if (L->field && (L->obs || L->thermo))
+        return fail(c, TTCF_EINVAL, "colour-field daughters cannot share a step call with "
+                                    "daughters recording the extra observables");
     L->lds_bytes = variant == kVariantNeighbourList ? nl_lds
                                                     : lds_bytes_for(nmax, cmax, threads, precision);
     if (L->lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
@@ -1021,6 +1049,9 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         if (d.xseries && !nl)
             return fail(c, TTCF_EINVAL, "daughters recording the extra observables need the "
                                         "neighbour-list form, and this system runs in cells");
+        if (d.field != kFieldShear && !nl)
+            return fail(c, TTCF_EINVAL, "colour-field daughters need the neighbour-list form, "
+                                        "and this system runs in cells");
         groups[2 * (nl ? 0 : 1) + (d.thermo ? 1 : 0)].push_back((int32_t)i);
     }
     const bool any_nl = !groups[0].empty() || !groups[1].empty();
@@ -1510,12 +1541,18 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
         dev_free(d_sub);
         for (size_t q = 0; q < which.size(); ++q) {
             const DaughterDesc& d0 = c->descs[ready[which[q]].first];
-            c->row_gamma.push_back(d0.gamma_dot);
+            const double temp =
+                c->mothers[c->batches[c->live[ready[which[q]].first].batch].mother].sys.temperature;
+            const bool colour = d0.field == kFieldColour;
+            // the row's field strength and coef, Omega(0) = -coef * (series(0) / V): the
+            // series is V P_xy for shear (Omega = -(V/T) gamma_dot P_xy) and V J_x for the
+            // colour field (Omega = +(V/T) F_e J_x)
+            c->row_gamma.push_back(colour ? d0.fe : d0.gamma_dot);
+            c->row_field.push_back(d0.field);
             c->row_dt.push_back(d0.sys.dt);
             c->row_maps.push_back((int32_t)(ready[which[q]].second - ready[which[q]].first));
-            c->row_coef.push_back(d0.sys.volume * d0.gamma_dot /
-                                  c->mothers[c->batches[c->live[ready[which[q]].first].batch].mother]
-                                      .sys.temperature);
+            c->row_coef.push_back(colour ? -d0.sys.volume * d0.fe / temp
+                                         : d0.sys.volume * d0.gamma_dot / temp);
             c->row_nt.push_back(len);
             c->row_health.push_back(hh[q]);
             c->row_x.push_back(has_x[q]);
@@ -1592,6 +1629,7 @@ static_assert(kObsSlabs == TTCF_BULK_SLABS, "slab count of the ABI");
 bool obs_columns(int32_t observable, int* col0, int* ncol) {
     switch (observable) {
         case TTCF_OBS_PXY: *col0 = -1; *ncol = 1; return true;
+        case TTCF_OBS_JX: *col0 = -1; *ncol = 1; return true;  // colour rows hold V J_x there
         case TTCF_OBS_N1: *col0 = 0; *ncol = 1; return true;
         case TTCF_OBS_N2: *col0 = 1; *ncol = 1; return true;
         case TTCF_OBS_ENERGY: *col0 = 2; *ncol = 1; return true;
@@ -1621,8 +1659,10 @@ int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, 
     if (!c || n_t <= 0 || !obs_columns(observable, &col0, &ncol)) return TTCF_EINVAL;
     int32_t rc0 = refresh_row_health(c);
     if (rc0 != TTCF_OK) return rc0;
+    const int32_t want_field = observable == TTCF_OBS_JX ? kFieldColour : kFieldShear;
     std::vector<int32_t> rows;
     for (int64_t r = 0; r < c->acc_rows; ++r) {
+        if (c->row_field[r] != want_field) continue;
         if (gamma_dot_filter > 0.0 && c->row_gamma[r] != gamma_dot_filter) continue;
         if (c->row_health[r] != 0) continue;
         if (gamma_dot_filter <= 0.0 && c->row_gamma[r] == 0.0) continue;
@@ -1890,6 +1930,7 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
         c->row_health.push_back(kRowPending);
         c->row_cv.push_back(0);
         c->row_x.push_back(0);
+        c->row_field.push_back(kFieldShear);
     }
     c->acc_rows += reserve;
     const int32_t zero = 0;
@@ -2013,9 +2054,12 @@ int32_t response_modified_impl(ttcf_ctx* c, int32_t observable, double gamma_dot
         return TTCF_EINVAL;
     int32_t rc = refresh_row_health(c);
     if (rc != TTCF_OK) return rc;
+    const int32_t want_field = observable == TTCF_OBS_JX ? kFieldColour : kFieldShear;
     std::vector<int32_t> rows;
     for (int64_t r = 0; r < c->acc_rows; ++r)
-        if (c->row_gamma[r] == gamma_dot_filter && c->row_health[r] == 0) rows.push_back((int32_t)r);
+        if (c->row_field[r] == want_field && c->row_gamma[r] == gamma_dot_filter &&
+            c->row_health[r] == 0)
+            rows.push_back((int32_t)r);
     if (rows.empty()) return fail(c, TTCF_ESTATE, "no accumulated group matches the filter");
     for (int32_t r : rows) {
         if (c->row_nt[r] < n_t) return fail(c, TTCF_ESTATE, "n_t exceeds a matching group's length");
@@ -2414,6 +2458,8 @@ int32_t cv_features_of(ttcf_ctx* c, int64_t first, int32_t count, float* d_feat,
         if (c->batches[c->live[i].batch].mother != mother)
             return fail(c, TTCF_EINVAL, "daughters of one call must share a mother");
         const DaughterDesc& d = c->descs[i];
+        if (d.field != kFieldShear)
+            return fail(c, TTCF_EINVAL, "the learned control variate serves shear daughters");
         if (d.done < std::max(1, n_out))
             return fail(c, TTCF_ESTATE, "the daughters have not been stepped far enough");
         if (c->live[i].state >= m.n_states)

@@ -72,12 +72,17 @@ struct DaughterDesc {
     // thermostat of the daughter: 0 Gaussian isokinetic, 1 Nose-Hoover (zeta carried from the
     // start state; d zeta/dt = (sum p^2 - nh_target)/nh_q)
     int32_t thermo;
-    int32_t pad2_;
+    int32_t field;      // kFieldShear, or kFieldColour (gamma_dot 0, fe the field strength)
     double zeta;
     double nh_q;
     double nh_target;
     double* xseries;    // (n_steps + 1) x kObsCols extra observables, or null
+    double fe;          // colour field strength F_e (kFieldColour)
 };
+
+// External field of a daughter: SLLOD shear at gamma_dot, or the colour field (charge +1 on
+// even atoms, -1 on odd ones, force charge * F_e along x; series V J_x = sum charge p_x).
+enum Field : int32_t { kFieldShear = 0, kFieldColour = 1 };
 
 enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2, kHealthListOverflow = 4 };
 
@@ -103,6 +108,7 @@ struct BatchLaunch {
     int32_t kmax;          // neighbour-list capacity per atom (neighbour-list form)
     int32_t thermo;        // daughter thermostat of every job (0 isokinetic, 1 Nose-Hoover)
     int32_t obs;           // 1: some job records the extra observables (list form only)
+    int32_t field;         // 1: some job is a colour-field daughter (list form, isokinetic)
     size_t lds_bytes;
 };
 

@@ -1677,7 +1677,10 @@ __device__ __forceinline__ float2 nl_publish(const SysDev& S, const double (&x)[
     return m;
 }
 
-template <int APT, bool NH, bool OBS>
+// COL: the build that also runs colour-field daughters (isokinetic only): atom a carries
+// the colour charge +1 (even a) or -1 (odd a), the field adds charge * F_e to its x force in
+// FP64, there is no shear, and the series records V J_x = sum_a charge p_x,a.
+template <int APT, bool NH, bool OBS, bool COL>
 __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L, int kmax,
                                 int nmax) {
     const int T = blockDim.x, t = threadIdx.x;
@@ -1686,7 +1689,8 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     const SysDev& S = *L.sys;
     const int n = S.n;
     double* st = dsc->state;
-    const double gd = dsc->gamma_dot;
+    const bool col = COL && dsc->field == kFieldColour;  // uniform per job
+    const double gd = col ? 0.0 : dsc->gamma_dot;
     int64_t k = dsc->k;
     int done = dsc->done;
     const int n_steps = dsc->n_steps;
@@ -1718,6 +1722,20 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
         path[j] = 0.f;
         path_in[j] = 0.f;
     }
+    // colour charges (zero past n and for shear daughters) and the field's x force in FP64
+    double cq[APT], ce[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * T;
+        cq[j] = (COL && col && a < n) ? ((a & 1) ? -1.0 : 1.0) : 0.0;
+        ce[j] = COL ? cq[j] * dsc->fe : 0.0;
+    }
+    auto fxd = [&](int j) -> double {
+        if constexpr (COL)
+            return (double)fx[j] + ce[j];
+        else
+            return (double)fx[j];
+    };
     double dxle = le_offset(S, gd, k);
     uint32_t dxq = fix32(dxle, S.fix_scale[0]);
     nl_publish<APT>(S, x, y, z, qx, qy, qz, path, path_in, L);
@@ -1732,17 +1750,17 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
         m0[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-        m0[1] += px[j] * py[j];
+        m0[1] += (COL && col) ? cq[j] * px[j] : px[j] * py[j];
         m0[2] += py[j] * py[j];
-        m0[3] += (double)fx[j] * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
-        m0[4] += (double)fx[j] * py[j];
-        m0[5] += (double)fx[j] * (double)fx[j] + (double)fy[j] * (double)fy[j] +
+        m0[3] += fxd(j) * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
+        m0[4] += fxd(j) * py[j];
+        m0[5] += fxd(j) * fxd(j) + (double)fy[j] * (double)fy[j] +
                  (double)fz[j] * (double)fz[j];
     }
     block_sum<7>(m0, L.red);
     if (done == 0) {
         if (k0 <= 0.0) k0 = 0.5 * m0[0];
-        if (t == 0) dsc->series[0] = m0[1] + m0[6];
+        if (t == 0) dsc->series[0] = (COL && col) ? m0[1] : m0[1] + m0[6];
         if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, 0, L);
     }
     if (health != 0) todo = 0;
@@ -1779,7 +1797,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             const double qxp = g1 * (px[j] - tg * py[j]);
             const double qyp = g1 * py[j];
             const double qzp = g1 * pz[j];
-            px[j] = (qxp + (double)fx[j] * s1) * isd1;
+            px[j] = (qxp + fxd(j) * s1) * isd1;
             py[j] = (qyp + (double)fy[j] * s1) * isd1;
             pz[j] = (qzp + (double)fz[j] * s1) * isd1;
         }
@@ -1854,15 +1872,15 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 #pragma unroll
         for (int j = 0; j < APT; ++j) {
             m[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-            m[1] += px[j] * py[j];
+            m[1] += (COL && col) ? cq[j] * px[j] : px[j] * py[j];
             m[2] += py[j] * py[j];
-            m[3] += (double)fx[j] * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
-            m[4] += (double)fx[j] * py[j];
+            m[3] += fxd(j) * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
+            m[4] += (COL && col) ? cq[j] * fxd(j) : fxd(j) * py[j];
             m[5] += (double)fy[j] * px[j];
-            m[6] += (double)fx[j] * (double)fy[j];
+            m[6] += fxd(j) * (double)fy[j];
             m[7] += (double)fy[j] * py[j];
             m[8] += (double)fy[j] * (double)fy[j];
-            m[9] += (double)fx[j] * (double)fx[j] + (double)fy[j] * (double)fy[j] +
+            m[9] += fxd(j) * fxd(j) + (double)fy[j] * (double)fy[j] +
                     (double)fz[j] * (double)fz[j];
             m[11] += x[j] + y[j] + z[j];
         }
@@ -1880,7 +1898,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
         const double c = sqrt(2.0 * k0 / ppt2);
 #pragma unroll
         for (int j = 0; j < APT; ++j) {
-            const double qxp = (px[j] + (double)fx[j] * s2) * isd2;
+            const double qxp = (px[j] + fxd(j) * s2) * isd2;
             const double qyp = (py[j] + (double)fy[j] * s2) * isd2;
             const double qzp = (pz[j] + (double)fz[j] * s2) * isd2;
             px[j] = c * (qxp - tg * qyp);
@@ -1893,7 +1911,8 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
         fp = c * (fp3 - tg * fxpy3);
         fxpy = c * fxpy3;
         ff = m[9];
-        const double vpxy = pxpy + m[10];
+        // colour: V J_x of the final momenta c (p + s2 F) / sd2 from the charge moments
+        const double vpxy = (COL && col) ? c * (m[1] + s2 * m[4]) * isd2 : pxpy + m[10];
         done += 1;
         if (t == 0) dsc->series[done] = vpxy;
         if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, done, L);
@@ -1933,7 +1952,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 // footprint among its daughters.
 constexpr int kNlJobBytes = 128;
 
-template <int APT, int MAXT, bool NH, bool OBS>
+template <int APT, int MAXT, bool NH, bool OBS, bool COL>
 __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
     extern __shared__ __align__(32) char smem[];
     int32_t* job = (int32_t*)smem;
@@ -1949,7 +1968,7 @@ __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
         const NlLds L = carve_nl(smem + kNlJobBytes, n, cells, kmax);
         for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
         // run_daughter_nl synchronises before its first use of the counts
-        run_daughter_nl<APT, NH, OBS>(d, b.max_steps, L, kmax, n);
+        run_daughter_nl<APT, NH, OBS, COL>(d, b.max_steps, L, kmax, n);
     }
 }
 
@@ -2035,29 +2054,29 @@ static hipError_t launch_daughters_r(const BatchLaunch& b, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-template <int APT, int MAXT, bool NH, bool OBS>
+template <int APT, int MAXT, bool NH, bool OBS, bool COL>
 static hipError_t launch_nl_t(const BatchLaunch& b, hipStream_t s) {
     if (b.threads > MAXT) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT, NH, OBS>,
+    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT, NH, OBS, COL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
-    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT, NH, OBS>), dim3(b.grid), dim3(b.threads),
+    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT, NH, OBS, COL>), dim3(b.grid), dim3(b.threads),
                        b.lds_bytes, s, b);
     return hipGetLastError();
 }
 
-template <bool NH, bool OBS>
+template <bool NH, bool OBS, bool COL>
 static hipError_t launch_nl(const BatchLaunch& b, hipStream_t s) {
     if (b.threads <= 512) {
         switch (b.apt) {
-            case 1: return launch_nl_t<1, 512, NH, OBS>(b, s);
-            case 2: return launch_nl_t<2, 512, NH, OBS>(b, s);
-            case 4: return launch_nl_t<4, 512, NH, OBS>(b, s);
+            case 1: return launch_nl_t<1, 512, NH, OBS, COL>(b, s);
+            case 2: return launch_nl_t<2, 512, NH, OBS, COL>(b, s);
+            case 4: return launch_nl_t<4, 512, NH, OBS, COL>(b, s);
         }
     } else {
         switch (b.apt) {
-            case 1: return launch_nl_t<1, 1024, NH, OBS>(b, s);
-            case 2: return launch_nl_t<2, 1024, NH, OBS>(b, s);
-            case 4: return launch_nl_t<4, 1024, NH, OBS>(b, s);
+            case 1: return launch_nl_t<1, 1024, NH, OBS, COL>(b, s);
+            case 2: return launch_nl_t<2, 1024, NH, OBS, COL>(b, s);
+            case 4: return launch_nl_t<4, 1024, NH, OBS, COL>(b, s);
         }
     }
     return hipErrorInvalidValue;
@@ -2071,10 +2090,17 @@ hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
         if (b.precision != 1) return hipErrorInvalidValue;
         // the extra observables have their own instantiations, so the plain build carries
         // none of their registers
-        if (b.obs) return b.thermo ? launch_nl<true, true>(b, s) : launch_nl<false, true>(b, s);
-        return b.thermo ? launch_nl<true, false>(b, s) : launch_nl<false, false>(b, s);
+        // colour-field daughters: isokinetic, without the extra observables
+        if (b.field) {
+            if (b.thermo || b.obs) return hipErrorInvalidValue;
+            return launch_nl<false, false, true>(b, s);
+        }
+        if (b.obs)
+            return b.thermo ? launch_nl<true, true, false>(b, s)
+                            : launch_nl<false, true, false>(b, s);
+        return b.thermo ? launch_nl<true, false, false>(b, s) : launch_nl<false, false, false>(b, s);
     }
-    if (b.obs) return hipErrorInvalidValue;  // the cell form records P_xy only
+    if (b.obs || b.field) return hipErrorInvalidValue;  // the cell form: shear and P_xy only
     if (b.thermo)
         return b.precision == 0 ? launch_daughters_r<double, true>(b, s)
                                 : launch_daughters_r<float, true>(b, s);

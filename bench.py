@@ -264,6 +264,32 @@ def observables_leg(T, stream, ctx, mid, s, n_states, nst, gd=1e-2):
     return out
 
 
+def colour_leg(T, stream, ctx, mid, s, n_states, nst, fields=(1e-2, 1e-4)):
+    """The benchmark's start states under the colour field instead of shear (charge +1 on
+    even atoms, -1 on odd ones): colour conductivity sigma(t) = <J_x(t)>/F_e by TTCF and by
+    the direct average at the end, with standard errors, and the kernel's throughput."""
+    import torch
+    r, p = ctx.ttcf_export_states(mid, n_states)
+    out = {"workload": f"N={s.n}, {n_states} states x 4 mappings x {nst} steps per field"}
+    for fe in fields:
+        with T.Context(stream) as c2:
+            m2 = c2.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1),
+                                     r[0], p[0], n_equil=0)
+            c2.ttcf_import_states(m2, r, p)
+            c2.ttcf_spawn_colour(m2, n_states, 0, fe, nst)
+            c2.ttcf_step_timing(reset=True)
+            c2.ttcf_step(nst)
+            ms, _ = c2.ttcf_step_timing(reset=True)
+            c2.ttcf_accumulate()
+            tm, tse, dm, dse, used = c2.ttcf_response(nst + 1, 0.0, observable=T.TTCF_OBS_JX)
+            torch.cuda.synchronize()
+        out[f"F_e={fe:g}"] = {"sigma_ttcf_end": float(tm[-1]), "sigma_ttcf_se_end": float(tse[-1]),
+                              "sigma_dav_end": float(dm[-1]), "sigma_dav_se_end": float(dse[-1]),
+                              "n_states": used,
+                              "kernel_atom_steps_per_s": 4 * n_states * s.n * nst / (ms / 1e3)}
+    return out
+
+
 def graph_leg(T, stream, n_cells=8, copies=1024, between=100, nst=500, gd=1e-2, replays=3,
               decorrelate=400, seed=7):
     """Whole batch cycles replayed from one captured graph: 1024 persistent copies of the
@@ -501,6 +527,8 @@ def main():
                     help="1: also compare isokinetic and Nose-Hoover daughters on the same states")
     ap.add_argument("--observables", type=int, default=1,
                     help="1: also measure daughters that record the extra bulk observables")
+    ap.add_argument("--colour", type=int, default=1,
+                    help="1: also measure colour-field daughters on the same start states")
     ap.add_argument("--graph", type=int, default=1,
                     help="1: also measure whole cycles replayed from a captured graph")
     ap.add_argument("--uneven", type=int, default=1,
@@ -593,6 +621,12 @@ def main():
             observables = observables_leg(T, stream, ctx, mid, s, args.states, nst)
         except Exception as e:  # the headline line is printed whatever happens here
             observables = {"error": repr(e)}
+    colour = None
+    if args.colour:
+        try:
+            colour = colour_leg(T, stream, ctx, mid, s, args.states, nst)
+        except Exception as e:  # the headline line is printed whatever happens here
+            colour = {"error": repr(e)}
     ctx.close()
 
     atom_steps = n_d * s.n * nst
@@ -644,6 +678,8 @@ def main():
         line["thermostats"] = thermostats
     if observables is not None:
         line["observables"] = observables
+    if colour is not None:
+        line["colour"] = colour
     if args.graph:
         try:
             line["graph"] = graph_leg(T, stream)

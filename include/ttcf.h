@@ -295,7 +295,10 @@ int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, 
 
 /* Shape of the daughter step kernel (the knobs a tuner searches). variant: 0 automatic,
  * 1 cell list rebuilt every step (FP64 or FP32 forces), 2 neighbour lists of radius
- * r_cut + skin rebuilt when needed (FP32 forces only); threads: workgroup size (0: the
+ * r_cut + skin rebuilt when needed (FP32 forces only; the lists sit in LDS where they fit,
+ * else in per-workgroup global scratch, as for N = 4000), 3 the same with the lists always
+ * in global scratch (for comparison: results equal variant 2's bit for bit); threads:
+ * workgroup size (0: the
  * system's block_threads, else the library's choice: 512 for the list form up to 2048 atoms);
  * skin <= 0 selects the automatic skin (the list-cell grid of a 0.25 sigma skin, with the skin
  * widened to fill those cells); kmax <= 0 selects 24 neighbours per atom, at most 32 (the

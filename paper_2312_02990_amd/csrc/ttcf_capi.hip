@@ -176,6 +176,9 @@ struct ttcf_ctx {
     std::vector<char> row_x;
     // external field of each accumulated row (kFieldShear or kFieldColour)
     std::vector<int32_t> row_field;
+    // list-form scratch for systems whose lists live in global memory
+    uint16_t* nl_scratch = nullptr;
+    size_t nl_scratch_bytes = 0;
     // learned control variate
     int32_t cv_out = 0;          // outputs (time points t_1..t_nout)
     int64_t cv_nparam = 0;
@@ -508,6 +511,7 @@ void ttcf_destroy(ttcf_ctx* c) {
     }
     dev_free(c->acc_xd);
     dev_free(c->acc_xi);
+    dev_free(c->nl_scratch);
     dev_free(c->d_descs);
     dev_free(c->d_order);
     dev_free(c->d_queue);
@@ -928,7 +932,8 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
 // workgroup size; kmax is the list capacity of the neighbour-list form.
 // block_explicit: some member's system fixes its workgroup size (block_threads > 0).
 int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, bool block_explicit,
-                   int variant, int precision, int32_t n_steps, int threads_req, BatchLaunch* L) {
+                   int variant, int precision, int32_t n_steps, int threads_req, BatchLaunch* L,
+                   bool global_lists = false) {
     int nmax = 0, cmax = 0, lcmax = 0, threads = 0, kmax = 0;
     size_t nl_lds = 0;
     bool explicit_threads = threads_req > 0 || block_explicit;
@@ -940,7 +945,7 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
         lcmax = std::max(lcmax, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2]);
         if (variant == kVariantNeighbourList)
             nl_lds = std::max(nl_lds, lds_bytes_nl(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2],
-                                                   d.kmax));
+                                                   d.kmax, global_lists));
         threads = std::max(threads, d.block);
     }
     if (threads_req > 0) threads = threads_req;
@@ -970,6 +975,14 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
     if (L->field && (L->obs || L->thermo))
         return fail(c, TTCF_EINVAL, "colour-field daughters cannot share a step call with "
                                     "daughters recording the extra observables");
+    if (global_lists) {
+        if (L->obs || L->field)
+            return fail(c, TTCF_EINVAL, "systems whose lists do not fit in LDS run shear "
+                                        "daughters recording P_xy only");
+        L->global_lists = 1;
+        for (const DaughterDesc* dp : group)
+            L->nbr_stride = std::max<int64_t>(L->nbr_stride, (int64_t)(dp->kmax + 1) * dp->sys.n);
+    }
     L->lds_bytes = variant == kVariantNeighbourList ? nl_lds
                                                     : lds_bytes_for(nmax, cmax, threads, precision);
     if (L->lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
@@ -1008,14 +1021,36 @@ StepShape resolve_shape(const ttcf_ctx* c, const SysDev& d, int precision, const
 }
 
 // Writes the list grid and capacity of shape e into a descriptor; *nl tells whether it runs in
-// the neighbour-list form (FP32 forces, not forced to cells, and its lists fit in LDS).
+// the neighbour-list form (FP32 forces, not forced to cells), with its lists in LDS when they
+// fit there (and variant 3 does not ask otherwise), else in global scratch
+// (d->global_lists) when the rest of its LDS does.
 int32_t apply_shape(ttcf_ctx* c, const StepShape& e, int precision, DaughterDesc* d, bool* nl) {
     d->kmax = e.kmax;
-    *nl = precision == TTCF_PREC_FP32_FORCES && e.variant != 1 && e.kmax <= kNlMaxKmax &&
-          set_list_grid(&d->sys, e.skin) &&
-          lds_bytes_nl(d->sys.n, d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2], e.kmax) <= c->max_lds;
-    if (e.variant == 2 && !*nl)
+    d->global_lists = 0;
+    *nl = false;
+    if (precision == TTCF_PREC_FP32_FORCES && e.variant != 1 && e.kmax <= kNlMaxKmax &&
+        set_list_grid(&d->sys, e.skin)) {
+        const int cells = d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2];
+        if (e.variant != 3 && lds_bytes_nl(d->sys.n, cells, e.kmax) <= c->max_lds) {
+            *nl = true;
+        } else if (lds_bytes_nl(d->sys.n, cells, e.kmax, true) <= c->max_lds) {
+            *nl = true;
+            d->global_lists = 1;
+        }
+    }
+    if ((e.variant == 2 || e.variant == 3) && !*nl)
         return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
+    return TTCF_OK;
+}
+
+// The context's global list scratch, grown (after the stream drains) to `bytes`.
+int32_t ensure_nl_scratch(ttcf_ctx* c, size_t bytes) {
+    if (bytes <= c->nl_scratch_bytes) return TTCF_OK;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    dev_free(c->nl_scratch);
+    c->nl_scratch = (uint16_t*)dev_alloc(bytes, c->stream);
+    c->nl_scratch_bytes = c->nl_scratch ? bytes : 0;
+    if (!c->nl_scratch) return fail(c, TTCF_ENOMEM, "list scratch allocation failed");
     return TTCF_OK;
 }
 
@@ -1027,10 +1062,11 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     if (c->descs.empty() || n_steps == 0) return TTCF_OK;
     int32_t rc = sync_descs(c);
     if (rc != TTCF_OK) return rc;
-    // daughters still to run; each goes to the neighbour-list form when it may and its lists
-    // fit, else to the cell form; each (form, thermostat) is one persistent launch, largest
-    // systems first. groups[2 form + thermo], form 0 lists, 1 cells
-    std::vector<int32_t> groups[4];
+    // daughters still to run; each goes to the neighbour-list form when it may (lists in LDS
+    // when they fit, else in global scratch), else to the cell form; each (form, thermostat)
+    // is one persistent launch, largest systems first. groups[2 form + thermo], form 0 lists,
+    // 1 cells, 2 lists in global scratch
+    std::vector<int32_t> groups[6];
     std::vector<StepShape> eff(c->descs.size());
     int precision = -1;
     for (size_t i = 0; i < c->descs.size(); ++i) {
@@ -1052,9 +1088,11 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         if (d.field != kFieldShear && !nl)
             return fail(c, TTCF_EINVAL, "colour-field daughters need the neighbour-list form, "
                                         "and this system runs in cells");
-        groups[2 * (nl ? 0 : 1) + (d.thermo ? 1 : 0)].push_back((int32_t)i);
+        const int form = !nl ? 1 : (d.global_lists ? 2 : 0);
+        groups[2 * form + (d.thermo ? 1 : 0)].push_back((int32_t)i);
     }
-    const bool any_nl = !groups[0].empty() || !groups[1].empty();
+    const bool any_nl = !groups[0].empty() || !groups[1].empty() || !groups[4].empty() ||
+                        !groups[5].empty();
     const bool any_cell = !groups[2].empty() || !groups[3].empty();
     if (!any_nl && !any_cell) return TTCF_OK;
     if (any_nl) {
@@ -1078,7 +1116,7 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     c->last_variant = !any_nl ? kVariantCells : (!any_cell ? kVariantNeighbourList : 3);
     size_t offset = 0;
-    for (int gi = 0; gi < 4; ++gi) {
+    for (int gi = 0; gi < 6; ++gi) {
         const int form = gi / 2;
         const std::vector<int32_t>& group = groups[gi];
         if (group.empty()) continue;
@@ -1091,9 +1129,14 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
                              c->mothers[c->batches[c->live[i].batch].mother].sys.block_threads > 0;
         }
         BatchLaunch L{};
-        rc = plan_group(c, ds, block_explicit, form == 0 ? kVariantNeighbourList : kVariantCells,
-                        precision, n_steps, eff[group[0]].threads, &L);
+        rc = plan_group(c, ds, block_explicit, form == 1 ? kVariantCells : kVariantNeighbourList,
+                        precision, n_steps, eff[group[0]].threads, &L, form == 2);
         if (rc != TTCF_OK) return rc;
+        if (form == 2) {
+            rc = ensure_nl_scratch(c, sizeof(uint16_t) * (size_t)L.grid * (size_t)L.nbr_stride);
+            if (rc != TTCF_OK) return rc;
+            L.nbr = c->nl_scratch;
+        }
         L.order = c->d_order + offset;
         offset += group.size();
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1151,7 +1194,7 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
 
 int32_t ttcf_set_step_shape(ttcf_ctx* c, int32_t variant, int32_t threads, double skin,
                             int32_t kmax) {
-    if (!c || variant < 0 || variant > 2 || threads < 0 || threads > kMaxThreads ||
+    if (!c || variant < 0 || variant > 3 || threads < 0 || threads > kMaxThreads ||
         (threads > 0 && threads % 64 != 0) || kmax > kNlMaxKmax)
         return fail(c, TTCF_EINVAL, "bad step shape (kmax is at most 32)");
     c->shape.variant = variant;
@@ -1215,7 +1258,8 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
             if (sh.variant == 2) {
                 SysDev probe = d;
                 set_list_grid(&probe, sh.skin);
-                if (lds_bytes_nl(d.n, probe.lc[0] * probe.lc[1] * probe.lc[2], sh.kmax) > c->max_lds)
+                if (lds_bytes_nl(d.n, probe.lc[0] * probe.lc[1] * probe.lc[2], sh.kmax, true) >
+                    c->max_lds)
                     break;
             }
             // enough copies of the probe states to give every compute unit four daughters,
@@ -1288,7 +1332,9 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
         set_list_grid(&probe, best_shape.skin);
         const int lcn = probe.lc[0] * probe.lc[1] * probe.lc[2];
         const int k = std::min(kNlMaxKmax, best_shape.kmax + 4);
-        if (lds_bytes_nl(d.n, lcn, k) <= c->max_lds) best_shape.kmax = k;
+        // the margin where the lists keep their place (LDS or global)
+        const bool in_lds = lds_bytes_nl(d.n, lcn, best_shape.kmax) <= c->max_lds;
+        if (!in_lds || lds_bytes_nl(d.n, lcn, k) <= c->max_lds) best_shape.kmax = k;
     }
     TunedShape t;
     t.arch = c->arch;
@@ -1911,9 +1957,15 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     std::vector<const DaughterDesc*> hp;
     for (auto& d : hd) hp.push_back(&d);
     BatchLaunch B{};
+    const bool gl = nl && !hd.empty() && hd[0].global_lists;
     rc = plan_group(c, hp, m.sys.block_threads > 0, nl ? kVariantNeighbourList : kVariantCells,
-                    precision, gd->n_steps, shape.threads, &B);
+                    precision, gd->n_steps, shape.threads, &B, gl);
     if (rc != TTCF_OK) return bail(rc, c->err);
+    if (gl) {
+        // the graph owns the list scratch its replays use
+        B.nbr = (uint16_t*)g->get(sizeof(uint16_t) * (size_t)B.grid * (size_t)B.nbr_stride);
+        if (!B.nbr) return bail(TTCF_ENOMEM, "list scratch allocation failed");
+    }
     B.descs = descs;
     B.order = order;
     B.queue = queue;

@@ -78,6 +78,8 @@ struct DaughterDesc {
     double nh_target;
     double* xseries;    // (n_steps + 1) x kObsCols extra observables, or null
     double fe;          // colour field strength F_e (kFieldColour)
+    int32_t global_lists;  // list form with the lists in global scratch (set by the host)
+    int32_t pad3_;
 };
 
 // External field of a daughter: SLLOD shear at gamma_dot, or the colour field (charge +1 on
@@ -109,6 +111,9 @@ struct BatchLaunch {
     int32_t thermo;        // daughter thermostat of every job (0 isokinetic, 1 Nose-Hoover)
     int32_t obs;           // 1: some job records the extra observables (list form only)
     int32_t field;         // 1: some job is a colour-field daughter (list form, isokinetic)
+    int32_t global_lists;  // 1: list form with the lists in global scratch
+    uint16_t* nbr;         // global_lists: grid x nbr_stride list entries
+    int64_t nbr_stride;    // >= (kmax + 1) n of every job
     size_t lds_bytes;
 };
 
@@ -214,7 +219,8 @@ int pick_apt(int n, int threads);
 size_t lds_bytes_for(int nmax, int cmax, int threads, int precision);
 // LDS of the neighbour-list step kernel for one daughter of n atoms, `cells` list cells and
 // list capacity kmax (a launch needs the largest over its daughters)
-size_t lds_bytes_nl(int n, int cells, int kmax);
+// LDS of one list-form job; global_lists: the lists themselves in global scratch
+size_t lds_bytes_nl(int n, int cells, int kmax, bool global_lists = false);
 
 hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s);
 hipError_t launch_mothers(const MotherLaunch* dev_ms, int count, const MotherLaunch& shape,

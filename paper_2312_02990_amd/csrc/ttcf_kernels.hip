@@ -1303,7 +1303,9 @@ struct NlPlan {
     size_t posq, nbr, ncnt, cnt, start, sid, rowinfo, red, scan, wmax, misc, sys, total;
 };
 
-__host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax) {
+// global_lists: the lists live in per-workgroup global scratch instead (systems whose lists
+// do not fit in LDS); everything else stays in LDS.
+__host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax, bool global_lists = false) {
     NlPlan p;
     size_t off = 0;
     auto take = [&](size_t bytes, size_t al) {
@@ -1313,7 +1315,8 @@ __host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax) {
         return at;
     };
     p.posq = take(16 * (size_t)nmax, 16);
-    p.nbr = take(2 * (size_t)(kmax + 1) * nmax, 16);  // row kmax: sink for rejected candidates
+    // row kmax: sink for rejected candidates
+    p.nbr = global_lists ? 0 : take(2 * (size_t)(kmax + 1) * nmax, 16);
     p.ncnt = take(4 * (size_t)nmax, 16);
     p.cnt = take(4 * (size_t)cmax, 16);
     p.start = take(4 * (size_t)(cmax + 1), 16);
@@ -1328,11 +1331,12 @@ __host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax) {
     return p;
 }
 
-__device__ inline NlLds carve_nl(char* base, int nmax, int cmax, int kmax) {
-    NlPlan p = plan_nl(nmax, cmax, kmax);
+__device__ inline NlLds carve_nl(char* base, int nmax, int cmax, int kmax,
+                                 uint16_t* global_nbr = nullptr) {
+    NlPlan p = plan_nl(nmax, cmax, kmax, global_nbr != nullptr);
     NlLds L;
     L.posq = (uint4*)(base + p.posq);
-    L.nbr = (uint16_t*)(base + p.nbr);
+    L.nbr = global_nbr ? global_nbr : (uint16_t*)(base + p.nbr);
     L.ncnt = (uint32_t*)(base + p.ncnt);
     L.cnt = (int32_t*)(base + p.cnt);
     L.start = (int32_t*)(base + p.start);
@@ -1952,7 +1956,8 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 // footprint among its daughters.
 constexpr int kNlJobBytes = 128;
 
-template <int APT, int MAXT, bool NH, bool OBS, bool COL>
+// GL: the lists of each workgroup in global scratch (b.nbr, b.nbr_stride entries apart).
+template <int APT, int MAXT, bool NH, bool OBS, bool COL, bool GL>
 __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
     extern __shared__ __align__(32) char smem[];
     int32_t* job = (int32_t*)smem;
@@ -1965,7 +1970,8 @@ __global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
         DaughterDesc* d = &b.descs[b.order[j]];
         const int n = d->sys.n, kmax = d->kmax;
         const int cells = d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2];
-        const NlLds L = carve_nl(smem + kNlJobBytes, n, cells, kmax);
+        const NlLds L = carve_nl(smem + kNlJobBytes, n, cells, kmax,
+                                 GL ? b.nbr + (size_t)blockIdx.x * b.nbr_stride : nullptr);
         for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
         // run_daughter_nl synchronises before its first use of the counts
         run_daughter_nl<APT, NH, OBS, COL>(d, b.max_steps, L, kmax, n);
@@ -2016,8 +2022,8 @@ int pick_apt(int n, int threads) {
     return -1;
 }
 
-size_t lds_bytes_nl(int n, int cells, int kmax) {
-    return kNlJobBytes + plan_nl(n, cells, kmax).total;
+size_t lds_bytes_nl(int n, int cells, int kmax, bool global_lists) {
+    return kNlJobBytes + plan_nl(n, cells, kmax, global_lists).total;
 }
 
 size_t lds_bytes_for(int nmax, int cmax, int threads, int precision) {
@@ -2054,29 +2060,29 @@ static hipError_t launch_daughters_r(const BatchLaunch& b, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-template <int APT, int MAXT, bool NH, bool OBS, bool COL>
+template <int APT, int MAXT, bool NH, bool OBS, bool COL, bool GL>
 static hipError_t launch_nl_t(const BatchLaunch& b, hipStream_t s) {
     if (b.threads > MAXT) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT, NH, OBS, COL>,
+    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT, NH, OBS, COL, GL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
-    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT, NH, OBS, COL>), dim3(b.grid), dim3(b.threads),
-                       b.lds_bytes, s, b);
+    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT, NH, OBS, COL, GL>), dim3(b.grid),
+                       dim3(b.threads), b.lds_bytes, s, b);
     return hipGetLastError();
 }
 
-template <bool NH, bool OBS, bool COL>
+template <bool NH, bool OBS, bool COL, bool GL = false>
 static hipError_t launch_nl(const BatchLaunch& b, hipStream_t s) {
     if (b.threads <= 512) {
         switch (b.apt) {
-            case 1: return launch_nl_t<1, 512, NH, OBS, COL>(b, s);
-            case 2: return launch_nl_t<2, 512, NH, OBS, COL>(b, s);
-            case 4: return launch_nl_t<4, 512, NH, OBS, COL>(b, s);
+            case 1: return launch_nl_t<1, 512, NH, OBS, COL, GL>(b, s);
+            case 2: return launch_nl_t<2, 512, NH, OBS, COL, GL>(b, s);
+            case 4: return launch_nl_t<4, 512, NH, OBS, COL, GL>(b, s);
         }
     } else {
         switch (b.apt) {
-            case 1: return launch_nl_t<1, 1024, NH, OBS, COL>(b, s);
-            case 2: return launch_nl_t<2, 1024, NH, OBS, COL>(b, s);
-            case 4: return launch_nl_t<4, 1024, NH, OBS, COL>(b, s);
+            case 1: return launch_nl_t<1, 1024, NH, OBS, COL, GL>(b, s);
+            case 2: return launch_nl_t<2, 1024, NH, OBS, COL, GL>(b, s);
+            case 4: return launch_nl_t<4, 1024, NH, OBS, COL, GL>(b, s);
         }
     }
     return hipErrorInvalidValue;
@@ -2090,6 +2096,12 @@ hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
         if (b.precision != 1) return hipErrorInvalidValue;
         // the extra observables have their own instantiations, so the plain build carries
         // none of their registers
+        // lists in global scratch: shear daughters of either thermostat, P_xy only
+        if (b.global_lists) {
+            if (b.obs || b.field || !b.nbr) return hipErrorInvalidValue;
+            return b.thermo ? launch_nl<true, false, false, true>(b, s)
+                            : launch_nl<false, false, false, true>(b, s);
+        }
         // colour-field daughters: isokinetic, without the extra observables
         if (b.field) {
             if (b.thermo || b.obs) return hipErrorInvalidValue;

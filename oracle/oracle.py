@@ -101,13 +101,16 @@ def _load():
                                               D, C.c_int32, D]
         lib.orc_colour_run.argtypes = [B, C.c_double, C.c_double, C.c_int32, C.c_double, D, D,
                                        C.c_int64, D, D, D]
-        lib.orc_run_daughters_colour.argtypes = [B, C.c_double, D, D, C.c_int32, I, I, D,
-                                                 C.c_int64, C.c_int32, D, D, D]
+        lib.orc_run_daughters_colour.argtypes = [B, C.c_double, D, D, D, C.c_double, C.c_double,
+                                                 C.c_double, C.c_int32, I, I, D, C.c_int64,
+                                                 C.c_int32, D, D, D]
+        lib.orc_nh_colour_run.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double,
+                                          C.c_double, D, D, D, C.c_int64, D, D, D, D]
         for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
                    "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
                    "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh",
                    "orc_observables", "orc_run_daughters_obs", "orc_colour_run",
-                   "orc_run_daughters_colour"):
+                   "orc_run_daughters_colour", "orc_nh_colour_run"):
             getattr(lib, fn).restype = C.c_int32
         _lib = lib
     return _lib
@@ -304,10 +307,28 @@ def colour_run(box: Box, r, p, fe: float, dt: float, nsteps: int, gik: bool = Tr
     return outs[0], outs[1], outs[2]
 
 
+def nh_colour_run(box: Box, r, p, zeta: float, fe: float, dt: float, temperature: float,
+                  q: float, nf: float, nsteps: int):
+    """Advance one Nose-Hoover colour-field trajectory in place (orc_nh_colour_run). Returns
+    (V J_x, K, U, zeta series, zeta_final), series of length nsteps+1."""
+    assert r.dtype == np.float64 and p.dtype == np.float64 and r.flags.c_contiguous
+    outs = [np.zeros(nsteps + 1) for _ in range(4)]
+    z = np.array([float(zeta)])
+    rc = _load().orc_nh_colour_run(C.byref(box), float(fe), float(dt), float(temperature),
+                                   float(q), float(nf), _dp(r), _dp(p), _dp(z), int(nsteps),
+                                   *[_dp(o) for o in outs])
+    if rc != 0:
+        raise RuntimeError(f"orc_nh_colour_run failed: {rc}")
+    return outs[0], outs[1], outs[2], outs[3], float(z[0])
+
+
 def run_daughters_colour(box: Box, states_r, states_p, state_of, map_of, fe_of, dt: float,
-                         nsteps: int, nthreads: int = 0, final_state: bool = False):
-    """Isokinetic colour-field daughters on a CPU thread pool: V J_x (n_d, nsteps+1)
-    [and final r, p] and the number of threads used."""
+                         nsteps: int, nthreads: int = 0, final_state: bool = False,
+                         states_zeta=None, temperature: float = 0.0, q: float = 0.0,
+                         nf: float = 0.0):
+    """Colour-field daughters on a CPU thread pool (isokinetic, or Nose-Hoover from each
+    state's zeta when states_zeta is given): V J_x (n_d, nsteps+1) [and final r, p] and the
+    number of threads used."""
     states_r = _f64(states_r)
     states_p = _f64(states_p)
     state_of = np.ascontiguousarray(state_of, np.int32)
@@ -319,8 +340,10 @@ def run_daughters_colour(box: Box, states_r, states_p, state_of, map_of, fe_of, 
     po = np.zeros((nd, 3 * box.n)) if final_state else None
     if nthreads <= 0:
         nthreads = os.cpu_count() or 1
+    zeta = _f64(states_zeta) if states_zeta is not None else None
     used = _load().orc_run_daughters_colour(C.byref(box), float(dt), _dp(states_r),
-                                            _dp(states_p), nd, _ip(state_of), _ip(map_of),
+                                            _dp(states_p), _dp(zeta), float(temperature),
+                                            float(q), float(nf), nd, _ip(state_of), _ip(map_of),
                                             _dp(fe_of), int(nsteps), int(nthreads), _dp(out),
                                             _dp(ro), _dp(po))
     if used < 0:

@@ -848,6 +848,59 @@ int32_t orc_colour_run(const orc_box* b, double fe, double dt, int32_t gik, doub
     return 0;
 }
 
+/* The colour field with the Nose-Hoover multiplier of Eq. (system1) in place of the Gaussian
+ * one: dp/dt = F + c F_e x_hat - zeta p, d zeta/dt = (sum p^2 - nf T)/q. The splitting of
+ * nh_sllod_run without its shear part, each part exact:
+ *   Z(h/2) T(h/2) K(h/2) D(h) [F(r)] K(h/2) T(h/2) Z(h/2)
+ * with K the kick under the total force F + c F_e x_hat. */
+int32_t orc_nh_colour_run(const orc_box* b, double fe, double dt, double temperature, double q,
+                          double nf, double* r, double* p, double* zeta, int64_t nsteps,
+                          double* jx_out, double* ke_out, double* pe_out, double* zeta_out) {
+    const int32_t n = b->n;
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    double* ft = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!f || !ft) {
+        free(f);
+        free(ft);
+        return -2;
+    }
+    double out[3];
+    if (orc_forces(b, 0.0, r, f, out) != 0) {
+        free(f);
+        free(ft);
+        return -1;
+    }
+    colour_total(n, f, fe, ft);
+    const double h = dt, tau = 0.5 * dt;
+    double zt = *zeta;
+    if (jx_out) jx_out[0] = colour_current(n, p);
+    if (ke_out) ke_out[0] = kinetic(n, p);
+    if (pe_out) pe_out[0] = out[0];
+    if (zeta_out) zeta_out[0] = zt;
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
+        double sc = exp(-zt * tau);
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] *= sc;
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] += tau * ft[c];
+        for (int32_t c = 0; c < 3 * n; ++c) r[c] += h * p[c];
+        wrap_le(b, 0.0, r);
+        orc_forces(b, 0.0, r, f, out);
+        colour_total(n, f, fe, ft);
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] += tau * ft[c];
+        sc = exp(-zt * tau);
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] *= sc;
+        zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
+        if (jx_out) jx_out[s] = colour_current(n, p);
+        if (ke_out) ke_out[s] = kinetic(n, p);
+        if (pe_out) pe_out[s] = out[0];
+        if (zeta_out) zeta_out[s] = zt;
+    }
+    *zeta = zt;
+    free(f);
+    free(ft);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* batch of daughters on a thread pool (one daughter per thread at a time)               */
 /* ------------------------------------------------------------------------------------ */
@@ -889,7 +942,11 @@ static void* batch_worker(void* arg) {
         double* ob = jb->obs_out ? jb->obs_out + (size_t)d * (size_t)(jb->nsteps + 1) *
                                                      (size_t)(3 + jb->n_slabs)
                                  : 0;
-        if (jb->colour) {
+        if (jb->colour && jb->states_zeta) {
+            double zt = (jb->map_of[d] & 1) ? -jb->states_zeta[s] : jb->states_zeta[s];
+            rc = orc_nh_colour_run(jb->b, jb->gamma_of[d], jb->dt, jb->temperature, jb->q, jb->nf,
+                                   r, p, &zt, jb->nsteps, vp, 0, 0, 0);
+        } else if (jb->colour) {
             rc = orc_colour_run(jb->b, jb->gamma_of[d], jb->dt, 1, 0.0, r, p, jb->nsteps, vp, 0,
                                 0);
         } else if (jb->states_zeta) {
@@ -950,12 +1007,13 @@ int32_t orc_run_daughters_obs(const orc_box* b, double dt, double temperature, d
 }
 
 int32_t orc_run_daughters_colour(const orc_box* b, double dt, const double* states_r,
-                                 const double* states_p, int32_t n_daughters,
+                                 const double* states_p, const double* states_zeta,
+                                 double temperature, double q, double nf, int32_t n_daughters,
                                  const int32_t* state_of, const int32_t* map_of,
                                  const double* fe_of, int64_t nsteps, int32_t nthreads,
                                  double* jx_out, double* r_out, double* p_out) {
-    return run_batch(b, dt, states_r, states_p, 0, 0.0, 0.0, 0.0, n_daughters, state_of, map_of,
-                     fe_of, nsteps, nthreads, jx_out, r_out, p_out, 0, 0, 1);
+    return run_batch(b, dt, states_r, states_p, states_zeta, temperature, q, nf, n_daughters,
+                     state_of, map_of, fe_of, nsteps, nthreads, jx_out, r_out, p_out, 0, 0, 1);
 }
 
 static int32_t run_batch(const orc_box* b, double dt, const double* states_r,

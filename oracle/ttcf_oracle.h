@@ -158,10 +158,21 @@ int32_t orc_colour_run(const orc_box* b, double fe, double dt, int32_t gik, doub
                        double* p, int64_t nsteps, double* jx_out, double* ke_out,
                        double* pe_out);
 
-/* Batch of isokinetic colour-field daughters (orc_colour_run), as orc_run_daughters with the
- * field strength fe_of[d] in place of the shear rate and V J_x in place of V P_xy. */
+/* The colour field with the Nose-Hoover multiplier of Eq. (system1): dp/dt = F + c F_e x_hat
+ * - zeta p, d zeta/dt = (sum p^2 - nf T)/q; steps Z T K D K T Z over half steps (the
+ * splitting of orc_nh_sllod_run without its shear part). Outputs as orc_nh_sllod_run, with
+ * jx_out = V J_x in place of V P_xy. */
+int32_t orc_nh_colour_run(const orc_box* b, double fe, double dt, double temperature, double q,
+                          double nf, double* r, double* p, double* zeta, int64_t nsteps,
+                          double* jx_out, double* ke_out, double* pe_out, double* zeta_out);
+
+/* Batch of colour-field daughters, as orc_run_daughters with the field strength fe_of[d] in
+ * place of the shear rate and V J_x in place of V P_xy: isokinetic (orc_colour_run) when
+ * states_zeta is NULL, else Nose-Hoover (orc_nh_colour_run) from each state's zeta, reversed
+ * by the mappings that reverse the momenta (m = 1, 3). */
 int32_t orc_run_daughters_colour(const orc_box* b, double dt, const double* states_r,
-                                 const double* states_p, int32_t n_daughters,
+                                 const double* states_p, const double* states_zeta,
+                                 double temperature, double q, double nf, int32_t n_daughters,
                                  const int32_t* state_of, const int32_t* map_of,
                                  const double* fe_of, int64_t nsteps, int32_t nthreads,
                                  double* jx_out, double* r_out, double* p_out);

@@ -115,3 +115,43 @@ def test_weak_field_ttcf_is_the_green_kubo_integral(orc):
     # the initial rise is (V/T) <J(0)^2> dt / 2 per step, positive; a field term of the wrong
     # sign in Omega would turn the whole curve over
     assert gk[1] > 0 and resp.ttcf[1] > 0
+
+
+def test_nose_hoover_colour_step(orc, liquid):
+    """Nose-Hoover colour daughters: at F_e = 0 the zero-shear Nose-Hoover SLLOD step; the
+    extended energy K + U + Q zeta^2/2 + nf T int zeta changes by the field work
+    F_e int V J_x with a second-order residual; (p, zeta) -> (-p, -zeta) retraces the path under
+    the same field."""
+    s, box, st = liquid
+    q = orc.nh_q(s.nf, s.temperature, TAU)
+    z0 = 0.3
+    r1, p1 = st.r.copy(), st.p.copy()
+    orc.nh_colour_run(box, r1, p1, z0, 0.0, s.dt, s.temperature, q, s.nf, 80)
+    r2, p2 = st.r.copy(), st.p.copy()
+    orc.nh_sllod_run(box, r2, p2, z0, 0.0, s.dt, s.temperature, q, s.nf, 80)
+    np.testing.assert_array_equal(r1, r2)
+    np.testing.assert_array_equal(p1, p2)
+
+    fe = 0.6
+
+    def residual(dt, nsteps):
+        r, p = st.r.copy(), st.p.copy()
+        j, k, u, zs, _ = orc.nh_colour_run(box, r, p, z0, fe, dt, s.temperature, q, s.nf, nsteps)
+        izeta = np.concatenate([[0.0], np.cumsum(0.5 * dt * (zs[1:] + zs[:-1]))])
+        h = k + u + 0.5 * q * zs ** 2 + s.nf * s.temperature * izeta
+        work = fe * np.concatenate([[0.0], np.cumsum(0.5 * dt * (j[1:] + j[:-1]))])
+        return np.abs((h - h[0]) - work).max(), np.abs(work).max()
+
+    res1, work = residual(s.dt, 200)
+    res2, _ = residual(s.dt / 2, 400)
+    assert work > 20 * res1
+    assert 3.0 < res1 / res2 < 5.0
+    r, p = st.r.copy(), st.p.copy()
+    *_, z1 = orc.nh_colour_run(box, r, p, z0, fe, s.dt, s.temperature, q, s.nf, 300)
+    p = -p
+    *_, z2 = orc.nh_colour_run(box, r, p, -z1, fe, s.dt, s.temperature, q, s.nf, 300)
+    dr = r - st.r
+    dr -= s.box * np.rint(dr / s.box)
+    assert np.abs(dr).max() < 1e-8
+    assert np.abs(-p - st.p).max() < 1e-8
+    assert abs(-z2 - z0) < 1e-9

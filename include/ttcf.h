@@ -134,15 +134,17 @@ int32_t ttcf_spawn_daughters(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
  * own dissipation function. The colour field (the colour-conductivity field of Evans and
  * Morriss; the paper names no second field): atom i carries the colour charge +1 (even i)
  * or -1 (odd i), and the field adds charge * F_e along x; no streaming term, no box shear.
- * Daughters are isokinetic, dp/dt = F + c F_e x_hat - alpha p with alpha keeping p.p fixed;
+ * Daughters follow the mother system's daughter thermostat: isokinetic, dp/dt = F + c F_e x_hat
+ * - alpha p with alpha keeping p.p fixed, or Nose-Hoover (alpha = zeta of Eq. system1, carried
+ * from the start state and reversed by mappings 1 and 3);
  * B(t) = J_x = (1/V) sum_i c_i p_x,i, Omega(0) = (V/T) F_e J_x(0) (from dH/dt = F_e V J_x).
  * The four mappings of Eq. (mappings) apply unchanged: J_x(0) takes the signs (+, -, -, +).
  * Arguments as ttcf_spawn_daughters, with the field strengths F_e in place of the shear
  * rates. The recorded series (ttcf_export_series) holds V J_x(t_k); ttcf_accumulate folds
  * these groups and ttcf_response(ctx, TTCF_OBS_JX, F_e, ...) returns <J_x(t)> (per unit
- * field, the colour conductivity, when the filter is <= 0). Neighbour-list form only:
- * TTCF_EINVAL for FP64 forces, Nose-Hoover daughters, an odd atom count, or with the extra
- * observables switched on; stepping them in the cell form also fails with TTCF_EINVAL. */
+ * field, the colour conductivity, when the filter is <= 0). Neighbour-list form with the lists
+ * in LDS only: TTCF_EINVAL for FP64 forces, an odd atom count, or with the extra observables
+ * switched on; stepping them in the cell form or with global lists also fails (TTCF_EINVAL). */
 int32_t ttcf_spawn_colour(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
                           int64_t steps_between, uint32_t mapping_mask, const double* field,
                           int32_t n_field, int32_t n_steps, int64_t* out_first);

@@ -827,8 +827,6 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
                                         "extra observables off");
         if (m.sys.precision != TTCF_PREC_FP32_FORCES)
             return fail(c, TTCF_EINVAL, "colour-field daughters run in the list form (FP32 forces)");
-        if (m.sys.daughter_thermostat != TTCF_DAUGHTER_GIK)
-            return fail(c, TTCF_EINVAL, "colour-field daughters are isokinetic");
         if (m.dev.n % 2 != 0)
             return fail(c, TTCF_EINVAL, "the colour field needs an even number of atoms");
     }
@@ -972,7 +970,7 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
         L->obs = L->obs || dp->xseries != nullptr;
         L->field = L->field || dp->field != kFieldShear;
     }
-    if (L->field && (L->obs || L->thermo))
+    if (L->field && L->obs)
         return fail(c, TTCF_EINVAL, "colour-field daughters cannot share a step call with "
                                     "daughters recording the extra observables");
     if (global_lists) {

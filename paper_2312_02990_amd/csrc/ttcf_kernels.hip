@@ -1681,7 +1681,7 @@ __device__ __forceinline__ float2 nl_publish(const SysDev& S, const double (&x)[
     return m;
 }
 
-// COL: the build that also runs colour-field daughters (isokinetic only): atom a carries
+// COL: the build that also runs colour-field daughters (either thermostat): atom a carries
 // the colour charge +1 (even a) or -1 (odd a), the field adds charge * F_e to its x force in
 // FP64, there is no shear, and the series records V J_x = sum_a charge p_x,a.
 template <int APT, bool NH, bool OBS, bool COL>
@@ -1784,7 +1784,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 #pragma unroll
             for (int j = 0; j < APT; ++j) {
                 const double qy = c1 * py[j];
-                px[j] = c1 * px[j] - tg * qy + tau * (double)fx[j];
+                px[j] = c1 * px[j] - tg * qy + tau * fxd(j);
                 py[j] = qy + tau * (double)fy[j];
                 pz[j] = c1 * pz[j] + tau * (double)fz[j];
             }
@@ -1851,17 +1851,17 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
 #pragma unroll
             for (int j = 0; j < APT; ++j) {
                 const double qy = py[j] + tau * (double)fy[j];
-                px[j] = c2 * (px[j] + tau * (double)fx[j] - tg * qy);
+                px[j] = c2 * (px[j] + tau * fxd(j) - tg * qy);
                 py[j] = c2 * qy;
                 pz[j] = c2 * (pz[j] + tau * (double)fz[j]);
                 m4[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                m4[1] += px[j] * py[j];
+                m4[1] += (COL && col) ? cq[j] * px[j] : px[j] * py[j];
                 m4[3] += x[j] + y[j] + z[j];
             }
             block_sum<4>(m4, L.red);
             pp = m4[0];
             zt += tau * (pp - nh_tgt) * nh_iq;
-            const double vpxy = m4[1] + m4[2];
+            const double vpxy = (COL && col) ? m4[1] : m4[1] + m4[2];
             done += 1;
             if (t == 0) dsc->series[done] = vpxy;
             if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, done, L);
@@ -2104,8 +2104,8 @@ hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
         }
         // colour-field daughters: isokinetic, without the extra observables
         if (b.field) {
-            if (b.thermo || b.obs) return hipErrorInvalidValue;
-            return launch_nl<false, false, true>(b, s);
+            if (b.obs) return hipErrorInvalidValue;
+            return b.thermo ? launch_nl<true, false, true>(b, s) : launch_nl<false, false, true>(b, s);
         }
         if (b.obs)
             return b.thermo ? launch_nl<true, true, false>(b, s)

@@ -326,12 +326,13 @@ def graph_leg(T, stream, n_cells=8, copies=1024, between=100, nst=500, gd=1e-2, 
 
 
 def channel_leg(T, stream, n_states=256, nst=1000, speeds=(1e-2, 1e-4), n_equil=2000,
-                between=20, seed=4):
+                between=20, seed=4, decorrelate=200, kick=0.05):
     """The confined channel at full size: 12000 fluid + 2 x 3000 tethered wall atoms, LJ
     with wetting factors 1.2 / 0.6325, r_c = 2.5, k = 150, wall thermostat at T = 1,
-    dt = 0.005. One mother equilibrates n_equil steps and is sampled every `between` steps
-    (a throughput workload: the paper samples 5 time units apart); each lattice speed gets
-    n_states x 4 daughters of nst steps in one launch."""
+    dt = 0.005. One mother equilibrates n_equil steps; n_states kicked copies of it then run
+    `decorrelate` + `between` steps in one launch and each saves one start state (the paper
+    samples one mother 5 time units apart); each lattice speed gets n_states x 4 daughters
+    of nst steps in one launch."""
     import torch
     import ttcf_inputs as I
     g = I.ChannelSystem()
@@ -342,10 +343,18 @@ def channel_leg(T, stream, n_states=256, nst=1000, speeds=(1e-2, 1e-4), n_equil=
     with T.ChannelContext(T.make_channel(g), r, p, lat, stream) as ctx:
         t0 = time.perf_counter()
         ctx.run_mother(n_equil)
-        ctx.sample_states(n_states, between)
+        torch.cuda.synchronize()
+        serial_s = time.perf_counter() - t0
+        ctx.sample_states_replicated(n_states, seeded_kicks(n_states, g.n, kick, seed + 1),
+                                     decorrelate, 1, between)
         torch.cuda.synchronize()
         out["mother_s"] = time.perf_counter() - t0
-        out["mother_atom_steps_per_s"] = (n_equil + n_states * between) * g.n / out["mother_s"]
+        out["mother_serial_s"] = serial_s
+        out["mother_replicas"] = {"copies": n_states, "kick": kick, "decorrelate_steps": decorrelate,
+                                  "steps_between": between,
+                                  "atom_steps_per_s": n_states * (decorrelate + between) * g.n /
+                                  (out["mother_s"] - serial_s)}
+        out["mother_atom_steps_per_s"] = n_equil * g.n / serial_s
         ctx.step_timing(reset=True)
         t0 = time.perf_counter()
         for v in speeds:

@@ -521,6 +521,18 @@ int32_t ttcf_channel_run_mother(ttcf_channel_ctx* ctx, int64_t n_steps);
 /* "run N_s timestep, save system state", n_states times: replaces the stored start states. */
 int32_t ttcf_channel_sample_states(ttcf_channel_ctx* ctx, int32_t n_states,
                                    int64_t steps_between);
+/* Beside the one serial mother (as ttcf_sample_states_replicated for the bulk): n_replicas
+ * copies of the mother's current state, copy q with the momentum kick kicks[q*3n ..] added
+ * (may be NULL; kicks let the copies decorrelate and should sum to zero per component), run
+ * the mother's dynamics in one persistent launch: decorrelate_steps steps, then
+ * states_per_replica states each steps_between steps apart. The stored set is replaced by
+ * the n_replicas * states_per_replica states, copy-major, with each copy's wall thermostat
+ * variable. The mother itself does not move. TTCF_EUNSTABLE if a copy fails its health
+ * check (the stored set is then empty). */
+int32_t ttcf_channel_sample_states_replicated(ttcf_channel_ctx* ctx, int32_t n_replicas,
+                                              const double* kicks, int64_t decorrelate_steps,
+                                              int32_t states_per_replica,
+                                              int64_t steps_between);
 /* Stored start states from / to host arrays: r, p (n_states x 3n), zeta (n_states). */
 int32_t ttcf_channel_import_states(ttcf_channel_ctx* ctx, int32_t n_states, const double* r,
                                    const double* p, const double* zeta);

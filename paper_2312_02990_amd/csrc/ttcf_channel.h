@@ -77,6 +77,12 @@ struct ChannelResponse {
 };
 
 size_t channel_lds_bytes(int nmax, int cmax);
+// replicas of the mother (momenta plus optional kicks) and snapshots of replicas into the
+// stored start states (slot q * per + slot of replica q)
+hipError_t launch_channel_replicate(const double* r, const double* p, const double* kicks,
+                                    int32_t n, ChannelDesc* descs, int32_t count, hipStream_t s);
+hipError_t launch_channel_snapshot(const ChannelDesc* descs, int32_t count, int32_t n,
+                                   double* states, int32_t per, int32_t slot, hipStream_t s);
 size_t channel_scratch_bytes(int nmax, int kmax);
 hipError_t launch_channel(const ChannelLaunch& b, hipStream_t s);
 hipError_t launch_channel_debug_forces(const ChannelLaunch& b, double* out, hipStream_t s);

@@ -593,6 +593,33 @@ __global__ void k_channel_spawn(const double* states, int32_t n, int32_t n_wall,
     }
 }
 
+// Replica q of the mother: its positions, and its momenta plus kick q (kicks may be null).
+__global__ void k_channel_replicate(const double* r, const double* p, const double* kicks,
+                                    int32_t n, ChannelDesc* descs, int32_t count) {
+    const int q = blockIdx.x;
+    if (q >= count) return;
+    ChannelDesc& D = descs[q];
+    const double* kq = kicks ? kicks + (size_t)q * 3 * n : nullptr;
+    for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+        D.r[i] = r[i];
+        D.p[i] = kq ? p[i] + kq[i] : p[i];
+    }
+}
+
+// Stored start state q * per + s: replica q's positions, momenta and thermostat variable.
+__global__ void k_channel_snapshot(const ChannelDesc* descs, int32_t count, int32_t n,
+                                   double* states, int32_t per, int32_t s) {
+    const int q = blockIdx.x;
+    if (q >= count) return;
+    const ChannelDesc& D = descs[q];
+    double* dst = states + ((size_t)q * per + s) * ((size_t)6 * n + 1);
+    for (int i = threadIdx.x; i < 3 * n; i += blockDim.x) {
+        dst[i] = D.r[i];
+        dst[3 * n + i] = D.p[i];
+    }
+    if (threadIdx.x == 0) dst[6 * (size_t)n] = D.zeta;
+}
+
 // ---- accumulate and response (several observables per time point) ------------------------
 // One thread per (group, observable): D(t) = mean_m B_m(t); I(t) = mean_m int_0^t S_m(0)
 // B_m(s) ds (trapezoid, compensated); the start state's TTCF series is D(0) - coef I(t).
@@ -729,6 +756,22 @@ hipError_t launch_channel_spawn(const double* states, int32_t n, int32_t n_wall,
     if (count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_channel_spawn, dim3(count), dim3(256), 0, s, states, n, n_wall, lx, latx0,
                        descs, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_channel_replicate(const double* r, const double* p, const double* kicks,
+                                    int32_t n, ChannelDesc* descs, int32_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_channel_replicate, dim3(count), dim3(256), 0, s, r, p, kicks, n, descs,
+                       count);
+    return hipGetLastError();
+}
+
+hipError_t launch_channel_snapshot(const ChannelDesc* descs, int32_t count, int32_t n,
+                                   double* states, int32_t per, int32_t slot, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_channel_snapshot, dim3(count), dim3(256), 0, s, descs, count, n, states,
+                       per, slot);
     return hipGetLastError();
 }
 

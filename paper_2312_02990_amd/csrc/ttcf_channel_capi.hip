@@ -413,6 +413,98 @@ int32_t ttcf_channel_sample_states(ttcf_channel_ctx* c, int32_t n_states, int64_
     return TTCF_OK;
 }
 
+int32_t ttcf_channel_sample_states_replicated(ttcf_channel_ctx* c, int32_t n_replicas,
+                                              const double* kicks, int64_t decorrelate_steps,
+                                              int32_t states_per_replica,
+                                              int64_t steps_between) {
+    if (!c || n_replicas <= 0 || decorrelate_steps < 0 || states_per_replica <= 0 ||
+        steps_between <= 0)
+        return TTCF_EINVAL;
+    const int64_t total = decorrelate_steps + (int64_t)states_per_replica * steps_between;
+    const int64_t n_out = (int64_t)n_replicas * states_per_replica;
+    if (total > (1 << 30) || n_out > (1 << 22))
+        return cfail(c, TTCF_EINVAL, "too many replica steps or states");
+    int32_t rc = grow_states(c, (int32_t)n_out);
+    if (rc != TTCF_OK) return rc;
+    const size_t n = (size_t)c->dev.n, R = (size_t)n_replicas;
+    double* rr = (double*)rt_alloc(sizeof(double) * 3 * n * R, c->stream);
+    double* pp = (double*)rt_alloc(sizeof(double) * 3 * n * R, c->stream);
+    float* ff = (float*)rt_alloc(sizeof(float) * 3 * n * R, c->stream);
+    double* dk = kicks ? (double*)rt_alloc(sizeof(double) * 3 * n * R, c->stream) : nullptr;
+    ChannelDesc* dd = (ChannelDesc*)rt_alloc(sizeof(ChannelDesc) * R, c->stream);
+    auto release = [&]() {
+        (void)hipStreamSynchronize(c->stream);
+        rt_free(rr);
+        rt_free(pp);
+        rt_free(ff);
+        rt_free(dk);
+        rt_free(dd);
+    };
+    if (!rr || !pp || !ff || !dd || (kicks && !dk)) {
+        release();
+        return cfail(c, TTCF_ENOMEM, "replica allocation failed");
+    }
+    // every replica: the mother's dynamics (lattice at rest), its own copy of the state
+    std::vector<ChannelDesc> hd(R);
+    for (size_t q = 0; q < R; ++q) {
+        ChannelDesc& D = hd[q];
+        D = c->mdesc;
+        D.r = rr + 3 * n * q;
+        D.p = pp + 3 * n * q;
+        D.f = ff + 3 * n * q;
+        D.series = nullptr;
+        D.v = 0.0;
+        D.done = 0;  // the first launch computes forces and the wall p^2 of the kicked state
+        D.n_steps = (int32_t)total;
+        D.health = 0;
+    }
+    auto chk = [&](hipError_t e, const char* what) -> int32_t {
+        if (e == hipSuccess) return TTCF_OK;
+        release();
+        return cfail(c, TTCF_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    };
+    if ((rc = chk(hipMemcpyAsync(dd, hd.data(), sizeof(ChannelDesc) * R, hipMemcpyHostToDevice,
+                                 c->stream), "descriptors")) != TTCF_OK)
+        return rc;
+    if (kicks &&
+        (rc = chk(hipMemcpyAsync(dk, kicks, sizeof(double) * 3 * n * R, hipMemcpyHostToDevice,
+                                 c->stream), "kicks")) != TTCF_OK)
+        return rc;
+    if ((rc = chk(launch_channel_replicate(c->m_r, c->m_p, dk, c->dev.n, dd, n_replicas,
+                                           c->stream), "replicate")) != TTCF_OK)
+        return rc;
+    // one persistent launch per stretch: decorrelation, then one per saved state
+    if (decorrelate_steps > 0) {
+        rc = launch(c, dd, n_replicas, (int32_t)decorrelate_steps, false);
+        if (rc != TTCF_OK) {
+            release();
+            return rc;
+        }
+    }
+    for (int32_t st = 0; st < states_per_replica; ++st) {
+        rc = launch(c, dd, n_replicas, (int32_t)steps_between, false);
+        if (rc != TTCF_OK) {
+            release();
+            return rc;
+        }
+        if ((rc = chk(launch_channel_snapshot(dd, n_replicas, c->dev.n, c->states,
+                                              states_per_replica, st, c->stream),
+                      "snapshot")) != TTCF_OK)
+            return rc;
+    }
+    if ((rc = chk(hipMemcpyAsync(hd.data(), dd, sizeof(ChannelDesc) * R, hipMemcpyDeviceToHost,
+                                 c->stream), "descriptors")) != TTCF_OK)
+        return rc;
+    release();
+    for (size_t q = 0; q < R; ++q)
+        if (hd[q].health != 0 || hd[q].done != (int32_t)total) {
+            c->n_states = 0;
+            return cfail(c, TTCF_EUNSTABLE, "a mother replica failed its health check");
+        }
+    c->n_states = (int32_t)n_out;
+    return TTCF_OK;
+}
+
 int32_t ttcf_channel_import_states(ttcf_channel_ctx* c, int32_t n_states, const double* r,
                                    const double* p, const double* zeta) {
     if (!c || n_states <= 0 || !r || !p || !zeta) return TTCF_EINVAL;

@@ -176,6 +176,8 @@ def lib():
         "ttcf_channel_create": [P, CH, D, D, D, V],
         "ttcf_channel_run_mother": [V, C.c_int64],
         "ttcf_channel_sample_states": [V, C.c_int32, C.c_int64],
+        "ttcf_channel_sample_states_replicated": [V, C.c_int32, D, C.c_int64, C.c_int32,
+                                                  C.c_int64],
         "ttcf_channel_import_states": [V, C.c_int32, D, D, D],
         "ttcf_channel_export_states": [V, C.c_int32, D, D, D],
         "ttcf_channel_export_mother": [V, D, D, D, L64],
@@ -231,6 +233,7 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_cv_response", "ttcf_mlp_forward", "ttcf_mlp_gradient",
             "ttcf_sample_states_replicated", "ttcf_channel_create", "ttcf_channel_destroy",
             "ttcf_channel_last_error", "ttcf_channel_run_mother", "ttcf_channel_sample_states",
+            "ttcf_channel_sample_states_replicated",
             "ttcf_channel_import_states", "ttcf_channel_export_states",
             "ttcf_channel_export_mother", "ttcf_channel_spawn", "ttcf_channel_step",
             "ttcf_channel_accumulate", "ttcf_channel_response", "ttcf_channel_export_series",
@@ -787,6 +790,14 @@ class ChannelContext:
     def sample_states(self, n_states: int, steps_between: int):
         self._chk(lib().ttcf_channel_sample_states(self._ctx, int(n_states), int(steps_between)),
                   "ttcf_channel_sample_states")
+
+    def sample_states_replicated(self, n_replicas: int, kicks, decorrelate_steps: int,
+                                 states_per_replica: int, steps_between: int):
+        """Start states from n_replicas kicked copies of the mother (kicks: (R, 3n) or None)."""
+        k = None if kicks is None else _f64(kicks).ravel()
+        self._chk(lib().ttcf_channel_sample_states_replicated(
+            self._ctx, int(n_replicas), _dp(k), int(decorrelate_steps), int(states_per_replica),
+            int(steps_between)), "ttcf_channel_sample_states_replicated")
 
     def import_states(self, r, p, zeta):
         r = _f64(r)

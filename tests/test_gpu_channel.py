@@ -83,6 +83,39 @@ def test_mother_trajectory_matches_oracle(T, CHO, states):
     assert zg == pytest.approx(st.zeta, abs=1e-4 * max(1.0, abs(st.zeta)))
 
 
+def test_replicated_mothers_match_oracle(T, CHO, states):
+    """Three kicked copies of the mother, 10 decorrelation steps, then 2 states each 10 steps
+    apart, in one persistent launch per stretch; against the oracle's mother dynamics from the
+    same kicked states. The mother itself does not move."""
+    c, q, rl, sr, sp, sz = states
+    g = GEOM
+    say("channel replicated mothers")
+    n, R, S, dec, between = g.n, 3, 2, 10, 10
+    rng = np.random.Generator(np.random.PCG64(77))
+    kicks = 0.05 * rng.standard_normal((R, 3, n))
+    kicks -= kicks.mean(axis=2, keepdims=True)
+    kicks = kicks.reshape(R, 3 * n)
+    with T.ChannelContext(T.make_channel(g), sr[0], sp[0], rl.reshape(3, -1)) as ctx:
+        ctx.sample_states_replicated(R, kicks, dec, S, between)
+        gr, gp, gz = ctx.export_states(R * S)
+        mr, mp, mz, steps = ctx.export_mother()
+    assert steps == 0
+    np.testing.assert_array_equal(mr, sr[0])
+    np.testing.assert_array_equal(mp, sp[0])
+    for k in range(R):
+        st = CHO.ChState(sr[0].copy(), sp[0] + kicks[k], 0.0)
+        CHO.run(c, st, rl, dec, g.temperature, q, g.dt)
+        for s in range(S):
+            CHO.run(c, st, rl, between, g.temperature, q, g.dt)
+            i = k * S + s
+            dr = (gr[i] - st.r).reshape(3, -1)
+            dr[0] -= g.lx * np.rint(dr[0] / g.lx)
+            dr[2] -= g.lz * np.rint(dr[2] / g.lz)
+            assert np.abs(dr).max() / g.lx <= 1e-4
+            assert np.abs(gp[i] - st.p).max() / np.sqrt(np.mean(st.p ** 2)) <= 1e-4
+            assert gz[i] == pytest.approx(st.zeta, abs=1e-4 * max(1.0, abs(st.zeta)))
+
+
 @pytest.fixture(scope="module")
 def daughters(T, CHO, states):
     """4 states x 4 mappings, 50 steps at lattice speed 0.5, on the GPU and in the oracle."""

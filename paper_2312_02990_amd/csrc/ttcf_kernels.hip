@@ -1284,13 +1284,18 @@ __global__ __launch_bounds__(kMaxThreads) void k_debug_pairs(SysDev S, double dx
 // reaches the skin, so every pair inside rc is always listed. Because each list is sorted
 // and pairs outside rc add nothing, the forces do not depend on when rebuilds happen.
 
+// Entries per trip of the force loop and candidates per trip of the list build: their loads
+// are issued together, so that LDS latency overlaps within a wave.
+constexpr int kNlPairsPerTrip = 2;
+constexpr int kNlScanPerTrip = 4;
+
 struct NlLds {
     uint4* posq;       // [nmax] fixed-point positions (X, Y, Z, unused)
     uint16_t* nbr;     // [kmax][nmax] neighbour ids, column a = atom a
     uint32_t* ncnt;    // [nmax] list lengths
     int32_t* cnt;      // [cmax] list-grid cell counts / cursors
     int32_t* start;    // [cmax + 1]
-    uint16_t* sid;     // [nmax + 4] atoms grouped by list-grid cell (4 entries of padding)
+    uint16_t* sid;     // [nmax + kNlScanPerTrip] atoms grouped by list-grid cell, then padding
     int32_t* rowinfo;  // [3 rows][2]: first column offset mod nx, column count
     double* red;       // block-reduction scratch
     int32_t* scan;     // [kMaxWaves]
@@ -1320,7 +1325,8 @@ __host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax, bool glo
     p.ncnt = take(4 * (size_t)nmax, 16);
     p.cnt = take(4 * (size_t)cmax, 16);
     p.start = take(4 * (size_t)(cmax + 1), 16);
-    p.sid = take(2 * (size_t)(nmax + 4), 16);  // 4 padding entries: reads past a range stay inside
+    // padding: the reads of a trip past the end of a range stay inside
+    p.sid = take(2 * (size_t)(nmax + kNlScanPerTrip), 16);
     p.rowinfo = take(4 * 8, 16);
     p.red = take(sizeof(double) * (kMaxWaves * kRedSlots + kRedSlots), 16);
     p.scan = take(4 * kMaxWaves, 16);
@@ -1452,20 +1458,20 @@ __device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_
         // the test fails with either shift.
         auto scan = [&](int lo, int hi, uint32_t rsh) {
 #pragma unroll 1
-            for (int tt = lo; tt < hi; tt += 4) {
-                int jn[4];
-                uint4 q[4];
+            for (int tt = lo; tt < hi; tt += kNlScanPerTrip) {
+                int jn[kNlScanPerTrip];
+                uint4 q[kNlScanPerTrip];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kNlScanPerTrip; ++u) {
                     // unconditional load (the array is padded); a value past the range is
                     // replaced before it is used as an index
                     const int raw = L.sid[tt + u];
                     jn[u] = tt + u < hi ? raw : a;
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) q[u] = L.posq[jn[u]];
+                for (int u = 0; u < kNlScanPerTrip; ++u) q[u] = L.posq[jn[u]];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kNlScanPerTrip; ++u) {
                     const float ddx = (float)(int32_t)(qx[j] - q[u].x - rsh) * ux;
                     const float ddy = (float)(int32_t)(qy[j] - q[u].y) * uy;
                     const float ddz = (float)(int32_t)(qz[j] - q[u].z) * uz;
@@ -1534,12 +1540,22 @@ __device__ __forceinline__ void nl_inner(const SysDev& S, uint32_t dxq, const ui
         uint32_t m = 0u;
         if (a < n) {
             const int c = L.ncnt[a];
-            for (int k = 0; k < c; ++k) {
-                const uint4 q = L.posq[L.nbr[k * nmax + a]];
-                float dx, dy, dz;
-                fix_sep(qx[j], qy[j], qz[j], q, dxq, S, dx, dy, dz);
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                m |= (r2 < ri2 ? 1u : 0u) << k;
+            // four entries per trip: their id loads, then their position loads, are issued
+            // together; entries past the count reread entry k and set no bit
+            for (int k = 0; k < c; k += 4) {
+                int id[4];
+                uint4 q[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) id[u] = L.nbr[(k + u < c ? k + u : k) * nmax + a];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) q[u] = L.posq[id[u]];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    float dx, dy, dz;
+                    fix_sep(qx[j], qy[j], qz[j], q[u], dxq, S, dx, dy, dz);
+                    const float r2 = dx * dx + dy * dy + dz * dz;
+                    m |= ((k + u < c) & (r2 < ri2)) ? 1u << ((k + u) & 31) : 0u;
+                }
             }
         }
         imask[j] = m;
@@ -1567,18 +1583,16 @@ __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
         {
             // the inner entries in list order (ascending ids): a fixed summation order, and
             // every skipped entry lies beyond r_c, where a pair adds an exact zero
-            uint32_t mk = imask[j];
-            while (mk != 0u) {
-                const int k = __builtin_ctz(mk);
-                mk &= mk - 1u;
-                const uint4 q = L.posq[L.nbr[k * nmax + a]];
+            // one pair, added in list order; `live` false adds exact zeros
+            auto pair = [&](const uint4& q, bool live) {
                 float dx, dy, dz;
                 fix_sep(qx[j], qy[j], qz[j], q, dxq, S, dx, dy, dz);
                 const float r2 = dx * dx + dy * dy + dz * dz;
                 // listed pairs beyond the cutoff contribute an exact zero (no branch)
                 const float inv = recip(r2);
                 const float s3 = inv * inv * inv;
-                const float fs = r2 < rc2 ? s3 * (48.f * s3 - 24.f * ca) * inv : 0.f;
+                const bool in = live & (r2 < rc2);
+                const float fs = in ? s3 * (48.f * s3 - 24.f * ca) * inv : 0.f;
                 gx += fs * dx;
                 gy += fs * dy;
                 gz += fs * dz;
@@ -1587,8 +1601,33 @@ __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
                     vxx += dx * (fs * dx);
                     vyy += dy * (fs * dy);
                     vzz += dz * (fs * dz);
-                    uu += r2 < rc2 ? 4.f * s3 * (s3 - ca) + ushift : 0.f;
+                    uu += in ? 4.f * s3 * (s3 - ca) + ushift : 0.f;
                 }
+            };
+            // kNlPairsPerTrip inner entries per trip: their id loads, then their position
+            // loads, are issued before the arithmetic; missing entries at the end repeat the
+            // first one and add nothing
+            uint32_t mk = imask[j];
+            while (mk != 0u) {
+                int kk[kNlPairsPerTrip];
+                bool live[kNlPairsPerTrip];
+                kk[0] = __builtin_ctz(mk);
+                live[0] = true;
+                mk &= mk - 1u;
+#pragma unroll
+                for (int u = 1; u < kNlPairsPerTrip; ++u) {
+                    live[u] = mk != 0u;
+                    kk[u] = live[u] ? __builtin_ctz(mk) : kk[0];
+                    mk &= mk - 1u;
+                }
+                int id[kNlPairsPerTrip];
+                uint4 q[kNlPairsPerTrip];
+#pragma unroll
+                for (int u = 0; u < kNlPairsPerTrip; ++u) id[u] = L.nbr[kk[u] * nmax + a];
+#pragma unroll
+                for (int u = 0; u < kNlPairsPerTrip; ++u) q[u] = L.posq[id[u]];
+#pragma unroll
+                for (int u = 0; u < kNlPairsPerTrip; ++u) pair(q[u], live[u]);
             }
         }
         fx[j] = gx;

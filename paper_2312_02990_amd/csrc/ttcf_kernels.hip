@@ -1528,7 +1528,8 @@ __device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_
 // Forces on the owned atoms from their lists; returns this thread's share of W_xy.
 // Marks, for every owned atom, the list entries within the inner radius (bit k: entry k);
 // entries beyond it cannot reach r_c before the next refresh.
-template <int APT>
+// PER: list entries per trip (their loads issued together).
+template <int APT, int PER>
 __device__ __forceinline__ void nl_inner(const SysDev& S, uint32_t dxq, const uint32_t (&qx)[APT],
                                          const uint32_t (&qy)[APT], const uint32_t (&qz)[APT],
                                          const NlLds& L, int nmax, uint32_t (&imask)[APT]) {
@@ -1540,17 +1541,17 @@ __device__ __forceinline__ void nl_inner(const SysDev& S, uint32_t dxq, const ui
         uint32_t m = 0u;
         if (a < n) {
             const int c = L.ncnt[a];
-            // four entries per trip: their id loads, then their position loads, are issued
+            // PER entries per trip: their id loads, then their position loads, are issued
             // together; entries past the count reread entry k and set no bit
-            for (int k = 0; k < c; k += 4) {
-                int id[4];
-                uint4 q[4];
+            for (int k = 0; k < c; k += PER) {
+                int id[PER];
+                uint4 q[PER];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) id[u] = L.nbr[(k + u < c ? k + u : k) * nmax + a];
+                for (int u = 0; u < PER; ++u) id[u] = L.nbr[(k + u < c ? k + u : k) * nmax + a];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) q[u] = L.posq[id[u]];
+                for (int u = 0; u < PER; ++u) q[u] = L.posq[id[u]];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < PER; ++u) {
                     float dx, dy, dz;
                     fix_sep(qx[j], qy[j], qz[j], q[u], dxq, S, dx, dy, dz);
                     const float r2 = dx * dx + dy * dy + dz * dz;
@@ -1604,30 +1605,32 @@ __device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
                     uu += in ? 4.f * s3 * (s3 - ca) + ushift : 0.f;
                 }
             };
-            // kNlPairsPerTrip inner entries per trip: their id loads, then their position
-            // loads, are issued before the arithmetic; missing entries at the end repeat the
-            // first one and add nothing
+            // P inner entries per trip: their id loads, then their position loads, are issued
+            // before the arithmetic; missing entries at the end repeat the first one and add
+            // nothing. The build with the extra pair sums keeps one entry per trip: with two
+            // it outgrows the register budget.
+            constexpr int P = OBS ? 1 : kNlPairsPerTrip;
             uint32_t mk = imask[j];
             while (mk != 0u) {
-                int kk[kNlPairsPerTrip];
-                bool live[kNlPairsPerTrip];
+                int kk[P];
+                bool live[P];
                 kk[0] = __builtin_ctz(mk);
                 live[0] = true;
                 mk &= mk - 1u;
 #pragma unroll
-                for (int u = 1; u < kNlPairsPerTrip; ++u) {
+                for (int u = 1; u < P; ++u) {
                     live[u] = mk != 0u;
                     kk[u] = live[u] ? __builtin_ctz(mk) : kk[0];
                     mk &= mk - 1u;
                 }
-                int id[kNlPairsPerTrip];
-                uint4 q[kNlPairsPerTrip];
+                int id[P];
+                uint4 q[P];
 #pragma unroll
-                for (int u = 0; u < kNlPairsPerTrip; ++u) id[u] = L.nbr[kk[u] * nmax + a];
+                for (int u = 0; u < P; ++u) id[u] = L.nbr[kk[u] * nmax + a];
 #pragma unroll
-                for (int u = 0; u < kNlPairsPerTrip; ++u) q[u] = L.posq[id[u]];
+                for (int u = 0; u < P; ++u) q[u] = L.posq[id[u]];
 #pragma unroll
-                for (int u = 0; u < kNlPairsPerTrip; ++u) pair(q[u], live[u]);
+                for (int u = 0; u < P; ++u) pair(q[u], live[u]);
             }
         }
         fx[j] = gx;
@@ -1784,7 +1787,9 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
     nl_publish<APT>(S, x, y, z, qx, qy, qz, path, path_in, L);
     nl_rebuild<APT>(S, dxle, dxq, x, y, z, qx, qy, qz, L, kmax, nmax);
     if (L.misc[1] != 0) health |= kHealthListOverflow;
-    nl_inner<APT>(S, dxq, qx, qy, qz, L, nmax, imask);
+    // the build with the extra pair sums keeps one entry per trip (register budget)
+    constexpr int kInnerPer = OBS ? 1 : 4;
+    nl_inner<APT, kInnerPer>(S, dxq, qx, qy, qz, L, nmax, imask);
     double xw[4];
     double wpart = nl_forces<APT, OBS>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax, xw);
     double* const xs = OBS ? dsc->xseries : nullptr;
@@ -1877,7 +1882,7 @@ __device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L
             since = 0;
         }
         if (rebuild || 2.f * dm.y + agd * tin * (reach + 2.f * dm.y) >= skin_in) {
-            nl_inner<APT>(S, dxq, qx, qy, qz, L, nmax, imask);
+            nl_inner<APT, kInnerPer>(S, dxq, qx, qy, qz, L, nmax, imask);
 #pragma unroll
             for (int j = 0; j < APT; ++j) path_in[j] = 0.f;
             since_in = 0;

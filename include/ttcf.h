@@ -151,7 +151,9 @@ int32_t ttcf_spawn_colour(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
 
 /* Alg. LAMMPS SCRIPT, "run N_d timestep": advances every live daughter by up to n_steps
  * steps (never past its own N_d) in one persistent kernel launch, recording B(t_k) = P_xy
- * after every step. Asynchronous on the context's stream. */
+ * (J_x for colour-field daughters) after every step. Asynchronous on the context's stream.
+ * TTCF_EINVAL when a daughter needs a kernel form its system cannot run (see
+ * ttcf_record_observables, ttcf_spawn_colour and ttcf_set_step_shape). */
 int32_t ttcf_step(ttcf_ctx* ctx, int32_t n_steps);
 
 /* Eq. (integrand) and Alg. SHELL SCRIPT "perform partial average and TTCF integration":
@@ -183,9 +185,10 @@ int32_t ttcf_response(ttcf_ctx* ctx, int32_t observable, double gamma_dot_filter
 /* Section Mathematical Framework: B(t) may be any phase function. Sets whether daughters
  * spawned from now on also record the extra bulk observables (TTCF_OBS_N1 .. _SLAB_PX) after
  * every step, beside V*P_xy; ttcf_accumulate folds them like P_xy. on: 0 or 1. They are
- * recorded by the neighbour-list form only: spawning them on a system with FP64 forces fails
- * with TTCF_EINVAL, and stepping them in the cell form (a system whose lists do not fit in
- * LDS) with TTCF_EINVAL. Captured graphs record P_xy only: with graphs alive, switching on
+ * recorded by the neighbour-list form with its lists in LDS only: spawning them on a system
+ * with FP64 forces fails with TTCF_EINVAL, and so does stepping them in the cell form or with
+ * lists in global scratch (a system whose lists do not fit in LDS). Captured graphs record
+ * P_xy only: with graphs alive, switching on
  * fails with TTCF_ESTATE, and ttcf_graph_create fails while it is on. The recording costs a
  * second kernel build with the extra pair sums and one more workgroup reduction per step. */
 int32_t ttcf_record_observables(ttcf_ctx* ctx, int32_t on);

@@ -188,3 +188,37 @@ def test_colour_daughters_are_refused_where_not_supported(T, states):
         with pytest.raises(T.TTCFError) as e:
             ctx.ttcf_step(10)
         assert e.value.code == T.TTCF_EINVAL
+
+
+def test_full_size_colour_batch_matches_oracle_sample(T, orc):
+    """N=2048, 1024 start states x 4 mappings x 500 steps under the colour field in one
+    launch; a sample of 4 daughters agrees with the oracle's own over the first 50 steps, and
+    J_x(0) cancels over each state's mappings."""
+    s = I.System(8)
+    r, p = I.initial_state(s, 2)
+    box = orc.make_box(s.n, s.box)
+    st = orc.NHState(r.ravel().copy(), p.ravel().copy())
+    sr16, sp16 = orc.mother_sample(box, st, 400, 16, 50, s.temperature, s.dt,
+                                   orc.nh_q(s.nf, s.temperature, TAU), s.nf)
+    sr, sp = np.tile(sr16, (64, 1)), np.tile(sp16, (64, 1))
+    nst, fe = 500, 1e-2
+    say("colour, full size: 4096 daughters x 500 steps")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1),
+                                   sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        first = ctx.ttcf_spawn_colour(mid, 1024, 0, fe, nst)
+        ctx.ttcf_step(nst)
+        sample = [0, 1, 4 * 517 + 2, 4 * 517 + 3]
+        ser = np.stack([ctx.ttcf_export_series(first + d, 1, nst + 1)[0] for d in sample])
+        j0 = ctx.ttcf_export_series(first, 4096, 1)[:, 0]
+        assert ctx.ttcf_accumulate() == 1024
+        tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, fe, observable=T.TTCF_OBS_JX)
+    assert used == 1024 and np.all(np.isfinite(tm))
+    np.testing.assert_allclose(j0.reshape(1024, 4).sum(axis=1), 0.0,
+                               atol=1e-12 * np.abs(j0).max())
+    st_of = np.array([d // 4 for d in sample]) % 16
+    mp_of = np.array([d % 4 for d in sample])
+    jo, _ = orc.run_daughters_colour(box, sr16, sp16, st_of, mp_of, np.full(len(sample), fe),
+                                     s.dt, 50, nthreads=4)
+    assert np.abs(ser[:, :51] - jo).max() / np.std(jo) <= 1e-4

@@ -219,3 +219,39 @@ def test_extra_observables_are_refused_where_not_recorded(T, states):
         with pytest.raises(T.TTCFError) as e:
             ctx.ttcf_step(10)
         assert e.value.code == T.TTCF_EINVAL
+
+
+def test_full_size_batch_records_the_oracle_observables(T, orc):
+    """N=2048, 1024 start states x 4 mappings x 500 steps with the observables recorded, in
+    one launch of the recording build; a sample of 4 daughters agrees with the oracle's own
+    over the first 30 steps (the bars above)."""
+    s = I.System(8)
+    r, p = I.initial_state(s, 2)
+    box = orc.make_box(s.n, s.box)
+    st = orc.NHState(r.ravel().copy(), p.ravel().copy())
+    sr16, sp16 = orc.mother_sample(box, st, 400, 16, 50, s.temperature, s.dt,
+                                   orc.nh_q(s.nf, s.temperature, TAU), s.nf)
+    sr, sp = np.tile(sr16, (64, 1)), np.tile(sp16, (64, 1))
+    nst, gd = 500, 1e-2
+    say("observables, full size: 4096 daughters x 500 steps")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1),
+                                   sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        ctx.ttcf_record_observables(True)
+        first = ctx.ttcf_spawn_daughters(mid, 1024, 0, gd, nst)
+        ctx.ttcf_step(nst)
+        sample = [0, 1, 4 * 517 + 2, 4 * 517 + 3]
+        obs = np.stack([ctx.ttcf_export_observables(first + d, 1, nst + 1)[0] for d in sample])
+        assert ctx.ttcf_accumulate() == 1024
+        tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, gd, observable=T.TTCF_OBS_ENERGY)
+    assert used == 1024 and np.all(np.isfinite(tm))
+    st_of = np.array([d // 4 for d in sample]) % 16
+    mp_of = np.array([d % 4 for d in sample])
+    _, oo = orc.run_daughters_obs(box, sr16, sp16, st_of, mp_of, np.full(len(sample), gd), s.dt,
+                                  30, nthreads=4)
+    for c in range(3):
+        scale = np.std(oo[:, :, c])
+        assert np.abs(obs[:, :31, c] - oo[:, :, c]).max() <= 1e-4 * scale, c
+    scale = np.std(oo[:, :, 3:])
+    assert np.abs(obs[:, :11, 3:] - oo[:, :11, 3:]).max() <= 1e-4 * scale

@@ -503,14 +503,15 @@ typedef struct {
     int32_t n_fluid;      /* fluid atoms                                                   */
     int32_t n_wall;       /* wall atoms of both walls (even; the first half is the bottom) */
     int32_t n_bins;       /* momentum-profile bins, 1..256                                 */
-    int32_t kmax;         /* neighbour-list capacity per atom (<= 0: 128)                  */
+    int32_t kmax;         /* neighbour-list capacity per atom (<= 0: 160)                  */
     double lx, lz;        /* periodic edges                                                */
     double y_extent;      /* every atom stays inside [0, y_extent)                         */
     double r_cut, c_ff, c_wf, k_spring;
     double temperature;   /* wall thermostat target                                        */
     double dt, nh_tau;    /* thermostat mass Q = 3 N_w T nh_tau^2                          */
     double bin_lo, bin_hi;
-    double skin;          /* neighbour-list skin (<= 0: 0.3)                               */
+    double skin;          /* neighbour-list skin (<= 0: 0.4, less where a small box needs
+                           * it for 3 list cells across x and z and 4 along y; at least 0.1) */
 } ttcf_channel;
 
 /* Alg. LAMMPS SCRIPT "initialise": a context holding the mother (positions r0, momenta p0,

@@ -112,7 +112,7 @@ int32_t build_dev(const ttcf_channel* ch, ChannelDev* d, std::string* why) {
     d->n_fluid = ch->n_fluid;
     d->n_wall = ch->n_wall;
     d->n_bins = ch->n_bins;
-    d->kmax = ch->kmax > 0 ? ch->kmax : 128;
+    d->kmax = ch->kmax > 0 ? ch->kmax : 160;
     if (d->kmax > 1024) {
         *why = "kmax must be at most 1024";
         return TTCF_EINVAL;
@@ -121,7 +121,14 @@ int32_t build_dev(const ttcf_channel* ch, ChannelDev* d, std::string* why) {
     d->lz = ch->lz;
     d->y_extent = ch->y_extent;
     d->rc = ch->r_cut;
-    d->skin = ch->skin > 0.0 ? ch->skin : 0.3;
+    if (ch->skin > 0.0) {
+        d->skin = ch->skin;
+    } else {
+        // 0.4 (the fastest on the full-size channel), narrowed where a small box needs it to
+        // keep three list cells across x and z and four along y
+        const double room = std::min(std::min(ch->lx, ch->lz) / 3.0, ch->y_extent / 4.0);
+        d->skin = std::max(0.1, std::min(0.4, (room - ch->r_cut) * (1.0 - 1e-9)));
+    }
     d->c_ff = ch->c_ff;
     d->c_wf = ch->c_wf;
     d->k_spring = ch->k_spring;

@@ -553,7 +553,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the daughter path shards by start state, and "
-              "this build measures one GPU's share.", file=sys.stderr)
+              "it measures one GPU's share.", file=sys.stderr)
         sys.exit(2)
 
     import torch

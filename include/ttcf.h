@@ -123,7 +123,9 @@ int32_t ttcf_init_mother(ttcf_ctx** ctx, const ttcf_system* sys, const double* r
  * mapping_mask: bit m selects mapping m of Eq. (mappings) (0xF: all four).
  * gamma_dot: n_gamma == 1 (one rate for all) or n_gamma == n_states (one per state, shared by
  *   its mapped daughters).
- * n_steps: daughter length N_d. Daughters are numbered state-major from *out_first.
+ * n_steps: daughter length N_d >= 1 (B(0) is recorded by the first step call, so a daughter
+ * of no steps would have nothing to accumulate). Daughters are numbered state-major from
+ * *out_first.
  * Omega(0) and B(0) are taken on the mapped start state. */
 int32_t ttcf_spawn_daughters(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
                              int64_t steps_between, uint32_t mapping_mask,
@@ -545,7 +547,7 @@ int32_t ttcf_channel_export_states(ttcf_channel_ctx* ctx, int32_t n_states, doub
 int32_t ttcf_channel_export_mother(ttcf_channel_ctx* ctx, double* r, double* p, double* zeta,
                                    int64_t* steps);
 /* Map the first n_states stored states (mapping_mask as for the bulk), set the lattice speed
- * v (n_v == 1, or one per state), daughters of n_steps steps, numbered state-major from
+ * v (n_v == 1, or one per state), daughters of n_steps >= 1 steps, numbered state-major from
  * *out_first. */
 int32_t ttcf_channel_spawn(ttcf_channel_ctx* ctx, int32_t n_states, uint32_t mapping_mask,
                            const double* v, int32_t n_v, int32_t n_steps, int64_t* out_first);

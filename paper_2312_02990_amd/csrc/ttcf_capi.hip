@@ -812,7 +812,7 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
     if (!c) return TTCF_EINVAL;
     if (mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || steps_between < 0 ||
         (mapping_mask & 0xFu) == 0 || (mapping_mask & ~0xFu) != 0 || !gamma_dot ||
-        !(n_gamma == 1 || n_gamma == n_states) || n_steps < 0)
+        !(n_gamma == 1 || n_gamma == n_states) || n_steps < 1)
         return fail(c, TTCF_EINVAL, "bad spawn arguments");
     for (int32_t g = 0; g < n_gamma; ++g)
         if (!std::isfinite(gamma_dot[g])) return fail(c, TTCF_EINVAL, "shear rates must be finite");

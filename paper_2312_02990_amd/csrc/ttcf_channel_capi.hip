@@ -560,7 +560,7 @@ int32_t ttcf_channel_export_mother(ttcf_channel_ctx* c, double* r, double* p, do
 
 int32_t ttcf_channel_spawn(ttcf_channel_ctx* c, int32_t n_states, uint32_t mapping_mask,
                            const double* v, int32_t n_v, int32_t n_steps, int64_t* out_first) {
-    if (!c || n_states <= 0 || !v || !(n_v == 1 || n_v == n_states) || n_steps < 0 ||
+    if (!c || n_states <= 0 || !v || !(n_v == 1 || n_v == n_states) || n_steps < 1 ||
         (mapping_mask & 0xFu) == 0 || (mapping_mask & ~0xFu) != 0)
         return cfail(c, TTCF_EINVAL, "bad spawn arguments");
     if (n_states > c->n_states) return cfail(c, TTCF_ESTATE, "fewer stored start states than asked for");

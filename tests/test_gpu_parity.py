@@ -762,7 +762,7 @@ def test_gpu_mother_is_canonical_at_T(T):
     with T.Context() as ctx:
         mid = ctx.ttcf_init_mother(gsys(T, s, 1), r0, p0, n_equil=2000, n_melt=1000, t_melt=2.0)
         ctx.ttcf_record_mother(mid, 200000)
-        ctx.ttcf_spawn_daughters(mid, 2000, 100, 1e-3, 0)
+        ctx.ttcf_sample_states(mid, 2000, 100)
         vp = ctx.ttcf_export_mother_series(mid, 200000)
         r, p = ctx.ttcf_export_states(mid, 2000)
     assert len(vp) == 200000

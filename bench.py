@@ -28,6 +28,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_ATOM_STEP = 96  # read and write of r and p in FP64 (6 x 8 B each way)
 GAMMAS = (1e-6, 1e-4, 1e-2, 1.0)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_daughters_config2_traffic.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_config2_valu.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_kernels.hip")
 
 
@@ -47,6 +48,21 @@ def measured_traffic():
     if rec.get("kernel_sha256_16") != kernel_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+def measured_valu():
+    """VALU figures of the step kernel from the committed SQ counter runs, if they were taken
+    on the current kernel source; otherwise None. The kernel keeps its state on chip, so its
+    bound is VALU issue rather than HBM."""
+    try:
+        with open(VALU_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256_16") != kernel_hash():
+        return None
+    return {k: rec[k] for k in ("valu_busy", "lane_slots_issued_frac", "active_lanes",
+                                "lane_slots_per_atom_step") if k in rec}
 
 
 def host_threads() -> int:
@@ -672,6 +688,7 @@ def main():
             "kernel": "k_daughters (persistent daughter step kernel)",
             "kernel_ms_per_launch": 1e3 * avg_launch_s,
             "algorithmic_bytes_per_launch": BYTES_PER_ATOM_STEP * atom_steps,
+            "valu": measured_valu(),
         },
         "kernel_atom_steps_per_s": atom_steps / avg_launch_s,
         "mother_s": mother_s,

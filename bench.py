@@ -243,6 +243,24 @@ def thermostat_leg(T, stream, ctx, mid, s, n_states, nst, gd=1e-2):
     return out
 
 
+def green_kubo_leg(T, ctx, mid, s, n_samples, nst, gd=1e-4):
+    """Weak-field check at full size: the TTCF viscosity eta(t) = -TTCF(t)/gamma_dot of the
+    benchmark's groups at gamma_dot = 1e-4 against the Green-Kubo integral
+    (V/T) int_0^t <P_xy(0) P_xy(s)> ds of the mother's recorded V P_xy (the series the start
+    states were sampled from), both at t = 0.25, 0.5 and the daughters' end."""
+    vp = ctx.ttcf_export_mother_series(mid, n_samples)
+    acf, _, _ = ctx.ttcf_mother_acf(mid, nst + 1, 0.05)
+    cov = acf * float(np.var(vp))                       # <VP(0) VP(t)>, mean removed
+    gk = np.concatenate([[0.0], np.cumsum(0.5 * s.dt * (cov[1:] + cov[:-1]))])
+    gk /= s.volume * s.temperature
+    tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, gd)
+    out = {"gamma_dot": gd, "n_states": used, "mother_samples": n_samples}
+    for k in (100, 200, nst):
+        out[f"t={k * s.dt:g}"] = {"eta_ttcf": float(-tm[k] / gd), "eta_ttcf_se": float(tse[k] / gd),
+                                  "eta_green_kubo": float(gk[k])}
+    return out
+
+
 def observables_leg(T, stream, ctx, mid, s, n_states, nst, gd=1e-2):
     """The benchmark's start states run once more with the extra bulk observables recorded
     (P_xx - P_yy, P_yy - P_zz, energy per atom, y-slab momentum profile): the step kernel's
@@ -634,6 +652,11 @@ def main():
     precision = None
     if args.precision == 1 and args.fp64_check:
         precision = precision_statement(T, ctx, mid, sysd, s, args.states, nst, stream)
+    green_kubo = None
+    try:
+        green_kubo = green_kubo_leg(T, ctx, mid, s, 100 * args.states, nst)
+    except Exception as e:  # the headline line is printed whatever happens here
+        green_kubo = {"error": repr(e)}
     thermostats = None
     if args.thermostats:
         try:
@@ -700,6 +723,8 @@ def main():
     }
     if precision is not None:
         line["precision"] = precision
+    if green_kubo is not None:
+        line["green_kubo"] = green_kubo
     if thermostats is not None:
         line["thermostats"] = thermostats
     if observables is not None:

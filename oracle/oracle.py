@@ -106,11 +106,19 @@ def _load():
                                                  C.c_int32, D, D, D]
         lib.orc_nh_colour_run.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double,
                                           C.c_double, D, D, D, C.c_int64, D, D, D, D]
+        lib.orc_pef_forces.argtypes = [B, D, D, D]
+        lib.orc_map_pef.argtypes = [B, C.c_int32, D, D, D, D]
+        lib.orc_map_pef.restype = None
+        lib.orc_pef_run.argtypes = [B, C.c_double, C.c_double, C.c_int32, C.c_double, D, D, D,
+                                    C.c_int64, D, D, D]
+        lib.orc_run_daughters_pef.argtypes = [B, C.c_double, D, D, C.c_int32, I, I, D, C.c_int64,
+                                              C.c_int32, D, D, D]
         for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
                    "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
                    "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh",
                    "orc_observables", "orc_run_daughters_obs", "orc_colour_run",
-                   "orc_run_daughters_colour", "orc_nh_colour_run"):
+                   "orc_run_daughters_colour", "orc_nh_colour_run", "orc_pef_forces",
+                   "orc_pef_run", "orc_run_daughters_pef"):
             getattr(lib, fn).restype = C.c_int32
         _lib = lib
     return _lib
@@ -356,6 +364,73 @@ def run_daughters_colour(box: Box, states_r, states_p, state_of, map_of, fe_of, 
 def omega0_colour(vjx0, fe, temperature):
     """Dissipation function of the colour field at t=0: Omega = (V/T) F_e J_x(0)."""
     return (np.asarray(fe, np.float64) / temperature) * np.asarray(vjx0, np.float64)
+
+
+def pef_box(box: Box, strain: float) -> Box:
+    """The planar-elongation box at strain e: L_x e^e, L_y e^-e, L_z."""
+    return Box(box.n, 0, box.lx * np.exp(strain), box.ly * np.exp(-strain), box.lz, box.rc,
+               box.c_attr, box.u_shift)
+
+
+def pef_forces(box: Box, r):
+    """All-pairs forces in the (deformed) orthorhombic box (orc_pef_forces): (f, U,
+    W_xx - W_yy, pairs)."""
+    r = _f64(r)
+    f = np.zeros(3 * box.n)
+    out = np.zeros(3)
+    rc = _load().orc_pef_forces(C.byref(box), _dp(r), _dp(f), _dp(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_pef_forces failed: {rc}")
+    return f, out[0], out[1], out[2]
+
+
+def map_pef(box: Box, m: int, r, p):
+    """Mapping m of planar elongation (bit 0: p -> -p, bit 1: exchange of the x and y axes)."""
+    r = _f64(r)
+    p = _f64(p)
+    ro = np.zeros(3 * box.n)
+    po = np.zeros(3 * box.n)
+    _load().orc_map_pef(C.byref(box), int(m), _dp(r), _dp(p), _dp(ro), _dp(po))
+    return ro, po
+
+
+def pef_run(box: Box, r, p, rate: float, dt: float, nsteps: int, gik: bool = True,
+            strain0: float = 0.0, k0: float = 0.0):
+    """Advance one planar-elongation trajectory in place (orc_pef_run) from strain strain0.
+    Returns (V (P_xx - P_yy), K, U) series of length nsteps+1 and the final strain."""
+    assert r.dtype == np.float64 and p.dtype == np.float64 and r.flags.c_contiguous
+    outs = [np.zeros(nsteps + 1) for _ in range(3)]
+    e = np.array([float(strain0)])
+    rc = _load().orc_pef_run(C.byref(box), float(rate), float(dt), int(gik), float(k0), _dp(e),
+                             _dp(r), _dp(p), int(nsteps), *[_dp(o) for o in outs])
+    if rc != 0:
+        raise RuntimeError(f"orc_pef_run failed: {rc}")
+    return outs[0], outs[1], outs[2], float(e[0])
+
+
+def run_daughters_pef(box: Box, states_r, states_p, state_of, map_of, rate_of, dt: float,
+                      nsteps: int, nthreads: int = 0, final_state: bool = False):
+    """Isokinetic planar-elongation daughters on a CPU thread pool: V (P_xx - P_yy)
+    (n_d, nsteps+1) [and final r, p in the deformed box] and the number of threads used."""
+    states_r = _f64(states_r)
+    states_p = _f64(states_p)
+    state_of = np.ascontiguousarray(state_of, np.int32)
+    map_of = np.ascontiguousarray(map_of, np.int32)
+    rate_of = _f64(rate_of)
+    nd = len(state_of)
+    out = np.zeros((nd, nsteps + 1))
+    ro = np.zeros((nd, 3 * box.n)) if final_state else None
+    po = np.zeros((nd, 3 * box.n)) if final_state else None
+    if nthreads <= 0:
+        nthreads = os.cpu_count() or 1
+    used = _load().orc_run_daughters_pef(C.byref(box), float(dt), _dp(states_r), _dp(states_p),
+                                         nd, _ip(state_of), _ip(map_of), _dp(rate_of),
+                                         int(nsteps), int(nthreads), _dp(out), _dp(ro), _dp(po))
+    if used < 0:
+        raise RuntimeError(f"orc_run_daughters_pef failed: {used}")
+    if final_state:
+        return out, ro, po, used
+    return out, used
 
 
 N_SLABS = 8  # slabs of the bulk momentum profile

@@ -17,6 +17,8 @@
  *   - The mappings of Eq. (mappings).
  *   - P_xy and the dissipation function of Eq. (TTCF1); Omega = -(V/T) gamma_dot P_xy in the
  *     pressure-tensor sign convention (the paper writes P_xy as a shear stress).
+ *   - Planar elongational flow, a field the Introduction names as one TTCF extends to, with
+ *     mappings of its own (Section Mathematical Framework: other fields need other mappings).
  * Where the paper does not fix a detail the chosen reading is stated at the spot.
  */
 #include "ttcf_oracle.h"
@@ -1032,6 +1034,247 @@ static int32_t run_batch(const orc_box* b, double dt, const double* states_r,
                        states_zeta, temperature, q, nf, n_slabs, obs_out, colour};
         jobs[t] = j;
         pthread_create(&th[t], 0, batch_worker, &jobs[t]);
+    }
+    int32_t status = 0;
+    for (int32_t t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], 0);
+        if (jobs[t].status) status = jobs[t].status;
+    }
+    free(jobs);
+    free(th);
+    return status ? status : nthreads;
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* planar elongational flow (PEF)                                                        */
+/* ------------------------------------------------------------------------------------ */
+/* The Introduction names elongational flow as a field TTCF extends to, and Section
+ * Mathematical Framework notes that another field needs its own mappings. Reading used
+ * here: the SLLOD equations of Eq. (system1) with the velocity gradient
+ * grad u = diag(rate, -rate, 0) in place of the shear,
+ *   dr/dt = p + r . grad u,  dp/dt = F - p . grad u - alpha p,
+ * the Gaussian isokinetic alpha, and an orthorhombic box that deforms with the flow:
+ *   L_x = L_x0 exp(e), L_y = L_y0 exp(-e), L_z = L_z0, e = e0 + rate (k dt)
+ * (the volume is conserved). Daughters are short transients, so no reproducible
+ * (Kraynik-Reinelt) lattice is needed; the box must keep every edge above 2 r_c.
+ * B = P_xx - P_yy and Omega = -(V/T) grad u : P = -(V/T) rate (P_xx - P_yy). */
+
+static void pef_box(const orc_box* b0, double e, orc_box* bk) {
+    *bk = *b0;
+    bk->lx = b0->lx * exp(e);
+    bk->ly = b0->ly * exp(-e);
+}
+
+/* Forces by a plain sum over all pairs i < j with the minimum image of the orthorhombic box
+ * (valid while every edge exceeds 2 r_c). out[0] = U, out[1] = W_xx - W_yy =
+ * sum_{i<j} (x_ij F_x,ij - y_ij F_y,ij), out[2] = interacting pairs. */
+int32_t orc_pef_forces(const orc_box* b, const double* r, double* f, double* out) {
+    const int32_t n = b->n;
+    if (!(b->lx > 2.0 * b->rc && b->ly > 2.0 * b->rc && b->lz > 2.0 * b->rc)) return -1;
+    const double rc2 = b->rc * b->rc;
+    double u = 0.0, w = 0.0, npair = 0.0;
+    for (int32_t k = 0; k < 3 * n; ++k) f[k] = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t j = i + 1; j < n; ++j) {
+            double dx = r[i] - r[j];
+            double dy = r[n + i] - r[n + j];
+            double dz = r[2 * n + i] - r[2 * n + j];
+            dx -= b->lx * rint(dx / b->lx);
+            dy -= b->ly * rint(dy / b->ly);
+            dz -= b->lz * rint(dz / b->lz);
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rc2) {
+                double fs, phi;
+                pair_eval(b, r2, &fs, &phi);
+                f[i] += fs * dx;
+                f[n + i] += fs * dy;
+                f[2 * n + i] += fs * dz;
+                f[j] -= fs * dx;
+                f[n + j] -= fs * dy;
+                f[2 * n + j] -= fs * dz;
+                u += phi;
+                w += dx * (fs * dx) - dy * (fs * dy);
+                npair += 1.0;
+            }
+        }
+    }
+    out[0] = u;
+    out[1] = w;
+    out[2] = npair;
+    return 0;
+}
+
+/* Mappings for PEF (reading): bit 0 reverses the momenta (time reversal), bit 1 exchanges
+ * the x and y axes of positions and momenta (a symmetry of the cubic box). P_xx - P_yy, and
+ * so Omega(0), keeps its sign under time reversal and changes it under the exchange: over
+ * m = 0..3 the signs are +, +, -, -. */
+void orc_map_pef(const orc_box* b, int32_t m, const double* r, const double* p, double* r_out,
+                 double* p_out) {
+    const int32_t n = b->n;
+    const int32_t sw = (m & 2) ? 1 : 0;
+    const double sg = (m & 1) ? -1.0 : 1.0;
+    for (int32_t i = 0; i < n; ++i) {
+        r_out[i] = r[(sw ? n : 0) + i];
+        r_out[n + i] = r[(sw ? 0 : n) + i];
+        r_out[2 * n + i] = r[2 * n + i];
+        p_out[i] = sg * p[(sw ? n : 0) + i];
+        p_out[n + i] = sg * p[(sw ? 0 : n) + i];
+        p_out[2 * n + i] = sg * p[2 * n + i];
+    }
+}
+
+/* (1 - exp(-u)) / u, the time integral of exp(-u s/h) over one step divided by h */
+static double pef_phi(double u) { return u == 0.0 ? 1.0 : -expm1(-u) / u; }
+
+/* One PEF trajectory of nsteps steps of h = dt. Symmetric splitting into a flow part E, the
+ * force part K and the streaming part D, each exact:
+ *   E(h/2) K(h/2) D(h) [k += 1, new box, wrap, F = F(r)] K(h/2) E(h/2)
+ * with
+ *   E: dp_x/dt = -rate p_x, dp_y/dt = +rate p_y (- alpha_E p under the constraint): the
+ *      unconstrained solution p_x e^{-rate tau}, p_y e^{rate tau} scaled back to the initial
+ *      p.p;
+ *   K: dp/dt = F (- alpha_K p), orc_iso_kick;
+ *   D: dx/dt = p_x + rate x, dy/dt = p_y - rate y, dz/dt = p_z with p fixed:
+ *      x -> e^{rate h} (x + h p_x phi(rate h)), y -> e^{-rate h} (y + h p_y phi(-rate h)),
+ *      phi(u) = (1 - e^{-u})/u, so that x / L_x advances by h p_x phi(rate h) / L_x(t).
+ * The isokinetic run ends each step with a rescale to K0 (round-off only); gik = 0 gives the
+ * adiabatic step (E without the multiplier, K a plain kick). vn1_out[s] = V (P_xx - P_yy)
+ * after step s (s = 0: the start). *e0 is the strain at the start; it is advanced. */
+int32_t orc_pef_run(const orc_box* b0, double rate, double dt, int32_t gik, double k0,
+                    double* e0, double* r, double* p, int64_t nsteps, double* vn1_out,
+                    double* ke_out, double* pe_out) {
+    const int32_t n = b0->n;
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!f) return -2;
+    double* x = r;
+    double* y = r + n;
+    double* z = r + 2 * n;
+    double* px = p;
+    double* py = p + n;
+    const double h = dt;
+    const double e_start = *e0;
+    orc_box bk;
+    pef_box(b0, e_start, &bk);
+    double out[3];
+    if (orc_pef_forces(&bk, r, f, out) != 0) {
+        free(f);
+        return -1;
+    }
+    if (k0 <= 0.0) k0 = kinetic(n, p);
+    const double ex = exp(-0.5 * rate * h), ey = exp(0.5 * rate * h);
+    const double dx_scale = exp(rate * h), dy_scale = exp(-rate * h);
+    const double phx = pef_phi(rate * h), phy = pef_phi(-rate * h);
+    double s0 = 0.0;
+    for (int32_t i = 0; i < n; ++i) s0 += px[i] * px[i] - py[i] * py[i];
+    if (vn1_out) vn1_out[0] = s0 + out[1];
+    if (ke_out) ke_out[0] = kinetic(n, p);
+    if (pe_out) pe_out[0] = out[0];
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        for (int half = 0; half < 2; ++half) {
+            if (half == 1) {
+                /* streaming, then the new box, wrap and forces */
+                for (int32_t i = 0; i < n; ++i) {
+                    x[i] = dx_scale * (x[i] + h * px[i] * phx);
+                    y[i] = dy_scale * (y[i] + h * py[i] * phy);
+                    z[i] += h * p[2 * n + i];
+                }
+                pef_box(b0, e_start + rate * ((double)s * h), &bk);
+                for (int32_t i = 0; i < n; ++i) {
+                    x[i] = wrap1(x[i], bk.lx);
+                    y[i] = wrap1(y[i], bk.ly);
+                    z[i] = wrap1(z[i], bk.lz);
+                }
+                if (orc_pef_forces(&bk, r, f, out) != 0) {
+                    free(f);
+                    return -1;
+                }
+            }
+            /* E then K in the first half step, K then E in the second */
+            for (int part = 0; part < 2; ++part) {
+                const int do_e = (half == 0) ? (part == 0) : (part == 1);
+                if (do_e) {
+                    double pp0 = 0.0, pp1 = 0.0;
+                    if (gik)
+                        for (int32_t c = 0; c < 3 * n; ++c) pp0 += p[c] * p[c];
+                    for (int32_t i = 0; i < n; ++i) {
+                        px[i] *= ex;
+                        py[i] *= ey;
+                    }
+                    if (gik) {
+                        for (int32_t c = 0; c < 3 * n; ++c) pp1 += p[c] * p[c];
+                        const double g = sqrt(pp0 / pp1);
+                        for (int32_t c = 0; c < 3 * n; ++c) p[c] *= g;
+                    }
+                } else if (gik) {
+                    orc_iso_kick(n, p, f, 0.5 * h);
+                } else {
+                    for (int32_t c = 0; c < 3 * n; ++c) p[c] += 0.5 * h * f[c];
+                }
+            }
+        }
+        if (gik) {
+            const double lam = sqrt(k0 / kinetic(n, p));
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] *= lam;
+        }
+        double sk = 0.0;
+        for (int32_t i = 0; i < n; ++i) sk += px[i] * px[i] - py[i] * py[i];
+        if (vn1_out) vn1_out[s] = sk + out[1];
+        if (ke_out) ke_out[s] = kinetic(n, p);
+        if (pe_out) pe_out[s] = out[0];
+    }
+    *e0 = e_start + rate * ((double)nsteps * h);
+    free(f);
+    return 0;
+}
+
+typedef struct {
+    const orc_box* b;
+    double dt;
+    const double *states_r, *states_p;
+    int32_t n_daughters;
+    const int32_t *state_of, *map_of;
+    const double* rate_of;
+    int64_t nsteps;
+    double *vn1_out, *r_out, *p_out;
+    int32_t tid, nthreads, status;
+} pef_job;
+
+static void* pef_worker(void* arg) {
+    pef_job* jb = (pef_job*)arg;
+    const size_t sz = 3 * (size_t)jb->b->n;
+    double* r = (double*)malloc(sizeof(double) * sz);
+    double* p = (double*)malloc(sizeof(double) * sz);
+    jb->status = 0;
+    for (int32_t d = jb->tid; d < jb->n_daughters; d += jb->nthreads) {
+        const int32_t s = jb->state_of[d];
+        orc_map_pef(jb->b, jb->map_of[d], jb->states_r + (size_t)s * sz,
+                    jb->states_p + (size_t)s * sz, r, p);
+        double e = 0.0;
+        int32_t rc = orc_pef_run(jb->b, jb->rate_of[d], jb->dt, 1, 0.0, &e, r, p, jb->nsteps,
+                                 jb->vn1_out + (size_t)d * (size_t)(jb->nsteps + 1), 0, 0);
+        if (rc) jb->status = rc;
+        if (jb->r_out) memcpy(jb->r_out + (size_t)d * sz, r, sizeof(double) * sz);
+        if (jb->p_out) memcpy(jb->p_out + (size_t)d * sz, p, sizeof(double) * sz);
+    }
+    free(r);
+    free(p);
+    return 0;
+}
+
+int32_t orc_run_daughters_pef(const orc_box* b, double dt, const double* states_r,
+                              const double* states_p, int32_t n_daughters,
+                              const int32_t* state_of, const int32_t* map_of,
+                              const double* rate_of, int64_t nsteps, int32_t nthreads,
+                              double* vn1_out, double* r_out, double* p_out) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > n_daughters) nthreads = n_daughters > 0 ? n_daughters : 1;
+    pef_job* jobs = (pef_job*)calloc((size_t)nthreads, sizeof(pef_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    for (int32_t t = 0; t < nthreads; ++t) {
+        pef_job j = {b,      dt,      states_r, states_p, n_daughters, state_of, map_of, rate_of,
+                     nsteps, vn1_out, r_out,    p_out,    t,           nthreads, 0};
+        jobs[t] = j;
+        pthread_create(&th[t], 0, pef_worker, &jobs[t]);
     }
     int32_t status = 0;
     for (int32_t t = 0; t < nthreads; ++t) {

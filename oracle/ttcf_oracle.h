@@ -177,6 +177,27 @@ int32_t orc_run_daughters_colour(const orc_box* b, double dt, const double* stat
                                  const double* fe_of, int64_t nsteps, int32_t nthreads,
                                  double* jx_out, double* r_out, double* p_out);
 
+/* Planar elongational flow (Introduction: TTCF extends to elongational flows): SLLOD with
+ * grad u = diag(rate, -rate, 0) in a box deforming as L_x0 e^e, L_y0 e^-e, L_z0,
+ * e = e0 + rate t, Gaussian isokinetic or adiabatic (gik = 0).
+ * orc_pef_forces: all-pairs forces with the orthorhombic minimum image (every edge must
+ * exceed 2 r_c, else -1); out = {U, W_xx - W_yy, pairs}.
+ * orc_map_pef: mapping m (bit 0 reverses p, bit 1 exchanges the x and y axes).
+ * orc_pef_run: one trajectory in place; *e0 is the start strain (advanced by the run);
+ * vn1_out = V (P_xx - P_yy), ke_out, pe_out: nsteps + 1 values each (NULL to skip).
+ * orc_run_daughters_pef: as orc_run_daughters with rate_of[d] and V (P_xx - P_yy) series. */
+int32_t orc_pef_forces(const orc_box* b, const double* r, double* f, double* out);
+void orc_map_pef(const orc_box* b, int32_t m, const double* r, const double* p, double* r_out,
+                 double* p_out);
+int32_t orc_pef_run(const orc_box* b0, double rate, double dt, int32_t gik, double k0,
+                    double* e0, double* r, double* p, int64_t nsteps, double* vn1_out,
+                    double* ke_out, double* pe_out);
+int32_t orc_run_daughters_pef(const orc_box* b, double dt, const double* states_r,
+                              const double* states_p, int32_t n_daughters,
+                              const int32_t* state_of, const int32_t* map_of,
+                              const double* rate_of, int64_t nsteps, int32_t nthreads,
+                              double* vn1_out, double* r_out, double* p_out);
+
 /* Batch of independent GIK-SLLOD daughters on a pool of nthreads threads.
  * Daughter d starts from start state state_of[d] under mapping map_of[d] with shear rate
  * gamma_of[d] and runs nsteps steps; its series V*P_xy(t_k), k = 0..nsteps, goes to

@@ -70,7 +70,8 @@ enum {
     TTCF_OBS_N2 = 4,
     TTCF_OBS_ENERGY = 5,
     TTCF_OBS_SLAB_PX = 6,
-    TTCF_OBS_JX = 7      /* colour-field daughters (ttcf_spawn_colour): the colour current J_x */
+    TTCF_OBS_JX = 7,     /* colour-field daughters (ttcf_spawn_colour): the colour current J_x */
+    TTCF_OBS_PEF_N1 = 8  /* planar-elongation daughters (ttcf_spawn_elongational): P_xx - P_yy */
 };
 enum { TTCF_BULK_SLABS = 8 };
 
@@ -151,9 +152,30 @@ int32_t ttcf_spawn_colour(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
                           int64_t steps_between, uint32_t mapping_mask, const double* field,
                           int32_t n_field, int32_t n_steps, int64_t* out_first);
 
+/* Introduction: TTCF extends to elongational flows; Section Mathematical Framework: a field
+ * other than shear needs its own mappings. Planar elongational flow (the paper prints no
+ * equations for it): SLLOD of Eq. (system1) with grad u = diag(rate, -rate, 0), isokinetic
+ * (alpha keeps p.p fixed), in an orthorhombic box deforming as L_x e^e, L_y e^-e, L_z with
+ * e = rate t (volume conserved); no reproducible lattice, as daughters are short.
+ * B(t) = P_xx - P_yy, Omega(0) = -(V/T) rate (P_xx - P_yy)(0) (from dH/dt = -V grad u : P).
+ * Mappings (bit m of mapping_mask): 0 identity, 1 reversed momenta, 2 x and y axes exchanged
+ * (positions and momenta), 3 both; P_xx - P_yy takes the signs (+, +, -, -), so <Omega(0)>
+ * vanishes over the four. Arguments as ttcf_spawn_daughters, with the elongation rates in
+ * place of the shear rates. The recorded series holds V (P_xx - P_yy)(t_k); the final
+ * states (ttcf_export_daughter) are in the coordinates of the deformed box. ttcf_accumulate
+ * folds these groups and ttcf_response(ctx, TTCF_OBS_PEF_N1, rate, ...) returns
+ * <P_xx - P_yy>(t) (-4 times the elongational viscosity times the rate in the linear regime).
+ * Forces are FP64 whatever the system's precision. TTCF_EINVAL for N > 2048, L_x != L_y, a
+ * Nose-Hoover daughter thermostat, the extra observables switched on, or a rate and length
+ * that would shrink a box edge below 3 r_c before the daughter ends. */
+int32_t ttcf_spawn_elongational(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
+                                int64_t steps_between, uint32_t mapping_mask, const double* rate,
+                                int32_t n_rate, int32_t n_steps, int64_t* out_first);
+
 /* Alg. LAMMPS SCRIPT, "run N_d timestep": advances every live daughter by up to n_steps
- * steps (never past its own N_d) in one persistent kernel launch, recording B(t_k) = P_xy
- * (J_x for colour-field daughters) after every step. Asynchronous on the context's stream.
+ * steps (never past its own N_d) in one persistent kernel launch per kernel form, recording
+ * B(t_k) = P_xy (J_x for colour-field daughters, P_xx - P_yy for planar-elongation ones) after
+ * every step. Asynchronous on the context's stream.
  * TTCF_EINVAL when a daughter needs a kernel form its system cannot run (see
  * ttcf_record_observables, ttcf_spawn_colour and ttcf_set_step_shape). */
 int32_t ttcf_step(ttcf_ctx* ctx, int32_t n_steps);

@@ -7,7 +7,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libttcf.so")
 SOURCES = [os.path.join(CSRC, "ttcf_kernels.hip"), os.path.join(CSRC, "ttcf_mlp.hip"),
            os.path.join(CSRC, "ttcf_capi.hip"), os.path.join(CSRC, "ttcf_channel.hip"),
-           os.path.join(CSRC, "ttcf_channel_capi.hip"), os.path.join(CSRC, "ttcf_estimators.hip")]
+           os.path.join(CSRC, "ttcf_channel_capi.hip"), os.path.join(CSRC, "ttcf_estimators.hip"),
+           os.path.join(CSRC, "ttcf_elongation.hip")]
 HEADERS = [os.path.join(CSRC, "ttcf_internal.h"), os.path.join(CSRC, "ttcf_channel.h"),
            os.path.join(os.path.dirname(HERE), "include", "ttcf.h")]
 

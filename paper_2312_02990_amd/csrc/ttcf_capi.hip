@@ -804,6 +804,13 @@ int32_t ttcf_spawn_colour(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t
                       false, out_first, kFieldColour);
 }
 
+int32_t ttcf_spawn_elongational(ttcf_ctx* c, int32_t mother, int32_t n_states,
+                                int64_t steps_between, uint32_t mapping_mask, const double* rate,
+                                int32_t n_rate, int32_t n_steps, int64_t* out_first) {
+    return spawn_impl(c, mother, n_states, steps_between, mapping_mask, rate, n_rate, n_steps,
+                      false, out_first, kFieldElong);
+}
+
 namespace {
 // prefix_ok: with steps_between == 0, the first n_states stored states may be used
 int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
@@ -829,6 +836,26 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
             return fail(c, TTCF_EINVAL, "colour-field daughters run in the list form (FP32 forces)");
         if (m.dev.n % 2 != 0)
             return fail(c, TTCF_EINVAL, "the colour field needs an even number of atoms");
+    }
+    if (field == kFieldElong) {
+        if (c->record_obs)
+            return fail(c, TTCF_EINVAL, "planar-elongation daughters record V (P_xx - P_yy) "
+                                        "only: switch the extra observables off");
+        if (m.sys.daughter_thermostat == TTCF_DAUGHTER_NH)
+            return fail(c, TTCF_EINVAL, "planar-elongation daughters are isokinetic");
+        if (m.dev.n > kPefMaxAtoms)
+            return fail(c, TTCF_EINVAL, "planar-elongation daughters hold at most 2048 atoms");
+        if (m.dev.box[0] != m.dev.box[1])
+            return fail(c, TTCF_EINVAL, "planar elongation exchanges x and y: the box must "
+                                        "have L_x = L_y");
+        // every edge stays at 3 r_c or more over the whole daughter (the cell stencil)
+        for (int32_t g = 0; g < n_gamma; ++g) {
+            const double shrink = std::exp(-std::fabs(gamma_dot[g]) * (double)n_steps * m.dev.dt);
+            if (m.dev.box[0] * shrink < 3.0 * m.dev.rc)
+                return fail(c, TTCF_EINVAL, "the elongation would shrink a box edge below 3 r_c "
+                                            "before the daughter ends (lower the rate or the "
+                                            "length, or use a larger system)");
+        }
     }
     if (steps_between > 0) {
         int32_t rc = ttcf_sample_states(c, mother, n_states, steps_between);
@@ -891,7 +918,7 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
             ds.series = b.series + (size_t)(n_steps + 1) * d;
             ds.xseries = b.xseries ? b.xseries + (size_t)(n_steps + 1) * kObsCols * d : nullptr;
             ds.sys = m.dev;
-            ds.gamma_dot = field == kFieldColour ? 0.0 : g;
+            ds.gamma_dot = field == kFieldColour ? 0.0 : g;  // the elongation rate for kFieldElong
             ds.field = field;
             ds.fe = field == kFieldColour ? g : 0.0;
             ds.k0 = 0.0;
@@ -913,9 +940,15 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
         }
     }
     HIPCHECK(c, hipMemcpyAsync(b.scratch, host.data(), scratch_bytes, hipMemcpyHostToDevice, c->stream));
-    HIPCHECK(c, launch_spawn(m.states, m.dev.n, n_states, (const int32_t*)((char*)b.scratch + sizeof(double*) * nd),
-                             (const int32_t*)((char*)b.scratch + sizeof(double*) * nd) + nd,
-                             (double* const*)b.scratch, nd, m.dev.box[0], c->stream));
+    {
+        const int32_t* d_state_of = (const int32_t*)((char*)b.scratch + sizeof(double*) * nd);
+        if (field == kFieldElong)
+            HIPCHECK(c, launch_spawn_pef(m.states, m.dev.n, d_state_of, d_state_of + nd,
+                                         (double* const*)b.scratch, nd, c->stream));
+        else
+            HIPCHECK(c, launch_spawn(m.states, m.dev.n, n_states, d_state_of, d_state_of + nd,
+                                     (double* const*)b.scratch, nd, m.dev.box[0], c->stream));
+    }
     // the host copy of the index arrays must outlive the asynchronous copy
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     c->batches.push_back(b);
@@ -1065,11 +1098,16 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     // is one persistent launch, largest systems first. groups[2 form + thermo], form 0 lists,
     // 1 cells, 2 lists in global scratch
     std::vector<int32_t> groups[6];
+    std::vector<int32_t> pef;  // planar-elongation daughters: their own kernel, FP64 forces
     std::vector<StepShape> eff(c->descs.size());
     int precision = -1;
     for (size_t i = 0; i < c->descs.size(); ++i) {
         DaughterDesc& d = c->descs[i];
         if (d.health != 0 || d.done >= d.n_steps || (only && !(*only)[i])) continue;
+        if (d.field == kFieldElong) {
+            pef.push_back((int32_t)i);
+            continue;
+        }
         const Mother& m = c->mothers[c->batches[c->live[i].batch].mother];
         if (precision < 0)
             precision = m.sys.precision;
@@ -1092,7 +1130,7 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     const bool any_nl = !groups[0].empty() || !groups[1].empty() || !groups[4].empty() ||
                         !groups[5].empty();
     const bool any_cell = !groups[2].empty() || !groups[3].empty();
-    if (!any_nl && !any_cell) return TTCF_OK;
+    if (!any_nl && !any_cell && pef.empty()) return TTCF_OK;
     if (any_nl) {
         rc = push_descs(c);  // the list grids were just written into the descriptors
         if (rc != TTCF_OK) return rc;
@@ -1103,6 +1141,8 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         std::stable_sort(g.begin(), g.end(), by_size);
         order.insert(order.end(), g.begin(), g.end());
     }
+    std::stable_sort(pef.begin(), pef.end(), by_size);
+    order.insert(order.end(), pef.begin(), pef.end());
     if (c->d_order_cap < order.size()) {
         dev_free(c->d_order);
         c->d_order = (int32_t*)dev_alloc(sizeof(int32_t) * order.size() * 2, c->stream);
@@ -1112,7 +1152,8 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     HIPCHECK(c, hipMemcpyAsync(c->d_order, order.data(), sizeof(int32_t) * order.size(),
                                hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
-    c->last_variant = !any_nl ? kVariantCells : (!any_cell ? kVariantNeighbourList : 3);
+    if (any_nl || any_cell)
+        c->last_variant = !any_nl ? kVariantCells : (!any_cell ? kVariantNeighbourList : 3);
     size_t offset = 0;
     for (int gi = 0; gi < 6; ++gi) {
         const int form = gi / 2;
@@ -1144,6 +1185,34 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
             HIPCHECK(c, hipEventRecord(e0, c->stream));
         }
         HIPCHECK(c, launch_daughters(L, c->stream));
+        if (timing) {
+            HIPCHECK(c, hipEventRecord(e1, c->stream));
+            c->pending_events.emplace_back(e0, e1);
+        }
+    }
+    if (!pef.empty()) {
+        PefLaunch P{};
+        P.descs = c->d_descs;
+        P.order = c->d_order + offset;
+        P.n_jobs = (int32_t)pef.size();
+        P.max_steps = n_steps;
+        for (int32_t i : pef) {
+            const SysDev& sd = c->descs[i].sys;
+            P.nmax = std::max(P.nmax, sd.n);
+            // no cell grid of a box of this volume exceeds volume / r_c^3 cells
+            P.cmax = std::max(P.cmax, pef_max_cells(sd.volume, sd.rc) + 8);
+        }
+        P.threads = pef_threads(P.nmax);
+        P.lds_bytes = lds_bytes_pef(P.nmax, P.cmax);
+        if (P.lds_bytes > c->max_lds)
+            return fail(c, TTCF_EINVAL, "planar-elongation batch exceeds the LDS of one workgroup");
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timing) {
+            HIPCHECK(c, hipEventCreate(&e0));
+            HIPCHECK(c, hipEventCreate(&e1));
+            HIPCHECK(c, hipEventRecord(e0, c->stream));
+        }
+        HIPCHECK(c, launch_pef(P, c->stream));
         if (timing) {
             HIPCHECK(c, hipEventRecord(e1, c->stream));
             c->pending_events.emplace_back(e0, e1);
@@ -1589,8 +1658,9 @@ int32_t ttcf_accumulate(ttcf_ctx* c, int64_t* out_groups) {
                 c->mothers[c->batches[c->live[ready[which[q]].first].batch].mother].sys.temperature;
             const bool colour = d0.field == kFieldColour;
             // the row's field strength and coef, Omega(0) = -coef * (series(0) / V): the
-            // series is V P_xy for shear (Omega = -(V/T) gamma_dot P_xy) and V J_x for the
-            // colour field (Omega = +(V/T) F_e J_x)
+            // series is V P_xy for shear (Omega = -(V/T) gamma_dot P_xy), V J_x for the
+            // colour field (Omega = +(V/T) F_e J_x) and V (P_xx - P_yy) for planar
+            // elongation (Omega = -(V/T) rate (P_xx - P_yy), the shear form)
             c->row_gamma.push_back(colour ? d0.fe : d0.gamma_dot);
             c->row_field.push_back(d0.field);
             c->row_dt.push_back(d0.sys.dt);
@@ -1674,12 +1744,19 @@ bool obs_columns(int32_t observable, int* col0, int* ncol) {
     switch (observable) {
         case TTCF_OBS_PXY: *col0 = -1; *ncol = 1; return true;
         case TTCF_OBS_JX: *col0 = -1; *ncol = 1; return true;  // colour rows hold V J_x there
+        case TTCF_OBS_PEF_N1: *col0 = -1; *ncol = 1; return true;  // elongation: V (P_xx - P_yy)
         case TTCF_OBS_N1: *col0 = 0; *ncol = 1; return true;
         case TTCF_OBS_N2: *col0 = 1; *ncol = 1; return true;
         case TTCF_OBS_ENERGY: *col0 = 2; *ncol = 1; return true;
         case TTCF_OBS_SLAB_PX: *col0 = 3; *ncol = kObsSlabs; return true;
     }
     return false;
+}
+
+// the field whose rows carry an observable
+int32_t field_of_observable(int32_t observable) {
+    return observable == TTCF_OBS_JX ? kFieldColour
+                                     : (observable == TTCF_OBS_PEF_N1 ? kFieldElong : kFieldShear);
 }
 
 // accumulator arrays and row stride of column `col` (-1: P_xy)
@@ -1703,7 +1780,7 @@ int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, 
     if (!c || n_t <= 0 || !obs_columns(observable, &col0, &ncol)) return TTCF_EINVAL;
     int32_t rc0 = refresh_row_health(c);
     if (rc0 != TTCF_OK) return rc0;
-    const int32_t want_field = observable == TTCF_OBS_JX ? kFieldColour : kFieldShear;
+    const int32_t want_field = field_of_observable(observable);
     std::vector<int32_t> rows;
     for (int64_t r = 0; r < c->acc_rows; ++r) {
         if (c->row_field[r] != want_field) continue;
@@ -2104,7 +2181,7 @@ int32_t response_modified_impl(ttcf_ctx* c, int32_t observable, double gamma_dot
         return TTCF_EINVAL;
     int32_t rc = refresh_row_health(c);
     if (rc != TTCF_OK) return rc;
-    const int32_t want_field = observable == TTCF_OBS_JX ? kFieldColour : kFieldShear;
+    const int32_t want_field = field_of_observable(observable);
     std::vector<int32_t> rows;
     for (int64_t r = 0; r < c->acc_rows; ++r)
         if (c->row_field[r] == want_field && c->row_gamma[r] == gamma_dot_filter &&

@@ -1,0 +1,542 @@
+// ttcf_elongation.hip -- planar elongational flow (PEF) daughters on gfx950.
+//
+// The Introduction names elongational flow among the fields TTCF extends to, and Section
+// Mathematical Framework notes that a field other than shear needs mappings of its own. The
+// paper prints no PEF equations; the dynamics here is SLLOD (Eq. system1 with the velocity
+// gradient grad u = diag(rate, -rate, 0) in place of the shear) with the Gaussian isokinetic
+// multiplier, in an orthorhombic box that deforms with the flow:
+//   L_x = L_x0 e^e, L_y = L_y0 e^-e, L_z = L_z0, e = rate (k dt)   (volume conserved).
+// Daughters are short transients, so the box needs no reproducible (Kraynik-Reinelt)
+// lattice; the host refuses a daughter whose box edges would fall below 3 r_c.
+//
+// Positions are held as fractions s of the current box. Under the flow, ds/dt = p / L(t),
+// which over a step with p fixed integrates exactly to s += h p phi(rate h) / L(t_k),
+// phi(u) = (1 - e^-u) / u (and phi(-rate h) along y). One step of h = dt:
+//   E(h/2) K(h/2) D(h) [k += 1, new box, cell list, forces] K(h/2) E(h/2), rescale to K0,
+// E: p_x e^{-rate tau}, p_y e^{rate tau}, scaled back to the step's p.p (the multiplier's
+// share of the flow term); K: the exact constrained kick under fixed forces (Zhang, J. Chem.
+// Phys. 106, 6102 (1997)). B = P_xx - P_yy, recorded as V (P_xx - P_yy) after every step;
+// Omega(0) = -(V/T) grad u : P = -(V/T) rate (P_xx - P_yy).
+//
+// Layout: one workgroup per daughter, two atoms per thread, momenta and forces in
+// registers, fractional positions in LDS by atom id. The cell grid is rebuilt every step
+// from the current box (n_a = floor(L_a / r_c) >= 3) with each cell's members in ascending
+// atom id, and every pair is evaluated from both sides (FP64), so each force, virial and
+// reduction has a fixed summation order: results are deterministic.
+
+#include <math.h>
+
+#include "ttcf_internal.h"
+
+namespace ttcf {
+namespace {
+
+constexpr int kPefApt = 2;  // atoms per thread
+
+struct PefPlan {
+    size_t sx, sy, sz, red, start, cnt, ws, sid, total;
+};
+
+__host__ __device__ inline size_t pef_align(size_t v) { return (v + 15) & ~(size_t)15; }
+
+__host__ __device__ inline PefPlan pef_plan(int nmax, int cmax) {
+    PefPlan p;
+    size_t o = 0;
+    p.sx = o;
+    o = pef_align(o + sizeof(double) * (size_t)nmax);
+    p.sy = o;
+    o = pef_align(o + sizeof(double) * (size_t)nmax);
+    p.sz = o;
+    o = pef_align(o + sizeof(double) * (size_t)nmax);
+    p.red = o;
+    o = pef_align(o + sizeof(double) * (size_t)(kMaxWaves * kRedSlots + kRedSlots));
+    p.start = o;
+    o = pef_align(o + sizeof(int32_t) * (size_t)(cmax + 1));
+    p.cnt = o;
+    o = pef_align(o + sizeof(int32_t) * (size_t)cmax);
+    p.ws = o;
+    o = pef_align(o + sizeof(int32_t) * (size_t)kMaxWaves);
+    p.sid = o;
+    o = pef_align(o + sizeof(uint16_t) * (size_t)nmax);
+    p.total = o;
+    return p;
+}
+
+struct PefShared {
+    double *sx, *sy, *sz;  // [nmax] fractional positions by atom id
+    double* red;           // reduction scratch
+    int32_t* start;        // [cells + 1] first sorted slot of each cell
+    int32_t* cnt;          // [cells] counts, then placement cursors
+    int32_t* ws;           // [waves] scan scratch
+    uint16_t* sid;         // [nmax] atom ids sorted by (cell, id)
+};
+
+// Sum of K doubles over the workgroup, the same total in every thread. Fixed order: an xor
+// butterfly inside each wave (lane 0's result is used), then the waves in sequence.
+template <int K>
+__device__ __forceinline__ void pef_sum(double (&v)[K], double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w * K + threadIdx.x];
+        red[kMaxWaves * kRedSlots + threadIdx.x] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = red[kMaxWaves * kRedSlots + k];
+}
+
+__device__ __forceinline__ double pef_wrap(double s) {
+    s -= floor(s);
+    return s >= 1.0 ? 0.0 : s;
+}
+
+// (1 - e^-u) / u
+__device__ __forceinline__ double pef_phi(double u) { return u == 0.0 ? 1.0 : -expm1(-u) / u; }
+
+// Exact flow of dp/dt = F - alpha p over tau with F fixed and alpha = F.p / p.p:
+// a = F.p/p.p, b = F.F/p.p, q = sqrt(b), s = a (cosh(q tau) - 1)/b + sinh(q tau)/q,
+// sdot = a sinh(q tau)/q + cosh(q tau), p -> (p + F s) / sdot.
+__device__ __forceinline__ void pef_kick_coeffs(double a, double b, double tau, double& s,
+                                                double& sdot) {
+    double ch1_b, sh_q;
+    if (b > 0.0) {
+        const double q = sqrt(b);
+        const double hs = sinh(0.5 * q * tau) / q;
+        ch1_b = 2.0 * hs * hs;
+        sh_q = sinh(q * tau) / q;
+    } else {
+        ch1_b = 0.5 * tau * tau;
+        sh_q = tau;
+    }
+    s = a * ch1_b + sh_q;
+    sdot = a * sh_q + (1.0 + b * ch1_b);
+}
+
+__device__ __forceinline__ int pef_cell(double s, int nc) {
+    const int c = (int)(s * (double)nc);
+    return c > nc - 1 ? nc - 1 : c;
+}
+
+// Force on atom i from the 27-cell stencil of the current cell list (cells in a fixed
+// order, members in ascending id), and its halves of the pair virial and energy.
+__device__ __forceinline__ void pef_atom_force(const PefShared& S, int i, int ncx, int ncy,
+                                               int ncz, double lx, double ly, double lz,
+                                               double rc2, double ca, double ush, double& fx,
+                                               double& fy, double& fz, double& w, double& u) {
+    const double six = S.sx[i], siy = S.sy[i], siz = S.sz[i];
+    const int cx = pef_cell(six, ncx), cy = pef_cell(siy, ncy), cz = pef_cell(siz, ncz);
+    for (int dz = -1; dz <= 1; ++dz) {
+        int zz = cz + dz;
+        zz += zz < 0 ? ncz : (zz >= ncz ? -ncz : 0);
+        for (int dy = -1; dy <= 1; ++dy) {
+            int yy = cy + dy;
+            yy += yy < 0 ? ncy : (yy >= ncy ? -ncy : 0);
+            for (int dx = -1; dx <= 1; ++dx) {
+                int xx = cx + dx;
+                xx += xx < 0 ? ncx : (xx >= ncx ? -ncx : 0);
+                const int c = xx + ncx * (yy + ncy * zz);
+                const int e = S.start[c + 1];
+                for (int q = S.start[c]; q < e; ++q) {
+                    const int m = S.sid[q];
+                    if (m == i) continue;
+                    double ddx = six - S.sx[m];
+                    double ddy = siy - S.sy[m];
+                    double ddz = siz - S.sz[m];
+                    ddx = (ddx - rint(ddx)) * lx;
+                    ddy = (ddy - rint(ddy)) * ly;
+                    ddz = (ddz - rint(ddz)) * lz;
+                    const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                    if (r2 < rc2) {
+                        const double inv = 1.0 / r2;
+                        const double s3 = inv * inv * inv;
+                        const double s6 = s3 * s3;
+                        const double fs = (48.0 * s6 - 24.0 * ca * s3) * inv;
+                        fx += fs * ddx;
+                        fy += fs * ddy;
+                        fz += fs * ddz;
+                        w += 0.5 * (fs * (ddx * ddx - ddy * ddy));
+                        u += 0.5 * (4.0 * (s6 - ca * s3) + ush);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Canonical cell list of the fractional positions in LDS (every thread calls it; it begins
+// and ends with a barrier), then the forces on the thread's atoms and its share of the pair
+// virial W_xx - W_yy (each pair is seen from both sides, so each side adds half).
+__device__ void pef_forces(const PefShared& S, int n, int ncx, int ncy, int ncz, double lx,
+                           double ly, double lz, double rc2, double ca, double ush,
+                           double (&fx)[kPefApt],
+                           double (&fy)[kPefApt], double (&fz)[kPefApt], double& w, double& u) {
+    const int T = blockDim.x, t = threadIdx.x;
+    const int lane = t & 63, wave = t >> 6, nw = T >> 6;
+    const int C = ncx * ncy * ncz;
+    __syncthreads();
+    for (int c = t; c < C; c += T) S.cnt[c] = 0;
+    __syncthreads();
+    int cell[kPefApt];
+#pragma unroll
+    for (int j = 0; j < kPefApt; ++j) {
+        const int a = t + j * T;
+        cell[j] = -1;
+        if (a < n) {
+            cell[j] = pef_cell(S.sx[a], ncx) +
+                      ncx * (pef_cell(S.sy[a], ncy) + ncy * pef_cell(S.sz[a], ncz));
+            atomicAdd(&S.cnt[cell[j]], 1);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the counts: contiguous chunks per thread, then waves in order
+    {
+        const int chunk = (C + T - 1) / T;
+        const int b = t * chunk;
+        const int e = min(C, b + chunk);
+        int local = 0;
+        for (int c = b; c < e; ++c) local += S.cnt[c];
+        int x = local;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) S.ws[wave] = x;
+        __syncthreads();
+        if (t == 0) {
+            int acc = 0;
+            for (int v = 0; v < nw; ++v) {
+                const int q = S.ws[v];
+                S.ws[v] = acc;
+                acc += q;
+            }
+            S.start[C] = acc;
+        }
+        __syncthreads();
+        int run = S.ws[wave] + x - local;
+        for (int c = b; c < e; ++c) {
+            const int q = S.cnt[c];
+            S.start[c] = run;
+            S.cnt[c] = run;
+            run += q;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPefApt; ++j)
+        if (cell[j] >= 0) S.sid[atomicAdd(&S.cnt[cell[j]], 1)] = (uint16_t)(t + j * T);
+    __syncthreads();
+    // members of each cell in ascending atom id (insertion sort; a few atoms per cell)
+    for (int c = t; c < C; c += T) {
+        const int b = S.start[c], e = S.start[c + 1];
+        for (int q = b + 1; q < e; ++q) {
+            const uint16_t v = S.sid[q];
+            int r = q - 1;
+            while (r >= b && S.sid[r] > v) {
+                S.sid[r + 1] = S.sid[r];
+                --r;
+            }
+            S.sid[r + 1] = v;
+        }
+    }
+    __syncthreads();
+    w = 0.0;
+    u = 0.0;
+    for (int j = 0; j < kPefApt; ++j) {
+        const int i = t + j * T;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        if (i < n) pef_atom_force(S, i, ncx, ncy, ncz, lx, ly, lz, rc2, ca, ush, ax, ay, az, w, u);
+        fx[j] = ax;
+        fy[j] = ay;
+        fz[j] = az;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
+    extern __shared__ __align__(16) char smem[];
+    const PefPlan plan = pef_plan(L.nmax, L.cmax);
+    PefShared S;
+    S.sx = (double*)(smem + plan.sx);
+    S.sy = (double*)(smem + plan.sy);
+    S.sz = (double*)(smem + plan.sz);
+    S.red = (double*)(smem + plan.red);
+    S.start = (int32_t*)(smem + plan.start);
+    S.cnt = (int32_t*)(smem + plan.cnt);
+    S.ws = (int32_t*)(smem + plan.ws);
+    S.sid = (uint16_t*)(smem + plan.sid);
+
+    DaughterDesc* dp = L.descs + L.order[blockIdx.x];
+    const int T = blockDim.x, t = threadIdx.x;
+    const int n = dp->sys.n;
+    const int32_t done0 = dp->done;
+    if (dp->health != 0 || done0 >= dp->n_steps) return;  // uniform over the workgroup
+    const int steps = min(L.max_steps, dp->n_steps - done0);
+    const double rate = dp->gamma_dot, h = dp->sys.dt;
+    const double l0x = dp->sys.box[0], l0y = dp->sys.box[1], lz = dp->sys.box[2];
+    const double rc = dp->sys.rc, rc2 = dp->sys.rc2, ca = dp->sys.c_attr, ush = dp->sys.u_shift;
+    double* st = dp->state;
+    double* series = dp->series;
+    int64_t k = dp->k;
+    int health = 0;
+    if (n > T * kPefApt || n > L.nmax) health = kHealthNonFinite;  // the host sizes launches
+    double e = rate * ((double)k * h);
+    double lx = l0x * exp(e), ly = l0y * exp(-e);
+    int ncx = (int)floor(lx / rc), ncy = (int)floor(ly / rc), ncz = (int)floor(lz / rc);
+    if (ncx < 3 || ncy < 3 || ncz < 3 || ncx * ncy * ncz > L.cmax) health = kHealthNonFinite;
+    if (health) {
+        if (t == 0) dp->health = health;
+        return;
+    }
+    const double ex = exp(-0.5 * rate * h), ey = exp(0.5 * rate * h);
+    const double phx = pef_phi(rate * h), phy = pef_phi(-rate * h);
+
+    double px[kPefApt], py[kPefApt], pz[kPefApt];
+    double fx[kPefApt], fy[kPefApt], fz[kPefApt];
+#pragma unroll
+    for (int j = 0; j < kPefApt; ++j) {
+        const int a = t + j * T;
+        px[j] = py[j] = pz[j] = 0.0;
+        if (a < n) {
+            S.sx[a] = pef_wrap(st[a] / lx);
+            S.sy[a] = pef_wrap(st[n + a] / ly);
+            S.sz[a] = pef_wrap(st[2 * n + a] / lz);
+            px[j] = st[3 * n + a];
+            py[j] = st[4 * n + a];
+            pz[j] = st[5 * n + a];
+        }
+    }
+    double w, u;
+    pef_forces(S, n, ncx, ncy, ncz, lx, ly, lz, rc2, ca, ush, fx, fy, fz, w, u);
+    double k0 = dp->k0;
+    {
+        double v[3] = {0.0, 0.0, w};
+#pragma unroll
+        for (int j = 0; j < kPefApt; ++j) {
+            v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+            v[1] += px[j] * px[j] - py[j] * py[j];
+        }
+        pef_sum<3>(v, S.red);
+        if (done0 == 0) {
+            k0 = 0.5 * v[0];
+            if (t == 0) series[0] = v[1] + v[2];
+        }
+    }
+    int it = 0;
+    for (; it < steps; ++it) {
+        // E(h/2)
+        {
+            double v[2] = {0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                px[j] *= ex;
+                py[j] *= ey;
+                v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+            }
+            pef_sum<2>(v, S.red);
+            const double g = sqrt(v[0] / v[1]);
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                px[j] *= g;
+                py[j] *= g;
+                pz[j] *= g;
+            }
+        }
+        // K(h/2)
+        {
+            double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                v[1] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+                v[2] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+            }
+            pef_sum<3>(v, S.red);
+            double s, sd;
+            pef_kick_coeffs(v[1] / v[0], v[2] / v[0], 0.5 * h, s, sd);
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                px[j] = (px[j] + fx[j] * s) / sd;
+                py[j] = (py[j] + fy[j] * s) / sd;
+                pz[j] = (pz[j] + fz[j] * s) / sd;
+            }
+        }
+        // D(h) in fractional coordinates, then the box of step k + 1. Every thread has
+        // passed the barriers of the two sums above, so no thread still reads S.sx, and
+        // each thread moves only its own atoms.
+        {
+            const double ax = h * phx / lx, ay = h * phy / ly, az = h / lz;
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                const int a = t + j * T;
+                if (a < n) {
+                    S.sx[a] = pef_wrap(S.sx[a] + px[j] * ax);
+                    S.sy[a] = pef_wrap(S.sy[a] + py[j] * ay);
+                    S.sz[a] = pef_wrap(S.sz[a] + pz[j] * az);
+                }
+            }
+            k += 1;
+            e = rate * ((double)k * h);
+            lx = l0x * exp(e);
+            ly = l0y * exp(-e);
+            ncx = (int)floor(lx / rc);
+            ncy = (int)floor(ly / rc);
+            if (ncx < 3 || ncy < 3 || ncx * ncy * ncz > L.cmax) {
+                health = kHealthNonFinite;  // uniform: every thread stops here
+                break;
+            }
+        }
+        pef_forces(S, n, ncx, ncy, ncz, lx, ly, lz, rc2, ca, ush, fx, fy, fz, w, u);
+        // K(h/2), with the virial of the new positions in the same sum
+        {
+            double v[4] = {0.0, 0.0, 0.0, w};
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                v[1] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+                v[2] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+            }
+            pef_sum<4>(v, S.red);
+            w = v[3];
+            double s, sd;
+            pef_kick_coeffs(v[1] / v[0], v[2] / v[0], 0.5 * h, s, sd);
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                px[j] = (px[j] + fx[j] * s) / sd;
+                py[j] = (py[j] + fy[j] * s) / sd;
+                pz[j] = (pz[j] + fz[j] * s) / sd;
+            }
+        }
+        // E(h/2)
+        {
+            double v[2] = {0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                px[j] *= ex;
+                py[j] *= ey;
+                v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+            }
+            pef_sum<2>(v, S.red);
+            const double g = sqrt(v[0] / v[1]);
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                px[j] *= g;
+                py[j] *= g;
+                pz[j] *= g;
+            }
+        }
+        // rescale to K0 (round-off only) and record V (P_xx - P_yy)
+        {
+            double v[2] = {0.0, 0.0};
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                v[1] += px[j] * px[j] - py[j] * py[j];
+            }
+            pef_sum<2>(v, S.red);
+            const double lam = sqrt(k0 / (0.5 * v[0]));
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                px[j] *= lam;
+                py[j] *= lam;
+                pz[j] *= lam;
+            }
+            const double vn1 = lam * lam * v[1] + w;
+            if (t == 0) series[done0 + it + 1] = vn1;
+            if (!isfinite(vn1)) {
+                health = kHealthNonFinite;  // uniform: every thread holds the same sum
+                ++it;
+                break;
+            }
+        }
+    }
+    // the state in the coordinates of the current box
+#pragma unroll
+    for (int j = 0; j < kPefApt; ++j) {
+        const int a = t + j * T;
+        if (a < n) {
+            st[a] = S.sx[a] * lx;
+            st[n + a] = S.sy[a] * ly;
+            st[2 * n + a] = S.sz[a] * lz;
+            st[3 * n + a] = px[j];
+            st[4 * n + a] = py[j];
+            st[5 * n + a] = pz[j];
+        }
+    }
+    if (t == 0) {
+        dp->k = k;
+        dp->done = done0 + it;
+        dp->k0 = k0;
+        dp->health = health;
+    }
+}
+
+// Start states of PEF daughters under their mappings: bit 0 of map reverses the momenta,
+// bit 1 exchanges the x and y axes of positions and momenta (the box is cubic).
+__global__ void k_spawn_pef(const double* states, int32_t n, const int32_t* state_of,
+                            const int32_t* map_of, double* const* dst) {
+    const int d = blockIdx.x;
+    const double* src = states + (size_t)state_of[d] * 6 * (size_t)n;
+    double* out = dst[d];
+    const int m = map_of[d];
+    const bool sw = (m & 2) != 0;
+    const double sg = (m & 1) ? -1.0 : 1.0;
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        const double x = src[a], y = src[n + a], z = src[2 * n + a];
+        const double px = src[3 * n + a], py = src[4 * n + a], pz = src[5 * n + a];
+        out[a] = sw ? y : x;
+        out[n + a] = sw ? x : y;
+        out[2 * n + a] = z;
+        out[3 * n + a] = sg * (sw ? py : px);
+        out[4 * n + a] = sg * (sw ? px : py);
+        out[5 * n + a] = sg * pz;
+    }
+}
+
+}  // namespace
+
+int pef_threads(int nmax) {
+    const int half = (nmax + kPefApt - 1) / kPefApt;
+    const int t = ((half + 63) / 64) * 64;
+    return t < 64 ? 64 : t;
+}
+
+int pef_max_cells(double volume, double rc) {
+    return (int)floor(volume / (rc * rc * rc));
+}
+
+size_t lds_bytes_pef(int nmax, int cmax) { return pef_plan(nmax, cmax).total; }
+
+hipError_t launch_pef(const PefLaunch& L, hipStream_t s) {
+    if (L.n_jobs <= 0) return hipSuccess;
+    if (L.threads < 64 || L.threads > kMaxThreads || L.threads % 64 != 0 ||
+        L.nmax > L.threads * kPefApt || L.cmax < 27)
+        return hipErrorInvalidValue;
+    (void)hipFuncSetAttribute((const void*)k_daughters_pef,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+    hipLaunchKernelGGL(k_daughters_pef, dim3(L.n_jobs), dim3(L.threads), L.lds_bytes, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_spawn_pef(const double* states, int32_t n, const int32_t* state_of,
+                            const int32_t* map_of, double* const* dst, int32_t n_daughters,
+                            hipStream_t s) {
+    if (n_daughters <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spawn_pef, dim3(n_daughters), dim3(256), 0, s, states, n, state_of,
+                       map_of, dst);
+    return hipGetLastError();
+}
+
+}  // namespace ttcf

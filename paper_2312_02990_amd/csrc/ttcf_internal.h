@@ -11,6 +11,7 @@ constexpr int kMaxWaves = kMaxThreads / 64;
 constexpr int kRedSlots = 12;       // doubles reduced per block reduction
 constexpr int kMaxCells1D = 1023;   // packed cell coordinates use 10 bits each
 constexpr int kMaxAtoms = 65535;    // sorted atom ids are stored as uint16
+constexpr int kPefMaxAtoms = 2048;  // planar-elongation daughters: two atoms per thread
 
 // Constants of one simulated system, uniform inside a workgroup.
 struct SysDev {
@@ -82,9 +83,11 @@ struct DaughterDesc {
     int32_t pad3_;
 };
 
-// External field of a daughter: SLLOD shear at gamma_dot, or the colour field (charge +1 on
-// even atoms, -1 on odd ones, force charge * F_e along x; series V J_x = sum charge p_x).
-enum Field : int32_t { kFieldShear = 0, kFieldColour = 1 };
+// External field of a daughter: SLLOD shear at gamma_dot, the colour field (charge +1 on
+// even atoms, -1 on odd ones, force charge * F_e along x; series V J_x = sum charge p_x), or
+// planar elongational flow at rate gamma_dot (grad u = diag(rate, -rate, 0) in a deforming
+// box; series V (P_xx - P_yy); k counts the steps that set the box strain rate k dt).
+enum Field : int32_t { kFieldShear = 0, kFieldColour = 1, kFieldElong = 2 };
 
 enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2, kHealthListOverflow = 4 };
 
@@ -115,6 +118,19 @@ struct BatchLaunch {
     uint16_t* nbr;         // global_lists: grid x nbr_stride list entries
     int64_t nbr_stride;    // >= (kmax + 1) n of every job
     size_t lds_bytes;
+};
+
+// Planar-elongation daughters (ttcf_elongation.hip): one workgroup per job, two atoms per
+// thread, FP64 forces over a cell grid rebuilt every step from the deformed box.
+struct PefLaunch {
+    DaughterDesc* descs;   // device array
+    const int32_t* order;  // device: desc index of each job
+    int32_t n_jobs;
+    int32_t max_steps;     // steps this call (each daughter stops at its own N_d)
+    int32_t threads;       // pef_threads(nmax)
+    int32_t nmax;          // largest system
+    int32_t cmax;          // >= the cell count of any job's box at any step
+    size_t lds_bytes;      // lds_bytes_pef(nmax, cmax)
 };
 
 struct MotherLaunch {
@@ -269,6 +285,13 @@ hipError_t launch_accumulate_obs(const AccumObsLaunch& a, hipStream_t s);
 // *counter += 1 (one thread)
 hipError_t launch_increment(int32_t* counter, hipStream_t s);
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s);
+int pef_threads(int nmax);
+int pef_max_cells(double volume, double rc);
+size_t lds_bytes_pef(int nmax, int cmax);
+hipError_t launch_pef(const PefLaunch& L, hipStream_t s);
+hipError_t launch_spawn_pef(const double* states, int32_t n, const int32_t* state_of,
+                            const int32_t* map_of, double* const* dst, int32_t n_daughters,
+                            hipStream_t s);
 hipError_t launch_spawn(const double* states, int32_t n, int32_t n_states, const int32_t* state_of,
                         const int32_t* map_of, double* const* dst, int32_t n_daughters, double lx,
                         hipStream_t s);

@@ -30,6 +30,8 @@ GAMMAS = (1e-6, 1e-4, 1e-2, 1.0)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_daughters_config2_traffic.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_config2_valu.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_kernels.hip")
+PEF_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_elongation.hip")
+PEF_VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_pef_n2048_valu.json")
 
 
 def kernel_hash() -> str:
@@ -324,6 +326,60 @@ def colour_leg(T, stream, ctx, mid, s, n_states, nst, fields=(1e-2, 1e-4)):
     return out
 
 
+def pef_roofline(kernel_ms, atom_steps):
+    """FP64 roofline of the planar-elongation kernel: the FP64 lane operations per atom-step
+    from the committed SQ counter run (while the kernel source matches it) over the live
+    kernel time, against the FP64 vector peak."""
+    try:
+        with open(PEF_VALU_FILE) as f:
+            rec = json.load(f)
+        with open(PEF_SRC, "rb") as f:
+            if rec.get("kernel_sha256_16") != hashlib.sha256(f.read()).hexdigest()[:16]:
+                return None
+    except (OSError, ValueError):
+        return None
+    flops = rec["fp64_flops_per_launch"] / rec["atom_steps_per_launch"] * atom_steps
+    achieved = flops / (kernel_ms / 1e3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": 78.6, "unit": "TFLOP/s",
+            "frac": achieved / 78.6, "traffic": None, "valu_busy": rec["valu_busy"],
+            "counts": "FP64 lane operations issued (FMA = 2, masked lanes included), from "
+                      + rec["source"]}
+
+
+def elongation_leg(T, stream, ctx, mid, s, n_states, nst, rates=(1.0, 1e-2, 1e-4)):
+    """The benchmark's start states under planar elongational flow instead of shear
+    (grad u = diag(rate, -rate, 0), mappings: identity, reversed momenta, x and y exchanged,
+    both): -<P_xx - P_yy>(t) / (4 rate), the elongational viscosity over 4 (the shear
+    viscosity in the linear regime), by TTCF and by the direct average at t = 0.25 and at
+    the end, with standard errors, and the FP64 kernel's throughput."""
+    import torch
+    r, p = ctx.ttcf_export_states(mid, n_states)
+    out = {"workload": f"N={s.n}, {n_states} states x 4 mappings x {nst} steps per rate"}
+    for rate in rates:
+        with T.Context(stream) as c2:
+            m2 = c2.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1),
+                                     r[0], p[0], n_equil=0)
+            c2.ttcf_import_states(m2, r, p)
+            c2.ttcf_spawn_elongational(m2, n_states, 0, rate, nst)
+            c2.ttcf_step_timing(reset=True)
+            c2.ttcf_step(nst)
+            ms, _ = c2.ttcf_step_timing(reset=True)
+            c2.ttcf_accumulate()
+            tm, tse, dm, dse, used = c2.ttcf_response(nst + 1, rate,
+                                                      observable=T.TTCF_OBS_PEF_N1)
+            torch.cuda.synchronize()
+        f = -1.0 / (4.0 * rate)
+        row = {"n_states": used, "kernel_ms": ms,
+               "kernel_atom_steps_per_s": 4 * n_states * s.n * nst / (ms / 1e3)}
+        for k in (100, nst):
+            row[f"t={k * s.dt:g}"] = {"eta_ttcf": float(f * tm[k]), "eta_ttcf_se": float(-f * tse[k]),
+                                      "eta_dav": float(f * dm[k]), "eta_dav_se": float(-f * dse[k])}
+        out[f"rate={rate:g}"] = row
+    ms = [out[k]["kernel_ms"] for k in out if k.startswith("rate=")]
+    out["roofline"] = pef_roofline(sum(ms) / len(ms), 4 * n_states * s.n * nst)
+    return out
+
+
 def graph_leg(T, stream, n_cells=8, copies=1024, between=100, nst=500, gd=1e-2, replays=3,
               decorrelate=400, seed=7):
     """Whole batch cycles replayed from one captured graph: 1024 persistent copies of the
@@ -570,6 +626,8 @@ def main():
                     help="1: also compare isokinetic and Nose-Hoover daughters on the same states")
     ap.add_argument("--observables", type=int, default=1,
                     help="1: also measure daughters that record the extra bulk observables")
+    ap.add_argument("--elongation", type=int, default=1,
+                    help="1: also measure planar-elongation daughters on the same start states")
     ap.add_argument("--colour", type=int, default=1,
                     help="1: also measure colour-field daughters on the same start states")
     ap.add_argument("--graph", type=int, default=1,
@@ -669,6 +727,12 @@ def main():
             observables = observables_leg(T, stream, ctx, mid, s, args.states, nst)
         except Exception as e:  # the headline line is printed whatever happens here
             observables = {"error": repr(e)}
+    elongation = None
+    if args.elongation:
+        try:
+            elongation = elongation_leg(T, stream, ctx, mid, s, args.states, nst)
+        except Exception as e:  # the headline line is printed whatever happens here
+            elongation = {"error": repr(e)}
     colour = None
     if args.colour:
         try:
@@ -731,6 +795,8 @@ def main():
         line["observables"] = observables
     if colour is not None:
         line["colour"] = colour
+    if elongation is not None:
+        line["elongation"] = elongation
     if args.graph:
         try:
             line["graph"] = graph_leg(T, stream)

@@ -128,45 +128,75 @@ __device__ __forceinline__ int pef_cell(double s, int nc) {
     return c > nc - 1 ? nc - 1 : c;
 }
 
+// Reciprocal: the hardware estimate refined by two Newton steps (within an ulp of 1/x).
+__device__ __forceinline__ double pef_recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
 // Force on atom i from the 27-cell stencil of the current cell list (cells in a fixed
-// order, members in ascending id), and its halves of the pair virial and energy.
+// order, members in ascending id), and its half of the pair virial. A stencil cell across
+// the box edge is the image shifted by one box length, so the separation of a member is
+// (s_i - shift) - s_j: with cells at least r_c wide, every pair within r_c is found through
+// its minimum image, and any other image is at least r_c away (every edge holds 3 cells).
 __device__ __forceinline__ void pef_atom_force(const PefShared& S, int i, int ncx, int ncy,
                                                int ncz, double lx, double ly, double lz,
-                                               double rc2, double ca, double ush, double& fx,
-                                               double& fy, double& fz, double& w, double& u) {
+                                               double rc2, double ca, double& fx, double& fy,
+                                               double& fz, double& w) {
     const double six = S.sx[i], siy = S.sy[i], siz = S.sz[i];
     const int cx = pef_cell(six, ncx), cy = pef_cell(siy, ncy), cz = pef_cell(siz, ncz);
+#pragma unroll 1
     for (int dz = -1; dz <= 1; ++dz) {
         int zz = cz + dz;
-        zz += zz < 0 ? ncz : (zz >= ncz ? -ncz : 0);
+        double az = siz;
+        if (zz < 0) {
+            zz += ncz;
+            az += 1.0;
+        } else if (zz >= ncz) {
+            zz -= ncz;
+            az -= 1.0;
+        }
+#pragma unroll 1
         for (int dy = -1; dy <= 1; ++dy) {
             int yy = cy + dy;
-            yy += yy < 0 ? ncy : (yy >= ncy ? -ncy : 0);
+            double ay = siy;
+            if (yy < 0) {
+                yy += ncy;
+                ay += 1.0;
+            } else if (yy >= ncy) {
+                yy -= ncy;
+                ay -= 1.0;
+            }
             for (int dx = -1; dx <= 1; ++dx) {
                 int xx = cx + dx;
-                xx += xx < 0 ? ncx : (xx >= ncx ? -ncx : 0);
+                double ax = six;
+                if (xx < 0) {
+                    xx += ncx;
+                    ax += 1.0;
+                } else if (xx >= ncx) {
+                    xx -= ncx;
+                    ax -= 1.0;
+                }
                 const int c = xx + ncx * (yy + ncy * zz);
                 const int e = S.start[c + 1];
                 for (int q = S.start[c]; q < e; ++q) {
                     const int m = S.sid[q];
                     if (m == i) continue;
-                    double ddx = six - S.sx[m];
-                    double ddy = siy - S.sy[m];
-                    double ddz = siz - S.sz[m];
-                    ddx = (ddx - rint(ddx)) * lx;
-                    ddy = (ddy - rint(ddy)) * ly;
-                    ddz = (ddz - rint(ddz)) * lz;
+                    const double ddx = (ax - S.sx[m]) * lx;
+                    const double ddy = (ay - S.sy[m]) * ly;
+                    const double ddz = (az - S.sz[m]) * lz;
                     const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                     if (r2 < rc2) {
-                        const double inv = 1.0 / r2;
+                        const double inv = pef_recip(r2);
                         const double s3 = inv * inv * inv;
-                        const double s6 = s3 * s3;
-                        const double fs = (48.0 * s6 - 24.0 * ca * s3) * inv;
+                        const double fs = (48.0 * s3 * s3 - 24.0 * ca * s3) * inv;
                         fx += fs * ddx;
                         fy += fs * ddy;
                         fz += fs * ddz;
                         w += 0.5 * (fs * (ddx * ddx - ddy * ddy));
-                        u += 0.5 * (4.0 * (s6 - ca * s3) + ush);
                     }
                 }
             }
@@ -178,9 +208,9 @@ __device__ __forceinline__ void pef_atom_force(const PefShared& S, int i, int nc
 // and ends with a barrier), then the forces on the thread's atoms and its share of the pair
 // virial W_xx - W_yy (each pair is seen from both sides, so each side adds half).
 __device__ void pef_forces(const PefShared& S, int n, int ncx, int ncy, int ncz, double lx,
-                           double ly, double lz, double rc2, double ca, double ush,
+                           double ly, double lz, double rc2, double ca,
                            double (&fx)[kPefApt],
-                           double (&fy)[kPefApt], double (&fz)[kPefApt], double& w, double& u) {
+                           double (&fy)[kPefApt], double (&fz)[kPefApt], double& w) {
     const int T = blockDim.x, t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6, nw = T >> 6;
     const int C = ncx * ncy * ncz;
@@ -252,11 +282,10 @@ __device__ void pef_forces(const PefShared& S, int n, int ncx, int ncy, int ncz,
     }
     __syncthreads();
     w = 0.0;
-    u = 0.0;
     for (int j = 0; j < kPefApt; ++j) {
         const int i = t + j * T;
         double ax = 0.0, ay = 0.0, az = 0.0;
-        if (i < n) pef_atom_force(S, i, ncx, ncy, ncz, lx, ly, lz, rc2, ca, ush, ax, ay, az, w, u);
+        if (i < n) pef_atom_force(S, i, ncx, ncy, ncz, lx, ly, lz, rc2, ca, ax, ay, az, w);
         fx[j] = ax;
         fy[j] = ay;
         fz[j] = az;
@@ -284,7 +313,7 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
     const int steps = min(L.max_steps, dp->n_steps - done0);
     const double rate = dp->gamma_dot, h = dp->sys.dt;
     const double l0x = dp->sys.box[0], l0y = dp->sys.box[1], lz = dp->sys.box[2];
-    const double rc = dp->sys.rc, rc2 = dp->sys.rc2, ca = dp->sys.c_attr, ush = dp->sys.u_shift;
+    const double rc = dp->sys.rc, rc2 = dp->sys.rc2, ca = dp->sys.c_attr;
     double* st = dp->state;
     double* series = dp->series;
     int64_t k = dp->k;
@@ -316,8 +345,8 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
             pz[j] = st[5 * n + a];
         }
     }
-    double w, u;
-    pef_forces(S, n, ncx, ncy, ncz, lx, ly, lz, rc2, ca, ush, fx, fy, fz, w, u);
+    double w;
+    pef_forces(S, n, ncx, ncy, ncz, lx, ly, lz, rc2, ca, fx, fy, fz, w);
     double k0 = dp->k0;
     {
         double v[3] = {0.0, 0.0, w};
@@ -397,7 +426,7 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
                 break;
             }
         }
-        pef_forces(S, n, ncx, ncy, ncz, lx, ly, lz, rc2, ca, ush, fx, fy, fz, w, u);
+        pef_forces(S, n, ncx, ncy, ncz, lx, ly, lz, rc2, ca, fx, fy, fz, w);
         // K(h/2), with the virial of the new positions in the same sum
         {
             double v[4] = {0.0, 0.0, 0.0, w};

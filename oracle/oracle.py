@@ -113,12 +113,18 @@ def _load():
                                     C.c_int64, D, D, D]
         lib.orc_run_daughters_pef.argtypes = [B, C.c_double, D, D, C.c_int32, I, I, D, C.c_int64,
                                               C.c_int32, D, D, D]
+        lib.orc_nh_pef_run.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_double,
+                                       C.c_double, D, D, D, D, C.c_int64, D, D, D, D]
+        lib.orc_run_daughters_pef_nh.argtypes = [B, C.c_double, C.c_double, C.c_double,
+                                                 C.c_double, D, D, D, C.c_int32, I, I, D,
+                                                 C.c_int64, C.c_int32, D, D, D]
         for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
                    "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
                    "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh",
                    "orc_observables", "orc_run_daughters_obs", "orc_colour_run",
                    "orc_run_daughters_colour", "orc_nh_colour_run", "orc_pef_forces",
-                   "orc_pef_run", "orc_run_daughters_pef"):
+                   "orc_pef_run", "orc_run_daughters_pef", "orc_nh_pef_run",
+                   "orc_run_daughters_pef_nh"):
             getattr(lib, fn).restype = C.c_int32
         _lib = lib
     return _lib
@@ -408,10 +414,29 @@ def pef_run(box: Box, r, p, rate: float, dt: float, nsteps: int, gik: bool = Tru
     return outs[0], outs[1], outs[2], float(e[0])
 
 
+def nh_pef_run(box: Box, r, p, zeta: float, rate: float, dt: float, temperature: float,
+               q: float, nf: float, nsteps: int, strain0: float = 0.0):
+    """Advance one Nose-Hoover planar-elongation trajectory in place (orc_nh_pef_run).
+    Returns (V (P_xx - P_yy), K, U, zeta series, zeta_final, final strain)."""
+    assert r.dtype == np.float64 and p.dtype == np.float64 and r.flags.c_contiguous
+    outs = [np.zeros(nsteps + 1) for _ in range(4)]
+    z = np.array([float(zeta)])
+    e = np.array([float(strain0)])
+    rc = _load().orc_nh_pef_run(C.byref(box), float(rate), float(dt), float(temperature),
+                                float(q), float(nf), _dp(e), _dp(r), _dp(p), _dp(z), int(nsteps),
+                                *[_dp(o) for o in outs])
+    if rc != 0:
+        raise RuntimeError(f"orc_nh_pef_run failed: {rc}")
+    return outs[0], outs[1], outs[2], outs[3], float(z[0]), float(e[0])
+
+
 def run_daughters_pef(box: Box, states_r, states_p, state_of, map_of, rate_of, dt: float,
-                      nsteps: int, nthreads: int = 0, final_state: bool = False):
-    """Isokinetic planar-elongation daughters on a CPU thread pool: V (P_xx - P_yy)
-    (n_d, nsteps+1) [and final r, p in the deformed box] and the number of threads used."""
+                      nsteps: int, nthreads: int = 0, final_state: bool = False,
+                      states_zeta=None, temperature: float = 0.0, q: float = 0.0,
+                      nf: float = 0.0):
+    """Planar-elongation daughters on a CPU thread pool (isokinetic, or Nose-Hoover from each
+    state's zeta when states_zeta is given): V (P_xx - P_yy) (n_d, nsteps+1) [and final r, p
+    in the deformed box] and the number of threads used."""
     states_r = _f64(states_r)
     states_p = _f64(states_p)
     state_of = np.ascontiguousarray(state_of, np.int32)
@@ -423,9 +448,18 @@ def run_daughters_pef(box: Box, states_r, states_p, state_of, map_of, rate_of, d
     po = np.zeros((nd, 3 * box.n)) if final_state else None
     if nthreads <= 0:
         nthreads = os.cpu_count() or 1
-    used = _load().orc_run_daughters_pef(C.byref(box), float(dt), _dp(states_r), _dp(states_p),
-                                         nd, _ip(state_of), _ip(map_of), _dp(rate_of),
-                                         int(nsteps), int(nthreads), _dp(out), _dp(ro), _dp(po))
+    if states_zeta is not None:
+        used = _load().orc_run_daughters_pef_nh(C.byref(box), float(dt), float(temperature),
+                                                float(q), float(nf), _dp(states_r),
+                                                _dp(states_p), _dp(_f64(states_zeta)), nd,
+                                                _ip(state_of), _ip(map_of), _dp(rate_of),
+                                                int(nsteps), int(nthreads), _dp(out), _dp(ro),
+                                                _dp(po))
+    else:
+        used = _load().orc_run_daughters_pef(C.byref(box), float(dt), _dp(states_r),
+                                             _dp(states_p), nd, _ip(state_of), _ip(map_of),
+                                             _dp(rate_of), int(nsteps), int(nthreads), _dp(out),
+                                             _dp(ro), _dp(po))
     if used < 0:
         raise RuntimeError(f"orc_run_daughters_pef failed: {used}")
     if final_state:

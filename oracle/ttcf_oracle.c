@@ -1237,6 +1237,9 @@ typedef struct {
     int64_t nsteps;
     double *vn1_out, *r_out, *p_out;
     int32_t tid, nthreads, status;
+    /* Nose-Hoover daughters when states_zeta is not NULL */
+    const double* states_zeta;
+    double temperature, q, nf;
 } pef_job;
 
 static void* pef_worker(void* arg) {
@@ -1250,8 +1253,17 @@ static void* pef_worker(void* arg) {
         orc_map_pef(jb->b, jb->map_of[d], jb->states_r + (size_t)s * sz,
                     jb->states_p + (size_t)s * sz, r, p);
         double e = 0.0;
-        int32_t rc = orc_pef_run(jb->b, jb->rate_of[d], jb->dt, 1, 0.0, &e, r, p, jb->nsteps,
-                                 jb->vn1_out + (size_t)d * (size_t)(jb->nsteps + 1), 0, 0);
+        double* vn = jb->vn1_out + (size_t)d * (size_t)(jb->nsteps + 1);
+        int32_t rc;
+        if (jb->states_zeta) {
+            /* the mappings that reverse the momenta (m = 1, 3) reverse the thermostat too */
+            double zt = (jb->map_of[d] & 1) ? -jb->states_zeta[s] : jb->states_zeta[s];
+            rc = orc_nh_pef_run(jb->b, jb->rate_of[d], jb->dt, jb->temperature, jb->q, jb->nf,
+                                &e, r, p, &zt, jb->nsteps, vn, 0, 0, 0);
+        } else {
+            rc = orc_pef_run(jb->b, jb->rate_of[d], jb->dt, 1, 0.0, &e, r, p, jb->nsteps, vn, 0,
+                             0);
+        }
         if (rc) jb->status = rc;
         if (jb->r_out) memcpy(jb->r_out + (size_t)d * sz, r, sizeof(double) * sz);
         if (jb->p_out) memcpy(jb->p_out + (size_t)d * sz, p, sizeof(double) * sz);
@@ -1261,18 +1273,20 @@ static void* pef_worker(void* arg) {
     return 0;
 }
 
-int32_t orc_run_daughters_pef(const orc_box* b, double dt, const double* states_r,
-                              const double* states_p, int32_t n_daughters,
-                              const int32_t* state_of, const int32_t* map_of,
-                              const double* rate_of, int64_t nsteps, int32_t nthreads,
-                              double* vn1_out, double* r_out, double* p_out) {
+static int32_t run_pef_batch(const orc_box* b, double dt, const double* states_r,
+                             const double* states_p, const double* states_zeta,
+                             double temperature, double q, double nf, int32_t n_daughters,
+                             const int32_t* state_of, const int32_t* map_of,
+                             const double* rate_of, int64_t nsteps, int32_t nthreads,
+                             double* vn1_out, double* r_out, double* p_out) {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > n_daughters) nthreads = n_daughters > 0 ? n_daughters : 1;
     pef_job* jobs = (pef_job*)calloc((size_t)nthreads, sizeof(pef_job));
     pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
     for (int32_t t = 0; t < nthreads; ++t) {
         pef_job j = {b,      dt,      states_r, states_p, n_daughters, state_of, map_of, rate_of,
-                     nsteps, vn1_out, r_out,    p_out,    t,           nthreads, 0};
+                     nsteps, vn1_out, r_out,    p_out,    t,           nthreads, 0,
+                     states_zeta, temperature, q, nf};
         jobs[t] = j;
         pthread_create(&th[t], 0, pef_worker, &jobs[t]);
     }
@@ -1284,4 +1298,108 @@ int32_t orc_run_daughters_pef(const orc_box* b, double dt, const double* states_
     free(jobs);
     free(th);
     return status ? status : nthreads;
+}
+
+/* Planar elongation with the Nose-Hoover multiplier of Eq. (system1) in place of the
+ * Gaussian one: dp/dt = F - p . grad u - zeta p, d zeta/dt = (sum p^2 - nf T)/q. The
+ * splitting of nh_sllod_run with the elongation's flow part E in place of the shear part,
+ * each part exact over half steps:
+ *   Z T E K D(h) [new box, wrap, F] K E T Z
+ * with Z: zeta += tau (sum p^2 - nf T)/q; T: p *= exp(-zeta tau); E: p_x e^{-rate tau},
+ * p_y e^{rate tau}; K: p += F tau; D the streaming of orc_pef_run. The sequence is
+ * symmetric: second order and time reversible under (p, zeta, rate) -> (-p, -zeta, -rate)
+ * from the final strain. zeta_out[s] holds zeta after step s. */
+int32_t orc_nh_pef_run(const orc_box* b0, double rate, double dt, double temperature, double q,
+                       double nf, double* e0, double* r, double* p, double* zeta, int64_t nsteps,
+                       double* vn1_out, double* ke_out, double* pe_out, double* zeta_out) {
+    const int32_t n = b0->n;
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!f) return -2;
+    double* x = r;
+    double* y = r + n;
+    double* z = r + 2 * n;
+    double* px = p;
+    double* py = p + n;
+    const double h = dt, tau = 0.5 * dt;
+    const double e_start = *e0;
+    orc_box bk;
+    pef_box(b0, e_start, &bk);
+    double out[3];
+    if (orc_pef_forces(&bk, r, f, out) != 0) {
+        free(f);
+        return -1;
+    }
+    const double ex = exp(-rate * tau), ey = exp(rate * tau);
+    const double dx_scale = exp(rate * h), dy_scale = exp(-rate * h);
+    const double phx = pef_phi(rate * h), phy = pef_phi(-rate * h);
+    double zt = *zeta;
+    double s0 = 0.0;
+    for (int32_t i = 0; i < n; ++i) s0 += px[i] * px[i] - py[i] * py[i];
+    if (vn1_out) vn1_out[0] = s0 + out[1];
+    if (ke_out) ke_out[0] = kinetic(n, p);
+    if (pe_out) pe_out[0] = out[0];
+    if (zeta_out) zeta_out[0] = zt;
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
+        double sc = exp(-zt * tau);
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] *= sc;
+        for (int32_t i = 0; i < n; ++i) {
+            px[i] *= ex;
+            py[i] *= ey;
+        }
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] += tau * f[c];
+        for (int32_t i = 0; i < n; ++i) {
+            x[i] = dx_scale * (x[i] + h * px[i] * phx);
+            y[i] = dy_scale * (y[i] + h * py[i] * phy);
+            z[i] += h * p[2 * n + i];
+        }
+        pef_box(b0, e_start + rate * ((double)s * h), &bk);
+        for (int32_t i = 0; i < n; ++i) {
+            x[i] = wrap1(x[i], bk.lx);
+            y[i] = wrap1(y[i], bk.ly);
+            z[i] = wrap1(z[i], bk.lz);
+        }
+        if (orc_pef_forces(&bk, r, f, out) != 0) {
+            free(f);
+            return -1;
+        }
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] += tau * f[c];
+        for (int32_t i = 0; i < n; ++i) {
+            px[i] *= ex;
+            py[i] *= ey;
+        }
+        sc = exp(-zt * tau);
+        for (int32_t c = 0; c < 3 * n; ++c) p[c] *= sc;
+        zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
+        double sk = 0.0;
+        for (int32_t i = 0; i < n; ++i) sk += px[i] * px[i] - py[i] * py[i];
+        if (vn1_out) vn1_out[s] = sk + out[1];
+        if (ke_out) ke_out[s] = kinetic(n, p);
+        if (pe_out) pe_out[s] = out[0];
+        if (zeta_out) zeta_out[s] = zt;
+    }
+    *zeta = zt;
+    *e0 = e_start + rate * ((double)nsteps * h);
+    free(f);
+    return 0;
+}
+
+int32_t orc_run_daughters_pef(const orc_box* b, double dt, const double* states_r,
+                              const double* states_p, int32_t n_daughters,
+                              const int32_t* state_of, const int32_t* map_of,
+                              const double* rate_of, int64_t nsteps, int32_t nthreads,
+                              double* vn1_out, double* r_out, double* p_out) {
+    return run_pef_batch(b, dt, states_r, states_p, 0, 0.0, 0.0, 0.0, n_daughters, state_of,
+                         map_of, rate_of, nsteps, nthreads, vn1_out, r_out, p_out);
+}
+
+int32_t orc_run_daughters_pef_nh(const orc_box* b, double dt, double temperature, double q,
+                                 double nf, const double* states_r, const double* states_p,
+                                 const double* states_zeta, int32_t n_daughters,
+                                 const int32_t* state_of, const int32_t* map_of,
+                                 const double* rate_of, int64_t nsteps, int32_t nthreads,
+                                 double* vn1_out, double* r_out, double* p_out) {
+    if (!states_zeta) return -1;
+    return run_pef_batch(b, dt, states_r, states_p, states_zeta, temperature, q, nf, n_daughters,
+                         state_of, map_of, rate_of, nsteps, nthreads, vn1_out, r_out, p_out);
 }

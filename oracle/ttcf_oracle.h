@@ -192,6 +192,19 @@ void orc_map_pef(const orc_box* b, int32_t m, const double* r, const double* p, 
 int32_t orc_pef_run(const orc_box* b0, double rate, double dt, int32_t gik, double k0,
                     double* e0, double* r, double* p, int64_t nsteps, double* vn1_out,
                     double* ke_out, double* pe_out);
+/* Nose-Hoover planar elongation (splitting Z T E K D K E T Z over half steps); outputs as
+ * orc_pef_run plus zeta_out (nsteps + 1 values, NULL to skip); *zeta is advanced.
+ * orc_run_daughters_pef_nh: as orc_run_daughters_pef from each state's zeta, reversed by the
+ * mappings that reverse the momenta (m = 1, 3). */
+int32_t orc_nh_pef_run(const orc_box* b0, double rate, double dt, double temperature, double q,
+                       double nf, double* e0, double* r, double* p, double* zeta, int64_t nsteps,
+                       double* vn1_out, double* ke_out, double* pe_out, double* zeta_out);
+int32_t orc_run_daughters_pef_nh(const orc_box* b, double dt, double temperature, double q,
+                                 double nf, const double* states_r, const double* states_p,
+                                 const double* states_zeta, int32_t n_daughters,
+                                 const int32_t* state_of, const int32_t* map_of,
+                                 const double* rate_of, int64_t nsteps, int32_t nthreads,
+                                 double* vn1_out, double* r_out, double* p_out);
 int32_t orc_run_daughters_pef(const orc_box* b, double dt, const double* states_r,
                               const double* states_p, int32_t n_daughters,
                               const int32_t* state_of, const int32_t* map_of,

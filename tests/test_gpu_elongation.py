@@ -198,3 +198,30 @@ def test_full_size_sampled(T, orc):
                                           nthreads=8, final_state=True)
     assert np.abs(ser - vo).max() / np.std(vo) <= 1e-8
     check_final(s, fin, ro, po, rate_of, nst, 1e-8)
+
+
+def test_uneven_systems_in_one_step_call(T, orc):
+    """N = 108 and N = 500 daughters in one launch (sized for the larger system): each
+    matches the oracle as when run alone."""
+    nst, n_states = 40, 2
+    cases = []
+    for cells, seed, rate in ((3, 85, 0.7), (5, 86, -0.4)):
+        s = I.System(cells)
+        box, sr, sp = oracle_states(orc, s, seed, n_states, n_equil=300)
+        cases.append((s, box, sr, sp, rate))
+    say("PEF uneven systems in one step call")
+    firsts = []
+    with T.Context() as ctx:
+        for s, box, sr, sp, rate in cases:
+            mid = ctx.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt,
+                                                     precision=1), sr[0], sp[0], n_equil=0)
+            ctx.ttcf_import_states(mid, sr, sp)
+            firsts.append(ctx.ttcf_spawn_elongational(mid, n_states, 0, rate, nst))
+        ctx.ttcf_step(nst)
+        sers = [ctx.ttcf_export_series(f, 4 * n_states, nst + 1) for f in firsts]
+    state_of = np.repeat(np.arange(n_states), 4)
+    map_of = np.tile(np.arange(4), n_states)
+    for (s, box, sr, sp, rate), ser in zip(cases, sers):
+        vo, _ = orc.run_daughters_pef(box, sr, sp, state_of, map_of, np.full(4 * n_states, rate),
+                                      s.dt, nst, nthreads=8)
+        assert np.abs(ser - vo).max() / np.std(vo) <= 1e-9

@@ -184,3 +184,48 @@ def test_ttcf_agrees_with_the_direct_average_at_a_strong_rate(orc, start_states)
     wrong = orc.ttcf_response(x / s.volume, -x[:, 0], np.full(4 * ns, rate), s.temperature, s.dt)
     for k in (50, 100):
         assert abs(wrong.ttcf[k] - resp.dav[k]) > 4 * np.hypot(wrong.ttcf_se[k], resp.dav_se[k])
+
+
+def test_nose_hoover_elongation_step(orc, liquid):
+    """Nose-Hoover planar elongation: at rate 0 the zero-shear Nose-Hoover SLLOD step; the
+    extended energy K + U + Q zeta^2/2 + nf T int zeta changes by -rate int V (P_xx - P_yy)
+    with a second-order residual (and fails by the whole work with the wrong sign);
+    (p, zeta, rate) -> (-p, -zeta, -rate) from the final strain retraces the path."""
+    s, box, st = liquid
+    q = orc.nh_q(s.nf, s.temperature, TAU)
+    z0 = 0.3
+    r1, p1 = st.r.copy(), st.p.copy()
+    orc.nh_pef_run(box, r1, p1, z0, 0.0, s.dt, s.temperature, q, s.nf, 80)
+    r2, p2 = st.r.copy(), st.p.copy()
+    orc.nh_sllod_run(box, r2, p2, z0, 0.0, s.dt, s.temperature, q, s.nf, 80)
+    np.testing.assert_allclose(r1, r2, rtol=0, atol=1e-10 * s.box)
+    np.testing.assert_allclose(p1, p2, rtol=0, atol=1e-10)
+
+    rate = 0.6
+
+    def residual(dt, nsteps, sign=1.0):
+        r, p = st.r.copy(), st.p.copy()
+        vn1, k, u, zs, _, _ = orc.nh_pef_run(box, r, p, z0, rate, dt, s.temperature, q, s.nf,
+                                             nsteps)
+        izeta = np.concatenate([[0.0], np.cumsum(0.5 * dt * (zs[1:] + zs[:-1]))])
+        h = k + u + 0.5 * q * zs ** 2 + s.nf * s.temperature * izeta
+        work = -sign * rate * np.concatenate([[0.0], np.cumsum(0.5 * dt * (vn1[1:] + vn1[:-1]))])
+        return np.abs((h - h[0]) - work).max(), np.abs(work).max()
+
+    res1, work = residual(s.dt, 160)
+    res2, _ = residual(s.dt / 2, 320)
+    assert work > 20 * res1
+    assert 3.0 < res1 / res2 < 5.0
+    wrong, _ = residual(s.dt, 160, sign=-1.0)
+    assert wrong > 10 * res1
+    r, p = st.r.copy(), st.p.copy()
+    *_, z1, e1 = orc.nh_pef_run(box, r, p, z0, rate, s.dt, s.temperature, q, s.nf, 250)
+    p = -p
+    *_, z2, e2 = orc.nh_pef_run(box, r, p, -z1, -rate, s.dt, s.temperature, q, s.nf, 250,
+                                strain0=e1)
+    assert abs(e2) < 1e-14
+    dr = r - st.r
+    dr -= s.box * np.rint(dr / s.box)
+    assert np.abs(dr).max() < 1e-8
+    assert np.abs(-p - st.p).max() < 1e-8
+    assert abs(-z2 - z0) < 1e-9

@@ -154,8 +154,10 @@ int32_t ttcf_spawn_colour(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
 
 /* Introduction: TTCF extends to elongational flows; Section Mathematical Framework: a field
  * other than shear needs its own mappings. Planar elongational flow (the paper prints no
- * equations for it): SLLOD of Eq. (system1) with grad u = diag(rate, -rate, 0), isokinetic
- * (alpha keeps p.p fixed), in an orthorhombic box deforming as L_x e^e, L_y e^-e, L_z with
+ * equations for it): SLLOD of Eq. (system1) with grad u = diag(rate, -rate, 0), with the
+ * mother system's daughter thermostat (isokinetic: alpha keeps p.p fixed; Nose-Hoover:
+ * alpha = zeta of Eq. system1, carried from the start state and reversed by mappings 1 and
+ * 3), in an orthorhombic box deforming as L_x e^e, L_y e^-e, L_z with
  * e = rate t (volume conserved); no reproducible lattice, as daughters are short.
  * B(t) = P_xx - P_yy, Omega(0) = -(V/T) rate (P_xx - P_yy)(0) (from dH/dt = -V grad u : P).
  * Mappings (bit m of mapping_mask): 0 identity, 1 reversed momenta, 2 x and y axes exchanged
@@ -165,9 +167,9 @@ int32_t ttcf_spawn_colour(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
  * states (ttcf_export_daughter) are in the coordinates of the deformed box. ttcf_accumulate
  * folds these groups and ttcf_response(ctx, TTCF_OBS_PEF_N1, rate, ...) returns
  * <P_xx - P_yy>(t) (-4 times the elongational viscosity times the rate in the linear regime).
- * Forces are FP64 whatever the system's precision. TTCF_EINVAL for N > 2048, L_x != L_y, a
- * Nose-Hoover daughter thermostat, the extra observables switched on, or a rate and length
- * that would shrink a box edge below 3 r_c before the daughter ends. */
+ * Forces are FP64 whatever the system's precision. TTCF_EINVAL for N > 2048, L_x != L_y,
+ * the extra observables switched on, or a rate and length that would shrink a box edge below
+ * 3 r_c before the daughter ends. */
 int32_t ttcf_spawn_elongational(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
                                 int64_t steps_between, uint32_t mapping_mask, const double* rate,
                                 int32_t n_rate, int32_t n_steps, int64_t* out_first);

@@ -841,8 +841,6 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
         if (c->record_obs)
             return fail(c, TTCF_EINVAL, "planar-elongation daughters record V (P_xx - P_yy) "
                                         "only: switch the extra observables off");
-        if (m.sys.daughter_thermostat == TTCF_DAUGHTER_NH)
-            return fail(c, TTCF_EINVAL, "planar-elongation daughters are isokinetic");
         if (m.dev.n > kPefMaxAtoms)
             return fail(c, TTCF_EINVAL, "planar-elongation daughters hold at most 2048 atoms");
         if (m.dev.box[0] != m.dev.box[1])
@@ -1098,14 +1096,14 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     // is one persistent launch, largest systems first. groups[2 form + thermo], form 0 lists,
     // 1 cells, 2 lists in global scratch
     std::vector<int32_t> groups[6];
-    std::vector<int32_t> pef;  // planar-elongation daughters: their own kernel, FP64 forces
+    std::vector<int32_t> pef[2];  // planar-elongation daughters by thermostat: own kernel, FP64
     std::vector<StepShape> eff(c->descs.size());
     int precision = -1;
     for (size_t i = 0; i < c->descs.size(); ++i) {
         DaughterDesc& d = c->descs[i];
         if (d.health != 0 || d.done >= d.n_steps || (only && !(*only)[i])) continue;
         if (d.field == kFieldElong) {
-            pef.push_back((int32_t)i);
+            pef[d.thermo ? 1 : 0].push_back((int32_t)i);
             continue;
         }
         const Mother& m = c->mothers[c->batches[c->live[i].batch].mother];
@@ -1130,7 +1128,7 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     const bool any_nl = !groups[0].empty() || !groups[1].empty() || !groups[4].empty() ||
                         !groups[5].empty();
     const bool any_cell = !groups[2].empty() || !groups[3].empty();
-    if (!any_nl && !any_cell && pef.empty()) return TTCF_OK;
+    if (!any_nl && !any_cell && pef[0].empty() && pef[1].empty()) return TTCF_OK;
     if (any_nl) {
         rc = push_descs(c);  // the list grids were just written into the descriptors
         if (rc != TTCF_OK) return rc;
@@ -1141,8 +1139,10 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         std::stable_sort(g.begin(), g.end(), by_size);
         order.insert(order.end(), g.begin(), g.end());
     }
-    std::stable_sort(pef.begin(), pef.end(), by_size);
-    order.insert(order.end(), pef.begin(), pef.end());
+    for (auto& g : pef) {
+        std::stable_sort(g.begin(), g.end(), by_size);
+        order.insert(order.end(), g.begin(), g.end());
+    }
     if (c->d_order_cap < order.size()) {
         dev_free(c->d_order);
         c->d_order = (int32_t*)dev_alloc(sizeof(int32_t) * order.size() * 2, c->stream);
@@ -1190,13 +1190,16 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
             c->pending_events.emplace_back(e0, e1);
         }
     }
-    if (!pef.empty()) {
+    for (int th = 0; th < 2; ++th) {
+        if (pef[th].empty()) continue;
         PefLaunch P{};
         P.descs = c->d_descs;
         P.order = c->d_order + offset;
-        P.n_jobs = (int32_t)pef.size();
+        offset += pef[th].size();
+        P.n_jobs = (int32_t)pef[th].size();
         P.max_steps = n_steps;
-        for (int32_t i : pef) {
+        P.thermo = th;
+        for (int32_t i : pef[th]) {
             const SysDev& sd = c->descs[i].sys;
             P.nmax = std::max(P.nmax, sd.n);
             // no cell grid of a box of this volume exceeds volume / r_c^3 cells

@@ -292,6 +292,10 @@ __device__ void pef_forces(const PefShared& S, int n, int ncx, int ncy, int ncz,
     }
 }
 
+// NH: Nose-Hoover daughters (dp/dt gains -zeta p, d zeta/dt = (sum p^2 - nf T)/Q), stepped
+// Z T E K D K E T Z over half steps with each part exact, in place of the isokinetic
+// E K D K E and rescale.
+template <bool NH>
 __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
     extern __shared__ __align__(16) char smem[];
     const PefPlan plan = pef_plan(L.nmax, L.cmax);
@@ -327,7 +331,9 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
         if (t == 0) dp->health = health;
         return;
     }
-    const double ex = exp(-0.5 * rate * h), ey = exp(0.5 * rate * h);
+    const double ex = exp(-0.5 * rate * h), ey = exp(0.5 * rate * h), tau = 0.5 * h;
+    double zeta = dp->zeta;
+    const double nh_q = dp->nh_q, nh_target = dp->nh_target;
     const double phx = pef_phi(rate * h), phy = pef_phi(-rate * h);
 
     double px[kPefApt], py[kPefApt], pz[kPefApt];
@@ -363,42 +369,60 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
     }
     int it = 0;
     for (; it < steps; ++it) {
-        // E(h/2)
-        {
-            double v[2] = {0.0, 0.0};
+        if constexpr (NH) {
+            // Z(h/2) T(h/2) E(h/2) K(h/2)
+            {
+                double v[1] = {0.0};
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                px[j] *= ex;
-                py[j] *= ey;
-                v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                for (int j = 0; j < kPefApt; ++j) v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                pef_sum<1>(v, S.red);
+                zeta += tau * (v[0] - nh_target) / nh_q;
+                const double sc = exp(-zeta * tau);
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] = (px[j] * sc) * ex + tau * fx[j];
+                    py[j] = (py[j] * sc) * ey + tau * fy[j];
+                    pz[j] = pz[j] * sc + tau * fz[j];
+                }
             }
-            pef_sum<2>(v, S.red);
-            const double g = sqrt(v[0] / v[1]);
+        } else {
+            // E(h/2)
+            {
+                double v[2] = {0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                px[j] *= g;
-                py[j] *= g;
-                pz[j] *= g;
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    px[j] *= ex;
+                    py[j] *= ey;
+                    v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                }
+                pef_sum<2>(v, S.red);
+                const double g = sqrt(v[0] / v[1]);
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] *= g;
+                    py[j] *= g;
+                    pz[j] *= g;
+                }
             }
-        }
-        // K(h/2)
-        {
-            double v[3] = {0.0, 0.0, 0.0};
+            // K(h/2)
+            {
+                double v[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                v[1] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
-                v[2] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
-            }
-            pef_sum<3>(v, S.red);
-            double s, sd;
-            pef_kick_coeffs(v[1] / v[0], v[2] / v[0], 0.5 * h, s, sd);
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    v[1] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+                    v[2] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+                }
+                pef_sum<3>(v, S.red);
+                double s, sd;
+                pef_kick_coeffs(v[1] / v[0], v[2] / v[0], 0.5 * h, s, sd);
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                px[j] = (px[j] + fx[j] * s) / sd;
-                py[j] = (py[j] + fy[j] * s) / sd;
-                pz[j] = (pz[j] + fz[j] * s) / sd;
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] = (px[j] + fx[j] * s) / sd;
+                    py[j] = (py[j] + fy[j] * s) / sd;
+                    pz[j] = (pz[j] + fz[j] * s) / sd;
+                }
             }
         }
         // D(h) in fractional coordinates, then the box of step k + 1. Every thread has
@@ -427,67 +451,92 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
             }
         }
         pef_forces(S, n, ncx, ncy, ncz, lx, ly, lz, rc2, ca, fx, fy, fz, w);
-        // K(h/2), with the virial of the new positions in the same sum
-        {
-            double v[4] = {0.0, 0.0, 0.0, w};
+        if constexpr (NH) {
+            // K(h/2) E(h/2) T(h/2) Z(h/2), with V (P_xx - P_yy) in the same sum
+            {
+                const double sc = exp(-zeta * tau);
+                double v[3] = {0.0, 0.0, w};
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                v[1] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
-                v[2] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] = ((px[j] + tau * fx[j]) * ex) * sc;
+                    py[j] = ((py[j] + tau * fy[j]) * ey) * sc;
+                    pz[j] = (pz[j] + tau * fz[j]) * sc;
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    v[1] += px[j] * px[j] - py[j] * py[j];
+                }
+                pef_sum<3>(v, S.red);
+                zeta += tau * (v[0] - nh_target) / nh_q;
+                const double vn1 = v[1] + v[2];
+                if (t == 0) series[done0 + it + 1] = vn1;
+                if (!isfinite(vn1)) {
+                    health = kHealthNonFinite;  // uniform: every thread holds the same sum
+                    ++it;
+                    break;
+                }
             }
-            pef_sum<4>(v, S.red);
-            w = v[3];
-            double s, sd;
-            pef_kick_coeffs(v[1] / v[0], v[2] / v[0], 0.5 * h, s, sd);
+        } else {
+            // K(h/2), with the virial of the new positions in the same sum
+            {
+                double v[4] = {0.0, 0.0, 0.0, w};
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                px[j] = (px[j] + fx[j] * s) / sd;
-                py[j] = (py[j] + fy[j] * s) / sd;
-                pz[j] = (pz[j] + fz[j] * s) / sd;
-            }
-        }
-        // E(h/2)
-        {
-            double v[2] = {0.0, 0.0};
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    v[1] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+                    v[2] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+                }
+                pef_sum<4>(v, S.red);
+                w = v[3];
+                double s, sd;
+                pef_kick_coeffs(v[1] / v[0], v[2] / v[0], 0.5 * h, s, sd);
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                px[j] *= ex;
-                py[j] *= ey;
-                v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] = (px[j] + fx[j] * s) / sd;
+                    py[j] = (py[j] + fy[j] * s) / sd;
+                    pz[j] = (pz[j] + fz[j] * s) / sd;
+                }
             }
-            pef_sum<2>(v, S.red);
-            const double g = sqrt(v[0] / v[1]);
+            // E(h/2)
+            {
+                double v[2] = {0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                px[j] *= g;
-                py[j] *= g;
-                pz[j] *= g;
-            }
-        }
-        // rescale to K0 (round-off only) and record V (P_xx - P_yy)
-        {
-            double v[2] = {0.0, 0.0};
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    px[j] *= ex;
+                    py[j] *= ey;
+                    v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                }
+                pef_sum<2>(v, S.red);
+                const double g = sqrt(v[0] / v[1]);
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                v[1] += px[j] * px[j] - py[j] * py[j];
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] *= g;
+                    py[j] *= g;
+                    pz[j] *= g;
+                }
             }
-            pef_sum<2>(v, S.red);
-            const double lam = sqrt(k0 / (0.5 * v[0]));
+            // rescale to K0 (round-off only) and record V (P_xx - P_yy)
+            {
+                double v[2] = {0.0, 0.0};
 #pragma unroll
-            for (int j = 0; j < kPefApt; ++j) {
-                px[j] *= lam;
-                py[j] *= lam;
-                pz[j] *= lam;
-            }
-            const double vn1 = lam * lam * v[1] + w;
-            if (t == 0) series[done0 + it + 1] = vn1;
-            if (!isfinite(vn1)) {
-                health = kHealthNonFinite;  // uniform: every thread holds the same sum
-                ++it;
-                break;
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    v[1] += px[j] * px[j] - py[j] * py[j];
+                }
+                pef_sum<2>(v, S.red);
+                const double lam = sqrt(k0 / (0.5 * v[0]));
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] *= lam;
+                    py[j] *= lam;
+                    pz[j] *= lam;
+                }
+                const double vn1 = lam * lam * v[1] + w;
+                if (t == 0) series[done0 + it + 1] = vn1;
+                if (!isfinite(vn1)) {
+                    health = kHealthNonFinite;  // uniform: every thread holds the same sum
+                    ++it;
+                    break;
+                }
             }
         }
     }
@@ -508,6 +557,7 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
         dp->k = k;
         dp->done = done0 + it;
         dp->k0 = k0;
+        if (NH) dp->zeta = zeta;
         dp->health = health;
     }
 }
@@ -553,9 +603,17 @@ hipError_t launch_pef(const PefLaunch& L, hipStream_t s) {
     if (L.threads < 64 || L.threads > kMaxThreads || L.threads % 64 != 0 ||
         L.nmax > L.threads * kPefApt || L.cmax < 27)
         return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_daughters_pef,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
-    hipLaunchKernelGGL(k_daughters_pef, dim3(L.n_jobs), dim3(L.threads), L.lds_bytes, s, L);
+    if (L.thermo) {
+        (void)hipFuncSetAttribute((const void*)k_daughters_pef<true>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+        hipLaunchKernelGGL(k_daughters_pef<true>, dim3(L.n_jobs), dim3(L.threads), L.lds_bytes, s,
+                           L);
+    } else {
+        (void)hipFuncSetAttribute((const void*)k_daughters_pef<false>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+        hipLaunchKernelGGL(k_daughters_pef<false>, dim3(L.n_jobs), dim3(L.threads), L.lds_bytes,
+                           s, L);
+    }
     return hipGetLastError();
 }
 

@@ -121,7 +121,8 @@ struct BatchLaunch {
 };
 
 // Planar-elongation daughters (ttcf_elongation.hip): one workgroup per job, two atoms per
-// thread, FP64 forces over a cell grid rebuilt every step from the deformed box.
+// thread, FP64 forces over a cell grid rebuilt every step from the deformed box; one launch
+// per daughter thermostat.
 struct PefLaunch {
     DaughterDesc* descs;   // device array
     const int32_t* order;  // device: desc index of each job
@@ -130,6 +131,7 @@ struct PefLaunch {
     int32_t threads;       // pef_threads(nmax)
     int32_t nmax;          // largest system
     int32_t cmax;          // >= the cell count of any job's box at any step
+    int32_t thermo;        // daughter thermostat of every job (0 isokinetic, 1 Nose-Hoover)
     size_t lds_bytes;      // lds_bytes_pef(nmax, cmax)
 };
 

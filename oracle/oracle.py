@@ -118,13 +118,23 @@ def _load():
         lib.orc_run_daughters_pef_nh.argtypes = [B, C.c_double, C.c_double, C.c_double,
                                                  C.c_double, D, D, D, C.c_int32, I, I, D,
                                                  C.c_int64, C.c_int32, D, D, D]
+        lib.orc_mix_forces.argtypes = [B, D, D, D, D]
+        lib.orc_map_mix.argtypes = [B, C.c_int32, D, D, D, D]
+        lib.orc_map_mix.restype = None
+        lib.orc_mix_run.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                    C.c_double, C.c_double, C.c_double, D, D, D, D, C.c_int64,
+                                    D, D, D]
+        lib.orc_run_daughters_mix.argtypes = [B, C.c_double, D, D, D, C.c_double, C.c_double,
+                                              C.c_double, C.c_int32, I, I, D, D, C.c_int64,
+                                              C.c_int32, D, D, D]
         for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
                    "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
                    "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh",
                    "orc_observables", "orc_run_daughters_obs", "orc_colour_run",
                    "orc_run_daughters_colour", "orc_nh_colour_run", "orc_pef_forces",
                    "orc_pef_run", "orc_run_daughters_pef", "orc_nh_pef_run",
-                   "orc_run_daughters_pef_nh"):
+                   "orc_run_daughters_pef_nh", "orc_mix_forces", "orc_mix_run",
+                   "orc_run_daughters_mix"):
             getattr(lib, fn).restype = C.c_int32
         _lib = lib
     return _lib
@@ -462,6 +472,82 @@ def run_daughters_pef(box: Box, states_r, states_p, state_of, map_of, rate_of, d
                                              _dp(ro), _dp(po))
     if used < 0:
         raise RuntimeError(f"orc_run_daughters_pef failed: {used}")
+    if final_state:
+        return out, ro, po, used
+    return out, used
+
+
+def mix_cell(box: Box, erate: float, srate: float, t: float):
+    """(H_xx, H_xy, H_yy) of the mixed-flow cell at time t: exp(A t) diag(L)."""
+    x = erate * t
+    sh = 1.0 if x == 0.0 else np.sinh(x) / x
+    return np.array([box.lx * np.exp(x), box.ly * srate * t * sh, box.ly * np.exp(-x)])
+
+
+def mix_forces(box: Box, h, r):
+    """Forces in the mixed-flow cell (orc_mix_forces): (f, U, W_xx - W_yy, W_xy, pairs)."""
+    r = _f64(r)
+    h = _f64(h)
+    f = np.zeros(3 * box.n)
+    out = np.zeros(4)
+    rc = _load().orc_mix_forces(C.byref(box), _dp(h), _dp(r), _dp(f), _dp(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_mix_forces failed: {rc}")
+    return f, out[0], out[1], out[2], out[3]
+
+
+def map_mix(box: Box, m: int, r, p):
+    """Mapping m of mixed flow (bit 1: exchange of the x and y axes, then bit 0: x-reflection)."""
+    r = _f64(r)
+    p = _f64(p)
+    ro = np.zeros(3 * box.n)
+    po = np.zeros(3 * box.n)
+    _load().orc_map_mix(C.byref(box), int(m), _dp(r), _dp(p), _dp(ro), _dp(po))
+    return ro, po
+
+
+def mix_run(box: Box, r, p, erate: float, srate: float, dt: float, nsteps: int,
+            gik: bool = True, t0: float = 0.0, zeta=None, temperature: float = 0.0,
+            q: float = 0.0, nf: float = 0.0):
+    """Advance one mixed-flow trajectory in place (orc_mix_run); Nose-Hoover when zeta is
+    given. Returns (V J, K, U) series of length nsteps+1, the final time and the final zeta."""
+    assert r.dtype == np.float64 and p.dtype == np.float64 and r.flags.c_contiguous
+    outs = [np.zeros(nsteps + 1) for _ in range(3)]
+    t = np.array([float(t0)])
+    z = np.array([float(zeta) if zeta is not None else 0.0])
+    rc = _load().orc_mix_run(C.byref(box), float(erate), float(srate), float(dt), int(gik),
+                             int(zeta is not None), float(temperature), float(q), float(nf),
+                             _dp(t), _dp(r), _dp(p), _dp(z), int(nsteps), *[_dp(o) for o in outs])
+    if rc != 0:
+        raise RuntimeError(f"orc_mix_run failed: {rc}")
+    return outs[0], outs[1], outs[2], float(t[0]), float(z[0])
+
+
+def run_daughters_mix(box: Box, states_r, states_p, state_of, map_of, er_of, sr_of, dt: float,
+                      nsteps: int, nthreads: int = 0, final_state: bool = False,
+                      states_zeta=None, temperature: float = 0.0, q: float = 0.0,
+                      nf: float = 0.0):
+    """Mixed-flow daughters on a CPU thread pool: V J (n_d, nsteps+1) [and final r, p] and the
+    number of threads used."""
+    states_r = _f64(states_r)
+    states_p = _f64(states_p)
+    state_of = np.ascontiguousarray(state_of, np.int32)
+    map_of = np.ascontiguousarray(map_of, np.int32)
+    er_of = _f64(er_of)
+    sr_of = _f64(sr_of)
+    nd = len(state_of)
+    out = np.zeros((nd, nsteps + 1))
+    ro = np.zeros((nd, 3 * box.n)) if final_state else None
+    po = np.zeros((nd, 3 * box.n)) if final_state else None
+    if nthreads <= 0:
+        nthreads = os.cpu_count() or 1
+    zeta = _f64(states_zeta) if states_zeta is not None else None
+    used = _load().orc_run_daughters_mix(C.byref(box), float(dt), _dp(states_r), _dp(states_p),
+                                         _dp(zeta), float(temperature), float(q), float(nf), nd,
+                                         _ip(state_of), _ip(map_of), _dp(er_of), _dp(sr_of),
+                                         int(nsteps), int(nthreads), _dp(out), _dp(ro), _dp(po))
+    if used < 0:
+        raise RuntimeError(f"orc_run_daughters_mix failed: {used}")
     if final_state:
         return out, ro, po, used
     return out, used

@@ -1403,3 +1403,294 @@ int32_t orc_run_daughters_pef_nh(const orc_box* b, double dt, double temperature
     return run_pef_batch(b, dt, states_r, states_p, states_zeta, temperature, q, nf, n_daughters,
                          state_of, map_of, rate_of, nsteps, nthreads, vn1_out, r_out, p_out);
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* mixed flow: shear and planar elongation together                                      */
+/* ------------------------------------------------------------------------------------ */
+/* The Introduction names mixed flows among those TTCF extends to. Reading used here: SLLOD
+ * with u_x = erate x + srate y, u_y = -erate y, i.e. dr/dt = p + A r, dp/dt = F - A p
+ * - alpha p with A = [[erate, srate, 0], [0, -erate, 0], [0, 0, 0]], Gaussian isokinetic
+ * (or Nose-Hoover) alpha, in the box that the flow carries: columns of
+ * H(t) = exp(A t) diag(L_x0, L_y0, L_z0), i.e.
+ *   H_xx = L_x0 e^{erate t}, H_yy = L_y0 e^{-erate t}, H_xy = L_y0 srate t sinhc(erate t)
+ * (sinhc x = sinh x / x), a triclinic cell of constant volume. Positions are wrapped by their
+ * fractional coordinates s = H^-1 r. The dissipative flux is grad u : P = erate (P_xx - P_yy)
+ * + srate P_xy; the daughters record V J with J = (grad u : P) / |rate|,
+ * |rate| = sqrt(erate^2 + srate^2), so that Omega(0) = -(V/T) |rate| J(0). */
+
+static double sinhc(double x) { return x == 0.0 ? 1.0 : sinh(x) / x; }
+
+static void mix_box(const orc_box* b0, double er, double sr, double t, double h[3]) {
+    h[0] = b0->lx * exp(er * t);
+    h[1] = b0->ly * sr * t * sinhc(er * t);
+    h[2] = b0->ly * exp(-er * t);
+}
+
+/* Forces in the triclinic cell (columns (h0, 0, 0), (h1, h2, 0), (0, 0, L_z)) by a plain sum
+ * over pairs i < j, each through the image that rounds its fractional separation: when every
+ * perpendicular width of the cell exceeds 2 r_c, that image is the only one within r_c
+ * (else -1). out = {U, W_xx - W_yy, W_xy, pairs}. */
+int32_t orc_mix_forces(const orc_box* b0, const double h[3], const double* r, double* f,
+                       double* out) {
+    const int32_t n = b0->n;
+    const double wx = h[0] * h[2] / sqrt(h[1] * h[1] + h[2] * h[2]);
+    if (!(wx > 2.0 * b0->rc && h[2] > 2.0 * b0->rc && b0->lz > 2.0 * b0->rc)) return -1;
+    const double rc2 = b0->rc * b0->rc;
+    double u = 0.0, wn = 0.0, wxy = 0.0, npair = 0.0;
+    for (int32_t k = 0; k < 3 * n; ++k) f[k] = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t j = i + 1; j < n; ++j) {
+            /* fractional separation: s = H^-1 (r_i - r_j) */
+            double dx = r[i] - r[j];
+            double dy = r[n + i] - r[n + j];
+            double dz = r[2 * n + i] - r[2 * n + j];
+            double sy = dy / h[2];
+            double sx = (dx - h[1] * sy) / h[0];
+            double sz = dz / b0->lz;
+            sx -= rint(sx);
+            sy -= rint(sy);
+            sz -= rint(sz);
+            dx = h[0] * sx + h[1] * sy;
+            dy = h[2] * sy;
+            dz = b0->lz * sz;
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rc2) {
+                double fs, phi;
+                pair_eval(b0, r2, &fs, &phi);
+                f[i] += fs * dx;
+                f[n + i] += fs * dy;
+                f[2 * n + i] += fs * dz;
+                f[j] -= fs * dx;
+                f[n + j] -= fs * dy;
+                f[2 * n + j] -= fs * dz;
+                u += phi;
+                wn += dx * (fs * dx) - dy * (fs * dy);
+                wxy += dx * (fs * dy);
+                npair += 1.0;
+            }
+        }
+    }
+    out[0] = u;
+    out[1] = wn;
+    out[2] = wxy;
+    out[3] = npair;
+    return 0;
+}
+
+/* Mappings for mixed flow (reading): bit 1 exchanges the x and y axes of positions and
+ * momenta, then bit 0 reflects x (x -> L_x - x, p_x -> -p_x). P_xx - P_yy changes sign under
+ * the exchange and P_xy under the reflection, so over m = 0..3 the flux J(0) takes
+ * erate N1 (+, +, -, -) + srate P_xy (+, -, +, -) and averages to zero. */
+void orc_map_mix(const orc_box* b, int32_t m, const double* r, const double* p, double* r_out,
+                 double* p_out) {
+    const int32_t n = b->n;
+    orc_map_pef(b, m & 2, r, p, r_out, p_out);
+    if (m & 1) {
+        for (int32_t i = 0; i < n; ++i) {
+            r_out[i] = (r_out[i] == 0.0) ? 0.0 : b->lx - r_out[i];
+            p_out[i] = -p_out[i];
+        }
+    }
+}
+
+/* wrap r into the cell H through its fractional coordinates */
+static void mix_wrap(int32_t n, const double h[3], double lz, double* r) {
+    for (int32_t i = 0; i < n; ++i) {
+        double sy = r[n + i] / h[2];
+        double sx = (r[i] - h[1] * sy) / h[0];
+        double sz = r[2 * n + i] / lz;
+        sx -= floor(sx);
+        sy -= floor(sy);
+        sz -= floor(sz);
+        if (sx >= 1.0) sx = 0.0;
+        if (sy >= 1.0) sy = 0.0;
+        if (sz >= 1.0) sz = 0.0;
+        r[i] = h[0] * sx + h[1] * sy;
+        r[n + i] = h[2] * sy;
+        r[2 * n + i] = lz * sz;
+    }
+}
+
+/* p -> exp(-A tau) p: p_x e^{-erate tau} - srate tau sinhc(erate tau) p_y, p_y e^{erate tau} */
+static void mix_flow(int32_t n, double* p, double er, double sr, double tau) {
+    const double a = exp(-er * tau), d = exp(er * tau), c = -sr * tau * sinhc(er * tau);
+    for (int32_t i = 0; i < n; ++i) {
+        const double px = p[i], py = p[n + i];
+        p[i] = a * px + c * py;
+        p[n + i] = d * py;
+    }
+}
+
+/* One mixed-flow trajectory, steps of h = dt from time t0 = *t (advanced by the run).
+ * Isokinetic: E(h/2) K(h/2) D(h) [new cell, wrap, F] K(h/2) E(h/2), rescale to K0, with
+ *   E: p -> exp(-A tau) p scaled back to its p.p;
+ *   K: orc_iso_kick;
+ *   D: r -> exp(A h) (r + N p), N = int_0^h exp(-A u) du
+ *      = [[h phi(erate h), -srate (h^2/2) sinhc(erate h/2)^2], [0, h phi(-erate h)]]
+ *      (phi(u) = (1 - e^-u)/u), the exact streaming with p fixed.
+ * gik = 0: the adiabatic step. thermo = 1 (gik ignored): Nose-Hoover, Z T E K D K E T Z.
+ * vj_out[s] = V J after step s. */
+int32_t orc_mix_run(const orc_box* b0, double er, double sr, double dt, int32_t gik,
+                    int32_t thermo, double temperature, double q, double nf, double* t,
+                    double* r, double* p, double* zeta, int64_t nsteps, double* vj_out,
+                    double* ke_out, double* pe_out) {
+    const int32_t n = b0->n;
+    double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
+    if (!f) return -2;
+    const double h = dt, tau = 0.5 * dt;
+    const double t0 = *t;
+    const double rn = sqrt(er * er + sr * sr);
+    double hb[3];
+    mix_box(b0, er, sr, t0, hb);
+    double out[4];
+    if (orc_mix_forces(b0, hb, r, f, out) != 0) {
+        free(f);
+        return -1;
+    }
+    double k0 = kinetic(n, p);
+    double zt = zeta ? *zeta : 0.0;
+    /* exp(A h) and N */
+    const double ea = exp(er * h), ed = exp(-er * h), eb = sr * h * sinhc(er * h);
+    const double nxx = h * pef_phi(er * h), nyy = h * pef_phi(-er * h);
+    const double hs = sinhc(0.5 * er * h);
+    const double nxy = -sr * 0.5 * h * h * hs * hs;
+#define MIX_VJ(KS)                                                                    \
+    do {                                                                              \
+        double s1 = 0.0, s2 = 0.0;                                                    \
+        for (int32_t i = 0; i < n; ++i) {                                             \
+            s1 += p[i] * p[i] - p[n + i] * p[n + i];                                  \
+            s2 += p[i] * p[n + i];                                                    \
+        }                                                                             \
+        if (vj_out) vj_out[KS] = rn > 0.0 ? (er * (s1 + out[1]) + sr * (s2 + out[2])) / rn : 0.0; \
+    } while (0)
+    MIX_VJ(0);
+    if (ke_out) ke_out[0] = kinetic(n, p);
+    if (pe_out) pe_out[0] = out[0];
+    for (int64_t s = 1; s <= nsteps; ++s) {
+        if (thermo) {
+            zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
+            const double sc = exp(-zt * tau);
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] *= sc;
+        }
+        {
+            const double pp0 = 2.0 * kinetic(n, p);
+            mix_flow(n, p, er, sr, tau);
+            if (gik && !thermo) {
+                const double g = sqrt(pp0 / (2.0 * kinetic(n, p)));
+                for (int32_t c = 0; c < 3 * n; ++c) p[c] *= g;
+            }
+        }
+        if (gik && !thermo)
+            orc_iso_kick(n, p, f, tau);
+        else
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] += tau * f[c];
+        for (int32_t i = 0; i < n; ++i) {
+            const double x = r[i] + nxx * p[i] + nxy * p[n + i];
+            const double y = r[n + i] + nyy * p[n + i];
+            r[i] = ea * x + eb * y;
+            r[n + i] = ed * y;
+            r[2 * n + i] += h * p[2 * n + i];
+        }
+        mix_box(b0, er, sr, t0 + (double)s * h, hb);
+        mix_wrap(n, hb, b0->lz, r);
+        if (orc_mix_forces(b0, hb, r, f, out) != 0) {
+            free(f);
+            return -1;
+        }
+        if (gik && !thermo)
+            orc_iso_kick(n, p, f, tau);
+        else
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] += tau * f[c];
+        {
+            const double pp0 = 2.0 * kinetic(n, p);
+            mix_flow(n, p, er, sr, tau);
+            if (gik && !thermo) {
+                const double g = sqrt(pp0 / (2.0 * kinetic(n, p)));
+                for (int32_t c = 0; c < 3 * n; ++c) p[c] *= g;
+            }
+        }
+        if (thermo) {
+            const double sc = exp(-zt * tau);
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] *= sc;
+            zt += tau * (2.0 * kinetic(n, p) - nf * temperature) / q;
+        } else if (gik) {
+            const double lam = sqrt(k0 / kinetic(n, p));
+            for (int32_t c = 0; c < 3 * n; ++c) p[c] *= lam;
+        }
+        MIX_VJ(s);
+        if (ke_out) ke_out[s] = kinetic(n, p);
+        if (pe_out) pe_out[s] = out[0];
+    }
+#undef MIX_VJ
+    if (zeta) *zeta = zt;
+    *t = t0 + (double)nsteps * h;
+    free(f);
+    return 0;
+}
+
+typedef struct {
+    const orc_box* b;
+    double dt;
+    const double *states_r, *states_p, *states_zeta;
+    int32_t n_daughters;
+    const int32_t *state_of, *map_of;
+    const double *er_of, *sr_of;
+    int64_t nsteps;
+    double *vj_out, *r_out, *p_out;
+    double temperature, q, nf;
+    int32_t tid, nthreads, status;
+} mix_job;
+
+static void* mix_worker(void* arg) {
+    mix_job* jb = (mix_job*)arg;
+    const size_t sz = 3 * (size_t)jb->b->n;
+    double* r = (double*)malloc(sizeof(double) * sz);
+    double* p = (double*)malloc(sizeof(double) * sz);
+    jb->status = 0;
+    for (int32_t d = jb->tid; d < jb->n_daughters; d += jb->nthreads) {
+        const int32_t s = jb->state_of[d];
+        orc_map_mix(jb->b, jb->map_of[d], jb->states_r + (size_t)s * sz,
+                    jb->states_p + (size_t)s * sz, r, p);
+        double t = 0.0;
+        /* none of the mixed-flow mappings reverses time: zeta is carried unchanged */
+        double zt = jb->states_zeta ? jb->states_zeta[s] : 0.0;
+        int32_t rc = orc_mix_run(jb->b, jb->er_of[d], jb->sr_of[d], jb->dt, 1,
+                                 jb->states_zeta ? 1 : 0, jb->temperature, jb->q, jb->nf, &t, r,
+                                 p, &zt, jb->nsteps,
+                                 jb->vj_out + (size_t)d * (size_t)(jb->nsteps + 1), 0, 0);
+        if (rc) jb->status = rc;
+        if (jb->r_out) memcpy(jb->r_out + (size_t)d * sz, r, sizeof(double) * sz);
+        if (jb->p_out) memcpy(jb->p_out + (size_t)d * sz, p, sizeof(double) * sz);
+    }
+    free(r);
+    free(p);
+    return 0;
+}
+
+int32_t orc_run_daughters_mix(const orc_box* b, double dt, const double* states_r,
+                              const double* states_p, const double* states_zeta,
+                              double temperature, double q, double nf, int32_t n_daughters,
+                              const int32_t* state_of, const int32_t* map_of,
+                              const double* er_of, const double* sr_of, int64_t nsteps,
+                              int32_t nthreads, double* vj_out, double* r_out, double* p_out) {
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > n_daughters) nthreads = n_daughters > 0 ? n_daughters : 1;
+    mix_job* jobs = (mix_job*)calloc((size_t)nthreads, sizeof(mix_job));
+    pthread_t* th = (pthread_t*)calloc((size_t)nthreads, sizeof(pthread_t));
+    for (int32_t t = 0; t < nthreads; ++t) {
+        mix_job j = {b,     dt,       states_r, states_p,    states_zeta, n_daughters,
+                     state_of, map_of, er_of,   sr_of,       nsteps,      vj_out,
+                     r_out, p_out,    temperature, q,       nf,          t,
+                     nthreads, 0};
+        jobs[t] = j;
+        pthread_create(&th[t], 0, mix_worker, &jobs[t]);
+    }
+    int32_t status = 0;
+    for (int32_t t = 0; t < nthreads; ++t) {
+        pthread_join(th[t], 0);
+        if (jobs[t].status) status = jobs[t].status;
+    }
+    free(jobs);
+    free(th);
+    return status ? status : nthreads;
+}

@@ -211,6 +211,33 @@ int32_t orc_run_daughters_pef(const orc_box* b, double dt, const double* states_
                               const double* rate_of, int64_t nsteps, int32_t nthreads,
                               double* vn1_out, double* r_out, double* p_out);
 
+/* Mixed flow (Introduction: TTCF extends to mixed flows): SLLOD with u_x = erate x + srate y,
+ * u_y = -erate y in the triclinic cell carried by the flow, H(t) = exp(A t) diag(L0):
+ * H_xx = L_x0 e^{erate t}, H_xy = L_y0 srate t sinhc(erate t), H_yy = L_y0 e^{-erate t}.
+ * orc_mix_forces: h = {H_xx, H_xy, H_yy}; every pair through the image that rounds its
+ * fractional separation (the only one within r_c while every perpendicular width exceeds
+ * 2 r_c, else -1); out = {U, W_xx - W_yy, W_xy, pairs}.
+ * orc_map_mix: bit 1 exchanges the x and y axes, then bit 0 reflects x.
+ * orc_mix_run: one trajectory from time *t (advanced); gik = 0 adiabatic; thermo = 1
+ * Nose-Hoover from *zeta (advanced); vj_out = V J, J = (erate (P_xx - P_yy) + srate P_xy) /
+ * sqrt(erate^2 + srate^2); ke_out, pe_out: nsteps + 1 values each (NULL to skip).
+ * orc_run_daughters_mix: isokinetic daughters, or Nose-Hoover when states_zeta is given
+ * (no mapping reverses time, so zeta is carried unchanged). */
+int32_t orc_mix_forces(const orc_box* b0, const double h[3], const double* r, double* f,
+                       double* out);
+void orc_map_mix(const orc_box* b, int32_t m, const double* r, const double* p, double* r_out,
+                 double* p_out);
+int32_t orc_mix_run(const orc_box* b0, double er, double sr, double dt, int32_t gik,
+                    int32_t thermo, double temperature, double q, double nf, double* t,
+                    double* r, double* p, double* zeta, int64_t nsteps, double* vj_out,
+                    double* ke_out, double* pe_out);
+int32_t orc_run_daughters_mix(const orc_box* b, double dt, const double* states_r,
+                              const double* states_p, const double* states_zeta,
+                              double temperature, double q, double nf, int32_t n_daughters,
+                              const int32_t* state_of, const int32_t* map_of,
+                              const double* er_of, const double* sr_of, int64_t nsteps,
+                              int32_t nthreads, double* vj_out, double* r_out, double* p_out);
+
 /* Batch of independent GIK-SLLOD daughters on a pool of nthreads threads.
  * Daughter d starts from start state state_of[d] under mapping map_of[d] with shear rate
  * gamma_of[d] and runs nsteps steps; its series V*P_xy(t_k), k = 0..nsteps, goes to

@@ -71,7 +71,8 @@ enum {
     TTCF_OBS_ENERGY = 5,
     TTCF_OBS_SLAB_PX = 6,
     TTCF_OBS_JX = 7,     /* colour-field daughters (ttcf_spawn_colour): the colour current J_x */
-    TTCF_OBS_PEF_N1 = 8  /* planar-elongation daughters (ttcf_spawn_elongational): P_xx - P_yy */
+    TTCF_OBS_PEF_N1 = 8, /* planar-elongation daughters (ttcf_spawn_elongational): P_xx - P_yy */
+    TTCF_OBS_MIX_J = 9   /* mixed-flow daughters (ttcf_spawn_mixed): the flux J */
 };
 enum { TTCF_BULK_SLABS = 8 };
 
@@ -173,6 +174,28 @@ int32_t ttcf_spawn_colour(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
 int32_t ttcf_spawn_elongational(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
                                 int64_t steps_between, uint32_t mapping_mask, const double* rate,
                                 int32_t n_rate, int32_t n_steps, int64_t* out_first);
+
+/* Introduction: TTCF extends to mixed flows. Mixed flow (the paper prints no equations for
+ * it): SLLOD of Eq. (system1) with u_x = erate x + srate y, u_y = -erate y, i.e.
+ * dr/dt = p + A r, dp/dt = F - A p - alpha p with A = [[erate, srate, 0], [0, -erate, 0],
+ * [0, 0, 0]], with the mother system's daughter thermostat, in the triclinic cell the flow
+ * carries, H(t) = exp(A t) diag(L): H_xx = L e^{erate t}, H_xy = L srate t sinh(erate t) /
+ * (erate t), H_yy = L e^{-erate t} (volume conserved; no cell flips, as daughters are short).
+ * B(t) = J = (erate (P_xx - P_yy) + srate P_xy) / |rate|, |rate| = sqrt(erate^2 + srate^2),
+ * the flux conjugate to the flow (grad u : P / |rate|); Omega(0) = -(V/T) |rate| J(0).
+ * Mappings (bit m of mapping_mask): bit 1 exchanges the x and y axes (positions and
+ * momenta), then bit 0 reflects x (x -> L - x, p_x -> -p_x); P_xx - P_yy takes the signs
+ * (+, +, -, -) and P_xy (+, -, +, -), so <Omega(0)> vanishes over the four. None reverses
+ * time, so Nose-Hoover daughters carry zeta unchanged.
+ * erate, srate: n_rate == 1 or n_states values each (one pair per start state). The series
+ * holds V J(t_k); ttcf_response(ctx, TTCF_OBS_MIX_J, |rate|, ...) returns <J>(t) (for a
+ * Newtonian fluid -eta (4 erate^2 + srate^2) / |rate|). Final states are in the coordinates
+ * of the carried cell. Forces are FP64. TTCF_EINVAL for N > 2048, L_x != L_y, both rates
+ * zero, the extra observables switched on, or rates and a length that would narrow a
+ * perpendicular width of the cell below 3 r_c before the daughter ends. */
+int32_t ttcf_spawn_mixed(ttcf_ctx* ctx, int32_t mother, int32_t n_states, int64_t steps_between,
+                         uint32_t mapping_mask, const double* erate, const double* srate,
+                         int32_t n_rate, int32_t n_steps, int64_t* out_first);
 
 /* Alg. LAMMPS SCRIPT, "run N_d timestep": advances every live daughter by up to n_steps
  * steps (never past its own N_d) in one persistent kernel launch per kernel form, recording

@@ -787,7 +787,8 @@ int32_t ttcf_sample_states(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_
 namespace {
 int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
                    uint32_t mapping_mask, const double* gamma_dot, int32_t n_gamma, int32_t n_steps,
-                   bool prefix_ok, int64_t* out_first, int32_t field = kFieldShear);
+                   bool prefix_ok, int64_t* out_first, int32_t field = kFieldShear,
+                   const double* erate = nullptr, const double* srate = nullptr);
 }
 
 int32_t ttcf_spawn_daughters(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
@@ -804,6 +805,23 @@ int32_t ttcf_spawn_colour(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t
                       false, out_first, kFieldColour);
 }
 
+int32_t ttcf_spawn_mixed(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
+                         uint32_t mapping_mask, const double* erate, const double* srate,
+                         int32_t n_rate, int32_t n_steps, int64_t* out_first) {
+    if (!c) return TTCF_EINVAL;
+    if (!erate || !srate || n_rate < 1 || n_rate > (1 << 24))
+        return fail(c, TTCF_EINVAL, "bad mixed-flow rates");
+    // the field strength |rate| sets Omega's coefficient and the response filter
+    std::vector<double> rn(n_rate);
+    for (int32_t g = 0; g < n_rate; ++g) {
+        rn[g] = std::sqrt(erate[g] * erate[g] + srate[g] * srate[g]);
+        if (!std::isfinite(rn[g]) || !(rn[g] > 0.0))
+            return fail(c, TTCF_EINVAL, "mixed-flow rates must be finite and not both zero");
+    }
+    return spawn_impl(c, mother, n_states, steps_between, mapping_mask, rn.data(), n_rate,
+                      n_steps, false, out_first, kFieldMixed, erate, srate);
+}
+
 int32_t ttcf_spawn_elongational(ttcf_ctx* c, int32_t mother, int32_t n_states,
                                 int64_t steps_between, uint32_t mapping_mask, const double* rate,
                                 int32_t n_rate, int32_t n_steps, int64_t* out_first) {
@@ -815,7 +833,8 @@ namespace {
 // prefix_ok: with steps_between == 0, the first n_states stored states may be used
 int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_between,
                    uint32_t mapping_mask, const double* gamma_dot, int32_t n_gamma, int32_t n_steps,
-                   bool prefix_ok, int64_t* out_first, int32_t field) {
+                   bool prefix_ok, int64_t* out_first, int32_t field, const double* erate,
+                   const double* srate) {
     if (!c) return TTCF_EINVAL;
     if (mother < 0 || mother >= (int32_t)c->mothers.size() || n_states <= 0 || steps_between < 0 ||
         (mapping_mask & 0xFu) == 0 || (mapping_mask & ~0xFu) != 0 || !gamma_dot ||
@@ -836,6 +855,30 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
             return fail(c, TTCF_EINVAL, "colour-field daughters run in the list form (FP32 forces)");
         if (m.dev.n % 2 != 0)
             return fail(c, TTCF_EINVAL, "the colour field needs an even number of atoms");
+    }
+    if (field == kFieldMixed) {
+        if (c->record_obs)
+            return fail(c, TTCF_EINVAL, "mixed-flow daughters record their flux only: switch "
+                                        "the extra observables off");
+        if (m.dev.n > kPefMaxAtoms)
+            return fail(c, TTCF_EINVAL, "mixed-flow daughters hold at most 2048 atoms");
+        if (m.dev.box[0] != m.dev.box[1])
+            return fail(c, TTCF_EINVAL, "the mixed-flow mappings exchange x and y: the box must "
+                                        "have L_x = L_y");
+        // the carried cell keeps every perpendicular width at 3 r_c or more, step by step
+        for (int32_t g = 0; g < n_gamma; ++g) {
+            const double er = erate[g], sr = srate[g], l = m.dev.box[0];
+            for (int32_t k = 0; k <= n_steps; ++k) {
+                const double t = (double)k * m.dev.dt, x = er * t;
+                const double hxx = l * std::exp(x), hyy = l * std::exp(-x);
+                const double hxy = l * sr * t * (x == 0.0 ? 1.0 : std::sinh(x) / x);
+                const double wx = hxx * hyy / std::sqrt(hxy * hxy + hyy * hyy);
+                if (wx < 3.0 * m.dev.rc || hyy < 3.0 * m.dev.rc)
+                    return fail(c, TTCF_EINVAL, "the mixed flow would narrow the cell below "
+                                                "3 r_c before the daughter ends (lower the rates "
+                                                "or the length, or use a larger system)");
+            }
+        }
     }
     if (field == kFieldElong) {
         if (c->record_obs)
@@ -917,6 +960,10 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
             ds.xseries = b.xseries ? b.xseries + (size_t)(n_steps + 1) * kObsCols * d : nullptr;
             ds.sys = m.dev;
             ds.gamma_dot = field == kFieldColour ? 0.0 : g;  // the elongation rate for kFieldElong
+            if (field == kFieldMixed) {
+                ds.erate = erate[n_gamma == 1 ? 0 : s];
+                ds.srate = srate[n_gamma == 1 ? 0 : s];
+            }
             ds.field = field;
             ds.fe = field == kFieldColour ? g : 0.0;
             ds.k0 = 0.0;
@@ -929,7 +976,8 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
             ds.block = m.threads;
             if (nh) {
                 ds.thermo = 1;
-                ds.zeta = (maps[q] & 1) ? -hz[s] : hz[s];  // mappings 1 and 3 reverse time
+                // mappings 1 and 3 reverse time, except for mixed flow (they reflect x there)
+                ds.zeta = ((maps[q] & 1) && field != kFieldMixed) ? -hz[s] : hz[s];
                 ds.nh_q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
                 ds.nh_target = nf * m.sys.temperature;
             }
@@ -940,9 +988,10 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
     HIPCHECK(c, hipMemcpyAsync(b.scratch, host.data(), scratch_bytes, hipMemcpyHostToDevice, c->stream));
     {
         const int32_t* d_state_of = (const int32_t*)((char*)b.scratch + sizeof(double*) * nd);
-        if (field == kFieldElong)
+        if (field == kFieldElong || field == kFieldMixed)
             HIPCHECK(c, launch_spawn_pef(m.states, m.dev.n, d_state_of, d_state_of + nd,
-                                         (double* const*)b.scratch, nd, c->stream));
+                                         (double* const*)b.scratch, nd,
+                                         field == kFieldMixed ? 1 : 0, m.dev.box[0], c->stream));
         else
             HIPCHECK(c, launch_spawn(m.states, m.dev.n, n_states, d_state_of, d_state_of + nd,
                                      (double* const*)b.scratch, nd, m.dev.box[0], c->stream));
@@ -1096,14 +1145,15 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     // is one persistent launch, largest systems first. groups[2 form + thermo], form 0 lists,
     // 1 cells, 2 lists in global scratch
     std::vector<int32_t> groups[6];
-    std::vector<int32_t> pef[2];  // planar-elongation daughters by thermostat: own kernel, FP64
+    // planar-elongation (0, 1) and mixed-flow (2, 3) daughters by thermostat: own kernels, FP64
+    std::vector<int32_t> pef[4];
     std::vector<StepShape> eff(c->descs.size());
     int precision = -1;
     for (size_t i = 0; i < c->descs.size(); ++i) {
         DaughterDesc& d = c->descs[i];
         if (d.health != 0 || d.done >= d.n_steps || (only && !(*only)[i])) continue;
-        if (d.field == kFieldElong) {
-            pef[d.thermo ? 1 : 0].push_back((int32_t)i);
+        if (d.field == kFieldElong || d.field == kFieldMixed) {
+            pef[(d.field == kFieldMixed ? 2 : 0) + (d.thermo ? 1 : 0)].push_back((int32_t)i);
             continue;
         }
         const Mother& m = c->mothers[c->batches[c->live[i].batch].mother];
@@ -1128,7 +1178,9 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     const bool any_nl = !groups[0].empty() || !groups[1].empty() || !groups[4].empty() ||
                         !groups[5].empty();
     const bool any_cell = !groups[2].empty() || !groups[3].empty();
-    if (!any_nl && !any_cell && pef[0].empty() && pef[1].empty()) return TTCF_OK;
+    if (!any_nl && !any_cell && pef[0].empty() && pef[1].empty() && pef[2].empty() &&
+        pef[3].empty())
+        return TTCF_OK;
     if (any_nl) {
         rc = push_descs(c);  // the list grids were just written into the descriptors
         if (rc != TTCF_OK) return rc;
@@ -1190,7 +1242,7 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
             c->pending_events.emplace_back(e0, e1);
         }
     }
-    for (int th = 0; th < 2; ++th) {
+    for (int th = 0; th < 4; ++th) {
         if (pef[th].empty()) continue;
         PefLaunch P{};
         P.descs = c->d_descs;
@@ -1198,7 +1250,8 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         offset += pef[th].size();
         P.n_jobs = (int32_t)pef[th].size();
         P.max_steps = n_steps;
-        P.thermo = th;
+        P.thermo = th & 1;
+        P.mix = th >> 1;
         for (int32_t i : pef[th]) {
             const SysDev& sd = c->descs[i].sys;
             P.nmax = std::max(P.nmax, sd.n);
@@ -1748,6 +1801,7 @@ bool obs_columns(int32_t observable, int* col0, int* ncol) {
         case TTCF_OBS_PXY: *col0 = -1; *ncol = 1; return true;
         case TTCF_OBS_JX: *col0 = -1; *ncol = 1; return true;  // colour rows hold V J_x there
         case TTCF_OBS_PEF_N1: *col0 = -1; *ncol = 1; return true;  // elongation: V (P_xx - P_yy)
+        case TTCF_OBS_MIX_J: *col0 = -1; *ncol = 1; return true;   // mixed flow: V J
         case TTCF_OBS_N1: *col0 = 0; *ncol = 1; return true;
         case TTCF_OBS_N2: *col0 = 1; *ncol = 1; return true;
         case TTCF_OBS_ENERGY: *col0 = 2; *ncol = 1; return true;
@@ -1758,8 +1812,12 @@ bool obs_columns(int32_t observable, int* col0, int* ncol) {
 
 // the field whose rows carry an observable
 int32_t field_of_observable(int32_t observable) {
-    return observable == TTCF_OBS_JX ? kFieldColour
-                                     : (observable == TTCF_OBS_PEF_N1 ? kFieldElong : kFieldShear);
+    switch (observable) {
+        case TTCF_OBS_JX: return kFieldColour;
+        case TTCF_OBS_PEF_N1: return kFieldElong;
+        case TTCF_OBS_MIX_J: return kFieldMixed;
+    }
+    return kFieldShear;
 }
 
 // accumulator arrays and row stride of column `col` (-1: P_xy)

@@ -204,13 +204,9 @@ __device__ __forceinline__ void pef_atom_force(const PefShared& S, int i, int nc
     }
 }
 
-// Canonical cell list of the fractional positions in LDS (every thread calls it; it begins
-// and ends with a barrier), then the forces on the thread's atoms and its share of the pair
-// virial W_xx - W_yy (each pair is seen from both sides, so each side adds half).
-__device__ void pef_forces(const PefShared& S, int n, int ncx, int ncy, int ncz, double lx,
-                           double ly, double lz, double rc2, double ca,
-                           double (&fx)[kPefApt],
-                           double (&fy)[kPefApt], double (&fz)[kPefApt], double& w) {
+// Canonical cell list of the fractional positions in LDS: every thread calls it; it begins
+// and ends with a barrier.
+__device__ void pef_build_cells(const PefShared& S, int n, int ncx, int ncy, int ncz) {
     const int T = blockDim.x, t = threadIdx.x;
     const int lane = t & 63, wave = t >> 6, nw = T >> 6;
     const int C = ncx * ncy * ncz;
@@ -281,6 +277,15 @@ __device__ void pef_forces(const PefShared& S, int n, int ncx, int ncy, int ncz,
         }
     }
     __syncthreads();
+}
+
+// The cell list, then the forces on the thread's atoms and its share of the pair virial
+// W_xx - W_yy (each pair is seen from both sides, so each side adds half).
+__device__ void pef_forces(const PefShared& S, int n, int ncx, int ncy, int ncz, double lx,
+                           double ly, double lz, double rc2, double ca, double (&fx)[kPefApt],
+                           double (&fy)[kPefApt], double (&fz)[kPefApt], double& w) {
+    const int T = blockDim.x, t = threadIdx.x;
+    pef_build_cells(S, n, ncx, ncy, ncz);
     w = 0.0;
     for (int j = 0; j < kPefApt; ++j) {
         const int i = t + j * T;
@@ -562,23 +567,409 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
     }
 }
 
-// Start states of PEF daughters under their mappings: bit 0 of map reverses the momenta,
-// bit 1 exchanges the x and y axes of positions and momenta (the box is cubic).
+// ---- mixed flow: shear and planar elongation together ---------------------------------
+// u_x = erate x + srate y, u_y = -erate y: dr/dt = p + A r, dp/dt = F - A p - alpha p with
+// A = [[erate, srate, 0], [0, -erate, 0], [0, 0, 0]] (the Introduction names mixed flows
+// among those TTCF extends to). The cell is the one the flow carries, H(t) = exp(A t)
+// diag(L): H_xx = L e^{erate t}, H_xy = L srate t sinhc(erate t), H_yy = L e^{-erate t}.
+// Positions are fractions s = H^-1 r; the streaming with p fixed gives exactly
+// s += H(t)^-1 N p, N = int_0^h exp(-A u) du; the flow part E is p -> exp(-A tau) p. The
+// cell grid uses the perpendicular widths of the tilted cell (n_x from L^2 / |b|, b its
+// second edge), so the 27-cell stencil with image shifts finds every pair within r_c.
+// The recorded flux is V J, J = (erate (P_xx - P_yy) + srate P_xy) / |rate|, and
+// Omega(0) = -(V/T) |rate| J(0).
+
+__device__ __forceinline__ double mix_sinhc(double x) { return x == 0.0 ? 1.0 : sinh(x) / x; }
+
+struct MixCell {
+    double hxx, hxy, hyy;
+    int ncx, ncy;
+};
+
+__device__ __forceinline__ MixCell mix_cell(double l0x, double l0y, double er, double sr,
+                                            double t, double rc) {
+    MixCell c;
+    const double x = er * t;
+    c.hxx = l0x * exp(x);
+    c.hxy = l0y * sr * t * mix_sinhc(x);
+    c.hyy = l0y * exp(-x);
+    const double wx = c.hxx * c.hyy / sqrt(c.hxy * c.hxy + c.hyy * c.hyy);
+    c.ncx = (int)floor(wx / rc);
+    c.ncy = (int)floor(c.hyy / rc);
+    return c;
+}
+
+// Force on atom i in the tilted cell, and its halves of W_xx - W_yy and W_xy.
+__device__ __forceinline__ void mix_atom_force(const PefShared& S, int i, int ncx, int ncy,
+                                               int ncz, const MixCell& H, double lz,
+                                               double rc2, double ca, double& fx, double& fy,
+                                               double& fz, double& wn, double& wxy) {
+    const double six = S.sx[i], siy = S.sy[i], siz = S.sz[i];
+    const int cx = pef_cell(six, ncx), cy = pef_cell(siy, ncy), cz = pef_cell(siz, ncz);
+#pragma unroll 1
+    for (int dz = -1; dz <= 1; ++dz) {
+        int zz = cz + dz;
+        double az = siz;
+        if (zz < 0) {
+            zz += ncz;
+            az += 1.0;
+        } else if (zz >= ncz) {
+            zz -= ncz;
+            az -= 1.0;
+        }
+#pragma unroll 1
+        for (int dy = -1; dy <= 1; ++dy) {
+            int yy = cy + dy;
+            double ay = siy;
+            if (yy < 0) {
+                yy += ncy;
+                ay += 1.0;
+            } else if (yy >= ncy) {
+                yy -= ncy;
+                ay -= 1.0;
+            }
+            for (int dx = -1; dx <= 1; ++dx) {
+                int xx = cx + dx;
+                double ax = six;
+                if (xx < 0) {
+                    xx += ncx;
+                    ax += 1.0;
+                } else if (xx >= ncx) {
+                    xx -= ncx;
+                    ax -= 1.0;
+                }
+                const int c = xx + ncx * (yy + ncy * zz);
+                const int e = S.start[c + 1];
+                for (int q = S.start[c]; q < e; ++q) {
+                    const int m = S.sid[q];
+                    if (m == i) continue;
+                    const double fsx = ax - S.sx[m], fsy = ay - S.sy[m];
+                    const double ddx = fsx * H.hxx + fsy * H.hxy;
+                    const double ddy = fsy * H.hyy;
+                    const double ddz = (az - S.sz[m]) * lz;
+                    const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                    if (r2 < rc2) {
+                        const double inv = pef_recip(r2);
+                        const double s3 = inv * inv * inv;
+                        const double fs = (48.0 * s3 * s3 - 24.0 * ca * s3) * inv;
+                        fx += fs * ddx;
+                        fy += fs * ddy;
+                        fz += fs * ddz;
+                        wn += 0.5 * (fs * (ddx * ddx - ddy * ddy));
+                        wxy += 0.5 * (fs * (ddx * ddy));
+                    }
+                }
+            }
+        }
+    }
+}
+
+__device__ void mix_forces(const PefShared& S, int n, int ncz, const MixCell& H, double lz,
+                           double rc2, double ca, double (&fx)[kPefApt], double (&fy)[kPefApt],
+                           double (&fz)[kPefApt], double& wn, double& wxy) {
+    const int T = blockDim.x, t = threadIdx.x;
+    pef_build_cells(S, n, H.ncx, H.ncy, ncz);
+    wn = 0.0;
+    wxy = 0.0;
+    for (int j = 0; j < kPefApt; ++j) {
+        const int i = t + j * T;
+        double ax = 0.0, ay = 0.0, az = 0.0;
+        if (i < n) mix_atom_force(S, i, H.ncx, H.ncy, ncz, H, lz, rc2, ca, ax, ay, az, wn, wxy);
+        fx[j] = ax;
+        fy[j] = ay;
+        fz[j] = az;
+    }
+}
+
+// NH: Nose-Hoover daughters (Z T E K D K E T Z over half steps), else isokinetic
+// (E K D K E with E and K constrained, then a rescale to K0).
+template <bool NH>
+__global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
+    extern __shared__ __align__(16) char smem[];
+    const PefPlan plan = pef_plan(L.nmax, L.cmax);
+    PefShared S;
+    S.sx = (double*)(smem + plan.sx);
+    S.sy = (double*)(smem + plan.sy);
+    S.sz = (double*)(smem + plan.sz);
+    S.red = (double*)(smem + plan.red);
+    S.start = (int32_t*)(smem + plan.start);
+    S.cnt = (int32_t*)(smem + plan.cnt);
+    S.ws = (int32_t*)(smem + plan.ws);
+    S.sid = (uint16_t*)(smem + plan.sid);
+
+    DaughterDesc* dp = L.descs + L.order[blockIdx.x];
+    const int T = blockDim.x, t = threadIdx.x;
+    const int n = dp->sys.n;
+    const int32_t done0 = dp->done;
+    if (dp->health != 0 || done0 >= dp->n_steps) return;  // uniform over the workgroup
+    const int steps = min(L.max_steps, dp->n_steps - done0);
+    const double er = dp->erate, sr = dp->srate, rn = dp->gamma_dot, h = dp->sys.dt;
+    const double l0x = dp->sys.box[0], l0y = dp->sys.box[1], lz = dp->sys.box[2];
+    const double rc = dp->sys.rc, rc2 = dp->sys.rc2, ca = dp->sys.c_attr;
+    double* st = dp->state;
+    double* series = dp->series;
+    int64_t k = dp->k;
+    int health = 0;
+    if (n > T * kPefApt || n > L.nmax || !(rn > 0.0)) health = kHealthNonFinite;
+    MixCell H = mix_cell(l0x, l0y, er, sr, (double)k * h, rc);
+    const int ncz = (int)floor(lz / rc);
+    if (H.ncx < 3 || H.ncy < 3 || ncz < 3 || H.ncx * H.ncy * ncz > L.cmax)
+        health = kHealthNonFinite;
+    if (health) {
+        if (t == 0) dp->health = health;
+        return;
+    }
+    const double tau = 0.5 * h;
+    // exp(-A tau) and N = int_0^h exp(-A u) du
+    const double fa = exp(-er * tau), fd = exp(er * tau), fc = -sr * tau * mix_sinhc(er * tau);
+    const double nxx = h * pef_phi(er * h), nyy = h * pef_phi(-er * h);
+    const double hs = mix_sinhc(0.5 * er * h);
+    const double nxy = -sr * 0.5 * h * h * hs * hs;
+    double zeta = dp->zeta;
+    const double nh_q = dp->nh_q, nh_target = dp->nh_target;
+
+    double px[kPefApt], py[kPefApt], pz[kPefApt];
+    double fx[kPefApt], fy[kPefApt], fz[kPefApt];
+#pragma unroll
+    for (int j = 0; j < kPefApt; ++j) {
+        const int a = t + j * T;
+        px[j] = py[j] = pz[j] = 0.0;
+        if (a < n) {
+            const double sy = st[n + a] / H.hyy;
+            S.sx[a] = pef_wrap((st[a] - H.hxy * sy) / H.hxx);
+            S.sy[a] = pef_wrap(sy);
+            S.sz[a] = pef_wrap(st[2 * n + a] / lz);
+            px[j] = st[3 * n + a];
+            py[j] = st[4 * n + a];
+            pz[j] = st[5 * n + a];
+        }
+    }
+    double wn, wxy;
+    mix_forces(S, n, ncz, H, lz, rc2, ca, fx, fy, fz, wn, wxy);
+    double k0 = dp->k0;
+    {
+        double v[5] = {0.0, 0.0, 0.0, wn, wxy};
+#pragma unroll
+        for (int j = 0; j < kPefApt; ++j) {
+            v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+            v[1] += px[j] * px[j] - py[j] * py[j];
+            v[2] += px[j] * py[j];
+        }
+        pef_sum<5>(v, S.red);
+        if (done0 == 0) {
+            k0 = 0.5 * v[0];
+            if (t == 0) series[0] = (er * (v[1] + v[3]) + sr * (v[2] + v[4])) / rn;
+        }
+    }
+    int it = 0;
+    for (; it < steps; ++it) {
+        if constexpr (NH) {
+            // Z(h/2) T(h/2) E(h/2) K(h/2)
+            double v[1] = {0.0};
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+            pef_sum<1>(v, S.red);
+            zeta += tau * (v[0] - nh_target) / nh_q;
+            const double sc = exp(-zeta * tau);
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                const double qx = px[j] * sc, qy = py[j] * sc;
+                px[j] = (fa * qx + fc * qy) + tau * fx[j];
+                py[j] = fd * qy + tau * fy[j];
+                pz[j] = pz[j] * sc + tau * fz[j];
+            }
+        } else {
+            // E(h/2), constrained
+            {
+                double v[2] = {0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    const double qx = fa * px[j] + fc * py[j];
+                    py[j] = fd * py[j];
+                    px[j] = qx;
+                    v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                }
+                pef_sum<2>(v, S.red);
+                const double g = sqrt(v[0] / v[1]);
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] *= g;
+                    py[j] *= g;
+                    pz[j] *= g;
+                }
+            }
+            // K(h/2)
+            {
+                double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    v[1] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+                    v[2] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+                }
+                pef_sum<3>(v, S.red);
+                double s1, sd;
+                pef_kick_coeffs(v[1] / v[0], v[2] / v[0], tau, s1, sd);
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] = (px[j] + fx[j] * s1) / sd;
+                    py[j] = (py[j] + fy[j] * s1) / sd;
+                    pz[j] = (pz[j] + fz[j] * s1) / sd;
+                }
+            }
+        }
+        // D(h): s += H(t)^-1 N p (every thread has passed the barriers of the sums above, so
+        // no thread still reads S.sx; each thread moves only its own atoms), then the cell
+        // of step k + 1
+        {
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                const int a = t + j * T;
+                if (a < n) {
+                    const double uy = nyy * py[j];
+                    const double dsy = uy / H.hyy;
+                    const double dsx = ((nxx * px[j] + nxy * py[j]) - H.hxy * dsy) / H.hxx;
+                    S.sx[a] = pef_wrap(S.sx[a] + dsx);
+                    S.sy[a] = pef_wrap(S.sy[a] + dsy);
+                    S.sz[a] = pef_wrap(S.sz[a] + h * pz[j] / lz);
+                }
+            }
+            k += 1;
+            H = mix_cell(l0x, l0y, er, sr, (double)k * h, rc);
+            if (H.ncx < 3 || H.ncy < 3 || H.ncx * H.ncy * ncz > L.cmax) {
+                health = kHealthNonFinite;  // uniform: every thread stops here
+                break;
+            }
+        }
+        mix_forces(S, n, ncz, H, lz, rc2, ca, fx, fy, fz, wn, wxy);
+        double vj;
+        if constexpr (NH) {
+            // K(h/2) E(h/2) T(h/2) Z(h/2), with the flux in the same sum
+            const double sc = exp(-zeta * tau);
+            double v[5] = {0.0, 0.0, 0.0, wn, wxy};
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                const double qx = px[j] + tau * fx[j], qy = py[j] + tau * fy[j];
+                px[j] = (fa * qx + fc * qy) * sc;
+                py[j] = (fd * qy) * sc;
+                pz[j] = (pz[j] + tau * fz[j]) * sc;
+                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                v[1] += px[j] * px[j] - py[j] * py[j];
+                v[2] += px[j] * py[j];
+            }
+            pef_sum<5>(v, S.red);
+            zeta += tau * (v[0] - nh_target) / nh_q;
+            vj = (er * (v[1] + v[3]) + sr * (v[2] + v[4])) / rn;
+        } else {
+            // K(h/2)
+            {
+                double v[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    v[1] += fx[j] * px[j] + fy[j] * py[j] + fz[j] * pz[j];
+                    v[2] += fx[j] * fx[j] + fy[j] * fy[j] + fz[j] * fz[j];
+                }
+                pef_sum<3>(v, S.red);
+                double s1, sd;
+                pef_kick_coeffs(v[1] / v[0], v[2] / v[0], tau, s1, sd);
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] = (px[j] + fx[j] * s1) / sd;
+                    py[j] = (py[j] + fy[j] * s1) / sd;
+                    pz[j] = (pz[j] + fz[j] * s1) / sd;
+                }
+            }
+            // E(h/2), constrained
+            {
+                double v[2] = {0.0, 0.0};
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                    const double qx = fa * px[j] + fc * py[j];
+                    py[j] = fd * py[j];
+                    px[j] = qx;
+                    v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                }
+                pef_sum<2>(v, S.red);
+                const double g = sqrt(v[0] / v[1]);
+#pragma unroll
+                for (int j = 0; j < kPefApt; ++j) {
+                    px[j] *= g;
+                    py[j] *= g;
+                    pz[j] *= g;
+                }
+            }
+            // rescale to K0 (round-off only), with the flux in the same sum
+            double v[5] = {0.0, 0.0, 0.0, wn, wxy};
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+                v[1] += px[j] * px[j] - py[j] * py[j];
+                v[2] += px[j] * py[j];
+            }
+            pef_sum<5>(v, S.red);
+            const double lam = sqrt(k0 / (0.5 * v[0]));
+#pragma unroll
+            for (int j = 0; j < kPefApt; ++j) {
+                px[j] *= lam;
+                py[j] *= lam;
+                pz[j] *= lam;
+            }
+            vj = (er * (lam * lam * v[1] + v[3]) + sr * (lam * lam * v[2] + v[4])) / rn;
+        }
+        if (t == 0) series[done0 + it + 1] = vj;
+        if (!isfinite(vj)) {
+            health = kHealthNonFinite;  // uniform: every thread holds the same sum
+            ++it;
+            break;
+        }
+    }
+    // the state in the coordinates of the current cell
+#pragma unroll
+    for (int j = 0; j < kPefApt; ++j) {
+        const int a = t + j * T;
+        if (a < n) {
+            st[a] = H.hxx * S.sx[a] + H.hxy * S.sy[a];
+            st[n + a] = H.hyy * S.sy[a];
+            st[2 * n + a] = lz * S.sz[a];
+            st[3 * n + a] = px[j];
+            st[4 * n + a] = py[j];
+            st[5 * n + a] = pz[j];
+        }
+    }
+    if (t == 0) {
+        dp->k = k;
+        dp->done = done0 + it;
+        dp->k0 = k0;
+        if (NH) dp->zeta = zeta;
+        dp->health = health;
+    }
+}
+
+// Start states of planar-elongation daughters under their mappings: bit 1 of map exchanges
+// the x and y axes of positions and momenta (the box is cubic), bit 0 reverses the momenta.
+// Mixed-flow daughters (mix): bit 1 exchanges the axes, then bit 0 reflects x
+// (x -> L_x - x, p_x -> -p_x).
 __global__ void k_spawn_pef(const double* states, int32_t n, const int32_t* state_of,
-                            const int32_t* map_of, double* const* dst) {
+                            const int32_t* map_of, double* const* dst, int32_t mix, double lx) {
     const int d = blockIdx.x;
     const double* src = states + (size_t)state_of[d] * 6 * (size_t)n;
     double* out = dst[d];
     const int m = map_of[d];
     const bool sw = (m & 2) != 0;
-    const double sg = (m & 1) ? -1.0 : 1.0;
+    const bool rev = !mix && (m & 1) != 0;
+    const bool refl = mix && (m & 1) != 0;
+    const double sg = rev ? -1.0 : 1.0;
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
         const double x = src[a], y = src[n + a], z = src[2 * n + a];
         const double px = src[3 * n + a], py = src[4 * n + a], pz = src[5 * n + a];
-        out[a] = sw ? y : x;
+        const double xs = sw ? y : x;
+        out[a] = refl ? (xs == 0.0 ? 0.0 : lx - xs) : xs;
         out[n + a] = sw ? x : y;
         out[2 * n + a] = z;
-        out[3 * n + a] = sg * (sw ? py : px);
+        out[3 * n + a] = (refl ? -1.0 : sg) * (sw ? py : px);
         out[4 * n + a] = sg * (sw ? px : py);
         out[5 * n + a] = sg * pz;
     }
@@ -603,7 +994,19 @@ hipError_t launch_pef(const PefLaunch& L, hipStream_t s) {
     if (L.threads < 64 || L.threads > kMaxThreads || L.threads % 64 != 0 ||
         L.nmax > L.threads * kPefApt || L.cmax < 27)
         return hipErrorInvalidValue;
-    if (L.thermo) {
+    if (L.mix) {
+        if (L.thermo) {
+            (void)hipFuncSetAttribute((const void*)k_daughters_mix<true>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+            hipLaunchKernelGGL(k_daughters_mix<true>, dim3(L.n_jobs), dim3(L.threads),
+                               L.lds_bytes, s, L);
+        } else {
+            (void)hipFuncSetAttribute((const void*)k_daughters_mix<false>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
+            hipLaunchKernelGGL(k_daughters_mix<false>, dim3(L.n_jobs), dim3(L.threads),
+                               L.lds_bytes, s, L);
+        }
+    } else if (L.thermo) {
         (void)hipFuncSetAttribute((const void*)k_daughters_pef<true>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)L.lds_bytes);
         hipLaunchKernelGGL(k_daughters_pef<true>, dim3(L.n_jobs), dim3(L.threads), L.lds_bytes, s,
@@ -619,10 +1022,10 @@ hipError_t launch_pef(const PefLaunch& L, hipStream_t s) {
 
 hipError_t launch_spawn_pef(const double* states, int32_t n, const int32_t* state_of,
                             const int32_t* map_of, double* const* dst, int32_t n_daughters,
-                            hipStream_t s) {
+                            int32_t mix, double lx, hipStream_t s) {
     if (n_daughters <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_spawn_pef, dim3(n_daughters), dim3(256), 0, s, states, n, state_of,
-                       map_of, dst);
+                       map_of, dst, mix, lx);
     return hipGetLastError();
 }
 

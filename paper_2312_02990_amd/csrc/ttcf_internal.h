@@ -81,13 +81,18 @@ struct DaughterDesc {
     double fe;          // colour field strength F_e (kFieldColour)
     int32_t global_lists;  // list form with the lists in global scratch (set by the host)
     int32_t pad3_;
+    // mixed flow (kFieldMixed): u_x = erate x + srate y, u_y = -erate y; gamma_dot holds
+    // sqrt(erate^2 + srate^2)
+    double erate, srate;
 };
 
 // External field of a daughter: SLLOD shear at gamma_dot, the colour field (charge +1 on
 // even atoms, -1 on odd ones, force charge * F_e along x; series V J_x = sum charge p_x), or
 // planar elongational flow at rate gamma_dot (grad u = diag(rate, -rate, 0) in a deforming
 // box; series V (P_xx - P_yy); k counts the steps that set the box strain rate k dt).
-enum Field : int32_t { kFieldShear = 0, kFieldColour = 1, kFieldElong = 2 };
+// Mixed flow: shear and planar elongation together (erate, srate), series V J with
+// J = (erate (P_xx - P_yy) + srate P_xy) / sqrt(erate^2 + srate^2).
+enum Field : int32_t { kFieldShear = 0, kFieldColour = 1, kFieldElong = 2, kFieldMixed = 3 };
 
 enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2, kHealthListOverflow = 4 };
 
@@ -132,6 +137,7 @@ struct PefLaunch {
     int32_t nmax;          // largest system
     int32_t cmax;          // >= the cell count of any job's box at any step
     int32_t thermo;        // daughter thermostat of every job (0 isokinetic, 1 Nose-Hoover)
+    int32_t mix;           // 1: mixed-flow daughters (k_daughters_mix)
     size_t lds_bytes;      // lds_bytes_pef(nmax, cmax)
 };
 
@@ -293,7 +299,7 @@ size_t lds_bytes_pef(int nmax, int cmax);
 hipError_t launch_pef(const PefLaunch& L, hipStream_t s);
 hipError_t launch_spawn_pef(const double* states, int32_t n, const int32_t* state_of,
                             const int32_t* map_of, double* const* dst, int32_t n_daughters,
-                            hipStream_t s);
+                            int32_t mix, double lx, hipStream_t s);
 hipError_t launch_spawn(const double* states, int32_t n, int32_t n_states, const int32_t* state_of,
                         const int32_t* map_of, double* const* dst, int32_t n_daughters, double lx,
                         hipStream_t s);

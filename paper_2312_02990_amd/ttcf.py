@@ -25,6 +25,7 @@ TTCF_OBS_VPROFILE = 2
 TTCF_OBS_N1, TTCF_OBS_N2, TTCF_OBS_ENERGY, TTCF_OBS_SLAB_PX = 3, 4, 5, 6
 TTCF_OBS_JX = 7
 TTCF_OBS_PEF_N1 = 8
+TTCF_OBS_MIX_J = 9
 TTCF_BULK_SLABS = 8
 OBS_COLS = 3 + TTCF_BULK_SLABS  # columns of ttcf_export_observables
 TTCF_CV_ESTIMATE = 1
@@ -152,6 +153,8 @@ def lib():
         "ttcf_export_observables": [V, C.c_int64, C.c_int32, C.c_int32, D],
         "ttcf_spawn_elongational": [V, C.c_int32, C.c_int32, C.c_int64, C.c_uint32, D,
                                     C.c_int32, C.c_int32, L64],
+        "ttcf_spawn_mixed": [V, C.c_int32, C.c_int32, C.c_int64, C.c_uint32, D, D, C.c_int32,
+                             C.c_int32, L64],
         "ttcf_mother_acf": [V, C.c_int32, C.c_int32, C.c_double, D, I, D],
         "ttcf_export_states_zeta": [V, C.c_int32, C.c_int32, D],
         "ttcf_export_mother": [V, C.c_int32, D, D, D, L64],
@@ -247,7 +250,7 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_import_states_zeta", "ttcf_export_states_zeta", "ttcf_acf", "ttcf_mother_acf",
             "ttcf_response_modified", "ttcf_observable_response_modified",
             "ttcf_record_observables", "ttcf_export_observables", "ttcf_spawn_colour",
-            "ttcf_spawn_elongational"]
+            "ttcf_spawn_elongational", "ttcf_spawn_mixed"]
 
 # network shape of the learned control variate (fixed by the library)
 CV_IN = 64
@@ -426,6 +429,21 @@ class Context:
                                              int(steps_between), int(mapping_mask), _dp(g),
                                              int(g.size), int(n_steps), C.byref(first)),
                "ttcf_spawn_elongational", self._ctx)
+        return first.value
+
+    def ttcf_spawn_mixed(self, mother: int, n_states: int, steps_between: int, erate, srate,
+                         n_steps: int, mapping_mask: int = 0xF) -> int:
+        """Mixed-flow daughters (u_x = erate x + srate y, u_y = -erate y), one rate pair for
+        all states or one per state."""
+        e = _f64(np.atleast_1d(erate))
+        g = _f64(np.atleast_1d(srate))
+        if e.size != g.size:
+            raise ValueError("erate and srate need the same length")
+        first = C.c_int64(-1)
+        _check(lib().ttcf_spawn_mixed(self._ctx, int(mother), int(n_states), int(steps_between),
+                                      int(mapping_mask), _dp(e), _dp(g), int(e.size),
+                                      int(n_steps), C.byref(first)), "ttcf_spawn_mixed",
+               self._ctx)
         return first.value
 
     def ttcf_step(self, n_steps: int):

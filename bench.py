@@ -32,6 +32,7 @@ VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_config2_valu.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_kernels.hip")
 PEF_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_elongation.hip")
 PEF_VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_pef_n2048_valu.json")
+MIX_VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_mix_n2048_valu.json")
 
 
 def kernel_hash() -> str:
@@ -326,12 +327,12 @@ def colour_leg(T, stream, ctx, mid, s, n_states, nst, fields=(1e-2, 1e-4)):
     return out
 
 
-def pef_roofline(kernel_ms, atom_steps):
-    """FP64 roofline of the planar-elongation kernel: the FP64 lane operations per atom-step
-    from the committed SQ counter run (while the kernel source matches it) over the live
-    kernel time, against the FP64 vector peak."""
+def pef_roofline(kernel_ms, atom_steps, valu_file=PEF_VALU_FILE):
+    """FP64 roofline of the planar-elongation (or mixed-flow) kernel: the FP64 lane
+    operations per atom-step from the committed SQ counter run (while the kernel source
+    matches it) over the live kernel time, against the FP64 vector peak."""
     try:
-        with open(PEF_VALU_FILE) as f:
+        with open(valu_file) as f:
             rec = json.load(f)
         with open(PEF_SRC, "rb") as f:
             if rec.get("kernel_sha256_16") != hashlib.sha256(f.read()).hexdigest()[:16]:
@@ -377,6 +378,40 @@ def elongation_leg(T, stream, ctx, mid, s, n_states, nst, rates=(1.0, 1e-2, 1e-4
         out[f"rate={rate:g}"] = row
     ms = [out[k]["kernel_ms"] for k in out if k.startswith("rate=")]
     out["roofline"] = pef_roofline(sum(ms) / len(ms), 4 * n_states * s.n * nst)
+    return out
+
+
+def mixed_leg(T, stream, ctx, mid, s, n_states, nst, pair=(0.5, 1.0), scales=(1.0, 1e-2, 1e-4)):
+    """The benchmark's start states under mixed flow (u_x = erate x + srate y,
+    u_y = -erate y, the pair scaled down): the generalised viscosity
+    -<J> |rate| / (4 erate^2 + srate^2) (the shear viscosity for a Newtonian fluid) by TTCF
+    and by the direct average at t = 0.25 and at the end, and the FP64 kernel's throughput."""
+    import torch
+    r, p = ctx.ttcf_export_states(mid, n_states)
+    out = {"workload": f"N={s.n}, {n_states} states x 4 mappings x {nst} steps per rate pair"}
+    for sc in scales:
+        er, sr = pair[0] * sc, pair[1] * sc
+        rn = float(np.sqrt(er * er + sr * sr))
+        with T.Context(stream) as c2:
+            m2 = c2.ttcf_init_mother(T.make_system(s.n, s.box, s.temperature, s.dt, precision=1),
+                                     r[0], p[0], n_equil=0)
+            c2.ttcf_import_states(m2, r, p)
+            c2.ttcf_spawn_mixed(m2, n_states, 0, er, sr, nst)
+            c2.ttcf_step_timing(reset=True)
+            c2.ttcf_step(nst)
+            ms, _ = c2.ttcf_step_timing(reset=True)
+            c2.ttcf_accumulate()
+            tm, tse, dm, dse, used = c2.ttcf_response(nst + 1, rn, observable=T.TTCF_OBS_MIX_J)
+            torch.cuda.synchronize()
+        f = -rn / (4.0 * er * er + sr * sr)
+        row = {"erate": er, "srate": sr, "n_states": used, "kernel_ms": ms,
+               "kernel_atom_steps_per_s": 4 * n_states * s.n * nst / (ms / 1e3)}
+        for k in (100, nst):
+            row[f"t={k * s.dt:g}"] = {"eta_ttcf": float(f * tm[k]), "eta_ttcf_se": float(-f * tse[k]),
+                                      "eta_dav": float(f * dm[k]), "eta_dav_se": float(-f * dse[k])}
+        out[f"scale={sc:g}"] = row
+    ms = [out[k]["kernel_ms"] for k in out if k.startswith("scale=")]
+    out["roofline"] = pef_roofline(sum(ms) / len(ms), 4 * n_states * s.n * nst, MIX_VALU_FILE)
     return out
 
 
@@ -626,6 +661,8 @@ def main():
                     help="1: also compare isokinetic and Nose-Hoover daughters on the same states")
     ap.add_argument("--observables", type=int, default=1,
                     help="1: also measure daughters that record the extra bulk observables")
+    ap.add_argument("--mixed", type=int, default=1,
+                    help="1: also measure mixed-flow daughters on the same start states")
     ap.add_argument("--elongation", type=int, default=1,
                     help="1: also measure planar-elongation daughters on the same start states")
     ap.add_argument("--colour", type=int, default=1,
@@ -733,6 +770,12 @@ def main():
             elongation = elongation_leg(T, stream, ctx, mid, s, args.states, nst)
         except Exception as e:  # the headline line is printed whatever happens here
             elongation = {"error": repr(e)}
+    mixed = None
+    if args.mixed:
+        try:
+            mixed = mixed_leg(T, stream, ctx, mid, s, args.states, nst)
+        except Exception as e:  # the headline line is printed whatever happens here
+            mixed = {"error": repr(e)}
     colour = None
     if args.colour:
         try:
@@ -797,6 +840,8 @@ def main():
         line["colour"] = colour
     if elongation is not None:
         line["elongation"] = elongation
+    if mixed is not None:
+        line["mixed"] = mixed
     if args.graph:
         try:
             line["graph"] = graph_leg(T, stream)

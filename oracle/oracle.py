@@ -123,10 +123,10 @@ def _load():
         lib.orc_map_mix.restype = None
         lib.orc_mix_run.argtypes = [B, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
                                     C.c_double, C.c_double, C.c_double, D, D, D, D, C.c_int64,
-                                    D, D, D]
+                                    D, D, D, D]
         lib.orc_run_daughters_mix.argtypes = [B, C.c_double, D, D, D, C.c_double, C.c_double,
                                               C.c_double, C.c_int32, I, I, D, D, C.c_int64,
-                                              C.c_int32, D, D, D]
+                                              C.c_int32, D, D, D, D]
         for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
                    "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
                    "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh",
@@ -517,7 +517,8 @@ def mix_run(box: Box, r, p, erate: float, srate: float, dt: float, nsteps: int,
     z = np.array([float(zeta) if zeta is not None else 0.0])
     rc = _load().orc_mix_run(C.byref(box), float(erate), float(srate), float(dt), int(gik),
                              int(zeta is not None), float(temperature), float(q), float(nf),
-                             _dp(t), _dp(r), _dp(p), _dp(z), int(nsteps), *[_dp(o) for o in outs])
+                             _dp(t), _dp(r), _dp(p), _dp(z), int(nsteps), *[_dp(o) for o in outs],
+                             None)
     if rc != 0:
         raise RuntimeError(f"orc_mix_run failed: {rc}")
     return outs[0], outs[1], outs[2], float(t[0]), float(z[0])
@@ -526,9 +527,10 @@ def mix_run(box: Box, r, p, erate: float, srate: float, dt: float, nsteps: int,
 def run_daughters_mix(box: Box, states_r, states_p, state_of, map_of, er_of, sr_of, dt: float,
                       nsteps: int, nthreads: int = 0, final_state: bool = False,
                       states_zeta=None, temperature: float = 0.0, q: float = 0.0,
-                      nf: float = 0.0):
+                      nf: float = 0.0, components: bool = False):
     """Mixed-flow daughters on a CPU thread pool: V J (n_d, nsteps+1) [and final r, p] and the
-    number of threads used."""
+    number of threads used; with components, also V (P_xx - P_yy) and V P_xy as
+    (n_d, nsteps+1, 2) after the thread count."""
     states_r = _f64(states_r)
     states_p = _f64(states_p)
     state_of = np.ascontiguousarray(state_of, np.int32)
@@ -542,15 +544,16 @@ def run_daughters_mix(box: Box, states_r, states_p, state_of, map_of, er_of, sr_
     if nthreads <= 0:
         nthreads = os.cpu_count() or 1
     zeta = _f64(states_zeta) if states_zeta is not None else None
+    comp = np.zeros((nd, nsteps + 1, 2)) if components else None
     used = _load().orc_run_daughters_mix(C.byref(box), float(dt), _dp(states_r), _dp(states_p),
                                          _dp(zeta), float(temperature), float(q), float(nf), nd,
                                          _ip(state_of), _ip(map_of), _dp(er_of), _dp(sr_of),
-                                         int(nsteps), int(nthreads), _dp(out), _dp(ro), _dp(po))
+                                         int(nsteps), int(nthreads), _dp(out), _dp(ro), _dp(po),
+                                         _dp(comp))
     if used < 0:
         raise RuntimeError(f"orc_run_daughters_mix failed: {used}")
-    if final_state:
-        return out, ro, po, used
-    return out, used
+    res = (out, ro, po, used) if final_state else (out, used)
+    return res + (comp,) if components else res
 
 
 N_SLABS = 8  # slabs of the bulk momentum profile

@@ -1529,11 +1529,12 @@ static void mix_flow(int32_t n, double* p, double er, double sr, double tau) {
  *      = [[h phi(erate h), -srate (h^2/2) sinhc(erate h/2)^2], [0, h phi(-erate h)]]
  *      (phi(u) = (1 - e^-u)/u), the exact streaming with p fixed.
  * gik = 0: the adiabatic step. thermo = 1 (gik ignored): Nose-Hoover, Z T E K D K E T Z.
- * vj_out[s] = V J after step s. */
+ * vj_out[s] = V J after step s; comp_out[2 s], comp_out[2 s + 1] = V (P_xx - P_yy) and V P_xy
+ * (NULL to skip). */
 int32_t orc_mix_run(const orc_box* b0, double er, double sr, double dt, int32_t gik,
                     int32_t thermo, double temperature, double q, double nf, double* t,
                     double* r, double* p, double* zeta, int64_t nsteps, double* vj_out,
-                    double* ke_out, double* pe_out) {
+                    double* ke_out, double* pe_out, double* comp_out) {
     const int32_t n = b0->n;
     double* f = (double*)malloc(sizeof(double) * 3 * (size_t)n);
     if (!f) return -2;
@@ -1562,6 +1563,10 @@ int32_t orc_mix_run(const orc_box* b0, double er, double sr, double dt, int32_t 
             s2 += p[i] * p[n + i];                                                    \
         }                                                                             \
         if (vj_out) vj_out[KS] = rn > 0.0 ? (er * (s1 + out[1]) + sr * (s2 + out[2])) / rn : 0.0; \
+        if (comp_out) {                                                               \
+            comp_out[2 * (KS)] = s1 + out[1];                                         \
+            comp_out[2 * (KS) + 1] = s2 + out[2];                                     \
+        }                                                                             \
     } while (0)
     MIX_VJ(0);
     if (ke_out) ke_out[0] = kinetic(n, p);
@@ -1636,7 +1641,7 @@ typedef struct {
     const int32_t *state_of, *map_of;
     const double *er_of, *sr_of;
     int64_t nsteps;
-    double *vj_out, *r_out, *p_out;
+    double *vj_out, *r_out, *p_out, *comp_out;
     double temperature, q, nf;
     int32_t tid, nthreads, status;
 } mix_job;
@@ -1657,7 +1662,9 @@ static void* mix_worker(void* arg) {
         int32_t rc = orc_mix_run(jb->b, jb->er_of[d], jb->sr_of[d], jb->dt, 1,
                                  jb->states_zeta ? 1 : 0, jb->temperature, jb->q, jb->nf, &t, r,
                                  p, &zt, jb->nsteps,
-                                 jb->vj_out + (size_t)d * (size_t)(jb->nsteps + 1), 0, 0);
+                                 jb->vj_out + (size_t)d * (size_t)(jb->nsteps + 1), 0, 0,
+                                 jb->comp_out ? jb->comp_out + (size_t)d * 2 * (size_t)(jb->nsteps + 1)
+                                              : 0);
         if (rc) jb->status = rc;
         if (jb->r_out) memcpy(jb->r_out + (size_t)d * sz, r, sizeof(double) * sz);
         if (jb->p_out) memcpy(jb->p_out + (size_t)d * sz, p, sizeof(double) * sz);
@@ -1672,7 +1679,8 @@ int32_t orc_run_daughters_mix(const orc_box* b, double dt, const double* states_
                               double temperature, double q, double nf, int32_t n_daughters,
                               const int32_t* state_of, const int32_t* map_of,
                               const double* er_of, const double* sr_of, int64_t nsteps,
-                              int32_t nthreads, double* vj_out, double* r_out, double* p_out) {
+                              int32_t nthreads, double* vj_out, double* r_out, double* p_out,
+                              double* comp_out) {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > n_daughters) nthreads = n_daughters > 0 ? n_daughters : 1;
     mix_job* jobs = (mix_job*)calloc((size_t)nthreads, sizeof(mix_job));
@@ -1680,8 +1688,8 @@ int32_t orc_run_daughters_mix(const orc_box* b, double dt, const double* states_
     for (int32_t t = 0; t < nthreads; ++t) {
         mix_job j = {b,     dt,       states_r, states_p,    states_zeta, n_daughters,
                      state_of, map_of, er_of,   sr_of,       nsteps,      vj_out,
-                     r_out, p_out,    temperature, q,       nf,          t,
-                     nthreads, 0};
+                     r_out, p_out,    comp_out, temperature, q,       nf,
+                     t,     nthreads, 0};
         jobs[t] = j;
         pthread_create(&th[t], 0, mix_worker, &jobs[t]);
     }

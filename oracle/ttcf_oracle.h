@@ -220,7 +220,8 @@ int32_t orc_run_daughters_pef(const orc_box* b, double dt, const double* states_
  * orc_map_mix: bit 1 exchanges the x and y axes, then bit 0 reflects x.
  * orc_mix_run: one trajectory from time *t (advanced); gik = 0 adiabatic; thermo = 1
  * Nose-Hoover from *zeta (advanced); vj_out = V J, J = (erate (P_xx - P_yy) + srate P_xy) /
- * sqrt(erate^2 + srate^2); ke_out, pe_out: nsteps + 1 values each (NULL to skip).
+ * sqrt(erate^2 + srate^2); ke_out, pe_out: nsteps + 1 values each; comp_out: 2 (nsteps + 1)
+ * values, V (P_xx - P_yy) and V P_xy per step (each NULL to skip).
  * orc_run_daughters_mix: isokinetic daughters, or Nose-Hoover when states_zeta is given
  * (no mapping reverses time, so zeta is carried unchanged). */
 int32_t orc_mix_forces(const orc_box* b0, const double h[3], const double* r, double* f,
@@ -230,13 +231,14 @@ void orc_map_mix(const orc_box* b, int32_t m, const double* r, const double* p, 
 int32_t orc_mix_run(const orc_box* b0, double er, double sr, double dt, int32_t gik,
                     int32_t thermo, double temperature, double q, double nf, double* t,
                     double* r, double* p, double* zeta, int64_t nsteps, double* vj_out,
-                    double* ke_out, double* pe_out);
+                    double* ke_out, double* pe_out, double* comp_out);
 int32_t orc_run_daughters_mix(const orc_box* b, double dt, const double* states_r,
                               const double* states_p, const double* states_zeta,
                               double temperature, double q, double nf, int32_t n_daughters,
                               const int32_t* state_of, const int32_t* map_of,
                               const double* er_of, const double* sr_of, int64_t nsteps,
-                              int32_t nthreads, double* vj_out, double* r_out, double* p_out);
+                              int32_t nthreads, double* vj_out, double* r_out, double* p_out,
+                              double* comp_out);
 
 /* Batch of independent GIK-SLLOD daughters on a pool of nthreads threads.
  * Daughter d starts from start state state_of[d] under mapping map_of[d] with shear rate

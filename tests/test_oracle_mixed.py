@@ -193,3 +193,20 @@ def test_ttcf_agrees_with_the_direct_average_at_a_strong_field(orc):
     wrong = orc.ttcf_response(x / s.volume, -x[:, 0], rn, s.temperature, s.dt)
     for k in (50, 100):
         assert abs(wrong.ttcf[k] - resp.dav[k]) > 4 * np.hypot(wrong.ttcf_se[k], resp.dav_se[k])
+
+
+def test_recorded_components_make_up_the_flux(orc, liquid):
+    # V (P_xx - P_yy) and V P_xy of the batch driver: the first equals the observables
+    # routine at the start, and (erate N1 + srate P_xy) / |rate| is the recorded flux
+    s, box, st = liquid
+    sr_, sp_ = st.r.reshape(1, -1), st.p.reshape(1, -1)
+    er, srate = 0.3, -0.5
+    x, _, comp = orc.run_daughters_mix(box, sr_, sp_, np.zeros(4, np.int32), np.arange(4),
+                                       np.full(4, er), np.full(4, srate), s.dt, 30, nthreads=4,
+                                       components=True)
+    rn = np.hypot(er, srate)
+    np.testing.assert_allclose((er * comp[..., 0] + srate * comp[..., 1]) / rn, x, rtol=1e-12,
+                               atol=1e-12 * np.abs(x).max())
+    rm, pm = orc.map_mix(box, 2, st.r, st.p)
+    assert comp[2, 0, 0] == pytest.approx(orc.observables(box, rm, pm)[0] * s.volume, rel=1e-10)
+    assert comp[2, 0, 1] == pytest.approx(orc.vpxy(box, rm, pm), rel=1e-10)

@@ -72,7 +72,9 @@ enum {
     TTCF_OBS_SLAB_PX = 6,
     TTCF_OBS_JX = 7,     /* colour-field daughters (ttcf_spawn_colour): the colour current J_x */
     TTCF_OBS_PEF_N1 = 8, /* planar-elongation daughters (ttcf_spawn_elongational): P_xx - P_yy */
-    TTCF_OBS_MIX_J = 9   /* mixed-flow daughters (ttcf_spawn_mixed): the flux J */
+    TTCF_OBS_MIX_J = 9,  /* mixed-flow daughters (ttcf_spawn_mixed): the flux J */
+    TTCF_OBS_MIX_N1 = 10,  /* mixed-flow daughters: P_xx - P_yy */
+    TTCF_OBS_MIX_PXY = 11  /* mixed-flow daughters: P_xy */
 };
 enum { TTCF_BULK_SLABS = 8 };
 
@@ -189,7 +191,10 @@ int32_t ttcf_spawn_elongational(ttcf_ctx* ctx, int32_t mother, int32_t n_states,
  * time, so Nose-Hoover daughters carry zeta unchanged.
  * erate, srate: n_rate == 1 or n_states values each (one pair per start state). The series
  * holds V J(t_k); ttcf_response(ctx, TTCF_OBS_MIX_J, |rate|, ...) returns <J>(t) (for a
- * Newtonian fluid -eta (4 erate^2 + srate^2) / |rate|). Final states are in the coordinates
+ * Newtonian fluid -eta (4 erate^2 + srate^2) / |rate|), and TTCF_OBS_MIX_N1 and
+ * TTCF_OBS_MIX_PXY the TTCF of each component under the same Omega (-4 eta erate and
+ * -eta srate in the linear regime); ttcf_export_observables exports them as columns 0 and 1
+ * of the extra-observable layout (the other columns hold zeros). Final states are in the coordinates
  * of the carried cell. Forces are FP64. TTCF_EINVAL for N > 2048, L_x != L_y, both rates
  * zero, the extra observables switched on, or rates and a length that would narrow a
  * perpendicular width of the cell below 3 r_c before the daughter ends. */

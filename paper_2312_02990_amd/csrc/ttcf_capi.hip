@@ -171,6 +171,8 @@ struct ttcf_ctx {
     // extra observables: recorded by daughters spawned while record_obs is set; accumulated
     // rows of kObsCols columns of acc_stride values (allocated with the first such spawn)
     bool record_obs = false;
+    // some spawned daughters record extra columns on their own (mixed flow: its components)
+    bool own_x = false;
     double* acc_xd = nullptr;
     double* acc_xi = nullptr;
     std::vector<char> row_x;
@@ -388,7 +390,9 @@ int32_t run_mother(ttcf_ctx* c, Mother& m, double temperature, int64_t n_chunks,
 
 int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
     const int32_t stride = std::max(c->acc_stride, n_t);
-    if (rows_needed <= c->acc_cap && stride == c->acc_stride) return TTCF_OK;
+    // groups with extra columns need their accumulator too, even where the rows would fit
+    const bool missing_x = (c->record_obs || c->own_x) && !c->acc_xd;
+    if (rows_needed <= c->acc_cap && stride == c->acc_stride && !missing_x) return TTCF_OK;
     if (!c->graphs.empty())
         return fail(c, TTCF_ESTATE, "accumulator capacity is pinned by a captured graph: destroy "
                                     "it before accumulating beyond the rows reserved for it");
@@ -403,7 +407,7 @@ int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
         return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
     double* nxd = nullptr;
     double* nxi = nullptr;
-    const bool with_x = c->record_obs || c->acc_xd;
+    const bool with_x = c->record_obs || c->own_x || c->acc_xd;
     if (with_x) {
         nxd = (double*)dev_alloc(sizeof(double) * (size_t)cap * kObsCols * stride, c->stream);
         nxi = (double*)dev_alloc(sizeof(double) * (size_t)cap * kObsCols * stride, c->stream);
@@ -921,10 +925,13 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
     b.series = (double*)dev_alloc(sizeof(double) * (size_t)(n_steps + 1) * nd, c->stream);
     const size_t scratch_bytes = sizeof(int32_t) * 2 * nd + sizeof(double*) * nd + 64;
     b.scratch = dev_alloc(scratch_bytes, c->stream);
-    if (c->record_obs)
+    // mixed-flow daughters always record their flux components (columns 0 and 1)
+    const bool with_x = c->record_obs || field == kFieldMixed;
+    if (field == kFieldMixed) c->own_x = true;
+    if (with_x)
         b.xseries = (double*)dev_alloc(sizeof(double) * (size_t)(n_steps + 1) * kObsCols * nd,
                                        c->stream);
-    if (!b.states || !b.series || !b.scratch || (c->record_obs && !b.xseries)) {
+    if (!b.states || !b.series || !b.scratch || (with_x && !b.xseries)) {
         dev_free(b.states);
         dev_free(b.series);
         dev_free(b.scratch);
@@ -1802,6 +1809,8 @@ bool obs_columns(int32_t observable, int* col0, int* ncol) {
         case TTCF_OBS_JX: *col0 = -1; *ncol = 1; return true;  // colour rows hold V J_x there
         case TTCF_OBS_PEF_N1: *col0 = -1; *ncol = 1; return true;  // elongation: V (P_xx - P_yy)
         case TTCF_OBS_MIX_J: *col0 = -1; *ncol = 1; return true;   // mixed flow: V J
+        case TTCF_OBS_MIX_N1: *col0 = 0; *ncol = 1; return true;   // mixed flow: P_xx - P_yy
+        case TTCF_OBS_MIX_PXY: *col0 = 1; *ncol = 1; return true;  // mixed flow: P_xy
         case TTCF_OBS_N1: *col0 = 0; *ncol = 1; return true;
         case TTCF_OBS_N2: *col0 = 1; *ncol = 1; return true;
         case TTCF_OBS_ENERGY: *col0 = 2; *ncol = 1; return true;
@@ -1815,7 +1824,9 @@ int32_t field_of_observable(int32_t observable) {
     switch (observable) {
         case TTCF_OBS_JX: return kFieldColour;
         case TTCF_OBS_PEF_N1: return kFieldElong;
-        case TTCF_OBS_MIX_J: return kFieldMixed;
+        case TTCF_OBS_MIX_J:
+        case TTCF_OBS_MIX_N1:
+        case TTCF_OBS_MIX_PXY: return kFieldMixed;
     }
     return kFieldShear;
 }

@@ -708,6 +708,9 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
     const double rc = dp->sys.rc, rc2 = dp->sys.rc2, ca = dp->sys.c_attr;
     double* st = dp->state;
     double* series = dp->series;
+    // the flux components P_xx - P_yy and P_xy (columns 0 and 1 of kObsCols per time point)
+    double* xs = dp->xseries;
+    const double inv_v = 1.0 / dp->sys.volume;
     int64_t k = dp->k;
     int health = 0;
     if (n > T * kPefApt || n > L.nmax || !(rn > 0.0)) health = kHealthNonFinite;
@@ -758,7 +761,14 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
         pef_sum<5>(v, S.red);
         if (done0 == 0) {
             k0 = 0.5 * v[0];
-            if (t == 0) series[0] = (er * (v[1] + v[3]) + sr * (v[2] + v[4])) / rn;
+            if (t == 0) {
+                series[0] = (er * (v[1] + v[3]) + sr * (v[2] + v[4])) / rn;
+                if (xs) {
+                    xs[0] = (v[1] + v[3]) * inv_v;
+                    xs[1] = (v[2] + v[4]) * inv_v;
+                    for (int c = 2; c < kObsCols; ++c) xs[c] = 0.0;
+                }
+            }
         }
     }
     int it = 0;
@@ -843,7 +853,7 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
             }
         }
         mix_forces(S, n, ncz, H, lz, rc2, ca, fx, fy, fz, wn, wxy);
-        double vj;
+        double vj, cn, cxy;  // flux, V (P_xx - P_yy), V P_xy
         if constexpr (NH) {
             // K(h/2) E(h/2) T(h/2) Z(h/2), with the flux in the same sum
             const double sc = exp(-zeta * tau);
@@ -860,7 +870,9 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
             }
             pef_sum<5>(v, S.red);
             zeta += tau * (v[0] - nh_target) / nh_q;
-            vj = (er * (v[1] + v[3]) + sr * (v[2] + v[4])) / rn;
+            cn = v[1] + v[3];
+            cxy = v[2] + v[4];
+            vj = (er * cn + sr * cxy) / rn;
         } else {
             // K(h/2)
             {
@@ -917,9 +929,19 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
                 py[j] *= lam;
                 pz[j] *= lam;
             }
-            vj = (er * (lam * lam * v[1] + v[3]) + sr * (lam * lam * v[2] + v[4])) / rn;
+            cn = lam * lam * v[1] + v[3];
+            cxy = lam * lam * v[2] + v[4];
+            vj = (er * cn + sr * cxy) / rn;
         }
-        if (t == 0) series[done0 + it + 1] = vj;
+        if (t == 0) {
+            series[done0 + it + 1] = vj;
+            if (xs) {
+                double* row = xs + (size_t)(done0 + it + 1) * kObsCols;
+                row[0] = cn * inv_v;
+                row[1] = cxy * inv_v;
+                for (int c = 2; c < kObsCols; ++c) row[c] = 0.0;
+            }
+        }
         if (!isfinite(vj)) {
             health = kHealthNonFinite;  // uniform: every thread holds the same sum
             ++it;

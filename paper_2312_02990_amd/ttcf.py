@@ -26,6 +26,8 @@ TTCF_OBS_N1, TTCF_OBS_N2, TTCF_OBS_ENERGY, TTCF_OBS_SLAB_PX = 3, 4, 5, 6
 TTCF_OBS_JX = 7
 TTCF_OBS_PEF_N1 = 8
 TTCF_OBS_MIX_J = 9
+TTCF_OBS_MIX_N1 = 10
+TTCF_OBS_MIX_PXY = 11
 TTCF_BULK_SLABS = 8
 OBS_COLS = 3 + TTCF_BULK_SLABS  # columns of ttcf_export_observables
 TTCF_CV_ESTIMATE = 1

@@ -173,3 +173,45 @@ def test_full_size_sampled(T, orc):
                                           final_state=True)
     assert np.abs(ser - vo).max() / np.std(vo) <= 1e-8
     check_final(orc, box, s, fin, ro, po, er[state_of], srate[state_of], nst, 1e-8)
+
+
+def test_flux_components_and_their_responses(T, orc):
+    """The recorded P_xx - P_yy and P_xy of mixed-flow daughters against the oracle's; their
+    TTCF and direct averages against the estimator on the GPU's own series (Omega from the
+    flux), and the flux response as the same combination of the component responses."""
+    s = I.System(3)
+    n_states, nst, er, srate = 8, 60, 0.3, -0.5
+    box, sr, sp = oracle_states(orc, s, 99, n_states)
+    rn = float(np.sqrt(er * er + srate * srate))
+    say("mixed flow components")
+    with T.Context() as ctx:
+        sysd = T.make_system(s.n, s.box, s.temperature, s.dt, precision=1)
+        mid = ctx.ttcf_init_mother(sysd, sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        first = ctx.ttcf_spawn_mixed(mid, n_states, 0, er, srate, nst)
+        ctx.ttcf_step(nst // 2)
+        ctx.ttcf_step(nst)
+        nd = 4 * n_states
+        ser = ctx.ttcf_export_series(first, nd, nst + 1)
+        obs = ctx.ttcf_export_observables(first, nd, nst + 1)
+        assert ctx.ttcf_accumulate() == n_states
+        rj = ctx.ttcf_response(nst + 1, rn, observable=T.TTCF_OBS_MIX_J)
+        rn1 = ctx.ttcf_response(nst + 1, rn, observable=T.TTCF_OBS_MIX_N1)
+        rxy = ctx.ttcf_response(nst + 1, rn, observable=T.TTCF_OBS_MIX_PXY)
+    assert np.all(obs[:, :, 2:] == 0.0)
+    state_of = np.repeat(np.arange(n_states), 4)
+    map_of = np.tile(np.arange(4), n_states)
+    vo, _, comp = orc.run_daughters_mix(box, sr, sp, state_of, map_of, np.full(nd, er),
+                                        np.full(nd, srate), s.dt, nst, nthreads=8,
+                                        components=True)
+    for c in (0, 1):
+        got = obs[:, :, c] * s.volume
+        assert np.abs(got - comp[..., c]).max() / np.std(comp[..., c]) <= 1e-9
+    rates = np.full(nd, rn)
+    for c, resp in ((0, rn1), (1, rxy)):
+        own = orc.ttcf_response(obs[:, :, c], ser[:, 0], rates, s.temperature, s.dt)
+        for got, want in zip(resp[:4], (own.ttcf, own.ttcf_se, own.dav, own.dav_se)):
+            np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-12 * np.abs(want).max())
+    # TTCF is linear in B under one Omega: J = (erate N1 + srate P_xy) / |rate|
+    comb = (er * rn1[0] + srate * rxy[0]) / rn
+    np.testing.assert_allclose(comb, rj[0], rtol=1e-9, atol=1e-12 * np.abs(rj[0]).max())

@@ -723,13 +723,29 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
         return;
     }
     const double tau = 0.5 * h;
-    // exp(-A tau) and N = int_0^h exp(-A u) du
-    const double fa = exp(-er * tau), fd = exp(er * tau), fc = -sr * tau * mix_sinhc(er * tau);
-    const double nxx = h * pef_phi(er * h), nyy = h * pef_phi(-er * h);
-    const double hs = mix_sinhc(0.5 * er * h);
-    const double nxy = -sr * 0.5 * h * h * hs * hs;
+    // Per-daughter constants live in LDS and are read where they are used, which keeps them
+    // out of the registers that the force loop needs: exp(-A tau) (fa, fc, fd),
+    // N = int_0^h exp(-A u) du (nxx, nxy, nyy), the rates, the thermostat, 1/V and K0.
+    __shared__ double kc[16];
+    enum { kFa, kFc, kFd, kNxx, kNxy, kNyy, kEr, kSr, kRn, kQ, kTarget, kInvV, kK0, kL0x, kL0y };
+    if (t == 0) {
+        kc[kFa] = exp(-er * tau);
+        kc[kFd] = exp(er * tau);
+        kc[kFc] = -sr * tau * mix_sinhc(er * tau);
+        kc[kNxx] = h * pef_phi(er * h);
+        kc[kNyy] = h * pef_phi(-er * h);
+        const double hs = mix_sinhc(0.5 * er * h);
+        kc[kNxy] = -sr * 0.5 * h * h * hs * hs;
+        kc[kEr] = er;
+        kc[kSr] = sr;
+        kc[kRn] = rn;
+        kc[kQ] = dp->nh_q;
+        kc[kTarget] = dp->nh_target;
+        kc[kInvV] = inv_v;
+        kc[kL0x] = l0x;
+        kc[kL0y] = l0y;
+    }
     double zeta = dp->zeta;
-    const double nh_q = dp->nh_q, nh_target = dp->nh_target;
 
     double px[kPefApt], py[kPefApt], pz[kPefApt];
     double fx[kPefApt], fy[kPefApt], fz[kPefApt];
@@ -771,6 +787,8 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
             }
         }
     }
+    if (t == 0) kc[kK0] = k0;
+    __syncthreads();
     int it = 0;
     for (; it < steps; ++it) {
         if constexpr (NH) {
@@ -779,13 +797,13 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
 #pragma unroll
             for (int j = 0; j < kPefApt; ++j) v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
             pef_sum<1>(v, S.red);
-            zeta += tau * (v[0] - nh_target) / nh_q;
+            zeta += tau * (v[0] - kc[kTarget]) / kc[kQ];
             const double sc = exp(-zeta * tau);
 #pragma unroll
             for (int j = 0; j < kPefApt; ++j) {
                 const double qx = px[j] * sc, qy = py[j] * sc;
-                px[j] = (fa * qx + fc * qy) + tau * fx[j];
-                py[j] = fd * qy + tau * fy[j];
+                px[j] = (kc[kFa] * qx + kc[kFc] * qy) + tau * fx[j];
+                py[j] = kc[kFd] * qy + tau * fy[j];
                 pz[j] = pz[j] * sc + tau * fz[j];
             }
         } else {
@@ -795,8 +813,8 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
 #pragma unroll
                 for (int j = 0; j < kPefApt; ++j) {
                     v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                    const double qx = fa * px[j] + fc * py[j];
-                    py[j] = fd * py[j];
+                    const double qx = kc[kFa] * px[j] + kc[kFc] * py[j];
+                    py[j] = kc[kFd] * py[j];
                     px[j] = qx;
                     v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
                 }
@@ -837,16 +855,16 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
             for (int j = 0; j < kPefApt; ++j) {
                 const int a = t + j * T;
                 if (a < n) {
-                    const double uy = nyy * py[j];
+                    const double uy = kc[kNyy] * py[j];
                     const double dsy = uy / H.hyy;
-                    const double dsx = ((nxx * px[j] + nxy * py[j]) - H.hxy * dsy) / H.hxx;
+                    const double dsx = ((kc[kNxx] * px[j] + kc[kNxy] * py[j]) - H.hxy * dsy) / H.hxx;
                     S.sx[a] = pef_wrap(S.sx[a] + dsx);
                     S.sy[a] = pef_wrap(S.sy[a] + dsy);
                     S.sz[a] = pef_wrap(S.sz[a] + h * pz[j] / lz);
                 }
             }
             k += 1;
-            H = mix_cell(l0x, l0y, er, sr, (double)k * h, rc);
+            H = mix_cell(kc[kL0x], kc[kL0y], kc[kEr], kc[kSr], (double)k * h, rc);
             if (H.ncx < 3 || H.ncy < 3 || H.ncx * H.ncy * ncz > L.cmax) {
                 health = kHealthNonFinite;  // uniform: every thread stops here
                 break;
@@ -861,18 +879,18 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
 #pragma unroll
             for (int j = 0; j < kPefApt; ++j) {
                 const double qx = px[j] + tau * fx[j], qy = py[j] + tau * fy[j];
-                px[j] = (fa * qx + fc * qy) * sc;
-                py[j] = (fd * qy) * sc;
+                px[j] = (kc[kFa] * qx + kc[kFc] * qy) * sc;
+                py[j] = (kc[kFd] * qy) * sc;
                 pz[j] = (pz[j] + tau * fz[j]) * sc;
                 v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
                 v[1] += px[j] * px[j] - py[j] * py[j];
                 v[2] += px[j] * py[j];
             }
             pef_sum<5>(v, S.red);
-            zeta += tau * (v[0] - nh_target) / nh_q;
+            zeta += tau * (v[0] - kc[kTarget]) / kc[kQ];
             cn = v[1] + v[3];
             cxy = v[2] + v[4];
-            vj = (er * cn + sr * cxy) / rn;
+            vj = (kc[kEr] * cn + kc[kSr] * cxy) / kc[kRn];
         } else {
             // K(h/2)
             {
@@ -899,8 +917,8 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
 #pragma unroll
                 for (int j = 0; j < kPefApt; ++j) {
                     v[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                    const double qx = fa * px[j] + fc * py[j];
-                    py[j] = fd * py[j];
+                    const double qx = kc[kFa] * px[j] + kc[kFc] * py[j];
+                    py[j] = kc[kFd] * py[j];
                     px[j] = qx;
                     v[1] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
                 }
@@ -922,7 +940,7 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
                 v[2] += px[j] * py[j];
             }
             pef_sum<5>(v, S.red);
-            const double lam = sqrt(k0 / (0.5 * v[0]));
+            const double lam = sqrt(kc[kK0] / (0.5 * v[0]));
 #pragma unroll
             for (int j = 0; j < kPefApt; ++j) {
                 px[j] *= lam;
@@ -931,14 +949,14 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
             }
             cn = lam * lam * v[1] + v[3];
             cxy = lam * lam * v[2] + v[4];
-            vj = (er * cn + sr * cxy) / rn;
+            vj = (kc[kEr] * cn + kc[kSr] * cxy) / kc[kRn];
         }
         if (t == 0) {
             series[done0 + it + 1] = vj;
             if (xs) {
                 double* row = xs + (size_t)(done0 + it + 1) * kObsCols;
-                row[0] = cn * inv_v;
-                row[1] = cxy * inv_v;
+                row[0] = cn * kc[kInvV];
+                row[1] = cxy * kc[kInvV];
                 for (int c = 2; c < kObsCols; ++c) row[c] = 0.0;
             }
         }

@@ -66,6 +66,8 @@ def _load():
         B = C.POINTER(Box)
         lib.orc_cell_dims.argtypes = [B, I]
         lib.orc_cell_list.argtypes = [B, D, I, I, I]
+        lib.orc_grid_dims.argtypes = [B, C.c_double, I]
+        lib.orc_cell_list_grid.argtypes = [B, I, D, I, I, I]
         lib.orc_forces.argtypes = [B, C.c_double, D, D, D]
         lib.orc_forces_brute.argtypes = [B, C.c_double, D, D, D]
         lib.orc_pairs.argtypes = [B, C.c_double, D, C.c_double, C.c_int64, I, I]
@@ -127,7 +129,8 @@ def _load():
         lib.orc_run_daughters_mix.argtypes = [B, C.c_double, D, D, D, C.c_double, C.c_double,
                                               C.c_double, C.c_int32, I, I, D, D, C.c_int64,
                                               C.c_int32, D, D, D, D]
-        for fn in ("orc_cell_dims", "orc_cell_list", "orc_forces", "orc_forces_brute",
+        for fn in ("orc_cell_dims", "orc_cell_list", "orc_grid_dims", "orc_cell_list_grid",
+                   "orc_forces", "orc_forces_brute",
                    "orc_nh_run", "orc_sllod_run", "orc_mother_sample", "orc_run_daughters",
                    "orc_nh_sllod_run", "orc_mother_sample_zeta", "orc_run_daughters_nh",
                    "orc_observables", "orc_run_daughters_obs", "orc_colour_run",
@@ -163,14 +166,24 @@ def cell_dims(box: Box):
     return d
 
 
-def cell_list(box: Box, r):
-    """(cell_of, order, start) of the canonical cell list (cell id, then atom id)."""
+def grid_dims(box: Box, side: float):
+    """Cells per edge of the grid whose cells are at least `side` wide: floor(L_a / side)."""
+    d = np.zeros(3, np.int32)
+    if _load().orc_grid_dims(C.byref(box), float(side), _ip(d)) != 0:
+        raise ValueError("box too small for a 27-cell grid of that side")
+    return d
+
+
+def cell_list(box: Box, r, dims=None):
+    """(cell_of, order, start) of the canonical cell list (cell id, then atom id), on the
+    grid of side >= rc, or on the given grid dims (e.g. grid_dims(box, rc + skin))."""
     r = _f64(r)
-    d = cell_dims(box)
+    d = cell_dims(box) if dims is None else np.ascontiguousarray(dims, np.int32)
     cell_of = np.zeros(box.n, np.int32)
     order = np.zeros(box.n, np.int32)
     start = np.zeros(int(d.prod()) + 1, np.int32)
-    rc = _load().orc_cell_list(C.byref(box), _dp(r), _ip(cell_of), _ip(order), _ip(start))
+    rc = _load().orc_cell_list_grid(C.byref(box), _ip(d), _dp(r), _ip(cell_of), _ip(order),
+                                    _ip(start))
     if rc != 0:
         raise RuntimeError(f"orc_cell_list failed: {rc}")
     return cell_of, order, start
@@ -189,10 +202,11 @@ def forces(box: Box, r, dxle: float = 0.0, brute: bool = False):
 
 
 def pairs(box: Box, r, dxle: float = 0.0, rlist: float | None = None, brute: bool = False):
-    """Sorted (i, j) pairs, i<j, closer than rlist (default rc)."""
+    """Sorted (i, j) pairs, i<j, closer than rlist (default rc; a larger rlist gives the
+    Verlet list of radius rc + skin)."""
     r = _f64(r)
     rl = box.rc if rlist is None else float(rlist)
-    cap = 64 * box.n
+    cap = max(64, int(8.0 * rl ** 3 * box.n / (box.lx * box.ly * box.lz) + 16)) * box.n
     pi = np.zeros(cap, np.int32)
     pj = np.zeros(cap, np.int32)
     fn = _load().orc_pairs_brute if brute else _load().orc_pairs
@@ -200,6 +214,17 @@ def pairs(box: Box, r, dxle: float = 0.0, rlist: float | None = None, brute: boo
     if cnt < 0:
         raise RuntimeError(f"oracle pairs failed: {cnt}")
     return pi[:cnt].copy(), pj[:cnt].copy()
+
+
+def verlet_lists(box: Box, r, rlist: float, dxle: float = 0.0):
+    """Per-atom Verlet lists of radius rlist: lists[i] = ascending ids j != i closer than rlist
+    (both directions of every pair of `pairs`)."""
+    pi, pj = pairs(box, r, dxle, rlist)
+    lists = [[] for _ in range(box.n)]
+    for i, j in zip(pi.tolist(), pj.tolist()):
+        lists[i].append(j)
+        lists[j].append(i)
+    return [np.array(sorted(x), np.int32) for x in lists]
 
 
 def vpxy(box: Box, r, p, dxle: float = 0.0) -> float:

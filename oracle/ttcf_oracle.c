@@ -64,13 +64,15 @@ static void min_image(const orc_box* b, double dxle, double xi, double yi, doubl
 /* cell list                                                                             */
 /* ------------------------------------------------------------------------------------ */
 
-int32_t orc_cell_dims(const orc_box* b, int32_t dims[3]) {
-    dims[0] = (int32_t)floor(b->lx / b->rc);
-    dims[1] = (int32_t)floor(b->ly / b->rc);
-    dims[2] = (int32_t)floor(b->lz / b->rc);
+int32_t orc_grid_dims(const orc_box* b, double side, int32_t dims[3]) {
+    dims[0] = (int32_t)floor(b->lx / side);
+    dims[1] = (int32_t)floor(b->ly / side);
+    dims[2] = (int32_t)floor(b->lz / side);
     if (dims[0] < 4 || dims[1] < 3 || dims[2] < 3) return -1;
     return 0;
 }
+
+int32_t orc_cell_dims(const orc_box* b, int32_t dims[3]) { return orc_grid_dims(b, b->rc, dims); }
 
 static int32_t cell_coord(double x, int32_t n, double inv_w) {
     int32_t c = (int32_t)floor(x * inv_w);
@@ -83,6 +85,12 @@ int32_t orc_cell_list(const orc_box* b, const double* r, int32_t* cell_of, int32
                       int32_t* start) {
     int32_t d[3];
     if (orc_cell_dims(b, d) != 0) return -1;
+    return orc_cell_list_grid(b, d, r, cell_of, order, start);
+}
+
+int32_t orc_cell_list_grid(const orc_box* b, const int32_t d[3], const double* r,
+                           int32_t* cell_of, int32_t* order, int32_t* start) {
+    if (d[0] < 4 || d[1] < 3 || d[2] < 3) return -1;
     const int32_t n = b->n;
     const int32_t ncell = d[0] * d[1] * d[2];
     const double inv[3] = {(double)d[0] / b->lx, (double)d[1] / b->ly, (double)d[2] / b->lz};
@@ -300,16 +308,19 @@ static void sort_pairs(int64_t cnt, int32_t* pi, int32_t* pj) {
     free(key);
 }
 
+/* Pair list of radius rlist. Up to rc it walks the canonical cell list; a Verlet list of a
+ * larger radius (rc plus a skin) walks a grid whose cells are at least rlist wide, so that the
+ * 27-cell neighbourhood still holds every candidate. */
 int64_t orc_pairs(const orc_box* b, double dxle, const double* r, double rlist, int64_t cap,
                   int32_t* pi, int32_t* pj) {
     int32_t d[3];
-    if (orc_cell_dims(b, d) != 0 || rlist > b->rc) return -2;
+    if (!(rlist > 0.0) || orc_grid_dims(b, rlist > b->rc ? rlist : b->rc, d) != 0) return -2;
     const int32_t n = b->n;
     const int32_t ncell = d[0] * d[1] * d[2];
     int32_t* cell_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
     int32_t* start = (int32_t*)malloc(sizeof(int32_t) * (size_t)(ncell + 1));
-    orc_cell_list(b, r, cell_of, order, start);
+    orc_cell_list_grid(b, d, r, cell_of, order, start);
     pair_ctx c = {b, dxle, r, rlist * rlist, cap, 0, pi, pj};
     for (int32_t i = 0; i < n; ++i)
         for_each_candidate(b, dxle, d, cell_of, order, start, i, rlist, pair_visit, &c);

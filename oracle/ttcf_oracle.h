@@ -34,12 +34,17 @@ typedef struct {
 
 /* Cell grid: n_a = floor(L_a / rc); returns 0 or -1 if any n_a < 3 or n_x < 4. */
 int32_t orc_cell_dims(const orc_box* b, int32_t dims[3]);
+/* Grid of cells at least `side` wide: n_a = floor(L_a / side); same conditions. */
+int32_t orc_grid_dims(const orc_box* b, double side, int32_t dims[3]);
 
 /* Canonical cell list of positions r (SoA, every coordinate in [0, L)):
  * cell_of[i] = cx + nx*(cy + ny*cz) with c_a = floor(r_a * (n_a / L_a)) clamped to [0, n_a-1];
  * order[] lists atom ids sorted by (cell id, atom id); start[c]..start[c+1] is cell c's range. */
 int32_t orc_cell_list(const orc_box* b, const double* r, int32_t* cell_of, int32_t* order,
                       int32_t* start);
+/* The same on a given grid d (c_a = floor(r_a * (d_a / L_a)), clamped). */
+int32_t orc_cell_list_grid(const orc_box* b, const int32_t d[3], const double* r,
+                           int32_t* cell_of, int32_t* order, int32_t* start);
 
 /* Pair forces through the cell list, Lees-Edwards offset dxle.
  * f: SoA forces; out[0] = U (potential energy), out[1] = W_xy = sum_{i<j} x_ij F_y,ij,
@@ -49,9 +54,11 @@ int32_t orc_forces(const orc_box* b, double dxle, const double* r, double* f, do
 /* Same quantities by an O(N^2) sum over explicit periodic / sliding-brick images. */
 int32_t orc_forces_brute(const orc_box* b, double dxle, const double* r, double* f, double* out);
 
-/* Pairs i<j with squared minimum-image separation < rlist^2, found through the cell list
- * (requires rlist <= rc) and returned sorted by (i, j). Returns the count, or -1 if the
- * capacity is too small. */
+/* Pairs i<j with squared minimum-image separation < rlist^2 (FP64, dx*dx + dy*dy + dz*dz
+ * without contraction), returned sorted by (i, j). Up to rlist = rc they are found through the
+ * canonical cell list; a Verlet list of radius rlist > rc (rc plus a skin) through the grid
+ * of cells at least rlist wide. Returns the count, -1 if the capacity is too small, -2 if the
+ * box is too small for that grid. */
 int64_t orc_pairs(const orc_box* b, double dxle, const double* r, double rlist, int64_t cap,
                   int32_t* pi, int32_t* pj);
 /* Same set by testing every pair i<j. */

@@ -130,3 +130,51 @@ def test_cell_list_is_canonical_and_geometric(orc):
     for comp, cc, nn in ((0, cx, d[0]), (1, cy, d[1]), (2, cz, d[2])):
         w = s.box / nn
         assert np.all(rr[comp] >= cc * w - 1e-12) and np.all(rr[comp] < (cc + 1) * w + 1e-12)
+
+
+@pytest.mark.parametrize("n_cells,dx_frac", [(4, 0.0), (4, 0.4), (4, -0.4), (5, 0.999999),
+                                              (6, 0.25)])
+def test_verlet_lists_equal_brute_force(orc, n_cells, dx_frac):
+    """Verlet lists of radius rc + skin (walked through the grid of cells at least that wide)
+    hold exactly the pairs that an all-pairs test over the sliding-brick images finds, at
+    several skins and Lees-Edwards offsets; the per-atom view lists both directions in
+    ascending order."""
+    s, box, r, _ = _liquid(orc, n_cells=n_cells, steps=100, seed=30 + n_cells)
+    dxle = dx_frac * s.box
+    for skin in (0.1, 0.25, 0.37, 0.6):
+        rl = box.rc + skin
+        if s.box / rl < 4:
+            continue
+        a = orc.pairs(box, r, dxle, rl)
+        b = orc.pairs(box, r, dxle, rl, brute=True)
+        assert len(a[0]) > 0
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        lists = orc.verlet_lists(box, r, rl, dxle)
+        assert sum(len(x) for x in lists) == 2 * len(a[0])
+        for i in (0, s.n // 2, s.n - 1):
+            assert np.all(np.diff(lists[i]) > 0) and i not in lists[i]
+            for j in lists[i]:
+                assert i in lists[j]
+        # nested radii: the list of a larger skin contains that of a smaller one
+        inner = set(zip(*orc.pairs(box, r, dxle, box.rc)))
+        assert inner <= set(zip(a[0].tolist(), a[1].tolist()))
+
+
+def test_list_grid_cell_list(orc):
+    """The cell list on the grid of a list radius: floor(L / (rc + skin)) cells per edge,
+    canonical (cell, id) order, every atom inside its cell, and a radius whose grid would have
+    fewer than 4 x 3 x 3 cells is refused."""
+    s, box, r, _ = _liquid(orc, n_cells=5, steps=100, seed=6)
+    rl = box.rc + 0.37
+    d = orc.grid_dims(box, rl)
+    assert np.array_equal(d, np.floor(s.box / rl).astype(np.int32) * np.ones(3, np.int32))
+    cell_of, order, start = orc.cell_list(box, r, d)
+    keys = cell_of[order].astype(np.int64) * s.n + order
+    assert np.all(np.diff(keys) > 0) and start[-1] == s.n
+    rr = r.reshape(3, s.n)
+    w = s.box / d[0]
+    for comp, cc in ((0, cell_of % d[0]), (1, (cell_of // d[0]) % d[1]),
+                     (2, cell_of // (d[0] * d[1]))):
+        assert np.all(rr[comp] >= cc * w - 1e-12) and np.all(rr[comp] < (cc + 1) * w + 1e-12)
+    with pytest.raises(ValueError):
+        orc.grid_dims(box, s.box / 3.5)

@@ -124,3 +124,40 @@ def test_features_flip_sign_under_mappings(orc):
     # slab sums add up to the totals
     assert f0[mom].sum() == pytest.approx(p[:s.n].sum(), abs=1e-10)
     assert f0[st].sum() == pytest.approx(np.dot(p[:s.n], p[s.n:2 * s.n]), rel=1e-12)
+
+
+def test_features_of_a_hand_placed_state():
+    """Atoms placed by hand in known slabs (centres, lower edges, the top edge of the box) with
+    momenta chosen per slab: every feature entry equals its value counted by hand, so a
+    slab-index, offset or component error fails here. Omega(0) = -(V/T) gamma_dot P_xy(0)."""
+    ly = 31.0 * 0.7                    # slab width 0.7
+    box = (5.0, ly, 6.0)
+    V, T, gd = box[0] * box[1] * box[2], 0.9, 3e-3
+    ys, pxs, pys = [], [], []
+    for k in (0, 3, 17, 30):           # slab centres
+        ys.append((k + 0.5) * 0.7)
+        pxs.append(k + 1.0)
+        pys.append(2.0)
+    ys.append(5 * 0.7)                 # exactly on the lower edge of slab 5
+    pxs.append(-4.0)
+    pys.append(0.5)
+    ys.append(np.nextafter(ly, 0.0))   # just below L_y: the last slab
+    pxs.append(10.0)
+    pys.append(-1.0)
+    n = len(ys)
+    r = np.concatenate([np.linspace(0.1, 4.9, n), np.array(ys), np.full(n, 3.0)])
+    p = np.concatenate([np.array(pxs), np.array(pys), np.linspace(-1.0, 1.0, n)])
+    vpxy0 = 12.5
+    f = M.features(r, p, box, vpxy0, gd, T, V)
+    assert f.shape == (64,)
+    assert f[0] == vpxy0 / V
+    assert f[1] == pytest.approx(-(V / T) * gd * (vpxy0 / V), rel=1e-15)
+    mom = np.zeros(31)
+    st = np.zeros(31)
+    mom[0], st[0] = 1.0, 2.0
+    mom[3], st[3] = 4.0, 8.0
+    mom[17], st[17] = 18.0, 36.0
+    mom[30], st[30] = 31.0 + 10.0, 62.0 - 10.0
+    mom[5], st[5] = -4.0, -2.0
+    assert np.array_equal(f[2:33], mom)
+    assert np.array_equal(f[33:64], st)

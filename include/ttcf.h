@@ -87,7 +87,7 @@ typedef struct {
     double  dt;            /* time step                                                         */
     double  r_cut;         /* cutoff; pairs interact when r^2 < r_cut^2 (WCA: 2^(1/6))          */
     double  c_attr;        /* attraction factor c (WCA: 1)                                      */
-    double  u_shift;       /* energy shift making phi(r_cut) = 0 (WCA: 1)                       */
+    double  u_shift;       /* energy shift (NaN: the library's, making phi(r_cut) = 0; WCA: 1)  */
     double  nh_tau;        /* mother Nose-Hoover time constant: Q = (3N-3) T nh_tau^2           */
     int32_t precision;     /* TTCF_PREC_*                                                       */
     int32_t block_threads; /* threads per workgroup for this system (0: chosen by the library)  */
@@ -337,6 +337,14 @@ int32_t ttcf_daughter_health(ttcf_ctx* ctx, int64_t daughter, int32_t* health);
 /* Failure injection: writes NaN into momentum component 0 of atom 0 of a live daughter. */
 int32_t ttcf_debug_poison(ttcf_ctx* ctx, int64_t daughter);
 
+/* Grids of a system (no device work): cells[3] (may be NULL) the canonical cell grid
+ * floor(L_a / r_cut) of ttcf_debug_cell_list and the cell form; list_cells[3] (may be NULL)
+ * the list grid floor(L_a / (r_cut + skin)) of the pair-list form for skin `skin` (<= 0:
+ * automatic), all zero when the box is too small for it; *list_skin (may be NULL) the skin
+ * used (the automatic one, or `skin`). TTCF_EINVAL for a system the library refuses. */
+int32_t ttcf_cell_grid(const ttcf_system* sys, double skin, int32_t* cells, int32_t* list_cells,
+                       double* list_skin);
+
 /* Stateless kernels on given host positions (SoA, inside the box), run on `stream`:
  * the canonical cell list (cell_of[n], order[n], start[n_cells+1]; cell id
  * cx + nx (cy + ny cz), c_a = floor(r_a * (n_a / L_a)), n_a = floor(L_a / r_cut)) ... */
@@ -351,19 +359,40 @@ int32_t ttcf_debug_pairs(const ttcf_system* sys, double dxle, const double* r, d
  * computed in sys->precision. */
 int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, double* f,
                           double* out, void* stream);
+/* The pair-list form's own list build and force pass (the device functions ttcf_step runs)
+ * on given host positions r (SoA, inside the box), at the Lees-Edwards offset of strain step
+ * kstep at shear rate gamma_dot (fmod(gamma_dot L_y (kstep dt), L_x), Example 1's sliding
+ * brick), list skin `skin` (<= 0: automatic) and pair capacity kcap per atom (<= 0:
+ * automatic), FP32 forces whatever sys->precision says. Writes:
+ *   dims[3] (may be NULL): the list grid lc_a = floor(L_a / (r_cut + skin));
+ *   cell_of[n]: list-grid cell of every atom, cx + lc_x (cy + lc_y cz), c_a = floor(r_a (lc_a /
+ *     L_a)) clamped; order[n]: atom ids in the build's order (by cell, then id);
+ *     start[cells + 1]: each cell's first position in that order;
+ *   pi, pj (capacity cap): the listed pairs as atom ids, pi < pj, sorted; *count their number
+ *     (-1 when cap is too small) -- the pairs whose FP32 fixed-point separation is below
+ *     r_cut + skin;
+ *   f[3n]: the forces the integrator uses; out[0] = W_xy; out[1] = the offset used;
+ *   out[2] = r_cut + skin; out[3] = 1 if a pair came closer than the fixed-point force range
+ *   allows.
+ * Returns TTCF_EUNSTABLE (outputs written, the pair list incomplete) when the capacity
+ * overflowed; TTCF_EINVAL for more than 4096 atoms or a box too small for the list grid. */
+int32_t ttcf_debug_pair_form(const ttcf_system* sys, double gamma_dot, int64_t kstep, double skin,
+                             int32_t kcap, const double* r, int32_t* dims, int32_t* cell_of,
+                             int32_t* order, int32_t* start, int64_t cap, int32_t* pi, int32_t* pj,
+                             int64_t* count, double* f, double* out, void* stream);
 
 /* Shape of the daughter step kernel (the knobs a tuner searches). variant: 0 automatic,
- * 1 cell list rebuilt every step (FP64 or FP32 forces), 2 neighbour lists of radius
- * r_cut + skin rebuilt when needed (FP32 forces only; the lists sit in LDS where they fit,
- * else in per-workgroup global scratch, as for N = 4000), 3 the same with the lists always
- * in global scratch (for comparison: results equal variant 2's bit for bit); threads:
- * workgroup size (0: the
- * system's block_threads, else the library's choice: 512 for the list form up to 2048 atoms);
- * skin <= 0 selects the automatic skin (the list-cell grid of a 0.25 sigma skin, with the skin
- * widened to fill those cells); kmax <= 0 selects 24 neighbours per atom, at most 32 (the
- * force loop visits the entries within r_cut + 0.1 sigma, kept as a 32-bit mask per atom and
- * refreshed from the lists under the same displacement bound as the lists). Affects the
- * following ttcf_step calls; results do not depend on the skin (lists are sorted, and pairs
+ * 1 cell list rebuilt every step (FP64 or FP32 forces), 2 pair list of radius r_cut + skin
+ * rebuilt when needed (FP32 forces, at most 4096 atoms: every pair within the radius stored
+ * once in per-workgroup global scratch, four atoms per thread, pair forces summed in 32-bit
+ * fixed point by LDS integer atomics), 3 the same as 2; threads: workgroup size of the cell
+ * form (0: the system's block_threads, else the library's choice; the pair form always uses
+ * 64 ceil(n / 256) threads per daughter); skin <= 0 selects the automatic skin (the list-cell
+ * grid of a 0.2 sigma skin, with the skin widened to fill those cells); kmax: pair capacity
+ * per atom of the pair form, at most 64 (<= 0: 1.5 times half the ideal-gas count within the
+ * list radius, plus two); a daughter whose list outgrows it is marked unhealthy (list
+ * overflow). Affects the following ttcf_step calls; results do not depend on the skin,
+ * capacity or rebuild schedule (integer force sums do not depend on their order, and pairs
  * beyond r_cut contribute nothing). */
 int32_t ttcf_set_step_shape(ttcf_ctx* ctx, int32_t variant, int32_t threads, double skin,
                             int32_t kmax);

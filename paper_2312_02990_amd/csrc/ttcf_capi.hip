@@ -104,13 +104,11 @@ struct Batch {
 };
 
 struct StepShape {              // knobs of the daughter step kernel (0: automatic)
-    int32_t variant = 0;        // 1 cell form, 2 neighbour-list form
+    int32_t variant = 0;        // 1 cell form, 2 pair-list form (3: the same as 2)
     int32_t threads = 0;
-    int32_t kmax = 0;           // list capacity per atom (0: kDefaultKmax)
+    int32_t kmax = 0;           // pair capacity per atom (0: auto_pair_cap)
     double skin = 0.0;          // list skin (<= 0: auto_skin)
 };
-
-constexpr int32_t kDefaultKmax = 24;
 
 struct TunedShape {             // one autotuner result
     std::string arch;           // device architecture name
@@ -178,8 +176,8 @@ struct ttcf_ctx {
     std::vector<char> row_x;
     // external field of each accumulated row (kFieldShear or kFieldColour)
     std::vector<int32_t> row_field;
-    // list-form scratch for systems whose lists live in global memory
-    uint16_t* nl_scratch = nullptr;
+    // pair-list form: the pair lists of the persistent workgroups (global scratch)
+    uint32_t* nl_scratch = nullptr;
     size_t nl_scratch_bytes = 0;
     // learned control variate
     int32_t cv_out = 0;          // outputs (time points t_1..t_nout)
@@ -259,7 +257,13 @@ int32_t build_sysdev(const ttcf_system* s, SysDev* d, std::string* why) {
     d->rc = s->r_cut;
     d->rc2 = s->r_cut * s->r_cut;
     d->c_attr = s->c_attr;
-    d->u_shift = s->u_shift;
+    // NaN: the shift that makes phi vanish at the cutoff (Example 1: continuity at r_c)
+    if (std::isnan(s->u_shift)) {
+        const double s6 = 1.0 / std::pow(s->r_cut, 6.0);
+        d->u_shift = -4.0 * (s6 * s6 - s->c_attr * s6);
+    } else {
+        d->u_shift = s->u_shift;
+    }
     d->dt = s->dt;
     d->volume = s->box[0] * s->box[1] * s->box[2];
     for (int a = 0; a < 3; ++a) {
@@ -270,19 +274,36 @@ int32_t build_sysdev(const ttcf_system* s, SysDev* d, std::string* why) {
     return TTCF_OK;
 }
 
-// List-build grid of the neighbour-list form for a given skin; false if the box is too
-// small for a 27-cell stencil of that reach.
-// Automatic skin: the list grid of a 0.25 sigma skin, with the skin widened to fill its
-// cells (cell width minus the cutoff, in the narrowest direction). Fewer rebuilds for the
-// same candidate count per rebuild.
+// List-build grid of the pair-list form for a given skin; false if the box is too small for
+// a 27-cell stencil of that reach.
+// Automatic skin: the list grid of a 0.2 sigma skin, with the skin widened to fill its cells
+// (cell width minus the cutoff, in the narrowest direction). Fewer rebuilds for the same
+// candidate count per rebuild. (At N = 2048, rho = 0.8442: 10 cells a side, skin 0.22.)
 double auto_skin(const SysDev& d) {
-    const double base = d.rc + 0.25;
+    const double base = d.rc + 0.2;
     double w = d.box[0];
     for (int a = 0; a < 3; ++a) {
         const double n = std::floor(d.box[a] / base);
         if (n >= 1.0) w = std::min(w, d.box[a] / n);
     }
-    return std::max(0.25, w * (1.0 - 1e-9) - d.rc);
+    return std::max(0.2, w * (1.0 - 1e-9) - d.rc);
+}
+
+// Separation below which a pair's force exceeds kPairForceGuard (bisection on the repulsive
+// branch of 24 (2 r^-13 - c r^-7), which falls monotonically up to its zero (2/c)^(1/6)).
+double guard_radius(const SysDev& d) {
+    auto force = [&](double r) {
+        const double s = 1.0 / (r * r), s3 = s * s * s;
+        return 24.0 * s3 * (2.0 * s3 - d.c_attr) / r;
+    };
+    double lo = 0.01, hi = d.c_attr > 0.0 ? std::pow(2.0 / d.c_attr, 1.0 / 6.0) : d.rc;
+    hi = std::min(hi, d.rc);
+    if (force(hi) >= kPairForceGuard) return hi;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        (force(mid) > kPairForceGuard ? lo : hi) = mid;
+    }
+    return lo;
 }
 
 bool set_list_grid(SysDev* d, double skin) {
@@ -295,10 +316,19 @@ bool set_list_grid(SysDev* d, double skin) {
         d->l_inv_w[a] = (double)d->lc[a] / d->box[a];
     }
     d->rl2_f = (float)(reach * reach);
-    d->skin_in = std::min(skin, kInnerSkin);
-    d->ri2_f = (float)((d->rc + d->skin_in) * (d->rc + d->skin_in));
+    const double rg = guard_radius(*d);
+    d->rg2_f = (float)(rg * rg);
     return d->lc[0] >= 4 && d->lc[1] >= 3 && d->lc[2] >= 3 && d->lc[0] <= kMaxCells1D &&
            d->lc[1] <= kMaxCells1D && d->lc[2] <= kMaxCells1D;
+}
+
+// Default pair capacity per atom of the pair-list form: half the ideal-gas count within the
+// list radius, with half again as margin (a wave's segment covers 256 atoms, so its total
+// count varies little), plus two.
+int32_t auto_pair_cap(const SysDev& d) {
+    const double reach = d.rc + d.skin;
+    const double half = 2.0943951023931953 * reach * reach * reach * (d.n / d.volume);
+    return std::min<int32_t>(kPairMaxCap, (int32_t)std::ceil(1.5 * half + 2.0));
 }
 
 int32_t check_shape(ttcf_ctx* c, const ttcf_system* s, const SysDev& d, int* threads, int* apt) {
@@ -1017,29 +1047,33 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
 // workgroup size; kmax is the list capacity of the neighbour-list form.
 // block_explicit: some member's system fixes its workgroup size (block_threads > 0).
 int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, bool block_explicit,
-                   int variant, int precision, int32_t n_steps, int threads_req, BatchLaunch* L,
-                   bool global_lists = false) {
+                   int variant, int precision, int32_t n_steps, int threads_req, BatchLaunch* L) {
     int nmax = 0, cmax = 0, lcmax = 0, threads = 0, kmax = 0;
     size_t nl_lds = 0;
-    bool explicit_threads = threads_req > 0 || block_explicit;
+    int64_t pair_stride = 0;
+    const bool nlf = variant == kVariantNeighbourList;
     for (const DaughterDesc* dp : group) {
         const DaughterDesc& d = *dp;
         kmax = std::max(kmax, d.kmax);
         nmax = std::max(nmax, d.sys.n);
         cmax = std::max(cmax, d.sys.nc[0] * d.sys.nc[1] * d.sys.nc[2]);
         lcmax = std::max(lcmax, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2]);
-        if (variant == kVariantNeighbourList)
-            nl_lds = std::max(nl_lds, lds_bytes_nl(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2],
-                                                   d.kmax, global_lists));
-        threads = std::max(threads, d.block);
+        if (nlf) {
+            nl_lds = std::max(nl_lds, lds_bytes_pairs(d.sys.n, d.sys.lc[0] * d.sys.lc[1] * d.sys.lc[2]));
+            threads = std::max(threads, pair_job_threads(d.sys.n));
+        } else {
+            threads = std::max(threads, d.block);
+        }
     }
-    if (threads_req > 0) threads = threads_req;
-    // 512 threads with up to 4 atoms each keep the list form free of register spills
-    // (at 1024 threads a lane has 128 registers and spills); measured faster at N = 2048
-    if (variant == kVariantNeighbourList && !explicit_threads && nmax <= 4 * 512)
-        threads = std::min(512, pick_threads(nmax, 0));
-    const int apt = pick_apt(nmax, threads);
+    // the pair-list form: four atoms per thread of each job, the workgroup as large as the
+    // largest job needs (the thread count of a job does not depend on the launch)
+    if (!nlf && threads_req > 0) threads = threads_req;
+    (void)block_explicit;
+    const int apt = nlf ? pair_job_apt(nmax) : pick_apt(nmax, threads);
     if (apt < 0) return fail(c, TTCF_EINVAL, "batch needs more than 4 atoms per thread");
+    if (nlf)
+        for (const DaughterDesc* dp : group)
+            pair_stride = std::max<int64_t>(pair_stride, pair_words(dp->sys.n, dp->kmax, apt));
     *L = BatchLaunch{};
     L->descs = c->d_descs;
     L->n_jobs = (int32_t)group.size();
@@ -1060,19 +1094,13 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
     if (L->field && L->obs)
         return fail(c, TTCF_EINVAL, "colour-field daughters cannot share a step call with "
                                     "daughters recording the extra observables");
-    if (global_lists) {
-        if (L->obs || L->field)
-            return fail(c, TTCF_EINVAL, "systems whose lists do not fit in LDS run shear "
-                                        "daughters recording P_xy only");
-        L->global_lists = 1;
-        for (const DaughterDesc* dp : group)
-            L->nbr_stride = std::max<int64_t>(L->nbr_stride, (int64_t)(dp->kmax + 1) * dp->sys.n);
-    }
-    L->lds_bytes = variant == kVariantNeighbourList ? nl_lds
-                                                    : lds_bytes_for(nmax, cmax, threads, precision);
+    L->pair_stride = pair_stride;
+    L->lds_bytes = nlf ? nl_lds : lds_bytes_for(nmax, cmax, threads, precision);
     if (L->lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
     const int per_cu_lds = (int)(c->max_lds / L->lds_bytes);
-    const int per_cu_waves = 32 / (threads / 64);  // 8 waves per SIMD, 4 SIMDs
+    // the pair-list kernel is compiled for 512-thread workgroups (256 registers: 2 waves per
+    // SIMD); the cell form allows 8 waves per SIMD
+    const int per_cu_waves = (nlf ? 8 : 32) / (threads / 64);
     const int per_cu = std::max(1, std::min(per_cu_lds, per_cu_waves));
     L->grid = std::min<int>(L->n_jobs, per_cu * c->num_cu);
     return TTCF_OK;
@@ -1101,39 +1129,34 @@ StepShape resolve_shape(const ttcf_ctx* c, const SysDev& d, int precision, const
     } else if (const TunedShape* t = find_tuned(c, d, precision)) {
         e = t->shape;
     }
-    if (e.kmax <= 0) e.kmax = kDefaultKmax;
     return e;
 }
 
-// Writes the list grid and capacity of shape e into a descriptor; *nl tells whether it runs in
-// the neighbour-list form (FP32 forces, not forced to cells), with its lists in LDS when they
-// fit there (and variant 3 does not ask otherwise), else in global scratch
-// (d->global_lists) when the rest of its LDS does.
+// Writes the list grid and pair capacity of shape e into a descriptor; *nl tells whether it
+// runs in the pair-list form (FP32 forces, at most kPairMaxAtoms atoms, not forced to cells,
+// and its LDS fits).
 int32_t apply_shape(ttcf_ctx* c, const StepShape& e, int precision, DaughterDesc* d, bool* nl) {
-    d->kmax = e.kmax;
-    d->global_lists = 0;
     *nl = false;
-    if (precision == TTCF_PREC_FP32_FORCES && e.variant != 1 && e.kmax <= kNlMaxKmax &&
-        set_list_grid(&d->sys, e.skin)) {
+    d->kmax = 0;
+    if (precision == TTCF_PREC_FP32_FORCES && e.variant != 1 && d->sys.n <= kPairMaxAtoms &&
+        e.kmax <= kPairMaxCap && set_list_grid(&d->sys, e.skin)) {
         const int cells = d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2];
-        if (e.variant != 3 && lds_bytes_nl(d->sys.n, cells, e.kmax) <= c->max_lds) {
+        if (lds_bytes_pairs(d->sys.n, cells) <= c->max_lds) {
             *nl = true;
-        } else if (lds_bytes_nl(d->sys.n, cells, e.kmax, true) <= c->max_lds) {
-            *nl = true;
-            d->global_lists = 1;
+            d->kmax = e.kmax > 0 ? e.kmax : auto_pair_cap(d->sys);
         }
     }
     if ((e.variant == 2 || e.variant == 3) && !*nl)
-        return fail(c, TTCF_EINVAL, "neighbour-list form does not fit this batch");
+        return fail(c, TTCF_EINVAL, "pair-list form does not fit this batch");
     return TTCF_OK;
 }
 
-// The context's global list scratch, grown (after the stream drains) to `bytes`.
+// The context's pair-list scratch, grown (after the stream drains) to `bytes`.
 int32_t ensure_nl_scratch(ttcf_ctx* c, size_t bytes) {
     if (bytes <= c->nl_scratch_bytes) return TTCF_OK;
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     dev_free(c->nl_scratch);
-    c->nl_scratch = (uint16_t*)dev_alloc(bytes, c->stream);
+    c->nl_scratch = (uint32_t*)dev_alloc(bytes, c->stream);
     c->nl_scratch_bytes = c->nl_scratch ? bytes : 0;
     if (!c->nl_scratch) return fail(c, TTCF_ENOMEM, "list scratch allocation failed");
     return TTCF_OK;
@@ -1147,10 +1170,10 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
     if (c->descs.empty() || n_steps == 0) return TTCF_OK;
     int32_t rc = sync_descs(c);
     if (rc != TTCF_OK) return rc;
-    // daughters still to run; each goes to the neighbour-list form when it may (lists in LDS
-    // when they fit, else in global scratch), else to the cell form; each (form, thermostat)
-    // is one persistent launch, largest systems first. groups[2 form + thermo], form 0 lists,
-    // 1 cells, 2 lists in global scratch
+    // daughters still to run; each goes to the pair-list form when it may, else to the cell
+    // form; each (form, thermostat) is one persistent launch, largest systems first.
+    // groups[2 form + thermo], form 0 pair lists (4 atoms per thread), 1 cells, 2 pair lists
+    // (8 atoms per thread: more than 2048 atoms)
     std::vector<int32_t> groups[6];
     // planar-elongation (0, 1) and mixed-flow (2, 3) daughters by thermostat: own kernels, FP64
     std::vector<int32_t> pef[4];
@@ -1179,7 +1202,7 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         if (d.field != kFieldShear && !nl)
             return fail(c, TTCF_EINVAL, "colour-field daughters need the neighbour-list form, "
                                         "and this system runs in cells");
-        const int form = !nl ? 1 : (d.global_lists ? 2 : 0);
+        const int form = !nl ? 1 : (pair_job_apt(d.sys.n) == 4 ? 0 : 2);
         groups[2 * form + (d.thermo ? 1 : 0)].push_back((int32_t)i);
     }
     const bool any_nl = !groups[0].empty() || !groups[1].empty() || !groups[4].empty() ||
@@ -1228,12 +1251,12 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         }
         BatchLaunch L{};
         rc = plan_group(c, ds, block_explicit, form == 1 ? kVariantCells : kVariantNeighbourList,
-                        precision, n_steps, eff[group[0]].threads, &L, form == 2);
+                        precision, n_steps, eff[group[0]].threads, &L);
         if (rc != TTCF_OK) return rc;
-        if (form == 2) {
-            rc = ensure_nl_scratch(c, sizeof(uint16_t) * (size_t)L.grid * (size_t)L.nbr_stride);
+        if (form != 1) {
+            rc = ensure_nl_scratch(c, sizeof(uint32_t) * (size_t)L.grid * (size_t)L.pair_stride);
             if (rc != TTCF_OK) return rc;
-            L.nbr = c->nl_scratch;
+            L.pairs = c->nl_scratch;
         }
         L.order = c->d_order + offset;
         offset += group.size();
@@ -1325,8 +1348,8 @@ int32_t ttcf_step(ttcf_ctx* c, int32_t n_steps) {
 int32_t ttcf_set_step_shape(ttcf_ctx* c, int32_t variant, int32_t threads, double skin,
                             int32_t kmax) {
     if (!c || variant < 0 || variant > 3 || threads < 0 || threads > kMaxThreads ||
-        (threads > 0 && threads % 64 != 0) || kmax > kNlMaxKmax)
-        return fail(c, TTCF_EINVAL, "bad step shape (kmax is at most 32)");
+        (threads > 0 && threads % 64 != 0) || kmax > kPairMaxCap)
+        return fail(c, TTCF_EINVAL, "bad step shape (kmax is at most 64)");
     c->shape.variant = variant;
     c->shape.threads = threads;
     c->shape.skin = skin > 0.0 ? skin : 0.0;
@@ -1346,8 +1369,9 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
     if (n_states == 0 || n_states > m.n_states) n_states = m.n_states;
     const SysDev& d = m.dev;
     const int precision = m.sys.precision;
-    // candidate shapes: each form at 256, 512 and 1024 threads; the list form also at the
-    // skins that fill list cells one coarser, equal to and one finer than the automatic grid
+    // candidate shapes: the cell form at 256, 512 and 1024 threads; the pair-list form (four
+    // atoms per thread) at the skins that fill list cells one coarser, equal to and one finer
+    // than the automatic grid
     std::vector<StepShape> cand;
     for (int t : {256, 512, 1024}) {
         if (pick_apt(d.n, t) < 0) continue;
@@ -1357,7 +1381,7 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
     std::vector<double> skins;
     if (precision == TTCF_PREC_FP32_FORCES) {
         const double lmin = std::min(d.box[0], std::min(d.box[1], d.box[2]));
-        const int n0 = (int)std::floor(lmin / (d.rc + 0.25));
+        const int n0 = (int)std::floor(lmin / (d.rc + 0.2));
         for (int lc = n0 - 1; lc <= n0 + 1; ++lc) {
             if (lc < 3) continue;
             const double skin = lmin / lc * (1.0 - 1e-9) - d.rc;
@@ -1365,16 +1389,13 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
             if (skin >= 0.1 && set_list_grid(&probe, skin)) skins.push_back(skin);
         }
     }
-    // expected list length at each skin sets the first capacity tried; a capacity that
-    // overflows on the probe is raised and the shape timed again
-    const double rho = d.n / d.volume;
-    for (double skin : skins)
-        for (int t : {256, 512, 1024}) {
-            if (pick_apt(d.n, t) < 0) continue;
-            const double reach = d.rc + skin;
-            const double mean = 4.18879020478639 * reach * reach * reach * rho;
-            int k0 = std::max(12, ((int)std::ceil(1.6 * mean) + 3) / 4 * 4);
-            if (k0 <= kNlMaxKmax) cand.push_back(StepShape{2, t, k0, skin});
+    // the automatic capacity at each skin is tried first; a capacity that overflows on the
+    // probe is raised and the shape timed again
+    if (d.n <= kPairMaxAtoms)
+        for (double skin : skins) {
+            SysDev probe = d;
+            set_list_grid(&probe, skin);
+            cand.push_back(StepShape{2, pair_job_threads(d.n), auto_pair_cap(probe), skin});
         }
     int32_t rc = sync_descs(c);
     if (rc != TTCF_OK) return rc;
@@ -1388,8 +1409,7 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
             if (sh.variant == 2) {
                 SysDev probe = d;
                 set_list_grid(&probe, sh.skin);
-                if (lds_bytes_nl(d.n, probe.lc[0] * probe.lc[1] * probe.lc[2], sh.kmax, true) >
-                    c->max_lds)
+                if (lds_bytes_pairs(d.n, probe.lc[0] * probe.lc[1] * probe.lc[2]) > c->max_lds)
                     break;
             }
             // enough copies of the probe states to give every compute unit four daughters,
@@ -1442,8 +1462,8 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
             if (health & ~kHealthListOverflow)
                 return fail(c, TTCF_EDEVICE, "probe daughters failed the health check");
             if (health & kHealthListOverflow) {
-                if (sh.kmax >= kNlMaxKmax) break;
-                sh.kmax = std::min(kNlMaxKmax, sh.kmax + 8);
+                if (sh.kmax >= kPairMaxCap) break;
+                sh.kmax = std::min(kPairMaxCap, sh.kmax + 4);
                 continue;
             }
             ++timed;
@@ -1456,16 +1476,8 @@ int32_t ttcf_autotune(ttcf_ctx* c, int32_t mother, int32_t n_states, double gamm
         }
     }
     if (timed == 0) return fail(c, TTCF_EINVAL, "no step shape fits this system");
-    // a margin over the largest list the probe needed, where the LDS allows
-    if (best_shape.variant == 2) {
-        SysDev probe = d;
-        set_list_grid(&probe, best_shape.skin);
-        const int lcn = probe.lc[0] * probe.lc[1] * probe.lc[2];
-        const int k = std::min(kNlMaxKmax, best_shape.kmax + 4);
-        // the margin where the lists keep their place (LDS or global)
-        const bool in_lds = lds_bytes_nl(d.n, lcn, best_shape.kmax) <= c->max_lds;
-        if (!in_lds || lds_bytes_nl(d.n, lcn, k) <= c->max_lds) best_shape.kmax = k;
-    }
+    // a margin over the capacity the probe needed
+    if (best_shape.variant == 2) best_shape.kmax = std::min(kPairMaxCap, best_shape.kmax + 2);
     TunedShape t;
     t.arch = c->arch;
     t.n = d.n;
@@ -1571,7 +1583,7 @@ int32_t ttcf_autotune_import(ttcf_ctx* c, const char* text) {
         t.ms_per_step = v[8];
         if (t.shape.variant < 1 || t.shape.variant > 2 || t.shape.threads % 64 != 0 ||
             t.shape.threads < 64 || t.shape.threads > kMaxThreads || t.shape.kmax < 0 ||
-            t.shape.kmax > (t.shape.variant == 2 ? kNlMaxKmax : 255) || !(t.shape.skin >= 0.0) ||
+            t.shape.kmax > (t.shape.variant == 2 ? kPairMaxCap : 255) || !(t.shape.skin >= 0.0) ||
             t.n < 2)
             return fail(c, TTCF_EINVAL, "autotune cache: shape out of range");
         got.push_back(t);
@@ -2104,14 +2116,13 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     std::vector<const DaughterDesc*> hp;
     for (auto& d : hd) hp.push_back(&d);
     BatchLaunch B{};
-    const bool gl = nl && !hd.empty() && hd[0].global_lists;
     rc = plan_group(c, hp, m.sys.block_threads > 0, nl ? kVariantNeighbourList : kVariantCells,
-                    precision, gd->n_steps, shape.threads, &B, gl);
+                    precision, gd->n_steps, shape.threads, &B);
     if (rc != TTCF_OK) return bail(rc, c->err);
-    if (gl) {
-        // the graph owns the list scratch its replays use
-        B.nbr = (uint16_t*)g->get(sizeof(uint16_t) * (size_t)B.grid * (size_t)B.nbr_stride);
-        if (!B.nbr) return bail(TTCF_ENOMEM, "list scratch allocation failed");
+    if (nl) {
+        // the graph owns the pair-list scratch its replays use
+        B.pairs = (uint32_t*)g->get(sizeof(uint32_t) * (size_t)B.grid * (size_t)B.pair_stride);
+        if (!B.pairs) return bail(TTCF_ENOMEM, "pair-list scratch allocation failed");
     }
     B.descs = descs;
     B.order = order;
@@ -3282,6 +3293,119 @@ int32_t ttcf_debug_forces(const ttcf_system* sys, double dxle, const double* r, 
     dev_free(buf);
     dev_free(d_r);
     return e == hipSuccess ? TTCF_OK : TTCF_EDEVICE;
+}
+
+int32_t ttcf_debug_pair_form(const ttcf_system* sys, double gamma_dot, int64_t kstep, double skin,
+                             int32_t kcap, const double* r, int32_t* dims, int32_t* cell_of,
+                             int32_t* order, int32_t* start, int64_t cap, int32_t* pi, int32_t* pj,
+                             int64_t* count, double* f, double* out, void* stream) {
+    if (!sys || !r || !cell_of || !order || !start || !pi || !pj || !count || !f || !out ||
+        cap < 0 || kcap > kPairMaxCap || !std::isfinite(gamma_dot) || !std::isfinite(skin))
+        return TTCF_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    SysDev S{};
+    std::string why;
+    int32_t rc = build_sysdev(sys, &S, &why);
+    if (rc != TTCF_OK) return rc;
+    if (S.n > kPairMaxAtoms || !set_list_grid(&S, skin)) return TTCF_EINVAL;
+    if (kcap <= 0) kcap = auto_pair_cap(S);
+    const int C = S.lc[0] * S.lc[1] * S.lc[2];
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return TTCF_EDEVICE;
+    if (lds_bytes_pairs(S.n, C) > prop.sharedMemPerBlock) return TTCF_EINVAL;
+    for (int k = 0; k < 3 * S.n; ++k)
+        if (!(r[k] >= 0.0 && r[k] < S.box[k / S.n])) return TTCF_EINVAL;
+    const int n = S.n;
+    const int waves = pair_job_threads(n) / 64;
+    const int apt = pair_job_apt(n);
+    const int64_t words = pair_words(n, kcap, apt);
+    // device layout: r (3n doubles), f (3n), out (4); pairs (words), seg counts (waves),
+    // cell_of, rank_of (n each), start (C + 1)
+    const size_t dbytes = sizeof(double) * (6 * (size_t)n + 4);
+    const size_t ibytes = sizeof(uint32_t) * ((size_t)words + waves + 2 * (size_t)n + C + 1);
+    char* buf = (char*)dev_alloc(dbytes + ibytes, s);
+    if (!buf) return TTCF_ENOMEM;
+    double* d_r = (double*)buf;
+    double* d_f = d_r + 3 * n;
+    double* d_out = d_f + 3 * n;
+    uint32_t* d_pairs = (uint32_t*)(buf + dbytes);
+    int32_t* d_seg = (int32_t*)(d_pairs + words);
+    int32_t* d_cell = d_seg + waves;
+    int32_t* d_rank = d_cell + n;
+    int32_t* d_start = d_rank + n;
+    std::vector<uint32_t> words_h((size_t)words);
+    std::vector<int32_t> seg(waves), rank(n);
+    hipError_t e = hipMemcpyAsync(d_r, r, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = launch_debug_pair_form(S, gamma_dot, kstep, d_r, kcap, d_pairs, d_seg, d_cell, d_rank,
+                                   d_start, d_f, d_out, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, d_f, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s);
+    double o3[3] = {0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(o3, d_out, sizeof(o3), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(words_h.data(), d_pairs, sizeof(uint32_t) * words, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(seg.data(), d_seg, sizeof(int32_t) * waves, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(cell_of, d_cell, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(rank.data(), d_rank, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(start, d_start, sizeof(int32_t) * (C + 1), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(buf);
+    if (e != hipSuccess) return TTCF_EDEVICE;
+    // ranks to atom ids: the build's order
+    std::vector<int32_t> atom_of(n, -1);
+    for (int a = 0; a < n; ++a) {
+        if (rank[a] < 0 || rank[a] >= n || atom_of[rank[a]] != -1) return TTCF_EDEVICE;
+        atom_of[rank[a]] = a;
+    }
+    for (int q = 0; q < n; ++q) order[q] = atom_of[q];
+    const int64_t seg_cap = (int64_t)kcap * 64 * apt;
+    bool overflow = false;
+    std::vector<int64_t> key;
+    for (int w = 0; w < waves; ++w) {
+        if (seg[w] > seg_cap) overflow = true;
+        const int64_t used = std::min<int64_t>(seg[w], seg_cap);
+        for (int64_t q = 0; q < used; ++q) {
+            const uint32_t word = words_h[(size_t)(w * seg_cap + q)];
+            const int a = atom_of[word & 0x3FFFu], b = atom_of[(word >> 14) & 0x3FFFu];
+            const int i = std::min(a, b), j = std::max(a, b);
+            key.push_back(((int64_t)i << 32) | (int64_t)j);
+        }
+    }
+    std::sort(key.begin(), key.end());
+    if ((int64_t)key.size() <= cap)
+        for (size_t q = 0; q < key.size(); ++q) {
+            pi[q] = (int32_t)(key[q] >> 32);
+            pj[q] = (int32_t)(key[q] & 0xffffffff);
+        }
+    *count = (int64_t)key.size() <= cap ? (int64_t)key.size() : -1;
+    out[0] = o3[0];
+    out[1] = o3[2];
+    out[2] = S.rc + S.skin;
+    out[3] = o3[1];
+    if (dims) {
+        dims[0] = S.lc[0];
+        dims[1] = S.lc[1];
+        dims[2] = S.lc[2];
+    }
+    return overflow ? TTCF_EUNSTABLE : TTCF_OK;
+}
+
+int32_t ttcf_cell_grid(const ttcf_system* sys, double skin, int32_t* cells, int32_t* list_cells,
+                       double* list_skin) {
+    if (!sys || !std::isfinite(skin)) return TTCF_EINVAL;
+    SysDev S{};
+    std::string why;
+    int32_t rc = build_sysdev(sys, &S, &why);
+    if (rc != TTCF_OK) return rc;
+    if (cells)
+        for (int a = 0; a < 3; ++a) cells[a] = S.nc[a];
+    const bool ok = set_list_grid(&S, skin);
+    if (list_cells)
+        for (int a = 0; a < 3; ++a) list_cells[a] = ok ? S.lc[a] : 0;
+    if (list_skin) *list_skin = ok ? S.skin : 0.0;
+    return TTCF_OK;
 }
 
 }  // extern "C"

@@ -36,11 +36,9 @@ struct SysDev {
     float fix_unit[3];     // L_a / 2^32
     float rc2_f;           // cutoff^2 and list radius^2 in FP32
     float rl2_f;
-    // inner radius rc + skin_in (skin_in <= skin): the list entries within it are the ones
-    // the force loop visits; their set is refreshed from the lists when atoms may have
-    // crossed skin_in since the last refresh
-    double skin_in;
-    float ri2_f;
+    // pair-list form: pairs closer than this (squared, FP32) have a force that could leave
+    // the range of the fixed-point force accumulators; meeting one marks the daughter
+    float rg2_f;
 };
 
 // Observables recorded beside V*P_xy when a daughter has an extra series (kObsCols per time
@@ -49,10 +47,12 @@ struct SysDev {
 constexpr int kObsSlabs = 8;
 constexpr int kObsCols = 3 + kObsSlabs;
 
-// Largest list capacity of the neighbour-list form (the inner set is a 32-bit mask).
-constexpr int kNlMaxKmax = 32;
-// Inner skin of the force loop (sigma).
-constexpr double kInnerSkin = 0.1;
+// Pair-list form: largest system (eight atoms per thread, 512 threads; pair words hold
+// 14-bit atom ranks), the largest pair capacity per atom, and the force magnitude whose
+// pairs are flagged (the fixed-point accumulators hold +-4096 force units).
+constexpr int kPairMaxAtoms = 4096;
+constexpr int kPairMaxCap = 64;
+constexpr double kPairForceGuard = 1024.0;
 
 // One daughter trajectory. Owned by the host runtime; the kernel updates k, done, health.
 struct DaughterDesc {
@@ -68,7 +68,8 @@ struct DaughterDesc {
     int32_t group;      // start-state group (accumulator slot)
     int32_t map;        // mapping 0..3
     int32_t block;      // threads per workgroup the launcher was sized for
-    int32_t kmax;       // neighbour-list form: list capacity per atom
+    int32_t kmax;       // pair-list form: pair capacity per atom (a wave's segment holds
+                        // kmax * 256 pairs)
     double* hseries;    // n_steps + 1 doubles: learned control variate h(t_k), or null
     // thermostat of the daughter: 0 Gaussian isokinetic, 1 Nose-Hoover (zeta carried from the
     // start state; d zeta/dt = (sum p^2 - nh_target)/nh_q)
@@ -79,7 +80,7 @@ struct DaughterDesc {
     double nh_target;
     double* xseries;    // (n_steps + 1) x kObsCols extra observables, or null
     double fe;          // colour field strength F_e (kFieldColour)
-    int32_t global_lists;  // list form with the lists in global scratch (set by the host)
+    int32_t pad2_;
     int32_t pad3_;
     // mixed flow (kFieldMixed): u_x = erate x + srate y, u_y = -erate y; gamma_dot holds
     // sqrt(erate^2 + srate^2)
@@ -94,12 +95,17 @@ struct DaughterDesc {
 // J = (erate (P_xx - P_yy) + srate P_xy) / sqrt(erate^2 + srate^2).
 enum Field : int32_t { kFieldShear = 0, kFieldColour = 1, kFieldElong = 2, kFieldMixed = 3 };
 
-enum Health : int32_t { kHealthNonFinite = 1, kHealthDrift = 2, kHealthListOverflow = 4 };
+enum Health : int32_t {
+    kHealthNonFinite = 1,
+    kHealthDrift = 2,
+    kHealthListOverflow = 4,
+    kHealthForceRange = 8  // a pair came closer than the fixed-point force range allows
+};
 
 // Daughter step kernels: the cell-list form rebuilds a canonical cell list every step and
-// evaluates pairs over the 27-cell stencil (FP64 or FP32 forces); the neighbour-list form
-// (FP32 forces) keeps per-atom lists of radius rc + skin in LDS and rebuilds them only when
-// the atoms have moved far enough to require it.
+// evaluates pairs over the 27-cell stencil (FP64 or FP32 forces); the pair-list form (FP32
+// forces) keeps every pair within rc + skin once in a list in global scratch, rebuilt only
+// when the atoms have moved far enough to require it.
 enum Variant : int32_t { kVariantCells = 0, kVariantNeighbourList = 1 };
 
 // Launch configuration of the persistent daughter kernel.
@@ -115,13 +121,13 @@ struct BatchLaunch {
     int32_t grid;          // workgroups (persistent)
     int32_t nmax, cmax;    // largest system / cell grid in the batch (LDS sizing)
     int32_t variant;       // Variant
-    int32_t kmax;          // neighbour-list capacity per atom (neighbour-list form)
+    int32_t kmax;          // pair capacity per atom (pair-list form)
     int32_t thermo;        // daughter thermostat of every job (0 isokinetic, 1 Nose-Hoover)
     int32_t obs;           // 1: some job records the extra observables (list form only)
-    int32_t field;         // 1: some job is a colour-field daughter (list form, isokinetic)
-    int32_t global_lists;  // 1: list form with the lists in global scratch
-    uint16_t* nbr;         // global_lists: grid x nbr_stride list entries
-    int64_t nbr_stride;    // >= (kmax + 1) n of every job
+    int32_t field;         // 1: some job is a colour-field daughter (list form)
+    int32_t pad_;
+    uint32_t* pairs;       // pair-list form: grid x pair_stride pair words
+    int64_t pair_stride;   // >= job_threads(n) / 64 * 256 * kmax of every job
     size_t lds_bytes;
 };
 
@@ -241,10 +247,26 @@ hipError_t launch_states_vpxy(const SysDev& sys, const double* states, int32_t c
 int pick_threads(int n, int requested);
 int pick_apt(int n, int threads);
 size_t lds_bytes_for(int nmax, int cmax, int threads, int precision);
-// LDS of the neighbour-list step kernel for one daughter of n atoms, `cells` list cells and
-// list capacity kmax (a launch needs the largest over its daughters)
-// LDS of one list-form job; global_lists: the lists themselves in global scratch
-size_t lds_bytes_nl(int n, int cells, int kmax, bool global_lists = false);
+// Pair-list form (ttcf_pairs.hip): LDS of one job of n atoms and `cells` list cells (a launch
+// needs the largest over its daughters), the threads that own a job's atoms (four each), and
+// the pair words of its segments per workgroup for a capacity of kcap pairs per atom.
+size_t lds_bytes_pairs(int n, int cells);
+int pair_job_threads(int n);
+int pair_job_apt(int n);
+// a launch runs every job with `apt` atoms per thread (the largest job's), so a job's wave
+// segments hold 64 apt kcap words each
+inline int64_t pair_words(int n, int kcap, int apt) {
+    return (int64_t)pair_job_threads(n) * apt * kcap;
+}
+hipError_t launch_pairs(const BatchLaunch& b, hipStream_t s);
+// The pair form's list build and one force pass on given positions (inspection): per atom its
+// list-grid cell and rank, the cell starts (cells + 1), the pair words of each wave segment
+// (kcap * 256 per wave) and their counts, the forces (3n), out[0] = W_xy, out[1] = 1 if a
+// pair fell inside the guard radius, out[2] = the Lees-Edwards offset used.
+hipError_t launch_debug_pair_form(const SysDev& S, double gamma_dot, int64_t kstep, const double* r,
+                                  int32_t kcap, uint32_t* pairs, int32_t* seg_count,
+                                  int32_t* cell_of, int32_t* rank_of, int32_t* start, double* f,
+                                  double* out, hipStream_t s);
 
 hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s);
 hipError_t launch_mothers(const MotherLaunch* dev_ms, int count, const MotherLaunch& shape,

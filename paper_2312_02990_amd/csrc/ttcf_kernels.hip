@@ -10,7 +10,7 @@
 // followed by a fixed-order sum over waves: results are deterministic.
 #include <hip/hip_runtime.h>
 
-#include "ttcf_internal.h"
+#include "ttcf_device.h"
 
 namespace ttcf {
 
@@ -26,72 +26,6 @@ __device__ __forceinline__ float pack_cell(float, int v) { return __int_as_float
 __device__ __forceinline__ double pack_cell(double, int v) { return (double)v; }
 __device__ __forceinline__ int unpack_cell(float w) { return __float_as_int(w); }
 __device__ __forceinline__ int unpack_cell(double w) { return (int)w; }
-
-// Reciprocal: hardware estimate refined by Newton steps to (near) correct rounding.
-__device__ __forceinline__ float recip(float x) {
-    float r = __builtin_amdgcn_rcpf(x);
-    float e = __builtin_fmaf(-x, r, 1.0f);
-    return __builtin_fmaf(r, e, r);
-}
-__device__ __forceinline__ double recip(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = __builtin_fma(-x, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-x, r, 1.0);
-    return __builtin_fma(r, e, r);
-}
-
-// Cell coordinate of one FP64 coordinate: floor(v * (n / L)), clamped. A lone product,
-// so nothing can be contracted and the result is bit-identical to any IEEE evaluation.
-__device__ __forceinline__ int cell_coord(double v, double inv_w, int nc) {
-    int c = (int)floor(v * inv_w);
-    return c < 0 ? 0 : (c > nc - 1 ? nc - 1 : c);
-}
-
-__device__ __forceinline__ double wrap1(double x, double l) {
-    if (x >= l) {
-        x -= l;
-        if (x >= l) x -= l * floor(x / l);
-    } else if (x < 0.0) {
-        x += l;
-        if (x < 0.0) x -= l * floor(x / l);
-        if (x >= l) x = 0.0;
-    }
-    return x;
-}
-
-// Lees-Edwards offset fmod(gamma_dot L_y (k dt), L_x), from the integer step counter. The
-// remainder v - q L_x of the right integer q is exactly representable, so one fused
-// multiply-add gives it exactly (the same bits as fmod); q from the rounded quotient can be
-// off by one, which the two checks correct.
-__device__ __forceinline__ double le_offset(const SysDev& S, double gamma_dot, int64_t k) {
-    const double v = gamma_dot * S.box[1] * ((double)k * S.dt);
-    const double lx = S.box[0];
-    const double av = fabs(v);
-    if (av < lx) return v;
-    const double q = floor(av / lx);
-    double r = __builtin_fma(-lx, q, av);
-    if (r < 0.0)
-        r = __builtin_fma(-lx, q - 1.0, av);
-    else if (r >= lx)
-        r = __builtin_fma(-lx, q + 1.0, av);
-    return v < 0.0 ? -r : r;
-}
-
-// Sliding-brick wrap of one atom after a move (y crossing shifts x by -+ dxle).
-__device__ __forceinline__ void wrap_le(const SysDev& S, double dxle, double& x, double& y,
-                                        double& z) {
-    if (y >= S.box[1]) {
-        y -= S.box[1];
-        x -= dxle;
-    } else if (y < 0.0) {
-        y += S.box[1];
-        x += dxle;
-        if (y >= S.box[1]) y = 0.0;
-    }
-    x = wrap1(x, S.box[0]);
-    z = wrap1(z, S.box[2]);
-}
 
 // ---------------------------------------------------------------------------------------
 // LDS layout
@@ -168,107 +102,6 @@ __device__ inline Lds<Real> carve(char* base, int nmax, int cmax) {
     L.misc = (int32_t*)(base + p.misc);
     L.sys = (SysDev*)(base + p.sys);
     return L;
-}
-
-// ---------------------------------------------------------------------------------------
-// block-level collectives
-// ---------------------------------------------------------------------------------------
-
-// One 32-bit DPP move (lanes without a source keep `old`).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ uint32_t dpp32(uint32_t old, uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xf, false);
-}
-
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_f64(double v) {
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = dpp32<CTRL, ROWS>(0u, (uint32_t)u);
-    const uint32_t hi = dpp32<CTRL, ROWS>(0u, (uint32_t)(u >> 32));
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
-}
-
-// Inclusive sum over the wave with row shifts (1, 2, 4, 8 inside rows of 16) and row
-// broadcasts (15, 31): lane 63 ends with the wave total. VALU data-parallel moves, no LDS.
-__device__ __forceinline__ double wave_total_dpp(double x) {
-    x += dpp_f64<0x111, 0xf>(x);  // row_shr:1
-    x += dpp_f64<0x112, 0xf>(x);  // row_shr:2
-    x += dpp_f64<0x114, 0xf>(x);  // row_shr:4
-    x += dpp_f64<0x118, 0xf>(x);  // row_shr:8
-    x += dpp_f64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-    x += dpp_f64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
-    return x;
-}
-
-// The same for the maximum of non-negative floats (0 is the identity).
-__device__ __forceinline__ float wave_max_dpp(float x) {
-    auto step = [](float a, uint32_t b) { return fmaxf(a, __builtin_bit_cast(float, b)); };
-    x = step(x, dpp32<0x111, 0xf>(0u, __builtin_bit_cast(uint32_t, x)));
-    x = step(x, dpp32<0x112, 0xf>(0u, __builtin_bit_cast(uint32_t, x)));
-    x = step(x, dpp32<0x114, 0xf>(0u, __builtin_bit_cast(uint32_t, x)));
-    x = step(x, dpp32<0x118, 0xf>(0u, __builtin_bit_cast(uint32_t, x)));
-    x = step(x, dpp32<0x142, 0xa>(0u, __builtin_bit_cast(uint32_t, x)));
-    x = step(x, dpp32<0x143, 0xc>(0u, __builtin_bit_cast(uint32_t, x)));
-    return x;
-}
-
-// Sum K doubles over the workgroup; every thread receives the totals. Fixed order: a scan
-// inside each wave (its total in lane 63), then wave 0..W-1 in sequence.
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double* red) {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int nw = blockDim.x >> 6;
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = wave_total_dpp(v[k]);
-    if (lane == 63) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) red[wave * K + k] = v[k];
-    }
-    __syncthreads();
-    if (threadIdx.x < K) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w) s += red[w * K + threadIdx.x];
-        red[kMaxWaves * kRedSlots + threadIdx.x] = s;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = red[kMaxWaves * kRedSlots + k];
-}
-
-// Exclusive scan of cnt[0..C) into start[0..C) (and into cnt as placement cursors).
-__device__ __forceinline__ void scan_cells(int32_t* cnt, int32_t* start, int C, int32_t* ws) {
-    const int T = blockDim.x, t = threadIdx.x;
-    const int lane = t & 63, wave = t >> 6, nw = T >> 6;
-    const int chunk = (C + T - 1) / T;
-    const int b = t * chunk;
-    const int e = min(C, b + chunk);
-    int local = 0;
-    for (int c = b; c < e; ++c) local += cnt[c];
-    int x = local;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) ws[wave] = x;
-    __syncthreads();
-    if (t == 0) {
-        int acc = 0;
-        for (int w = 0; w < nw; ++w) {
-            int v = ws[w];
-            ws[w] = acc;
-            acc += v;
-        }
-    }
-    __syncthreads();
-    int run = ws[wave] + x - local;
-    for (int c = b; c < e; ++c) {
-        int v = cnt[c];
-        start[c] = run;
-        cnt[c] = run;
-        run += v;
-    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -474,51 +307,6 @@ __device__ void compute_forces(const SysDev& S, double dxle, const double (&x)[A
             fx[j] = fy[j] = fz[j] = 0.0;
         }
     }
-}
-
-// ---------------------------------------------------------------------------------------
-// isokinetic integrator coefficients
-// ---------------------------------------------------------------------------------------
-
-// Exact flow over tau of dp/dt = F - (F.p/p.p) p with F fixed: p -> (p + F s)/sdot,
-// s = (a/b)(cosh(q tau) - 1) + sinh(q tau)/q, sdot = (a/q) sinh(q tau) + cosh(q tau),
-// a = F.p/p.p, b = F.F/p.p, q = sqrt(b) (Zhang, J. Chem. Phys. 106, 6102 (1997)).
-// With u = b tau^2 = (q tau)^2 the two combinations needed are power series in u:
-//   (cosh(q tau) - 1)/b = tau^2 (1/2 + u/24 + u^2/720 + ...)
-//   sinh(q tau)/q       = tau   (1 + u/6 + u^2/120 + ...)
-// Seven terms reach double precision for u < 0.04 (q tau < 0.2, the usual regime: the
-// first omitted term is below 1e-17 of the sum); larger arguments use the library sinh.
-__device__ __forceinline__ void iso_kick_coeffs(double a, double b, double tau, double& s,
-                                                double& sdot) {
-    double ch1_b, sh_q;
-    const double u = b * tau * tau;
-    if (u < 0.04) {
-        // Horner forms of the two series, coefficients 2/(2k+2)! and 1/(2k+1)!
-        double c = 1.0 / 87178291200.0;  // 1/14!
-        c = c * u + 1.0 / 479001600.0;   // 1/12!
-        c = c * u + 1.0 / 3628800.0;     // 1/10!
-        c = c * u + 1.0 / 40320.0;       // 1/8!
-        c = c * u + 1.0 / 720.0;         // 1/6!
-        c = c * u + 1.0 / 24.0;          // 1/4!
-        c = c * u + 0.5;                 // 1/2!
-        double d = 1.0 / 1307674368000.0;  // 1/15!
-        d = d * u + 1.0 / 6227020800.0;    // 1/13!
-        d = d * u + 1.0 / 39916800.0;      // 1/11!
-        d = d * u + 1.0 / 362880.0;        // 1/9!
-        d = d * u + 1.0 / 5040.0;          // 1/7!
-        d = d * u + 1.0 / 120.0;           // 1/5!
-        d = d * u + 1.0 / 6.0;             // 1/3!
-        d = d * u + 1.0;
-        ch1_b = tau * tau * c;
-        sh_q = tau * d;
-    } else {
-        const double q = sqrt(b);
-        const double hs = sinh(0.5 * q * tau) / q;
-        ch1_b = 2.0 * hs * hs;
-        sh_q = sinh(q * tau) / q;
-    }
-    s = a * ch1_b + sh_q;
-    sdot = a * sh_q + (1.0 + b * ch1_b);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1265,764 +1053,6 @@ __global__ __launch_bounds__(kMaxThreads) void k_debug_pairs(SysDev S, double dx
 }
 
 // ---------------------------------------------------------------------------------------
-// neighbour-list form of the daughter step (FP32 pair forces)
-// ---------------------------------------------------------------------------------------
-//
-// Pair separations come from 32-bit fixed-point coordinates X = rint(x 2^32 / L): the box
-// is exactly 2^32 units wide, so the wrapped integer difference X_i - X_j is the periodic
-// minimum image. The y difference tells whether the pair reaches across the sliding
-// boundary (n_y = +-1); then the Lees-Edwards offset, also in fixed point, is subtracted
-// from the x difference. The result is converted to FP32 once, so the separation carries
-// one rounding of a number no larger than the cutoff.
-//
-// Every atom keeps a list of the atoms within rc + skin, sorted by atom id, in LDS. A pair's
-// relative displacement since the list was built is at most
-//   2 d + |gamma_dot| t (rc + 2 d),
-// with d the largest peculiar path length of any atom and t the time since the build (the
-// second term is the shear flow between the two atoms; across the y boundary the drifting
-// offset compensates the images' streaming). The lists are rebuilt as soon as that bound
-// reaches the skin, so every pair inside rc is always listed. Because each list is sorted
-// and pairs outside rc add nothing, the forces do not depend on when rebuilds happen.
-
-// Entries per trip of the force loop and candidates per trip of the list build: their loads
-// are issued together, so that LDS latency overlaps within a wave.
-constexpr int kNlPairsPerTrip = 2;
-constexpr int kNlScanPerTrip = 4;
-
-struct NlLds {
-    uint4* posq;       // [nmax] fixed-point positions (X, Y, Z, unused)
-    uint16_t* nbr;     // [kmax][nmax] neighbour ids, column a = atom a
-    uint32_t* ncnt;    // [nmax] list lengths
-    int32_t* cnt;      // [cmax] list-grid cell counts / cursors
-    int32_t* start;    // [cmax + 1]
-    uint16_t* sid;     // [nmax + kNlScanPerTrip] atoms grouped by list-grid cell, then padding
-    int32_t* rowinfo;  // [3 rows][2]: first column offset mod nx, column count
-    double* red;       // block-reduction scratch
-    int32_t* scan;     // [kMaxWaves]
-    float* wmax;       // [2 kMaxWaves] per-wave maxima of the two path lengths
-    int32_t* misc;     // [4]: [0] job, [1] list overflow
-    SysDev* sys;
-};
-
-struct NlPlan {
-    size_t posq, nbr, ncnt, cnt, start, sid, rowinfo, red, scan, wmax, misc, sys, total;
-};
-
-// global_lists: the lists live in per-workgroup global scratch instead (systems whose lists
-// do not fit in LDS); everything else stays in LDS.
-__host__ __device__ inline NlPlan plan_nl(int nmax, int cmax, int kmax, bool global_lists = false) {
-    NlPlan p;
-    size_t off = 0;
-    auto take = [&](size_t bytes, size_t al) {
-        off = align_up(off, al);
-        size_t at = off;
-        off += bytes;
-        return at;
-    };
-    p.posq = take(16 * (size_t)nmax, 16);
-    // row kmax: sink for rejected candidates
-    p.nbr = global_lists ? 0 : take(2 * (size_t)(kmax + 1) * nmax, 16);
-    p.ncnt = take(4 * (size_t)nmax, 16);
-    p.cnt = take(4 * (size_t)cmax, 16);
-    p.start = take(4 * (size_t)(cmax + 1), 16);
-    // padding: the reads of a trip past the end of a range stay inside
-    p.sid = take(2 * (size_t)(nmax + kNlScanPerTrip), 16);
-    p.rowinfo = take(4 * 8, 16);
-    p.red = take(sizeof(double) * (kMaxWaves * kRedSlots + kRedSlots), 16);
-    p.scan = take(4 * kMaxWaves, 16);
-    p.wmax = take(8 * kMaxWaves, 16);
-    p.misc = take(4 * 4, 16);
-    p.sys = take(sizeof(SysDev), 16);
-    p.total = align_up(off, 128);
-    return p;
-}
-
-__device__ inline NlLds carve_nl(char* base, int nmax, int cmax, int kmax,
-                                 uint16_t* global_nbr = nullptr) {
-    NlPlan p = plan_nl(nmax, cmax, kmax, global_nbr != nullptr);
-    NlLds L;
-    L.posq = (uint4*)(base + p.posq);
-    L.nbr = global_nbr ? global_nbr : (uint16_t*)(base + p.nbr);
-    L.ncnt = (uint32_t*)(base + p.ncnt);
-    L.cnt = (int32_t*)(base + p.cnt);
-    L.start = (int32_t*)(base + p.start);
-    L.sid = (uint16_t*)(base + p.sid);
-    L.rowinfo = (int32_t*)(base + p.rowinfo);
-    L.red = (double*)(base + p.red);
-    L.scan = (int32_t*)(base + p.scan);
-    L.wmax = (float*)(base + p.wmax);
-    L.misc = (int32_t*)(base + p.misc);
-    L.sys = (SysDev*)(base + p.sys);
-    return L;
-}
-
-__device__ __forceinline__ uint32_t fix32(double v, double scale) {
-    return (uint32_t)(int64_t)rint(v * scale);
-}
-
-// Separation (FP32) of fixed-point positions i and j; dxq is the LE offset in fixed point.
-__device__ __forceinline__ void fix_sep(uint32_t xi, uint32_t yi, uint32_t zi, const uint4& q,
-                                        uint32_t dxq, const SysDev& S, float& dx, float& dy,
-                                        float& dz) {
-    const uint32_t uy = yi - q.y;
-    const int32_t iy = (int32_t)uy;
-    // n_y = +1 when y_i - y_j > L/2 (the image above is nearer), -1 when < -L/2, else 0:
-    // n_y = (sign bit of the wrapped difference) - (borrow of the unsigned subtraction);
-    // the x difference then loses n_y times the offset
-    const uint32_t sgn = uy >> 31;
-    const uint32_t brw = yi < q.y ? 1u : 0u;
-    const uint32_t shift = ((0u - sgn) & dxq) - ((0u - brw) & dxq);
-    const int32_t ix = (int32_t)(xi - q.x - shift);
-    const int32_t iz = (int32_t)(zi - q.z);
-    dx = (float)ix * S.fix_unit[0];
-    dy = (float)iy * S.fix_unit[1];
-    dz = (float)iz * S.fix_unit[2];
-}
-
-// Rebuild the lists: counting sort of the atoms into the list grid (cells >= rc + skin wide),
-// then every owner collects its atoms' neighbours within rc + skin over the 27-cell stencil
-// (LE-displaced x range for rows across the y boundary) and sorts them by id.
-template <int APT>
-__device__ __forceinline__ void nl_rebuild(const SysDev& S, double dxle, uint32_t dxq, const double (&x)[APT],
-                           const double (&y)[APT], const double (&z)[APT],
-                           const uint32_t (&qx)[APT], const uint32_t (&qy)[APT],
-                           const uint32_t (&qz)[APT], const NlLds& L, int kmax, int nmax) {
-    const int T = blockDim.x, t = threadIdx.x, n = S.n;
-    const int nc0 = S.lc[0], nc1 = S.lc[1], nc2 = S.lc[2];
-    const int C = nc0 * nc1 * nc2;
-    int cell[APT];
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        const int a = t + j * T;
-        cell[j] = -1;
-        if (a < n) {
-            const int cx = cell_coord(x[j], S.l_inv_w[0], nc0);
-            const int cy = cell_coord(y[j], S.l_inv_w[1], nc1);
-            const int cz = cell_coord(z[j], S.l_inv_w[2], nc2);
-            cell[j] = cx + nc0 * (cy + nc1 * cz);
-            atomicAdd(&L.cnt[cell[j]], 1);
-        }
-    }
-    if (t == 0) {
-        L.misc[1] = 0;
-        const double reach = S.rc + S.skin;
-        const double wx = S.lw[0];
-        const double margin = 1e-6 * reach;
-        for (int row = 0; row < 3; ++row) {
-            int off, nq;
-            if (row == 1) {
-                off = -1;
-                nq = 3;
-            } else {
-                double sh = (row == 0 ? -1.0 : 1.0) * dxle;
-                sh -= S.box[0] * rint(sh / S.box[0]);
-                off = (int)floor((-reach - margin - sh) / wx);
-                const int hi = (int)floor((wx + reach + margin - sh) / wx);
-                nq = hi - off + 1;
-                if (nq > 5) nq = 5;
-                if (nq > nc0) nq = nc0;
-            }
-            L.rowinfo[2 * row] = ((off % nc0) + nc0) % nc0;
-            L.rowinfo[2 * row + 1] = nq;
-        }
-    }
-    __syncthreads();
-    scan_cells(L.cnt, L.start, C, L.scan);
-    if (t == 0) L.start[C] = n;
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        if (cell[j] >= 0) {
-            const int idx = atomicAdd(&L.cnt[cell[j]], 1);
-            L.sid[idx] = (uint16_t)(t + j * T);
-        }
-    }
-    __syncthreads();
-    const float rl2 = S.rl2_f;
-    const float ux = S.fix_unit[0], uy = S.fix_unit[1], uz = S.fix_unit[2];
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        const int a = t + j * T;
-        if (a >= n) continue;
-        const int c0 = cell[j];
-        const int cx = c0 % nc0, cy = (c0 / nc0) % nc1, cz = c0 / (nc0 * nc1);
-        int count = 0;
-        // the cells of one stencil row are consecutive cell ids, so their atoms form one
-        // contiguous range of the sorted order (two when the row wraps around in x)
-        // branch-free: every candidate is written, rejected ones into the sink row kmax
-        const int sink = kmax * nmax + a;
-        int slot = a;  // count * nmax + a while count < kmax
-        // rsh: the Lees-Edwards x shift of the row's y image (+offset for a row wrapped from
-        // the top, -offset from the bottom, 0 otherwise). A candidate within the list radius is
-        // nearer than half the box in y, so its minimum image is the row's image; for the others
-        // the test fails with either shift.
-        auto scan = [&](int lo, int hi, uint32_t rsh) {
-#pragma unroll 1
-            for (int tt = lo; tt < hi; tt += kNlScanPerTrip) {
-                int jn[kNlScanPerTrip];
-                uint4 q[kNlScanPerTrip];
-#pragma unroll
-                for (int u = 0; u < kNlScanPerTrip; ++u) {
-                    // unconditional load (the array is padded); a value past the range is
-                    // replaced before it is used as an index
-                    const int raw = L.sid[tt + u];
-                    jn[u] = tt + u < hi ? raw : a;
-                }
-#pragma unroll
-                for (int u = 0; u < kNlScanPerTrip; ++u) q[u] = L.posq[jn[u]];
-#pragma unroll
-                for (int u = 0; u < kNlScanPerTrip; ++u) {
-                    const float ddx = (float)(int32_t)(qx[j] - q[u].x - rsh) * ux;
-                    const float ddy = (float)(int32_t)(qy[j] - q[u].y) * uy;
-                    const float ddz = (float)(int32_t)(qz[j] - q[u].z) * uz;
-                    const bool hit = (jn[u] != a) & (ddx * ddx + ddy * ddy + ddz * ddz < rl2);
-                    const bool room = hit & (count < kmax);
-                    L.nbr[room ? slot : sink] = (uint16_t)jn[u];
-                    slot += room ? nmax : 0;
-                    count += hit ? 1 : 0;
-                }
-            }
-        };
-#pragma unroll 1
-        for (int r9 = 0; r9 < 9; ++r9) {
-            int zz = cz + r9 / 3 - 1;
-            zz = zz < 0 ? zz + nc2 : (zz >= nc2 ? zz - nc2 : zz);
-            int yy = cy + r9 % 3 - 1;
-            int row = 1;
-            if (yy < 0) {
-                yy += nc1;
-                row = 0;
-            } else if (yy >= nc1) {
-                yy -= nc1;
-                row = 2;
-            }
-            const int nq = L.rowinfo[2 * row + 1];
-            int x0 = cx + L.rowinfo[2 * row];
-            if (x0 >= nc0) x0 -= nc0;
-            const int base = nc0 * (yy + nc1 * zz);
-            const int xe = x0 + nq;
-            const uint32_t rsh = row == 2 ? dxq : (row == 0 ? 0u - dxq : 0u);
-            scan(L.start[base + x0], L.start[base + (xe < nc0 ? xe : nc0)], rsh);
-            if (xe > nc0) scan(L.start[base], L.start[base + xe - nc0], rsh);
-        }
-        if (count > kmax) {
-            L.misc[1] = 1;
-            count = kmax;
-        }
-        // ascending ids: a fixed summation order for the forces
-        for (int i = 1; i < count; ++i) {
-            const uint16_t v = L.nbr[i * nmax + a];
-            int k = i - 1;
-            while (k >= 0 && L.nbr[k * nmax + a] > v) {
-                L.nbr[(k + 1) * nmax + a] = L.nbr[k * nmax + a];
-                --k;
-            }
-            L.nbr[(k + 1) * nmax + a] = v;
-        }
-        L.ncnt[a] = (uint32_t)count;
-    }
-    for (int c = t; c < C; c += T) L.cnt[c] = 0;
-    __syncthreads();
-}
-
-// Forces on the owned atoms from their lists; returns this thread's share of W_xy.
-// Marks, for every owned atom, the list entries within the inner radius (bit k: entry k);
-// entries beyond it cannot reach r_c before the next refresh.
-// PER: list entries per trip (their loads issued together).
-template <int APT, int PER>
-__device__ __forceinline__ void nl_inner(const SysDev& S, uint32_t dxq, const uint32_t (&qx)[APT],
-                                         const uint32_t (&qy)[APT], const uint32_t (&qz)[APT],
-                                         const NlLds& L, int nmax, uint32_t (&imask)[APT]) {
-    const int T = blockDim.x, t = threadIdx.x, n = S.n;
-    const float ri2 = S.ri2_f;
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        const int a = t + j * T;
-        uint32_t m = 0u;
-        if (a < n) {
-            const int c = L.ncnt[a];
-            // PER entries per trip: their id loads, then their position loads, are issued
-            // together; entries past the count reread entry k and set no bit
-            for (int k = 0; k < c; k += PER) {
-                int id[PER];
-                uint4 q[PER];
-#pragma unroll
-                for (int u = 0; u < PER; ++u) id[u] = L.nbr[(k + u < c ? k + u : k) * nmax + a];
-#pragma unroll
-                for (int u = 0; u < PER; ++u) q[u] = L.posq[id[u]];
-#pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    float dx, dy, dz;
-                    fix_sep(qx[j], qy[j], qz[j], q[u], dxq, S, dx, dy, dz);
-                    const float r2 = dx * dx + dy * dy + dz * dz;
-                    m |= ((k + u < c) & (r2 < ri2)) ? 1u << ((k + u) & 31) : 0u;
-                }
-            }
-        }
-        imask[j] = m;
-    }
-}
-
-// OBS: also this thread's halves of the pair sums W_xx, W_yy, W_zz and U (xw).
-template <int APT, bool OBS>
-__device__ __forceinline__ double nl_forces(const SysDev& S, uint32_t dxq,
-                                            const uint32_t (&qx)[APT], const uint32_t (&qy)[APT],
-                                            const uint32_t (&qz)[APT], const uint32_t (&imask)[APT],
-                                            float (&fx)[APT], float (&fy)[APT], float (&fz)[APT],
-                                            const NlLds& L, int nmax, double (&xw)[4]) {
-    const int T = blockDim.x, t = threadIdx.x;
-    const float rc2 = S.rc2_f;
-    const float ca = (float)S.c_attr;
-    const float ushift = (float)S.u_shift;
-    double wacc = 0.0;
-    if (OBS) xw[0] = xw[1] = xw[2] = xw[3] = 0.0;
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        const int a = t + j * T;
-        float gx = 0.f, gy = 0.f, gz = 0.f, w = 0.f;
-        float vxx = 0.f, vyy = 0.f, vzz = 0.f, uu = 0.f;
-        {
-            // the inner entries in list order (ascending ids): a fixed summation order, and
-            // every skipped entry lies beyond r_c, where a pair adds an exact zero
-            // one pair, added in list order; `live` false adds exact zeros
-            auto pair = [&](const uint4& q, bool live) {
-                float dx, dy, dz;
-                fix_sep(qx[j], qy[j], qz[j], q, dxq, S, dx, dy, dz);
-                const float r2 = dx * dx + dy * dy + dz * dz;
-                // listed pairs beyond the cutoff contribute an exact zero (no branch)
-                const float inv = recip(r2);
-                const float s3 = inv * inv * inv;
-                const bool in = live & (r2 < rc2);
-                const float fs = in ? s3 * (48.f * s3 - 24.f * ca) * inv : 0.f;
-                gx += fs * dx;
-                gy += fs * dy;
-                gz += fs * dz;
-                w += dx * (fs * dy);
-                if (OBS) {
-                    vxx += dx * (fs * dx);
-                    vyy += dy * (fs * dy);
-                    vzz += dz * (fs * dz);
-                    uu += in ? 4.f * s3 * (s3 - ca) + ushift : 0.f;
-                }
-            };
-            // P inner entries per trip: their id loads, then their position loads, are issued
-            // before the arithmetic; missing entries at the end repeat the first one and add
-            // nothing. The build with the extra pair sums keeps one entry per trip: with two
-            // it outgrows the register budget.
-            constexpr int P = OBS ? 1 : kNlPairsPerTrip;
-            uint32_t mk = imask[j];
-            while (mk != 0u) {
-                int kk[P];
-                bool live[P];
-                kk[0] = __builtin_ctz(mk);
-                live[0] = true;
-                mk &= mk - 1u;
-#pragma unroll
-                for (int u = 1; u < P; ++u) {
-                    live[u] = mk != 0u;
-                    kk[u] = live[u] ? __builtin_ctz(mk) : kk[0];
-                    mk &= mk - 1u;
-                }
-                int id[P];
-                uint4 q[P];
-#pragma unroll
-                for (int u = 0; u < P; ++u) id[u] = L.nbr[kk[u] * nmax + a];
-#pragma unroll
-                for (int u = 0; u < P; ++u) q[u] = L.posq[id[u]];
-#pragma unroll
-                for (int u = 0; u < P; ++u) pair(q[u], live[u]);
-            }
-        }
-        fx[j] = gx;
-        fy[j] = gy;
-        fz[j] = gz;
-        wacc += (double)w;
-        if (OBS) {
-            xw[0] += 0.5 * (double)vxx;
-            xw[1] += 0.5 * (double)vyy;
-            xw[2] += 0.5 * (double)vzz;
-            xw[3] += 0.5 * (double)uu;
-        }
-    }
-    return 0.5 * wacc;
-}
-
-// The extra observables of the owned atoms at one time point (momenta p, positions in
-// [0, L), pair halves xw of the last force pass), reduced over the workgroup and written by
-// thread 0 to row `row` of the daughter's extra series.
-template <int APT>
-__device__ __forceinline__ void nl_record_obs(const SysDev& S, const double (&y)[APT],
-                                              const double (&px)[APT], const double (&py)[APT],
-                                              const double (&pz)[APT], const double (&xw)[4],
-                                              double* xs, int row, const NlLds& L) {
-    double o[kObsCols];
-#pragma unroll
-    for (int c = 0; c < kObsCols; ++c) o[c] = 0.0;
-    const double slab_scale = (double)kObsSlabs / S.box[1];
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        // lanes past n hold zero momenta and add nothing
-        const double xx = px[j] * px[j], yy = py[j] * py[j], zz = pz[j] * pz[j];
-        o[0] += xx - yy;
-        o[1] += yy - zz;
-        o[2] += 0.5 * (xx + yy + zz);
-        int sl = (int)floor(y[j] * slab_scale);
-        sl = sl < 0 ? 0 : (sl > kObsSlabs - 1 ? kObsSlabs - 1 : sl);
-#pragma unroll
-        for (int q = 0; q < kObsSlabs; ++q) o[3 + q] += sl == q ? px[j] : 0.0;
-    }
-    o[0] += xw[0] - xw[1];
-    o[1] += xw[1] - xw[2];
-    o[2] += xw[3];
-    block_sum<kObsCols>(o, L.red);
-    if (threadIdx.x == 0) {
-        double* out = xs + (size_t)row * kObsCols;
-        const double iv = 1.0 / S.volume;
-        out[0] = o[0] * iv;
-        out[1] = o[1] * iv;
-        out[2] = o[2] / (double)S.n;
-#pragma unroll
-        for (int q = 0; q < kObsSlabs; ++q) out[3 + q] = o[3 + q] * ((double)kObsSlabs * iv);
-    }
-}
-
-// Publish the fixed-point positions of the owned atoms and the wave maxima of the path
-// lengths; after the barrier every thread reads the workgroup maximum.
-template <int APT>
-__device__ __forceinline__ float2 nl_publish(const SysDev& S, const double (&x)[APT],
-                                             const double (&y)[APT], const double (&z)[APT],
-                                             uint32_t (&qx)[APT], uint32_t (&qy)[APT],
-                                             uint32_t (&qz)[APT], const float (&path)[APT],
-                                             const float (&path_in)[APT], const NlLds& L) {
-    const int T = blockDim.x, t = threadIdx.x, n = S.n;
-    float pm = 0.f, pi = 0.f;
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        const int a = t + j * T;
-        qx[j] = fix32(x[j], S.fix_scale[0]);
-        qy[j] = fix32(y[j], S.fix_scale[1]);
-        qz[j] = fix32(z[j], S.fix_scale[2]);
-        if (a < n) {
-            L.posq[a] = make_uint4(qx[j], qy[j], qz[j], 0u);
-            pm = fmaxf(pm, path[j]);
-            pi = fmaxf(pi, path_in[j]);
-        }
-    }
-    pm = wave_max_dpp(pm);
-    pi = wave_max_dpp(pi);
-    if ((t & 63) == 63) {
-        L.wmax[2 * (t >> 6)] = pm;
-        L.wmax[2 * (t >> 6) + 1] = pi;
-    }
-    __syncthreads();
-    float2 m = make_float2(0.f, 0.f);
-    for (int w = 0; w < (T >> 6); ++w) {
-        m.x = fmaxf(m.x, L.wmax[2 * w]);
-        m.y = fmaxf(m.y, L.wmax[2 * w + 1]);
-    }
-    return m;
-}
-
-// COL: the build that also runs colour-field daughters (either thermostat): atom a carries
-// the colour charge +1 (even a) or -1 (odd a), the field adds charge * F_e to its x force in
-// FP64, there is no shear, and the series records V J_x = sum_a charge p_x,a.
-template <int APT, bool NH, bool OBS, bool COL>
-__device__ void run_daughter_nl(DaughterDesc* dsc, int steps_cap, const NlLds& L, int kmax,
-                                int nmax) {
-    const int T = blockDim.x, t = threadIdx.x;
-    if (t == 0) *L.sys = dsc->sys;
-    __syncthreads();
-    const SysDev& S = *L.sys;
-    const int n = S.n;
-    double* st = dsc->state;
-    const bool col = COL && dsc->field == kFieldColour;  // uniform per job
-    const double gd = col ? 0.0 : dsc->gamma_dot;
-    int64_t k = dsc->k;
-    int done = dsc->done;
-    const int n_steps = dsc->n_steps;
-    double k0 = dsc->k0;
-    int health = dsc->health;
-    // Nose-Hoover daughters (Eq. system1 as printed): zeta from the mapped start state
-    constexpr bool nh = NH;  // the descriptor's thermo selects the instantiation
-    double zt = dsc->zeta;
-    const double nh_iq = nh ? 1.0 / dsc->nh_q : 0.0, nh_tgt = dsc->nh_target;
-    int todo = min(steps_cap, n_steps - done);
-    if (health != 0) todo = 0;
-    if (todo <= 0 && done > 0) return;
-
-    double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT];
-    float fx[APT], fy[APT], fz[APT];  // FP32 pair forces; every use below promotes them to FP64
-    uint32_t qx[APT], qy[APT], qz[APT];
-    float path[APT], path_in[APT];  // path lengths since the last rebuild / inner refresh
-    uint32_t imask[APT];
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        const int a = t + j * T;
-        const bool v = a < n;
-        x[j] = v ? st[a] : 0.0;
-        y[j] = v ? st[n + a] : 0.0;
-        z[j] = v ? st[2 * n + a] : 0.0;
-        px[j] = v ? st[3 * n + a] : 0.0;
-        py[j] = v ? st[4 * n + a] : 0.0;
-        pz[j] = v ? st[5 * n + a] : 0.0;
-        path[j] = 0.f;
-        path_in[j] = 0.f;
-    }
-    // colour charges (zero past n and for shear daughters) and the field's x force in FP64
-    double cq[APT], ce[APT];
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        const int a = t + j * T;
-        cq[j] = (COL && col && a < n) ? ((a & 1) ? -1.0 : 1.0) : 0.0;
-        ce[j] = COL ? cq[j] * dsc->fe : 0.0;
-    }
-    auto fxd = [&](int j) -> double {
-        if constexpr (COL)
-            return (double)fx[j] + ce[j];
-        else
-            return (double)fx[j];
-    };
-    double dxle = le_offset(S, gd, k);
-    uint32_t dxq = fix32(dxle, S.fix_scale[0]);
-    nl_publish<APT>(S, x, y, z, qx, qy, qz, path, path_in, L);
-    nl_rebuild<APT>(S, dxle, dxq, x, y, z, qx, qy, qz, L, kmax, nmax);
-    if (L.misc[1] != 0) health |= kHealthListOverflow;
-    // the build with the extra pair sums keeps one entry per trip (register budget)
-    constexpr int kInnerPer = OBS ? 1 : 4;
-    nl_inner<APT, kInnerPer>(S, dxq, qx, qy, qz, L, nmax, imask);
-    double xw[4];
-    double wpart = nl_forces<APT, OBS>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax, xw);
-    double* const xs = OBS ? dsc->xseries : nullptr;
-
-    double m0[7] = {0, 0, 0, 0, 0, 0, wpart};
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        m0[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-        m0[1] += (COL && col) ? cq[j] * px[j] : px[j] * py[j];
-        m0[2] += py[j] * py[j];
-        m0[3] += fxd(j) * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
-        m0[4] += fxd(j) * py[j];
-        m0[5] += fxd(j) * fxd(j) + (double)fy[j] * (double)fy[j] +
-                 (double)fz[j] * (double)fz[j];
-    }
-    block_sum<7>(m0, L.red);
-    if (done == 0) {
-        if (k0 <= 0.0) k0 = 0.5 * m0[0];
-        if (t == 0) dsc->series[0] = (COL && col) ? m0[1] : m0[1] + m0[6];
-        if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, 0, L);
-    }
-    if (health != 0) todo = 0;
-    double pp = m0[0], pxpy = m0[1], pypy = m0[2], fp = m0[3], fxpy = m0[4], ff = m0[5];
-    const double h = S.dt, tau = 0.5 * S.dt, tg = tau * gd;
-    const float reach = (float)S.rc;
-    const float skin = (float)S.skin;
-    const float skin_in = (float)S.skin_in;
-    const float agd = (float)fabs(gd);
-    int since = 0, since_in = 0;
-
-    for (int step = 0; step < todo; ++step) {
-        if (nh) {
-            // ---- first half: Z(tau) T(tau) S(tau) K(tau); pp = sum p^2 of the current p
-            zt += tau * (pp - nh_tgt) * nh_iq;
-            const double c1 = exp(-zt * tau);
-#pragma unroll
-            for (int j = 0; j < APT; ++j) {
-                const double qy = c1 * py[j];
-                px[j] = c1 * px[j] - tg * qy + tau * fxd(j);
-                py[j] = qy + tau * (double)fy[j];
-                pz[j] = c1 * pz[j] + tau * (double)fz[j];
-            }
-        } else {
-        // ---- first half: S(tau) then K(tau)
-        const double ppt = pp - 2.0 * tg * pxpy + tg * tg * pypy;
-        const double g1 = sqrt(pp / ppt);
-        const double fp1 = g1 * (fp - tg * fxpy);
-        double s1, sd1;
-        iso_kick_coeffs(fp1 / pp, ff / pp, tau, s1, sd1);
-        const double isd1 = 1.0 / sd1;
-#pragma unroll
-        for (int j = 0; j < APT; ++j) {
-            const double qxp = g1 * (px[j] - tg * py[j]);
-            const double qyp = g1 * py[j];
-            const double qzp = g1 * pz[j];
-            px[j] = (qxp + fxd(j) * s1) * isd1;
-            py[j] = (qyp + (double)fy[j] * s1) * isd1;
-            pz[j] = (qzp + (double)fz[j] * s1) * isd1;
-        }
-        }
-        // ---- streaming D(h), new strain, sliding-brick wrap, peculiar path length
-        k += 1;
-        dxle = le_offset(S, gd, k);
-        dxq = fix32(dxle, S.fix_scale[0]);
-#pragma unroll
-        for (int j = 0; j < APT; ++j) {
-            const double vx = px[j] + tg * py[j];
-            const float dl = (float)h * sqrtf((float)(vx * vx + py[j] * py[j] + pz[j] * pz[j]));
-            path[j] += dl;
-            path_in[j] += dl;
-            x[j] += h * px[j] + h * gd * (y[j] + tau * py[j]);
-            y[j] += h * py[j];
-            z[j] += h * pz[j];
-            wrap_le(S, dxle, x[j], y[j], z[j]);
-        }
-        const float2 dm = nl_publish<APT>(S, x, y, z, qx, qy, qz, path, path_in, L);
-        ++since;
-        ++since_in;
-        const float tsince = (float)(since * h), tin = (float)(since_in * h);
-        // the same displacement bound guards the lists (skin) and the inner set (skin_in)
-        const bool rebuild = 2.f * dm.x + agd * tsince * (reach + 2.f * dm.x) >= skin;
-        if (rebuild) {
-            nl_rebuild<APT>(S, dxle, dxq, x, y, z, qx, qy, qz, L, kmax, nmax);
-            if (L.misc[1] != 0) {
-                health |= kHealthListOverflow;
-                break;
-            }
-#pragma unroll
-            for (int j = 0; j < APT; ++j) path[j] = 0.f;
-            since = 0;
-        }
-        if (rebuild || 2.f * dm.y + agd * tin * (reach + 2.f * dm.y) >= skin_in) {
-            nl_inner<APT, kInnerPer>(S, dxq, qx, qy, qz, L, nmax, imask);
-#pragma unroll
-            for (int j = 0; j < APT; ++j) path_in[j] = 0.f;
-            since_in = 0;
-        }
-        wpart = nl_forces<APT, OBS>(S, dxq, qx, qy, qz, imask, fx, fy, fz, L, nmax, xw);
-        if (nh) {
-            // ---- second half: K(tau) S(tau) T(tau), then Z(tau) on the new sum p^2
-            const double c2 = exp(-zt * tau);
-            double m4[4] = {0, 0, wpart, 0};  // pp, pxpy, W, position sum
-#pragma unroll
-            for (int j = 0; j < APT; ++j) {
-                const double qy = py[j] + tau * (double)fy[j];
-                px[j] = c2 * (px[j] + tau * fxd(j) - tg * qy);
-                py[j] = c2 * qy;
-                pz[j] = c2 * (pz[j] + tau * (double)fz[j]);
-                m4[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-                m4[1] += (COL && col) ? cq[j] * px[j] : px[j] * py[j];
-                m4[3] += x[j] + y[j] + z[j];
-            }
-            block_sum<4>(m4, L.red);
-            pp = m4[0];
-            zt += tau * (pp - nh_tgt) * nh_iq;
-            const double vpxy = (COL && col) ? m4[1] : m4[1] + m4[2];
-            done += 1;
-            if (t == 0) dsc->series[done] = vpxy;
-            if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, done, L);
-            if (!isfinite(vpxy) || !isfinite(zt) || !isfinite(m4[3])) {
-                health |= kHealthNonFinite;
-                break;
-            }
-            continue;
-        }
-        // ---- moments of (p'', F): pp, pxpy, pypy, fp, fxpy, fypx, fxfy, fypy, fyfy, ff, W, pos
-        double m[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, wpart, 0};
-#pragma unroll
-        for (int j = 0; j < APT; ++j) {
-            m[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
-            m[1] += (COL && col) ? cq[j] * px[j] : px[j] * py[j];
-            m[2] += py[j] * py[j];
-            m[3] += fxd(j) * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
-            m[4] += (COL && col) ? cq[j] * fxd(j) : fxd(j) * py[j];
-            m[5] += (double)fy[j] * px[j];
-            m[6] += fxd(j) * (double)fy[j];
-            m[7] += (double)fy[j] * py[j];
-            m[8] += (double)fy[j] * (double)fy[j];
-            m[9] += fxd(j) * fxd(j) + (double)fy[j] * (double)fy[j] +
-                    (double)fz[j] * (double)fz[j];
-            m[11] += x[j] + y[j] + z[j];
-        }
-        block_sum<12>(m, L.red);
-        double s2, sd2;
-        iso_kick_coeffs(m[3] / m[0], m[9] / m[0], tau, s2, sd2);
-        const double isd2 = 1.0 / sd2;
-        const double pp3 = (m[0] + 2.0 * s2 * m[3] + s2 * s2 * m[9]) * isd2 * isd2;
-        const double pxpy3 = (m[1] + s2 * (m[4] + m[5]) + s2 * s2 * m[6]) * isd2 * isd2;
-        const double pypy3 = (m[2] + 2.0 * s2 * m[7] + s2 * s2 * m[8]) * isd2 * isd2;
-        const double fp3 = (m[3] + s2 * m[9]) * isd2;
-        const double fxpy3 = (m[4] + s2 * m[6]) * isd2;
-        const double ppt2 = pp3 - 2.0 * tg * pxpy3 + tg * tg * pypy3;
-        const double pxpyt = pxpy3 - tg * pypy3;
-        const double c = sqrt(2.0 * k0 / ppt2);
-#pragma unroll
-        for (int j = 0; j < APT; ++j) {
-            const double qxp = (px[j] + fxd(j) * s2) * isd2;
-            const double qyp = (py[j] + (double)fy[j] * s2) * isd2;
-            const double qzp = (pz[j] + (double)fz[j] * s2) * isd2;
-            px[j] = c * (qxp - tg * qyp);
-            py[j] = c * qyp;
-            pz[j] = c * qzp;
-        }
-        pp = c * c * ppt2;
-        pxpy = c * c * pxpyt;
-        pypy = c * c * pypy3;
-        fp = c * (fp3 - tg * fxpy3);
-        fxpy = c * fxpy3;
-        ff = m[9];
-        // colour: V J_x of the final momenta c (p + s2 F) / sd2 from the charge moments
-        const double vpxy = (COL && col) ? c * (m[1] + s2 * m[4]) * isd2 : pxpy + m[10];
-        done += 1;
-        if (t == 0) dsc->series[done] = vpxy;
-        if (OBS && xs) nl_record_obs<APT>(S, y, px, py, pz, xw, xs, done, L);
-        if (!isfinite(vpxy) || !isfinite(c) || !isfinite(m[11])) {
-            health |= kHealthNonFinite;
-            break;
-        }
-        if (fabs(pp3 / m[0] - 1.0) > 1e-10) {
-            health |= kHealthDrift;
-            break;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < APT; ++j) {
-        const int a = t + j * T;
-        if (a < n) {
-            st[a] = x[j];
-            st[n + a] = y[j];
-            st[2 * n + a] = z[j];
-            st[3 * n + a] = px[j];
-            st[4 * n + a] = py[j];
-            st[5 * n + a] = pz[j];
-        }
-    }
-    if (t == 0) {
-        dsc->k = k;
-        dsc->done = done;
-        dsc->k0 = k0;
-        dsc->health = health;
-        dsc->zeta = zt;
-    }
-    __syncthreads();
-}
-
-// The job slot sits at the start of the LDS; behind it the LDS is laid out per job for that
-// daughter's own size, list grid and capacity, so a launch needs only the largest single
-// footprint among its daughters.
-constexpr int kNlJobBytes = 128;
-
-// GL: the lists of each workgroup in global scratch (b.nbr, b.nbr_stride entries apart).
-template <int APT, int MAXT, bool NH, bool OBS, bool COL, bool GL>
-__global__ __launch_bounds__(MAXT) void k_daughters_nl(BatchLaunch b) {
-    extern __shared__ __align__(32) char smem[];
-    int32_t* job = (int32_t*)smem;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) *job = atomicAdd(b.queue, 1);
-        __syncthreads();
-        const int j = __builtin_amdgcn_readfirstlane(*job);
-        if (j >= b.n_jobs) break;
-        DaughterDesc* d = &b.descs[b.order[j]];
-        const int n = d->sys.n, kmax = d->kmax;
-        const int cells = d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2];
-        const NlLds L = carve_nl(smem + kNlJobBytes, n, cells, kmax,
-                                 GL ? b.nbr + (size_t)blockIdx.x * b.nbr_stride : nullptr);
-        for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
-        // run_daughter_nl synchronises before its first use of the counts
-        run_daughter_nl<APT, NH, OBS, COL>(d, b.max_steps, L, kmax, n);
-    }
-}
-
-// ---------------------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------------------
 
@@ -2066,10 +1096,6 @@ int pick_apt(int n, int threads) {
     return -1;
 }
 
-size_t lds_bytes_nl(int n, int cells, int kmax, bool global_lists) {
-    return kNlJobBytes + plan_nl(n, cells, kmax, global_lists).total;
-}
-
 size_t lds_bytes_for(int nmax, int cmax, int threads, int precision) {
     (void)threads;
     return plan_lds(nmax, cmax, precision == 0 ? sizeof(double) : sizeof(float)).total;
@@ -2104,58 +1130,11 @@ static hipError_t launch_daughters_r(const BatchLaunch& b, hipStream_t s) {
     return hipErrorInvalidValue;
 }
 
-template <int APT, int MAXT, bool NH, bool OBS, bool COL, bool GL>
-static hipError_t launch_nl_t(const BatchLaunch& b, hipStream_t s) {
-    if (b.threads > MAXT) return hipErrorInvalidValue;
-    (void)hipFuncSetAttribute((const void*)k_daughters_nl<APT, MAXT, NH, OBS, COL, GL>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
-    hipLaunchKernelGGL((k_daughters_nl<APT, MAXT, NH, OBS, COL, GL>), dim3(b.grid),
-                       dim3(b.threads), b.lds_bytes, s, b);
-    return hipGetLastError();
-}
-
-template <bool NH, bool OBS, bool COL, bool GL = false>
-static hipError_t launch_nl(const BatchLaunch& b, hipStream_t s) {
-    if (b.threads <= 512) {
-        switch (b.apt) {
-            case 1: return launch_nl_t<1, 512, NH, OBS, COL, GL>(b, s);
-            case 2: return launch_nl_t<2, 512, NH, OBS, COL, GL>(b, s);
-            case 4: return launch_nl_t<4, 512, NH, OBS, COL, GL>(b, s);
-        }
-    } else {
-        switch (b.apt) {
-            case 1: return launch_nl_t<1, 1024, NH, OBS, COL, GL>(b, s);
-            case 2: return launch_nl_t<2, 1024, NH, OBS, COL, GL>(b, s);
-            case 4: return launch_nl_t<4, 1024, NH, OBS, COL, GL>(b, s);
-        }
-    }
-    return hipErrorInvalidValue;
-}
-
 hipError_t launch_daughters(const BatchLaunch& b, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, b.queue, 1);
     // one instantiation per daughter thermostat: the isokinetic build does not carry the
     // Nose-Hoover branch's registers (10% on the list form)
-    if (b.variant == kVariantNeighbourList) {
-        if (b.precision != 1) return hipErrorInvalidValue;
-        // the extra observables have their own instantiations, so the plain build carries
-        // none of their registers
-        // lists in global scratch: shear daughters of either thermostat, P_xy only
-        if (b.global_lists) {
-            if (b.obs || b.field || !b.nbr) return hipErrorInvalidValue;
-            return b.thermo ? launch_nl<true, false, false, true>(b, s)
-                            : launch_nl<false, false, false, true>(b, s);
-        }
-        // colour-field daughters: isokinetic, without the extra observables
-        if (b.field) {
-            if (b.obs) return hipErrorInvalidValue;
-            return b.thermo ? launch_nl<true, false, true>(b, s) : launch_nl<false, false, true>(b, s);
-        }
-        if (b.obs)
-            return b.thermo ? launch_nl<true, true, false>(b, s)
-                            : launch_nl<false, true, false>(b, s);
-        return b.thermo ? launch_nl<true, false, false>(b, s) : launch_nl<false, false, false>(b, s);
-    }
+    if (b.variant == kVariantNeighbourList) return launch_pairs(b, s);
     if (b.obs || b.field) return hipErrorInvalidValue;  // the cell form: shear and P_xy only
     if (b.thermo)
         return b.precision == 0 ? launch_daughters_r<double, true>(b, s)

@@ -1,0 +1,1032 @@
+// ttcf_pairs.hip -- pair-list form of the daughter step kernel on gfx950 (FP32 pair forces,
+// FP64 integration, thermostat and sums).
+//
+// One workgroup integrates one daughter at a time (persistent, jobs from a queue), four atoms
+// per thread: atom a belongs to thread a mod T_job, T_job = 64 ceil(n / 256), so a daughter's
+// arithmetic does not depend on the launch's workgroup size. Positions and momenta stay in
+// FP64 registers of their owner for the whole call.
+//
+// Pair list. Every pair closer than the list radius r_l = r_c + skin is stored once, as one
+// 32-bit word (two 14-bit atom ranks and the pair's y image), in a segment of per-workgroup
+// global scratch that belongs to one wave. The list is built from a cell grid whose cells
+// are at least r_l wide: the atoms are counting-sorted into canonical (cell, atom id) order
+// (their rank), and the atom of rank s scans the half of the 27-cell neighbourhood that lies
+// after it (its own cell past s, the next cell in x, the row above in y, and the three rows
+// of the next layer in z; rows across the y boundary are the Lees-Edwards images, displaced
+// by the offset). It is rebuilt when the atoms may have moved far enough for an unlisted pair
+// to reach r_c (the bound of the previous list form: 2 d + |gamma_dot| t (r_c + 2 d) >= skin,
+// d the largest peculiar path length since the build).
+//
+// Forces. A wave walks its own segment 64 pairs at a time, every lane busy. Each pair's force
+// is rounded to 32-bit fixed point (nearest multiple of 2^-19 force units) and added to both atoms with LDS integer
+// atomics (+ to one, - to the other). Integer sums do not depend on their order, so every
+// atom's force is independent of the list's order, of the skin and grid, of which lane or
+// wave evaluated a pair, and of the rebuild schedule; the total force is exactly zero. The
+// virial x_ij F_y,ij of each pair is rounded to a multiple of 2^-20 and summed as an exact
+// integer in FP64, so W_xy has the same independence.
+//
+// Separations come from 32-bit fixed-point positions X = round(x 2^32 / L) (the box is 2^32
+// units wide, so integer differences wrap to the minimum image). Between rebuilds the
+// published positions are unwrapped: an atom that crossed the y boundary c times keeps
+// X + c offset(t) in x, so each pair keeps the y image it was built with, and the separation
+// is X_i - X_j - n_y offset(t) with n_y stored in the pair word.
+#include "ttcf_device.h"
+
+namespace ttcf {
+namespace {
+
+constexpr int kPairThreads = 512;            // workgroup size (256 registers per lane)
+constexpr int kJobBytes = 128;               // job slot in front of the per-job LDS
+constexpr int kPfRed = 16;                   // doubles per thread in one block reduction
+constexpr float kForceUnits = 524288.0f;     // 2^19 fixed-point units per force unit
+constexpr float kForceStep = 1.0f / 524288.0f;
+constexpr float kSumUnits = 1048576.0f;      // 2^20 units per virial or energy unit
+constexpr double kSumStep = 1.0 / 1048576.0;
+constexpr double kRound52 = 6755399441055744.0;  // 1.5 * 2^52: adding it rounds to an integer
+constexpr double kTwo52 = 4503599627370496.0;    // 2^52
+
+struct PairLds {
+    uint4* pos;        // [n] by rank: fixed-point x, y, z; w = cx | cy << 10 | cz << 20
+    int4* facc;        // [n] by rank: fixed-point force accumulators (x, y, z, unused)
+    int32_t* cnt;      // [cells] counts, then placement cursors
+    int32_t* start;    // [cells + 1]
+    int32_t* rowinfo;  // [3 rows][2]: first x cell offset mod lc_x, cell count
+    double* red;       // [kMaxWaves * kPfRed] wave partials of the step's reduction
+    double* red2;      // the same for the extra-observable reduction
+    int32_t* scan;     // [kMaxWaves]
+    float* wmax;       // [kMaxWaves] wave maxima of the path length
+    int32_t* flags;    // [kMaxWaves] per wave: its pair list overflowed
+    double* ktab;      // [16] series coefficients of the isokinetic kick
+    SysDev* sys;
+    // during a rebuild the facc area holds the sorted atom ids (u16 [n]) and the rank of
+    // every atom id (u16 [n])
+};
+
+struct PairPlan {
+    size_t pos, facc, cnt, start, rowinfo, red, red2, scan, wmax, flags, ktab, sys, total;
+};
+
+__host__ __device__ inline size_t pf_align(size_t v, size_t a) { return (v + a - 1) & ~(a - 1); }
+
+__host__ __device__ inline PairPlan plan_pairs(int n, int cells) {
+    PairPlan p;
+    size_t off = 0;
+    auto take = [&](size_t bytes, size_t al) {
+        off = pf_align(off, al);
+        const size_t at = off;
+        off += bytes;
+        return at;
+    };
+    p.pos = take(16 * (size_t)n, 16);
+    p.facc = take(16 * (size_t)n, 16);
+    p.cnt = take(4 * (size_t)cells, 16);
+    p.start = take(4 * (size_t)(cells + 1), 16);
+    p.rowinfo = take(4 * 8, 16);
+    p.red = take(sizeof(double) * kMaxWaves * kPfRed, 16);
+    p.red2 = take(sizeof(double) * kMaxWaves * kPfRed, 16);
+    p.scan = take(4 * kMaxWaves, 16);
+    p.wmax = take(4 * kMaxWaves, 16);
+    p.flags = take(4 * kMaxWaves, 16);
+    p.ktab = take(sizeof(double) * 16, 16);
+    p.sys = take(sizeof(SysDev), 16);
+    p.total = pf_align(off, 128);
+    return p;
+}
+
+__device__ inline PairLds carve_pairs(char* base, int n, int cells) {
+    const PairPlan p = plan_pairs(n, cells);
+    PairLds L;
+    L.pos = (uint4*)(base + p.pos);
+    L.facc = (int4*)(base + p.facc);
+    L.cnt = (int32_t*)(base + p.cnt);
+    L.start = (int32_t*)(base + p.start);
+    L.rowinfo = (int32_t*)(base + p.rowinfo);
+    L.red = (double*)(base + p.red);
+    L.red2 = (double*)(base + p.red2);
+    L.scan = (int32_t*)(base + p.scan);
+    L.wmax = (float*)(base + p.wmax);
+    L.flags = (int32_t*)(base + p.flags);
+    L.ktab = (double*)(base + p.ktab);
+    L.sys = (SysDev*)(base + p.sys);
+    return L;
+}
+
+// Atoms per thread of a daughter of n atoms (4 up to 2048 atoms, else 8), and the threads that
+// own its atoms: a multiple of 64 up to 512.
+__host__ __device__ inline int job_apt(int n) { return n <= 4 * kPairThreads ? 4 : 8; }
+__host__ __device__ inline int job_threads(int n) {
+    const int per_wave = 64 * job_apt(n);
+    return ((n + per_wave - 1) / per_wave) * 64;
+}
+
+// round(v 2^32 / L) mod 2^32 for v in [0, L): one fused multiply-add puts the rounded value in
+// the low mantissa bits of 2^52 + v scale.
+__device__ __forceinline__ uint32_t fixq(double v, double scale) {
+    return (uint32_t)__double2loint(__builtin_fma(v, scale, kTwo52));
+}
+
+// round(a b 2^20) as an exact FP64 integer (|a b| < 2^31).
+__device__ __forceinline__ double quant(float a, float b) {
+    return __builtin_fma((double)a, (double)(b * kSumUnits), kRound52) - kRound52;
+}
+
+// The series coefficients of iso_kick_coeffs_tab, written to the job's LDS by one thread:
+// tab[k] = 1/(2k+2)! (k = 0..6), tab[7 + k] = 1/(2k+1)! (k = 0..7).
+__device__ __forceinline__ void write_kick_table(double* tab) {
+    double f = 1.0;  // running factorial
+    for (int m = 1; m <= 15; ++m) {
+        f *= (double)m;
+        if (m % 2 == 0) tab[m / 2 - 1] = 1.0 / f;
+        else tab[7 + m / 2] = 1.0 / f;
+    }
+}
+
+// iso_kick_coeffs with the series coefficients read from LDS where they are used (as
+// literals the compiler hoists them into registers for the whole step loop), and, for
+// q tau beyond the series' range, the argument halved until it is in range and the
+// doubling formulas sinh 2x = 2 sinh x cosh x, cosh 2x - 1 = 2 sinh^2 x applied back.
+// Returns s and sdot of the exact constrained kick over tau.
+__device__ __forceinline__ void iso_kick_coeffs_tab(double a, double b, double tau,
+                                                    const double* tab, double& s,
+                                                    double& sdot) {
+    double ch1_b, sh_q;
+    const double u = b * tau * tau;
+    if (u < 0.04) {
+        double c = tab[6];
+        for (int k = 5; k >= 0; --k) c = c * u + tab[k];
+        double d = tab[14];
+        for (int k = 6; k >= 0; --k) d = d * u + tab[7 + k];
+        ch1_b = tau * tau * c;
+        sh_q = tau * d;
+    } else {
+        int m = 0;
+        double v = u;
+        while (v >= 0.04) {
+            v *= 0.25;
+            ++m;
+        }
+        double c = tab[6];
+        for (int k = 5; k >= 0; --k) c = c * v + tab[k];
+        double d = tab[14];
+        for (int k = 6; k >= 0; --k) d = d * v + tab[7 + k];
+        const double th = sqrt(v);
+        double c1 = v * c, sh = th * d;  // cosh x - 1, sinh x at x = q tau / 2^m
+        for (int i = 0; i < m; ++i) {
+            const double nsh = 2.0 * sh * (1.0 + c1);
+            c1 = 2.0 * sh * sh;
+            sh = nsh;
+        }
+        const double q = sqrt(b);
+        ch1_b = c1 / b;
+        sh_q = sh / q;
+    }
+    s = a * ch1_b + sh_q;
+    sdot = a * sh_q + (1.0 + b * ch1_b);
+}
+
+// Sum K doubles over the first nw waves; every thread receives the totals. Fixed order: a
+// scan inside each wave (total in lane 63), then waves 0..nw-1 in sequence, done by lanes
+// 0..K-1 of every wave and broadcast from them. One barrier; `red` may be written again
+// only after a later barrier.
+template <int K>
+__device__ __forceinline__ void pf_block_sum(double (&v)[K], double* red, int nw) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = wave_total_dpp(v[k]);
+    if (lane == 63 && wave < nw) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave * kPfRed + k] = v[k];
+    }
+    __syncthreads();
+    double s = 0.0;
+    if (lane < K)
+        for (int w = 0; w < nw; ++w) s += red[w * kPfRed + lane];
+    const uint64_t u = __builtin_bit_cast(uint64_t, s);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const uint32_t l = (uint32_t)__builtin_amdgcn_readlane(lo, k);
+        const uint32_t h = (uint32_t)__builtin_amdgcn_readlane(hi, k);
+        v[k] = __builtin_bit_cast(double, ((uint64_t)h << 32) | l);
+    }
+}
+
+// The dynamic LDS of the kernels below: a job slot, then the running job's layout.
+extern __shared__ __align__(32) char pf_smem[];
+
+__device__ __forceinline__ PairLds job_lds(int n, int cells) {
+    return carve_pairs(pf_smem + kJobBytes, n, cells);
+}
+
+typedef __attribute__((address_space(1))) uint32_t gu32;  // global pair words
+
+// ---------------------------------------------------------------------------------------
+// list build
+// ---------------------------------------------------------------------------------------
+
+// Pairs of this wave's ranks (rank s tests the half neighbourhood after it) into `seg`
+// (capacity seg_cap). Returns the number found (wave-uniform; may exceed the capacity).
+// Out of line, so that the step loop's registers and these do not add up.
+template <int APT>
+__device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, gu32* seg,
+                                            int seg_cap, int tj) {
+    const PairLds L = job_lds(n, cells);
+    const SysDev& S = *L.sys;
+    const int nc0 = S.lc[0], nc1 = S.lc[1], nc2 = S.lc[2];
+    const int t = threadIdx.x, lane = t & 63;
+    int base = 0;  // wave-uniform: pairs found so far by this wave
+    if (t >= tj) return 0;
+    const float rl2 = S.rl2_f;
+    const float ux = S.fix_unit[0], uy = S.fix_unit[1], uz = S.fix_unit[2];
+    const int r0 = (t >> 6) * 64 * APT;
+#pragma unroll 1
+    for (int u = 0; u < APT; ++u) {
+        if (r0 + u * 64 >= n) break;  // wave-uniform
+        const int s = r0 + u * 64 + lane;
+        const bool own = s < n;
+        const uint4 qi = L.pos[own ? s : 0];
+        const int cx = (int)(qi.w & 1023u), cy = (int)((qi.w >> 10) & 1023u),
+                  cz = (int)(qi.w >> 20);
+#pragma unroll 1
+        for (int r = 0; r < 5; ++r) {
+            // row r: (dz, dy) = (0, 0) own cell past s and the next cell in x; (0, +1);
+            // (+1, -1), (+1, 0), (+1, +1) -- the 3-cell x window, or for a row across the y
+            // boundary the window of its displaced image
+            int lo0, hi0, lo1 = 0, hi1 = 0, ny = 0;
+            if (r == 0) {
+                const int rowb = nc0 * (cy + nc1 * cz);
+                lo0 = s + 1;
+                if (cx + 1 < nc0) {
+                    hi0 = L.start[rowb + cx + 2];
+                } else {
+                    hi0 = L.start[rowb + cx + 1];
+                    lo1 = L.start[rowb];
+                    hi1 = L.start[rowb + 1];
+                }
+            } else {
+                const int dz = r == 1 ? 0 : 1;
+                const int dy = r == 1 ? 1 : r - 3;
+                int zz = cz + dz;
+                if (zz >= nc2) zz -= nc2;
+                int yy = cy + dy;
+                if (yy < 0) {
+                    yy += nc1;
+                    ny = -1;
+                } else if (yy >= nc1) {
+                    yy -= nc1;
+                    ny = 1;
+                }
+                int x0, nq;
+                if (ny == 0) {
+                    x0 = cx == 0 ? nc0 - 1 : cx - 1;
+                    nq = 3;
+                } else {
+                    const int row = ny > 0 ? 2 : 0;
+                    x0 = cx + L.rowinfo[2 * row];
+                    if (x0 >= nc0) x0 -= nc0;
+                    nq = L.rowinfo[2 * row + 1];
+                }
+                // cells x0 .. x0 + nq - 1 (mod lc_x): one or two rank ranges (the start of
+                // cell lc_x of a row is the end of the row)
+                const int xe = x0 + nq;
+                const int rowb = nc0 * (yy + nc1 * zz);
+                lo0 = L.start[rowb + x0];
+                if (xe <= nc0) {
+                    hi0 = L.start[rowb + xe];
+                } else {
+                    hi0 = L.start[rowb + nc0];
+                    lo1 = L.start[rowb];
+                    hi1 = L.start[rowb + xe - nc0];
+                }
+            }
+            const uint32_t rsh = ny > 0 ? dxq : (ny < 0 ? 0u - dxq : 0u);
+            const int len0 = own ? max(hi0 - lo0, 0) : 0;
+            const int len = len0 + (own ? max(hi1 - lo1, 0) : 0);
+            const uint32_t wbase = (uint32_t)s | ((uint32_t)(ny + 1) << 28);
+            // one candidate per lane per trip; trips until the wave's longest row is done
+            for (int v = 0; __builtin_amdgcn_ballot_w64(v < len) != 0; ++v) {
+                const bool valid = v < len;
+                const int k = !valid ? s : (v < len0 ? lo0 + v : lo1 + (v - len0));
+                const uint4 q = L.pos[own ? k : 0];
+                const float ddx = (float)(int32_t)(qi.x - q.x - rsh) * ux;
+                const float ddy = (float)(int32_t)(qi.y - q.y) * uy;
+                const float ddz = (float)(int32_t)(qi.z - q.z) * uz;
+                const bool hit = valid & (ddx * ddx + ddy * ddy + ddz * ddz < rl2);
+                const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const int at = base + below;
+                if (hit && at < seg_cap) seg[at] = wbase | ((uint32_t)k << 14);
+                base += (int)__builtin_popcountll(m);
+            }
+        }
+    }
+    return base;
+}
+
+// Rebuild at Lees-Edwards offset dxle (dxq in fixed point) from the owners' FP64 positions:
+// canonical (cell, id) ranks on the list grid, positions published (crossing counts reset),
+// this wave's pairs in `seg`. Returns the wave's pair count (may exceed seg_cap); *overflow
+// receives whether any wave's list overflowed (the same in every thread). cell: the list-grid
+// cell of each owned atom (-1 past n). Every thread of the workgroup calls it.
+template <int APT>
+__device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t dxq,
+                                          const double (&x)[APT], const double (&y)[APT],
+                                          const double (&z)[APT], int (&rank)[APT],
+                                          int (&cr)[APT], const PairLds& L, gu32* seg,
+                                          int seg_cap, int tj, int (&cell)[APT], bool* overflow) {
+    const int T = blockDim.x, t = threadIdx.x, n = S.n;
+    const int nc0 = S.lc[0], nc1 = S.lc[1], nc2 = S.lc[2];
+    const int C = nc0 * nc1 * nc2;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * tj;
+        cell[j] = -1;
+        if (t < tj && a < n) {
+            const int cx = cell_coord(x[j], S.l_inv_w[0], nc0);
+            const int cy = cell_coord(y[j], S.l_inv_w[1], nc1);
+            const int cz = cell_coord(z[j], S.l_inv_w[2], nc2);
+            cell[j] = cx + nc0 * (cy + nc1 * cz);
+            atomicAdd(&L.cnt[cell[j]], 1);
+        }
+    }
+    if (t == 0) {
+        // x windows of the rows across the y boundary: every cell whose image (displaced by
+        // -+dxle) overlaps [cx w - r_l, (cx + 1) w + r_l], plus a margin for the FP32 test
+        const double reach = S.rc + S.skin;
+        const double wx = S.lw[0];
+        const double margin = 1e-6 * reach;
+        for (int row = 0; row < 3; row += 2) {
+            double sh = (row == 0 ? -1.0 : 1.0) * dxle;
+            sh -= S.box[0] * rint(sh / S.box[0]);
+            const int off = (int)floor((-reach - margin - sh) / wx);
+            const int hi = (int)floor((wx + reach + margin - sh) / wx);
+            int nq = hi - off + 1;
+            if (nq > nc0) nq = nc0;
+            L.rowinfo[2 * row] = ((off % nc0) + nc0) % nc0;
+            L.rowinfo[2 * row + 1] = nq;
+        }
+    }
+    __syncthreads();
+    scan_cells(L.cnt, L.start, C, L.scan);
+    if (t == 0) L.start[C] = n;
+    __syncthreads();
+    uint16_t* sid = (uint16_t*)L.facc;
+    uint16_t* rk = sid + n;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        if (cell[j] >= 0) {
+            const int idx = atomicAdd(&L.cnt[cell[j]], 1);
+            sid[idx] = (uint16_t)(t + j * tj);
+        }
+    }
+    __syncthreads();
+    // canonical order inside each cell (ascending id), the rank of every atom, cursors reset
+    for (int c = t; c < C; c += T) {
+        const int lo = L.start[c], hi = L.start[c + 1];
+        for (int i = lo + 1; i < hi; ++i) {
+            const uint16_t v = sid[i];
+            int k = i - 1;
+            while (k >= lo && sid[k] > v) {
+                sid[k + 1] = sid[k];
+                --k;
+            }
+            sid[k + 1] = v;
+        }
+        for (int i = lo; i < hi; ++i) rk[sid[i]] = (uint16_t)i;
+        L.cnt[c] = 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * tj;
+        cr[j] = 0;
+        rank[j] = 0;
+        if (cell[j] >= 0) {
+            rank[j] = rk[a];
+            const int c = cell[j];
+            const uint32_t cx = (uint32_t)(c % nc0), cy = (uint32_t)((c / nc0) % nc1),
+                           cz = (uint32_t)(c / (nc0 * nc1));
+            L.pos[rank[j]] = make_uint4(fixq(x[j], S.fix_scale[0]), fixq(y[j], S.fix_scale[1]),
+                                        fixq(z[j], S.fix_scale[2]), cx | (cy << 10) | (cz << 20));
+        }
+    }
+    __syncthreads();
+    // the scratch is free again: clear the force accumulators for the next force pass
+    for (int i = t; i < n; i += T) L.facc[i] = make_int4(0, 0, 0, 0);
+    const int count = pf_gen_pairs<APT>(n, C, dxq, seg, seg_cap, tj);
+    const int wave = t >> 6, nwb = T >> 6;
+    if ((t & 63) == 0) L.flags[wave] = count > seg_cap ? 1 : 0;
+    __syncthreads();
+    int any = 0;
+    for (int w = 0; w < nwb; ++w) any |= L.flags[w];
+    *overflow = any != 0;
+    return count;
+}
+
+// ---------------------------------------------------------------------------------------
+// force pass
+// ---------------------------------------------------------------------------------------
+
+// Lane shares of the pair sums of one force pass, in units of 2^-20 (exact integers): W_xy,
+// and (OBS) W_xx, W_yy, W_zz and U; close: a pair came inside the guard radius.
+struct PfSums {
+    double w, xx, yy, zz, u;
+    int close;
+};
+
+// Forces of this wave's `count` pairs into the fixed-point accumulators. Out of line, so
+// that the step loop's registers and these do not add up.
+template <bool OBS>
+__device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
+                                                      const gu32* seg, int count) {
+    const PairLds L = job_lds(n, cells);
+    const SysDev& S = *L.sys;
+    const int lane = threadIdx.x & 63;
+    const float rc2 = S.rc2_f, rg2 = S.rg2_f;
+    const float ca = (float)S.c_attr;
+    const float ushift = (float)S.u_shift;
+    const float ux = S.fix_unit[0], uy = S.fix_unit[1], uz = S.fix_unit[2];
+    PfSums o{0.0, 0.0, 0.0, 0.0, 0.0, 0};
+    bool close = false;
+    uint32_t wn = lane < count ? seg[lane] : 0u;
+    for (int p0 = 0; p0 < count; p0 += 64) {
+        const bool live = p0 + lane < count;
+        const uint32_t word = wn;
+        wn = p0 + 64 + lane < count ? seg[p0 + 64 + lane] : 0u;
+        const int si = (int)(word & 0x3FFFu), sj = (int)((word >> 14) & 0x3FFFu);
+        const uint32_t img = word >> 28;  // n_y + 1
+        const uint4 qi = L.pos[si];
+        const uint4 qj = L.pos[sj];
+        const uint32_t sh = img == 2u ? dxq : (img == 0u ? 0u - dxq : 0u);
+        const float dx = (float)(int32_t)(qi.x - qj.x - sh) * ux;
+        const float dy = (float)(int32_t)(qi.y - qj.y) * uy;
+        const float dz = (float)(int32_t)(qi.z - qj.z) * uz;
+        const float r2 = dx * dx + dy * dy + dz * dz;
+        if (live & (r2 < rc2)) {
+            const float inv = recip(r2);
+            const float s3 = inv * inv * inv;
+            const float fs = s3 * (48.f * s3 - 24.f * ca) * inv;
+            const float gx = fs * dx, gy = fs * dy, gz = fs * dz;
+            close |= r2 < rg2;
+            // rounded to the nearest unit (ties to even, so symmetric): the two atoms get
+            // exactly opposite increments
+            const int qx = __float2int_rn(gx * kForceUnits), qy = __float2int_rn(gy * kForceUnits),
+                      qz = __float2int_rn(gz * kForceUnits);
+            int* ai = (int*)&L.facc[si];
+            int* aj = (int*)&L.facc[sj];
+            atomicAdd(ai + 0, qx);
+            atomicAdd(ai + 1, qy);
+            atomicAdd(ai + 2, qz);
+            atomicAdd(aj + 0, -qx);
+            atomicAdd(aj + 1, -qy);
+            atomicAdd(aj + 2, -qz);
+            o.w += quant(dx, gy);
+            if (OBS) {
+                o.xx += quant(dx, gx);
+                o.yy += quant(dy, gy);
+                o.zz += quant(dz, gz);
+                o.u += quant(1.0f, 4.f * s3 * (s3 - ca) + ushift);
+            }
+        }
+    }
+    o.close = close ? 1 : 0;
+    return o;
+}
+
+// ---------------------------------------------------------------------------------------
+// extra observables
+// ---------------------------------------------------------------------------------------
+
+// The extra observables at one time point: kinetic parts from the owned atoms' momenta p,
+// pair parts (exact integers in units of 2^-20) of the force pass, reduced over the
+// workgroup (kinetic and pair sums in separate slots) and written by thread 0 to row `row`.
+template <int APT>
+__device__ __forceinline__ void pf_record_obs(const SysDev& S, const double (&y)[APT],
+                                              const double (&px)[APT], const double (&py)[APT],
+                                              const double (&pz)[APT], const PfSums& ps,
+                                              double* xs, int row, const PairLds& L, int nw) {
+    double o[kObsCols + 4];
+#pragma unroll
+    for (int c = 0; c < kObsCols; ++c) o[c] = 0.0;
+    const double slab_scale = (double)kObsSlabs / S.box[1];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        // lanes past n hold zero momenta and add nothing
+        const double xx = px[j] * px[j], yy = py[j] * py[j], zz = pz[j] * pz[j];
+        o[0] += xx - yy;
+        o[1] += yy - zz;
+        o[2] += 0.5 * (xx + yy + zz);
+        int sl = (int)floor(y[j] * slab_scale);
+        sl = sl < 0 ? 0 : (sl > kObsSlabs - 1 ? kObsSlabs - 1 : sl);
+#pragma unroll
+        for (int q = 0; q < kObsSlabs; ++q) o[3 + q] += sl == q ? px[j] : 0.0;
+    }
+    o[kObsCols] = ps.xx;
+    o[kObsCols + 1] = ps.yy;
+    o[kObsCols + 2] = ps.zz;
+    o[kObsCols + 3] = ps.u;
+    pf_block_sum<kObsCols + 4>(o, L.red2, nw);
+    if (threadIdx.x == 0) {
+        const double wxx = o[kObsCols] * kSumStep, wyy = o[kObsCols + 1] * kSumStep,
+                     wzz = o[kObsCols + 2] * kSumStep, u = o[kObsCols + 3] * kSumStep;
+        double* out = xs + (size_t)row * kObsCols;
+        const double iv = 1.0 / S.volume;
+        out[0] = (o[0] + (wxx - wyy)) * iv;
+        out[1] = (o[1] + (wyy - wzz)) * iv;
+        out[2] = (o[2] + u) / (double)S.n;
+#pragma unroll
+        for (int q = 0; q < kObsSlabs; ++q) out[3 + q] = o[3 + q] * ((double)kObsSlabs * iv);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// one daughter
+// ---------------------------------------------------------------------------------------
+
+// Publish the owned atoms' fixed-point positions (unwrapped by their crossing counts) and
+// return the workgroup maximum of their path lengths since the last build (one barrier).
+template <int APT>
+__device__ __forceinline__ float pf_publish(const SysDev& S, uint32_t dxq, const double (&x)[APT],
+                                            const double (&y)[APT], const double (&z)[APT],
+                                            const int (&rank)[APT], const int (&cr)[APT],
+                                            const float (&path)[APT], const PairLds& L, int tj,
+                                            int nw) {
+    const int t = threadIdx.x, n = S.n;
+    float pm = 0.f;
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * tj;
+        if (t < tj && a < n) {
+            // x, y, z only: w keeps the cell of the last build
+            *(uint3*)&L.pos[rank[j]] =
+                make_uint3(fixq(x[j], S.fix_scale[0]) + (uint32_t)cr[j] * dxq,
+                           fixq(y[j], S.fix_scale[1]), fixq(z[j], S.fix_scale[2]));
+            pm = fmaxf(pm, path[j]);
+        }
+    }
+    pm = wave_max_dpp(pm);
+    if ((t & 63) == 63) L.wmax[t >> 6] = pm;
+    __syncthreads();
+    float m = 0.f;
+    for (int w = 0; w < nw; ++w) m = fmaxf(m, L.wmax[w]);
+    return m;
+}
+
+// Daughter step, h = dt, tau = h/2, tg = tau gamma_dot. Both thermostats split the step as
+//   [first half] D(h) [forces] [second half],
+// isokinetic: first half S(tau) K(tau), second half K(tau) S(tau) and the rescale to K0 (the
+// exact constrained flows, closed forms from the moments of (p, F)); Nose-Hoover (Eq.
+// system1 as printed): first half Z(tau) T(tau) S(tau) K(tau), second half K(tau) S(tau)
+// T(tau) Z(tau). Either half maps p to a p + b F + c p_y x_hat + d F_y x_hat (y, z: a p + b F)
+// with scalars from the moments reduced once per step, so the second half of one step and the
+// first half of the next are applied together as one update of the momenta; the end-of-step
+// moments that B(t) and the next first half need follow in closed form.
+// COL: the build that also runs colour-field daughters (either thermostat): atom a carries
+// the colour charge +1 (even a) or -1 (odd a), the field adds charge * F_e to its x force in
+// FP64, there is no shear, and the series records V J_x = sum_a charge p_x,a.
+template <int APT, bool NH, bool OBS, bool COL>
+__device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairLds& L,
+                                   gu32* pair_base) {
+    const int t = threadIdx.x;
+    if (t == 0) {
+        *L.sys = dsc->sys;
+        write_kick_table(L.ktab);
+    }
+    __syncthreads();
+    const SysDev& S = *L.sys;
+    const int n = S.n;
+    const int cells = S.lc[0] * S.lc[1] * S.lc[2];
+    const int tj = job_threads(n);
+    const int nw = tj >> 6;
+    const int wave = t >> 6;
+    double* st = dsc->state;
+    const bool col = COL && dsc->field == kFieldColour;  // uniform per job
+    const double gd = col ? 0.0 : dsc->gamma_dot;
+    int64_t k = dsc->k;
+    int done = dsc->done;
+    const int n_steps = dsc->n_steps;
+    double k0 = dsc->k0;
+    int health = dsc->health;
+    double zt = dsc->zeta;
+    const double nh_iq = NH ? 1.0 / dsc->nh_q : 0.0, nh_tgt = dsc->nh_target;
+    int todo = min(steps_cap, n_steps - done);
+    if (health != 0) todo = 0;
+    if (todo <= 0 && done > 0) return;
+    // this wave's pair segment
+    const int seg_cap = dsc->kmax * 64 * APT;
+    gu32* seg = pair_base + (size_t)wave * seg_cap;
+
+    double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT];
+    float fx[APT], fy[APT], fz[APT];  // FP32 forces; every use promotes them to FP64
+    int rank[APT], cr[APT], cell[APT];
+    float path[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * tj;
+        const bool v = t < tj && a < n;
+        x[j] = v ? st[a] : 0.0;
+        y[j] = v ? st[n + a] : 0.0;
+        z[j] = v ? st[2 * n + a] : 0.0;
+        px[j] = v ? st[3 * n + a] : 0.0;
+        py[j] = v ? st[4 * n + a] : 0.0;
+        pz[j] = v ? st[5 * n + a] : 0.0;
+        path[j] = 0.f;
+        fx[j] = fy[j] = fz[j] = 0.f;
+    }
+    // colour charges (zero past n and for shear daughters) and the field's x force in FP64
+    double ce[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * tj;
+        const double cq = (COL && col && t < tj && a < n) ? ((a & 1) ? -1.0 : 1.0) : 0.0;
+        ce[j] = COL ? cq * dsc->fe : 0.0;
+    }
+    auto charge = [&](int j) -> double { return ((t + j * tj) & 1) ? -1.0 : 1.0; };
+    auto fxd = [&](int j) -> double {
+        if constexpr (COL)
+            return (double)fx[j] + ce[j];
+        else
+            return (double)fx[j];
+    };
+    double dxle = le_offset(S, gd, k);
+    uint32_t dxq = fix32(dxle, S.fix_scale[0]);
+    PfSums ps{0.0, 0.0, 0.0, 0.0, 0.0, 0};
+    bool ovf = false;
+    // forces of the start state
+    int count = pf_rebuild<APT>(S, dxle, dxq, x, y, z, rank, cr, L, seg, seg_cap, tj, cell, &ovf);
+    if (ovf) health |= kHealthListOverflow;
+    count = min(count, seg_cap);
+    if (t < tj) ps = pf_forces<OBS>(n, cells, dxq, seg, count);
+    __syncthreads();
+    auto readback = [&]() {
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const int a = t + j * tj;
+            if (t < tj && a < n) {
+                const int4 q = L.facc[rank[j]];
+                fx[j] = (float)q.x * kForceStep;
+                fy[j] = (float)q.y * kForceStep;
+                fz[j] = (float)q.z * kForceStep;
+                L.facc[rank[j]] = make_int4(0, 0, 0, 0);
+            }
+        }
+    };
+    readback();
+    double* const xs = OBS ? dsc->xseries : nullptr;
+
+    double m0[8] = {0, 0, 0, 0, 0, 0, ps.w, (double)ps.close};
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        // one multiply-add with a selected factor, so that shear daughters get the same
+        // contractions in every build
+        const double w1 = (COL && col) ? charge(j) : py[j];
+        m0[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j];
+        m0[1] += w1 * px[j];
+        m0[2] += py[j] * py[j];
+        m0[3] += fxd(j) * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
+        m0[4] += fxd(j) * py[j];
+        m0[5] += fxd(j) * fxd(j) + (double)fy[j] * (double)fy[j] +
+                 (double)fz[j] * (double)fz[j];
+    }
+    pf_block_sum<8>(m0, L.red, nw);
+    if (m0[7] != 0.0) health |= kHealthForceRange;
+    if (done == 0) {
+        if (k0 <= 0.0) k0 = 0.5 * m0[0];
+        if (t == 0) dsc->series[0] = (COL && col) ? m0[1] : m0[1] + m0[6] * kSumStep;
+        if (OBS && xs) pf_record_obs<APT>(S, y, px, py, pz, ps, xs, 0, L, nw);
+    }
+    if (health != 0) todo = 0;
+    const double h = S.dt, tau = 0.5 * S.dt, tg = tau * gd;
+    const float reach = (float)S.rc;
+    const float skin = (float)S.skin;
+    const float agd = (float)fabs(gd);
+    int since = 0;
+    // First half of a step from the end-of-step moments pp, pxpy, pypy, fp, fxpy, ff (F the
+    // current forces): p -> e p + g p_y x_hat + hh F.
+    double pp = m0[0], pxpy = m0[1], pypy = m0[2], fp = m0[3], fxpy = m0[4], ff = m0[5];
+    auto first_half = [&](double& e, double& g, double& hh) {
+        if (NH) {
+            zt += tau * (pp - nh_tgt) * nh_iq;
+            const double c1 = exp(-zt * tau);
+            e = c1;
+            g = -tg * c1;
+            hh = tau;
+        } else {
+            const double ppt = pp - 2.0 * tg * pxpy + tg * tg * pypy;
+            const double g1 = sqrt(pp / ppt);
+            const double fp1 = g1 * (fp - tg * fxpy);
+            double s1, sd1;
+            iso_kick_coeffs_tab(fp1 / pp, ff / pp, tau, L.ktab, s1, sd1);
+            const double isd1 = 1.0 / sd1;
+            e = g1 * isd1;
+            g = -tg * e;
+            hh = s1 * isd1;
+        }
+    };
+    if (todo > 0) {
+        double e, g, hh;
+        first_half(e, g, hh);
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double qx = e * px[j] + g * py[j] + hh * fxd(j);
+            py[j] = e * py[j] + hh * (double)fy[j];
+            pz[j] = e * pz[j] + hh * (double)fz[j];
+            px[j] = qx;
+        }
+    }
+
+    for (int step = 0; step < todo; ++step) {
+        // ---- streaming D(h), new strain, sliding-brick wrap (crossings counted), path length
+        k += 1;
+        dxle = le_offset(S, gd, k);
+        dxq = fix32(dxle, S.fix_scale[0]);
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double vx = px[j] + tg * py[j];
+            path[j] += (float)h * sqrtf((float)(vx * vx + py[j] * py[j] + pz[j] * pz[j]));
+            x[j] += h * px[j] + h * gd * (y[j] + tau * py[j]);
+            y[j] += h * py[j];
+            z[j] += h * pz[j];
+            cr[j] += y[j] >= S.box[1] ? 1 : (y[j] < 0.0 ? -1 : 0);
+            wrap_le(S, dxle, x[j], y[j], z[j]);
+        }
+        const float dm = pf_publish<APT>(S, dxq, x, y, z, rank, cr, path, L, tj, nw);
+        ++since;
+        const float tsince = (float)(since * h);
+        if (2.f * dm + agd * tsince * (reach + 2.f * dm) >= skin) {
+            count = pf_rebuild<APT>(S, dxle, dxq, x, y, z, rank, cr, L, seg, seg_cap, tj, cell, &ovf);
+            if (ovf) {  // the same in every thread
+                health |= kHealthListOverflow;
+                break;
+            }
+#pragma unroll
+            for (int j = 0; j < APT; ++j) path[j] = 0.f;
+            since = 0;
+        }
+        if (t < tj) ps = pf_forces<OBS>(n, cells, dxq, seg, count);
+        __syncthreads();
+        readback();
+        // ---- moments of (p, F): pp, pxpy, pypy, fp, fxpy, fypx, fxfy, fypy, fyfy, ff, W,
+        // range flag; a non-finite position makes pp non-finite (0 times it)
+        double m[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, ps.w, (double)ps.close};
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double w1 = (COL && col) ? charge(j) : py[j];  // as for m0
+            m[0] += px[j] * px[j] + py[j] * py[j] + pz[j] * pz[j] + 0.0 * (x[j] + y[j] + z[j]);
+            m[1] += w1 * px[j];
+            m[2] += py[j] * py[j];
+            m[3] += fxd(j) * px[j] + (double)fy[j] * py[j] + (double)fz[j] * pz[j];
+            m[4] += w1 * fxd(j);
+            m[5] += (double)fy[j] * px[j];
+            m[6] += fxd(j) * (double)fy[j];
+            m[7] += (double)fy[j] * py[j];
+            m[8] += (double)fy[j] * (double)fy[j];
+            m[9] += fxd(j) * fxd(j) + (double)fy[j] * (double)fy[j] +
+                    (double)fz[j] * (double)fz[j];
+        }
+        pf_block_sum<12>(m, L.red, nw);
+        // ---- second half: p_end = A p + B F + (C p_y + D F_y) x_hat, end-of-step moments
+        double A, B, C, D, vpxy;
+        bool drift = false;
+        if (NH) {
+            const double c2 = exp(-zt * tau);
+            A = c2;
+            B = c2 * tau;
+            C = -c2 * tg;
+            D = C * tau;
+            pp = A * A * m[0] + 2.0 * A * B * m[3] + B * B * m[9] + C * C * m[2] +
+                 2.0 * C * D * m[7] + D * D * m[8] + 2.0 * A * C * m[1] + 2.0 * A * D * m[5] +
+                 2.0 * B * C * m[4] + 2.0 * B * D * m[6];
+            pxpy = A * A * m[1] + A * B * (m[5] + m[4]) + B * B * m[6] + A * C * m[2] +
+                   (B * C + A * D) * m[7] + B * D * m[8];
+            zt += tau * (pp - nh_tgt) * nh_iq;
+        } else {
+            double s2, sd2;
+            iso_kick_coeffs_tab(m[3] / m[0], m[9] / m[0], tau, L.ktab, s2, sd2);
+            const double isd2 = 1.0 / sd2;
+            const double pp3 = (m[0] + 2.0 * s2 * m[3] + s2 * s2 * m[9]) * isd2 * isd2;
+            const double pxpy3 = (m[1] + s2 * (m[4] + m[5]) + s2 * s2 * m[6]) * isd2 * isd2;
+            const double pypy3 = (m[2] + 2.0 * s2 * m[7] + s2 * s2 * m[8]) * isd2 * isd2;
+            const double fp3 = (m[3] + s2 * m[9]) * isd2;
+            const double fxpy3 = (m[4] + s2 * m[6]) * isd2;
+            const double ppt2 = pp3 - 2.0 * tg * pxpy3 + tg * tg * pypy3;
+            const double c = sqrt(2.0 * k0 / ppt2);
+            A = c * isd2;
+            B = A * s2;
+            C = -tg * A;
+            D = -tg * B;
+            pp = c * c * ppt2;
+            pxpy = c * c * (pxpy3 - tg * pypy3);
+            pypy = c * c * pypy3;
+            fp = c * (fp3 - tg * fxpy3);
+            fxpy = c * fxpy3;
+            ff = m[9];
+            drift = fabs(pp3 / m[0] - 1.0) > 1e-10;
+        }
+        // colour: V J_x of the final momenta from the charge moments (no shear: C = D = 0)
+        vpxy = (COL && col) ? A * m[1] + B * m[4] : pxpy + m[10] * kSumStep;
+        done += 1;
+        if (t == 0) dsc->series[done] = vpxy;
+        if (m[11] != 0.0) health |= kHealthForceRange;
+        if (!isfinite(vpxy) || !isfinite(pp) || !isfinite(zt)) health |= kHealthNonFinite;
+        if (drift) health |= kHealthDrift;
+        const bool last = step + 1 == todo || health != 0;
+        if (OBS && xs) {
+            double qx[APT], qy[APT], qz[APT];
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                qx[j] = A * px[j] + B * fxd(j) + C * py[j] + D * (double)fy[j];
+                qy[j] = A * py[j] + B * (double)fy[j];
+                qz[j] = A * pz[j] + B * (double)fz[j];
+            }
+            pf_record_obs<APT>(S, y, qx, qy, qz, ps, xs, done, L, nw);
+        }
+        if (last) {
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                const double qx = A * px[j] + B * fxd(j) + C * py[j] + D * (double)fy[j];
+                py[j] = A * py[j] + B * (double)fy[j];
+                pz[j] = A * pz[j] + B * (double)fz[j];
+                px[j] = qx;
+            }
+            break;
+        }
+        // ---- the next step's first half, applied together with this second half
+        double e, g, hh;
+        first_half(e, g, hh);
+        const double K1 = e * A, K2 = e * C + g * A, K3 = e * B + hh, K4 = e * D + g * B;
+#pragma unroll
+        for (int j = 0; j < APT; ++j) {
+            const double qx = K1 * px[j] + K2 * py[j] + K3 * fxd(j) + K4 * (double)fy[j];
+            py[j] = K1 * py[j] + K3 * (double)fy[j];
+            pz[j] = K1 * pz[j] + K3 * (double)fz[j];
+            px[j] = qx;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * tj;
+        if (t < tj && a < n) {
+            st[a] = x[j];
+            st[n + a] = y[j];
+            st[2 * n + a] = z[j];
+            st[3 * n + a] = px[j];
+            st[4 * n + a] = py[j];
+            st[5 * n + a] = pz[j];
+        }
+    }
+    if (t == 0) {
+        dsc->k = k;
+        dsc->done = done;
+        dsc->k0 = k0;
+        dsc->health = health;
+        dsc->zeta = zt;
+    }
+    // the accumulators must be zero for the next job (a call that stopped after a force pass
+    // without reading it back would leave forces in them)
+    for (int i = t; i < n; i += blockDim.x) L.facc[i] = make_int4(0, 0, 0, 0);
+    __syncthreads();
+}
+
+template <int APT, bool NH, bool OBS, bool COL>
+__global__ __launch_bounds__(kPairThreads) void k_daughters_pairs(BatchLaunch b) {
+    int32_t* job = (int32_t*)pf_smem;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) *job = atomicAdd(b.queue, 1);
+        __syncthreads();
+        const int j = __builtin_amdgcn_readfirstlane(*job);
+        if (j >= b.n_jobs) break;
+        DaughterDesc* d = &b.descs[b.order[j]];
+        const int n = d->sys.n;
+        const int cells = d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2];
+        const PairLds L = job_lds(n, cells);
+        for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) L.facc[i] = make_int4(0, 0, 0, 0);
+        // run_daughter_pairs synchronises before its first use of the counts
+        run_daughter_pairs<APT, NH, OBS, COL>(d, b.max_steps, L,
+                                         (gu32*)(b.pairs + (size_t)blockIdx.x * b.pair_stride));
+    }
+}
+
+// The list build and one force pass on given positions, with the step kernel's own
+// functions (one workgroup): list-grid cell and rank of every atom, the cell starts, the
+// pair words of every wave segment (translated to atom ids by the host), the forces the
+// integrator would use, W_xy, and flags.
+template <int APT>
+__global__ __launch_bounds__(kPairThreads) void k_debug_pair_form(
+    SysDev Sg, double gamma_dot, int64_t kstep, const double* r, int32_t kcap, uint32_t* pairs,
+    int32_t* seg_count, int32_t* cell_of, int32_t* rank_of, int32_t* start, double* f,
+    double* out) {
+    const int cells = Sg.lc[0] * Sg.lc[1] * Sg.lc[2];
+    const PairLds L = job_lds(Sg.n, cells);
+    const int t = threadIdx.x;
+    if (t == 0) *L.sys = Sg;
+    for (int c = t; c < cells; c += blockDim.x) L.cnt[c] = 0;
+    for (int i = t; i < Sg.n; i += blockDim.x) L.facc[i] = make_int4(0, 0, 0, 0);
+    __syncthreads();
+    const SysDev& S = *L.sys;
+    const int n = S.n, tj = job_threads(n), wave = t >> 6;
+    double x[APT], y[APT], z[APT];
+    int rank[APT], cr[APT], cell[APT];
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * tj;
+        const bool v = t < tj && a < n;
+        x[j] = v ? r[a] : 0.0;
+        y[j] = v ? r[n + a] : 0.0;
+        z[j] = v ? r[2 * n + a] : 0.0;
+    }
+    const double dxle = le_offset(S, gamma_dot, kstep);
+    const uint32_t dxq = fix32(dxle, S.fix_scale[0]);
+    const int seg_cap = kcap * 64 * APT;
+    gu32* seg = (gu32*)(pairs + (size_t)wave * seg_cap);
+    bool ovf = false;
+    const int count = pf_rebuild<APT>(S, dxle, dxq, x, y, z, rank, cr, L, seg, seg_cap, tj, cell, &ovf);
+    PfSums ps{0.0, 0.0, 0.0, 0.0, 0.0, 0};
+    if (t < tj) ps = pf_forces<false>(n, cells, dxq, seg, min(count, seg_cap));
+    if ((t & 63) == 0 && t < tj) seg_count[wave] = count;
+    __syncthreads();
+    double m[2] = {ps.w, (double)ps.close};
+    pf_block_sum<2>(m, L.red, tj >> 6);
+#pragma unroll
+    for (int j = 0; j < APT; ++j) {
+        const int a = t + j * tj;
+        if (t < tj && a < n) {
+            const int4 q = L.facc[rank[j]];
+            f[a] = (double)((float)q.x * kForceStep);
+            f[n + a] = (double)((float)q.y * kForceStep);
+            f[2 * n + a] = (double)((float)q.z * kForceStep);
+            cell_of[a] = cell[j];
+            rank_of[a] = rank[j];
+        }
+    }
+    for (int c = t; c <= cells; c += blockDim.x) start[c] = L.start[c];
+    if (t == 0) {
+        out[0] = m[0] * kSumStep;
+        out[1] = m[1];
+        out[2] = dxle;
+    }
+}
+
+}  // namespace
+
+int pair_job_threads(int n) { return job_threads(n); }
+int pair_job_apt(int n) { return job_apt(n); }
+
+size_t lds_bytes_pairs(int n, int cells) { return kJobBytes + plan_pairs(n, cells).total; }
+
+template <int APT, bool NH, bool OBS, bool COL>
+static hipError_t launch_pairs_t(const BatchLaunch& b, hipStream_t s) {
+    (void)hipFuncSetAttribute((const void*)k_daughters_pairs<APT, NH, OBS, COL>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
+    hipLaunchKernelGGL((k_daughters_pairs<APT, NH, OBS, COL>), dim3(b.grid), dim3(b.threads),
+                       b.lds_bytes, s, b);
+    return hipGetLastError();
+}
+
+template <bool NH, bool OBS, bool COL>
+static hipError_t launch_pairs_a(const BatchLaunch& b, hipStream_t s) {
+    // the atoms per thread of the largest job; every job of the launch runs with it
+    return b.apt == 4 ? launch_pairs_t<4, NH, OBS, COL>(b, s) : launch_pairs_t<8, NH, OBS, COL>(b, s);
+}
+
+hipError_t launch_pairs(const BatchLaunch& b, hipStream_t s) {
+    if (b.precision != 1 || !b.pairs || b.threads > kPairThreads || b.threads % 64 != 0 ||
+        (b.apt != 4 && b.apt != 8))
+        return hipErrorInvalidValue;
+    // colour-field daughters do not record the extra observables
+    if (b.field) {
+        if (b.obs) return hipErrorInvalidValue;
+        return b.thermo ? launch_pairs_a<true, false, true>(b, s)
+                        : launch_pairs_a<false, false, true>(b, s);
+    }
+    if (b.obs)
+        return b.thermo ? launch_pairs_a<true, true, false>(b, s)
+                        : launch_pairs_a<false, true, false>(b, s);
+    return b.thermo ? launch_pairs_a<true, false, false>(b, s)
+                    : launch_pairs_a<false, false, false>(b, s);
+}
+
+hipError_t launch_debug_pair_form(const SysDev& S, double gamma_dot, int64_t kstep, const double* r,
+                                  int32_t kcap, uint32_t* pairs, int32_t* seg_count,
+                                  int32_t* cell_of, int32_t* rank_of, int32_t* start, double* f,
+                                  double* out, hipStream_t s) {
+    const int threads = job_threads(S.n);
+    const size_t lds = lds_bytes_pairs(S.n, S.lc[0] * S.lc[1] * S.lc[2]);
+    if (job_apt(S.n) == 4) {
+        (void)hipFuncSetAttribute((const void*)k_debug_pair_form<4>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_debug_pair_form<4>, dim3(1), dim3(threads), lds, s, S, gamma_dot,
+                           kstep, r, kcap, pairs, seg_count, cell_of, rank_of, start, f, out);
+    } else {
+        (void)hipFuncSetAttribute((const void*)k_debug_pair_form<8>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_debug_pair_form<8>, dim3(1), dim3(threads), lds, s, S, gamma_dot,
+                           kstep, r, kcap, pairs, seg_count, cell_of, rank_of, start, f, out);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ttcf

@@ -89,8 +89,7 @@ def make_system(n_atoms: int, box, temperature: float = 0.722, dt: float = 0.002
     if np.isscalar(box):
         box = (float(box),) * 3
     if u_shift is None:
-        s6 = 1.0 / r_cut ** 6
-        u_shift = -4.0 * (s6 * s6 - c_attr * s6)
+        u_shift = float("nan")  # the library's shift: phi(r_cut) = 0
     s = System()
     s.n_atoms = int(n_atoms)
     s.potential = int(potential)
@@ -169,6 +168,9 @@ def lib():
         "ttcf_debug_cell_list": [S, D, I, I, I, I, V],
         "ttcf_debug_pairs": [S, C.c_double, D, C.c_double, C.c_int64, I, I, L64, V],
         "ttcf_debug_forces": [S, C.c_double, D, D, D, V],
+        "ttcf_cell_grid": [S, C.c_double, I, I, D],
+        "ttcf_debug_pair_form": [S, C.c_double, C.c_int64, C.c_double, C.c_int32, D, I, I, I, I,
+                                 C.c_int64, I, I, L64, D, D, V],
         "ttcf_step_timing": [V, D, L64, C.c_int32],
         "ttcf_set_step_shape": [V, C.c_int32, C.c_int32, C.c_double, C.c_int32],
         "ttcf_cv_init": [V, C.c_int32, F, C.c_int64],
@@ -236,6 +238,7 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_record_mother", "ttcf_export_mother_series", "ttcf_export_daughter",
             "ttcf_export_series", "ttcf_daughter_health", "ttcf_debug_poison",
             "ttcf_debug_cell_list", "ttcf_debug_pairs", "ttcf_debug_forces", "ttcf_step_timing",
+            "ttcf_cell_grid", "ttcf_debug_pair_form",
             "ttcf_set_step_shape", "ttcf_cv_init", "ttcf_cv_export_weights",
             "ttcf_cv_add_training", "ttcf_cv_export_training", "ttcf_cv_train", "ttcf_cv_attach", "ttcf_cv_calibrate", "ttcf_cv_mean_term",
             "ttcf_cv_response", "ttcf_mlp_forward", "ttcf_mlp_gradient",
@@ -317,11 +320,22 @@ def use_torch_allocator():
 # stateless kernels
 # ----------------------------------------------------------------------------------------
 
+def ttcf_cell_grid(sys: System, skin: float = 0.0):
+    """(cells, list_cells, list_skin): the canonical cell grid and the pair-list form's list
+    grid for `skin` (<= 0: automatic), as the library sizes them."""
+    cells = np.zeros(3, np.int32)
+    lcells = np.zeros(3, np.int32)
+    ls = C.c_double(0.0)
+    _check(lib().ttcf_cell_grid(C.byref(sys), float(skin), _ip(cells), _ip(lcells), C.byref(ls)),
+           "ttcf_cell_grid")
+    return cells, lcells, ls.value
+
+
 def ttcf_debug_cell_list(sys: System, r, stream=None):
     r = _f64(r).ravel()
     n = sys.n_atoms
     dims = np.zeros(3, np.int32)
-    ncell = int(np.prod([int(np.floor(sys.box[a] / sys.r_cut)) for a in range(3)]))
+    ncell = int(np.prod(ttcf_cell_grid(sys)[0]))
     cell_of = np.zeros(n, np.int32)
     order = np.zeros(n, np.int32)
     start = np.zeros(ncell + 1, np.int32)
@@ -342,6 +356,41 @@ def ttcf_debug_pairs(sys: System, r, dxle: float = 0.0, rlist: float | None = No
     if cnt.value < 0:
         raise TTCFError(TTCF_EINVAL, "ttcf_debug_pairs", "capacity too small")
     return pi[:cnt.value].copy(), pj[:cnt.value].copy()
+
+
+def ttcf_debug_pair_form(sys: System, r, gamma_dot: float = 0.0, kstep: int = 0,
+                         skin: float = 0.0, kcap: int = 0, stream=None):
+    """The pair-list form's own list build and force pass on positions r. Returns a dict:
+    dims (list grid), cell_of, order, start, pairs (pi, pj: atom ids, pi < pj, sorted), f
+    (3, n) forces as the integrator uses them, w_xy, dxle (the offset used), rlist, close
+    (a pair inside the fixed-point force range's guard radius), overflow (capacity)."""
+    r = _f64(r).ravel()
+    n = sys.n_atoms
+    _, lc, _ = ttcf_cell_grid(sys, skin)
+    ncell = int(np.prod(lc))
+    dims = np.zeros(3, np.int32)
+    cell_of = np.zeros(n, np.int32)
+    order = np.zeros(n, np.int32)
+    start = np.zeros(ncell + 1, np.int32)
+    cap = 64 * n
+    pi = np.zeros(cap, np.int32)
+    pj = np.zeros(cap, np.int32)
+    cnt = C.c_int64(0)
+    f = np.zeros(3 * n)
+    out = np.zeros(4)
+    code = lib().ttcf_debug_pair_form(C.byref(sys), float(gamma_dot), int(kstep), float(skin),
+                                      int(kcap), _dp(r), _ip(dims), _ip(cell_of), _ip(order),
+                                      _ip(start), cap, _ip(pi), _ip(pj), C.byref(cnt), _dp(f),
+                                      _dp(out), stream)
+    if code not in (TTCF_OK, TTCF_EUNSTABLE):
+        _check(code, "ttcf_debug_pair_form")
+    if cnt.value < 0:
+        raise TTCFError(TTCF_EINVAL, "ttcf_debug_pair_form", "capacity too small")
+    k = cnt.value
+    return dict(dims=dims, cell_of=cell_of, order=order, start=start,
+                pairs=(pi[:k].copy(), pj[:k].copy()), f=f.reshape(3, n), w_xy=out[0],
+                dxle=out[1], rlist=out[2], close=bool(out[3] != 0.0),
+                overflow=code == TTCF_EUNSTABLE)
 
 
 def ttcf_debug_forces(sys: System, r, dxle: float = 0.0, stream=None):

@@ -228,6 +228,23 @@ int32_t fail(ttcf_ctx* c, int32_t code, const std::string& msg) {
             return fail((ctx), TTCF_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Separation below which a pair's force exceeds kPairForceGuard (bisection on the repulsive
+// branch of 24 (2 r^-13 - c r^-7), which falls monotonically up to its zero (2/c)^(1/6)).
+double guard_radius(const SysDev& d) {
+    auto force = [&](double r) {
+        const double s = 1.0 / (r * r), s3 = s * s * s;
+        return 24.0 * s3 * (2.0 * s3 - d.c_attr) / r;
+    };
+    double lo = 0.01, hi = d.c_attr > 0.0 ? std::pow(2.0 / d.c_attr, 1.0 / 6.0) : d.rc;
+    hi = std::min(hi, d.rc);
+    if (force(hi) >= kPairForceGuard) return hi;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        (force(mid) > kPairForceGuard ? lo : hi) = mid;
+    }
+    return lo;
+}
+
 int32_t build_sysdev(const ttcf_system* s, SysDev* d, std::string* why) {
     if (s->n_atoms < 2 || s->n_atoms > kMaxAtoms) {
         *why = "n_atoms must be in [2, 65535]";
@@ -271,6 +288,8 @@ int32_t build_sysdev(const ttcf_system* s, SysDev* d, std::string* why) {
         d->fix_unit[a] = (float)(s->box[a] / 4294967296.0);
     }
     d->rc2_f = (float)d->rc2;
+    const double rg = guard_radius(*d);  // depends on the potential only
+    d->rg2_f = (float)(rg * rg);
     return TTCF_OK;
 }
 
@@ -289,23 +308,6 @@ double auto_skin(const SysDev& d) {
     return std::max(0.2, w * (1.0 - 1e-9) - d.rc);
 }
 
-// Separation below which a pair's force exceeds kPairForceGuard (bisection on the repulsive
-// branch of 24 (2 r^-13 - c r^-7), which falls monotonically up to its zero (2/c)^(1/6)).
-double guard_radius(const SysDev& d) {
-    auto force = [&](double r) {
-        const double s = 1.0 / (r * r), s3 = s * s * s;
-        return 24.0 * s3 * (2.0 * s3 - d.c_attr) / r;
-    };
-    double lo = 0.01, hi = d.c_attr > 0.0 ? std::pow(2.0 / d.c_attr, 1.0 / 6.0) : d.rc;
-    hi = std::min(hi, d.rc);
-    if (force(hi) >= kPairForceGuard) return hi;
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        (force(mid) > kPairForceGuard ? lo : hi) = mid;
-    }
-    return lo;
-}
-
 bool set_list_grid(SysDev* d, double skin) {
     if (!(skin > 0.0)) skin = auto_skin(*d);
     const double reach = d->rc + skin;
@@ -316,8 +318,6 @@ bool set_list_grid(SysDev* d, double skin) {
         d->l_inv_w[a] = (double)d->lc[a] / d->box[a];
     }
     d->rl2_f = (float)(reach * reach);
-    const double rg = guard_radius(*d);
-    d->rg2_f = (float)(rg * rg);
     return d->lc[0] >= 4 && d->lc[1] >= 3 && d->lc[2] >= 3 && d->lc[0] <= kMaxCells1D &&
            d->lc[1] <= kMaxCells1D && d->lc[2] <= kMaxCells1D;
 }

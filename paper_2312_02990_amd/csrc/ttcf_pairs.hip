@@ -37,6 +37,7 @@ namespace {
 
 constexpr int kPairThreads = 512;            // workgroup size (256 registers per lane)
 constexpr int kJobBytes = 128;               // job slot in front of the per-job LDS
+constexpr int kScanPerTrip = 4;              // list build: candidates per lane per trip
 constexpr int kPfRed = 16;                   // doubles per thread in one block reduction
 constexpr float kForceUnits = 524288.0f;     // 2^19 fixed-point units per force unit
 constexpr float kForceStep = 1.0f / 524288.0f;
@@ -47,7 +48,8 @@ constexpr double kTwo52 = 4503599627370496.0;    // 2^52
 
 struct PairLds {
     uint4* pos;        // [n] by rank: fixed-point x, y, z; w = cx | cy << 10 | cz << 20
-    int4* facc;        // [n] by rank: fixed-point force accumulators (x, y, z, unused)
+    int4* facc;        // [n] by rank: fixed-point force accumulators: (x, y) packed in one
+                       // 64-bit integer y 2^32 + x, then z, then unused
     int32_t* cnt;      // [cells] counts, then placement cursors
     int32_t* start;    // [cells + 1]
     int32_t* rowinfo;  // [3 rows][2]: first x cell offset mod lc_x, cell count
@@ -56,6 +58,7 @@ struct PairLds {
     int32_t* scan;     // [kMaxWaves]
     float* wmax;       // [kMaxWaves] wave maxima of the path length
     int32_t* flags;    // [kMaxWaves] per wave: its pair list overflowed
+    int32_t* wcnt;     // [kMaxWaves] pairs in each wave's segment (at most its capacity)
     double* ktab;      // [16] series coefficients of the isokinetic kick
     SysDev* sys;
     // during a rebuild the facc area holds the sorted atom ids (u16 [n]) and the rank of
@@ -63,7 +66,7 @@ struct PairLds {
 };
 
 struct PairPlan {
-    size_t pos, facc, cnt, start, rowinfo, red, red2, scan, wmax, flags, ktab, sys, total;
+    size_t pos, facc, cnt, start, rowinfo, red, red2, scan, wmax, flags, wcnt, ktab, sys, total;
 };
 
 __host__ __device__ inline size_t pf_align(size_t v, size_t a) { return (v + a - 1) & ~(a - 1); }
@@ -87,6 +90,7 @@ __host__ __device__ inline PairPlan plan_pairs(int n, int cells) {
     p.scan = take(4 * kMaxWaves, 16);
     p.wmax = take(4 * kMaxWaves, 16);
     p.flags = take(4 * kMaxWaves, 16);
+    p.wcnt = take(4 * kMaxWaves, 16);
     p.ktab = take(sizeof(double) * 16, 16);
     p.sys = take(sizeof(SysDev), 16);
     p.total = pf_align(off, 128);
@@ -106,6 +110,7 @@ __device__ inline PairLds carve_pairs(char* base, int n, int cells) {
     L.scan = (int32_t*)(base + p.scan);
     L.wmax = (float*)(base + p.wmax);
     L.flags = (int32_t*)(base + p.flags);
+    L.wcnt = (int32_t*)(base + p.wcnt);
     L.ktab = (double*)(base + p.ktab);
     L.sys = (SysDev*)(base + p.sys);
     return L;
@@ -123,6 +128,13 @@ __host__ __device__ inline int job_threads(int n) {
 // the low mantissa bits of 2^52 + v scale.
 __device__ __forceinline__ uint32_t fixq(double v, double scale) {
     return (uint32_t)__double2loint(__builtin_fma(v, scale, kTwo52));
+}
+
+// The fixed-point force of an accumulator: x and y from the packed 64-bit sum y 2^32 + x.
+__device__ __forceinline__ int3 unpack_force(const int4& q) {
+    const long long v = ((long long)(uint32_t)q.y << 32) | (uint32_t)q.x;
+    const int lo = (int)(uint32_t)v;
+    return make_int3(lo, (int)((v - (long long)lo) >> 32), q.z);
 }
 
 // round(a b 2^20) as an exact FP64 integer (|a b| < 2^31).
@@ -182,6 +194,67 @@ __device__ __forceinline__ void iso_kick_coeffs_tab(double a, double b, double t
     }
     s = a * ch1_b + sh_q;
     sdot = a * sh_q + (1.0 + b * ch1_b);
+}
+
+// One DPP move of a double from the lane the control selects (every lane has a source).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// One stage of a transposed reduction: a lane with `upper` set keeps a[H..2H) and hands
+// a[0..H) to the lane the control selects, the others keep a[0..H) and hand a[H..2H); the
+// kept half adds what arrives. The control must pair every lane with one of the other kind
+// holding the same value subsets (an exchange, or a rotation that flips one lane bit).
+template <int H, int CTRL>
+__device__ __forceinline__ void xstage(double* a, bool upper) {
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double keep = upper ? a[H + i] : a[i];
+        const double send = upper ? a[i] : a[H + i];
+        a[i] = keep + dpp_move<CTRL>(send);
+    }
+}
+
+// The 12-value sum of the step over the first nw waves; every thread receives the totals.
+// Inside a wave a transposed reduction: lane bit 0 (exchange with lane ^ 1) splits 12 values
+// into 6, bit 1 (lane ^ 2) into 3, bit 2 (rotation by 4 in a row of 16) into 2 of 3 plus a
+// zero, bit 3 (rotation by 8) into 1; two cross-row sums (lane ^ 16, lane ^ 32) complete the
+// wave totals, 16 slots of which 12 hold values. Then waves 0..nw-1 in sequence, as in
+// pf_block_sum below. Fixed order throughout; one barrier, and the same rule for `red`.
+__device__ __forceinline__ void pf_block_sum12(double (&v)[12], double* red, int nw) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool b0 = lane & 1, b1 = lane & 2, b2 = lane & 4, b3 = lane & 8;
+    double a[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) a[k] = v[k];
+    xstage<6, 0xB1>(a, b0);  // quad_perm [1, 0, 3, 2]
+    xstage<3, 0x4E>(a, b1);  // quad_perm [2, 3, 0, 1]
+    a[3] = 0.0;
+    xstage<2, 0x124>(a, b2);  // row_ror:4
+    xstage<1, 0x128>(a, b3);  // row_ror:8
+    a[0] += __shfl_xor(a[0], 16, 64);
+    a[0] += __shfl_xor(a[0], 32, 64);
+    // value held by this lane: 6 b0 + 3 b1 + (0, 1 or 2 from b2, b3; none if both are set)
+    const int idx = 6 * (int)b0 + 3 * (int)b1 + (b2 ? 2 : (int)b3);
+    if (lane < 16 && !(b2 && b3) && wave < nw) red[wave * kPfRed + idx] = a[0];
+    __syncthreads();
+    double s = 0.0;
+    if (lane < 12)
+        for (int w = 0; w < nw; ++w) s += red[w * kPfRed + lane];
+    const uint64_t u = __builtin_bit_cast(uint64_t, s);
+    const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
+#pragma unroll
+    for (int k = 0; k < 12; ++k) {
+        const uint32_t l = (uint32_t)__builtin_amdgcn_readlane(lo, k);
+        const uint32_t h = (uint32_t)__builtin_amdgcn_readlane(hi, k);
+        v[k] = __builtin_bit_cast(double, ((uint64_t)h << 32) | l);
+    }
 }
 
 // Sum K doubles over the first nw waves; every thread receives the totals. Fixed order: a
@@ -303,21 +376,31 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, gu32
             const int len0 = own ? max(hi0 - lo0, 0) : 0;
             const int len = len0 + (own ? max(hi1 - lo1, 0) : 0);
             const uint32_t wbase = (uint32_t)s | ((uint32_t)(ny + 1) << 28);
-            // one candidate per lane per trip; trips until the wave's longest row is done
-            for (int v = 0; __builtin_amdgcn_ballot_w64(v < len) != 0; ++v) {
-                const bool valid = v < len;
-                const int k = !valid ? s : (v < len0 ? lo0 + v : lo1 + (v - len0));
-                const uint4 q = L.pos[own ? k : 0];
-                const float ddx = (float)(int32_t)(qi.x - q.x - rsh) * ux;
-                const float ddy = (float)(int32_t)(qi.y - q.y) * uy;
-                const float ddz = (float)(int32_t)(qi.z - q.z) * uz;
-                const bool hit = valid & (ddx * ddx + ddy * ddy + ddz * ddz < rl2);
-                const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
-                const int below = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                const int at = base + below;
-                if (hit && at < seg_cap) seg[at] = wbase | ((uint32_t)k << 14);
-                base += (int)__builtin_popcountll(m);
+            // kScanPerTrip candidates per lane per trip, their loads issued together; trips
+            // until the wave's longest row is done
+            for (int v = 0; __builtin_amdgcn_ballot_w64(v < len) != 0; v += kScanPerTrip) {
+                int k[kScanPerTrip];
+                uint4 q[kScanPerTrip];
+#pragma unroll
+                for (int u = 0; u < kScanPerTrip; ++u) {
+                    const int vv = v + u;
+                    k[u] = vv >= len ? s : (vv < len0 ? lo0 + vv : lo1 + (vv - len0));
+                }
+#pragma unroll
+                for (int u = 0; u < kScanPerTrip; ++u) q[u] = L.pos[own ? k[u] : 0];
+#pragma unroll
+                for (int u = 0; u < kScanPerTrip; ++u) {
+                    const float ddx = (float)(int32_t)(qi.x - q[u].x - rsh) * ux;
+                    const float ddy = (float)(int32_t)(qi.y - q[u].y) * uy;
+                    const float ddz = (float)(int32_t)(qi.z - q[u].z) * uz;
+                    const bool hit = (v + u < len) & (ddx * ddx + ddy * ddy + ddz * ddz < rl2);
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
+                    const int below = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    const int at = base + below;
+                    if (hit && at < seg_cap) seg[at] = wbase | ((uint32_t)k[u] << 14);
+                    base += (int)__builtin_popcountll(m);
+                }
             }
         }
     }
@@ -416,7 +499,10 @@ __device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t
     for (int i = t; i < n; i += T) L.facc[i] = make_int4(0, 0, 0, 0);
     const int count = pf_gen_pairs<APT>(n, C, dxq, seg, seg_cap, tj);
     const int wave = t >> 6, nwb = T >> 6;
-    if ((t & 63) == 0) L.flags[wave] = count > seg_cap ? 1 : 0;
+    if ((t & 63) == 0) {
+        L.flags[wave] = count > seg_cap ? 1 : 0;
+        L.wcnt[wave] = min(count, seg_cap);
+    }
     __syncthreads();
     int any = 0;
     for (int w = 0; w < nwb; ++w) any |= L.flags[w];
@@ -435,29 +521,64 @@ struct PfSums {
     int close;
 };
 
-// Forces of this wave's `count` pairs into the fixed-point accumulators. Out of line, so
-// that the step loop's registers and these do not add up.
+// A pair word that stands for no pair (lanes past a segment's end): image code 3, atoms at
+// rank 0 so that its position loads stay in bounds.
+constexpr uint32_t kNoPair = 3u << 28;
+
+// Forces of the pairs of every wave segment into the fixed-point accumulators. The segments'
+// 64-pair chunks, taken in order (segment 0 first), go round robin to the waves of the
+// workgroup: wave w forces chunks w, w + W, w + 2W, ... of W waves, so every wave gets the
+// same share whatever its own list held. Called by every thread; the pair counts come from
+// the last build (L.wcnt). Out of line, so that the step loop's registers and these do not
+// add up.
 template <bool OBS>
 __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
-                                                      const gu32* seg, int count) {
+                                            const gu32* pair_base, int seg_cap) {
     const PairLds L = job_lds(n, cells);
     const SysDev& S = *L.sys;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, nwb = blockDim.x >> 6;
     const float rc2 = S.rc2_f, rg2 = S.rg2_f;
     const float ca = (float)S.c_attr;
     const float ushift = (float)S.u_shift;
     const float ux = S.fix_unit[0], uy = S.fix_unit[1], uz = S.fix_unit[2];
     PfSums o{0.0, 0.0, 0.0, 0.0, 0.0, 0};
     bool close = false;
-    uint32_t wn = lane < count ? seg[lane] : 0u;
-    for (int p0 = 0; p0 < count; p0 += 64) {
-        const bool live = p0 + lane < count;
-        const uint32_t word = wn;
-        wn = p0 + 64 + lane < count ? seg[p0 + 64 + lane] : 0u;
+    // lane s < W: pairs of segment s and the chunks before it; lanes from W on: the total
+    int seg_pairs = 0, seg_first = 0;
+#pragma unroll
+    for (int s = 0; s < kPairThreads / 64; ++s) {
+        const int c = s < nwb ? L.wcnt[s] : 0;
+        if (s == lane) seg_pairs = c;
+        if (s < lane) seg_first += (c + 63) >> 6;
+    }
+    const int chunks = __builtin_amdgcn_readlane(seg_first, kPairThreads / 64);
+    // the word of chunk g in this lane: segment s is the last one starting at or before g
+    auto word_of = [&](int g) -> uint32_t {
+        if (g >= chunks) return kNoPair;
+        const int s = __popcll(__ballot(seg_first <= g)) - 1;
+        const int first = __builtin_amdgcn_readlane(seg_first, s);
+        const int cnt = __builtin_amdgcn_readlane(seg_pairs, s);
+        const int at = (g - first) * 64 + lane;
+        return at < cnt ? pair_base[(size_t)s * seg_cap + at] : kNoPair;
+    };
+    // software pipeline: the pair words two chunks ahead and the positions one chunk ahead
+    // are loaded before this chunk's atomics (LDS operations complete in order, so loads
+    // issued after the atomics would wait for them)
+    const int g0 = threadIdx.x >> 6;
+    uint32_t w_next = word_of(g0);
+    uint32_t w_after = word_of(g0 + nwb);
+    uint3 pi_next = *(const uint3*)&L.pos[w_next & 0x3FFFu];
+    uint3 pj_next = *(const uint3*)&L.pos[(w_next >> 14) & 0x3FFFu];
+    for (int g = g0; g < chunks; g += nwb) {
+        const uint32_t word = w_next;
+        const bool live = (word >> 28) != 3u;
+        const uint3 qi = pi_next, qj = pj_next;
+        w_next = w_after;
+        w_after = word_of(g + 2 * nwb);
+        pi_next = *(const uint3*)&L.pos[w_next & 0x3FFFu];
+        pj_next = *(const uint3*)&L.pos[(w_next >> 14) & 0x3FFFu];
         const int si = (int)(word & 0x3FFFu), sj = (int)((word >> 14) & 0x3FFFu);
         const uint32_t img = word >> 28;  // n_y + 1
-        const uint4 qi = L.pos[si];
-        const uint4 qj = L.pos[sj];
         const uint32_t sh = img == 2u ? dxq : (img == 0u ? 0u - dxq : 0u);
         const float dx = (float)(int32_t)(qi.x - qj.x - sh) * ux;
         const float dy = (float)(int32_t)(qi.y - qj.y) * uy;
@@ -473,14 +594,15 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
             // exactly opposite increments
             const int qx = __float2int_rn(gx * kForceUnits), qy = __float2int_rn(gy * kForceUnits),
                       qz = __float2int_rn(gz * kForceUnits);
-            int* ai = (int*)&L.facc[si];
-            int* aj = (int*)&L.facc[sj];
-            atomicAdd(ai + 0, qx);
-            atomicAdd(ai + 1, qy);
-            atomicAdd(ai + 2, qz);
-            atomicAdd(aj + 0, -qx);
-            atomicAdd(aj + 1, -qy);
-            atomicAdd(aj + 2, -qz);
+            // x and y share one 64-bit integer, V = qy 2^32 + qx: sums of such values are
+            // exact, and each component stays within +-2^31, so both decode exactly
+            const unsigned long long v = (unsigned long long)(((long long)qy << 32) + (long long)qx);
+            unsigned long long* ai = (unsigned long long*)&L.facc[si];
+            unsigned long long* aj = (unsigned long long*)&L.facc[sj];
+            atomicAdd(ai, v);
+            atomicAdd((int*)ai + 2, qz);
+            atomicAdd(aj, 0ull - v);
+            atomicAdd((int*)aj + 2, -qz);
             o.w += quant(dx, gy);
             if (OBS) {
                 o.xx += quant(dx, gx);
@@ -598,7 +720,7 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
     const int n = S.n;
     const int cells = S.lc[0] * S.lc[1] * S.lc[2];
     const int tj = job_threads(n);
-    const int nw = tj >> 6;
+    const int nw = blockDim.x >> 6;  // waves of the workgroup (the owners and any others)
     const int wave = t >> 6;
     double* st = dsc->state;
     const bool col = COL && dsc->field == kFieldColour;  // uniform per job
@@ -654,17 +776,16 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
     PfSums ps{0.0, 0.0, 0.0, 0.0, 0.0, 0};
     bool ovf = false;
     // forces of the start state
-    int count = pf_rebuild<APT>(S, dxle, dxq, x, y, z, rank, cr, L, seg, seg_cap, tj, cell, &ovf);
+    pf_rebuild<APT>(S, dxle, dxq, x, y, z, rank, cr, L, seg, seg_cap, tj, cell, &ovf);
     if (ovf) health |= kHealthListOverflow;
-    count = min(count, seg_cap);
-    if (t < tj) ps = pf_forces<OBS>(n, cells, dxq, seg, count);
+    ps = pf_forces<OBS>(n, cells, dxq, pair_base, seg_cap);
     __syncthreads();
     auto readback = [&]() {
 #pragma unroll
         for (int j = 0; j < APT; ++j) {
             const int a = t + j * tj;
             if (t < tj && a < n) {
-                const int4 q = L.facc[rank[j]];
+                const int3 q = unpack_force(L.facc[rank[j]]);
                 fx[j] = (float)q.x * kForceStep;
                 fy[j] = (float)q.y * kForceStep;
                 fz[j] = (float)q.z * kForceStep;
@@ -755,7 +876,7 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
         ++since;
         const float tsince = (float)(since * h);
         if (2.f * dm + agd * tsince * (reach + 2.f * dm) >= skin) {
-            count = pf_rebuild<APT>(S, dxle, dxq, x, y, z, rank, cr, L, seg, seg_cap, tj, cell, &ovf);
+            pf_rebuild<APT>(S, dxle, dxq, x, y, z, rank, cr, L, seg, seg_cap, tj, cell, &ovf);
             if (ovf) {  // the same in every thread
                 health |= kHealthListOverflow;
                 break;
@@ -764,7 +885,7 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
             for (int j = 0; j < APT; ++j) path[j] = 0.f;
             since = 0;
         }
-        if (t < tj) ps = pf_forces<OBS>(n, cells, dxq, seg, count);
+        ps = pf_forces<OBS>(n, cells, dxq, pair_base, seg_cap);
         __syncthreads();
         readback();
         // ---- moments of (p, F): pp, pxpy, pypy, fp, fxpy, fypx, fxfy, fypy, fyfy, ff, W,
@@ -785,7 +906,7 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
             m[9] += fxd(j) * fxd(j) + (double)fy[j] * (double)fy[j] +
                     (double)fz[j] * (double)fz[j];
         }
-        pf_block_sum<12>(m, L.red, nw);
+        pf_block_sum12(m, L.red, nw);
         // ---- second half: p_end = A p + B F + (C p_y + D F_y) x_hat, end-of-step moments
         double A, B, C, D, vpxy;
         bool drift = false;
@@ -945,16 +1066,16 @@ __global__ __launch_bounds__(kPairThreads) void k_debug_pair_form(
     bool ovf = false;
     const int count = pf_rebuild<APT>(S, dxle, dxq, x, y, z, rank, cr, L, seg, seg_cap, tj, cell, &ovf);
     PfSums ps{0.0, 0.0, 0.0, 0.0, 0.0, 0};
-    if (t < tj) ps = pf_forces<false>(n, cells, dxq, seg, min(count, seg_cap));
+    ps = pf_forces<false>(n, cells, dxq, (const gu32*)pairs, seg_cap);
     if ((t & 63) == 0 && t < tj) seg_count[wave] = count;
     __syncthreads();
     double m[2] = {ps.w, (double)ps.close};
-    pf_block_sum<2>(m, L.red, tj >> 6);
+    pf_block_sum<2>(m, L.red, blockDim.x >> 6);
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
         const int a = t + j * tj;
         if (t < tj && a < n) {
-            const int4 q = L.facc[rank[j]];
+            const int3 q = unpack_force(L.facc[rank[j]]);
             f[a] = (double)((float)q.x * kForceStep);
             f[n + a] = (double)((float)q.y * kForceStep);
             f[2 * n + a] = (double)((float)q.z * kForceStep);

@@ -47,7 +47,9 @@ enum {
     TTCF_ENOMEM = -2,    /* device or host allocation failed                              */
     TTCF_EDEVICE = -3,   /* a HIP call failed, or no usable gfx950 device                 */
     TTCF_ESTATE = -4,    /* call out of order (e.g. a response before any accumulation)   */
-    TTCF_EUNSTABLE = -5  /* every daughter group failed its health check                  */
+    TTCF_EUNSTABLE = -5, /* every daughter group failed its health check                  */
+    TTCF_ESCRATCH = -6   /* ttcf_pair_forces_static: the input needs more than its static
+                            device scratch of TTCF_STATIC_SCRATCH_BYTES                      */
 };
 
 enum { TTCF_WCA = 0, TTCF_LJ = 1 };
@@ -380,6 +382,31 @@ int32_t ttcf_debug_pair_form(const ttcf_system* sys, double gamma_dot, int64_t k
                              int32_t kcap, const double* r, int32_t* dims, int32_t* cell_of,
                              int32_t* order, int32_t* start, int64_t cap, int32_t* pi, int32_t* pj,
                              int64_t* count, double* f, double* out, void* stream);
+
+/* For callers that cannot allocate device memory (code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the list build and force pass of
+ * ttcf_debug_pair_form (the same kernel) with no allocation of any kind on the device. The
+ * pair lists and the build's other by-products go to a static device array of
+ * TTCF_STATIC_SCRATCH_BYTES (1 MiB) that every GPU the library runs on holds from the first
+ * call there until the process ends; an input that needs more (pair words
+ * 64 ceil(n / 256 or 512) * apt * kcap, plus the cells and atoms) returns TTCF_ESCRATCH.
+ * Liquids of up to 4096 atoms at the automatic capacity (kcap near 10) fit, and any system of
+ * up to 2048 atoms at the largest, kcap = 64.
+ *   r:   DEVICE positions (3n FP64, SoA), inside the box (not checked: positions outside
+ *        are binned into the edge cells and give meaningless forces, never an access out of
+ *        bounds);
+ *   f:   DEVICE output, 3n FP64 forces (the ones ttcf_debug_pair_form returns);
+ *   out: DEVICE output, 4 FP64: W_xy, 1 if a pair came closer than the fixed-point force
+ *        range allows, the Lees-Edwards offset used, 1 if the capacity kcap overflowed (the
+ *        forces then miss pairs).
+ * Other arguments as for ttcf_debug_pair_form. Enqueued on `stream`, no synchronisation;
+ * r, f and out must stay valid until the stream has run it. Calls on one GPU share that
+ * GPU's scratch: calls that can overlap on one GPU (other streams, other threads) race and
+ * must be ordered by the caller. Nothing in the scratch needs to start at zero. */
+int32_t ttcf_pair_forces_static(const ttcf_system* sys, double gamma_dot, int64_t kstep,
+                                double skin, int32_t kcap, const double* r, double* f,
+                                double* out, void* stream);
+enum { TTCF_STATIC_SCRATCH_BYTES = 1 << 20 };
 
 /* Shape of the daughter step kernel (the knobs a tuner searches). variant: 0 automatic,
  * 1 cell list rebuilt every step (FP64 or FP32 forces), 2 pair list of radius r_cut + skin

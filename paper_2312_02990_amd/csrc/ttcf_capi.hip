@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -516,6 +517,8 @@ const char* ttcf_strerror(int32_t code) {
         case TTCF_EDEVICE: return "device error";
         case TTCF_ESTATE: return "call out of order";
         case TTCF_EUNSTABLE: return "every daughter group failed its health check";
+        case TTCF_ESCRATCH:
+            return "the input needs more than the static scratch of the allocation-free call";
     }
     return "unknown error";
 }
@@ -3406,6 +3409,91 @@ int32_t ttcf_cell_grid(const ttcf_system* sys, double skin, int32_t* cells, int3
         for (int a = 0; a < 3; ++a) list_cells[a] = ok ? S.lc[a] : 0;
     if (list_skin) *list_skin = ok ? S.skin : 0.0;
     return TTCF_OK;
+}
+
+}  // extern "C"
+
+// ---- allocation-free pair-form forces ---------------------------------------------------
+
+// The device scratch of ttcf_pair_forces_static: the pair lists and the build's by-products,
+// one copy on every GPU the library runs on, held until the process ends. Host code uses it
+// only through the address hipGetSymbolAddress returns on each device (the array's own name
+// is a host-side stand-in, not a device address).
+static __device__ __align__(256) uint32_t scratch[TTCF_STATIC_SCRATCH_BYTES / 4];
+
+namespace {
+
+constexpr int kStaticMaxDevices = 64;
+
+struct StaticScratch {
+    uint32_t* ptr = nullptr;  // this device's copy of `scratch`
+    size_t lds = 0;           // its LDS per workgroup
+};
+
+std::mutex g_static_mu;
+StaticScratch g_static[kStaticMaxDevices];
+
+// The current device's scratch, looked up once per device (with that device current).
+int32_t static_scratch(StaticScratch* out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kStaticMaxDevices)
+        return TTCF_EDEVICE;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticScratch& d = g_static[dev];
+    if (!d.ptr) {
+        void* ptr = nullptr;
+        int lds = 0;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr ||
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess)
+            return TTCF_EDEVICE;
+        d.lds = (size_t)lds;
+        d.ptr = (uint32_t*)ptr;
+    }
+    *out = d;
+    return TTCF_OK;
+}
+
+inline int64_t words256(int64_t words) { return (words + 63) & ~int64_t(63); }
+
+}  // namespace
+
+extern "C" {
+
+int32_t ttcf_pair_forces_static(const ttcf_system* sys, double gamma_dot, int64_t kstep,
+                                double skin, int32_t kcap, const double* r, double* f,
+                                double* out, void* stream) {
+    if (!sys || !r || !f || !out || kcap > kPairMaxCap || !std::isfinite(gamma_dot) ||
+        !std::isfinite(skin))
+        return TTCF_EINVAL;
+    SysDev S{};
+    std::string why;
+    int32_t rc = build_sysdev(sys, &S, &why);
+    if (rc != TTCF_OK) return rc;
+    if (S.n > kPairMaxAtoms || !set_list_grid(&S, skin)) return TTCF_EINVAL;
+    if (kcap <= 0) kcap = auto_pair_cap(S);
+    const int n = S.n;
+    const int C = S.lc[0] * S.lc[1] * S.lc[2];
+    const int waves = pair_job_threads(n) / 64;
+    // scratch layout (each part 256-byte aligned): pair words, wave counts, cell and rank of
+    // every atom, cell starts
+    const int64_t w_pairs = words256(pair_words(n, kcap, pair_job_apt(n)));
+    const int64_t w_seg = words256(waves), w_atoms = words256(n);
+    const int64_t need = w_pairs + w_seg + 2 * w_atoms + words256(C + 1);
+    if (need * 4 > TTCF_STATIC_SCRATCH_BYTES) return TTCF_ESCRATCH;
+    StaticScratch d;
+    rc = static_scratch(&d);
+    if (rc != TTCF_OK) return rc;
+    if (lds_bytes_pairs(n, C) > d.lds) return TTCF_EINVAL;
+    uint32_t* pairs = d.ptr;
+    int32_t* seg = (int32_t*)(pairs + w_pairs);
+    int32_t* cell_of = seg + w_seg;
+    int32_t* rank_of = cell_of + w_atoms;
+    int32_t* start = rank_of + w_atoms;
+    const hipError_t e = launch_debug_pair_form(S, gamma_dot, kstep, r, kcap, pairs, seg,
+                                                cell_of, rank_of, start, f, out,
+                                                (hipStream_t)stream);
+    return e == hipSuccess ? TTCF_OK : TTCF_EDEVICE;
 }
 
 }  // extern "C"

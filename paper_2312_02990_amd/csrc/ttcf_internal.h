@@ -261,8 +261,9 @@ inline int64_t pair_words(int n, int kcap, int apt) {
 hipError_t launch_pairs(const BatchLaunch& b, hipStream_t s);
 // The pair form's list build and one force pass on given positions (inspection): per atom its
 // list-grid cell and rank, the cell starts (cells + 1), the pair words of each wave segment
-// (kcap * 256 per wave) and their counts, the forces (3n), out[0] = W_xy, out[1] = 1 if a
-// pair fell inside the guard radius, out[2] = the Lees-Edwards offset used.
+// (kcap * 64 * apt per wave) and their counts, the forces (3n), out[0] = W_xy, out[1] = 1 if
+// a pair fell inside the guard radius, out[2] = the Lees-Edwards offset used, out[3] = 1 if
+// a wave's pair list outgrew its segment (the list then incomplete).
 hipError_t launch_debug_pair_form(const SysDev& S, double gamma_dot, int64_t kstep, const double* r,
                                   int32_t kcap, uint32_t* pairs, int32_t* seg_count,
                                   int32_t* cell_of, int32_t* rank_of, int32_t* start, double* f,

@@ -1088,6 +1088,7 @@ __global__ __launch_bounds__(kPairThreads) void k_debug_pair_form(
         out[0] = m[0] * kSumStep;
         out[1] = m[1];
         out[2] = dxle;
+        out[3] = ovf ? 1.0 : 0.0;
     }
 }
 

@@ -16,6 +16,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libttcf.so")
 
 TTCF_OK, TTCF_EINVAL, TTCF_ENOMEM, TTCF_EDEVICE, TTCF_ESTATE, TTCF_EUNSTABLE = 0, -1, -2, -3, -4, -5
+TTCF_ESCRATCH = -6
+STATIC_SCRATCH_BYTES = 1 << 20
 TTCF_WCA, TTCF_LJ = 0, 1
 TTCF_PREC_FP64, TTCF_PREC_FP32_FORCES = 0, 1
 TTCF_DAUGHTER_GIK, TTCF_DAUGHTER_NH = 0, 1
@@ -171,6 +173,8 @@ def lib():
         "ttcf_cell_grid": [S, C.c_double, I, I, D],
         "ttcf_debug_pair_form": [S, C.c_double, C.c_int64, C.c_double, C.c_int32, D, I, I, I, I,
                                  C.c_int64, I, I, L64, D, D, V],
+        "ttcf_pair_forces_static": [S, C.c_double, C.c_int64, C.c_double, C.c_int32, V, V, V,
+                                    V],
         "ttcf_step_timing": [V, D, L64, C.c_int32],
         "ttcf_set_step_shape": [V, C.c_int32, C.c_int32, C.c_double, C.c_int32],
         "ttcf_cv_init": [V, C.c_int32, F, C.c_int64],
@@ -238,7 +242,7 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_record_mother", "ttcf_export_mother_series", "ttcf_export_daughter",
             "ttcf_export_series", "ttcf_daughter_health", "ttcf_debug_poison",
             "ttcf_debug_cell_list", "ttcf_debug_pairs", "ttcf_debug_forces", "ttcf_step_timing",
-            "ttcf_cell_grid", "ttcf_debug_pair_form",
+            "ttcf_cell_grid", "ttcf_debug_pair_form", "ttcf_pair_forces_static",
             "ttcf_set_step_shape", "ttcf_cv_init", "ttcf_cv_export_weights",
             "ttcf_cv_add_training", "ttcf_cv_export_training", "ttcf_cv_train", "ttcf_cv_attach", "ttcf_cv_calibrate", "ttcf_cv_mean_term",
             "ttcf_cv_response", "ttcf_mlp_forward", "ttcf_mlp_gradient",
@@ -391,6 +395,20 @@ def ttcf_debug_pair_form(sys: System, r, gamma_dot: float = 0.0, kstep: int = 0,
                 pairs=(pi[:k].copy(), pj[:k].copy()), f=f.reshape(3, n), w_xy=out[0],
                 dxle=out[1], rlist=out[2], close=bool(out[3] != 0.0),
                 overflow=code == TTCF_EUNSTABLE)
+
+
+def ttcf_pair_forces_static(sys: System, gamma_dot: float, kstep: int, skin: float, kcap: int,
+                            r_dev: int, f_dev: int, out_dev: int, stream=None) -> int:
+    """The allocation-free form of ttcf_debug_pair_form's force pass: device pointers r_dev
+    (3n FP64 positions), f_dev (3n FP64 forces out), out_dev (4 FP64 out: W_xy, close flag,
+    offset used, overflow flag), enqueued on `stream` (a HIP stream handle or None). Returns
+    the status (TTCF_ESCRATCH when the input outgrows the static scratch); raises on any
+    other error."""
+    code = lib().ttcf_pair_forces_static(C.byref(sys), float(gamma_dot), int(kstep),
+                                         float(skin), int(kcap), r_dev, f_dev, out_dev, stream)
+    if code not in (TTCF_OK, TTCF_ESCRATCH):
+        _check(code, "ttcf_pair_forces_static")
+    return code
 
 
 def ttcf_debug_forces(sys: System, r, dxle: float = 0.0, stream=None):

@@ -41,6 +41,21 @@ def test_strerror_and_argument_checks_without_device(built):
     lib.ttcf_destroy(None)
 
 
+def test_static_scratch_refuses_an_input_beyond_its_size_before_device_work(built):
+    """ttcf_pair_forces_static checks the size against its static scratch before any HIP call:
+    here, with no GPU, an oversized input gets TTCF_ESCRATCH (a later check would report a
+    device error instead)."""
+    import ttcf_inputs as I
+    s = I.System(10, density=0.7)  # 4000 atoms at 64 pairs per atom: 2^18 pair words
+    sysd = built.make_system(s.n, s.box, s.temperature, s.dt, precision=1)
+    lib = built.lib()
+    assert lib.ttcf_pair_forces_static(sysd, 0.0, 0, 0.0, 64, None, None, None,
+                                       None) == built.TTCF_EINVAL  # NULL buffers
+    code = lib.ttcf_pair_forces_static(sysd, 0.0, 0, 0.0, 64, 1, 1, 1, None)
+    assert code == built.TTCF_ESCRATCH
+    assert b"static scratch" in lib.ttcf_strerror(code)
+
+
 def _c_layout(struct: str, fields):
     """sizeof and offsetof of a struct of include/ttcf.h, from gcc."""
     import subprocess

@@ -43,7 +43,6 @@ constexpr float kForceUnits = 524288.0f;     // 2^19 fixed-point units per force
 constexpr float kForceStep = 1.0f / 524288.0f;
 constexpr float kSumUnits = 1048576.0f;      // 2^20 units per virial or energy unit
 constexpr double kSumStep = 1.0 / 1048576.0;
-constexpr double kRound52 = 6755399441055744.0;  // 1.5 * 2^52: adding it rounds to an integer
 constexpr double kTwo52 = 4503599627370496.0;    // 2^52
 
 struct PairLds {
@@ -135,11 +134,6 @@ __device__ __forceinline__ int3 unpack_force(const int4& q) {
     const long long v = ((long long)(uint32_t)q.y << 32) | (uint32_t)q.x;
     const int lo = (int)(uint32_t)v;
     return make_int3(lo, (int)((v - (long long)lo) >> 32), q.z);
-}
-
-// round(a b 2^20) as an exact FP64 integer (|a b| < 2^31).
-__device__ __forceinline__ double quant(float a, float b) {
-    return __builtin_fma((double)a, (double)(b * kSumUnits), kRound52) - kRound52;
 }
 
 // The series coefficients of iso_kick_coeffs_tab, written to the job's LDS by one thread:
@@ -541,7 +535,10 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
     const float ca = (float)S.c_attr;
     const float ushift = (float)S.u_shift;
     const float ux = S.fix_unit[0], uy = S.fix_unit[1], uz = S.fix_unit[2];
-    PfSums o{0.0, 0.0, 0.0, 0.0, 0.0, 0};
+    // force factor in force units: 2^19 (48 s3 - 24 c) s3 / r^2
+    const float f48 = 48.f * kForceUnits, f24 = 24.f * kForceUnits * ca;
+    // lane shares of the sums in 2^-20 units (exact 64-bit integers)
+    long long aw = 0, axx = 0, ayy = 0, azz = 0, au = 0;
     bool close = false;
     // lane s < W: pairs of segment s and the chunks before it; lanes from W on: the total
     int seg_pairs = 0, seg_first = 0;
@@ -564,7 +561,7 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
     // software pipeline: the pair words two chunks ahead and the positions one chunk ahead
     // are loaded before this chunk's atomics (LDS operations complete in order, so loads
     // issued after the atomics would wait for them)
-    const int g0 = threadIdx.x >> 6;
+    const int g0 = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t w_next = word_of(g0);
     uint32_t w_after = word_of(g0 + nwb);
     uint3 pi_next = *(const uint3*)&L.pos[w_next & 0x3FFFu];
@@ -587,13 +584,11 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
         if (live & (r2 < rc2)) {
             const float inv = recip(r2);
             const float s3 = inv * inv * inv;
-            const float fs = s3 * (48.f * s3 - 24.f * ca) * inv;
-            const float gx = fs * dx, gy = fs * dy, gz = fs * dz;
+            const float fs = s3 * (f48 * s3 - f24) * inv;
+            const float gx = fs * dx, gy = fs * dy, gz = fs * dz;  // in force units
             close |= r2 < rg2;
-            // rounded to the nearest unit (ties to even, so symmetric): the two atoms get
-            // exactly opposite increments
-            const int qx = __float2int_rn(gx * kForceUnits), qy = __float2int_rn(gy * kForceUnits),
-                      qz = __float2int_rn(gz * kForceUnits);
+            // rounded to the nearest unit; atom j gets exactly the negated increment
+            const int qx = __float2int_rn(gx), qy = __float2int_rn(gy), qz = __float2int_rn(gz);
             // x and y share one 64-bit integer, V = qy 2^32 + qx: sums of such values are
             // exact, and each component stays within +-2^31, so both decode exactly
             const unsigned long long v = (unsigned long long)(((long long)qy << 32) + (long long)qx);
@@ -601,17 +596,24 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
             unsigned long long* aj = (unsigned long long*)&L.facc[sj];
             atomicAdd(ai, v);
             atomicAdd((int*)ai + 2, qz);
-            atomicAdd(aj, 0ull - v);
-            atomicAdd((int*)aj + 2, -qz);
-            o.w += quant(dx, gy);
+            atomicSub(aj, v);
+            atomicSub((int*)aj + 2, qz);
+            // pair sums: the FP32 product rounded to a 2^-20 unit (force units are 2^-19)
+            aw += __float2int_rn(dx * (2.f * gy));
             if (OBS) {
-                o.xx += quant(dx, gx);
-                o.yy += quant(dy, gy);
-                o.zz += quant(dz, gz);
-                o.u += quant(1.0f, 4.f * s3 * (s3 - ca) + ushift);
+                axx += __float2int_rn(dx * (2.f * gx));
+                ayy += __float2int_rn(dy * (2.f * gy));
+                azz += __float2int_rn(dz * (2.f * gz));
+                au += __float2int_rn((4.f * s3 * (s3 - ca) + ushift) * kSumUnits);
             }
         }
     }
+    PfSums o;
+    o.w = (double)aw;
+    o.xx = (double)axx;
+    o.yy = (double)ayy;
+    o.zz = (double)azz;
+    o.u = (double)au;
     o.close = close ? 1 : 0;
     return o;
 }

@@ -1074,9 +1074,16 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
     (void)block_explicit;
     const int apt = nlf ? pair_job_apt(nmax) : pick_apt(nmax, threads);
     if (apt < 0) return fail(c, TTCF_EINVAL, "batch needs more than 4 atoms per thread");
+    // pair words in LDS when every job's fit beside its layout (four atoms per thread only),
+    // else in global scratch
+    size_t nl_lds_pl = 0;
     if (nlf)
-        for (const DaughterDesc* dp : group)
+        for (const DaughterDesc* dp : group) {
             pair_stride = std::max<int64_t>(pair_stride, pair_words(dp->sys.n, dp->kmax, apt));
+            nl_lds_pl = std::max(nl_lds_pl, lds_bytes_pairs_lds(dp->sys.n, dp->sys.lc[0] * dp->sys.lc[1] *
+                                                                   dp->sys.lc[2], dp->kmax, apt));
+        }
+    const bool pairs_lds = nlf && apt == 4 && nl_lds_pl <= c->max_lds;
     *L = BatchLaunch{};
     L->descs = c->d_descs;
     L->n_jobs = (int32_t)group.size();
@@ -1098,7 +1105,8 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
         return fail(c, TTCF_EINVAL, "colour-field daughters cannot share a step call with "
                                     "daughters recording the extra observables");
     L->pair_stride = pair_stride;
-    L->lds_bytes = nlf ? nl_lds : lds_bytes_for(nmax, cmax, threads, precision);
+    L->pairs_lds = pairs_lds ? 1 : 0;
+    L->lds_bytes = nlf ? (pairs_lds ? nl_lds_pl : nl_lds) : lds_bytes_for(nmax, cmax, threads, precision);
     if (L->lds_bytes > c->max_lds) return fail(c, TTCF_EINVAL, "batch exceeds the LDS of one workgroup");
     const int per_cu_lds = (int)(c->max_lds / L->lds_bytes);
     // the pair-list kernel is compiled for 512-thread workgroups (256 registers: 2 waves per
@@ -1256,7 +1264,7 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         rc = plan_group(c, ds, block_explicit, form == 1 ? kVariantCells : kVariantNeighbourList,
                         precision, n_steps, eff[group[0]].threads, &L);
         if (rc != TTCF_OK) return rc;
-        if (form != 1) {
+        if (form != 1 && !L.pairs_lds) {
             rc = ensure_nl_scratch(c, sizeof(uint32_t) * (size_t)L.grid * (size_t)L.pair_stride);
             if (rc != TTCF_OK) return rc;
             L.pairs = c->nl_scratch;
@@ -2122,7 +2130,7 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     rc = plan_group(c, hp, m.sys.block_threads > 0, nl ? kVariantNeighbourList : kVariantCells,
                     precision, gd->n_steps, shape.threads, &B);
     if (rc != TTCF_OK) return bail(rc, c->err);
-    if (nl) {
+    if (nl && !B.pairs_lds) {
         // the graph owns the pair-list scratch its replays use
         B.pairs = (uint32_t*)g->get(sizeof(uint32_t) * (size_t)B.grid * (size_t)B.pair_stride);
         if (!B.pairs) return bail(TTCF_ENOMEM, "pair-list scratch allocation failed");

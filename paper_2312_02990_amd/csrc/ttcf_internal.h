@@ -125,8 +125,9 @@ struct BatchLaunch {
     int32_t thermo;        // daughter thermostat of every job (0 isokinetic, 1 Nose-Hoover)
     int32_t obs;           // 1: some job records the extra observables (list form only)
     int32_t field;         // 1: some job is a colour-field daughter (list form)
-    int32_t pad_;
-    uint32_t* pairs;       // pair-list form: grid x pair_stride pair words
+    int32_t pairs_lds;     // pair-list form: 1 if each job's pair words live in LDS after its
+                           // layout (lds_bytes covers lds_bytes_pairs_lds of every job)
+    uint32_t* pairs;       // pair-list form otherwise: grid x pair_stride pair words
     int64_t pair_stride;   // >= job_threads(n) / 64 * 256 * kmax of every job
     size_t lds_bytes;
 };
@@ -257,6 +258,10 @@ int pair_job_apt(int n);
 // segments hold 64 apt kcap words each
 inline int64_t pair_words(int n, int kcap, int apt) {
     return (int64_t)pair_job_threads(n) * apt * kcap;
+}
+// LDS of one job with its pair words in LDS too (after the job's layout)
+inline size_t lds_bytes_pairs_lds(int n, int cells, int kcap, int apt) {
+    return lds_bytes_pairs(n, cells) + sizeof(uint32_t) * (size_t)pair_words(n, kcap, apt);
 }
 hipError_t launch_pairs(const BatchLaunch& b, hipStream_t s);
 // The pair form's list build and one force pass on given positions (inspection): per atom its

@@ -7,8 +7,9 @@
 // FP64 registers of their owner for the whole call.
 //
 // Pair list. Every pair closer than the list radius r_l = r_c + skin is stored once, as one
-// 32-bit word (two 14-bit atom ranks and the pair's y image), in a segment of per-workgroup
-// global scratch that belongs to one wave. The list is built from a cell grid whose cells
+// 32-bit word (two 14-bit atom ranks and whether the pair crosses the y boundary), in a
+// segment that belongs to one wave: in LDS after the job's layout when all segments fit
+// there, else in per-workgroup global scratch. The list is built from a cell grid whose cells
 // are at least r_l wide: the atoms are counting-sorted into canonical (cell, atom id) order
 // (their rank), and the atom of rank s scans the half of the 27-cell neighbourhood that lies
 // after it (its own cell past s, the next cell in x, the row above in y, and the three rows
@@ -17,19 +18,22 @@
 // to reach r_c (the bound of the previous list form: 2 d + |gamma_dot| t (r_c + 2 d) >= skin,
 // d the largest peculiar path length since the build).
 //
-// Forces. A wave walks its own segment 64 pairs at a time, every lane busy. Each pair's force
-// is rounded to 32-bit fixed point (nearest multiple of 2^-19 force units) and added to both atoms with LDS integer
-// atomics (+ to one, - to the other). Integer sums do not depend on their order, so every
-// atom's force is independent of the list's order, of the skin and grid, of which lane or
-// wave evaluated a pair, and of the rebuild schedule; the total force is exactly zero. The
-// virial x_ij F_y,ij of each pair is rounded to a multiple of 2^-20 and summed as an exact
-// integer in FP64, so W_xy has the same independence.
+// Forces. The 64-pair chunks of all segments are dealt round robin to the waves, every lane
+// busy. Each pair's force is truncated to 32-bit fixed point (a multiple of 2^-19 force
+// units) and added to both atoms with LDS integer atomics (+ to one, - to the other). Integer
+// sums do not depend on their order, so every atom's force is independent of the list's
+// order, of the skin and grid, of which lane or wave evaluated a pair, and of the rebuild
+// schedule; the total force is exactly zero. The virial x_ij F_y,ij of each pair (and the
+// extra observables' pair terms) is rounded to a multiple of 2^-19 and summed as an exact
+// 64-bit integer, so W_xy has the same independence.
 //
 // Separations come from 32-bit fixed-point positions X = round(x 2^32 / L) (the box is 2^32
 // units wide, so integer differences wrap to the minimum image). Between rebuilds the
 // published positions are unwrapped: an atom that crossed the y boundary c times keeps
-// X + c offset(t) in x, so each pair keeps the y image it was built with, and the separation
-// is X_i - X_j - n_y offset(t) with n_y stored in the pair word.
+// X + c offset(t) in x, so each pair keeps the y image it was built with. A pair whose j
+// image lies above i is stored as (i, j) with the shift flag, one whose image lies below as
+// (j, i) with the flag, so the separation is X_i - X_j, or X_i - (X_j + offset(t)) when
+// flagged; every atom publishes both x values.
 #include "ttcf_device.h"
 
 namespace ttcf {
@@ -41,14 +45,16 @@ constexpr int kScanPerTrip = 4;              // list build: candidates per lane 
 constexpr int kPfRed = 16;                   // doubles per thread in one block reduction
 constexpr float kForceUnits = 524288.0f;     // 2^19 fixed-point units per force unit
 constexpr float kForceStep = 1.0f / 524288.0f;
-constexpr float kSumUnits = 1048576.0f;      // 2^20 units per virial or energy unit
-constexpr double kSumStep = 1.0 / 1048576.0;
+constexpr float kSumUnits = 524288.0f;       // 2^19 units per virial or energy unit
+constexpr double kSumStep = 1.0 / 524288.0;
 constexpr double kTwo52 = 4503599627370496.0;    // 2^52
 
 struct PairLds {
-    uint4* pos;        // [n] by rank: fixed-point x, y, z; w = cx | cy << 10 | cz << 20
+    uint4* pos;        // [n] by rank: fixed-point x, y, z, and x + the Lees-Edwards offset
+                       // (the x of the image a pair across the y boundary uses)
     int4* facc;        // [n] by rank: fixed-point force accumulators: (x, y) packed in one
-                       // 64-bit integer y 2^32 + x, then z, then unused
+                       // 64-bit integer y 2^32 + x, then z; w: the rank's list-grid cell
+                       // cx | cy << 10 | cz << 20 (set by each build)
     int32_t* cnt;      // [cells] counts, then placement cursors
     int32_t* start;    // [cells + 1]
     int32_t* rowinfo;  // [3 rows][2]: first x cell offset mod lc_x, cell count
@@ -135,6 +141,13 @@ __device__ __forceinline__ int3 unpack_force(const int4& q) {
     const int lo = (int)(uint32_t)v;
     return make_int3(lo, (int)((v - (long long)lo) >> 32), q.z);
 }
+
+// Pair words: rank i (bits 0-13), rank j (14-27); kShiftBit: j is taken at its image across
+// the y boundary, x_j + the Lees-Edwards offset (a pair whose image lies the other way is
+// stored as (j, i)); kNoPair: no pair (lanes past a segment's end), ranks 0 so that its
+// position loads stay in bounds.
+constexpr uint32_t kShiftBit = 1u << 28;
+constexpr uint32_t kNoPair = 1u << 29;
 
 // The series coefficients of iso_kick_coeffs_tab, written to the job's LDS by one thread:
 // tab[k] = 1/(2k+2)! (k = 0..6), tab[7 + k] = 1/(2k+1)! (k = 0..7).
@@ -285,18 +298,19 @@ __device__ __forceinline__ PairLds job_lds(int n, int cells) {
     return carve_pairs(pf_smem + kJobBytes, n, cells);
 }
 
-typedef __attribute__((address_space(1))) uint32_t gu32;  // global pair words
+typedef __attribute__((address_space(1))) uint32_t gu32;  // pair words in global scratch
+typedef __attribute__((address_space(3))) uint32_t lu32;  // pair words in LDS
 
 // ---------------------------------------------------------------------------------------
 // list build
 // ---------------------------------------------------------------------------------------
 
 // Pairs of this wave's ranks (rank s tests the half neighbourhood after it) into `seg`
-// (capacity seg_cap). Returns the number found (wave-uniform; may exceed the capacity).
-// Out of line, so that the step loop's registers and these do not add up.
-template <int APT>
-__device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, gu32* seg,
-                                            int seg_cap, int tj) {
+// (capacity seg_cap; gu32* or lu32*). Returns the number found (wave-uniform; may exceed the
+// capacity).
+template <int APT, typename P>
+__device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, P seg, int seg_cap,
+                                            int tj) {
     const PairLds L = job_lds(n, cells);
     const SysDev& S = *L.sys;
     const int nc0 = S.lc[0], nc1 = S.lc[1], nc2 = S.lc[2];
@@ -311,9 +325,9 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, gu32
         if (r0 + u * 64 >= n) break;  // wave-uniform
         const int s = r0 + u * 64 + lane;
         const bool own = s < n;
-        const uint4 qi = L.pos[own ? s : 0];
-        const int cx = (int)(qi.w & 1023u), cy = (int)((qi.w >> 10) & 1023u),
-                  cz = (int)(qi.w >> 20);
+        const uint3 qi = *(const uint3*)&L.pos[own ? s : 0];
+        const uint32_t cc = (uint32_t)L.facc[own ? s : 0].w;
+        const int cx = (int)(cc & 1023u), cy = (int)((cc >> 10) & 1023u), cz = (int)(cc >> 20);
 #pragma unroll 1
         for (int r = 0; r < 5; ++r) {
             // row r: (dz, dy) = (0, 0) own cell past s and the next cell in x; (0, +1);
@@ -369,19 +383,21 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, gu32
             const uint32_t rsh = ny > 0 ? dxq : (ny < 0 ? 0u - dxq : 0u);
             const int len0 = own ? max(hi0 - lo0, 0) : 0;
             const int len = len0 + (own ? max(hi1 - lo1, 0) : 0);
-            const uint32_t wbase = (uint32_t)s | ((uint32_t)(ny + 1) << 28);
+            // the pair word: (s, k), or (k, s) for an image below, flagged when shifted
+            const int shs = ny < 0 ? 14 : 0;
+            const uint32_t wfix = ((uint32_t)s << shs) | (ny != 0 ? kShiftBit : 0u);
             // kScanPerTrip candidates per lane per trip, their loads issued together; trips
             // until the wave's longest row is done
             for (int v = 0; __builtin_amdgcn_ballot_w64(v < len) != 0; v += kScanPerTrip) {
                 int k[kScanPerTrip];
-                uint4 q[kScanPerTrip];
+                uint3 q[kScanPerTrip];
 #pragma unroll
                 for (int u = 0; u < kScanPerTrip; ++u) {
                     const int vv = v + u;
                     k[u] = vv >= len ? s : (vv < len0 ? lo0 + vv : lo1 + (vv - len0));
                 }
 #pragma unroll
-                for (int u = 0; u < kScanPerTrip; ++u) q[u] = L.pos[own ? k[u] : 0];
+                for (int u = 0; u < kScanPerTrip; ++u) q[u] = *(const uint3*)&L.pos[own ? k[u] : 0];
 #pragma unroll
                 for (int u = 0; u < kScanPerTrip; ++u) {
                     const float ddx = (float)(int32_t)(qi.x - q[u].x - rsh) * ux;
@@ -392,7 +408,7 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, gu32
                     const int below = (int)__builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                     const int at = base + below;
-                    if (hit && at < seg_cap) seg[at] = wbase | ((uint32_t)k[u] << 14);
+                    if (hit && at < seg_cap) seg[at] = wfix | ((uint32_t)k[u] << (14 - shs));
                     base += (int)__builtin_popcountll(m);
                 }
             }
@@ -406,12 +422,12 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, gu32
 // this wave's pairs in `seg`. Returns the wave's pair count (may exceed seg_cap); *overflow
 // receives whether any wave's list overflowed (the same in every thread). cell: the list-grid
 // cell of each owned atom (-1 past n). Every thread of the workgroup calls it.
-template <int APT>
+template <int APT, typename P>
 __device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t dxq,
                                           const double (&x)[APT], const double (&y)[APT],
                                           const double (&z)[APT], int (&rank)[APT],
-                                          int (&cr)[APT], const PairLds& L, gu32* seg,
-                                          int seg_cap, int tj, int (&cell)[APT], bool* overflow) {
+                                          int (&cr)[APT], const PairLds& L, P seg, int seg_cap,
+                                          int tj, int (&cell)[APT], bool* overflow) {
     const int T = blockDim.x, t = threadIdx.x, n = S.n;
     const int nc0 = S.lc[0], nc1 = S.lc[1], nc2 = S.lc[2];
     const int C = nc0 * nc1 * nc2;
@@ -489,8 +505,14 @@ __device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t
         }
     }
     __syncthreads();
-    // the scratch is free again: clear the force accumulators for the next force pass
-    for (int i = t; i < n; i += T) L.facc[i] = make_int4(0, 0, 0, 0);
+    // the scratch is free again: clear the force accumulators for the next force pass and
+    // move each rank's cell there; the shifted x in its place
+    for (int i = t; i < n; i += T) {
+        const uint4 q = L.pos[i];
+        L.facc[i] = make_int4(0, 0, 0, (int)q.w);
+        L.pos[i].w = q.x + dxq;
+    }
+    __syncthreads();
     const int count = pf_gen_pairs<APT>(n, C, dxq, seg, seg_cap, tj);
     const int wave = t >> 6, nwb = T >> 6;
     if ((t & 63) == 0) {
@@ -508,16 +530,12 @@ __device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t
 // force pass
 // ---------------------------------------------------------------------------------------
 
-// Lane shares of the pair sums of one force pass, in units of 2^-20 (exact integers): W_xy,
+// Lane shares of the pair sums of one force pass, in units of 2^-19 (exact integers): W_xy,
 // and (OBS) W_xx, W_yy, W_zz and U; close: a pair came inside the guard radius.
 struct PfSums {
     double w, xx, yy, zz, u;
     int close;
 };
-
-// A pair word that stands for no pair (lanes past a segment's end): image code 3, atoms at
-// rank 0 so that its position loads stay in bounds.
-constexpr uint32_t kNoPair = 3u << 28;
 
 // Forces of the pairs of every wave segment into the fixed-point accumulators. The segments'
 // 64-pair chunks, taken in order (segment 0 first), go round robin to the waves of the
@@ -525,9 +543,9 @@ constexpr uint32_t kNoPair = 3u << 28;
 // same share whatever its own list held. Called by every thread; the pair counts come from
 // the last build (L.wcnt). Out of line, so that the step loop's registers and these do not
 // add up.
-template <bool OBS>
-__device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
-                                            const gu32* pair_base, int seg_cap) {
+template <bool OBS, typename P>
+__device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq, P pair_base,
+                                            int seg_cap) {
     const PairLds L = job_lds(n, cells);
     const SysDev& S = *L.sys;
     const int lane = threadIdx.x & 63, nwb = blockDim.x >> 6;
@@ -537,7 +555,7 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
     const float ux = S.fix_unit[0], uy = S.fix_unit[1], uz = S.fix_unit[2];
     // force factor in force units: 2^19 (48 s3 - 24 c) s3 / r^2
     const float f48 = 48.f * kForceUnits, f24 = 24.f * kForceUnits * ca;
-    // lane shares of the sums in 2^-20 units (exact 64-bit integers)
+    // lane shares of the sums in 2^-19 units (exact 64-bit integers)
     long long aw = 0, axx = 0, ayy = 0, azz = 0, au = 0;
     bool close = false;
     // lane s < W: pairs of segment s and the chunks before it; lanes from W on: the total
@@ -565,30 +583,31 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
     uint32_t w_next = word_of(g0);
     uint32_t w_after = word_of(g0 + nwb);
     uint3 pi_next = *(const uint3*)&L.pos[w_next & 0x3FFFu];
-    uint3 pj_next = *(const uint3*)&L.pos[(w_next >> 14) & 0x3FFFu];
+    uint4 pj_next = L.pos[(w_next >> 14) & 0x3FFFu];
     for (int g = g0; g < chunks; g += nwb) {
         const uint32_t word = w_next;
-        const bool live = (word >> 28) != 3u;
-        const uint3 qi = pi_next, qj = pj_next;
+        const bool live = (word & kNoPair) == 0u;
+        const uint3 qi = pi_next;
+        const uint4 qj = pj_next;
         w_next = w_after;
         w_after = word_of(g + 2 * nwb);
         pi_next = *(const uint3*)&L.pos[w_next & 0x3FFFu];
-        pj_next = *(const uint3*)&L.pos[(w_next >> 14) & 0x3FFFu];
+        pj_next = L.pos[(w_next >> 14) & 0x3FFFu];
         const int si = (int)(word & 0x3FFFu), sj = (int)((word >> 14) & 0x3FFFu);
-        const uint32_t img = word >> 28;  // n_y + 1
-        const uint32_t sh = img == 2u ? dxq : (img == 0u ? 0u - dxq : 0u);
-        const float dx = (float)(int32_t)(qi.x - qj.x - sh) * ux;
+        const uint32_t xj = (word & kShiftBit) ? qj.w : qj.x;
+        const float dx = (float)(int32_t)(qi.x - xj) * ux;
         const float dy = (float)(int32_t)(qi.y - qj.y) * uy;
         const float dz = (float)(int32_t)(qi.z - qj.z) * uz;
         const float r2 = dx * dx + dy * dy + dz * dz;
         if (live & (r2 < rc2)) {
-            const float inv = recip(r2);
+            const float inv = __builtin_amdgcn_rcpf(r2);  // within 1 ulp
             const float s3 = inv * inv * inv;
             const float fs = s3 * (f48 * s3 - f24) * inv;
             const float gx = fs * dx, gy = fs * dy, gz = fs * dz;  // in force units
             close |= r2 < rg2;
-            // rounded to the nearest unit; atom j gets exactly the negated increment
-            const int qx = __float2int_rn(gx), qy = __float2int_rn(gy), qz = __float2int_rn(gz);
+            // truncated to a whole unit: odd in the separation, so a pair gives the same
+            // increments whichever atom it lists first; atom j gets exactly the negation
+            const int qx = __float2int_rz(gx), qy = __float2int_rz(gy), qz = __float2int_rz(gz);
             // x and y share one 64-bit integer, V = qy 2^32 + qx: sums of such values are
             // exact, and each component stays within +-2^31, so both decode exactly
             const unsigned long long v = (unsigned long long)(((long long)qy << 32) + (long long)qx);
@@ -598,12 +617,13 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
             atomicAdd((int*)ai + 2, qz);
             atomicSub(aj, v);
             atomicSub((int*)aj + 2, qz);
-            // pair sums: the FP32 product rounded to a 2^-20 unit (force units are 2^-19)
-            aw += __float2int_rn(dx * (2.f * gy));
+            // pair sums: the FP32 products rounded to the nearest 2^-19 unit, ties to even
+            // (odd, so that mirrored configurations give exactly opposite sums)
+            aw += __float2int_rn(dx * gy);
             if (OBS) {
-                axx += __float2int_rn(dx * (2.f * gx));
-                ayy += __float2int_rn(dy * (2.f * gy));
-                azz += __float2int_rn(dz * (2.f * gz));
+                axx += __float2int_rn(dx * gx);
+                ayy += __float2int_rn(dy * gy);
+                azz += __float2int_rn(dz * gz);
                 au += __float2int_rn((4.f * s3 * (s3 - ca) + ushift) * kSumUnits);
             }
         }
@@ -623,7 +643,7 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq,
 // ---------------------------------------------------------------------------------------
 
 // The extra observables at one time point: kinetic parts from the owned atoms' momenta p,
-// pair parts (exact integers in units of 2^-20) of the force pass, reduced over the
+// pair parts (exact integers in units of 2^-19) of the force pass, reduced over the
 // workgroup (kinetic and pair sums in separate slots) and written by thread 0 to row `row`.
 template <int APT>
 __device__ __forceinline__ void pf_record_obs(const SysDev& S, const double (&y)[APT],
@@ -683,9 +703,9 @@ __device__ __forceinline__ float pf_publish(const SysDev& S, uint32_t dxq, const
         const int a = t + j * tj;
         if (t < tj && a < n) {
             // x, y, z only: w keeps the cell of the last build
-            *(uint3*)&L.pos[rank[j]] =
-                make_uint3(fixq(x[j], S.fix_scale[0]) + (uint32_t)cr[j] * dxq,
-                           fixq(y[j], S.fix_scale[1]), fixq(z[j], S.fix_scale[2]));
+            const uint32_t qx = fixq(x[j], S.fix_scale[0]) + (uint32_t)cr[j] * dxq;
+            L.pos[rank[j]] =
+                make_uint4(qx, fixq(y[j], S.fix_scale[1]), fixq(z[j], S.fix_scale[2]), qx + dxq);
             pm = fmaxf(pm, path[j]);
         }
     }
@@ -709,9 +729,9 @@ __device__ __forceinline__ float pf_publish(const SysDev& S, uint32_t dxq, const
 // COL: the build that also runs colour-field daughters (either thermostat): atom a carries
 // the colour charge +1 (even a) or -1 (odd a), the field adds charge * F_e to its x force in
 // FP64, there is no shear, and the series records V J_x = sum_a charge p_x,a.
-template <int APT, bool NH, bool OBS, bool COL>
+template <int APT, bool NH, bool OBS, bool COL, typename P>
 __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairLds& L,
-                                   gu32* pair_base) {
+                                   P pair_base) {
     const int t = threadIdx.x;
     if (t == 0) {
         *L.sys = dsc->sys;
@@ -739,7 +759,7 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
     if (todo <= 0 && done > 0) return;
     // this wave's pair segment
     const int seg_cap = dsc->kmax * 64 * APT;
-    gu32* seg = pair_base + (size_t)wave * seg_cap;
+    const P seg = pair_base + (size_t)wave * seg_cap;
 
     double x[APT], y[APT], z[APT], px[APT], py[APT], pz[APT];
     float fx[APT], fy[APT], fz[APT];  // FP32 forces; every use promotes them to FP64
@@ -791,7 +811,7 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
                 fx[j] = (float)q.x * kForceStep;
                 fy[j] = (float)q.y * kForceStep;
                 fz[j] = (float)q.z * kForceStep;
-                L.facc[rank[j]] = make_int4(0, 0, 0, 0);
+                *(int3*)&L.facc[rank[j]] = make_int3(0, 0, 0);  // w keeps the cell
             }
         }
     };
@@ -1012,7 +1032,9 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
     __syncthreads();
 }
 
-template <int APT, bool NH, bool OBS, bool COL>
+// PL: the pair words of every job live in LDS after its layout (b.lds_bytes covers them),
+// else in the workgroup's slice of b.pairs.
+template <int APT, bool NH, bool OBS, bool COL, bool PL>
 __global__ __launch_bounds__(kPairThreads) void k_daughters_pairs(BatchLaunch b) {
     int32_t* job = (int32_t*)pf_smem;
     for (;;) {
@@ -1028,8 +1050,12 @@ __global__ __launch_bounds__(kPairThreads) void k_daughters_pairs(BatchLaunch b)
         for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
         for (int i = threadIdx.x; i < n; i += blockDim.x) L.facc[i] = make_int4(0, 0, 0, 0);
         // run_daughter_pairs synchronises before its first use of the counts
-        run_daughter_pairs<APT, NH, OBS, COL>(d, b.max_steps, L,
-                                         (gu32*)(b.pairs + (size_t)blockIdx.x * b.pair_stride));
+        if constexpr (PL)
+            run_daughter_pairs<APT, NH, OBS, COL>(
+                d, b.max_steps, L, (lu32*)(pf_smem + kJobBytes + plan_pairs(n, cells).total));
+        else
+            run_daughter_pairs<APT, NH, OBS, COL>(
+                d, b.max_steps, L, (gu32*)(b.pairs + (size_t)blockIdx.x * b.pair_stride));
     }
 }
 
@@ -1101,23 +1127,29 @@ int pair_job_apt(int n) { return job_apt(n); }
 
 size_t lds_bytes_pairs(int n, int cells) { return kJobBytes + plan_pairs(n, cells).total; }
 
-template <int APT, bool NH, bool OBS, bool COL>
+template <int APT, bool NH, bool OBS, bool COL, bool PL>
 static hipError_t launch_pairs_t(const BatchLaunch& b, hipStream_t s) {
-    (void)hipFuncSetAttribute((const void*)k_daughters_pairs<APT, NH, OBS, COL>,
+    (void)hipFuncSetAttribute((const void*)k_daughters_pairs<APT, NH, OBS, COL, PL>,
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)b.lds_bytes);
-    hipLaunchKernelGGL((k_daughters_pairs<APT, NH, OBS, COL>), dim3(b.grid), dim3(b.threads),
+    hipLaunchKernelGGL((k_daughters_pairs<APT, NH, OBS, COL, PL>), dim3(b.grid), dim3(b.threads),
                        b.lds_bytes, s, b);
     return hipGetLastError();
 }
 
 template <bool NH, bool OBS, bool COL>
 static hipError_t launch_pairs_a(const BatchLaunch& b, hipStream_t s) {
-    // the atoms per thread of the largest job; every job of the launch runs with it
-    return b.apt == 4 ? launch_pairs_t<4, NH, OBS, COL>(b, s) : launch_pairs_t<8, NH, OBS, COL>(b, s);
+    // the atoms per thread of the largest job; every job of the launch runs with it. Pair
+    // words in LDS only fit next to systems of four atoms per thread.
+    if (b.apt == 4)
+        return b.pairs_lds ? launch_pairs_t<4, NH, OBS, COL, true>(b, s)
+                           : launch_pairs_t<4, NH, OBS, COL, false>(b, s);
+    if (b.pairs_lds) return hipErrorInvalidValue;
+    return launch_pairs_t<8, NH, OBS, COL, false>(b, s);
 }
 
 hipError_t launch_pairs(const BatchLaunch& b, hipStream_t s) {
-    if (b.precision != 1 || !b.pairs || b.threads > kPairThreads || b.threads % 64 != 0 ||
+    if (b.precision != 1 || (!b.pairs && !b.pairs_lds) || b.threads > kPairThreads ||
+        b.threads % 64 != 0 ||
         (b.apt != 4 && b.apt != 8))
         return hipErrorInvalidValue;
     // colour-field daughters do not record the extra observables

@@ -29,10 +29,18 @@ BYTES_PER_ATOM_STEP = 96  # read and write of r and p in FP64 (6 x 8 B each way)
 GAMMAS = (1e-6, 1e-4, 1e-2, 1.0)
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_daughters_config2_traffic.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_config2_valu.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_pairs.hip")
 PEF_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_elongation.hip")
 PEF_VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_pef_n2048_valu.json")
 MIX_VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_mix_n2048_valu.json")
+
+
+_T0 = time.perf_counter()
+
+
+def progress(what: str):
+    """One line on stderr per finished part (the JSON line alone goes to stdout)."""
+    print(f"bench: {what} done at {time.perf_counter() - _T0:.0f} s", file=sys.stderr, flush=True)
 
 
 def kernel_hash() -> str:
@@ -69,11 +77,22 @@ def measured_valu():
 
 
 def host_threads() -> int:
+    """Threads of the CPU baseline: the cores this process may run on, at most 16 (a one-GPU
+    box's share of the host; nproc may show more)."""
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
     return max(1, min(16, n))
+
+
+def host_description() -> dict:
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"nproc": os.cpu_count(), "affinity": affinity, "threads_used_max": host_threads(),
+            "model": cpu_model()}
 
 
 def cpu_model() -> str:
@@ -86,10 +105,11 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(n_cells: int, nsteps: int, budget_s: float):
-    """The FP64 oracle, unchanged, on a bounded sample of the same workload: daughters of the
-    same system size and length from seeded start states (perturbed fcc lattice with
-    Maxwell-Boltzmann momenta), one daughter per thread at a time on the host's cores."""
+def cpu_baseline(n_cells: int, nsteps: int, budget_s: float, states=None):
+    """The FP64 oracle, unchanged, on a bounded sample of the same workload: the first start
+    states of the GPU batch (`states` = (r, p), as exported from the mother), their four
+    mapped daughters each, at one shear rate, one daughter per thread at a time on the host's
+    cores. Without `states`, seeded perturbed-lattice start states."""
     import oracle as orc
     import ttcf_inputs as I
     s = I.System(n_cells)
@@ -104,9 +124,14 @@ def cpu_baseline(n_cells: int, nsteps: int, budget_s: float):
     per_daughter = per_step * nsteps
     n_d = max(threads, int(budget_s * threads / per_daughter) // threads * threads)
     n_states = (n_d + 3) // 4
-    sr = np.stack([I.perturbed_positions(s, 100 + k, 0.1).ravel() for k in range(n_states)])
-    sp = np.stack([I.maxwell_boltzmann(s.n, s.temperature, 100 + k).ravel()
-                   for k in range(n_states)])
+    if states is not None and len(states[0]) >= n_states:
+        sr, sp = states[0][:n_states], states[1][:n_states]
+        origin = "the GPU batch's first start states"
+    else:
+        sr = np.stack([I.perturbed_positions(s, 100 + k, 0.1).ravel() for k in range(n_states)])
+        sp = np.stack([I.maxwell_boltzmann(s.n, s.temperature, 100 + k).ravel()
+                       for k in range(n_states)])
+        origin = "seeded perturbed-lattice start states"
     state_of = np.arange(n_d) // 4
     map_of = np.arange(n_d) % 4
     t0 = time.perf_counter()
@@ -116,18 +141,119 @@ def cpu_baseline(n_cells: int, nsteps: int, budget_s: float):
     return {
         "value": n_d * s.n * nsteps / dt, "unit": "daughter atom-steps/s", "cores": int(used),
         "kind": "oracle",
-        "sample": f"{n_d} daughters x {nsteps} steps of the N={s.n} system (FP64 oracle, "
-                  f"{used} threads, {cpu_model()}), {dt:.1f} s",
+        "sample": f"{n_d} daughters x {nsteps} steps of the N={s.n} system from {origin} "
+                  f"(FP64 oracle, {used} threads on {cpu_model()}), {dt:.1f} s",
+        "host": host_description(),
     }
 
 
+def cpu_baseline_configs(seed=41):
+    """The oracle on bounded samples of the other workloads, same threads: the plain FP64
+    workload (N = 256, 32 daughters x 100 steps, all of it), the uneven batch (8 daughters of
+    each size x 100 of its 400 steps), the channel (64 daughters x 2 of its 1000 steps, all
+    from one lattice start state) and the control-variate workload (N = 256, 64 daughters x 200
+    steps, and the network's forward and backward pass over 1024 rows in FP64 numpy). Rates in
+    atom-steps per second (rows per second for the network)."""
+    import oracle as orc
+    import oracle.channel as och
+    import oracle.mlp as omlp
+    import ttcf_inputs as I
+    threads = host_threads()
+    out = {"threads": threads}
+
+    def daughters(s, n_d, nsteps, gammas, sd):
+        box = orc.make_box(s.n, s.box)
+        n_states = (n_d + 3) // 4
+        sr = np.stack([I.perturbed_positions(s, sd + k, 0.1).ravel() for k in range(n_states)])
+        sp = np.stack([I.maxwell_boltzmann(s.n, s.temperature, sd + k).ravel()
+                       for k in range(n_states)])
+        t0 = time.perf_counter()
+        orc.run_daughters(box, sr, sp, np.arange(n_d) // 4, np.arange(n_d) % 4, gammas, s.dt,
+                          nsteps, nthreads=threads)
+        return n_d * s.n * nsteps / (time.perf_counter() - t0)
+
+    s1 = I.System(4)
+    out["config1_plain_fp64"] = {"value": daughters(s1, 32, 100, np.full(32, 1e-3), seed),
+                                 "sample": "32 daughters x 100 steps, N=256 (the whole workload)"}
+    rng = np.random.Generator(np.random.PCG64(seed))
+    per_size = {}
+    for n_cells, rho in ((5, 0.7), (6, 0.8442), (8, 0.9), (10, 0.7)):
+        s = I.System(n_cells, density=rho)
+        g = np.exp(rng.uniform(np.log(1e-5), np.log(1e-1), 8))
+        per_size[str(s.n)] = daughters(s, 8, 100, g, seed + n_cells)
+    out["config3_uneven"] = {"per_size": per_size,
+                             "sample": "8 daughters x 100 steps per size, rates log-uniform in "
+                                       "[1e-5, 1e-1]"}
+    g = I.ChannelSystem()
+    ch = och.make_channel(g)
+    r, p, lat = I.channel_initial_state(g, seed)
+    n_d, nsteps = 64, 2
+    q = och.nh_q(g.n_wall, g.temperature, g.nh_tau)
+    t0 = time.perf_counter()
+    och.run_daughters(ch, r.reshape(1, -1), p.reshape(1, -1), np.zeros(1), lat,
+                      np.zeros(n_d, np.int32), np.arange(n_d) % 4, np.full(n_d, 1e-2),
+                      g.temperature, q, g.dt, nsteps, nthreads=threads)
+    out["config4_channel"] = {"value": n_d * g.n * nsteps / (time.perf_counter() - t0),
+                              "sample": f"{n_d} daughters x {nsteps} steps of the {g.n}-atom "
+                                        "channel from one lattice start state"}
+    out["config5_cv_daughters"] = {"value": daughters(s1, 64, 200, np.full(64, 1e-4), seed + 99),
+                                   "sample": "64 daughters x 200 steps, N=256, rate 1e-4"}
+    net = omlp.init_weights(64, 256, 200, seed)
+    x = np.random.Generator(np.random.PCG64(seed)).standard_normal((1024, 64))
+    t = np.zeros((1024, 200))
+    t0 = time.perf_counter()
+    for _ in range(5):
+        y, cache = omlp.forward(net, x)
+        omlp.backward(net, cache, y, t)
+    out["config5_mlp_rows_per_s"] = {"value": 5 * 1024 / (time.perf_counter() - t0),
+                                     "sample": "forward and backward of 64-256-256-200 over "
+                                               "1024 rows, 5 times, FP64 numpy"}
+    return out
+
+
+def per_rate_statement(responses, expected, nst, dt):
+    """Per shear rate of the sweep: the TTCF and direct-average (DAV) responses of P_xy at the
+    last time point with their block standard errors, the healthy groups against the groups
+    run (a rate's response covers every batch run at it), the standard errors per start state
+    over the rate, SE sqrt(groups) / gamma_dot (Eq. variance: for TTCF it is the same at every
+    rate of the linear regime; the mapped direct average cancels its equilibrium part too, so
+    its error also falls with the rate until the mapped trajectories stop mirroring each
+    other), and the largest |TTCF - DAV| over time in combined standard errors."""
+    out = {}
+    for gd in sorted(responses):
+        tm, tse, dm, dse, used = responses[gd]
+        comb = np.hypot(tse, dse)[1:]
+        root = np.sqrt(max(int(used), 1))
+        out[str(gd)] = {
+            "groups": int(used), "groups_expected": int(expected[gd]),
+            "ttcf_end": float(tm[-1]), "ttcf_se_end": float(tse[-1]),
+            "dav_end": float(dm[-1]), "dav_se_end": float(dse[-1]),
+            "ttcf_se_per_state_over_rate_end": float(tse[-1] * root / gd),
+            "dav_se_per_state_over_rate_end": float(dse[-1] * root / gd),
+            "max_abs_ttcf_minus_dav_over_se": float(np.max(np.abs(tm[1:] - dm[1:]) / comb)),
+            "t_end": nst * dt,
+        }
+    small = [g for g in responses if g < 1.0]  # the linear-response part of the sweep
+    ratio = lambda v: float(max(v) / min(v)) if v and min(v) > 0 else None
+    summary = {
+        "ttcf_se_per_state_over_rate_max_over_min_linear":
+            ratio([out[str(g)]["ttcf_se_per_state_over_rate_end"] for g in small]),
+        "all_groups_healthy": all(int(responses[g][4]) == expected[g] for g in responses),
+    }
+    return {"rates": out, "summary": summary}
+
+
 def precision_statement(T, ctx, mid, sysd, s, n_states, nst, stream):
-    """FP32-force responses against FP64-force responses from the same start states, at each
-    shear rate: max over t of |difference| in units of the FP64 response's standard error, and
-    relative to the largest |TTCF|."""
+    """FP32-force responses against FP64-force responses (the paper's arithmetic) from the
+    same start states, at each shear rate: max over t of |difference| in units of the FP64
+    response's standard error, and relative to the largest |TTCF|. Both reruns step all four
+    rates' daughters in one call, timed: the throughput of each arithmetic on the same
+    workload, with the roofline fraction of the headline (96 B per atom-step)."""
+    import torch
     r, p = ctx.ttcf_export_states(mid, n_states)
     sys64 = T.make_system(s.n, s.box, s.temperature, s.dt, precision=0)
-    out = {}
+    out, rates = {}, {}
+    atom_steps = 4 * n_states * len(GAMMAS) * s.n * nst
     for prec, tag in ((1, "fp32"), (0, "fp64")):
         res = {}
         with T.Context(stream) as c2:
@@ -136,11 +262,27 @@ def precision_statement(T, ctx, mid, sysd, s, n_states, nst, stream):
             c2.ttcf_import_states(m2, r, p)
             for gd in GAMMAS:
                 c2.ttcf_spawn_daughters(m2, n_states, 0, gd, nst)
+            torch.cuda.synchronize()
+            c2.ttcf_step_timing(reset=True)
+            t0 = time.perf_counter()
             c2.ttcf_step(nst)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms, launches = c2.ttcf_step_timing(reset=True)
             c2.ttcf_accumulate()
             for gd in GAMMAS:
                 res[gd] = c2.ttcf_response(nst + 1, gd)
         out[tag] = res
+        achieved = BYTES_PER_ATOM_STEP * atom_steps / (ms / 1e3) / 1e9
+        rates[tag] = {
+            "atom_steps_per_s": atom_steps / wall,
+            "kernel_atom_steps_per_s": atom_steps / (ms / 1e3),
+            "kernel_ms": ms, "launches": int(launches),
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS},
+            "workload": f"{4 * n_states * len(GAMMAS)} daughters (all four rates) x {nst} "
+                        f"steps of N={s.n} in one step call",
+        }
     stmt = {}
     for gd in GAMMAS:
         a, b = out["fp32"][gd], out["fp64"][gd]
@@ -151,7 +293,8 @@ def precision_statement(T, ctx, mid, sysd, s, n_states, nst, stream):
             "dav_max_err_over_se": float(np.max(np.abs(a[2][k] - b[2][k]) / b[3][k])),
         }
     return {"reference": "same start states, FP64 pair forces (the FP64 form matches the "
-                         "oracle to 1e-9 over 50 steps)", "per_shear_rate": stmt}
+                         "oracle to 1e-9 over 50 steps)", "per_shear_rate": stmt,
+            "throughput": rates}
 
 
 def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per_size=128,
@@ -203,8 +346,34 @@ def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per
     ms, launches = ctx.ttcf_step_timing(reset=True)
     groups = ctx.ttcf_accumulate()
     tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, 0.0)
-    ctx.close()
     atom_steps = total_atoms * nst
+    # each size alone (the same states and rates, one step call per size)
+    per_size_rate = {}
+    for nc in sizes:
+        n = 4 * nc ** 3
+        mine = [(mid, count, g) for mid, count, nn, g in spawned if nn == n]
+        for mid, count, g in mine:
+            ctx.ttcf_spawn_daughters(mid, count, 0, g, nst)
+        ctx.ttcf_step_timing(reset=True)
+        ctx.ttcf_step(nst)
+        ms1, _ = ctx.ttcf_step_timing(reset=True)
+        ctx.ttcf_accumulate()
+        per_size_rate[str(n)] = 4 * sum(c for _, c, _ in mine) * n * nst / (ms1 / 1e3)
+    # the same batch as one captured cycle over all twelve mothers: each replay runs the
+    # mothers' kicked copies (one state each, 50 steps), spawns, steps and accumulates
+    parts = [{"mother": mid, "n_replicas": count, "states_per_replica": 1, "steps_between": 50,
+              "gamma_dot": g, "kicks": seeded_kicks(count, n, 0.05, seed + 100 + mid),
+              "decorrelate_steps": 200} for mid, count, n, g in spawned]
+    replays = 2
+    gr = ctx.ttcf_graph_create_multi(parts, nst, replays + 1)
+    gr.launch(1)  # warm
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gr.launch(replays)
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / replays
+    g_resp = ctx.ttcf_response(nst + 1, 0.0)
+    ctx.close()
     return {"workload": f"sizes {[4 * n ** 3 for n in sizes]} x densities {list(densities)}, "
                         f"{per_size} states per size x 4 mappings, {nst} steps, per-state shear "
                         f"rates log-uniform in [1e-5, 1e-1]",
@@ -213,7 +382,14 @@ def uneven_leg(T, stream, sizes=(5, 6, 8, 10), densities=(0.7, 0.8442, 0.9), per
             "end_to_end_atom_steps_per_s": atom_steps / wall, "mothers_s": mother_s,
             "autotune_s": tune_s, "tuned_shapes": shapes,
             "healthy_groups": int(groups),
-            "per_unit_rate_ttcf_end": float(tm[-1]), "per_unit_rate_ttcf_se_end": float(tse[-1])}
+            "per_unit_rate_ttcf_end": float(tm[-1]), "per_unit_rate_ttcf_se_end": float(tse[-1]),
+            "per_size_kernel_atom_steps_per_s": per_size_rate,
+            "captured": {"ms_per_cycle": 1e3 * graph_s,
+                         "daughter_atom_steps_per_s": atom_steps / graph_s,
+                         "mother_atom_steps_per_cycle": sum(c * n * 50 for _, c, n, _ in spawned),
+                         "groups_after_replays": int(g_resp[4]),
+                         "cycle": "12 mothers' kicked copies (one state each, 50 steps) -> spawn "
+                                  "-> one step per kernel form -> accumulate, one HIP graph"}}
 
 
 def thermostat_leg(T, stream, ctx, mid, s, n_states, nst, gd=1e-2):
@@ -725,58 +901,76 @@ def main():
 
     nst = args.daughter_steps
     n_d = 4 * args.states
+    # per shear rate: groups expected and healthy so far (a rate's response covers every
+    # batch run at it), and the latest response
+    expected, healthy, responses = {}, {}, {}
 
     def one_step(i):
         gd = GAMMAS[i % len(GAMMAS)]
         ctx.ttcf_spawn_daughters(mid, args.states, 0, gd, nst)
         ctx.ttcf_step(nst)
         ctx.ttcf_accumulate()
-        return ctx.ttcf_response(nst + 1, gd)
+        res = ctx.ttcf_response(nst + 1, gd)
+        new = res[4] - healthy.get(gd, 0)  # healthy groups of this batch
+        expected[gd] = expected.get(gd, 0) + args.states
+        healthy[gd] = res[4]
+        responses[gd] = res
+        return gd, new
 
     for i in range(args.warmup):
         one_step(i)
     ctx.ttcf_step_timing(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    last = None
+    healthy_timed = 0
+    last_gd = None
     for i in range(args.steps):
-        last = one_step(args.warmup + i)
+        last_gd, new = one_step(args.warmup + i)
+        healthy_timed += new
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms, launches = ctx.ttcf_step_timing(reset=True)
+    start_states = ctx.ttcf_export_states(mid, args.states) if args.cpu_budget > 0 else None
+    progress("headline")
     precision = None
     if args.precision == 1 and args.fp64_check:
         precision = precision_statement(T, ctx, mid, sysd, s, args.states, nst, stream)
+    progress("precision")
     green_kubo = None
     try:
         green_kubo = green_kubo_leg(T, ctx, mid, s, 100 * args.states, nst)
     except Exception as e:  # the headline line is printed whatever happens here
         green_kubo = {"error": repr(e)}
     thermostats = None
+    progress("green-kubo")
     if args.thermostats:
         try:
             thermostats = thermostat_leg(T, stream, ctx, mid, s, args.states, nst)
         except Exception as e:  # the headline line is printed whatever happens here
             thermostats = {"error": repr(e)}
     observables = None
+    progress("thermostats")
     if args.observables:
         try:
             observables = observables_leg(T, stream, ctx, mid, s, args.states, nst)
         except Exception as e:  # the headline line is printed whatever happens here
             observables = {"error": repr(e)}
     elongation = None
+    progress("observables")
     if args.elongation:
         try:
             elongation = elongation_leg(T, stream, ctx, mid, s, args.states, nst)
         except Exception as e:  # the headline line is printed whatever happens here
             elongation = {"error": repr(e)}
     mixed = None
+    progress("elongation")
     if args.mixed:
         try:
             mixed = mixed_leg(T, stream, ctx, mid, s, args.states, nst)
         except Exception as e:  # the headline line is printed whatever happens here
             mixed = {"error": repr(e)}
     colour = None
+    progress("mixed")
     if args.colour:
         try:
             colour = colour_leg(T, stream, ctx, mid, s, args.states, nst)
@@ -785,7 +979,8 @@ def main():
     ctx.close()
 
     atom_steps = n_d * s.n * nst
-    value = atom_steps * args.steps / wall
+    # only the daughters of healthy groups count (a group whose list overflowed stops early)
+    value = 4 * healthy_timed * s.n * nst / wall
     avg_launch_s = kern_ms / 1e3 / max(launches, 1)
     achieved = BYTES_PER_ATOM_STEP * atom_steps / avg_launch_s / 1e9
     traffic = measured_traffic()
@@ -815,7 +1010,7 @@ def main():
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_daughters (persistent daughter step kernel)",
+            "kernel": "k_daughters_pairs (persistent pair-list daughter step kernel)",
             "kernel_ms_per_launch": 1e3 * avg_launch_s,
             "algorithmic_bytes_per_launch": BYTES_PER_ATOM_STEP * atom_steps,
             "valu": measured_valu(),
@@ -824,9 +1019,10 @@ def main():
         "mother_s": mother_s,
         "mother_acf": mother_acf,
         "mother_atom_steps_per_s": mother_steps * s.n / mother_s,
-        "last_response": {"gamma_dot": GAMMAS[(args.warmup + args.steps - 1) % len(GAMMAS)],
-                          "ttcf_end": float(last[0][-1]), "ttcf_se_end": float(last[1][-1]),
-                          "dav_end": float(last[2][-1]), "dav_se_end": float(last[3][-1])},
+        "healthy_groups_timed": {"healthy": int(healthy_timed),
+                                 "expected": int(args.states * args.steps),
+                                 "all_healthy": int(healthy_timed) == args.states * args.steps},
+        "per_rate": per_rate_statement(responses, expected, nst, s.dt),
     }
     if precision is not None:
         line["precision"] = precision
@@ -842,28 +1038,38 @@ def main():
         line["elongation"] = elongation
     if mixed is not None:
         line["mixed"] = mixed
+    progress("colour")
     if args.graph:
         try:
             line["graph"] = graph_leg(T, stream)
         except Exception as e:  # the headline line is printed whatever happens here
             line["graph"] = {"error": repr(e)}
+    progress("graph")
     if args.uneven:
         try:
             line["uneven"] = uneven_leg(T, stream)
         except Exception as e:  # the headline line is printed whatever happens here
             line["uneven"] = {"error": repr(e)}
+    progress("uneven")
     if args.channel:
         try:
             line["channel"] = channel_leg(T, stream)
         except Exception as e:  # the headline line is printed whatever happens here
             line["channel"] = {"error": repr(e)}
+    progress("channel")
     if args.cv:
         try:
             line["cv"] = cv_leg(T, stream)
         except Exception as e:  # the headline line is printed whatever happens here
             line["cv"] = {"error": repr(e)}
+    progress("cv")
     if args.cpu_budget > 0:
-        line["cpu_baseline"] = cpu_baseline(args.n_cells, nst, args.cpu_budget)
+        line["cpu_baseline"] = cpu_baseline(args.n_cells, nst, args.cpu_budget, start_states)
+        try:
+            line["cpu_baseline_other_configs"] = cpu_baseline_configs()
+        except Exception as e:  # the headline line is printed whatever happens here
+            line["cpu_baseline_other_configs"] = {"error": repr(e)}
+    progress("cpu baseline")
     print(json.dumps(line), flush=True)
 
 

@@ -498,6 +498,17 @@ typedef struct ttcf_graph_desc {
  * the context's other work. Errors: TTCF_EINVAL (bad description, shape does not fit),
  * TTCF_ENOMEM, TTCF_EDEVICE (capture or instantiation failed). */
 int32_t ttcf_graph_create(ttcf_ctx* ctx, const ttcf_graph_desc* desc, ttcf_graph** out);
+/* One cycle over several mothers, for a batch of uneven N (Sec. Software methodology: Alg.
+ * SHELL SCRIPT's independent jobs, here one graph): descs[k] describes mother k's part as
+ * for ttcf_graph_create (distinct mothers; every part the same n_steps and max_replays, every
+ * mother the same force precision). A replay runs each part's mothers and spawns, then steps
+ * all daughters together in the persistent launches of their kernel form and thermostat,
+ * largest systems first, exactly as ttcf_step steps such a mix, and folds every group; groups
+ * are numbered part by part, state-major, as the same ttcf_spawn_daughters calls in part
+ * order would number them, and rows are reserved for max_replays times all saved states.
+ * Errors as ttcf_graph_create; TTCF_EINVAL for n_desc <= 0 or > 4096. */
+int32_t ttcf_graph_create_multi(ttcf_ctx* ctx, const ttcf_graph_desc* descs, int32_t n_desc,
+                                ttcf_graph** out);
 /* Replays the cycle n_replays times on the context's stream (asynchronous). TTCF_ESTATE when
  * that would exceed max_replays. */
 int32_t ttcf_graph_launch(ttcf_graph* graph, int32_t n_replays);

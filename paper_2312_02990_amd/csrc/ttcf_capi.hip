@@ -419,11 +419,32 @@ int32_t run_mother(ttcf_ctx* c, Mother& m, double temperature, int64_t n_chunks,
     return TTCF_OK;
 }
 
+// The extra-column accumulator at the current capacity and stride, if the accumulator exists
+// without it (a later growth copies it along).
+int32_t ensure_acc_x(ttcf_ctx* c) {
+    if (c->acc_xd || c->acc_cap == 0) return TTCF_OK;
+    double* xd = (double*)dev_alloc(sizeof(double) * (size_t)c->acc_cap * kObsCols * c->acc_stride,
+                                    c->stream);
+    double* xi = (double*)dev_alloc(sizeof(double) * (size_t)c->acc_cap * kObsCols * c->acc_stride,
+                                    c->stream);
+    if (!xd || !xi) {
+        dev_free(xd);
+        dev_free(xi);
+        return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
+    }
+    c->acc_xd = xd;
+    c->acc_xi = xi;
+    return TTCF_OK;
+}
+
 int32_t grow_acc(ttcf_ctx* c, int64_t rows_needed, int32_t n_t) {
     const int32_t stride = std::max(c->acc_stride, n_t);
     // groups with extra columns need their accumulator too, even where the rows would fit
-    const bool missing_x = (c->record_obs || c->own_x) && !c->acc_xd;
-    if (rows_needed <= c->acc_cap && stride == c->acc_stride && !missing_x) return TTCF_OK;
+    if ((c->record_obs || c->own_x) && !c->acc_xd) {
+        const int32_t rc = ensure_acc_x(c);
+        if (rc != TTCF_OK) return rc;
+    }
+    if (rows_needed <= c->acc_cap && stride == c->acc_stride) return TTCF_OK;
     if (!c->graphs.empty())
         return fail(c, TTCF_ESTATE, "accumulator capacity is pinned by a captured graph: destroy "
                                     "it before accumulating beyond the rows reserved for it");
@@ -958,9 +979,14 @@ int32_t spawn_impl(ttcf_ctx* c, int32_t mother, int32_t n_states, int64_t steps_
     b.series = (double*)dev_alloc(sizeof(double) * (size_t)(n_steps + 1) * nd, c->stream);
     const size_t scratch_bytes = sizeof(int32_t) * 2 * nd + sizeof(double*) * nd + 64;
     b.scratch = dev_alloc(scratch_bytes, c->stream);
-    // mixed-flow daughters always record their flux components (columns 0 and 1)
+    // mixed-flow daughters always record their flux components (columns 0 and 1); their
+    // accumulator columns exist from here on (a captured graph may pin the other arrays)
     const bool with_x = c->record_obs || field == kFieldMixed;
-    if (field == kFieldMixed) c->own_x = true;
+    if (field == kFieldMixed) {
+        c->own_x = true;
+        rc = ensure_acc_x(c);
+        if (rc != TTCF_OK) return rc;
+    }
     if (with_x)
         b.xseries = (double*)dev_alloc(sizeof(double) * (size_t)(n_steps + 1) * kObsCols * nd,
                                        c->stream);
@@ -1947,13 +1973,15 @@ int32_t ttcf_response(ttcf_ctx* c, int32_t observable, double gamma_dot_filter, 
 // ---------------------------------------------------------------------------------------
 struct ttcf_graph {
     ttcf_ctx* ctx = nullptr;
-    int32_t mother = -1;
     hipStream_t cap = nullptr;        // private stream the cycle was captured on
+    std::vector<hipStream_t> side;    // branches of the capture (the parts' mothers and spawns)
+    std::vector<hipEvent_t> events;   // fork and join points of the branches
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<void*> bufs;          // device buffers owned by the graph
-    int32_t n_states = 0, n_groups = 0, max_replays = 0, replays = 0;
-    int64_t mother_steps_per_replay = 0;  // steps the context's own mother advances per replay
+    int32_t n_states = 0, max_replays = 0, replays = 0;
+    // (mother, steps the context's own mother advances per replay) of every part
+    std::vector<std::pair<int32_t, int64_t>> mother_steps;
     void* get(size_t bytes) {
         void* p = dev_alloc(bytes + 64, ctx->stream);
         if (p) bufs.push_back(p);
@@ -1969,183 +1997,279 @@ void free_graph(ttcf_graph* g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->cap) (void)hipStreamDestroy(g->cap);
+    for (hipStream_t s : g->side) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : g->events) (void)hipEventDestroy(e);
     for (void* p : g->bufs) dev_free(p);
     delete g;
 }
 
-}  // namespace
+// One mother's share of a captured cycle.
+struct GraphPart {
+    const ttcf_graph_desc* gd = nullptr;
+    int32_t n = 0;                      // atoms
+    size_t sz = 0;                      // doubles per state
+    int32_t n_states = 0, nm = 0, nd = 0, n_copies = 0;
+    std::vector<int32_t> maps;
+    int32_t st0 = 0, d0 = 0;            // its first state (group) and daughter in the cycle
+    size_t dstate0 = 0;                 // its daughters' first double in the state buffer
+    double* states = nullptr;           // saved start states
+    double* szeta = nullptr;            // their thermostat variables
+    MotherLaunch* d_ml = nullptr;
+    std::vector<MotherLaunch> ml;
+    bool nh = false;
+    StepShape shape;
+};
 
-int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** out) {
-    if (!c || !gd || !out) return TTCF_EINVAL;
-    if (gd->mother < 0 || gd->mother >= (int32_t)c->mothers.size() || gd->n_replicas < 0 ||
-        gd->states_per_replica <= 0 || gd->steps_between <= 0 || gd->decorrelate_steps < 0 ||
-        (gd->mapping_mask & 0xFu) == 0 || (gd->mapping_mask & ~0xFu) != 0 || !gd->gamma_dot ||
-        gd->n_steps <= 0 || gd->max_replays <= 0)
-        return fail(c, TTCF_EINVAL, "bad graph description");
+// Records one cycle over the mothers of `gds` (every part as ttcf_graph_create describes):
+// each part's mothers save their states and their daughters are spawned, then all daughters
+// run in the persistent step launches of their (form, thermostat), largest systems first, as
+// ttcf_step would run them, and every group is folded into the reserved rows.
+int32_t graph_create_impl(ttcf_ctx* c, const ttcf_graph_desc* gds, int32_t n_desc,
+                          ttcf_graph** out) {
+    if (!c || !gds || n_desc <= 0 || !out) return TTCF_EINVAL;
     if (c->record_obs)
         return fail(c, TTCF_ESTATE, "captured cycles record P_xy only: switch the extra "
                                     "observables off first");
-    const int64_t ns64 = (int64_t)std::max(1, gd->n_replicas) * gd->states_per_replica;
-    if (ns64 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many start states per replay");
-    const int32_t n_states = (int32_t)ns64;
-    if (!(gd->n_gamma == 1 || gd->n_gamma == n_states))
-        return fail(c, TTCF_EINVAL, "n_gamma must be 1 or the number of saved states");
-    for (int32_t q = 0; q < gd->n_gamma; ++q)
-        if (!std::isfinite(gd->gamma_dot[q])) return fail(c, TTCF_EINVAL, "shear rates must be finite");
-    Mother& m = c->mothers[gd->mother];
-    const int n = m.dev.n;
-    const size_t sz = 6 * (size_t)n;
-    std::vector<int32_t> maps;
-    for (int q = 0; q < 4; ++q)
-        if (gd->mapping_mask & (1u << q)) maps.push_back(q);
-    const int32_t nm = (int32_t)maps.size();
-    const int32_t nd = n_states * nm;
-    const int32_t n_t = gd->n_steps + 1;
-    const int64_t reserve = (int64_t)gd->max_replays * n_states;
+    std::vector<GraphPart> parts(n_desc);
+    int64_t states64 = 0;
+    int32_t nd = 0;
+    int precision = -1;
+    size_t dstate_total = 0;
+    const int32_t n_steps = gds[0].n_steps;
+    const int32_t max_replays = gds[0].max_replays;
+    for (int32_t k = 0; k < n_desc; ++k) {
+        const ttcf_graph_desc* gd = &gds[k];
+        if (gd->mother < 0 || gd->mother >= (int32_t)c->mothers.size() || gd->n_replicas < 0 ||
+            gd->states_per_replica <= 0 || gd->steps_between <= 0 || gd->decorrelate_steps < 0 ||
+            (gd->mapping_mask & 0xFu) == 0 || (gd->mapping_mask & ~0xFu) != 0 || !gd->gamma_dot ||
+            gd->n_steps <= 0 || gd->max_replays <= 0)
+            return fail(c, TTCF_EINVAL, "bad graph description");
+        if (gd->n_steps != n_steps || gd->max_replays != max_replays)
+            return fail(c, TTCF_EINVAL, "the parts of a cycle share n_steps and max_replays");
+        for (int32_t j = 0; j < k; ++j)
+            if (gds[j].mother == gd->mother)
+                return fail(c, TTCF_EINVAL, "a mother appears in two parts of a cycle");
+        const Mother& m = c->mothers[gd->mother];
+        if (precision < 0)
+            precision = m.sys.precision;
+        else if (precision != m.sys.precision)
+            return fail(c, TTCF_EINVAL, "the mothers of a cycle mix force precisions");
+        GraphPart& P = parts[k];
+        P.gd = gd;
+        P.n = m.dev.n;
+        P.sz = 6 * (size_t)P.n;
+        P.n_copies = std::max(1, gd->n_replicas);
+        const int64_t ns64 = (int64_t)P.n_copies * gd->states_per_replica;
+        if (ns64 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many start states per replay");
+        P.n_states = (int32_t)ns64;
+        if (!(gd->n_gamma == 1 || gd->n_gamma == P.n_states))
+            return fail(c, TTCF_EINVAL, "n_gamma must be 1 or the number of saved states");
+        for (int32_t q = 0; q < gd->n_gamma; ++q)
+            if (!std::isfinite(gd->gamma_dot[q]))
+                return fail(c, TTCF_EINVAL, "shear rates must be finite");
+        for (int q = 0; q < 4; ++q)
+            if (gd->mapping_mask & (1u << q)) P.maps.push_back(q);
+        P.nm = (int32_t)P.maps.size();
+        P.nd = P.n_states * P.nm;
+        P.st0 = (int32_t)states64;
+        P.d0 = nd;
+        P.dstate0 = dstate_total;
+        P.nh = m.sys.daughter_thermostat == TTCF_DAUGHTER_NH;
+        states64 += P.n_states;
+        if (states64 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many start states per replay");
+        nd += P.nd;
+        dstate_total += P.sz * P.nd;
+    }
+    const int32_t n_states = (int32_t)states64;
+    const int32_t n_t = n_steps + 1;
+    const int64_t reserve = (int64_t)max_replays * n_states;
     // accumulator rows: grow (while nothing pins it) to hold the reserved rows and headroom
     int32_t rc = grow_acc(c, c->acc_rows + reserve + 4096, n_t);
     if (rc != TTCF_OK) return rc;
 
     ttcf_graph* g = new ttcf_graph();
     g->ctx = c;
-    g->mother = gd->mother;
     g->n_states = n_states;
-    g->n_groups = n_states;
-    g->max_replays = gd->max_replays;
+    g->max_replays = max_replays;
     auto bail = [&](int32_t code, const std::string& msg) {
         (void)hipStreamSynchronize(c->stream);
         free_graph(g);
         return fail(c, code, msg);
     };
-    double* states = (double*)g->get(sizeof(double) * sz * n_states);
-    double* dstates = (double*)g->get(sizeof(double) * sz * nd);
+    double* dstates = (double*)g->get(sizeof(double) * dstate_total);
     double* series = (double*)g->get(sizeof(double) * (size_t)n_t * nd);
     DaughterDesc* descs = (DaughterDesc*)g->get(sizeof(DaughterDesc) * nd);
     DaughterDesc* templ = (DaughterDesc*)g->get(sizeof(DaughterDesc) * nd);
     int32_t* ints = (int32_t*)g->get(sizeof(int32_t) * ((size_t)3 * nd + n_states + 8));
     double** dst = (double**)g->get(sizeof(double*) * nd);
-    const int32_t n_copies = std::max(1, gd->n_replicas);
-    MotherLaunch* d_ml = (MotherLaunch*)g->get(sizeof(MotherLaunch) * n_copies);
-    double* szeta = (double*)g->get(sizeof(double) * n_states);  // thermostat of each state
-    if (!states || !dstates || !series || !descs || !templ || !ints || !dst || !d_ml || !szeta)
+    if (!dstates || !series || !descs || !templ || !ints || !dst)
         return bail(TTCF_ENOMEM, "graph allocation failed");
     int32_t* order = ints;
-    int32_t* state_of = order + nd;
+    int32_t* state_of = order + nd;         // the part's own state index
     int32_t* map_of = state_of + nd;
     int32_t* first_of = map_of + nd;        // n_states + 1
     int32_t* queue = first_of + n_states + 1;
     int32_t* replay = queue + 4;
 
-    // mothers of the cycle: the context's mother itself, or persistent copies of it
-    std::vector<MotherLaunch> ml(n_copies);
-    const double nf = 3.0 * n - 3.0;
-    double* rep = nullptr;
-    if (gd->n_replicas > 0) {
-        rep = (double*)g->get(sizeof(double) * (sz * n_copies + n_copies));
-        double* kick_d = gd->kicks ? (double*)g->get(sizeof(double) * 3 * (size_t)n * n_copies)
-                                   : nullptr;
-        if (!rep || (gd->kicks && !kick_d)) return bail(TTCF_ENOMEM, "graph allocation failed");
-        if (gd->kicks && hipMemcpyAsync(kick_d, gd->kicks, sizeof(double) * 3 * (size_t)n * n_copies,
-                                        hipMemcpyHostToDevice, c->stream) != hipSuccess)
-            return bail(TTCF_EDEVICE, "kick upload failed");
-        if (launch_replicate(m.state, m.zeta, n, kick_d, n_copies, rep, rep + sz * n_copies,
-                             c->stream) != hipSuccess)
-            return bail(TTCF_EDEVICE, "replica launch failed");
-    }
-    for (int r = 0; r < n_copies; ++r) {
-        MotherLaunch& L = ml[r];
-        L.sys = m.dev;
-        L.state = rep ? rep + sz * r : m.state;
-        L.zeta = rep ? rep + sz * n_copies + r : m.zeta;
-        L.temperature = m.sys.temperature;
-        L.nf = nf;
-        L.q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
-        L.threads = m.threads;
-        L.apt = m.apt;
-        L.precision = m.sys.precision;
-        L.lds_bytes = lds_for(m.dev, m.sys.precision);
-        L.series = nullptr;
-    }
-    if (rep && gd->decorrelate_steps > 0) {
-        // once, outside the graph, through the context's own launch block
-        for (auto& L : ml) {
-            L.n_chunks = 0;
-            L.steps_per_chunk = gd->decorrelate_steps;
-            L.snapshots = nullptr;
+    // mothers of the cycle: each part's mother itself, or persistent copies of it
+    for (GraphPart& P : parts) {
+        const ttcf_graph_desc* gd = P.gd;
+        Mother& m = c->mothers[gd->mother];
+        const int n = P.n;
+        P.states = (double*)g->get(sizeof(double) * P.sz * P.n_states);
+        P.szeta = (double*)g->get(sizeof(double) * P.n_states);
+        P.d_ml = (MotherLaunch*)g->get(sizeof(MotherLaunch) * P.n_copies);
+        if (!P.states || !P.szeta || !P.d_ml) return bail(TTCF_ENOMEM, "graph allocation failed");
+        P.ml.assign(P.n_copies, MotherLaunch{});
+        const double nf = 3.0 * n - 3.0;
+        double* rep = nullptr;
+        if (gd->n_replicas > 0) {
+            rep = (double*)g->get(sizeof(double) * (P.sz * P.n_copies + P.n_copies));
+            double* kick_d = gd->kicks
+                                 ? (double*)g->get(sizeof(double) * 3 * (size_t)n * P.n_copies)
+                                 : nullptr;
+            if (!rep || (gd->kicks && !kick_d)) return bail(TTCF_ENOMEM, "graph allocation failed");
+            if (gd->kicks &&
+                hipMemcpyAsync(kick_d, gd->kicks, sizeof(double) * 3 * (size_t)n * P.n_copies,
+                               hipMemcpyHostToDevice, c->stream) != hipSuccess)
+                return bail(TTCF_EDEVICE, "kick upload failed");
+            if (launch_replicate(m.state, m.zeta, n, kick_d, P.n_copies, rep,
+                                 rep + P.sz * P.n_copies, c->stream) != hipSuccess)
+                return bail(TTCF_EDEVICE, "replica launch failed");
         }
-        rc = upload_mother_launches(c, ml.data(), n_copies);
-        if (rc != TTCF_OK) return bail(rc, c->err);
-        if (launch_mothers(c->d_mlaunch, n_copies, ml[0], c->stream) != hipSuccess)
-            return bail(TTCF_EDEVICE, "decorrelation launch failed");
+        for (int r = 0; r < P.n_copies; ++r) {
+            MotherLaunch& L = P.ml[r];
+            L.sys = m.dev;
+            L.state = rep ? rep + P.sz * r : m.state;
+            L.zeta = rep ? rep + P.sz * P.n_copies + r : m.zeta;
+            L.temperature = m.sys.temperature;
+            L.nf = nf;
+            L.q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
+            L.threads = m.threads;
+            L.apt = m.apt;
+            L.precision = m.sys.precision;
+            L.lds_bytes = lds_for(m.dev, m.sys.precision);
+            L.series = nullptr;
+        }
+        if (rep && gd->decorrelate_steps > 0) {
+            // once, outside the graph, through the context's own launch block
+            for (auto& L : P.ml) {
+                L.n_chunks = 0;
+                L.steps_per_chunk = gd->decorrelate_steps;
+                L.snapshots = nullptr;
+            }
+            rc = upload_mother_launches(c, P.ml.data(), P.n_copies);
+            if (rc != TTCF_OK) return bail(rc, c->err);
+            if (launch_mothers(c->d_mlaunch, P.n_copies, P.ml[0], c->stream) != hipSuccess)
+                return bail(TTCF_EDEVICE, "decorrelation launch failed");
+        }
+        for (int r = 0; r < P.n_copies; ++r) {
+            P.ml[r].n_chunks = gd->states_per_replica;
+            P.ml[r].steps_per_chunk = gd->steps_between;
+            P.ml[r].snapshots = P.states + P.sz * (size_t)r * gd->states_per_replica;
+            P.ml[r].snap_zeta = P.szeta + (size_t)r * gd->states_per_replica;
+        }
+        g->mother_steps.emplace_back(
+            gd->mother, rep ? 0 : (int64_t)gd->states_per_replica * gd->steps_between);
     }
-    for (int r = 0; r < n_copies; ++r) {
-        ml[r].n_chunks = gd->states_per_replica;
-        ml[r].steps_per_chunk = gd->steps_between;
-        ml[r].snapshots = states + sz * (size_t)r * gd->states_per_replica;
-        ml[r].snap_zeta = szeta + (size_t)r * gd->states_per_replica;
-    }
-    g->mother_steps_per_replay = rep ? 0 : (int64_t)gd->states_per_replica * gd->steps_between;
 
-    // daughter descriptors (state-major groups, as ttcf_spawn_daughters) and their shape
-    const int precision = m.sys.precision;
-    const StepShape shape = resolve_shape(c, m.dev, precision, nullptr);
+    // daughter descriptors (state-major groups per part, parts in order, as the same
+    // ttcf_spawn_daughters calls would number them), their shapes and their step launches
     std::vector<DaughterDesc> hd(nd);
     std::vector<double*> hdst(nd);
     std::vector<int32_t> hints(3 * (size_t)nd + n_states + 1);
-    bool nl = false;
-    const bool nh = m.sys.daughter_thermostat == TTCF_DAUGHTER_NH;
-    for (int32_t st = 0; st < n_states; ++st) {
-        const int32_t group = c->next_group++;
-        const double gdot = gd->gamma_dot[gd->n_gamma == 1 ? 0 : st];
-        for (int32_t q = 0; q < nm; ++q) {
-            const int32_t d = st * nm + q;
-            DaughterDesc& ds = hd[d];
-            ds = DaughterDesc{};
-            ds.state = dstates + sz * d;
-            ds.series = series + (size_t)n_t * d;
-            ds.sys = m.dev;
-            ds.gamma_dot = gdot;
-            ds.n_steps = gd->n_steps;
-            ds.group = group;
-            ds.map = maps[q];
-            ds.block = m.threads;
-            if (nh) {  // zeta itself is written by a kernel at every replay
-                ds.thermo = 1;
-                ds.nh_q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
-                ds.nh_target = nf * m.sys.temperature;
+    std::vector<char> nl_of(nd, 0);
+    bool block_explicit = false;
+    for (GraphPart& P : parts) {
+        const ttcf_graph_desc* gd = P.gd;
+        const Mother& m = c->mothers[gd->mother];
+        block_explicit = block_explicit || m.sys.block_threads > 0;
+        P.shape = resolve_shape(c, m.dev, precision, nullptr);
+        const double nf = 3.0 * P.n - 3.0;
+        for (int32_t st = 0; st < P.n_states; ++st) {
+            const int32_t group = c->next_group++;
+            const double gdot = gd->gamma_dot[gd->n_gamma == 1 ? 0 : st];
+            for (int32_t q = 0; q < P.nm; ++q) {
+                const int32_t d = P.d0 + st * P.nm + q;
+                DaughterDesc& ds = hd[d];
+                ds = DaughterDesc{};
+                ds.state = dstates + P.dstate0 + P.sz * (size_t)(st * P.nm + q);
+                ds.series = series + (size_t)n_t * d;
+                ds.sys = m.dev;
+                ds.gamma_dot = gdot;
+                ds.n_steps = n_steps;
+                ds.group = group;
+                ds.map = P.maps[q];
+                ds.block = m.threads;
+                if (P.nh) {  // zeta itself is written by a kernel at every replay
+                    ds.thermo = 1;
+                    ds.nh_q = nf * m.sys.temperature * m.sys.nh_tau * m.sys.nh_tau;
+                    ds.nh_target = nf * m.sys.temperature;
+                }
+                bool nl = false;
+                rc = apply_shape(c, P.shape, precision, &ds, &nl);
+                if (rc != TTCF_OK) return bail(rc, c->err);
+                nl_of[d] = nl ? 1 : 0;
+                hdst[d] = ds.state;
+                hints[nd + d] = st;                   // state_of (the part's own index)
+                hints[2 * (size_t)nd + d] = P.maps[q];  // map_of
             }
-            rc = apply_shape(c, shape, precision, &ds, &nl);
-            if (rc != TTCF_OK) return bail(rc, c->err);
-            hdst[d] = ds.state;
-            hints[d] = d;                    // order: one system size, any order
-            hints[nd + d] = st;              // state_of
-            hints[2 * (size_t)nd + d] = maps[q];  // map_of
+            hints[3 * (size_t)nd + P.st0 + st] = P.d0 + st * P.nm;  // first_of
         }
-        hints[3 * (size_t)nd + st] = st * nm;    // first_of
     }
     hints[3 * (size_t)nd + n_states] = nd;
-    std::vector<const DaughterDesc*> hp;
-    for (auto& d : hd) hp.push_back(&d);
-    BatchLaunch B{};
-    rc = plan_group(c, hp, m.sys.block_threads > 0, nl ? kVariantNeighbourList : kVariantCells,
-                    precision, gd->n_steps, shape.threads, &B);
-    if (rc != TTCF_OK) return bail(rc, c->err);
-    if (nl && !B.pairs_lds) {
-        // the graph owns the pair-list scratch its replays use
-        B.pairs = (uint32_t*)g->get(sizeof(uint32_t) * (size_t)B.grid * (size_t)B.pair_stride);
-        if (!B.pairs) return bail(TTCF_ENOMEM, "pair-list scratch allocation failed");
+    // launch groups as in ttcf_step: (form, thermostat), form 0 pair lists at four atoms per
+    // thread, 1 cells, 2 pair lists at eight; largest systems first inside each
+    std::vector<int32_t> groups[6];
+    for (int32_t d = 0; d < nd; ++d) {
+        const int form = !nl_of[d] ? 1 : (pair_job_apt(hd[d].sys.n) == 4 ? 0 : 2);
+        groups[2 * form + (hd[d].thermo ? 1 : 0)].push_back(d);
     }
-    B.descs = descs;
-    B.order = order;
-    B.queue = queue;
+    std::vector<BatchLaunch> launches;
+    size_t offset = 0;
+    for (int gi = 0; gi < 6; ++gi) {
+        std::vector<int32_t>& grp = groups[gi];
+        if (grp.empty()) continue;
+        std::stable_sort(grp.begin(), grp.end(),
+                         [&](int32_t a, int32_t b) { return hd[a].sys.n > hd[b].sys.n; });
+        std::vector<const DaughterDesc*> hp;
+        for (int32_t d : grp) {
+            hp.push_back(&hd[d]);
+            hints[offset + hp.size() - 1] = d;   // order
+        }
+        const int form = gi / 2;
+        const StepShape& sh = parts[0].shape;
+        int threads_req = sh.threads;
+        for (const GraphPart& P : parts)
+            if (grp[0] >= P.d0 && grp[0] < P.d0 + P.nd) threads_req = P.shape.threads;
+        BatchLaunch B{};
+        rc = plan_group(c, hp, block_explicit, form == 1 ? kVariantCells : kVariantNeighbourList,
+                        precision, n_steps, threads_req, &B);
+        if (rc != TTCF_OK) return bail(rc, c->err);
+        if (form != 1 && !B.pairs_lds) {
+            // the graph owns the pair-list scratch its replays use
+            B.pairs = (uint32_t*)g->get(sizeof(uint32_t) * (size_t)B.grid * (size_t)B.pair_stride);
+            if (!B.pairs) return bail(TTCF_ENOMEM, "pair-list scratch allocation failed");
+        }
+        B.descs = descs;
+        B.order = order + offset;
+        B.queue = queue;
+        launches.push_back(B);
+        offset += grp.size();
+    }
 
     // reserved rows: metadata on the host and the device; pending until a replay writes them
     const int64_t row0 = c->acc_rows;
     for (int64_t r = 0; r < reserve; ++r) {
-        const DaughterDesc& d0 = hd[(size_t)(r % n_states) * nm];
+        const int32_t st = (int32_t)(r % n_states);
+        const GraphPart* P = &parts[0];
+        for (const GraphPart& Q : parts)
+            if (st >= Q.st0 && st < Q.st0 + Q.n_states) P = &Q;
+        const DaughterDesc& d0 = hd[P->d0 + (size_t)(st - P->st0) * P->nm];
+        const Mother& m = c->mothers[P->gd->mother];
         c->row_gamma.push_back(d0.gamma_dot);
         c->row_dt.push_back(d0.sys.dt);
-        c->row_maps.push_back(nm);
+        c->row_maps.push_back(P->nm);
         c->row_coef.push_back(d0.sys.volume * d0.gamma_dot / m.sys.temperature);
         c->row_nt.push_back(n_t);
         c->row_health.push_back(kRowPending);
@@ -2154,25 +2278,7 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
         c->row_field.push_back(kFieldShear);
     }
     c->acc_rows += reserve;
-    const int32_t zero = 0;
-    if (hipMemcpyAsync(templ, hd.data(), sizeof(DaughterDesc) * nd, hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess ||
-        hipMemcpyAsync(dst, hdst.data(), sizeof(double*) * nd, hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess ||
-        hipMemcpyAsync(ints, hints.data(), sizeof(int32_t) * hints.size(), hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess ||
-        hipMemcpyAsync(replay, &zero, sizeof(int32_t), hipMemcpyHostToDevice, c->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(d_ml, ml.data(), sizeof(MotherLaunch) * n_copies, hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->d_row_gamma, c->row_gamma.data(), sizeof(double) * c->row_gamma.size(),
-                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->d_row_coef, c->row_coef.data(), sizeof(double) * c->row_coef.size(),
-                       hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemcpyAsync(c->d_row_health + row0, c->row_health.data() + row0,
-                       sizeof(int32_t) * (size_t)reserve, hipMemcpyHostToDevice, c->stream) !=
-            hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
+    auto undo_rows = [&]() {
         c->acc_rows = row0;
         c->row_gamma.resize(row0);
         c->row_dt.resize(row0);
@@ -2181,6 +2287,32 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
         c->row_nt.resize(row0);
         c->row_health.resize(row0);
         c->row_cv.resize(row0);
+        c->row_x.resize(row0);
+        c->row_field.resize(row0);
+    };
+    const int32_t zero = 0;
+    bool ok = hipMemcpyAsync(templ, hd.data(), sizeof(DaughterDesc) * nd, hipMemcpyHostToDevice,
+                             c->stream) == hipSuccess &&
+              hipMemcpyAsync(dst, hdst.data(), sizeof(double*) * nd, hipMemcpyHostToDevice,
+                             c->stream) == hipSuccess &&
+              hipMemcpyAsync(ints, hints.data(), sizeof(int32_t) * hints.size(),
+                             hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+              hipMemcpyAsync(replay, &zero, sizeof(int32_t), hipMemcpyHostToDevice, c->stream) ==
+                  hipSuccess;
+    for (GraphPart& P : parts)
+        ok = ok && hipMemcpyAsync(P.d_ml, P.ml.data(), sizeof(MotherLaunch) * P.n_copies,
+                                  hipMemcpyHostToDevice, c->stream) == hipSuccess;
+    ok = ok &&
+         hipMemcpyAsync(c->d_row_gamma, c->row_gamma.data(), sizeof(double) * c->row_gamma.size(),
+                        hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+         hipMemcpyAsync(c->d_row_coef, c->row_coef.data(), sizeof(double) * c->row_coef.size(),
+                        hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+         hipMemcpyAsync(c->d_row_health + row0, c->row_health.data() + row0,
+                        sizeof(int32_t) * (size_t)reserve, hipMemcpyHostToDevice, c->stream) ==
+             hipSuccess &&
+         hipStreamSynchronize(c->stream) == hipSuccess;
+    if (!ok) {
+        undo_rows();
         return bail(TTCF_EDEVICE, "graph upload failed");
     }
     AccumLaunch A{};
@@ -2196,32 +2328,53 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     A.row_stride = c->acc_stride;
     A.row_step = replay;
 
-    // the cycle: mothers -> spawn -> descriptor reset -> step -> accumulate -> next row block
-    auto undo_rows = [&]() {
-        c->acc_rows = row0;
-        c->row_gamma.resize(row0);
-        c->row_dt.resize(row0);
-        c->row_maps.resize(row0);
-        c->row_coef.resize(row0);
-        c->row_nt.resize(row0);
-        c->row_health.resize(row0);
-        c->row_cv.resize(row0);
-    };
-    if (hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) != hipSuccess) {
+    // the cycle: mothers -> spawn -> descriptor reset -> step -> accumulate -> next row block.
+    // With several parts, each part's mothers and spawn form a branch of the graph (up to
+    // kBranches branches, parts dealt round robin), so small mother launches run side by side.
+    constexpr int kBranches = 8;
+    const int n_branch = n_desc > 1 ? std::min<int>(n_desc, kBranches) : 0;
+    bool made = hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking) == hipSuccess;
+    for (int b = 0; made && b < n_branch; ++b) {
+        hipStream_t st = nullptr;
+        made = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (made) g->side.push_back(st);
+    }
+    for (int b = 0; made && b < (n_branch ? n_branch + 1 : 0); ++b) {
+        hipEvent_t ev = nullptr;
+        made = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        if (made) g->events.push_back(ev);
+    }
+    if (!made) {
         undo_rows();
         return bail(TTCF_EDEVICE, "stream creation failed");
     }
     hipError_t e = hipStreamBeginCapture(g->cap, hipStreamCaptureModeRelaxed);
     if (e == hipSuccess) {
-        hipError_t e1 = launch_mothers(d_ml, n_copies, ml[0], g->cap);
-        if (e1 == hipSuccess)
-            e1 = launch_spawn(states, n, n_states, state_of, map_of, dst, nd, m.dev.box[0], g->cap);
+        hipError_t e1 = hipSuccess;
+        if (n_branch > 0) e1 = hipEventRecord(g->events[0], g->cap);
+        for (int b = 0; b < n_branch && e1 == hipSuccess; ++b)
+            e1 = hipStreamWaitEvent(g->side[b], g->events[0], 0);
+        for (int32_t k = 0; k < n_desc && e1 == hipSuccess; ++k) {
+            GraphPart& P = parts[k];
+            hipStream_t st = n_branch ? g->side[k % n_branch] : g->cap;
+            e1 = launch_mothers(P.d_ml, P.n_copies, P.ml[0], st);
+            if (e1 == hipSuccess)
+                e1 = launch_spawn(P.states, P.n, P.n_states, state_of + P.d0, map_of + P.d0,
+                                  dst + P.d0, P.nd, c->mothers[P.gd->mother].dev.box[0], st);
+        }
+        for (int b = 0; b < n_branch && e1 == hipSuccess; ++b) {
+            e1 = hipEventRecord(g->events[1 + b], g->side[b]);
+            if (e1 == hipSuccess) e1 = hipStreamWaitEvent(g->cap, g->events[1 + b], 0);
+        }
         if (e1 == hipSuccess)
             e1 = launch_copy_words((const uint64_t*)templ, (uint64_t*)descs,
                                    (int64_t)(sizeof(DaughterDesc) / 8) * nd, g->cap);
-        if (e1 == hipSuccess && nh)
-            e1 = launch_desc_zeta(descs, szeta, state_of, map_of, nd, g->cap);
-        if (e1 == hipSuccess) e1 = launch_daughters(B, g->cap);
+        for (GraphPart& P : parts)
+            if (e1 == hipSuccess && P.nh)
+                e1 = launch_desc_zeta(descs + P.d0, P.szeta, state_of + P.d0, map_of + P.d0, P.nd,
+                                      g->cap);
+        for (const BatchLaunch& B : launches)
+            if (e1 == hipSuccess) e1 = launch_daughters(B, g->cap);
         if (e1 == hipSuccess) e1 = launch_accumulate(A, g->cap);
         if (e1 == hipSuccess) e1 = launch_increment(replay, g->cap);
         e = hipStreamEndCapture(g->cap, &g->graph);
@@ -2238,6 +2391,18 @@ int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** o
     return TTCF_OK;
 }
 
+}  // namespace
+
+int32_t ttcf_graph_create(ttcf_ctx* c, const ttcf_graph_desc* gd, ttcf_graph** out) {
+    return graph_create_impl(c, gd, 1, out);
+}
+
+int32_t ttcf_graph_create_multi(ttcf_ctx* c, const ttcf_graph_desc* gds, int32_t n_desc,
+                                ttcf_graph** out) {
+    if (n_desc <= 0 || n_desc > 4096) return TTCF_EINVAL;
+    return graph_create_impl(c, gds, n_desc, out);
+}
+
 int32_t ttcf_graph_launch(ttcf_graph* g, int32_t n_replays) {
     if (!g || n_replays < 0) return TTCF_EINVAL;
     ttcf_ctx* c = g->ctx;
@@ -2246,7 +2411,7 @@ int32_t ttcf_graph_launch(ttcf_graph* g, int32_t n_replays) {
     for (int32_t r = 0; r < n_replays; ++r) {
         HIPCHECK(c, hipGraphLaunch(g->exec, c->stream));
         ++g->replays;
-        c->mothers[g->mother].steps += g->mother_steps_per_replay;
+        for (const auto& ms : g->mother_steps) c->mothers[ms.first].steps += ms.second;
         c->graph_rows_dirty = true;
     }
     return TTCF_OK;
@@ -2347,19 +2512,10 @@ int32_t ttcf_record_observables(ttcf_ctx* c, int32_t on) {
     if (!c || (on != 0 && on != 1)) return TTCF_EINVAL;
     if (on && !c->graphs.empty())
         return fail(c, TTCF_ESTATE, "captured graphs exist; they record P_xy only");
-    if (on && !c->acc_xd && c->acc_cap > 0) {
+    if (on) {
         // the accumulator exists without the extra columns: give it them now
-        double* xd = (double*)dev_alloc(sizeof(double) * (size_t)c->acc_cap * kObsCols *
-                                            c->acc_stride, c->stream);
-        double* xi = (double*)dev_alloc(sizeof(double) * (size_t)c->acc_cap * kObsCols *
-                                            c->acc_stride, c->stream);
-        if (!xd || !xi) {
-            dev_free(xd);
-            dev_free(xi);
-            return fail(c, TTCF_ENOMEM, "accumulator allocation failed");
-        }
-        c->acc_xd = xd;
-        c->acc_xi = xi;
+        const int32_t rc = ensure_acc_x(c);
+        if (rc != TTCF_OK) return rc;
     }
     c->record_obs = on != 0;
     return TTCF_OK;

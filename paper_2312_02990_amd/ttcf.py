@@ -208,6 +208,7 @@ def lib():
                                           C.c_int64],
         "ttcf_graph_create": [V, C.POINTER(GraphDesc), P],
         "ttcf_graph_launch": [V, C.c_int32],
+        "ttcf_graph_create_multi": [V, C.POINTER(GraphDesc), C.c_int32, P],
         "ttcf_graph_replays": [V, I],
         "ttcf_autotune": [V, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.POINTER(Shape)],
         "ttcf_autotune_export": [V, C.c_char_p, C.c_int64, L64],
@@ -256,6 +257,7 @@ EXPORTED = ["ttcf_set_allocator", "ttcf_init_mother", "ttcf_spawn_daughters", "t
             "ttcf_channel_debug_forces", "ttcf_channel_step_timing", "ttcf_autotune",
             "ttcf_autotune_export", "ttcf_autotune_import", "ttcf_graph_create",
             "ttcf_graph_launch", "ttcf_graph_replays", "ttcf_graph_destroy",
+            "ttcf_graph_create_multi",
             "ttcf_import_states_zeta", "ttcf_export_states_zeta", "ttcf_acf", "ttcf_mother_acf",
             "ttcf_response_modified", "ttcf_observable_response_modified",
             "ttcf_record_observables", "ttcf_export_observables", "ttcf_spawn_colour",
@@ -694,6 +696,28 @@ class Context:
         h = C.c_void_p(None)
         _check(lib().ttcf_graph_create(self._ctx, C.byref(d), C.byref(h)), "ttcf_graph_create",
                self._ctx)
+        gr = Graph(self, h)
+        self._graphs.append(gr)
+        return gr
+
+    def ttcf_graph_create_multi(self, parts, n_steps: int, max_replays: int):
+        """Records one batch cycle over several mothers as one HIP graph (see include/ttcf.h).
+        parts: dicts with keys mother, states_per_replica, steps_between, gamma_dot and
+        optionally n_replicas, kicks, decorrelate_steps, mapping_mask."""
+        keep = []
+        arr = (GraphDesc * len(parts))()
+        for k, p in enumerate(parts):
+            g = _f64(np.atleast_1d(p["gamma_dot"]))
+            kk = p.get("kicks")
+            kk = None if kk is None else _f64(kk).ravel()
+            keep += [g, kk]
+            arr[k] = GraphDesc(int(p["mother"]), int(p.get("n_replicas", 0)), _dp(kk),
+                               int(p.get("decorrelate_steps", 0)), int(p["states_per_replica"]),
+                               int(p["steps_between"]), int(p.get("mapping_mask", 0xF)), _dp(g),
+                               int(g.size), int(n_steps), int(max_replays))
+        h = C.c_void_p(None)
+        _check(lib().ttcf_graph_create_multi(self._ctx, arr, len(parts), C.byref(h)),
+               "ttcf_graph_create_multi", self._ctx)
         gr = Graph(self, h)
         self._graphs.append(gr)
         return gr

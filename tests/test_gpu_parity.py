@@ -706,6 +706,54 @@ def test_graph_replays_equal_eager_cycles(T, precision, thermostat):
         assert ctx.ttcf_response(nst + 1, 0.0)[4] == (reps + 1) * ns
 
 
+@pytest.mark.parametrize("precision,thermostat", [(0, 0), (1, 0), (1, 1)])
+def test_graph_of_uneven_mothers_equals_eager_cycles(T, precision, thermostat):
+    """One captured cycle over two mothers of different N (256 and 500), each saving 3 states
+    30 steps apart at per-state rates, 25-step daughters stepped together: after each replay
+    the response over all groups and both mothers equal those of the eager cycles (each
+    mother's spawn in order, one step call, one accumulation) bit for bit."""
+    systems = [I.System(4), I.System(5)]
+    starts = [I.initial_state(sy, 71 + k) for k, sy in enumerate(systems)]
+    ns, sb, nst, reps = 3, 30, 25, 3
+    gams = [I.log_uniform_rates(ns, 1e-3, 1e-1, 72 + k) for k in range(2)]
+    say("uneven graph vs eager, precision", precision, "thermostat", thermostat)
+
+    def mothers(ctx):
+        return [ctx.ttcf_init_mother(T.make_system(sy.n, sy.box, sy.temperature, sy.dt,
+                                                   precision=precision, thermostat=thermostat),
+                                     r0, p0, n_equil=100)
+                for sy, (r0, p0) in zip(systems, starts)]
+
+    eager = []
+    with T.Context() as ctx:
+        mids = mothers(ctx)
+        for _ in range(reps):
+            for mid, g in zip(mids, gams):
+                ctx.ttcf_spawn_daughters(mid, ns, sb, g, nst)
+            ctx.ttcf_step(nst)
+            assert ctx.ttcf_accumulate() == 2 * ns
+            eager.append(ctx.ttcf_response(nst + 1, 0.0))
+        eager_mothers = [ctx.ttcf_export_mother(mid) for mid in mids]
+    with T.Context() as ctx:
+        mids = mothers(ctx)
+        gr = ctx.ttcf_graph_create_multi(
+            [{"mother": mid, "states_per_replica": ns, "steps_between": sb, "gamma_dot": g}
+             for mid, g in zip(mids, gams)], nst, reps)
+        for k in range(reps):
+            gr.launch(1)
+            _same_response(ctx.ttcf_response(nst + 1, 0.0), eager[k])
+            ctx.ttcf_export_mother(mids[0])  # eager work between replays
+        assert gr.replays == reps
+        for mid, em in zip(mids, eager_mothers):
+            r, p, z, steps = ctx.ttcf_export_mother(mid)
+            assert np.array_equal(r, em[0]) and np.array_equal(p, em[1])
+            assert z == em[2] and steps == em[3]
+        part = {"mother": mids[0], "states_per_replica": 1, "steps_between": 5, "gamma_dot": 0.1}
+        with pytest.raises(T.TTCFError) as e:  # one mother in two parts
+            ctx.ttcf_graph_create_multi([part, dict(part)], nst, 1)
+        assert e.value.code == T.TTCF_EINVAL
+
+
 def test_graph_with_parallel_mother_copies(T):
     """Mother copies (kicked, decorrelated) persist across replays: the first replay equals
     eager replicated sampling bit for bit, and two replays of 2 states per copy equal one
@@ -784,19 +832,29 @@ def test_gpu_mother_is_canonical_at_T(T):
 # the headline workload at full size, in the benchmark's launch configuration
 # ----------------------------------------------------------------------------------------
 
-def test_config2_full_size_sampled(T, orc):
-    """N=2048, 1024 start states x 4 mappings = 4096 daughters x 500 steps, FP32 forces, in
-    one persistent launch. The oracle (16 equilibrated states, tiled to 1024) recomputes a
-    sample of 8 daughters; their first 50 steps agree to 1e-4; every daughter keeps its
-    kinetic energy and the mapped P_xy(0) cancel."""
+@pytest.fixture(scope="module")
+def cfg2(orc):
+    """Config 2's system, N=2048: 16 start states of an oracle mother (400 steps, then every
+    50), the benchmark's batch made by tiling them to 1024."""
     s = I.System(8)
     box, sr16, sp16 = oracle_states(orc, s, seed=2, n_states=16, n_melt=0, n_equil=400,
                                     between=50)
+    return s, box, sr16, sp16
+
+
+@pytest.mark.parametrize("gd", [1e-2, 1.0])
+def test_config2_full_size_sampled(T, orc, cfg2, gd):
+    """N=2048, 1024 start states x 4 mappings = 4096 daughters x 500 steps, FP32 forces, in
+    one persistent launch, at a shear rate of the sweep (at 1.0 the Lees-Edwards offset passes
+    L_x, 1.25 L_x at the end). The oracle recomputes a sample of 8 daughters; their first 50
+    steps agree element by element to 1e-4; every daughter keeps its kinetic energy, the mapped
+    P_xy(0) cancel, and every group stays healthy."""
+    s, box, sr16, sp16 = cfg2
     reps = 64
     sr = np.tile(sr16, (reps, 1))
     sp = np.tile(sp16, (reps, 1))
-    nst, gd = 500, 1e-2
-    say("config 2 full size: 4096 daughters x 500 steps")
+    nst = 500
+    say(f"config 2 full size: 4096 daughters x 500 steps at {gd}")
     with T.Context() as ctx:
         mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
         ctx.ttcf_import_states(mid, sr, sp)
@@ -821,3 +879,31 @@ def test_config2_full_size_sampled(T, orc):
         assert k == nst
         k_start = 0.5 * np.sum(sp[d // 4] ** 2)
         assert 0.5 * np.sum(pg ** 2) == pytest.approx(k_start, rel=1e-13)
+
+
+def test_config2_response_of_16_states_matches_oracle(T, orc, cfg2):
+    """The full 500 steps of config 2's system at 1e-2 from 16 start states (64 daughters):
+    the GPU's TTCF and direct average (FP32 forces) against the oracle's own daughters and
+    estimator (FP64), within 2 combined standard errors at every time point (Eq. TTCF)."""
+    s, box, sr16, sp16 = cfg2
+    nst, gd = 500, 1e-2
+    say("config 2, 16 states x 4 mappings x 500 steps")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr16[0], sp16[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr16, sp16)
+        ctx.ttcf_spawn_daughters(mid, 16, 0, gd, nst)
+        ctx.ttcf_step(nst)
+        assert ctx.ttcf_accumulate() == 16
+        tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, gd)
+    assert used == 16
+    state_of = np.repeat(np.arange(16), 4)
+    map_of = np.tile(np.arange(4), 16)
+    vo, _ = orc.run_daughters(box, sr16, sp16, state_of, map_of, np.full(64, gd), s.dt, nst,
+                              nthreads=16)
+    oref = orc.ttcf_response(vo / s.volume, vo[:, 0], np.full(64, gd), s.temperature, s.dt)
+    comb = np.hypot(tse, oref.ttcf_se)
+    assert np.all(np.abs(tm - oref.ttcf)[1:] <= 2.0 * comb[1:])
+    assert np.all(np.abs(dm - oref.dav) <= 2.0 * np.hypot(dse, oref.dav_se) + 1e-15)
+    # the same start states: over the first 50 steps (trajectories equal to 1e-4) the two
+    # estimates agree to 1e-3 of the per-state responses' scale
+    assert np.all(np.abs(tm - oref.ttcf)[:51] <= 1e-3 * np.abs(oref.g).max())

@@ -803,6 +803,64 @@ def cv_leg(T, stream, gd=1e-4, nst=200, train_states=4096, eval_states=4096, epo
     return out
 
 
+def cv_ceiling(T, stream, gd=1e-4, nst=200, n_states=256, siblings=8,
+               scales=(1e-6, 1e-3, 1e-1), pos_scales=(1e-3, 1e-2), seed=6):
+    """The most any start-state control variate can remove on the control-variate workload
+    (N=256, rate 1e-4, 200-step daughters). Every start state gets `siblings` copies whose
+    momenta carry a small zero-sum kick (scale x sqrt(T) per component), or whose positions
+    are displaced (scale x the mean spacing rho^(-1/3) per component, momenta kept); their
+    mapped daughters run 200 steps. G_n(t) = B(0) + int_0^t Omega(0) B(s) ds averaged over a state's
+    four mappings (its contribution to Eq. TTCF). A one-way analysis of variance over states
+    and siblings splits Var(G_n(t)) into the part the start state fixes, R^2 (stable under
+    perturbations of that size), and the rest, which no function of the start state can
+    predict at that resolution: a control variate of the start state reduces the standard
+    error at most by 1 / sqrt(1 - R^2), with every cost left out."""
+    import torch
+    import ttcf_inputs as I
+    s = I.System(4)
+    sysd = T.make_system(s.n, s.box, s.temperature, s.dt, precision=1)
+    out = {"workload": f"{n_states} start states x {siblings} kicked siblings x 4 mappings x "
+                       f"{nst} steps, N={s.n}, shear rate {gd}"}
+    with T.Context(stream) as ctx:
+        r0, p0 = I.initial_state(s, seed)
+        mid = ctx.ttcf_init_mother(sysd, r0, p0, n_equil=2000, n_melt=1000, t_melt=2.0)
+        ctx.ttcf_sample_states_replicated(mid, n_states,
+                                          seeded_kicks(n_states, s.n, 0.05, seed * 1000 + 9),
+                                          400, 1, 100)
+        r, p = ctx.ttcf_export_states(mid, n_states)
+        rng = np.random.Generator(np.random.PCG64(seed * 1000 + 10))
+        spacing = s.density ** (-1.0 / 3.0)
+        for kind, scale in [("kick", a) for a in scales] + [("shift", a) for a in pos_scales]:
+            z = rng.standard_normal((n_states * siblings, 3, s.n))
+            z -= z.mean(axis=2, keepdims=True)
+            rs = np.repeat(r, siblings, axis=0)
+            ps = np.repeat(p, siblings, axis=0)
+            if kind == "kick":
+                ps = ps + scale * np.sqrt(s.temperature) * z.reshape(n_states * siblings, -1)
+            else:
+                rs = np.mod(rs + scale * spacing * z.reshape(n_states * siblings, -1), s.box)
+            ctx.ttcf_import_states(mid, rs, ps)
+            first = ctx.ttcf_spawn_daughters(mid, n_states * siblings, 0, gd, nst)
+            ctx.ttcf_step(nst)
+            ser = ctx.ttcf_export_series(first, 4 * n_states * siblings, nst + 1)
+            torch.cuda.synchronize()
+            b = ser / s.volume                                   # P_xy(t) per daughter
+            omega = -(gd / s.temperature) * ser[:, :1]           # Omega(0) = -(V/T) gd P_xy(0)
+            f = omega * b
+            integ = np.concatenate([np.zeros((len(f), 1)),
+                                    np.cumsum(0.5 * (f[:, 1:] + f[:, :-1]) * s.dt, axis=1)], axis=1)
+            g = (b[:, :1] + integ).reshape(n_states, siblings, 4, nst + 1).mean(axis=2)
+            within = g.var(axis=1, ddof=1).mean(axis=0)          # per time point
+            between = g.mean(axis=1).var(axis=0, ddof=1) - within / siblings
+            r2 = np.clip(between / np.maximum(between + within, 1e-300), 0.0, 1.0)
+            out[f"{kind}={scale:g}"] = {
+                "r2_at_steps": {str(j): float(r2[j]) for j in (1, 10, 50, 100, nst)},
+                "max_se_gain_at_steps": {str(j): float(1.0 / np.sqrt(max(1.0 - r2[j], 1e-12)))
+                                         for j in (1, 10, 50, 100, nst)}}
+            ctx.ttcf_accumulate()
+    return out
+
+
 def _seeded_weights(n_out: int, seed: int):
     """He-normal weights, zero biases, FP32 (numpy PCG64, seeded)."""
     rng = np.random.Generator(np.random.PCG64(seed + 100))
@@ -1062,6 +1120,10 @@ def main():
             line["cv"] = cv_leg(T, stream)
         except Exception as e:  # the headline line is printed whatever happens here
             line["cv"] = {"error": repr(e)}
+        try:
+            line["cv"]["ceiling"] = cv_ceiling(T, stream)
+        except Exception as e:  # the headline line is printed whatever happens here
+            line["cv"]["ceiling"] = {"error": repr(e)}
     progress("cv")
     if args.cpu_budget > 0:
         line["cpu_baseline"] = cpu_baseline(args.n_cells, nst, args.cpu_budget, start_states)

@@ -521,8 +521,10 @@ void ttcf_graph_destroy(ttcf_graph* graph);
 /* ---- learned control variate for Eq. (TTCF) ------------------------------------------
  * Not part of the paper's method: a variance-reduction layer over its estimator. A network
  * g(x) predicts B(t_1..t_K) of a daughter from 64 features x of its mapped start state
- * (P_xy(0), Omega(0) of Eq. (TTCF1), and per slab of 31 equal slabs in y the sums of p_x and
- * of p_x p_y). Each daughter gets h(t_k) = Omega(0) int_0^{t_k} g ds (trapezoid rule on the
+ * (P_xy(0), Omega(0) of Eq. (TTCF1); per slab of 20 equal slabs in y the sums of p_x, of
+ * p_x p_y and of half the pair virials x_ij F_y,ij of its atoms; and the two parts of
+ * d(V P_xy)/dt at t = 0 without force derivatives, sum_i (F_x,i p_y,i + p_x,i F_y,i) and
+ * sum_{i<j} (p_x,i - p_x,j) F_y,ij; systems up to about 2200 atoms). Each daughter gets h(t_k) = Omega(0) int_0^{t_k} g ds (trapezoid rule on the
  * step grid, g(0) = B(0)); a start state's H_n is the mean of h over its mappings. The
  * estimate is mean_n [G_n(t) - H_n(t)] + mu_H(t), with G_n the start state's Eq. (TTCF)
  * series and mu_H = E[H] over equilibrium start states, estimated from independent mother

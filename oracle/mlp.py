@@ -2,9 +2,12 @@
 
 The paper has no learned component; this follows the learned-control-variate form of the
 TTCF estimator that the build adds beside the plain method:
-  * start-state features x(Gamma): P_xy(0), Omega(0) and, for 31 slabs in y, the sums of
-    p_x and of p_x p_y over the atoms of the slab (reading: the 62 "binned stress/momentum"
-    features are the kinetic ones, which transform by sign flips under Eq. (mappings));
+  * start-state features x(Gamma): P_xy(0), Omega(0); for 20 slabs in y the sums over the
+    slab's atoms of p_x, of p_x p_y (the kinetic shear stress) and of the pair virial
+    x_ij F_y,ij (the configurational shear stress, each pair half to the slab of either
+    atom); and the two parts of d(V P_xy)/dt at t = 0 that need no force derivative,
+    sum_i (F_x,i p_y,i + p_x,i F_y,i) and sum_{i<j} (p_x,i - p_x,j) F_y,ij (reading: the 62
+    "binned stress/momentum" features are these 60 slab sums and the two rates);
   * an MLP g(x) = W3 gelu(W2 gelu(W1 x + b1) + b2) + b3 that predicts B(t_k), k = 1..n_out;
   * the control variate of one daughter, h = Omega(0) int_0^t g(x, s) ds (trapezoid rule with
     g(x, 0) = B(0), the known start value), whose mean over equilibrium start states is
@@ -23,7 +26,8 @@ from dataclasses import dataclass
 import numpy as np
 from scipy.special import erf
 
-N_SLABS = 31
+N_SLABS = 20
+WCA_RC = 2.0 ** (1.0 / 6.0)
 
 
 def bf16_round(a):
@@ -47,20 +51,51 @@ def gelu_grad(z):
 # features
 # ----------------------------------------------------------------------------------------
 
-def features(r, p, box, vpxy0, gamma_dot, temperature, volume):
-    """64 features of one (mapped) start state, FP64: [P_xy(0), Omega(0), sum p_x per slab
-    (31), sum p_x p_y per slab (31)]. r, p: SoA (3n,). Slab k = floor(y * 31 / Ly), clamped."""
+def pair_forces(r, box, rc=WCA_RC, c_attr=1.0):
+    """Every pair i < j closer than rc in a periodic box without Lees-Edwards offset (a start
+    state), by brute force: i, j, the minimum-image separation r_i - r_j (n_pairs, 3) and the
+    force on i from j, 24 (2 r^-14 - c r^-8) (r_i - r_j) (Eq. LJ with c = c_attr)."""
+    n = len(r) // 3
+    x = np.asarray(r, np.float64).reshape(3, n).T
+    L = np.asarray(box, np.float64)
+    i, j = np.triu_indices(n, 1)
+    d = x[i] - x[j]
+    d -= L * np.rint(d / L)
+    r2 = (d * d).sum(axis=1)
+    keep = r2 < rc * rc
+    i, j, d, r2 = i[keep], j[keep], d[keep], r2[keep]
+    inv2 = 1.0 / r2
+    inv6 = inv2 ** 3
+    f = (24.0 * inv6 * (2.0 * inv6 - c_attr) * inv2)[:, None] * d
+    return i, j, d, f
+
+
+def features(r, p, box, vpxy0, gamma_dot, temperature, volume, rc=WCA_RC, c_attr=1.0):
+    """64 features of one (mapped) start state, FP64: [P_xy(0), Omega(0), per slab (20 each):
+    sum p_x, sum p_x p_y, sum of half the pair virials x_ij F_y,ij of the slab's atoms; then
+    sum_i (F_x,i p_y,i + p_x,i F_y,i), sum_{i<j} (p_x,i - p_x,j) F_y,ij]. r, p: SoA (3n,).
+    Slab k = floor(y * 20 / Ly), clamped."""
     n = len(r) // 3
     y = r[n:2 * n]
     px, py = p[:n], p[n:2 * n]
     k = np.minimum(np.floor(y * (N_SLABS / box[1])).astype(int), N_SLABS - 1)
     mom = np.zeros(N_SLABS)
     st = np.zeros(N_SLABS)
+    vir = np.zeros(N_SLABS)
     np.add.at(mom, k, px)
     np.add.at(st, k, px * py)
+    i, j, d, f = pair_forces(r, box, rc, c_attr)
+    w = d[:, 0] * f[:, 1]
+    np.add.at(vir, k[i], 0.5 * w)
+    np.add.at(vir, k[j], 0.5 * w)
+    F = np.zeros((n, 3))
+    np.add.at(F, i, f)
+    np.add.at(F, j, -f)
+    d1 = np.sum(F[:, 0] * py + px * F[:, 1])
+    d2 = np.sum((px[i] - px[j]) * f[:, 1])
     pxy0 = vpxy0 / volume
     om = -(volume / temperature) * gamma_dot * pxy0
-    return np.concatenate([[pxy0, om], mom, st])
+    return np.concatenate([[pxy0, om], mom, st, vir, [d1, d2]])
 
 
 # ----------------------------------------------------------------------------------------

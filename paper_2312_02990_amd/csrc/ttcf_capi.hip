@@ -2856,9 +2856,12 @@ int32_t cv_features_of(ttcf_ctx* c, int64_t first, int32_t count, float* d_feat,
                                c->stream));
     HIPCHECK(c, launch_cv_gather_series(d_ser, count, n_out, 1.0 / m.dev.volume, d_targets, d_vp,
                                         c->stream));
+    if (lds_bytes_cv_features(m.dev.n) > c->max_lds)
+        return fail(c, TTCF_EINVAL, "system too large for the control-variate features");
     HIPCHECK(c, launch_cv_features(m.states, m.dev.n, d_idx, d_idx + count, d_vp, nullptr, count,
-                                   m.dev.box[1], m.dev.volume, m.sys.temperature,
-                                   c->descs[i0].gamma_dot, d_feat, d_b0, d_om, c->stream));
+                                   m.dev.box, m.dev.rc2, m.dev.c_attr, m.dev.volume,
+                                   m.sys.temperature, c->descs[i0].gamma_dot, d_feat, d_b0, d_om,
+                                   c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     if (i0_out) *i0_out = i0;
     return TTCF_OK;
@@ -3143,6 +3146,8 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
         return fail(c, TTCF_EINVAL, "the mean term already holds samples at another shear rate");
     Mother& m = c->mothers[mother];
     const int n = m.dev.n, O = c->cv_out;
+    if (lds_bytes_cv_features(n) > c->max_lds)
+        return fail(c, TTCF_EINVAL, "system too large for the control-variate features");
     const int64_t per_round = (int64_t)n_replicas * states_per_replica;
     if (per_round * 4 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many samples per round");
     Scratch sc(c->stream);
@@ -3172,9 +3177,9 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
         rc = R.sample(c, states_per_replica, steps_between, snaps);
         if (rc != TTCF_OK) return rc;
         HIPCHECK(c, launch_states_vpxy(m.dev, snaps, (int32_t)per_round, vp, c->stream));
-        HIPCHECK(c, launch_cv_features(snaps, n, idx, idx + rows, vp, sgn, rows, m.dev.box[1],
-                                       m.dev.volume, m.sys.temperature, gamma_dot, feat, b0,
-                                       b0 + rows, c->stream));
+        HIPCHECK(c, launch_cv_features(snaps, n, idx, idx + rows, vp, sgn, rows, m.dev.box,
+                                       m.dev.rc2, m.dev.c_attr, m.dev.volume, m.sys.temperature,
+                                       gamma_dot, feat, b0, b0 + rows, c->stream));
         rc = cv_predict_h(c, feat, b0, b0 + rows, rows, m.dev.dt, hh, O + 1);
         if (rc != TTCF_OK) return rc;
         HIPCHECK(c, launch_cv_mu_accum(hh, (int)per_round, 4, O + 1, c->cv_mu, c->cv_mu + (O + 1),

@@ -196,7 +196,7 @@ struct ResponseLaunch {
 
 // ---- learned control variate ---------------------------------------------------------
 constexpr int kCvIn = 64;       // features per start state
-constexpr int kCvSlabs = 31;    // y slabs of the binned features
+constexpr int kCvSlabs = 20;    // y slabs of the binned features (3 per slab, then 2 rates)
 constexpr int kCvHidden = 256;  // hidden width of both hidden layers
 
 struct GemmArgs {
@@ -231,11 +231,12 @@ hipError_t launch_cv_scatter_h(const double* h, int32_t stride, int32_t count, d
                                const int32_t* lens, hipStream_t s);
 hipError_t launch_cv_beta(const ResponseLaunch& r, double* beta, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s);
+size_t lds_bytes_cv_features(int32_t n);
 hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* state_of,
                               const int32_t* map_of, const double* vpxy0, const double* vsign,
-                              int32_t rows, double ly, double volume, double temperature,
-                              double gamma_dot, float* out, double* b0_out, double* om_out,
-                              hipStream_t s);
+                              int32_t rows, const double* box, double rc2, double c_attr,
+                              double volume, double temperature, double gamma_dot, float* out,
+                              double* b0_out, double* om_out, hipStream_t s);
 hipError_t launch_cv_h(const float* pred, int rows, int n_out, const float* ymu, const float* yinv,
                        const double* b0, const double* omega, double dt, double* out,
                        int64_t out_stride, hipStream_t s);

@@ -228,13 +228,29 @@ hipError_t launch_col_stats(const float* X, int64_t rows, int cols, float* mu, f
 // ---------------------------------------------------------------------------------------
 // features of mapped start states
 // ---------------------------------------------------------------------------------------
-// Row layout (kCvIn = 64): [P_xy(0), Omega(0), sum p_x over slab k (31), sum p_x p_y over slab
-// k (31)], slab k = floor(y * 31 / Ly) clamped. One workgroup per row; thread q < 62 owns one
-// slab sum and adds the atoms in index order (deterministic).
-__global__ void k_cv_features(const double* states, int32_t n, const int32_t* state_of,
-                              const int32_t* map_of, const double* vpxy0, const double* vsign,
-                              int32_t rows, double ly, double volume, double temperature,
-                              double gamma_dot, float* out, double* b0_out, double* om_out) {
+// Row layout (kCvIn = 64): [P_xy(0), Omega(0); per slab k of kCvSlabs = 20 in y (k = floor(y
+// 20 / Ly) clamped): sum p_x, sum p_x p_y, and half the pair virial x_ij F_y,ij of each of the
+// slab's atoms; then sum_i (F_x,i p_y,i + p_x,i F_y,i) and sum_{i<j} (p_x,i - p_x,j) F_y,ij],
+// all of the mapped start state (Eq. (mappings): x -> -x for mappings 2 and 3, p_x and p_y
+// signs as below). One workgroup of 64 threads per row: the mapped state is staged in LDS,
+// thread q computes the pair terms of atoms q, q + 64, ... against every other atom (each
+// pair seen from both sides, so no atomics), then thread q < 62 forms one sum in atom order
+// (deterministic). FP64 throughout; LDS 9 n doubles.
+__global__ __launch_bounds__(64) void k_cv_features(
+    const double* states, int32_t n, const int32_t* state_of, const int32_t* map_of,
+    const double* vpxy0, const double* vsign, int32_t rows, double lx, double ly, double lz,
+    double rc2, double c_attr, double volume, double temperature, double gamma_dot, float* out,
+    double* b0_out, double* om_out) {
+    extern __shared__ double cvs[];
+    double* X = cvs;
+    double* Y = X + n;
+    double* Z = Y + n;
+    double* PX = Z + n;
+    double* PY = PX + n;
+    double* FX = PY + n;
+    double* FY = FX + n;
+    double* VIR = FY + n;
+    double* D2 = VIR + n;
     const int row = blockIdx.x;
     if (row >= rows) return;
     const double* st = states + (size_t)state_of[row] * 6 * (size_t)n;
@@ -242,20 +258,65 @@ __global__ void k_cv_features(const double* states, int32_t n, const int32_t* st
     // mapping signs: p -> -p (m=1); (x, px) -> (-x, -px) (m=2); (x, py, pz) -> -(...) (m=3)
     const double sx = (m == 1 || m == 2) ? -1.0 : 1.0;
     const double sy = (m == 1 || m == 3) ? -1.0 : 1.0;
+    const double sr = (m == 2 || m == 3) ? -1.0 : 1.0;  // x of the positions
     const int q = threadIdx.x;
+    for (int a = q; a < n; a += blockDim.x) {
+        X[a] = sr * st[a];
+        Y[a] = st[n + a];
+        Z[a] = st[2 * n + a];
+        PX[a] = sx * st[3 * n + a];
+        PY[a] = sy * st[4 * n + a];
+    }
+    __syncthreads();
+    // minimum image with the reciprocal edges (the image chosen differs from a division's
+    // only for separations within rounding of half a box, far beyond r_c)
+    const double ilx = 1.0 / lx, ily = 1.0 / ly, ilz = 1.0 / lz;
+    for (int i = q; i < n; i += blockDim.x) {
+        const double xi = X[i], yi = Y[i], zi = Z[i], pxi = PX[i];
+        double fx = 0.0, fy = 0.0, vir = 0.0, d2 = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = xi - X[j], dy = yi - Y[j], dz = zi - Z[j];
+            dx -= lx * rint(dx * ilx);
+            dy -= ly * rint(dy * ily);
+            dz -= lz * rint(dz * ilz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rc2) {
+                const double inv2 = 1.0 / r2;
+                const double inv6 = inv2 * inv2 * inv2;
+                const double fs = 24.0 * inv6 * (2.0 * inv6 - c_attr) * inv2;
+                fx += fs * dx;
+                fy += fs * dy;
+                vir += 0.5 * dx * (fs * dy);
+                d2 += 0.5 * (pxi - PX[j]) * (fs * dy);
+            }
+        }
+        FX[i] = fx;
+        FY[i] = fy;
+        VIR[i] = vir;
+        D2[i] = d2;
+    }
+    __syncthreads();
     float* o = out + (size_t)row * kCvIn;
-    if (q < 2 * kCvSlabs) {
+    if (q < 3 * kCvSlabs) {
         const int slab = q % kCvSlabs;
-        const bool stress = q >= kCvSlabs;
+        const int kind = q / kCvSlabs;  // 0 p_x, 1 p_x p_y, 2 virial
         const double inv = (double)kCvSlabs / ly;
         double acc = 0.0;
         for (int a = 0; a < n; ++a) {
-            int k = (int)floor(st[n + a] * inv);
+            int k = (int)floor(Y[a] * inv);
             k = k < 0 ? 0 : (k > kCvSlabs - 1 ? kCvSlabs - 1 : k);
             if (k != slab) continue;
-            const double px = sx * st[3 * n + a];
-            acc += stress ? px * (sy * st[4 * n + a]) : px;
+            acc += kind == 0 ? PX[a] : (kind == 1 ? PX[a] * PY[a] : VIR[a]);
         }
+        o[2 + q] = (float)acc;
+    } else if (q == 3 * kCvSlabs) {
+        double acc = 0.0;
+        for (int a = 0; a < n; ++a) acc += FX[a] * PY[a] + PX[a] * FY[a];
+        o[2 + q] = (float)acc;
+    } else if (q == 3 * kCvSlabs + 1) {
+        double acc = 0.0;
+        for (int a = 0; a < n; ++a) acc += D2[a];
         o[2 + q] = (float)acc;
     }
     if (q == 0) {
@@ -270,14 +331,20 @@ __global__ void k_cv_features(const double* states, int32_t n, const int32_t* st
     }
 }
 
+size_t lds_bytes_cv_features(int32_t n) { return sizeof(double) * 9 * (size_t)n; }
+
 hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* state_of,
                               const int32_t* map_of, const double* vpxy0, const double* vsign,
-                              int32_t rows, double ly, double volume, double temperature,
-                              double gamma_dot, float* out, double* b0_out, double* om_out,
-                              hipStream_t s) {
+                              int32_t rows, const double* box, double rc2, double c_attr,
+                              double volume, double temperature, double gamma_dot, float* out,
+                              double* b0_out, double* om_out, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cv_features, dim3(rows), dim3(64), 0, s, states, n, state_of, map_of,
-                       vpxy0, vsign, rows, ly, volume, temperature, gamma_dot, out, b0_out, om_out);
+    const size_t lds = lds_bytes_cv_features(n);
+    (void)hipFuncSetAttribute((const void*)k_cv_features,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_cv_features, dim3(rows), dim3(64), lds, s, states, n, state_of, map_of,
+                       vpxy0, vsign, rows, box[0], box[1], box[2], rc2, c_attr, volume,
+                       temperature, gamma_dot, out, b0_out, om_out);
     return hipGetLastError();
 }
 

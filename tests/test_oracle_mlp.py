@@ -99,6 +99,8 @@ def test_fixed_control_variate_is_unbiased_and_reduces_variance():
 
 
 def test_features_flip_sign_under_mappings(orc):
+    """Eq. (mappings) on every feature block, and the slab sums against totals from the C
+    oracle (its own cell-list forces and W_xy, a separate implementation)."""
     s = I.System(3)
     r = I.perturbed_positions(s, 2, 0.1).ravel()
     p = I.maxwell_boltzmann(s.n, s.temperature, 2).ravel()
@@ -109,32 +111,66 @@ def test_features_flip_sign_under_mappings(orc):
         rm, pm = orc.apply_mapping(box, m, r, p)
         f.append(M.features(rm, pm, (s.box,) * 3, orc.vpxy(box, rm, pm), gd, T, V))
     f0 = f[0]
-    mom, st = slice(2, 33), slice(33, 64)
-    assert np.abs(f0[mom]).max() > 0 and np.abs(f0[st]).max() > 0
-    # p -> -p: momenta flip, kinetic stress and P_xy unchanged
+    mom, st, vir = slice(2, 22), slice(22, 42), slice(42, 62)
+    assert np.abs(f0[mom]).max() > 0 and np.abs(f0[st]).max() > 0 and np.abs(f0[vir]).max() > 0
+    assert f0[62] != 0 and f0[63] != 0
+    # p -> -p: momenta and both rates flip; kinetic and configurational stress, P_xy unchanged
     np.testing.assert_allclose(f[1][mom], -f0[mom], atol=1e-12)
     np.testing.assert_allclose(f[1][st], f0[st], atol=1e-12)
-    # (x, px) -> (-x, -px): momenta and stress flip, as do P_xy and Omega
+    np.testing.assert_allclose(f[1][vir], f0[vir], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(f[1][62:], -f0[62:], rtol=1e-10)
+    # (x, px) -> (-x, -px): everything flips, P_xy and Omega too
     np.testing.assert_allclose(f[2][mom], -f0[mom], atol=1e-12)
     np.testing.assert_allclose(f[2][st], -f0[st], atol=1e-12)
+    np.testing.assert_allclose(f[2][vir], -f0[vir], rtol=1e-8, atol=1e-8)
+    np.testing.assert_allclose(f[2][62:], -f0[62:], rtol=1e-8)
     np.testing.assert_allclose(f[2][:2], -f0[:2], rtol=1e-10)
-    # (x, py, pz) -> (-x, -py, -pz): momenta unchanged, stress flips
+    # (x, py, pz) -> (-x, -py, -pz): momenta and rates unchanged, both stresses flip
     np.testing.assert_allclose(f[3][mom], f0[mom], atol=1e-12)
     np.testing.assert_allclose(f[3][st], -f0[st], atol=1e-12)
-    # slab sums add up to the totals
+    np.testing.assert_allclose(f[3][vir], -f0[vir], rtol=1e-8, atol=1e-8)
+    np.testing.assert_allclose(f[3][62:], f0[62:], rtol=1e-8)
+    # slab sums add up to the totals; the configurational ones to the C oracle's W_xy, and
+    # the first rate to its forces
     assert f0[mom].sum() == pytest.approx(p[:s.n].sum(), abs=1e-10)
     assert f0[st].sum() == pytest.approx(np.dot(p[:s.n], p[s.n:2 * s.n]), rel=1e-12)
+    F, _, w, _ = orc.forces(box, r)
+    assert f0[vir].sum() == pytest.approx(w, rel=1e-10)
+    pp = p.reshape(3, s.n)
+    assert f0[62] == pytest.approx(np.sum(F[0] * pp[1] + pp[0] * F[1]), rel=1e-10)
+
+
+def test_features_of_a_close_pair():
+    """Two atoms closer than r_c in slabs 3 and 4 (the rest of the box empty): each slab holds
+    half the pair virial, the first rate is sum F_x p_y + p_x F_y and the second
+    (p_x,A - p_x,B) F_y on A, with the force from the C oracle."""
+    import oracle as orc
+    box = (5.0, 20 * 0.7, 6.0)
+    V = box[0] * box[1] * box[2]
+    r = np.array([1.0, 1.6, 2.45, 2.9, 3.0, 3.0])      # A in slab 3, B in slab 4
+    p = np.array([0.7, -1.1, 0.3, 0.9, 0.2, -0.4])
+    f = M.features(r, p, box, 0.0, 1e-3, 1.0, V)
+    F, _, w, npairs = orc.forces(orc.make_box(2, box), r)
+    assert npairs == 1 and F[1, 0] != 0
+    vir = np.zeros(20)
+    vir[3] = vir[4] = 0.5 * (r[0] - r[1]) * F[1, 0]
+    np.testing.assert_allclose(f[42:62], vir, rtol=1e-12, atol=0)
+    assert f[42:62].sum() == pytest.approx(w, rel=1e-12)
+    d1 = sum(F[0, a] * p[2 + a] + p[a] * F[1, a] for a in range(2))
+    assert f[62] == pytest.approx(d1, rel=1e-12)
+    assert f[63] == pytest.approx((p[0] - p[1]) * F[1, 0], rel=1e-12)
+    assert np.all(f[2:42][[0 + 3, 0 + 4]] == p[:2]) and f[22 + 3] == p[0] * p[2]
 
 
 def test_features_of_a_hand_placed_state():
     """Atoms placed by hand in known slabs (centres, lower edges, the top edge of the box) with
     momenta chosen per slab: every feature entry equals its value counted by hand, so a
     slab-index, offset or component error fails here. Omega(0) = -(V/T) gamma_dot P_xy(0)."""
-    ly = 31.0 * 0.7                    # slab width 0.7
-    box = (5.0, ly, 6.0)
+    ly = 20.0 * 0.7                    # slab width 0.7
+    box = (5.0, ly, 9.0)
     V, T, gd = box[0] * box[1] * box[2], 0.9, 3e-3
     ys, pxs, pys = [], [], []
-    for k in (0, 3, 17, 30):           # slab centres
+    for k in (0, 3, 17, 19):           # slab centres
         ys.append((k + 0.5) * 0.7)
         pxs.append(k + 1.0)
         pys.append(2.0)
@@ -145,19 +181,21 @@ def test_features_of_a_hand_placed_state():
     pxs.append(10.0)
     pys.append(-1.0)
     n = len(ys)
-    r = np.concatenate([np.linspace(0.1, 4.9, n), np.array(ys), np.full(n, 3.0)])
+    # z 1.5 apart: no pair comes closer than r_c
+    r = np.concatenate([np.linspace(0.1, 4.9, n), np.array(ys), 1.5 * np.arange(n)])
     p = np.concatenate([np.array(pxs), np.array(pys), np.linspace(-1.0, 1.0, n)])
     vpxy0 = 12.5
     f = M.features(r, p, box, vpxy0, gd, T, V)
     assert f.shape == (64,)
     assert f[0] == vpxy0 / V
     assert f[1] == pytest.approx(-(V / T) * gd * (vpxy0 / V), rel=1e-15)
-    mom = np.zeros(31)
-    st = np.zeros(31)
+    mom = np.zeros(20)
+    st = np.zeros(20)
     mom[0], st[0] = 1.0, 2.0
     mom[3], st[3] = 4.0, 8.0
     mom[17], st[17] = 18.0, 36.0
-    mom[30], st[30] = 31.0 + 10.0, 62.0 - 10.0
+    mom[19], st[19] = 20.0 + 10.0, 40.0 - 10.0
     mom[5], st[5] = -4.0, -2.0
-    assert np.array_equal(f[2:33], mom)
-    assert np.array_equal(f[33:64], st)
+    assert np.array_equal(f[2:22], mom)
+    assert np.array_equal(f[22:42], st)
+    assert np.all(f[42:] == 0.0)  # no pair closer than r_c

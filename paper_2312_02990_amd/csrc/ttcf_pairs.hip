@@ -52,9 +52,11 @@ constexpr double kTwo52 = 4503599627370496.0;    // 2^52
 struct PairLds {
     uint4* pos;        // [n] by rank: fixed-point x, y, z, and x + the Lees-Edwards offset
                        // (the x of the image a pair across the y boundary uses)
-    int4* facc;        // [n] by rank: fixed-point force accumulators: (x, y) packed in one
-                       // 64-bit integer y 2^32 + x, then z; w: the rank's list-grid cell
-                       // cx | cy << 10 | cz << 20 (set by each build)
+    unsigned long long* fxy;  // [n] by rank: fixed-point force accumulators, x and y packed
+                              // in one 64-bit integer y 2^32 + x
+    int32_t* fz;              // [n] by rank: the same for z (separate arrays of 8- and 4-byte
+                              // stride spread random ranks over more LDS banks)
+    uint32_t* fcell;          // [n] by rank: list-grid cell cx | cy << 10 | cz << 20 (each build)
     int32_t* cnt;      // [cells] counts, then placement cursors
     int32_t* start;    // [cells + 1]
     int32_t* rowinfo;  // [3 rows][2]: first x cell offset mod lc_x, cell count
@@ -66,12 +68,13 @@ struct PairLds {
     int32_t* wcnt;     // [kMaxWaves] pairs in each wave's segment (at most its capacity)
     double* ktab;      // [16] series coefficients of the isokinetic kick
     SysDev* sys;
-    // during a rebuild the facc area holds the sorted atom ids (u16 [n]) and the rank of
+    // during a rebuild the fxy area holds the sorted atom ids (u16 [n]) and the rank of
     // every atom id (u16 [n])
 };
 
 struct PairPlan {
-    size_t pos, facc, cnt, start, rowinfo, red, red2, scan, wmax, flags, wcnt, ktab, sys, total;
+    size_t pos, fxy, fz, fcell, cnt, start, rowinfo, red, red2, scan, wmax, flags, wcnt, ktab, sys,
+        total;
 };
 
 __host__ __device__ inline size_t pf_align(size_t v, size_t a) { return (v + a - 1) & ~(a - 1); }
@@ -86,7 +89,9 @@ __host__ __device__ inline PairPlan plan_pairs(int n, int cells) {
         return at;
     };
     p.pos = take(16 * (size_t)n, 16);
-    p.facc = take(16 * (size_t)n, 16);
+    p.fxy = take(8 * (size_t)n, 16);
+    p.fz = take(4 * (size_t)n, 16);
+    p.fcell = take(4 * (size_t)n, 16);
     p.cnt = take(4 * (size_t)cells, 16);
     p.start = take(4 * (size_t)(cells + 1), 16);
     p.rowinfo = take(4 * 8, 16);
@@ -106,7 +111,9 @@ __device__ inline PairLds carve_pairs(char* base, int n, int cells) {
     const PairPlan p = plan_pairs(n, cells);
     PairLds L;
     L.pos = (uint4*)(base + p.pos);
-    L.facc = (int4*)(base + p.facc);
+    L.fxy = (unsigned long long*)(base + p.fxy);
+    L.fz = (int32_t*)(base + p.fz);
+    L.fcell = (uint32_t*)(base + p.fcell);
     L.cnt = (int32_t*)(base + p.cnt);
     L.start = (int32_t*)(base + p.start);
     L.rowinfo = (int32_t*)(base + p.rowinfo);
@@ -136,10 +143,10 @@ __device__ __forceinline__ uint32_t fixq(double v, double scale) {
 }
 
 // The fixed-point force of an accumulator: x and y from the packed 64-bit sum y 2^32 + x.
-__device__ __forceinline__ int3 unpack_force(const int4& q) {
-    const long long v = ((long long)(uint32_t)q.y << 32) | (uint32_t)q.x;
+__device__ __forceinline__ int3 unpack_force(unsigned long long xy, int z) {
+    const long long v = (long long)xy;
     const int lo = (int)(uint32_t)v;
-    return make_int3(lo, (int)((v - (long long)lo) >> 32), q.z);
+    return make_int3(lo, (int)((v - (long long)lo) >> 32), z);
 }
 
 // Pair words: rank i (bits 0-13), rank j (14-27); kShiftBit: j is taken at its image across
@@ -326,7 +333,7 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, P se
         const int s = r0 + u * 64 + lane;
         const bool own = s < n;
         const uint3 qi = *(const uint3*)&L.pos[own ? s : 0];
-        const uint32_t cc = (uint32_t)L.facc[own ? s : 0].w;
+        const uint32_t cc = L.fcell[own ? s : 0];
         const int cx = (int)(cc & 1023u), cy = (int)((cc >> 10) & 1023u), cz = (int)(cc >> 20);
 #pragma unroll 1
         for (int r = 0; r < 5; ++r) {
@@ -464,7 +471,7 @@ __device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t
     scan_cells(L.cnt, L.start, C, L.scan);
     if (t == 0) L.start[C] = n;
     __syncthreads();
-    uint16_t* sid = (uint16_t*)L.facc;
+    uint16_t* sid = (uint16_t*)L.fxy;
     uint16_t* rk = sid + n;
 #pragma unroll
     for (int j = 0; j < APT; ++j) {
@@ -509,7 +516,9 @@ __device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t
     // move each rank's cell there; the shifted x in its place
     for (int i = t; i < n; i += T) {
         const uint4 q = L.pos[i];
-        L.facc[i] = make_int4(0, 0, 0, (int)q.w);
+        L.fxy[i] = 0ull;
+        L.fz[i] = 0;
+        L.fcell[i] = q.w;
         L.pos[i].w = q.x + dxq;
     }
     __syncthreads();
@@ -611,12 +620,10 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq, P pa
             // x and y share one 64-bit integer, V = qy 2^32 + qx: sums of such values are
             // exact, and each component stays within +-2^31, so both decode exactly
             const unsigned long long v = (unsigned long long)(((long long)qy << 32) + (long long)qx);
-            unsigned long long* ai = (unsigned long long*)&L.facc[si];
-            unsigned long long* aj = (unsigned long long*)&L.facc[sj];
-            atomicAdd(ai, v);
-            atomicAdd((int*)ai + 2, qz);
-            atomicSub(aj, v);
-            atomicSub((int*)aj + 2, qz);
+            atomicAdd(&L.fxy[si], v);
+            atomicAdd(&L.fz[si], qz);
+            atomicSub(&L.fxy[sj], v);
+            atomicSub(&L.fz[sj], qz);
             // pair sums: the FP32 products rounded to the nearest 2^-19 unit, ties to even
             // (odd, so that mirrored configurations give exactly opposite sums)
             aw += __float2int_rn(dx * gy);
@@ -807,11 +814,12 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
         for (int j = 0; j < APT; ++j) {
             const int a = t + j * tj;
             if (t < tj && a < n) {
-                const int3 q = unpack_force(L.facc[rank[j]]);
+                const int3 q = unpack_force(L.fxy[rank[j]], L.fz[rank[j]]);
                 fx[j] = (float)q.x * kForceStep;
                 fy[j] = (float)q.y * kForceStep;
                 fz[j] = (float)q.z * kForceStep;
-                *(int3*)&L.facc[rank[j]] = make_int3(0, 0, 0);  // w keeps the cell
+                L.fxy[rank[j]] = 0ull;
+                L.fz[rank[j]] = 0;
             }
         }
     };
@@ -1028,7 +1036,10 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
     }
     // the accumulators must be zero for the next job (a call that stopped after a force pass
     // without reading it back would leave forces in them)
-    for (int i = t; i < n; i += blockDim.x) L.facc[i] = make_int4(0, 0, 0, 0);
+    for (int i = t; i < n; i += blockDim.x) {
+        L.fxy[i] = 0ull;
+        L.fz[i] = 0;
+    }
     __syncthreads();
 }
 
@@ -1048,7 +1059,10 @@ __global__ __launch_bounds__(kPairThreads) void k_daughters_pairs(BatchLaunch b)
         const int cells = d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2];
         const PairLds L = job_lds(n, cells);
         for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) L.facc[i] = make_int4(0, 0, 0, 0);
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            L.fxy[i] = 0ull;
+            L.fz[i] = 0;
+        }
         // run_daughter_pairs synchronises before its first use of the counts
         if constexpr (PL)
             run_daughter_pairs<APT, NH, OBS, COL>(
@@ -1073,7 +1087,10 @@ __global__ __launch_bounds__(kPairThreads) void k_debug_pair_form(
     const int t = threadIdx.x;
     if (t == 0) *L.sys = Sg;
     for (int c = t; c < cells; c += blockDim.x) L.cnt[c] = 0;
-    for (int i = t; i < Sg.n; i += blockDim.x) L.facc[i] = make_int4(0, 0, 0, 0);
+    for (int i = t; i < Sg.n; i += blockDim.x) {
+        L.fxy[i] = 0ull;
+        L.fz[i] = 0;
+    }
     __syncthreads();
     const SysDev& S = *L.sys;
     const int n = S.n, tj = job_threads(n), wave = t >> 6;
@@ -1103,7 +1120,7 @@ __global__ __launch_bounds__(kPairThreads) void k_debug_pair_form(
     for (int j = 0; j < APT; ++j) {
         const int a = t + j * tj;
         if (t < tj && a < n) {
-            const int3 q = unpack_force(L.facc[rank[j]]);
+            const int3 q = unpack_force(L.fxy[rank[j]], L.fz[rank[j]]);
             f[a] = (double)((float)q.x * kForceStep);
             f[n + a] = (double)((float)q.y * kForceStep);
             f[2 * n + a] = (double)((float)q.z * kForceStep);

@@ -899,8 +899,19 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
             x[j] += h * px[j] + h * gd * (y[j] + tau * py[j]);
             y[j] += h * py[j];
             z[j] += h * pz[j];
-            cr[j] += y[j] >= S.box[1] ? 1 : (y[j] < 0.0 ? -1 : 0);
-            wrap_le(S, dxle, x[j], y[j], z[j]);
+            // sliding-brick wrap without branches: a step moves an atom far less than a box
+            // edge, so each axis needs at most one image shift (the same operations as
+            // wrap_le in that case); a y crossing shifts x by -+ the offset
+            const double lx = S.box[0], ly = S.box[1], lz = S.box[2];
+            const bool up = y[j] >= ly, dn = y[j] < 0.0;
+            cr[j] += up ? 1 : (dn ? -1 : 0);
+            y[j] += up ? -ly : (dn ? ly : 0.0);
+            y[j] = y[j] >= ly ? 0.0 : y[j];  // a tiny negative y plus L rounded up to L
+            x[j] += up ? -dxle : (dn ? dxle : 0.0);
+            x[j] += x[j] >= lx ? -lx : (x[j] < 0.0 ? lx : 0.0);
+            x[j] = x[j] >= lx ? 0.0 : x[j];
+            z[j] += z[j] >= lz ? -lz : (z[j] < 0.0 ? lz : 0.0);
+            z[j] = z[j] >= lz ? 0.0 : z[j];
         }
         const float dm = pf_publish<APT>(S, dxq, x, y, z, rank, cr, path, L, tj, nw);
         ++since;

@@ -33,6 +33,9 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_pairs.hip"
 PEF_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_elongation.hip")
 PEF_VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_pef_n2048_valu.json")
 MIX_VALU_FILE = os.path.join(ROOT, "profiles", "k_daughters_mix_n2048_valu.json")
+CH_SRC = os.path.join(ROOT, "paper_2312_02990_amd", "csrc", "ttcf_channel.hip")
+CH_VALU_FILE = os.path.join(ROOT, "profiles", "k_channel_config4_valu.json")
+LANE_SLOT_PEAK = 256 * 4 * 16 * 2.4e9  # VALU lane-instruction slots per second
 
 
 _T0 = time.perf_counter()
@@ -669,6 +672,7 @@ def channel_leg(T, stream, n_states=256, nst=1000, speeds=(1e-2, 1e-4), n_equil=
         out["kernel_atom_steps_per_s"] = atom_steps / (ms / 1e3)
         out["end_to_end_atom_steps_per_s"] = atom_steps / wall
         out["kernel_ms_per_launch"] = ms / max(launches, 1)
+        out["roofline"] = channel_roofline(atom_steps / (ms / 1e3))
         resp = {}
         for v in speeds:
             tm, tse, dm, dse, used = ctx.response(T.TTCF_OBS_WALL_STRESS, v, nst + 1)
@@ -683,6 +687,27 @@ def channel_leg(T, stream, n_states=256, nst=1000, speeds=(1e-2, 1e-4), n_equil=
                             "n_states": int(used)}
         out["responses"] = resp
     return out
+
+
+def channel_roofline(atom_steps_per_s: float):
+    """The channel kernel is bound by VALU issue (FP32 LJ pair forces at r_c = 2.5): the lane
+    slots it issues per second (its measured slots per atom-step, from the committed SQ counter
+    runs on the current source, times the live rate) against the chip's 3.93e13 (256 CUs x 4
+    SIMDs x 16 lanes x 2.4 GHz). None without a matching counter run."""
+    try:
+        with open(CH_VALU_FILE) as f:
+            rec = json.load(f)
+        with open(CH_SRC, "rb") as f:
+            cur = hashlib.sha256(f.read()).hexdigest()[:16]
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sha256_16") != cur:
+        return None
+    achieved = rec["lane_slots_per_atom_step"] * atom_steps_per_s
+    return {"bound": "alu", "achieved": achieved, "peak": LANE_SLOT_PEAK, "unit": "lane-slots/s",
+            "frac": achieved / LANE_SLOT_PEAK, "valu_busy": rec.get("valu_busy"),
+            "active_lanes": rec.get("active_lanes"),
+            "lane_slots_per_atom_step": rec["lane_slots_per_atom_step"], "traffic": None}
 
 
 def seeded_kicks(n_rep: int, n: int, scale: float, seed: int):

@@ -178,10 +178,12 @@ __device__ __forceinline__ void iso_kick_coeffs_tab(double a, double b, double t
     double ch1_b, sh_q;
     const double u = b * tau * tau;
     if (u < 0.04) {
-        double c = tab[6];
-        for (int k = 5; k >= 0; --k) c = c * u + tab[k];
-        double d = tab[14];
-        for (int k = 6; k >= 0; --k) d = d * u + tab[7 + k];
+        // Estrin's scheme: the same polynomials in fewer dependent steps
+        const double u2 = u * u, u4 = u2 * u2;
+        const double c = (tab[0] + tab[1] * u) + u2 * (tab[2] + tab[3] * u) +
+                         u4 * ((tab[4] + tab[5] * u) + u2 * tab[6]);
+        const double d = (tab[7] + tab[8] * u) + u2 * (tab[9] + tab[10] * u) +
+                         u4 * ((tab[11] + tab[12] * u) + u2 * (tab[13] + tab[14] * u));
         ch1_b = tau * tau * c;
         sh_q = tau * d;
     } else {
@@ -210,6 +212,29 @@ __device__ __forceinline__ void iso_kick_coeffs_tab(double a, double b, double t
     sdot = a * sh_q + (1.0 + b * ch1_b);
 }
 
+// 1/x to about an ulp for x of normal size: the hardware reciprocal and two Newton steps
+// (the step's scalars are one dependent chain that every wave waits on, so the short chain
+// pays where a correctly rounded division would not).
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+
+// 1/sqrt(x) to about an ulp for positive x of normal size: the hardware estimate and two
+// Newton steps y <- y (1 + (1 - x y^2) / 2).
+__device__ __forceinline__ double rsq_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const double e = __builtin_fma(-(x * y), y, 1.0);
+        y = __builtin_fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
 // One DPP move of a double from the lane the control selects (every lane has a source).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
@@ -219,6 +244,36 @@ __device__ __forceinline__ double dpp_move(double v) {
     const uint32_t hi =
         (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// The value of lane ^ D (D = 16: lanes of rows 0 and 2; D = 32: lanes 0..31) from gfx950's
+// row and half swaps (the second result of a swap of x with itself holds, in those lanes, the
+// other row's or half's values).
+template <int D>
+__device__ __forceinline__ double swap_partner(double v) {
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)u, hi = (uint32_t)(u >> 32);
+    uint32_t plo, phi;
+    if constexpr (D == 16) {
+        plo = __builtin_amdgcn_permlane16_swap(lo, lo, false, false)[1];
+        phi = __builtin_amdgcn_permlane16_swap(hi, hi, false, false)[1];
+    } else {
+        plo = __builtin_amdgcn_permlane32_swap(lo, lo, false, false)[1];
+        phi = __builtin_amdgcn_permlane32_swap(hi, hi, false, false)[1];
+    }
+    return __builtin_bit_cast(double, ((uint64_t)phi << 32) | plo);
+}
+
+// Sum of red[w kPfRed] over waves w = 0..nw-1 in that order, the loads issued together (a
+// wave past nw adds an exact zero).
+__device__ __forceinline__ double waves_sum(const double* red, int nw) {
+    double v[kPairThreads / 64];
+#pragma unroll
+    for (int w = 0; w < kPairThreads / 64; ++w) v[w] = w < nw ? red[w * kPfRed] : 0.0;
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPairThreads / 64; ++w) s += v[w];
+    return s;
 }
 
 // One stage of a transposed reduction: a lane with `upper` set keeps a[H..2H) and hands
@@ -252,15 +307,15 @@ __device__ __forceinline__ void pf_block_sum12(double (&v)[12], double* red, int
     a[3] = 0.0;
     xstage<2, 0x124>(a, b2);  // row_ror:4
     xstage<1, 0x128>(a, b3);  // row_ror:8
-    a[0] += __shfl_xor(a[0], 16, 64);
-    a[0] += __shfl_xor(a[0], 32, 64);
+    // cross-row sums without LDS: in rows 0 and 2 the lane of row + 1, then in lanes 0..31
+    // the lane 32 above (the swaps' second results; only row 0 is used)
+    a[0] += swap_partner<16>(a[0]);
+    a[0] += swap_partner<32>(a[0]);
     // value held by this lane: 6 b0 + 3 b1 + (0, 1 or 2 from b2, b3; none if both are set)
     const int idx = 6 * (int)b0 + 3 * (int)b1 + (b2 ? 2 : (int)b3);
     if (lane < 16 && !(b2 && b3) && wave < nw) red[wave * kPfRed + idx] = a[0];
     __syncthreads();
-    double s = 0.0;
-    if (lane < 12)
-        for (int w = 0; w < nw; ++w) s += red[w * kPfRed + lane];
+    const double s = lane < 12 ? waves_sum(red + lane, nw) : 0.0;
     const uint64_t u = __builtin_bit_cast(uint64_t, s);
     const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
 #pragma unroll
@@ -285,9 +340,7 @@ __device__ __forceinline__ void pf_block_sum(double (&v)[K], double* red, int nw
         for (int k = 0; k < K; ++k) red[wave * kPfRed + k] = v[k];
     }
     __syncthreads();
-    double s = 0.0;
-    if (lane < K)
-        for (int w = 0; w < nw; ++w) s += red[w * kPfRed + lane];
+    const double s = lane < K ? waves_sum(red + lane, nw) : 0.0;
     const uint64_t u = __builtin_bit_cast(uint64_t, s);
     const int lo = (int)(uint32_t)u, hi = (int)(uint32_t)(u >> 32);
 #pragma unroll
@@ -306,6 +359,7 @@ __device__ __forceinline__ PairLds job_lds(int n, int cells) {
 }
 
 typedef __attribute__((address_space(1))) uint32_t gu32;  // pair words in global scratch
+typedef __attribute__((address_space(1))) double gf64;    // series in global memory
 typedef __attribute__((address_space(3))) uint32_t lu32;  // pair words in LDS
 
 // ---------------------------------------------------------------------------------------
@@ -324,8 +378,10 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, P se
     const int t = threadIdx.x, lane = t & 63;
     int base = 0;  // wave-uniform: pairs found so far by this wave
     if (t >= tj) return 0;
-    const float rl2 = S.rl2_f;
-    const float ux = S.fix_unit[0], uy = S.fix_unit[1], uz = S.fix_unit[2];
+    // r_l^2 and the y and z fixed-point steps in units of the x step
+    const float ux = S.fix_unit[0];
+    const float rl2u = S.rl2_f / (ux * ux);
+    const float ryx = S.fix_unit[1] / ux, rzx = S.fix_unit[2] / ux;
     const int r0 = (t >> 6) * 64 * APT;
 #pragma unroll 1
     for (int u = 0; u < APT; ++u) {
@@ -393,6 +449,9 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, P se
             // the pair word: (s, k), or (k, s) for an image below, flagged when shifted
             const int shs = ny < 0 ? 14 : 0;
             const uint32_t wfix = ((uint32_t)s << shs) | (ny != 0 ? kShiftBit : 0u);
+            // candidate vv of the row: rank lo0 + vv in the first range, lo1 + (vv - len0)
+            // in the second
+            const int off1 = lo1 - len0;
             // kScanPerTrip candidates per lane per trip, their loads issued together; trips
             // until the wave's longest row is done
             for (int v = 0; __builtin_amdgcn_ballot_w64(v < len) != 0; v += kScanPerTrip) {
@@ -401,16 +460,18 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, P se
 #pragma unroll
                 for (int u = 0; u < kScanPerTrip; ++u) {
                     const int vv = v + u;
-                    k[u] = vv >= len ? s : (vv < len0 ? lo0 + vv : lo1 + (vv - len0));
+                    const int kk = vv + (vv < len0 ? lo0 : off1);
+                    k[u] = vv < len ? kk : 0;  // (len is 0 past n)
                 }
 #pragma unroll
-                for (int u = 0; u < kScanPerTrip; ++u) q[u] = *(const uint3*)&L.pos[own ? k[u] : 0];
+                for (int u = 0; u < kScanPerTrip; ++u) q[u] = *(const uint3*)&L.pos[k[u]];
 #pragma unroll
                 for (int u = 0; u < kScanPerTrip; ++u) {
-                    const float ddx = (float)(int32_t)(qi.x - q[u].x - rsh) * ux;
-                    const float ddy = (float)(int32_t)(qi.y - q[u].y) * uy;
-                    const float ddz = (float)(int32_t)(qi.z - q[u].z) * uz;
-                    const bool hit = (v + u < len) & (ddx * ddx + ddy * ddy + ddz * ddz < rl2);
+                    // the squared distance in units of the x fixed-point step
+                    const float ddx = (float)(int32_t)(qi.x - q[u].x - rsh);
+                    const float ddy = (float)(int32_t)(qi.y - q[u].y) * ryx;
+                    const float ddz = (float)(int32_t)(qi.z - q[u].z) * rzx;
+                    const bool hit = (v + u < len) & (ddx * ddx + ddy * ddy + ddz * ddz < rl2u);
                     const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
                     const int below = (int)__builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -530,7 +591,8 @@ __device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t
     }
     __syncthreads();
     int any = 0;
-    for (int w = 0; w < nwb; ++w) any |= L.flags[w];
+#pragma unroll
+    for (int w = 0; w < kPairThreads / 64; ++w) any |= w < nwb ? L.flags[w] : 0;
     *overflow = any != 0;
     return count;
 }
@@ -616,14 +678,17 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq, P pa
             close |= r2 < rg2;
             // truncated to a whole unit: odd in the separation, so a pair gives the same
             // increments whichever atom it lists first; atom j gets exactly the negation
-            const int qx = __float2int_rz(gx), qy = __float2int_rz(gy), qz = __float2int_rz(gz);
+            // (a plain conversion: v_cvt_i32_f32 rounds toward zero)
+            const int qx = (int)gx, qy = (int)gy, qz = (int)gz;
             // x and y share one 64-bit integer, V = qy 2^32 + qx: sums of such values are
             // exact, and each component stays within +-2^31, so both decode exactly
             const unsigned long long v = (unsigned long long)(((long long)qy << 32) + (long long)qx);
-            atomicAdd(&L.fxy[si], v);
-            atomicAdd(&L.fz[si], qz);
-            atomicSub(&L.fxy[sj], v);
-            atomicSub(&L.fz[sj], qz);
+            // (LDS atomics without return; j's through the subtracting form, so that no
+            // negated copies are needed)
+            __hip_atomic_fetch_add(&L.fxy[si], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&L.fz[si], qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_sub(&L.fxy[sj], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_sub(&L.fz[sj], qz, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             // pair sums: the FP32 products rounded to the nearest 2^-19 unit, ties to even
             // (odd, so that mirrored configurations give exactly opposite sums)
             aw += __float2int_rn(dx * gy);
@@ -656,7 +721,7 @@ template <int APT>
 __device__ __forceinline__ void pf_record_obs(const SysDev& S, const double (&y)[APT],
                                               const double (&px)[APT], const double (&py)[APT],
                                               const double (&pz)[APT], const PfSums& ps,
-                                              double* xs, int row, const PairLds& L, int nw) {
+                                              gf64* xs, int row, const PairLds& L, int nw) {
     double o[kObsCols + 4];
 #pragma unroll
     for (int c = 0; c < kObsCols; ++c) o[c] = 0.0;
@@ -681,7 +746,7 @@ __device__ __forceinline__ void pf_record_obs(const SysDev& S, const double (&y)
     if (threadIdx.x == 0) {
         const double wxx = o[kObsCols] * kSumStep, wyy = o[kObsCols + 1] * kSumStep,
                      wzz = o[kObsCols + 2] * kSumStep, u = o[kObsCols + 3] * kSumStep;
-        double* out = xs + (size_t)row * kObsCols;
+        gf64* out = xs + (size_t)row * kObsCols;
         const double iv = 1.0 / S.volume;
         out[0] = (o[0] + (wxx - wyy)) * iv;
         out[1] = (o[1] + (wyy - wzz)) * iv;
@@ -719,8 +784,12 @@ __device__ __forceinline__ float pf_publish(const SysDev& S, uint32_t dxq, const
     pm = wave_max_dpp(pm);
     if ((t & 63) == 63) L.wmax[t >> 6] = pm;
     __syncthreads();
+    float v[kPairThreads / 64];
+#pragma unroll
+    for (int w = 0; w < kPairThreads / 64; ++w) v[w] = w < nw ? L.wmax[w] : 0.f;
     float m = 0.f;
-    for (int w = 0; w < nw; ++w) m = fmaxf(m, L.wmax[w]);
+#pragma unroll
+    for (int w = 0; w < kPairThreads / 64; ++w) m = fmaxf(m, v[w]);
     return m;
 }
 
@@ -824,7 +893,11 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
         }
     };
     readback();
-    double* const xs = OBS ? dsc->xseries : nullptr;
+    // the series as global pointers held for the whole call: a generic store would make the
+    // next barrier wait for it, and a store through the descriptor's pointer would make the
+    // compiler reload that pointer every step
+    gf64* const xs = OBS ? (gf64*)dsc->xseries : nullptr;
+    gf64* const series = (gf64*)dsc->series;
 
     double m0[8] = {0, 0, 0, 0, 0, 0, ps.w, (double)ps.close};
 #pragma unroll
@@ -844,11 +917,14 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
     if (m0[7] != 0.0) health |= kHealthForceRange;
     if (done == 0) {
         if (k0 <= 0.0) k0 = 0.5 * m0[0];
-        if (t == 0) dsc->series[0] = (COL && col) ? m0[1] : m0[1] + m0[6] * kSumStep;
+        if (t == 0) dsc->k0 = k0;
+        if (t == 0) series[0] = (COL && col) ? m0[1] : m0[1] + m0[6] * kSumStep;
         if (OBS && xs) pf_record_obs<APT>(S, y, px, py, pz, ps, xs, 0, L, nw);
     }
     if (health != 0) todo = 0;
+    const double sqrt2k0 = sqrt(2.0 * k0);
     const double h = S.dt, tau = 0.5 * S.dt, tg = tau * gd;
+    const float hpath = (float)h * (1.f + 0x1p-20f);
     const float reach = (float)S.rc;
     const float skin = (float)S.skin;
     const float agd = (float)fabs(gd);
@@ -865,11 +941,12 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
             hh = tau;
         } else {
             const double ppt = pp - 2.0 * tg * pxpy + tg * tg * pypy;
-            const double g1 = sqrt(pp / ppt);
+            const double g1 = pp * rsq_nr(pp * ppt);  // sqrt(pp / ppt)
+            const double ipp = rcp_nr(pp);
             const double fp1 = g1 * (fp - tg * fxpy);
             double s1, sd1;
-            iso_kick_coeffs_tab(fp1 / pp, ff / pp, tau, L.ktab, s1, sd1);
-            const double isd1 = 1.0 / sd1;
+            iso_kick_coeffs_tab(fp1 * ipp, ff * ipp, tau, L.ktab, s1, sd1);
+            const double isd1 = rcp_nr(sd1);
             e = g1 * isd1;
             g = -tg * e;
             hh = s1 * isd1;
@@ -892,26 +969,37 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
         k += 1;
         dxle = le_offset(S, gd, k);
         dxq = fix32(dxle, S.fix_scale[0]);
+        const double lx = S.box[0], ly = S.box[1], lz = S.box[2];
+        bool out = false;
 #pragma unroll
         for (int j = 0; j < APT; ++j) {
             const double vx = px[j] + tg * py[j];
-            path[j] += (float)h * sqrtf((float)(vx * vx + py[j] * py[j] + pz[j] * pz[j]));
+            // the hardware square root (about an ulp) with the step scaled up by 2^-20, so
+            // that the path length stays an upper bound
+            path[j] += hpath * __builtin_amdgcn_sqrtf((float)(vx * vx + py[j] * py[j] + pz[j] * pz[j]));
             x[j] += h * px[j] + h * gd * (y[j] + tau * py[j]);
             y[j] += h * py[j];
             z[j] += h * pz[j];
-            // sliding-brick wrap without branches: a step moves an atom far less than a box
-            // edge, so each axis needs at most one image shift (the same operations as
-            // wrap_le in that case); a y crossing shifts x by -+ the offset
-            const double lx = S.box[0], ly = S.box[1], lz = S.box[2];
-            const bool up = y[j] >= ly, dn = y[j] < 0.0;
-            cr[j] += up ? 1 : (dn ? -1 : 0);
-            y[j] += up ? -ly : (dn ? ly : 0.0);
-            y[j] = y[j] >= ly ? 0.0 : y[j];  // a tiny negative y plus L rounded up to L
-            x[j] += up ? -dxle : (dn ? dxle : 0.0);
-            x[j] += x[j] >= lx ? -lx : (x[j] < 0.0 ? lx : 0.0);
-            x[j] = x[j] >= lx ? 0.0 : x[j];
-            z[j] += z[j] >= lz ? -lz : (z[j] < 0.0 ? lz : 0.0);
-            z[j] = z[j] >= lz ? 0.0 : z[j];
+            out |= (x[j] < 0.0) | (x[j] >= lx) | (y[j] < 0.0) | (y[j] >= ly) | (z[j] < 0.0) |
+                   (z[j] >= lz);
+        }
+        // sliding-brick wrap, only in a wave where an atom left the box (a few percent of the
+        // steps): a step moves an atom far less than a box edge, so each axis needs at most
+        // one image shift (the same operations as wrap_le in that case); a y crossing shifts
+        // x by -+ the offset
+        if (__builtin_amdgcn_ballot_w64(out) != 0) {
+#pragma unroll
+            for (int j = 0; j < APT; ++j) {
+                const bool up = y[j] >= ly, dn = y[j] < 0.0;
+                cr[j] += up ? 1 : (dn ? -1 : 0);
+                y[j] += up ? -ly : (dn ? ly : 0.0);
+                y[j] = y[j] >= ly ? 0.0 : y[j];  // a tiny negative y plus L rounded up to L
+                x[j] += up ? -dxle : (dn ? dxle : 0.0);
+                x[j] += x[j] >= lx ? -lx : (x[j] < 0.0 ? lx : 0.0);
+                x[j] = x[j] >= lx ? 0.0 : x[j];
+                z[j] += z[j] >= lz ? -lz : (z[j] < 0.0 ? lz : 0.0);
+                z[j] = z[j] >= lz ? 0.0 : z[j];
+            }
         }
         const float dm = pf_publish<APT>(S, dxq, x, y, z, rank, cr, path, L, tj, nw);
         ++since;
@@ -965,15 +1053,16 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
             zt += tau * (pp - nh_tgt) * nh_iq;
         } else {
             double s2, sd2;
-            iso_kick_coeffs_tab(m[3] / m[0], m[9] / m[0], tau, L.ktab, s2, sd2);
-            const double isd2 = 1.0 / sd2;
+            const double im0 = rcp_nr(m[0]);
+            iso_kick_coeffs_tab(m[3] * im0, m[9] * im0, tau, L.ktab, s2, sd2);
+            const double isd2 = rcp_nr(sd2);
             const double pp3 = (m[0] + 2.0 * s2 * m[3] + s2 * s2 * m[9]) * isd2 * isd2;
             const double pxpy3 = (m[1] + s2 * (m[4] + m[5]) + s2 * s2 * m[6]) * isd2 * isd2;
             const double pypy3 = (m[2] + 2.0 * s2 * m[7] + s2 * s2 * m[8]) * isd2 * isd2;
             const double fp3 = (m[3] + s2 * m[9]) * isd2;
             const double fxpy3 = (m[4] + s2 * m[6]) * isd2;
             const double ppt2 = pp3 - 2.0 * tg * pxpy3 + tg * tg * pypy3;
-            const double c = sqrt(2.0 * k0 / ppt2);
+            const double c = sqrt2k0 * rsq_nr(ppt2);  // sqrt(2 k0 / ppt2)
             A = c * isd2;
             B = A * s2;
             C = -tg * A;
@@ -984,12 +1073,12 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
             fp = c * (fp3 - tg * fxpy3);
             fxpy = c * fxpy3;
             ff = m[9];
-            drift = fabs(pp3 / m[0] - 1.0) > 1e-10;
+            drift = fabs(pp3 * im0 - 1.0) > 1e-10;
         }
         // colour: V J_x of the final momenta from the charge moments (no shear: C = D = 0)
         vpxy = (COL && col) ? A * m[1] + B * m[4] : pxpy + m[10] * kSumStep;
         done += 1;
-        if (t == 0) dsc->series[done] = vpxy;
+        if (t == 0) series[done] = vpxy;
         if (m[11] != 0.0) health |= kHealthForceRange;
         if (!isfinite(vpxy) || !isfinite(pp) || !isfinite(zt)) health |= kHealthNonFinite;
         if (drift) health |= kHealthDrift;
@@ -1041,7 +1130,6 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
     if (t == 0) {
         dsc->k = k;
         dsc->done = done;
-        dsc->k0 = k0;
         dsc->health = health;
         dsc->zeta = zt;
     }

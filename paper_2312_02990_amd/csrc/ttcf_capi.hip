@@ -1109,7 +1109,7 @@ int32_t plan_group(ttcf_ctx* c, const std::vector<const DaughterDesc*>& group, b
             nl_lds_pl = std::max(nl_lds_pl, lds_bytes_pairs_lds(dp->sys.n, dp->sys.lc[0] * dp->sys.lc[1] *
                                                                    dp->sys.lc[2], dp->kmax, apt));
         }
-    const bool pairs_lds = nlf && apt == 4 && nl_lds_pl <= c->max_lds;
+    const bool pairs_lds = nlf && apt == pair_small_apt() && nl_lds_pl <= c->max_lds;
     *L = BatchLaunch{};
     L->descs = c->d_descs;
     L->n_jobs = (int32_t)group.size();
@@ -1239,7 +1239,7 @@ int32_t step_impl(ttcf_ctx* c, int32_t n_steps, const std::vector<char>* only,
         if (d.field != kFieldShear && !nl)
             return fail(c, TTCF_EINVAL, "colour-field daughters need the neighbour-list form, "
                                         "and this system runs in cells");
-        const int form = !nl ? 1 : (pair_job_apt(d.sys.n) == 4 ? 0 : 2);
+        const int form = !nl ? 1 : (pair_job_apt(d.sys.n) == pair_small_apt() ? 0 : 2);
         groups[2 * form + (d.thermo ? 1 : 0)].push_back((int32_t)i);
     }
     const bool any_nl = !groups[0].empty() || !groups[1].empty() || !groups[4].empty() ||
@@ -2222,7 +2222,7 @@ int32_t graph_create_impl(ttcf_ctx* c, const ttcf_graph_desc* gds, int32_t n_des
     // thread, 1 cells, 2 pair lists at eight; largest systems first inside each
     std::vector<int32_t> groups[6];
     for (int32_t d = 0; d < nd; ++d) {
-        const int form = !nl_of[d] ? 1 : (pair_job_apt(hd[d].sys.n) == 4 ? 0 : 2);
+        const int form = !nl_of[d] ? 1 : (pair_job_apt(hd[d].sys.n) == pair_small_apt() ? 0 : 2);
         groups[2 * form + (hd[d].thermo ? 1 : 0)].push_back(d);
     }
     std::vector<BatchLaunch> launches;

@@ -255,6 +255,7 @@ size_t lds_bytes_for(int nmax, int cmax, int threads, int precision);
 size_t lds_bytes_pairs(int n, int cells);
 int pair_job_threads(int n);
 int pair_job_apt(int n);
+int pair_small_apt();  // atoms per thread of the systems whose pair words can sit in LDS
 // a launch runs every job with `apt` atoms per thread (the largest job's), so a job's wave
 // segments hold 64 apt kcap words each
 inline int64_t pair_words(int n, int kcap, int apt) {

@@ -7,7 +7,7 @@
 
 namespace ttcf {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // float -> bfloat16 bits, round to nearest even
@@ -25,10 +25,11 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 
 // ---------------------------------------------------------------------------------------
 // GEMM: C(m, n) = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]
-// Operands are rounded to bfloat16 as they are staged into LDS; v_mfma_f32_16x16x16_bf16
-// accumulates in FP32. Workgroup tile 64 x 64 (four waves of 32 x 32, each 2 x 2 MFMA
-// tiles), K step 32. Operand layout of the 16x16x16 instruction: lane l holds A[l % 16][4 (l /
-// 16) + i] and B[4 (l / 16) + i][l % 16] (i = 0..3); the result D[4 (l / 16) + i][l % 16].
+// Operands are rounded to bfloat16 as they are staged into LDS; gfx950's
+// v_mfma_f32_16x16x32_bf16 accumulates in FP32. Workgroup tile 64 x 64 (four waves of
+// 32 x 32, each 2 x 2 MFMA tiles), K step 32: one matrix instruction per tile and step.
+// Operand layout of the 16x16x32 instruction: lane l holds A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16] (i = 0..7); the result D[4 (l / 16) + i][l % 16].
 // Epilogues: 0 C = acc + bias; 1 Z = acc + bias, C = gelu(Z); 2 C = acc * gelu'(Zin).
 // The K loop runs in a fixed order: results are deterministic.
 // ---------------------------------------------------------------------------------------
@@ -60,25 +61,26 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
             Bs[r][c] = f2bf(v);
         }
         __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < kBK; kk += 16) {
-            const int kb = kk + (lane >> 4) * 4;
-            bf16x4 a[2], b[2];
+        {
+            const int kb = (lane >> 4) * 8;
+            bf16x8 a[2], b[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 const int row = wm + i * 16 + (lane & 15);
-                a[i] = bf16x4{As[row][kb], As[row][kb + 1], As[row][kb + 2], As[row][kb + 3]};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) a[i][e] = __builtin_bit_cast(__bf16, As[row][kb + e]);
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 const int col = wn + j * 16 + (lane & 15);
-                b[j] = bf16x4{Bs[kb][col], Bs[kb + 1][col], Bs[kb + 2][col], Bs[kb + 3][col]};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) b[j][e] = __builtin_bit_cast(__bf16, Bs[kb + e][col]);
             }
 #pragma unroll
             for (int i = 0; i < 2; ++i)
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }

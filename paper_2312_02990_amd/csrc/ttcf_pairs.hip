@@ -39,7 +39,10 @@
 namespace ttcf {
 namespace {
 
-constexpr int kPairThreads = 512;            // workgroup size (256 registers per lane)
+constexpr int kPairThreads = 512;            // largest workgroup (256 registers per lane)
+constexpr int kSmallApt = 4;                 // atoms per thread up to kSmallApt kPairThreads atoms
+constexpr int kLargeApt = 8;                 // atoms per thread of larger systems
+constexpr int kLargeThreads = 512;           // workgroup limit of the kLargeApt build
 constexpr int kJobBytes = 128;               // job slot in front of the per-job LDS
 constexpr int kScanPerTrip = 4;              // list build: candidates per lane per trip
 constexpr int kPfRed = 16;                   // doubles per thread in one block reduction
@@ -130,7 +133,9 @@ __device__ inline PairLds carve_pairs(char* base, int n, int cells) {
 
 // Atoms per thread of a daughter of n atoms (4 up to 2048 atoms, else 8), and the threads that
 // own its atoms: a multiple of 64 up to 512.
-__host__ __device__ inline int job_apt(int n) { return n <= 4 * kPairThreads ? 4 : 8; }
+__host__ __device__ inline int job_apt(int n) {
+    return n <= kSmallApt * kPairThreads ? kSmallApt : kLargeApt;
+}
 __host__ __device__ inline int job_threads(int n) {
     const int per_wave = 64 * job_apt(n);
     return ((n + per_wave - 1) / per_wave) * 64;
@@ -366,9 +371,9 @@ typedef __attribute__((address_space(3))) uint32_t lu32;  // pair words in LDS
 // list build
 // ---------------------------------------------------------------------------------------
 
-// Pairs of this wave's ranks (rank s tests the half neighbourhood after it) into `seg`
-// (capacity seg_cap; gu32* or lu32*). Returns the number found (wave-uniform; may exceed the
-// capacity).
+// Pairs of the 64-rank groups this wave takes (rank s tests the half neighbourhood after it)
+// into `seg` (capacity seg_cap; gu32* or lu32*). Returns the number found (wave-uniform; may
+// exceed the capacity).
 template <int APT, typename P>
 __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, P seg, int seg_cap,
                                             int tj) {
@@ -382,11 +387,16 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, P se
     const float ux = S.fix_unit[0];
     const float rl2u = S.rl2_f / (ux * ux);
     const float ryx = S.fix_unit[1] / ux, rzx = S.fix_unit[2] / ux;
-    const int r0 = (t >> 6) * 64 * APT;
+    // groups of 64 consecutive ranks go to the waves as they ask (a counter in LDS), so that
+    // a wave whose rows were short takes more of them; forces do not depend on which wave
+    // lists a pair
 #pragma unroll 1
-    for (int u = 0; u < APT; ++u) {
-        if (r0 + u * 64 >= n) break;  // wave-uniform
-        const int s = r0 + u * 64 + lane;
+    for (;;) {
+        int grp = 0;
+        if (lane == 0) grp = atomicAdd(&L.scan[0], 1);
+        const int r0 = __builtin_amdgcn_readfirstlane(grp) * 64;
+        if (r0 >= n) break;  // wave-uniform
+        const int s = r0 + lane;
         const bool own = s < n;
         const uint3 qi = *(const uint3*)&L.pos[own ? s : 0];
         const uint32_t cc = L.fcell[own ? s : 0];
@@ -471,12 +481,17 @@ __device__ __forceinline__ int pf_gen_pairs(int n, int cells, uint32_t dxq, P se
                     const float ddx = (float)(int32_t)(qi.x - q[u].x - rsh);
                     const float ddy = (float)(int32_t)(qi.y - q[u].y) * ryx;
                     const float ddz = (float)(int32_t)(qi.z - q[u].z) * rzx;
-                    const bool hit = (v + u < len) & (ddx * ddx + ddy * ddy + ddz * ddz < rl2u);
+                    // one compare against a limit that no square reaches past the row's end,
+                    // so that the ballot is that compare's mask
+                    const float lim = v + u < len ? rl2u : -1.f;
+                    const bool hit = ddx * ddx + ddy * ddy + ddz * ddz < lim;
                     const uint64_t m = __builtin_amdgcn_ballot_w64(hit);
                     const int below = (int)__builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    const int at = base + below;
-                    if (hit && at < seg_cap) seg[at] = wfix | ((uint32_t)k[u] << (14 - shs));
+                    // past the capacity every hit lands in the last slot (the count reports
+                    // the overflow)
+                    const int at = min(base + below, seg_cap - 1);
+                    if (hit) seg[at] = wfix | ((uint32_t)k[u] << (14 - shs));
                     base += (int)__builtin_popcountll(m);
                 }
             }
@@ -582,6 +597,7 @@ __device__ __forceinline__ int pf_rebuild(const SysDev& S, double dxle, uint32_t
         L.fcell[i] = q.w;
         L.pos[i].w = q.x + dxq;
     }
+    if (t == 0) L.scan[0] = 0;  // the list build's group counter (the scan is done with it)
     __syncthreads();
     const int count = pf_gen_pairs<APT>(n, C, dxq, seg, seg_cap, tj);
     const int wave = t >> 6, nwb = T >> 6;
@@ -1145,7 +1161,8 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
 // PL: the pair words of every job live in LDS after its layout (b.lds_bytes covers them),
 // else in the workgroup's slice of b.pairs.
 template <int APT, bool NH, bool OBS, bool COL, bool PL>
-__global__ __launch_bounds__(kPairThreads) void k_daughters_pairs(BatchLaunch b) {
+__global__ __launch_bounds__(APT == kLargeApt ? kLargeThreads : kPairThreads) void k_daughters_pairs(
+    BatchLaunch b) {
     int32_t* job = (int32_t*)pf_smem;
     for (;;) {
         __syncthreads();
@@ -1177,7 +1194,7 @@ __global__ __launch_bounds__(kPairThreads) void k_daughters_pairs(BatchLaunch b)
 // pair words of every wave segment (translated to atom ids by the host), the forces the
 // integrator would use, W_xy, and flags.
 template <int APT>
-__global__ __launch_bounds__(kPairThreads) void k_debug_pair_form(
+__global__ __launch_bounds__(APT == kLargeApt ? kLargeThreads : kPairThreads) void k_debug_pair_form(
     SysDev Sg, double gamma_dot, int64_t kstep, const double* r, int32_t kcap, uint32_t* pairs,
     int32_t* seg_count, int32_t* cell_of, int32_t* rank_of, int32_t* start, double* f,
     double* out) {
@@ -1240,6 +1257,7 @@ __global__ __launch_bounds__(kPairThreads) void k_debug_pair_form(
 
 int pair_job_threads(int n) { return job_threads(n); }
 int pair_job_apt(int n) { return job_apt(n); }
+int pair_small_apt() { return kSmallApt; }
 
 size_t lds_bytes_pairs(int n, int cells) { return kJobBytes + plan_pairs(n, cells).total; }
 
@@ -1256,17 +1274,17 @@ template <bool NH, bool OBS, bool COL>
 static hipError_t launch_pairs_a(const BatchLaunch& b, hipStream_t s) {
     // the atoms per thread of the largest job; every job of the launch runs with it. Pair
     // words in LDS only fit next to systems of four atoms per thread.
-    if (b.apt == 4)
-        return b.pairs_lds ? launch_pairs_t<4, NH, OBS, COL, true>(b, s)
-                           : launch_pairs_t<4, NH, OBS, COL, false>(b, s);
+    if (b.apt == kSmallApt)
+        return b.pairs_lds ? launch_pairs_t<kSmallApt, NH, OBS, COL, true>(b, s)
+                           : launch_pairs_t<kSmallApt, NH, OBS, COL, false>(b, s);
     if (b.pairs_lds) return hipErrorInvalidValue;
-    return launch_pairs_t<8, NH, OBS, COL, false>(b, s);
+    return launch_pairs_t<kLargeApt, NH, OBS, COL, false>(b, s);
 }
 
 hipError_t launch_pairs(const BatchLaunch& b, hipStream_t s) {
     if (b.precision != 1 || (!b.pairs && !b.pairs_lds) || b.threads > kPairThreads ||
         b.threads % 64 != 0 ||
-        (b.apt != 4 && b.apt != 8))
+        (b.apt != kSmallApt && b.apt != kLargeApt))
         return hipErrorInvalidValue;
     // colour-field daughters do not record the extra observables
     if (b.field) {
@@ -1287,15 +1305,16 @@ hipError_t launch_debug_pair_form(const SysDev& S, double gamma_dot, int64_t kst
                                   double* out, hipStream_t s) {
     const int threads = job_threads(S.n);
     const size_t lds = lds_bytes_pairs(S.n, S.lc[0] * S.lc[1] * S.lc[2]);
-    if (job_apt(S.n) == 4) {
-        (void)hipFuncSetAttribute((const void*)k_debug_pair_form<4>,
+    if (job_apt(S.n) == kSmallApt) {
+        (void)hipFuncSetAttribute((const void*)k_debug_pair_form<kSmallApt>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_debug_pair_form<4>, dim3(1), dim3(threads), lds, s, S, gamma_dot,
-                           kstep, r, kcap, pairs, seg_count, cell_of, rank_of, start, f, out);
+        hipLaunchKernelGGL(k_debug_pair_form<kSmallApt>, dim3(1), dim3(threads), lds, s, S,
+                           gamma_dot, kstep, r, kcap, pairs, seg_count, cell_of, rank_of, start, f,
+                           out);
     } else {
-        (void)hipFuncSetAttribute((const void*)k_debug_pair_form<8>,
+        (void)hipFuncSetAttribute((const void*)k_debug_pair_form<kLargeApt>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_debug_pair_form<8>, dim3(1), dim3(threads), lds, s, S, gamma_dot,
+        hipLaunchKernelGGL(k_debug_pair_form<kLargeApt>, dim3(1), dim3(threads), lds, s, S, gamma_dot,
                            kstep, r, kcap, pairs, seg_count, cell_of, rank_of, start, f, out);
     }
     return hipGetLastError();

@@ -240,6 +240,23 @@ __device__ __forceinline__ double rsq_nr(double x) {
     return y;
 }
 
+// le_offset without branches (the same value: the remainder of |v| by L_x is exact whichever
+// of the neighbouring multiples the estimate q lands on, and the fused multiply-adds
+// compute it from q - 1, q or q + 1 exactly); ilx = 1 / L_x.
+__device__ __forceinline__ double le_offset_nb(const SysDev& S, double gamma_dot, int64_t k,
+                                               double ilx) {
+    const double v = gamma_dot * S.box[1] * ((double)k * S.dt);
+    const double lx = S.box[0];
+    const double av = fabs(v);
+    const double q = floor(av * ilx);
+    const double r0 = __builtin_fma(-lx, q, av);
+    const double rm = __builtin_fma(-lx, q - 1.0, av);
+    const double rp = __builtin_fma(-lx, q + 1.0, av);
+    const double r = r0 < 0.0 ? rm : (r0 >= lx ? rp : r0);
+    const double sr = v < 0.0 ? -r : r;
+    return av < lx ? v : sr;
+}
+
 // One DPP move of a double from the lane the control selects (every lane has a source).
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double v) {
@@ -980,11 +997,16 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
         }
     }
 
+    // the offset of the next step, computed a step ahead where its dependent chain overlaps
+    // the kick scalars' chain
+    const double ilx = 1.0 / S.box[0];
+    double dxle_n = le_offset_nb(S, gd, k + 1, ilx);
+    uint32_t dxq_n = fix32(dxle_n, S.fix_scale[0]);
     for (int step = 0; step < todo; ++step) {
         // ---- streaming D(h), new strain, sliding-brick wrap (crossings counted), path length
         k += 1;
-        dxle = le_offset(S, gd, k);
-        dxq = fix32(dxle, S.fix_scale[0]);
+        dxle = dxle_n;
+        dxq = dxq_n;
         const double lx = S.box[0], ly = S.box[1], lz = S.box[2];
         bool out = false;
 #pragma unroll
@@ -1120,6 +1142,8 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
             break;
         }
         // ---- the next step's first half, applied together with this second half
+        dxle_n = le_offset_nb(S, gd, k + 1, ilx);
+        dxq_n = fix32(dxle_n, S.fix_scale[0]);
         double e, g, hh;
         first_half(e, g, hh);
         const double K1 = e * A, K2 = e * C + g * A, K3 = e * B + hh, K4 = e * D + g * B;

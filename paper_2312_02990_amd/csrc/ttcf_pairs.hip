@@ -1008,7 +1008,6 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
         dxle = dxle_n;
         dxq = dxq_n;
         const double lx = S.box[0], ly = S.box[1], lz = S.box[2];
-        bool out = false;
 #pragma unroll
         for (int j = 0; j < APT; ++j) {
             const double vx = px[j] + tg * py[j];
@@ -1018,16 +1017,17 @@ __device__ void run_daughter_pairs(DaughterDesc* dsc, int steps_cap, const PairL
             x[j] += h * px[j] + h * gd * (y[j] + tau * py[j]);
             y[j] += h * py[j];
             z[j] += h * pz[j];
-            out |= (x[j] < 0.0) | (x[j] >= lx) | (y[j] < 0.0) | (y[j] >= ly) | (z[j] < 0.0) |
-                   (z[j] >= lz);
         }
-        // sliding-brick wrap, only in a wave where an atom left the box (a few percent of the
-        // steps): a step moves an atom far less than a box edge, so each axis needs at most
-        // one image shift (the same operations as wrap_le in that case); a y crossing shifts
-        // x by -+ the offset
-        if (__builtin_amdgcn_ballot_w64(out) != 0) {
+        // sliding-brick wrap of the atoms of slot j, only in a wave where one of them left the
+        // box (a few percent of the steps, and one slot at a time, so that the waves reach the
+        // next barrier together): a step moves an atom far less than a box edge, so each axis
+        // needs at most one image shift (the same operations as wrap_le in that case); a y
+        // crossing shifts x by -+ the offset
 #pragma unroll
-            for (int j = 0; j < APT; ++j) {
+        for (int j = 0; j < APT; ++j) {
+            const bool out = (x[j] < 0.0) | (x[j] >= lx) | (y[j] < 0.0) | (y[j] >= ly) |
+                             (z[j] < 0.0) | (z[j] >= lz);
+            if (__builtin_amdgcn_ballot_w64(out) != 0) {
                 const bool up = y[j] >= ly, dn = y[j] < 0.0;
                 cr[j] += up ? 1 : (dn ? -1 : 0);
                 y[j] += up ? -ly : (dn ? ly : 0.0);

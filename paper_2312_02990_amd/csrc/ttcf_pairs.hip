@@ -44,7 +44,7 @@ constexpr int kSmallApt = 4;                 // atoms per thread up to kSmallApt
 constexpr int kLargeApt = 8;                 // atoms per thread of larger systems
 constexpr int kLargeThreads = 512;           // workgroup limit of the kLargeApt build
 constexpr int kJobBytes = 128;               // job slot in front of the per-job LDS
-constexpr int kScanPerTrip = 4;              // list build: candidates per lane per trip
+constexpr int kScanPerTrip = 3;              // list build: candidates per lane per trip
 constexpr int kPfRed = 16;                   // doubles per thread in one block reduction
 constexpr float kForceUnits = 524288.0f;     // 2^19 fixed-point units per force unit
 constexpr float kForceStep = 1.0f / 524288.0f;

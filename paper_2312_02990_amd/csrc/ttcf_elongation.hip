@@ -33,8 +33,11 @@ namespace {
 
 constexpr int kPefApt = 2;  // atoms per thread
 
+constexpr int kPefMaxHits = 24;  // pairs within r_c per atom held between the two passes
+constexpr int kPefScan = 3;      // candidates per lane per trip of the first pass
+
 struct PefPlan {
-    size_t sx, sy, sz, red, start, cnt, ws, sid, total;
+    size_t sx, sy, sz, red, start, cnt, ws, sid, hits, total;
 };
 
 __host__ __device__ inline size_t pef_align(size_t v) { return (v + 15) & ~(size_t)15; }
@@ -58,6 +61,8 @@ __host__ __device__ inline PefPlan pef_plan(int nmax, int cmax) {
     o = pef_align(o + sizeof(int32_t) * (size_t)kMaxWaves);
     p.sid = o;
     o = pef_align(o + sizeof(uint16_t) * (size_t)nmax);
+    p.hits = o;
+    o = pef_align(o + sizeof(uint16_t) * (size_t)kPefMaxHits * kMaxThreads);
     p.total = o;
     return p;
 }
@@ -69,6 +74,7 @@ struct PefShared {
     int32_t* cnt;          // [cells] counts, then placement cursors
     int32_t* ws;           // [waves] scan scratch
     uint16_t* sid;         // [nmax] atom ids sorted by (cell, id)
+    uint16_t* hits;        // [kPefMaxHits][threads] each lane's pairs within r_c (row, range, id)
 };
 
 // Sum of K doubles over the workgroup, the same total in every thread. Fixed order: an xor
@@ -135,6 +141,105 @@ __device__ __forceinline__ double pef_recip(double x) {
     r = __builtin_fma(r, e, r);
     e = __builtin_fma(-x, r, 1.0);
     return __builtin_fma(r, e, r);
+}
+
+// Force on atom i in two passes over the 27-cell stencil of the current cell list. Pass 1
+// runs its nine rows (dz, dy), each the rank range of the row's three x cells (two ranges
+// where the row wraps in x), kPefScan candidates per lane per trip, and keeps the members
+// within r_c in the lane's hit list as (row, range, atom id); pass 2 evaluates the listed
+// pairs with every lane busy until the longest list is done, so the force arithmetic runs
+// once per pair rather than once per candidate slot of the wave. Members keep the fixed
+// (row, rank) order, so each force and virial sum has a fixed order. A stencil cell across
+// the box edge is the image shifted by one box length (see pef_atom_force). SEP(ax, ay, az,
+// m, d) sets the separation d of atom i at fractional (ax, ay, az) from member m; ACC(fs, d)
+// adds a pair with force factor fs. A list longer than kPefMaxHits makes the force NaN
+// (the daughter then fails its health check).
+template <class SEP, class ACC>
+__device__ __forceinline__ void pef_rows_force(const PefShared& S, int i, int ncx, int ncy,
+                                               int ncz, double rc2, double ca, double& fx,
+                                               double& fy, double& fz, SEP sep, ACC acc) {
+    const int T = blockDim.x, t = threadIdx.x;
+    const bool own = i >= 0;
+    const double six = own ? S.sx[i] : 0.0, siy = own ? S.sy[i] : 0.0, siz = own ? S.sz[i] : 0.0;
+    const int cx = pef_cell(six, ncx), cy = pef_cell(siy, ncy), cz = pef_cell(siz, ncz);
+    // the second range of a row wrapping in x: cell ncx - 1 at +1 (cx = 0) or cell 0 at -1
+    const double shx1 = cx == 0 ? 1.0 : -1.0;
+    // image shifts of row r in y and z, and the first rank of its cell row
+    auto row = [&](int r, double& shy, double& shz, int& rowb) {
+        const int dz = r / 3 - 1, dy = r % 3 - 1;
+        int zz = cz + dz, yy = cy + dy;
+        shz = zz < 0 ? 1.0 : (zz >= ncz ? -1.0 : 0.0);
+        zz += zz < 0 ? ncz : (zz >= ncz ? -ncz : 0);
+        shy = yy < 0 ? 1.0 : (yy >= ncy ? -1.0 : 0.0);
+        yy += yy < 0 ? ncy : (yy >= ncy ? -ncy : 0);
+        rowb = ncx * (yy + ncy * zz);
+    };
+    int nh = 0;
+#pragma unroll 1
+    for (int r = 0; r < 9; ++r) {
+        double shy, shz;
+        int rowb;
+        row(r, shy, shz, rowb);
+        int lo0, hi0, lo1 = 0, hi1 = 0;
+        if (cx >= 1 && cx <= ncx - 2) {
+            lo0 = S.start[rowb + cx - 1];
+            hi0 = S.start[rowb + cx + 2];
+        } else if (cx == 0) {
+            lo0 = S.start[rowb];
+            hi0 = S.start[rowb + 2];
+            lo1 = S.start[rowb + ncx - 1];
+            hi1 = S.start[rowb + ncx];
+        } else {
+            lo0 = S.start[rowb + ncx - 2];
+            hi0 = S.start[rowb + ncx];
+            lo1 = S.start[rowb];
+            hi1 = S.start[rowb + 1];
+        }
+        const int len0 = own ? hi0 - lo0 : 0;
+        const int len = len0 + (own ? hi1 - lo1 : 0);
+        const int off1 = lo1 - len0;
+        const double ay = siy + shy, az = siz + shz;
+        for (int v = 0; __builtin_amdgcn_ballot_w64(v < len) != 0; v += kPefScan) {
+            int m[kPefScan];
+#pragma unroll
+            for (int u = 0; u < kPefScan; ++u) {
+                const int vv = v + u;
+                m[u] = S.sid[vv < len ? vv + (vv < len0 ? lo0 : off1) : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < kPefScan; ++u) {
+                const int vv = v + u;
+                const bool r1 = vv >= len0;
+                double d[3];
+                sep(six + (r1 ? shx1 : 0.0), ay, az, m[u], d);
+                const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                if ((vv < len) & (m[u] != i) & (r2 < rc2)) {
+                    if (nh < kPefMaxHits)
+                        S.hits[nh * T + t] = (uint16_t)((r << 12) | ((r1 ? 1 : 0) << 11) | m[u]);
+                    ++nh;
+                }
+            }
+        }
+    }
+    for (int k = 0; __builtin_amdgcn_ballot_w64(k < nh) != 0; ++k) {
+        if (k < nh && k < kPefMaxHits) {
+            const uint32_t e = S.hits[k * T + t];
+            double shy, shz;
+            int rowb;
+            row((int)(e >> 12), shy, shz, rowb);
+            double d[3];
+            sep(six + ((e >> 11) & 1u ? shx1 : 0.0), siy + shy, siz + shz, (int)(e & 0x7FFu), d);
+            const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            const double inv = pef_recip(r2);
+            const double s3 = inv * inv * inv;
+            const double fs = (48.0 * s3 * s3 - 24.0 * ca * s3) * inv;
+            fx += fs * d[0];
+            fy += fs * d[1];
+            fz += fs * d[2];
+            acc(fs, d);
+        }
+    }
+    if (nh > kPefMaxHits) fx = __builtin_nan("");
 }
 
 // Force on atom i from the 27-cell stencil of the current cell list (cells in a fixed
@@ -287,10 +392,18 @@ __device__ void pef_forces(const PefShared& S, int n, int ncx, int ncy, int ncz,
     const int T = blockDim.x, t = threadIdx.x;
     pef_build_cells(S, n, ncx, ncy, ncz);
     w = 0.0;
+    auto sep = [&](double ax, double ay, double az, int m, double (&d)[3]) {
+        d[0] = (ax - S.sx[m]) * lx;
+        d[1] = (ay - S.sy[m]) * ly;
+        d[2] = (az - S.sz[m]) * lz;
+    };
+    auto acc = [&](double fs, const double (&d)[3]) {
+        w += 0.5 * (fs * (d[0] * d[0] - d[1] * d[1]));
+    };
     for (int j = 0; j < kPefApt; ++j) {
         const int i = t + j * T;
         double ax = 0.0, ay = 0.0, az = 0.0;
-        if (i < n) pef_atom_force(S, i, ncx, ncy, ncz, lx, ly, lz, rc2, ca, ax, ay, az, w);
+        pef_rows_force(S, i < n ? i : -1, ncx, ncy, ncz, rc2, ca, ax, ay, az, sep, acc);
         fx[j] = ax;
         fy[j] = ay;
         fz[j] = az;
@@ -313,6 +426,7 @@ __global__ void __launch_bounds__(1024) k_daughters_pef(PefLaunch L) {
     S.cnt = (int32_t*)(smem + plan.cnt);
     S.ws = (int32_t*)(smem + plan.ws);
     S.sid = (uint16_t*)(smem + plan.sid);
+    S.hits = (uint16_t*)(smem + plan.hits);
 
     DaughterDesc* dp = L.descs + L.order[blockIdx.x];
     const int T = blockDim.x, t = threadIdx.x;
@@ -671,10 +785,20 @@ __device__ void mix_forces(const PefShared& S, int n, int ncz, const MixCell& H,
     pef_build_cells(S, n, H.ncx, H.ncy, ncz);
     wn = 0.0;
     wxy = 0.0;
+    auto sep = [&](double ax, double ay, double az, int m, double (&d)[3]) {
+        const double fsx = ax - S.sx[m], fsy = ay - S.sy[m];
+        d[0] = fsx * H.hxx + fsy * H.hxy;
+        d[1] = fsy * H.hyy;
+        d[2] = (az - S.sz[m]) * lz;
+    };
+    auto acc = [&](double fs, const double (&d)[3]) {
+        wn += 0.5 * (fs * (d[0] * d[0] - d[1] * d[1]));
+        wxy += 0.5 * (fs * (d[0] * d[1]));
+    };
     for (int j = 0; j < kPefApt; ++j) {
         const int i = t + j * T;
         double ax = 0.0, ay = 0.0, az = 0.0;
-        if (i < n) mix_atom_force(S, i, H.ncx, H.ncy, ncz, H, lz, rc2, ca, ax, ay, az, wn, wxy);
+        pef_rows_force(S, i < n ? i : -1, H.ncx, H.ncy, ncz, rc2, ca, ax, ay, az, sep, acc);
         fx[j] = ax;
         fy[j] = ay;
         fz[j] = az;
@@ -696,6 +820,7 @@ __global__ void __launch_bounds__(1024) k_daughters_mix(PefLaunch L) {
     S.cnt = (int32_t*)(smem + plan.cnt);
     S.ws = (int32_t*)(smem + plan.ws);
     S.sid = (uint16_t*)(smem + plan.sid);
+    S.hits = (uint16_t*)(smem + plan.hits);
 
     DaughterDesc* dp = L.descs + L.order[blockIdx.x];
     const int T = blockDim.x, t = threadIdx.x;

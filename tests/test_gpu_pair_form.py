@@ -8,7 +8,7 @@ oracle, on liquid configurations of N = 256, 2048 and 4000 at Lees-Edwards offse
   * the offset the kernel used equals the oracle's fmod(gamma_dot L_y k dt, L_x) bit for bit;
   * the listed pairs closer than r_c are exactly the oracle's pair set; every oracle pair
     closer than r_list - eps is listed, and none farther than r_list + eps (eps covers the
-    FP32 fixed-point separation);
+    FP32 fixed-point separation), in cubic boxes and in one whose sides differ;
   * forces within max_i |dF_i| / rms_i |F_i| <= 1e-5 of the oracle's, W_xy within 1e-5 of
     the sum of |x_ij F_y,ij|, and the total force zero;
   * forces and W_xy do not depend on the skin or the pair capacity (bit for bit);
@@ -89,46 +89,66 @@ def test_list_grid_cells_and_order_bit_exact(T, orc, states, name):
         assert not out["overflow"] and not out["close"]
 
 
+def check_pairs_and_forces(T, orc, s, box, r, gd, k, lbox):
+    """The pair and force checks of the module docstring for one configuration in the box
+    lbox = (L_x, L_y, L_z); returns the listed pair count."""
+    sysd = T.make_system(s.n, lbox, s.temperature, s.dt, precision=1)
+    rr = r.reshape(3, s.n)
+    out = T.ttcf_debug_pair_form(sysd, r, gd, k)
+    dxle, rl = out["dxle"], out["rlist"]
+    gpu = set(zip(out["pairs"][0].tolist(), out["pairs"][1].tolist()))
+    assert len(gpu) == len(out["pairs"][0])  # every pair listed once
+    # oracle FP64 distance of every GPU pair
+    pi, pj = np.array(sorted(gpu)).T
+    dx = rr[:, pi] - rr[:, pj]
+    ny = np.rint(dx[1] / lbox[1])
+    dx[1] -= ny * lbox[1]
+    dx[0] -= ny * dxle
+    dx[0] -= lbox[0] * np.rint(dx[0] / lbox[0])
+    dx[2] -= lbox[2] * np.rint(dx[2] / lbox[2])
+    dist = np.sqrt((dx * dx).sum(0))
+    eps = 1e-5 * rl
+    assert dist.max() < rl + eps
+    # inside the cutoff: exactly the oracle's pair set
+    inside = {(a, b) for a, b, q in zip(pi.tolist(), pj.tolist(), dist) if q < box.rc}
+    oi, oj = orc.pairs(box, r, dxle, box.rc)
+    assert inside == set(zip(oi.tolist(), oj.tolist()))
+    # every oracle pair within r_list - eps is listed
+    vi, vj = orc.pairs(box, r, dxle, rl - eps)
+    assert set(zip(vi.tolist(), vj.tolist())) <= gpu
+    # forces and virial
+    fo, _, wo, _ = orc.forces(box, r, dxle)
+    fg = out["f"]
+    rms = np.sqrt((fo * fo).sum(0).mean())
+    err = np.sqrt(((fg - fo) ** 2).sum(0)).max() / rms
+    say(f"   {len(gpu)} pairs, force error {err:.2e} of rms {rms:.2f}, "
+        f"W {out['w_xy']:.6f} vs {wo:.6f}")
+    assert err <= 1e-5
+    wscale = np.abs(fo).sum() * box.rc
+    assert abs(out["w_xy"] - wo) <= 1e-5 * wscale
+    assert np.abs(fg.sum(axis=1)).max() <= 1e-6 * np.abs(fg).sum()
+    return len(gpu)
+
+
 @pytest.mark.parametrize("name", ["n256", "n2048", "n4000"])
 def test_pairs_and_forces_match_oracle(T, orc, states, name):
     for gd, k in offsets(states[name, 0.0, 0][0]):
         s, box, r = states[name, gd, k]
-        sysd = T.make_system(s.n, s.box, s.temperature, s.dt, precision=1)
-        rr = r.reshape(3, s.n)
         say(f"{name} pairs/forces at gamma_dot={gd}, k={k}")
-        out = T.ttcf_debug_pair_form(sysd, r, gd, k)
-        dxle, rl = out["dxle"], out["rlist"]
-        gpu = set(zip(out["pairs"][0].tolist(), out["pairs"][1].tolist()))
-        assert len(gpu) == len(out["pairs"][0])  # every pair listed once
-        # oracle FP64 distance of every GPU pair
-        pi, pj = np.array(sorted(gpu)).T
-        dx = rr[:, pi] - rr[:, pj]
-        ny = np.rint(dx[1] / s.box)
-        dx[1] -= ny * s.box
-        dx[0] -= ny * dxle
-        dx[0] -= s.box * np.rint(dx[0] / s.box)
-        dx[2] -= s.box * np.rint(dx[2] / s.box)
-        dist = np.sqrt((dx * dx).sum(0))
-        eps = 1e-5 * rl
-        assert dist.max() < rl + eps
-        # inside the cutoff: exactly the oracle's pair set
-        inside = {(a, b) for a, b, q in zip(pi.tolist(), pj.tolist(), dist) if q < box.rc}
-        oi, oj = orc.pairs(box, r, dxle, box.rc)
-        assert inside == set(zip(oi.tolist(), oj.tolist()))
-        # every oracle pair within r_list - eps is listed
-        vi, vj = orc.pairs(box, r, dxle, rl - eps)
-        assert set(zip(vi.tolist(), vj.tolist())) <= gpu
-        # forces and virial
-        fo, _, wo, _ = orc.forces(box, r, dxle)
-        fg = out["f"]
-        rms = np.sqrt((fo * fo).sum(0).mean())
-        err = np.sqrt(((fg - fo) ** 2).sum(0)).max() / rms
-        say(f"   {len(gpu)} pairs, force error {err:.2e} of rms {rms:.2f}, "
-            f"W {out['w_xy']:.6f} vs {wo:.6f}")
-        assert err <= 1e-5
-        wscale = np.abs(fo).sum() * box.rc
-        assert abs(out["w_xy"] - wo) <= 1e-5 * wscale
-        assert np.abs(fg.sum(axis=1)).max() <= 1e-6 * np.abs(fg).sum()
+        check_pairs_and_forces(T, orc, s, box, r, gd, k, (s.box,) * 3)
+
+
+def test_pairs_and_forces_in_a_non_cubic_box(T, orc, states):
+    """Fixed-point units that differ by axis: the N = 2048 configurations stretched by 1.05
+    in x and y (so that the image offset, which scales with L_y and wraps at L_x,
+    still matches the stretched positions; no pair comes closer), checked as above."""
+    for gd, k in offsets(states["n2048", 0.0, 0][0]):
+        s, _, r = states["n2048", gd, k]
+        lbox = (s.box * 1.05, s.box * 1.05, s.box)
+        rs = r.reshape(3, s.n) * np.array(lbox)[:, None] / s.box
+        box = orc.make_box(s.n, lbox)
+        say(f"n2048 non-cubic pairs/forces at gamma_dot={gd}, k={k}")
+        check_pairs_and_forces(T, orc, s, box, np.ascontiguousarray(rs).ravel(), gd, k, lbox)
 
 
 def test_forces_do_not_depend_on_skin_or_capacity(T, states):

@@ -706,16 +706,44 @@ __device__ __forceinline__ void neumaier_add(double& sum, double& comp, double v
 
 constexpr int kMaxMaps = 4;
 
-__global__ void k_accumulate(AccumLaunch a) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.n_groups) return;
+// s + e = a + b exactly (Knuth's branch-free two-sum)
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+    s = a + b;
+    const double bp = s - a;
+    e = (a - (s - bp)) + (b - bp);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave, compensated: on return s + c is the sum
+// of the lane's and all lower lanes' v, each partial carried as a two-sum pair (a fixed
+// combination order, so the result does not depend on timing).
+__device__ __forceinline__ void wave_scan_comp(double v, double& s, double& c) {
+    const int lane = threadIdx.x & 63;
+    s = v;
+    c = 0.0;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const double ls = __shfl_up(s, d, 64), lc = __shfl_up(c, d, 64);
+        if (lane >= d) {
+            double t, e;
+            two_sum(ls, s, t, e);
+            s = t;
+            c = lc + c + e;
+        }
+    }
+}
+
+// One wave per group; its lanes take 64 consecutive time points at a time. The trapezoid
+// terms of int_0^t P(0) P(s) ds are summed by a compensated prefix scan over the lanes, with
+// the total so far carried from one block of 64 points to the next.
+__global__ __launch_bounds__(64) void k_accumulate(AccumLaunch a) {
+    const int g = blockIdx.x, lane = threadIdx.x;
     const int b = a.first_of[g], e = a.first_of[g + 1];
     // output row of this group
     const size_t row = (size_t)g + (a.row_step ? (size_t)(*a.row_step) * (size_t)a.n_groups : 0);
     const size_t stride = a.row_stride > 0 ? (size_t)a.row_stride : (size_t)a.n_t;
     const int nm = min(e - b, kMaxMaps);
     int health = 0;
-    double p0[kMaxMaps], sum[kMaxMaps], comp[kMaxMaps], prev[kMaxMaps];
+    double p0[kMaxMaps], cs[kMaxMaps], cc[kMaxMaps];
     const double* ser[kMaxMaps];
     double inv_v = 1.0, dt = 0.0;
     for (int m = 0; m < nm; ++m) {
@@ -725,19 +753,20 @@ __global__ void k_accumulate(AccumLaunch a) {
         inv_v = 1.0 / d.sys.volume;
         dt = d.sys.dt;
         p0[m] = d.series[0] * inv_v;
-        prev[m] = p0[m];
-        sum[m] = 0.0;
-        comp[m] = 0.0;
+        cs[m] = 0.0;
+        cc[m] = 0.0;
     }
-    a.health_out[row] = health;
-    a.gamma_out[row] = a.descs[b].gamma_dot;
+    if (lane == 0) {
+        a.health_out[row] = health;
+        a.gamma_out[row] = a.descs[b].gamma_dot;
+    }
     const double inm = 1.0 / (double)nm;
     double* dout = a.d_out + row * stride;
     double* iout = a.i_out + row * stride;
     if (a.h_out) {
         // mapping mean of the learned control variate (0 where a daughter has none)
         double* hout = a.h_out + row * stride;
-        for (int k = 0; k < a.n_t; ++k) {
+        for (int k = lane; k < a.n_t; k += 64) {
             double hs = 0.0;
             for (int m = 0; m < nm; ++m) {
                 const double* hh = a.descs[b + m].hseries;
@@ -746,23 +775,29 @@ __global__ void k_accumulate(AccumLaunch a) {
             hout[k] = hs * inm;
         }
     }
-    {
-        double dsum = 0.0;
-        for (int m = 0; m < nm; ++m) dsum += p0[m];
-        dout[0] = dsum * inm;
-        iout[0] = 0.0;
-    }
-    for (int k = 1; k < a.n_t; ++k) {
+    for (int k0 = 0; k0 < a.n_t; k0 += 64) {
+        const int k = k0 + lane;
+        const bool live = k < a.n_t;
         double dsum = 0.0, isum = 0.0;
         for (int m = 0; m < nm; ++m) {
-            const double cur = ser[m][k] * inv_v;
-            neumaier_add(sum[m], comp[m], 0.5 * dt * (p0[m] * prev[m] + p0[m] * cur));
-            prev[m] = cur;
+            const double cur = live ? ser[m][k] * inv_v : 0.0;
+            const double prev = live && k > 0 ? ser[m][k - 1] * inv_v : 0.0;
+            // the trapezoid over [t_{k-1}, t_k] (none at k = 0)
+            const double term = live && k > 0 ? 0.5 * dt * (p0[m] * prev + p0[m] * cur) : 0.0;
+            double s, c;
+            wave_scan_comp(term, s, c);
+            double t, err;
+            two_sum(cs[m], s, t, err);
+            const double tc = cc[m] + c + err;
             dsum += cur;
-            isum += sum[m] + comp[m];
+            isum += t + tc;
+            cs[m] = __shfl(t, 63, 64);
+            cc[m] = __shfl(tc, 63, 64);
         }
-        dout[k] = dsum * inm;
-        iout[k] = isum * inm;
+        if (live) {
+            dout[k] = dsum * inm;
+            iout[k] = isum * inm;
+        }
     }
 }
 
@@ -770,50 +805,86 @@ __global__ void k_accumulate(AccumLaunch a) {
 // response: mean and block standard error over the selected groups, per time point
 // ---------------------------------------------------------------------------------------
 // G_n(t) = D_n(0) - coef_n I_n(t), coef_n = V gamma_n / T, is the start state's TTCF estimate
-// (Eq. TTCF with Omega(0) = -(V/T) gamma_n P_xy(0)); D_n(t) its direct average. Two passes (mean, then the
-// squared deviations), each a compensated sum in a fixed row order.
-__global__ void k_response(ResponseLaunch r) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= r.n_t) return;
+// (Eq. TTCF with Omega(0) = -(V/T) gamma_n P_xy(0)); D_n(t) its direct average. Two passes
+// (mean, then the squared deviations). A workgroup takes 64 time points, one per lane; its
+// kRespWaves waves split the rows (wave w takes rows w, w + kRespWaves, ...), each a
+// compensated sum, and the wave partials are combined in wave order: a fixed order.
+constexpr int kRespWaves = 16;
+
+__device__ __forceinline__ void resp_values(const ResponseLaunch& r, int row, int k,
+                                            double beta, double& g, double& dv) {
+    const double* dser = r.d_all + (size_t)row * r.n_t_stride;
+    const double* iser = r.i_all + (size_t)row * r.n_t_stride;
+    g = dser[0] - r.coef[row] * iser[k];
+    if (r.h_all) g -= beta * r.h_all[(size_t)row * r.n_t_stride + k];
+    dv = dser[k];
+    if (r.normalise) {
+        const double gam = r.gamma[row];
+        g /= gam;
+        dv /= gam;
+    }
+}
+
+// the block-wide compensated sums of two per-thread (sum, comp) pairs, per lane, in wave
+// order; every thread receives its lane's totals
+__device__ __forceinline__ void resp_combine(double (*part)[kRespWaves][64], double& a_s,
+                                             double& a_c, double& b_s, double& b_c) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    part[0][w][lane] = a_s;
+    part[1][w][lane] = a_c;
+    part[2][w][lane] = b_s;
+    part[3][w][lane] = b_c;
+    __syncthreads();
+    double as = 0, ac = 0, bs = 0, bc = 0;
+    for (int v = 0; v < kRespWaves; ++v) {
+        neumaier_add(as, ac, part[0][v][lane]);
+        neumaier_add(as, ac, part[1][v][lane]);
+        neumaier_add(bs, bc, part[2][v][lane]);
+        neumaier_add(bs, bc, part[3][v][lane]);
+    }
+    __syncthreads();  // the partials may be overwritten after this
+    a_s = as;
+    a_c = ac;
+    b_s = bs;
+    b_c = bc;
+}
+
+__global__ __launch_bounds__(64 * kRespWaves) void k_response(ResponseLaunch r) {
+    __shared__ double part[4][kRespWaves][64];
+    __shared__ int cnt[kRespWaves];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int k0 = blockIdx.x * 64 + lane;
+    const bool live = k0 < r.n_t;
+    const int k = live ? k0 : 0;
     double gs = 0, gc = 0, ds = 0, dc = 0;
     int used = 0;
     const double beta = r.beta ? r.beta[k] : 1.0;
-    for (int i = 0; i < r.n_rows; ++i) {
+    for (int i = w; i < r.n_rows; i += kRespWaves) {
         const int row = r.rows[i];
         if (r.health[row] != 0) continue;
-        const double* dser = r.d_all + (size_t)row * r.n_t_stride;
-        const double* iser = r.i_all + (size_t)row * r.n_t_stride;
-        const double gam = r.gamma[row];
-        double g = dser[0] - r.coef[row] * iser[k];
-        if (r.h_all) g -= beta * r.h_all[(size_t)row * r.n_t_stride + k];
-        double dv = dser[k];
-        if (r.normalise) {
-            g /= gam;
-            dv /= gam;
-        }
+        double g, dv;
+        resp_values(r, row, k, beta, g, dv);
         neumaier_add(gs, gc, g);
         neumaier_add(ds, dc, dv);
         ++used;
     }
+    if (lane == 0) cnt[w] = used;
+    resp_combine(part, gs, gc, ds, dc);  // (its first barrier also publishes cnt)
+    used = 0;
+    for (int v = 0; v < kRespWaves; ++v) used += cnt[v];
     const double gm = (gs + gc) / (double)used;
     const double dm = (ds + dc) / (double)used;
     double gv = 0, gvc = 0, dvv = 0, dvc = 0;
-    for (int i = 0; i < r.n_rows; ++i) {
+    for (int i = w; i < r.n_rows; i += kRespWaves) {
         const int row = r.rows[i];
         if (r.health[row] != 0) continue;
-        const double* dser = r.d_all + (size_t)row * r.n_t_stride;
-        const double* iser = r.i_all + (size_t)row * r.n_t_stride;
-        const double gam = r.gamma[row];
-        double g = dser[0] - r.coef[row] * iser[k];
-        if (r.h_all) g -= beta * r.h_all[(size_t)row * r.n_t_stride + k];
-        double dv = dser[k];
-        if (r.normalise) {
-            g /= gam;
-            dv /= gam;
-        }
+        double g, dv;
+        resp_values(r, row, k, beta, g, dv);
         neumaier_add(gv, gvc, (g - gm) * (g - gm));
         neumaier_add(dvv, dvc, (dv - dm) * (dv - dm));
     }
+    resp_combine(part, gv, gvc, dvv, dvc);
+    if (w != 0 || !live) return;
     const double denom = used > 1 ? (double)(used - 1) * (double)used : 1.0;
     r.out[k] = gm + (r.mu_h ? beta * r.mu_h[k] : 0.0);
     r.out[r.n_t + k] = used > 1 ? sqrt((gv + gvc) / denom) : 0.0;
@@ -1192,7 +1263,7 @@ hipError_t launch_replicate(const double* src, const double* zsrc, int32_t n, co
 
 hipError_t launch_accumulate(const AccumLaunch& a, hipStream_t s) {
     if (a.n_groups <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_accumulate, dim3((a.n_groups + 63) / 64), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_accumulate, dim3(a.n_groups), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1295,7 +1366,7 @@ hipError_t launch_increment(int32_t* counter, hipStream_t s) {
 }
 
 hipError_t launch_response(const ResponseLaunch& r, hipStream_t s) {
-    hipLaunchKernelGGL(k_response, dim3((r.n_t + 63) / 64), dim3(64), 0, s, r);
+    hipLaunchKernelGGL(k_response, dim3((r.n_t + 63) / 64), dim3(64 * kRespWaves), 0, s, r);
     return hipGetLastError();
 }
 

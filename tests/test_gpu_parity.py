@@ -467,6 +467,52 @@ def test_response_filters_and_normalisation(T, orc, cfg1):
     assert c[4] == 16
 
 
+def test_accumulate_and_response_on_the_gpu_series(T, orc, cfg1):
+    """The accumulator (per group, a compensated prefix scan of the trapezoid terms over
+    blocks of 64 time points) and the response kernels, applied to the GPU's own exported
+    daughter series, against the oracle's estimator on those series: 201 time points (three
+    full blocks and a ragged tail), two shear rates, the per-rate filters and the
+    per-unit-rate normalisation, to rounding (1e-12 of the per-state scale for the means,
+    1e-9 relative for the block standard errors)."""
+    s, box, sr, sp = cfg1
+    nst = 200
+    say("accumulate/response on the GPU's own series")
+    with T.Context() as ctx:
+        mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
+        ctx.ttcf_import_states(mid, sr, sp)
+        fa = ctx.ttcf_spawn_daughters(mid, 8, 0, 1e-2, nst)
+        fb = ctx.ttcf_spawn_daughters(mid, 8, 0, 0.5, nst)
+        ctx.ttcf_step(nst)
+        sa = ctx.ttcf_export_series(fa, 32, nst + 1)
+        sb = ctx.ttcf_export_series(fb, 32, nst + 1)
+        assert ctx.ttcf_accumulate() == 16
+        ra = ctx.ttcf_response(nst + 1, 1e-2)
+        rb = ctx.ttcf_response(nst + 1, 0.5)
+        rn = ctx.ttcf_response(nst + 1, 0.0)
+    refs = []
+    for got, ser, gd in ((ra, sa, 1e-2), (rb, sb, 0.5)):
+        ref = orc.ttcf_response(ser / s.volume, ser[:, 0], np.full(32, gd), s.temperature, s.dt)
+        refs.append((ref, gd))
+        assert got[4] == 8
+        sc = np.abs(ref.g).max()
+        assert np.abs(got[0] - ref.ttcf).max() <= 1e-12 * sc
+        assert np.abs(got[2] - ref.dav).max() <= 1e-12 * np.abs(ref.d).max()
+        np.testing.assert_allclose(got[1], ref.ttcf_se, rtol=1e-9, atol=1e-14 * sc)
+        np.testing.assert_allclose(got[3], ref.dav_se, rtol=1e-9,
+                                   atol=1e-14 * np.abs(ref.d).max())
+    # per unit rate: the 16 groups, each divided by its own rate
+    g = np.concatenate([ref.g / gd for ref, gd in refs])
+    d = np.concatenate([ref.d / gd for ref, gd in refs])
+    assert rn[4] == 16
+    sq = np.sqrt(16)
+    assert np.abs(rn[0] - g.mean(axis=0)).max() <= 1e-12 * np.abs(g).max()
+    assert np.abs(rn[2] - d.mean(axis=0)).max() <= 1e-12 * np.abs(d).max()
+    np.testing.assert_allclose(rn[1], g.std(axis=0, ddof=1) / sq, rtol=1e-9,
+                               atol=1e-14 * np.abs(g).max())
+    np.testing.assert_allclose(rn[3], d.std(axis=0, ddof=1) / sq, rtol=1e-9,
+                               atol=1e-14 * np.abs(d).max())
+
+
 def test_health_check_excludes_whole_group(T, orc, cfg1):
     s, box, sr, sp = cfg1
     nst = 20

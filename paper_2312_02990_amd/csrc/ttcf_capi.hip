@@ -3146,7 +3146,7 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
         return fail(c, TTCF_EINVAL, "the mean term already holds samples at another shear rate");
     Mother& m = c->mothers[mother];
     const int n = m.dev.n, O = c->cv_out;
-    if (lds_bytes_cv_features(n) > c->max_lds)
+    if (lds_bytes_cv_features_maps(n) > c->max_lds)
         return fail(c, TTCF_EINVAL, "system too large for the control-variate features");
     const int64_t per_round = (int64_t)n_replicas * states_per_replica;
     if (per_round * 4 > (1 << 22)) return fail(c, TTCF_EINVAL, "too many samples per round");
@@ -3158,17 +3158,11 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
     float* feat = sc.get<float>((size_t)rows * kCvIn);
     double* b0 = sc.get<double>(2 * (size_t)rows);
     double* hh = sc.get<double>((size_t)rows * (O + 1));
-    int32_t* idx = sc.get<int32_t>(2 * (size_t)rows);
     double* sgn = sc.get<double>(4);
-    if (!snaps || !vp || !feat || !b0 || !hh || !idx || !sgn)
+    double* mu_part = sc.get<double>(cv_mu_scratch_doubles(O + 1));
+    if (!snaps || !vp || !feat || !b0 || !hh || !sgn || !mu_part)
         return fail(c, TTCF_ENOMEM, "mean-term allocation failed");
-    std::vector<int32_t> hs(2 * (size_t)rows);
-    for (int r = 0; r < rows; ++r) {
-        hs[r] = r / 4;         // state
-        hs[rows + r] = r % 4;  // mapping
-    }
     const double sgn_h[4] = {1.0, 1.0, -1.0, -1.0};  // sign of P_xy(0) under each mapping
-    HIPCHECK(c, hipMemcpyAsync(idx, hs.data(), sizeof(int32_t) * hs.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHECK(c, hipMemcpyAsync(sgn, sgn_h, sizeof(sgn_h), hipMemcpyHostToDevice, c->stream));
     Replicas R;
     rc = R.start(c, m, n_replicas, kicks, decorrelate_steps);
@@ -3177,13 +3171,15 @@ int32_t ttcf_cv_mean_term(ttcf_ctx* c, int32_t mother, int32_t n_replicas, const
         rc = R.sample(c, states_per_replica, steps_between, snaps);
         if (rc != TTCF_OK) return rc;
         HIPCHECK(c, launch_states_vpxy(m.dev, snaps, (int32_t)per_round, vp, c->stream));
-        HIPCHECK(c, launch_cv_features(snaps, n, idx, idx + rows, vp, sgn, rows, m.dev.box,
-                                       m.dev.rc2, m.dev.c_attr, m.dev.volume, m.sys.temperature,
-                                       gamma_dot, feat, b0, b0 + rows, c->stream));
+        HIPCHECK(c, launch_cv_features_maps(snaps, n, (int32_t)per_round, vp, sgn, m.dev.box,
+                                            m.dev.rc2, m.dev.c_attr, m.dev.volume,
+                                            m.sys.temperature, gamma_dot, feat, b0, b0 + rows,
+                                            c->stream));
         rc = cv_predict_h(c, feat, b0, b0 + rows, rows, m.dev.dt, hh, O + 1);
         if (rc != TTCF_OK) return rc;
         HIPCHECK(c, launch_cv_mu_accum(hh, (int)per_round, 4, O + 1, c->cv_mu, c->cv_mu + (O + 1),
-                                       c->cv_mu + 2 * (O + 1), c->cv_mu + 3 * (O + 1), c->stream));
+                                       c->cv_mu + 2 * (O + 1), c->cv_mu + 3 * (O + 1), mu_part,
+                                       c->stream));
     }
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     c->cv_mu_count += per_round * rounds;

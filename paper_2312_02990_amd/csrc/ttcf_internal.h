@@ -232,6 +232,14 @@ hipError_t launch_cv_scatter_h(const double* h, int32_t stride, int32_t count, d
 hipError_t launch_cv_beta(const ResponseLaunch& r, double* beta, hipStream_t s);
 hipError_t launch_fill_f64(double* p, double v, int64_t count, hipStream_t s);
 size_t lds_bytes_cv_features(int32_t n);
+size_t lds_bytes_cv_features_maps(int32_t n);
+// the features of rows 4 s + m (m = 0..3, the four mappings) of each of n_states states, the
+// pair sums done once per state; vpxy0 by state, vsign by mapping
+hipError_t launch_cv_features_maps(const double* states, int32_t n, int32_t n_states,
+                                   const double* vpxy0, const double* vsign, const double* box,
+                                   double rc2, double c_attr, double volume, double temperature,
+                                   double gamma_dot, float* out, double* b0_out, double* om_out,
+                                   hipStream_t s);
 hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* state_of,
                               const int32_t* map_of, const double* vpxy0, const double* vsign,
                               int32_t rows, const double* box, double rc2, double c_attr,
@@ -240,8 +248,11 @@ hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* st
 hipError_t launch_cv_h(const float* pred, int rows, int n_out, const float* ymu, const float* yinv,
                        const double* b0, const double* omega, double dt, double* out,
                        int64_t out_stride, hipStream_t s);
+// part: cv_mu_scratch_doubles(nt) doubles of device scratch for the partial sums
+size_t cv_mu_scratch_doubles(int nt);
 hipError_t launch_cv_mu_accum(const double* h, int groups, int maps, int nt, double* sum,
-                              double* comp, double* sumsq, double* compsq, hipStream_t s);
+                              double* comp, double* sumsq, double* compsq, double* part,
+                              hipStream_t s);
 hipError_t launch_states_vpxy(const SysDev& sys, const double* states, int32_t count, double* out,
                               hipStream_t s);
 

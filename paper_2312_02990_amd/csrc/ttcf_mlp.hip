@@ -333,7 +333,114 @@ __global__ __launch_bounds__(64) void k_cv_features(
     }
 }
 
+// The same features for the four mapped rows of each of n_states start states (row
+// 4 s + m), the pair sums done once per state: every feature of mapping m is the unmapped one
+// times a sign (p_x sums and the two force-momentum sums by s_x, p_x p_y by s_x s_y, the virial
+// by s_r, the sign of x), and the per-row kernel's operations give exactly those negations,
+// so both kernels write the same bits.
+__global__ __launch_bounds__(64) void k_cv_features_maps(
+    const double* states, int32_t n, int32_t n_states, const double* vpxy0, const double* vsign,
+    double lx, double ly, double lz, double rc2, double c_attr, double volume,
+    double temperature, double gamma_dot, float* out, double* b0_out, double* om_out) {
+    extern __shared__ double cvs[];
+    double* X = cvs;
+    double* Y = X + n;
+    double* Z = Y + n;
+    double* PX = Z + n;
+    double* PY = PX + n;
+    double* FX = PY + n;
+    double* FY = FX + n;
+    double* VIR = FY + n;
+    double* D2 = VIR + n;
+    double* feat = D2 + n;  // [3 kCvSlabs + 2] the unmapped features
+    const int st_i = blockIdx.x;
+    if (st_i >= n_states) return;
+    const double* st = states + (size_t)st_i * 6 * (size_t)n;
+    const int q = threadIdx.x;
+    for (int a = q; a < n; a += blockDim.x) {
+        X[a] = st[a];
+        Y[a] = st[n + a];
+        Z[a] = st[2 * n + a];
+        PX[a] = st[3 * n + a];
+        PY[a] = st[4 * n + a];
+    }
+    __syncthreads();
+    const double ilx = 1.0 / lx, ily = 1.0 / ly, ilz = 1.0 / lz;
+    for (int i = q; i < n; i += blockDim.x) {
+        const double xi = X[i], yi = Y[i], zi = Z[i], pxi = PX[i];
+        double fx = 0.0, fy = 0.0, vir = 0.0, d2 = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (j == i) continue;
+            double dx = xi - X[j], dy = yi - Y[j], dz = zi - Z[j];
+            dx -= lx * rint(dx * ilx);
+            dy -= ly * rint(dy * ily);
+            dz -= lz * rint(dz * ilz);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rc2) {
+                const double inv2 = 1.0 / r2;
+                const double inv6 = inv2 * inv2 * inv2;
+                const double fs = 24.0 * inv6 * (2.0 * inv6 - c_attr) * inv2;
+                fx += fs * dx;
+                fy += fs * dy;
+                vir += 0.5 * dx * (fs * dy);
+                d2 += 0.5 * (pxi - PX[j]) * (fs * dy);
+            }
+        }
+        FX[i] = fx;
+        FY[i] = fy;
+        VIR[i] = vir;
+        D2[i] = d2;
+    }
+    __syncthreads();
+    if (q < 3 * kCvSlabs) {
+        const int slab = q % kCvSlabs;
+        const int kind = q / kCvSlabs;  // 0 p_x, 1 p_x p_y, 2 virial
+        const double inv = (double)kCvSlabs / ly;
+        double acc = 0.0;
+        for (int a = 0; a < n; ++a) {
+            int k = (int)floor(Y[a] * inv);
+            k = k < 0 ? 0 : (k > kCvSlabs - 1 ? kCvSlabs - 1 : k);
+            if (k != slab) continue;
+            acc += kind == 0 ? PX[a] : (kind == 1 ? PX[a] * PY[a] : VIR[a]);
+        }
+        feat[q] = acc;
+    } else if (q == 3 * kCvSlabs) {
+        double acc = 0.0;
+        for (int a = 0; a < n; ++a) acc += FX[a] * PY[a] + PX[a] * FY[a];
+        feat[q] = acc;
+    } else if (q == 3 * kCvSlabs + 1) {
+        double acc = 0.0;
+        for (int a = 0; a < n; ++a) acc += D2[a];
+        feat[q] = acc;
+    }
+    __syncthreads();
+    // row 4 st_i + m: mapping signs p -> -p (m=1); (x, px) -> (-x, -px) (m=2);
+    // (x, py, pz) -> -(...) (m=3)
+    for (int e = q; e < 4 * (3 * kCvSlabs + 2); e += blockDim.x) {
+        const int m = e / (3 * kCvSlabs + 2), f = e % (3 * kCvSlabs + 2);
+        const double sx = (m == 1 || m == 2) ? -1.0 : 1.0;
+        const double sy = (m == 1 || m == 3) ? -1.0 : 1.0;
+        const double sr = (m == 2 || m == 3) ? -1.0 : 1.0;
+        const int kind = f < 3 * kCvSlabs ? f / kCvSlabs : 3;
+        const double sg = kind == 0 ? sx : (kind == 1 ? sx * sy : (kind == 2 ? sr : sx));
+        out[(size_t)(4 * st_i + m) * kCvIn + 2 + f] = (float)(sg * feat[f]);
+    }
+    if (q < 4) {
+        const int row = 4 * st_i + q;
+        const double vp = vpxy0[st_i] * vsign[q];
+        const double pxy = vp / volume;
+        const double om = -(volume / temperature) * gamma_dot * pxy;
+        out[(size_t)row * kCvIn] = (float)pxy;
+        out[(size_t)row * kCvIn + 1] = (float)om;
+        if (b0_out) b0_out[row] = pxy;
+        if (om_out) om_out[row] = om;
+    }
+}
+
 size_t lds_bytes_cv_features(int32_t n) { return sizeof(double) * 9 * (size_t)n; }
+size_t lds_bytes_cv_features_maps(int32_t n) {
+    return lds_bytes_cv_features(n) + sizeof(double) * (3 * kCvSlabs + 2);
+}
 
 hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* state_of,
                               const int32_t* map_of, const double* vpxy0, const double* vsign,
@@ -347,6 +454,21 @@ hipError_t launch_cv_features(const double* states, int32_t n, const int32_t* st
     hipLaunchKernelGGL(k_cv_features, dim3(rows), dim3(64), lds, s, states, n, state_of, map_of,
                        vpxy0, vsign, rows, box[0], box[1], box[2], rc2, c_attr, volume,
                        temperature, gamma_dot, out, b0_out, om_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cv_features_maps(const double* states, int32_t n, int32_t n_states,
+                                   const double* vpxy0, const double* vsign, const double* box,
+                                   double rc2, double c_attr, double volume, double temperature,
+                                   double gamma_dot, float* out, double* b0_out, double* om_out,
+                                   hipStream_t s) {
+    if (n_states <= 0) return hipSuccess;
+    const size_t lds = lds_bytes_cv_features_maps(n);
+    (void)hipFuncSetAttribute((const void*)k_cv_features_maps,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_cv_features_maps, dim3(n_states), dim3(64), lds, s, states, n, n_states,
+                       vpxy0, vsign, box[0], box[1], box[2], rc2, c_attr, volume, temperature,
+                       gamma_dot, out, b0_out, om_out);
     return hipGetLastError();
 }
 
@@ -429,23 +551,54 @@ hipError_t launch_cv_h(const float* pred, int rows, int n_out, const float* ymu,
 }
 
 // mean-term accumulation: for every t, add the mapping means of h over the groups of this
-// chunk (group = 4 consecutive rows) into compensated sums of H and H^2.
-__global__ void k_cv_mu_accum(const double* h, int groups, int maps, int nt, double* sum,
-                              double* comp, double* sumsq, double* compsq) {
+// chunk (group = `maps` consecutive rows) into compensated sums of H and H^2. First pass:
+// workgroup (t block, partition p) takes the groups of partition p (contiguous ranges), its
+// wave w every kMuWaves-th of them, and writes the wave's compensated partial sums; second
+// pass: per t, the partials are added to the running sums in (p, w) order. The result does not
+// depend on timing.
+constexpr int kMuParts = 32;
+constexpr int kMuWaves = 8;
+
+__device__ __forceinline__ void mu_neumaier(double& sum, double& comp, double v) {
+    const double t = sum + v;
+    comp += fabs(sum) >= fabs(v) ? (sum - t) + v : (v - t) + sum;
+    sum = t;
+}
+
+__global__ __launch_bounds__(64 * kMuWaves) void k_cv_mu_partial(const double* h, int groups,
+                                                                  int maps, int nt,
+                                                                  double* part) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + lane, p = blockIdx.y;
+    if (k >= nt) return;
+    const int per = (groups + kMuParts - 1) / kMuParts;
+    const int g0 = p * per, g1 = min(groups, g0 + per);
+    double s = 0.0, c = 0.0, s2 = 0.0, c2 = 0.0;
+    for (int g = g0 + w; g < g1; g += kMuWaves) {
+        double v = 0.0;
+        for (int m = 0; m < maps; ++m) v += h[((size_t)g * maps + m) * nt + k];
+        v /= (double)maps;
+        mu_neumaier(s, c, v);
+        mu_neumaier(s2, c2, v * v);
+    }
+    double* out = part + (size_t)(p * kMuWaves + w) * 4 * nt;
+    out[k] = s;
+    out[nt + k] = c;
+    out[2 * nt + k] = s2;
+    out[3 * nt + k] = c2;
+}
+
+__global__ void k_cv_mu_combine(const double* part, int nt, double* sum, double* comp,
+                                double* sumsq, double* compsq) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nt) return;
     double s = sum[k], c = comp[k], s2 = sumsq[k], c2 = compsq[k];
-    for (int gidx = 0; gidx < groups; ++gidx) {
-        double v = 0.0;
-        for (int m = 0; m < maps; ++m) v += h[(size_t)(gidx * maps + m) * nt + k];
-        v /= (double)maps;
-        double tsum = s + v;
-        c += fabs(s) >= fabs(v) ? (s - tsum) + v : (v - tsum) + s;
-        s = tsum;
-        const double v2 = v * v;
-        tsum = s2 + v2;
-        c2 += fabs(s2) >= fabs(v2) ? (s2 - tsum) + v2 : (v2 - tsum) + s2;
-        s2 = tsum;
+    for (int i = 0; i < kMuParts * kMuWaves; ++i) {
+        const double* q = part + (size_t)i * 4 * nt;
+        mu_neumaier(s, c, q[k]);
+        mu_neumaier(s, c, q[nt + k]);
+        mu_neumaier(s2, c2, q[2 * nt + k]);
+        mu_neumaier(s2, c2, q[3 * nt + k]);
     }
     sum[k] = s;
     comp[k] = c;
@@ -453,10 +606,16 @@ __global__ void k_cv_mu_accum(const double* h, int groups, int maps, int nt, dou
     compsq[k] = c2;
 }
 
+size_t cv_mu_scratch_doubles(int nt) { return (size_t)kMuParts * kMuWaves * 4 * (size_t)nt; }
+
 hipError_t launch_cv_mu_accum(const double* h, int groups, int maps, int nt, double* sum,
-                              double* comp, double* sumsq, double* compsq, hipStream_t s) {
-    hipLaunchKernelGGL(k_cv_mu_accum, dim3((nt + 63) / 64), dim3(64), 0, s, h, groups, maps, nt, sum,
-                       comp, sumsq, compsq);
+                              double* comp, double* sumsq, double* compsq, double* part,
+                              hipStream_t s) {
+    if (groups <= 0 || nt <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cv_mu_partial, dim3((nt + 63) / 64, kMuParts), dim3(64 * kMuWaves), 0, s,
+                       h, groups, maps, nt, part);
+    hipLaunchKernelGGL(k_cv_mu_combine, dim3((nt + 63) / 64), dim3(64), 0, s, part, nt, sum, comp,
+                       sumsq, compsq);
     return hipGetLastError();
 }
 

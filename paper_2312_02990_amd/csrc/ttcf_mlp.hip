@@ -119,12 +119,23 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t s) {
 // small element-wise and reduction kernels (fixed-order sums)
 // ---------------------------------------------------------------------------------------
 
-__global__ void k_colsum(const float* X, int M, int N, int ld, float* out) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
+// out[n] = sum over the M rows of X(m, n): 64 columns per workgroup, its 16 waves taking
+// every 16th row, the wave partials added in wave order (a fixed order)
+__global__ __launch_bounds__(1024) void k_colsum(const float* X, int M, int N, int ld,
+                                                 float* out) {
+    __shared__ float part[16][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int m = 0; m < M; ++m) s += X[(int64_t)m * ld + n];
-    out[n] = s;
+    if (n < N)
+        for (int m = w; m < M; m += 16) s += X[(int64_t)m * ld + n];
+    part[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && n < N) {
+        float t = 0.f;
+        for (int v = 0; v < 16; ++v) t += part[v][lane];
+        out[n] = t;
+    }
 }
 
 // dY = 2 (Y - T) / (M N); loss (one value) = mean (Y - T)^2 when loss != null
@@ -191,7 +202,7 @@ __global__ void k_col_stats(const float* X, int64_t rows, int cols, float* mu, f
 }
 
 hipError_t launch_colsum(const float* X, int M, int N, int ld, float* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_colsum, dim3((N + 127) / 128), dim3(128), 0, s, X, M, N, ld, out);
+    hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64), dim3(1024), 0, s, X, M, N, ld, out);
     return hipGetLastError();
 }
 hipError_t launch_mse_grad(const float* Y, const float* Tg, int64_t count, float scale, float* dY,

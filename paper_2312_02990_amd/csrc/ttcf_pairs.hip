@@ -54,7 +54,8 @@ constexpr double kTwo52 = 4503599627370496.0;    // 2^52
 
 struct PairLds {
     uint4* pos;        // [n] by rank: fixed-point x, y, z, and x + the Lees-Edwards offset
-                       // (the x of the image a pair across the y boundary uses)
+                       // (the x of the image a pair across the y boundary uses); then the two
+                       // dummy entries (0, 0, 0, 0) and 2^31 (L/2) in every component
     unsigned long long* fxy;  // [n] by rank: fixed-point force accumulators, x and y packed
                               // in one 64-bit integer y 2^32 + x
     int32_t* fz;              // [n] by rank: the same for z (separate arrays of 8- and 4-byte
@@ -91,7 +92,7 @@ __host__ __device__ inline PairPlan plan_pairs(int n, int cells) {
         off += bytes;
         return at;
     };
-    p.pos = take(16 * (size_t)n, 16);
+    p.pos = take(16 * (size_t)(n + 2), 16);  // and the two dummy entries of the no-pair word
     p.fxy = take(8 * (size_t)n, 16);
     p.fz = take(4 * (size_t)n, 16);
     p.fcell = take(4 * (size_t)n, 16);
@@ -156,10 +157,13 @@ __device__ __forceinline__ int3 unpack_force(unsigned long long xy, int z) {
 
 // Pair words: rank i (bits 0-13), rank j (14-27); kShiftBit: j is taken at its image across
 // the y boundary, x_j + the Lees-Edwards offset (a pair whose image lies the other way is
-// stored as (j, i)); kNoPair: no pair (lanes past a segment's end), ranks 0 so that its
-// position loads stay in bounds.
+// stored as (j, i)); no pair (lanes past a segment's end): the word of the two dummy entries
+// after the n atoms' positions, (n, n + 1), which lie half a box apart along every axis, so that
+// the force pass needs no test of its own for them.
 constexpr uint32_t kShiftBit = 1u << 28;
-constexpr uint32_t kNoPair = 1u << 29;
+__device__ __forceinline__ uint32_t no_pair_word(int n) {
+    return (uint32_t)n | ((uint32_t)(n + 1) << 14);
+}
 
 // The series coefficients of iso_kick_coeffs_tab, written to the job's LDS by one thread:
 // tab[k] = 1/(2k+2)! (k = 0..6), tab[7 + k] = 1/(2k+1)! (k = 0..7).
@@ -671,14 +675,15 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq, P pa
         if (s < lane) seg_first += (c + 63) >> 6;
     }
     const int chunks = __builtin_amdgcn_readlane(seg_first, kPairThreads / 64);
+    const uint32_t nopair = no_pair_word(n);
     // the word of chunk g in this lane: segment s is the last one starting at or before g
     auto word_of = [&](int g) -> uint32_t {
-        if (g >= chunks) return kNoPair;
+        if (g >= chunks) return nopair;
         const int s = __popcll(__ballot(seg_first <= g)) - 1;
         const int first = __builtin_amdgcn_readlane(seg_first, s);
         const int cnt = __builtin_amdgcn_readlane(seg_pairs, s);
         const int at = (g - first) * 64 + lane;
-        return at < cnt ? pair_base[(size_t)s * seg_cap + at] : kNoPair;
+        return at < cnt ? pair_base[(size_t)s * seg_cap + at] : nopair;
     };
     // software pipeline: the pair words two chunks ahead and the positions one chunk ahead
     // are loaded before this chunk's atomics (LDS operations complete in order, so loads
@@ -690,7 +695,6 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq, P pa
     uint4 pj_next = L.pos[(w_next >> 14) & 0x3FFFu];
     for (int g = g0; g < chunks; g += nwb) {
         const uint32_t word = w_next;
-        const bool live = (word & kNoPair) == 0u;
         const uint3 qi = pi_next;
         const uint4 qj = pj_next;
         w_next = w_after;
@@ -703,7 +707,7 @@ __device__ __forceinline__ PfSums pf_forces(int n, int cells, uint32_t dxq, P pa
         const float dy = (float)(int32_t)(qi.y - qj.y) * uy;
         const float dz = (float)(int32_t)(qi.z - qj.z) * uz;
         const float r2 = dx * dx + dy * dy + dz * dz;
-        if (live & (r2 < rc2)) {
+        if (r2 < rc2) {
             const float inv = __builtin_amdgcn_rcpf(r2);  // within 1 ulp
             const float s3 = inv * inv * inv;
             const float fs = s3 * (f48 * s3 - f24) * inv;
@@ -1199,6 +1203,10 @@ __global__ __launch_bounds__(APT == kLargeApt ? kLargeThreads : kPairThreads) vo
         const int cells = d->sys.lc[0] * d->sys.lc[1] * d->sys.lc[2];
         const PairLds L = job_lds(n, cells);
         for (int c = threadIdx.x; c < cells; c += blockDim.x) L.cnt[c] = 0;
+        if (threadIdx.x == 0) {
+            L.pos[n] = make_uint4(0u, 0u, 0u, 0u);
+            L.pos[n + 1] = make_uint4(1u << 31, 1u << 31, 1u << 31, 1u << 31);
+        }
         for (int i = threadIdx.x; i < n; i += blockDim.x) {
             L.fxy[i] = 0ull;
             L.fz[i] = 0;
@@ -1227,6 +1235,10 @@ __global__ __launch_bounds__(APT == kLargeApt ? kLargeThreads : kPairThreads) vo
     const int t = threadIdx.x;
     if (t == 0) *L.sys = Sg;
     for (int c = t; c < cells; c += blockDim.x) L.cnt[c] = 0;
+    if (t == 0) {
+        L.pos[Sg.n] = make_uint4(0u, 0u, 0u, 0u);
+        L.pos[Sg.n + 1] = make_uint4(1u << 31, 1u << 31, 1u << 31, 1u << 31);
+    }
     for (int i = t; i < Sg.n; i += blockDim.x) {
         L.fxy[i] = 0ull;
         L.fz[i] = 0;

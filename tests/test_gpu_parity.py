@@ -467,16 +467,17 @@ def test_response_filters_and_normalisation(T, orc, cfg1):
     assert c[4] == 16
 
 
-def test_accumulate_and_response_on_the_gpu_series(T, orc, cfg1):
+@pytest.mark.parametrize("nst", [1, 63, 64, 200])
+def test_accumulate_and_response_on_the_gpu_series(T, orc, cfg1, nst):
     """The accumulator (per group, a compensated prefix scan of the trapezoid terms over
     blocks of 64 time points) and the response kernels, applied to the GPU's own exported
-    daughter series, against the oracle's estimator on those series: 201 time points (three
-    full blocks and a ragged tail), two shear rates, the per-rate filters and the
-    per-unit-rate normalisation, to rounding (1e-12 of the per-state scale for the means,
-    1e-9 relative for the block standard errors)."""
+    daughter series, against the oracle's estimator on those series: 2, 64 (one full block),
+    65 (a block and one point) and 201 time points (three full blocks and a ragged tail), two
+    shear rates, the per-rate filters and the per-unit-rate normalisation, to rounding
+    (1e-12 of the per-state scale for the means, 1e-9 relative for the block standard
+    errors)."""
     s, box, sr, sp = cfg1
-    nst = 200
-    say("accumulate/response on the GPU's own series")
+    say(f"accumulate/response on the GPU's own series, {nst + 1} points")
     with T.Context() as ctx:
         mid = ctx.ttcf_init_mother(gsys(T, s, 1), sr[0], sp[0], n_equil=0)
         ctx.ttcf_import_states(mid, sr, sp)

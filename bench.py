@@ -425,17 +425,18 @@ def thermostat_leg(T, stream, ctx, mid, s, n_states, nst, gd=1e-2):
     return out
 
 
-def green_kubo_leg(T, ctx, mid, s, n_samples, nst, gd=1e-4):
+def green_kubo_leg(T, ctx, mid, s, n_samples, nst, gd=1e-4, resp_ctx=None):
     """Weak-field check at full size: the TTCF viscosity eta(t) = -TTCF(t)/gamma_dot of the
     benchmark's groups at gamma_dot = 1e-4 against the Green-Kubo integral
     (V/T) int_0^t <P_xy(0) P_xy(s)> ds of the mother's recorded V P_xy (the series the start
-    states were sampled from), both at t = 0.25, 0.5 and the daughters' end."""
+    states were sampled from), both at t = 0.25, 0.5 and the daughters' end. resp_ctx: the
+    context that holds the benchmark's groups at gamma_dot (ctx when None)."""
     vp = ctx.ttcf_export_mother_series(mid, n_samples)
     acf, _, _ = ctx.ttcf_mother_acf(mid, nst + 1, 0.05)
     cov = acf * float(np.var(vp))                       # <VP(0) VP(t)>, mean removed
     gk = np.concatenate([[0.0], np.cumsum(0.5 * s.dt * (cov[1:] + cov[:-1]))])
     gk /= s.volume * s.temperature
-    tm, tse, dm, dse, used = ctx.ttcf_response(nst + 1, gd)
+    tm, tse, dm, dse, used = (ctx if resp_ctx is None else resp_ctx).ttcf_response(nst + 1, gd)
     out = {"gamma_dot": gd, "n_states": used, "mother_samples": n_samples}
     for k in (100, 200, nst):
         out[f"t={k * s.dt:g}"] = {"eta_ttcf": float(-tm[k] / gd), "eta_ttcf_se": float(tse[k] / gd),
@@ -1059,8 +1060,7 @@ def main():
         km, kl = c.ttcf_step_timing(reset=True)
         kern_ms += km
         launches += kl
-    for c, _, _ in ctxs[1:]:
-        c.close()
+
     start_states = ctx.ttcf_export_states(mid, args.states) if args.cpu_budget > 0 else None
     progress("headline")
     precision = None
@@ -1069,9 +1069,12 @@ def main():
     progress("precision")
     green_kubo = None
     try:
-        green_kubo = green_kubo_leg(T, ctx, mid, s, 100 * args.states, nst)
+        green_kubo = green_kubo_leg(T, ctx, mid, s, 100 * args.states, nst,
+                                    resp_ctx=ctxs[GAMMAS.index(1e-4) % len(ctxs)][0])
     except Exception as e:  # the headline line is printed whatever happens here
         green_kubo = {"error": repr(e)}
+    for c, _, _ in ctxs[1:]:
+        c.close()
     thermostats = None
     progress("green-kubo")
     if args.thermostats:

@@ -88,3 +88,13 @@ def test_struct_layouts_match_header(built, name, struct):
 def C_sizeof(t):
     import ctypes
     return ctypes.sizeof(t)
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library the binding raises (there is no CPU implementation to fall
+    back on)."""
+    from paper_2312_02990_amd import ttcf
+    monkeypatch.setattr(ttcf, "_lib", None)
+    monkeypatch.setattr(ttcf, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libttcf.so"))
+    with pytest.raises(ImportError, match="no CPU implementation"):
+        ttcf.lib()

@@ -998,16 +998,20 @@ def main():
     # its last batch, then its next spawn) runs while the other's kernel does. The step
     # kernels are chained by events, so they never share the GPU; the per-launch kernel times
     # stay those of a kernel alone.
+    # (both on streams of their own: work on the legacy default stream would wait for every
+    # other stream's, and theirs for it)
     ctxs = [(ctx, mid, torch.cuda.current_stream())]
     if args.pipeline:
         import ctypes
-        s2 = torch.cuda.Stream()
-        ctx2 = T.Context(ctypes.c_void_p(s2.cuda_stream))
         r_st, p_st = ctx.ttcf_export_states(mid, args.states)
-        mid2 = ctx2.ttcf_init_mother(sysd, r_st[0], p_st[0], n_equil=0)
-        ctx2.ttcf_set_step_shape(args.variant, args.threads, args.skin, args.kmax)
-        ctx2.ttcf_import_states(mid2, r_st, p_st)
-        ctxs.append((ctx2, mid2, s2))
+        ctxs = []
+        for _ in range(2):
+            sk = torch.cuda.Stream()
+            ck = T.Context(ctypes.c_void_p(sk.cuda_stream))
+            mk = ck.ttcf_init_mother(sysd, r_st[0], p_st[0], n_equil=0)
+            ck.ttcf_set_step_shape(args.variant, args.threads, args.skin, args.kmax)
+            ck.ttcf_import_states(mk, r_st, p_st)
+            ctxs.append((ck, mk, sk))
         del r_st, p_st
 
     def spawn_step(i, after):
@@ -1073,8 +1077,9 @@ def main():
                                     resp_ctx=ctxs[GAMMAS.index(1e-4) % len(ctxs)][0])
     except Exception as e:  # the headline line is printed whatever happens here
         green_kubo = {"error": repr(e)}
-    for c, _, _ in ctxs[1:]:
-        c.close()
+    for c, _, _ in ctxs:
+        if c is not ctx:
+            c.close()
     thermostats = None
     progress("green-kubo")
     if args.thermostats:
